@@ -1,0 +1,194 @@
+/*
+ * vtm.h -- C ABI of the MI355X (gfx950) Virtual Transmission Method library.
+ *
+ * The library solves the nodal-analysis system of a current-driven circuit,
+ * A x = b (Section II, eq. 1), by the Virtual Transmission Method of Wei and
+ * Yang (arXiv 0910.0663):
+ *
+ *   - wire tearing (Section V, Steps 1-4): every branch whose two nodes lie in
+ *     different sub-circuits of the caller's node partition is cut at its
+ *     middle, i --g-- j == i --2g-- m --2g-- j, and the middle node m is split
+ *     into twins joined by a lossless line of characteristic impedance Z
+ *     (level-one tearing: each line joins exactly two sub-circuits);
+ *   - the iteration (Section VI, eqs. 9-14 with every line delay equal to one
+ *     sweep): each sweep, every sub-circuit solves its own system, in which a
+ *     line appears as its admittance W = 1/Z plus an incident-wave source; each
+ *     line then carries the outgoing wave W u - i of one twin to the other twin
+ *     for the next sweep.  Boundary variables start at zero.
+ *
+ * Convergence for SPD A and SPD Z is Theorem 1 (Section VII); its limit is the
+ * solution of the untorn system (Appendix).
+ *
+ * Memory: matrices and partitions are HOST pointers and are copied; right-hand
+ * sides, solutions and gradients are DEVICE pointers (HIP, the device current
+ * when vtm_setup ran).  Multi-column vectors are column-major [nrhs][n]:
+ * element (node i, column r) is at r*n + i.  All work runs on the stream given
+ * to vtm_setup.  No exception crosses the ABI; every call returns a status and
+ * vtm_last_error() gives a message for the calling thread.  One handle must
+ * not be used by two host threads at once.
+ */
+#ifndef VTM_H
+#define VTM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VTM_OK = 0,
+    VTM_E_ARG = 1,          /* malformed input (sizes, ranges, NaN, labels)          */
+    VTM_E_UNTEARABLE = 2,   /* a cross-partition coupling is not A_ij == A_ji < 0    */
+    VTM_E_SINGULAR = 3,     /* a sub-circuit matrix (with its line admittances) is singular */
+    VTM_E_DIVERGED = 4,     /* residual non-finite or above opt.divergence           */
+    VTM_E_MAXITER = 5,      /* opt.max_sweeps reached without convergence            */
+    VTM_E_HIP = 6,          /* HIP runtime error                                     */
+    VTM_E_OOM = 7,          /* device or pinned-host allocation failed               */
+    VTM_E_UNSUPPORTED = 8   /* valid input outside this build's limits               */
+} vtm_status;
+
+typedef enum {
+    VTM_FP64 = 0,           /* FP64 local inverses, waves and sweeps                 */
+    VTM_FP32_REFINE = 1,    /* FP32 inverses and sweeps inside FP64 refinement       */
+    VTM_BF16_REFINE = 2     /* BF16 inverses (MFMA, FP32 accumulate) inside FP64 refinement */
+} vtm_precision;
+
+/* Sparse matrix, compressed rows, host memory, FP64.  Any row order; column
+ * indices need not be sorted; duplicate entries are summed. */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const int64_t *rowptr;  /* n + 1 */
+    const int32_t *col;     /* nnz   */
+    const double *val;      /* nnz   */
+} vtm_csr;
+
+typedef struct {
+    int32_t precision;      /* vtm_precision                                         */
+    int32_t nrhs_max;       /* widest solve this handle will run (sizes work space)  */
+    int32_t check_every;    /* sweeps between FP64 residual checks (>= 1)            */
+    int32_t max_outer;      /* refinement: most outer corrections                    */
+    int64_t max_sweeps;     /* per plain solve, or per inner solve when refining     */
+    double divergence;      /* a relative residual above this means divergence       */
+    double inner_drop;      /* refinement: inner target ||r - A d|| / ||r||; 0 = default
+                               (1e-5 for FP32, 1e-2 for BF16)                        */
+    int32_t use_graph;      /* replay each check interval as one captured hipGraph   */
+    int32_t timing;         /* 1: time every sweep launch with HIP events (report)   */
+} vtm_options;
+
+typedef struct {
+    int64_t sweeps;         /* sweeps run (summed over inner solves when refining)   */
+    int32_t outer;          /* refinement corrections applied (0 for VTM_FP64)       */
+    int32_t checks;         /* residual checks run                                   */
+    double relres_max;      /* final max over columns of ||b - A x|| / ||b||         */
+    double solve_ms;        /* wall time of the call                                 */
+    double sweep_kernel_ms; /* opt.timing: summed duration of the sweep launches     */
+    int64_t sweep_launches; /* opt.timing: number of sweep launches timed            */
+    double *relres;         /* optional caller array [nrhs]: final per-column value  */
+} vtm_report;
+
+typedef struct vtm_handle_s *vtm_handle;
+
+/* Fills *opt with defaults: FP64, nrhs_max 1, check_every 8, max_outer 30,
+ * max_sweeps 1000000, divergence 1e6, inner_drop 0, use_graph 0, timing 0. */
+void vtm_default_options(vtm_options *opt);
+
+/*
+ * vtm_setup -- tear A along the partition and factor every sub-circuit.
+ *
+ * Defines the operation of Section V (Steps 1-4, eqs. 6-8) and the local
+ * systems of Section VI (eq. 11: the C + W block).
+ *
+ *   A       host CSR of the untorn system, n x n.
+ *   part    host int32[n]: sub-circuit of every node, labels 0..S-1, each used.
+ *   Z       host: nZ == 1 -> one impedance (ohm, > 0) for every cut wire;
+ *           nZ == number of cut wires -> one per wire, wires in canonical order
+ *           (lower node ascending, then upper node ascending).
+ *   opt     options (NULL = defaults).
+ *   stream  hipStream_t for all later work (NULL = the null stream).
+ *   out     receives the handle; the handle owns every device buffer.
+ *
+ * Every pair (i, j) in different sub-circuits with a nonzero entry must have
+ * A_ij == A_ji < 0 (a two-terminal conductance g = -A_ij), else
+ * VTM_E_UNTEARABLE.  Sub-circuits may not exceed 2048 nodes
+ * (VTM_E_UNSUPPORTED).  n and nnz must fit int32.  Returns after the setup
+ * kernels finish.
+ */
+vtm_status vtm_setup(const vtm_csr *A, const int32_t *part, const double *Z, int64_t nZ,
+                     const vtm_options *opt, void *stream, vtm_handle *out);
+
+/*
+ * vtm_solve -- run VTM sweeps (Section VI, eqs. 11 and 14) from zero boundary
+ * variables until every column has ||b - A x||_2 / ||b||_2 <= tol, the
+ * residual taken on the untorn A in FP64 every opt.check_every sweeps.
+ *
+ *   b, x    device FP64 [nrhs][n] (column-major), original node order; x is
+ *           written (the last iterate also on DIVERGED / MAXITER).
+ *   nrhs    1 .. opt.nrhs_max.
+ *   tol     > 0.
+ *   rep     optional report.
+ *
+ * A zero column converges at once with x = 0.  With a refining precision the
+ * sweeps run in FP32/BF16 on A d = r and x += d, r = b - A x in FP64, until
+ * the FP64 residual meets tol (VTM_E_MAXITER after opt.max_outer).
+ */
+vtm_status vtm_solve(vtm_handle h, const double *b, double *x, int32_t nrhs, double tol,
+                     vtm_report *rep);
+
+/*
+ * vtm_solve_adjoint -- solve A^T lambda = g by the same iteration on the torn
+ * A^T, reusing the stored sub-circuit inverses read transposed (valid because
+ * every cut coupling is symmetric, so the torn A^T is the transposed torn A).
+ * Same conventions and errors as vtm_solve.
+ */
+vtm_status vtm_solve_adjoint(vtm_handle h, const double *g, double *lambda, int32_t nrhs,
+                             double tol, vtm_report *rep);
+
+/*
+ * vtm_grad -- derivative of a loss L(x) with respect to branch conductances,
+ * from A x = b and A^T lambda = dL/dx:
+ *     dL_dg[e] = - sum_r (lambda_i - lambda_j)(x_i - x_j),  branch e = (i, j).
+ * (dL/db = lambda needs no call.)
+ *
+ *   x, lambda   device FP64 [nrhs][n].
+ *   branch_ij   device int32 [m][2] (pairs i, j; original node ids); a pair
+ *               naming a node outside [0, n) yields NaN for that branch.
+ *   dL_dg       device FP64 [m], overwritten.
+ */
+vtm_status vtm_grad(vtm_handle h, const double *x, const double *lambda, int32_t nrhs,
+                    const int32_t *branch_ij, int64_t m, double *dL_dg);
+
+/*
+ * Checkpoint / resume of the iteration state: the incident wave at every port
+ * (two ports per cut wire: port 2e on the lower node of wire e, 2e+1 on the
+ * upper), device FP64 [nrhs][2 * n_wires].  vtm_set_waves makes the next
+ * vtm_solve start from these waves instead of zero.
+ */
+vtm_status vtm_get_waves(vtm_handle h, double *waves, int32_t nrhs);
+vtm_status vtm_set_waves(vtm_handle h, const double *waves, int32_t nrhs);
+
+/* Sizes of a handle: nodes, sub-circuits, cut wires, bytes of stored inverses. */
+vtm_status vtm_info(vtm_handle h, int64_t *n, int64_t *n_sub, int64_t *n_wires,
+                    int64_t *inverse_bytes);
+
+void vtm_destroy(vtm_handle h);
+const char *vtm_status_str(vtm_status s);
+const char *vtm_last_error(void);
+
+/*
+ * vtm_plan -- host-only tearing plan (no device work), for inspection and tests.
+ * Runs the same planner as vtm_setup.  Outputs may be NULL.
+ *   n_sub, n_wires       counts.
+ *   wires     int32 [n_wires][2]  cut wires (i < j), canonical order.
+ *   coef      double [n_wires][4] per wire: G = 2gW/(2g+W) (port conductance),
+ *             c = 2g/(2g+W) (wave-to-source gain), beta = 4gW/(2g+W) and
+ *             gamma = (W-2g)/(2g+W) (outgoing wave = beta*u + gamma*a).
+ */
+vtm_status vtm_plan(const vtm_csr *A, const int32_t *part, const double *Z, int64_t nZ,
+                    int64_t *n_sub, int64_t *n_wires, int32_t *wires, double *coef);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VTM_H */

@@ -1,0 +1,76 @@
+"""Differentiation through a VTM solve: ``VTMSolve.apply(b, g, circuit)``.
+
+Forward: build the nodal matrix of the circuit for branch conductances g,
+tear and factor it (vtm_setup, only when g changed) and solve A x = b
+(vtm_solve).  Backward: lambda = A^-T dL/dx by VTM on the torn A^T with the
+same stored inverses (vtm_solve_adjoint); dL/db = lambda and
+dL/dg_e = -(lambda_i - lambda_j)(x_i - x_j) (vtm_grad).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .binding import Solver
+from workloads import nodal_matrix
+
+
+class Circuit:
+    """Grid-like circuit structure: branches, ground conductances, partition, line impedance."""
+
+    def __init__(self, n, edges, ground, part, Z, tol=1e-8, precision="fp32_refine", vccs=None,
+                 **solver_kw):
+        self.n = int(n)
+        self.edges = np.asarray(edges, dtype=np.int64)
+        self.ground = np.asarray(ground, dtype=np.float64)
+        self.part = np.asarray(part, dtype=np.int32)
+        self.Z = Z
+        self.tol = float(tol)
+        self.precision = precision
+        self.vccs = vccs
+        self.solver_kw = solver_kw
+        self._key = None
+        self._solver = None
+        self._ij = None
+        self.last_forward = None
+        self.last_adjoint = None
+
+    def solver(self, g: torch.Tensor) -> Solver:
+        gh = g.detach().to("cpu", torch.float64).numpy()
+        key = gh.tobytes()
+        if key != self._key:
+            if self._solver is not None:
+                self._solver.close()
+            A = nodal_matrix(self.n, self.edges, gh, self.ground, self.vccs)
+            self._solver = Solver(A, self.part, self.Z, precision=self.precision, **self.solver_kw)
+            self._key = key
+        return self._solver
+
+    def branch_ij(self, device) -> torch.Tensor:
+        if self._ij is None or self._ij.device != device:
+            self._ij = torch.as_tensor(self.edges.astype(np.int32), device=device)
+        return self._ij
+
+
+class VTMSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, b, g, circuit: Circuit):
+        solver = circuit.solver(g)
+        x, rep = solver.solve(b.detach(), circuit.tol)
+        circuit.last_forward = rep
+        ctx.circuit = circuit
+        ctx.solver = solver
+        ctx.b_shape = b.shape
+        ctx.save_for_backward(x)
+        return x.reshape(b.shape)
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        solver, circuit = ctx.solver, ctx.circuit
+        gx = gx.reshape(x.shape).to(torch.float64).contiguous()
+        lam, rep = solver.solve_adjoint(gx, circuit.tol)
+        circuit.last_adjoint = rep
+        grad_b = lam.reshape(ctx.b_shape) if ctx.needs_input_grad[0] else None
+        grad_g = solver.grad(x, lam, circuit.branch_ij(x.device)) if ctx.needs_input_grad[1] else None
+        return grad_b, grad_g, None

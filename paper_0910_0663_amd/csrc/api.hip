@@ -1,0 +1,555 @@
+// C ABI: handle lifetime, setup, the solve driver and the adjoint/gradient calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "vtm.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+vtm_status fail(vtm_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define VTM_HIP(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(e_ == hipErrorOutOfMemory ? VTM_E_OOM : VTM_E_HIP,                         \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                        \
+    } while (0)
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t count = 0;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t n) {
+        count = n;
+        return hipMalloc(reinterpret_cast<void**>(&p), (n ? n : 1) * sizeof(T));
+    }
+    hipError_t upload(const std::vector<T>& v, hipStream_t st) {
+        hipError_t e = alloc(v.size());
+        if (e != hipSuccess || v.empty()) return e;
+        return hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+    }
+};
+
+std::vector<float> to_float(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
+
+}  // namespace
+
+struct vtm_handle_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    vtm_options opt{};
+    vtm::Plan plan;
+    int nrhs_max = 1;
+
+    // untorn renumbered matrix, and its transpose when A is not symmetric
+    DevBuf<int32_t> rowptr, col, rowptrT, colT;
+    DevBuf<double> val, valT;
+    // sub-circuits and ports
+    DevBuf<int32_t> perm, iperm, sub_off, port_off, port_node, port_slot, port_twin, abi2port;
+    DevBuf<int64_t> kofs;
+    DevBuf<double> dmod;
+    DevBuf<double> c64, beta64, gamma64;
+    DevBuf<float> c32, beta32, gamma32;
+    // stored inverses
+    DevBuf<double> K64;
+    DevBuf<float> K32;
+    // work vectors, [rows][nrhs]
+    DevBuf<double> bp, xp, rp;            // FP64: permuted b, x, residual
+    DevBuf<double> a64[2];                // FP64 waves
+    DevBuf<float> b32, d32, a32[2];       // low-precision inner solve
+    DevBuf<double> partial, norms;
+    DevBuf<int> flag;
+    double* h_norms = nullptr;            // pinned
+    bool waves_set = false;               // next solve resumes from the stored waves
+    // per-launch timing of the sweep kernel (opt.timing)
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+
+    ~vtm_handle_s() {
+        if (h_norms) (void)hipHostFree(h_norms);
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+
+    vtm::PortArrays ports() const {
+        return vtm::PortArrays{port_off.p, port_node.p, port_slot.p, port_twin.p, plan.max_slot};
+    }
+};
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// FP64 residual of x against b (both [n][nrhs] renumbered) -> relres per column.
+// With transpose set the residual is taken on A^T (the adjoint system).
+template <typename TX>
+vtm_status residual(vtm_handle h, const double* b, const TX* x, int nrhs, double* r_out,
+                    std::vector<double>& rel, bool transpose) {
+    const vtm::Plan& P = h->plan;
+    const bool useT = transpose && !P.symmetric;
+    VTM_HIP(vtm::launch_residual<TX>(int(P.n), nrhs, useT ? h->rowptrT.p : h->rowptr.p,
+                                     useT ? h->colT.p : h->col.p, useT ? h->valT.p : h->val.p, b, x, r_out,
+                                     h->partial.p, h->norms.p, h->stream));
+    VTM_HIP(hipMemcpyAsync(h->h_norms, h->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost,
+                           h->stream));
+    VTM_HIP(hipStreamSynchronize(h->stream));
+    rel.resize(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+        const double rr = h->h_norms[2 * r], bb = h->h_norms[2 * r + 1];
+        rel[r] = bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+    }
+    return VTM_OK;
+}
+
+struct IterOut;
+
+// Event pair around one sweep launch (opt.timing); events are reused per check interval.
+vtm_status timing_event(vtm_handle h, hipEvent_t* out) {
+    if (h->ev_used == h->ev.size()) {
+        hipEvent_t e;
+        VTM_HIP(hipEventCreate(&e));
+        h->ev.push_back(e);
+    }
+    *out = h->ev[h->ev_used++];
+    VTM_HIP(hipEventRecord(*out, h->stream));
+    return VTM_OK;
+}
+
+// Sums the durations of the recorded event pairs (after a stream sync) and resets them.
+vtm_status timing_collect(vtm_handle h, double& ms, int64_t& launches) {
+    for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
+        float t = 0.f;
+        VTM_HIP(hipEventElapsedTime(&t, h->ev[k], h->ev[k + 1]));
+        ms += t;
+        ++launches;
+    }
+    h->ev_used = 0;
+    return VTM_OK;
+}
+
+// One sweep on the FP64 or FP32 buffers; cur selects the wave buffer read.
+vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, int cur, bool adjoint) {
+    const vtm::Plan& P = h->plan;
+    hipEvent_t e0, e1;
+    if (h->opt.timing) {
+        vtm_status st = timing_event(h, &e0);
+        if (st != VTM_OK) return st;
+    }
+    if (!low) {
+        VTM_HIP((vtm::launch_sweep<double, double>(int(P.S), P.max_ns, nrhs, h->K64.p, h->kofs.p, h->sub_off.p,
+                                                   h->ports(), h->c64.p, h->beta64.p, h->gamma64.p,
+                                                   static_cast<const double*>(b), h->a64[cur].p,
+                                                   h->a64[cur ^ 1].p, static_cast<double*>(x), adjoint,
+                                                   h->stream)));
+    } else {
+        VTM_HIP((vtm::launch_sweep<float, float>(int(P.S), P.max_ns, nrhs, h->K32.p, h->kofs.p, h->sub_off.p,
+                                                 h->ports(), h->c32.p, h->beta32.p, h->gamma32.p,
+                                                 static_cast<const float*>(b), h->a32[cur].p, h->a32[cur ^ 1].p,
+                                                 static_cast<float*>(x), adjoint, h->stream)));
+    }
+    if (h->opt.timing) return timing_event(h, &e1);
+    return VTM_OK;
+}
+
+struct IterOut {
+    int64_t sweeps = 0;
+    int checks = 0;
+    int outer = 0;
+    double sweep_ms = 0.0;
+    int64_t launches = 0;
+    std::vector<double> rel;
+    vtm_status status = VTM_OK;
+};
+
+// Plain FP64 VTM on (bp -> xp), checking every m sweeps.  Waves start at zero
+// unless resume is set.
+vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resume, IterOut& out) {
+    const vtm::Plan& P = h->plan;
+    const int64_t np = P.nports * nrhs;
+    const int m = h->opt.check_every;
+    int cur = 0;
+    if (!resume) VTM_HIP(vtm::launch_fill<double>(np, 0.0, h->a64[0].p, h->stream));
+    VTM_HIP(vtm::launch_fill<double>(P.n * nrhs, 0.0, h->xp.p, h->stream));
+    // x^0 = 0: the check before any sweep (b = 0 converges at once)
+    vtm_status st = residual<double>(h, h->bp.p, h->xp.p, nrhs, nullptr, out.rel, adjoint);
+    if (st != VTM_OK) return st;
+    ++out.checks;
+    auto done = [&](const std::vector<double>& rel) {
+        for (double v : rel)
+            if (!(v <= tol)) return false;
+        return true;
+    };
+    if (done(out.rel)) return VTM_OK;
+    while (true) {
+        const int64_t chunk = std::min<int64_t>(m, h->opt.max_sweeps - out.sweeps);
+        for (int64_t k = 0; k < chunk; ++k) {
+            st = sweep_once(h, false, nrhs, h->bp.p, h->xp.p, cur, adjoint);
+            if (st != VTM_OK) return st;
+            cur ^= 1;
+        }
+        out.sweeps += chunk;
+        st = residual<double>(h, h->bp.p, h->xp.p, nrhs, nullptr, out.rel, adjoint);
+        if (st != VTM_OK) return st;
+        ++out.checks;
+        if ((st = timing_collect(h, out.sweep_ms, out.launches)) != VTM_OK) return st;
+        bool bad = false;
+        for (double v : out.rel)
+            if (!std::isfinite(v) || v > h->opt.divergence) bad = true;
+        if (bad) {
+            out.status = VTM_E_DIVERGED;
+            break;
+        }
+        if (done(out.rel)) break;
+        if (out.sweeps >= h->opt.max_sweeps) {
+            out.status = VTM_E_MAXITER;
+            break;
+        }
+    }
+    // leave the latest waves in buffer 0 for export / resume
+    if (cur == 1)
+        VTM_HIP(hipMemcpyAsync(h->a64[0].p, h->a64[1].p, sizeof(double) * np, hipMemcpyDeviceToDevice,
+                               h->stream));
+    return VTM_OK;
+}
+
+// Mixed precision: FP64 outer refinement around an FP32 inner VTM.
+vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut& out) {
+    const vtm::Plan& P = h->plan;
+    const int64_t nv = P.n * nrhs, np = P.nports * nrhs;
+    const int m = h->opt.check_every;
+    double drop = h->opt.inner_drop;
+    if (!(drop > 0.0)) drop = h->opt.precision == VTM_BF16_REFINE ? 1e-2 : 1e-5;
+    VTM_HIP(vtm::launch_fill<double>(nv, 0.0, h->xp.p, h->stream));
+    std::vector<double> rel, rnorm, e;
+    auto all_le = [](const std::vector<double>& v, double t) {
+        for (double x : v)
+            if (!(x <= t)) return false;
+        return true;
+    };
+    for (int outer = 0;; ++outer) {
+        // r = b - A x (FP64), stored for the inner solve
+        vtm_status st = residual<double>(h, h->bp.p, h->xp.p, nrhs, h->rp.p, rel, adjoint);
+        if (st != VTM_OK) return st;
+        ++out.checks;
+        out.rel = rel;
+        for (double v : rel)
+            if (!std::isfinite(v) || v > h->opt.divergence) {
+                out.status = VTM_E_DIVERGED;
+                return VTM_OK;
+            }
+        if (all_le(rel, tol)) return VTM_OK;
+        if (outer >= h->opt.max_outer) {
+            out.status = VTM_E_MAXITER;
+            return VTM_OK;
+        }
+        VTM_HIP((vtm::launch_convert<double, float>(nv, h->rp.p, h->b32.p, h->stream)));
+        VTM_HIP(vtm::launch_fill<float>(np, 0.0f, h->a32[0].p, h->stream));
+        int cur = 0;
+        int64_t inner = 0;
+        std::vector<double> best(nrhs, INFINITY);
+        int since = 0;
+        while (true) {
+            const int64_t chunk = std::min<int64_t>(m, h->opt.max_sweeps - inner);
+            for (int64_t k = 0; k < chunk; ++k) {
+                st = sweep_once(h, true, nrhs, h->b32.p, h->d32.p, cur, adjoint);
+                if (st != VTM_OK) return st;
+                cur ^= 1;
+            }
+            inner += chunk;
+            // ||r - A d|| / ||r|| in FP64
+            st = residual<float>(h, h->rp.p, h->d32.p, nrhs, nullptr, e, adjoint);
+            if (st != VTM_OK) return st;
+            ++out.checks;
+            if ((st = timing_collect(h, out.sweep_ms, out.launches)) != VTM_OK) return st;
+            bool improved = false, bad = false;
+            for (int r = 0; r < nrhs; ++r) {
+                if (!std::isfinite(e[r])) bad = true;
+                if (e[r] < 0.99 * best[r]) {
+                    best[r] = e[r];
+                    improved = true;
+                }
+            }
+            if (bad) {
+                out.sweeps += inner;
+                out.status = VTM_E_DIVERGED;
+                return VTM_OK;
+            }
+            since = improved ? 0 : since + 1;
+            if (all_le(e, drop) || since >= 3 || inner >= h->opt.max_sweeps) break;
+        }
+        out.sweeps += inner;
+        VTM_HIP(vtm::launch_add<float>(nv, h->d32.p, h->xp.p, h->stream));
+        ++out.outer;
+    }
+}
+
+vtm_status solve_common(vtm_handle h, const double* b, double* x, int32_t nrhs, double tol, vtm_report* rep,
+                        bool adjoint) {
+    const auto t0 = Clock::now();
+    if (!h) return fail(VTM_E_ARG, "null handle");
+    h->ev_used = 0;
+    if (!b || !x) return fail(VTM_E_ARG, "null vector");
+    if (nrhs < 1 || nrhs > h->nrhs_max) return fail(VTM_E_ARG, "nrhs outside 1..nrhs_max");
+    if (!(tol > 0.0)) return fail(VTM_E_ARG, "tol must be positive");
+    VTM_HIP(hipSetDevice(h->device));
+    const vtm::Plan& P = h->plan;
+    VTM_HIP(vtm::launch_gather(int(P.n), nrhs, h->perm.p, b, h->bp.p, h->stream));
+    IterOut out;
+    vtm_status st;
+    if (h->opt.precision == VTM_FP64) {
+        st = run_fp64(h, nrhs, tol, adjoint, h->waves_set, out);
+    } else {
+        st = run_refine(h, nrhs, tol, adjoint, out);
+    }
+    h->waves_set = false;
+    if (st != VTM_OK) return st;
+    VTM_HIP(vtm::launch_scatter(int(P.n), nrhs, h->iperm.p, h->xp.p, x, h->stream));
+    VTM_HIP(hipStreamSynchronize(h->stream));
+    if (rep) {
+        rep->sweeps = out.sweeps;
+        rep->outer = out.outer;
+        rep->checks = out.checks;
+        double mx = 0.0;
+        for (double v : out.rel) mx = std::isnan(v) ? v : std::max(mx, v);
+        rep->relres_max = mx;
+        rep->solve_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+        rep->sweep_kernel_ms = out.sweep_ms;
+        rep->sweep_launches = out.launches;
+        if (rep->relres)
+            for (int r = 0; r < nrhs; ++r) rep->relres[r] = out.rel[r];
+    }
+    if (out.status == VTM_E_DIVERGED) return fail(VTM_E_DIVERGED, "the iteration diverged");
+    if (out.status == VTM_E_MAXITER) return fail(VTM_E_MAXITER, "no convergence within the sweep limit");
+    return VTM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void vtm_default_options(vtm_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = VTM_FP64;
+    opt->nrhs_max = 1;
+    opt->check_every = 8;
+    opt->max_outer = 30;
+    opt->max_sweeps = 1000000;
+    opt->divergence = 1e6;
+    opt->inner_drop = 0.0;
+    opt->use_graph = 0;
+    opt->timing = 0;
+}
+
+const char* vtm_status_str(vtm_status s) {
+    switch (s) {
+        case VTM_OK: return "VTM_OK";
+        case VTM_E_ARG: return "VTM_E_ARG";
+        case VTM_E_UNTEARABLE: return "VTM_E_UNTEARABLE";
+        case VTM_E_SINGULAR: return "VTM_E_SINGULAR";
+        case VTM_E_DIVERGED: return "VTM_E_DIVERGED";
+        case VTM_E_MAXITER: return "VTM_E_MAXITER";
+        case VTM_E_HIP: return "VTM_E_HIP";
+        case VTM_E_OOM: return "VTM_E_OOM";
+        case VTM_E_UNSUPPORTED: return "VTM_E_UNSUPPORTED";
+    }
+    return "VTM_E_UNKNOWN";
+}
+
+const char* vtm_last_error(void) { return g_err.c_str(); }
+
+vtm_status vtm_plan(const vtm_csr* A, const int32_t* part, const double* Z, int64_t nZ, int64_t* n_sub,
+                    int64_t* n_wires, int32_t* wires, double* coef) {
+    vtm::Plan P;
+    std::string err;
+    vtm_status st = vtm::build_plan(A, part, Z, nZ, P, err);
+    if (st != VTM_OK) return fail(st, err);
+    if (n_sub) *n_sub = P.S;
+    if (n_wires) *n_wires = P.nwires;
+    for (int64_t e = 0; e < P.nwires; ++e) {
+        if (wires) {
+            wires[2 * e] = P.wi[e];
+            wires[2 * e + 1] = P.wj[e];
+        }
+        if (coef) {
+            const vtm::PortCoef k = vtm::port_coef(P.wg[e], P.wW[e]);
+            coef[4 * e + 0] = k.G;
+            coef[4 * e + 1] = k.c;
+            coef[4 * e + 2] = k.beta;
+            coef[4 * e + 3] = k.gamma;
+        }
+    }
+    return VTM_OK;
+}
+
+vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int64_t nZ,
+                     const vtm_options* opt, void* stream, vtm_handle* out) {
+    if (!out) return fail(VTM_E_ARG, "null output handle");
+    *out = nullptr;
+    vtm_options o;
+    vtm_default_options(&o);
+    if (opt) o = *opt;
+    if (o.precision < VTM_FP64 || o.precision > VTM_BF16_REFINE)
+        return fail(VTM_E_ARG, "unknown precision");
+    if (o.precision == VTM_BF16_REFINE) return fail(VTM_E_UNSUPPORTED, "BF16 path not built");
+    if (o.nrhs_max < 1 || o.nrhs_max > 256) return fail(VTM_E_ARG, "nrhs_max outside 1..256");
+    if (o.check_every < 1 || o.max_sweeps < 1 || o.max_outer < 0 || !(o.divergence > 0.0))
+        return fail(VTM_E_ARG, "bad iteration limits");
+
+    auto h = std::make_unique<vtm_handle_s>();
+    h->opt = o;
+    h->nrhs_max = o.nrhs_max;
+    h->stream = static_cast<hipStream_t>(stream);
+    std::string err;
+    vtm_status st = vtm::build_plan(A, part, Z, nZ, h->plan, err);
+    if (st != VTM_OK) return fail(st, err);
+    VTM_HIP(hipGetDevice(&h->device));
+    const vtm::Plan& P = h->plan;
+    hipStream_t s = h->stream;
+
+    VTM_HIP(h->rowptr.upload(P.rowptr, s));
+    VTM_HIP(h->col.upload(P.col, s));
+    VTM_HIP(h->val.upload(P.val, s));
+    if (!P.symmetric) {
+        std::vector<int32_t> rT, cT;
+        std::vector<double> vT;
+        vtm::transpose_csr(P, rT, cT, vT);
+        VTM_HIP(h->rowptrT.upload(rT, s));
+        VTM_HIP(h->colT.upload(cT, s));
+        VTM_HIP(h->valT.upload(vT, s));
+        VTM_HIP(hipStreamSynchronize(s));
+    }
+    VTM_HIP(h->perm.upload(P.perm, s));
+    VTM_HIP(h->iperm.upload(P.iperm, s));
+    VTM_HIP(h->sub_off.upload(P.sub_off, s));
+    VTM_HIP(h->kofs.upload(P.kofs, s));
+    VTM_HIP(h->dmod.upload(P.dmod, s));
+    VTM_HIP(h->port_off.upload(P.port_off, s));
+    VTM_HIP(h->port_node.upload(P.port_node, s));
+    VTM_HIP(h->port_slot.upload(P.port_slot, s));
+    VTM_HIP(h->port_twin.upload(P.port_twin, s));
+    VTM_HIP(h->abi2port.upload(P.abi2port, s));
+    VTM_HIP(h->flag.alloc(1));
+    VTM_HIP(hipMemsetAsync(h->flag.p, 0, sizeof(int), s));
+
+    const int64_t nk = P.kofs[P.S];
+    const int nr = h->nrhs_max;
+    VTM_HIP(h->bp.alloc(P.n * nr));
+    VTM_HIP(h->xp.alloc(P.n * nr));
+    VTM_HIP(h->partial.alloc(size_t(vtm::kResidBlocks) * nr * 2));
+    VTM_HIP(h->norms.alloc(size_t(2) * nr));
+    VTM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->h_norms), sizeof(double) * 2 * nr));
+    if (o.precision == VTM_FP64) {
+        VTM_HIP(h->c64.upload(P.pc, s));
+        VTM_HIP(h->beta64.upload(P.pbeta, s));
+        VTM_HIP(h->gamma64.upload(P.pgamma, s));
+        VTM_HIP(h->a64[0].alloc(P.nports * nr));
+        VTM_HIP(h->a64[1].alloc(P.nports * nr));
+        VTM_HIP(vtm::launch_fill<double>(P.nports * nr, 0.0, h->a64[0].p, s));
+        VTM_HIP(h->K64.alloc(nk));
+        VTM_HIP(vtm::launch_setup<double>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
+                                          h->val.p, h->dmod.p, h->K64.p, h->K64.p, h->flag.p, s));
+    } else {
+        VTM_HIP(h->c32.upload(to_float(P.pc), s));
+        VTM_HIP(h->beta32.upload(to_float(P.pbeta), s));
+        VTM_HIP(h->gamma32.upload(to_float(P.pgamma), s));
+        VTM_HIP(h->a32[0].alloc(P.nports * nr));
+        VTM_HIP(h->a32[1].alloc(P.nports * nr));
+        VTM_HIP(vtm::launch_fill<float>(P.nports * nr, 0.0f, h->a32[0].p, s));
+        VTM_HIP(h->rp.alloc(P.n * nr));
+        VTM_HIP(h->b32.alloc(P.n * nr));
+        VTM_HIP(h->d32.alloc(P.n * nr));
+        VTM_HIP(h->K32.alloc(nk));
+        DevBuf<double> scratch;
+        if (P.max_ns > vtm::kLdsSetupMax) VTM_HIP(scratch.alloc(nk));
+        VTM_HIP(vtm::launch_setup<float>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
+                                         h->val.p, h->dmod.p, h->K32.p, scratch.p, h->flag.p, s));
+        VTM_HIP(hipStreamSynchronize(s));
+    }
+    int flag = 0;
+    VTM_HIP(hipMemcpyAsync(&flag, h->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    VTM_HIP(hipStreamSynchronize(s));
+    if (flag & 1) return fail(VTM_E_SINGULAR, "a sub-circuit matrix is singular");
+    *out = h.release();
+    return VTM_OK;
+}
+
+vtm_status vtm_solve(vtm_handle h, const double* b, double* x, int32_t nrhs, double tol, vtm_report* rep) {
+    return solve_common(h, b, x, nrhs, tol, rep, false);
+}
+
+vtm_status vtm_solve_adjoint(vtm_handle h, const double* g, double* lambda, int32_t nrhs, double tol,
+                             vtm_report* rep) {
+    return solve_common(h, g, lambda, nrhs, tol, rep, true);
+}
+
+vtm_status vtm_grad(vtm_handle h, const double* x, const double* lambda, int32_t nrhs, const int32_t* branch_ij,
+                    int64_t m, double* dL_dg) {
+    if (!h) return fail(VTM_E_ARG, "null handle");
+    if (m < 0 || nrhs < 1 || (m > 0 && (!x || !lambda || !branch_ij || !dL_dg)))
+        return fail(VTM_E_ARG, "bad gradient arguments");
+    VTM_HIP(hipSetDevice(h->device));
+    VTM_HIP(vtm::launch_grad(m, int(h->plan.n), nrhs, x, lambda, branch_ij, dL_dg, h->stream));
+    VTM_HIP(hipStreamSynchronize(h->stream));
+    return VTM_OK;
+}
+
+vtm_status vtm_get_waves(vtm_handle h, double* waves, int32_t nrhs) {
+    if (!h || !waves || nrhs < 1 || nrhs > h->nrhs_max) return fail(VTM_E_ARG, "bad wave arguments");
+    VTM_HIP(hipSetDevice(h->device));
+    if (h->opt.precision == VTM_FP64)
+        VTM_HIP(vtm::launch_waves_io<double>(h->plan.nports, nrhs, h->abi2port.p, h->a64[0].p, waves, true,
+                                             h->stream));
+    else
+        VTM_HIP(vtm::launch_waves_io<float>(h->plan.nports, nrhs, h->abi2port.p, h->a32[0].p, waves, true,
+                                            h->stream));
+    VTM_HIP(hipStreamSynchronize(h->stream));
+    return VTM_OK;
+}
+
+vtm_status vtm_set_waves(vtm_handle h, const double* waves, int32_t nrhs) {
+    if (!h || !waves || nrhs < 1 || nrhs > h->nrhs_max) return fail(VTM_E_ARG, "bad wave arguments");
+    if (h->opt.precision != VTM_FP64) return fail(VTM_E_UNSUPPORTED, "resume needs the FP64 precision");
+    VTM_HIP(hipSetDevice(h->device));
+    VTM_HIP(vtm::launch_waves_io<double>(h->plan.nports, nrhs, h->abi2port.p, h->a64[0].p,
+                                         const_cast<double*>(waves), false, h->stream));
+    VTM_HIP(hipStreamSynchronize(h->stream));
+    h->waves_set = true;
+    return VTM_OK;
+}
+
+vtm_status vtm_info(vtm_handle h, int64_t* n, int64_t* n_sub, int64_t* n_wires, int64_t* inverse_bytes) {
+    if (!h) return fail(VTM_E_ARG, "null handle");
+    if (n) *n = h->plan.n;
+    if (n_sub) *n_sub = h->plan.S;
+    if (n_wires) *n_wires = h->plan.nwires;
+    if (inverse_bytes)
+        *inverse_bytes = h->plan.kofs[h->plan.S] * (h->opt.precision == VTM_FP64 ? 8 : 4);
+    return VTM_OK;
+}
+
+void vtm_destroy(vtm_handle h) {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+}  // extern "C"

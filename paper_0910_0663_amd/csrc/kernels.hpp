@@ -1,0 +1,79 @@
+// Launchers of the HIP kernels (gfx950).  All take the stream to run on and
+// return the launch status; none synchronizes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace vtm {
+
+// Largest sub-circuit whose local matrix is factored entirely in LDS.
+constexpr int kLdsSetupMax = 80;
+
+struct PortArrays {
+    const int32_t* off;    // [S + 1]
+    const int32_t* node;   // local node of each port
+    const int32_t* slot;   // rank among the ports of its node
+    const int32_t* twin;   // port receiving this port's outgoing wave
+    int max_slot;
+};
+
+// ---- setup ----------------------------------------------------------------
+// Forms K_s = A_ss + diag(dmod) (the cut branch g replaced by the port
+// conductance G at every port node) for every sub-circuit and writes K_s^-1,
+// column-major, into out + kofs[s].  Sub-circuits with ns <= kLdsSetupMax are
+// inverted in LDS; larger ones are assembled into scratch64 (FP64, same
+// offsets; may equal out when TO is double) and inverted there by a blocked
+// Gauss-Jordan elimination with partial pivoting.  flag bit 0 = singular.
+template <typename TO>
+hipError_t launch_setup(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs,
+                        const int32_t* rowptr, const int32_t* col, const double* val,
+                        const double* dmod, TO* out, double* scratch64, int* flag,
+                        hipStream_t st);
+
+// ---- sweep ----------------------------------------------------------------
+// One VTM sweep for every sub-circuit (one workgroup each): right-hand side
+// b + c * a at the port nodes, x = K^-1 rhs (K^-T when adjoint), then the
+// outgoing wave beta * x + gamma * a sent to the twin port in a_next.
+// Vectors are [rows][nrhs] (right-hand side fastest).
+template <typename TO, typename TV>
+hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t* kofs,
+                        const int32_t* sub_off, PortArrays ports, const TV* pc, const TV* pbeta,
+                        const TV* pgamma, const TV* b, const TV* a_cur, TV* a_next, TV* x,
+                        bool adjoint, hipStream_t st);
+
+// ---- residual -------------------------------------------------------------
+// r = b - A x in FP64 on the untorn (renumbered) A; per right-hand side
+// sums of r^2 and b^2 land in norms[2 * rhs + {0, 1}] (fixed summation order).
+// r_out may be null.  partial must hold kResidBlocks * nrhs * 2 doubles.
+constexpr int kResidBlocks = 1024;
+template <typename TX>
+hipError_t launch_residual(int n, int nrhs, const int32_t* rowptr, const int32_t* col,
+                           const double* val, const double* b, const TX* x, double* r_out,
+                           double* partial, double* norms, hipStream_t st);
+
+// ---- vector utilities -------------------------------------------------------
+// dst[i][r] = src[r][perm[i]]   (column-major caller layout -> renumbered rows)
+hipError_t launch_gather(int n, int nrhs, const int32_t* perm, const double* src, double* dst,
+                         hipStream_t st);
+// dst[r][j] = src[iperm[j]][r]
+hipError_t launch_scatter(int n, int nrhs, const int32_t* iperm, const double* src, double* dst,
+                          hipStream_t st);
+template <typename T>
+hipError_t launch_fill(int64_t count, T value, T* dst, hipStream_t st);
+// dst = (TD) src
+template <typename TS, typename TD>
+hipError_t launch_convert(int64_t count, const TS* src, TD* dst, hipStream_t st);
+// x += (double) d
+template <typename TD>
+hipError_t launch_add(int64_t count, const TD* d, double* x, hipStream_t st);
+// out[r][q] = a[abi2port[q]][r] (get) or a[abi2port[q]][r] = in[r][q] (set)
+template <typename TV>
+hipError_t launch_waves_io(int64_t np, int nrhs, const int32_t* abi2port, TV* a, double* abi,
+                           bool to_abi, hipStream_t st);
+// dL_dg[e] = -sum_r (lam_i - lam_j)(x_i - x_j)
+hipError_t launch_grad(int64_t m, int n, int nrhs, const double* x, const double* lam,
+                       const int32_t* ij, double* dL_dg, hipStream_t st);
+
+}  // namespace vtm

@@ -1,0 +1,283 @@
+// Host tearing planner (Section V, Steps 1-4, in the edge-cut reading).
+//
+// A branch i --g-- j whose nodes lie in different sub-circuits is cut at its
+// middle: i --2g-- m --2g-- j.  The middle node m is split into two twins, one
+// per side, joined by a lossless line of admittance W.  Eliminating a twin from
+// its sub-circuit (twin equation 2g(v - u_i) + W v = a) leaves, at node i:
+//   - the cut branch g replaced by a port conductance G = 2gW / (2g + W)
+//     on the diagonal (the "C + W" block of eq. 11 after elimination),
+//   - the incident wave a entering the right-hand side as c * a, c = 2g/(2g+W),
+//   - the outgoing wave W v - i = 2 W v - a = beta * u_i + gamma * a with
+//     beta = 4gW/(2g+W), gamma = (W - 2g)/(2g+W) (eq. 11, second line).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <numeric>
+
+namespace vtm {
+
+PortCoef port_coef(double g, double W) {
+    const double s = 2.0 * g + W;
+    return PortCoef{2.0 * g * W / s, 2.0 * g / s, 4.0 * g * W / s, (W - 2.0 * g) / s};
+}
+
+namespace {
+
+struct Entry {
+    int32_t c;
+    double v;
+};
+
+}  // namespace
+
+vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, int64_t nZ,
+                      Plan& P, std::string& err) {
+    if (!A || !part || !Z || !A->rowptr || (!A->col && A->nnz) || (!A->val && A->nnz)) {
+        err = "null argument";
+        return VTM_E_ARG;
+    }
+    const int64_t n = A->n, nnz = A->nnz;
+    if (n <= 0 || nnz < 0) {
+        err = "n must be positive and nnz non-negative";
+        return VTM_E_ARG;
+    }
+    if (n > std::numeric_limits<int32_t>::max() || nnz > std::numeric_limits<int32_t>::max()) {
+        err = "n and nnz must fit int32";
+        return VTM_E_UNSUPPORTED;
+    }
+    if (A->rowptr[0] != 0 || A->rowptr[n] != nnz) {
+        err = "rowptr must start at 0 and end at nnz";
+        return VTM_E_ARG;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (A->rowptr[i + 1] < A->rowptr[i]) {
+            err = "rowptr must be non-decreasing";
+            return VTM_E_ARG;
+        }
+    for (int64_t k = 0; k < nnz; ++k) {
+        if (A->col[k] < 0 || A->col[k] >= n) {
+            err = "column index out of range";
+            return VTM_E_ARG;
+        }
+        if (!std::isfinite(A->val[k])) {
+            err = "non-finite matrix entry";
+            return VTM_E_ARG;
+        }
+    }
+
+    // ---- labels -------------------------------------------------------------
+    int64_t S = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (part[i] < 0) {
+            err = "negative sub-circuit label";
+            return VTM_E_ARG;
+        }
+        S = std::max<int64_t>(S, int64_t(part[i]) + 1);
+    }
+    std::vector<int32_t> count(S, 0);
+    for (int64_t i = 0; i < n; ++i) count[part[i]]++;
+    for (int64_t s = 0; s < S; ++s)
+        if (count[s] == 0) {
+            err = "sub-circuit label " + std::to_string(s) + " is unused";
+            return VTM_E_ARG;
+        }
+    P.n = n;
+    P.S = S;
+    P.sub_off.assign(S + 1, 0);
+    for (int64_t s = 0; s < S; ++s) P.sub_off[s + 1] = P.sub_off[s] + count[s];
+    P.max_ns = *std::max_element(count.begin(), count.end());
+    if (P.max_ns > 2048) {
+        err = "a sub-circuit has more than 2048 nodes";
+        return VTM_E_UNSUPPORTED;
+    }
+    P.perm.resize(n);
+    P.iperm.resize(n);
+    {
+        std::vector<int32_t> fill(P.sub_off.begin(), P.sub_off.end() - 1);
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t r = fill[part[i]]++;
+            P.perm[r] = int32_t(i);
+            P.iperm[i] = r;
+        }
+    }
+    P.kofs.assign(S + 1, 0);
+    for (int64_t s = 0; s < S; ++s) P.kofs[s + 1] = P.kofs[s] + int64_t(count[s]) * count[s];
+
+    // ---- rows with merged duplicates and sorted columns (old numbering) -------
+    std::vector<int64_t> mrow(n + 1, 0);
+    std::vector<Entry> ment;
+    ment.reserve(nnz);
+    {
+        std::vector<Entry> row;
+        for (int64_t i = 0; i < n; ++i) {
+            row.clear();
+            for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) row.push_back({A->col[k], A->val[k]});
+            std::sort(row.begin(), row.end(), [](const Entry& a, const Entry& b) { return a.c < b.c; });
+            size_t start = ment.size();
+            for (const Entry& e : row) {
+                if (ment.size() > start && ment.back().c == e.c)
+                    ment.back().v += e.v;
+                else
+                    ment.push_back(e);
+            }
+            // explicit zeros off the diagonal couple nothing
+            size_t w = start;
+            for (size_t k = start; k < ment.size(); ++k)
+                if (ment[k].v != 0.0 || ment[k].c == i) ment[w++] = ment[k];
+            ment.resize(w);
+            mrow[i + 1] = int64_t(ment.size());
+        }
+    }
+
+    // ---- exact symmetry (lets the adjoint share the forward path) -------------
+    auto find = [&](int64_t r, int32_t c, double& v) -> bool {
+        auto lo = ment.begin() + mrow[r], hi = ment.begin() + mrow[r + 1];
+        auto it = std::lower_bound(lo, hi, c, [](const Entry& e, int32_t cc) { return e.c < cc; });
+        if (it == hi || it->c != c) return false;
+        v = it->v;
+        return true;
+    };
+    P.symmetric = true;
+    for (int64_t i = 0; i < n && P.symmetric; ++i)
+        for (int64_t k = mrow[i]; k < mrow[i + 1]; ++k) {
+            double v;
+            if (!find(ment[k].c, int32_t(i), v) || v != ment[k].v) {
+                P.symmetric = false;
+                break;
+            }
+        }
+
+    // ---- cut wires (canonical order falls out of the row scan) ----------------
+    P.wi.clear();
+    P.wj.clear();
+    P.wg.clear();
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = mrow[i]; k < mrow[i + 1]; ++k) {
+            const int32_t j = ment[k].c;
+            if (part[i] == part[j]) continue;
+            double vt;
+            if (!find(j, int32_t(i), vt) || vt != ment[k].v) {
+                err = "coupling between nodes " + std::to_string(i) + " and " + std::to_string(j) +
+                      " in different sub-circuits is not symmetric";
+                return VTM_E_UNTEARABLE;
+            }
+            if (!(ment[k].v < 0.0)) {
+                err = "coupling between nodes " + std::to_string(i) + " and " + std::to_string(j) +
+                      " in different sub-circuits is not a positive conductance";
+                return VTM_E_UNTEARABLE;
+            }
+            if (j > i) {
+                P.wi.push_back(int32_t(i));
+                P.wj.push_back(j);
+                P.wg.push_back(-ment[k].v);
+            }
+        }
+    const int64_t nw = int64_t(P.wi.size());
+    P.nwires = nw;
+    P.nports = 2 * nw;
+    if (nZ != 1 && nZ != nw) {
+        err = "nZ must be 1 or the number of cut wires (" + std::to_string(nw) + ")";
+        return VTM_E_ARG;
+    }
+    P.wW.resize(nw);
+    for (int64_t e = 0; e < nw; ++e) {
+        const double z = Z[nZ == 1 ? 0 : e];
+        if (!(z > 0.0) || !std::isfinite(z)) {
+            err = "line impedance must be positive and finite";
+            return VTM_E_ARG;
+        }
+        P.wW[e] = 1.0 / z;
+    }
+
+    // ---- ports -----------------------------------------------------------------
+    // key per ABI port q (2e lower node, 2e+1 upper): (sub, local node, wire)
+    const int64_t np = P.nports;
+    std::vector<int32_t> q_sub(np), q_loc(np);
+    for (int64_t e = 0; e < nw; ++e) {
+        for (int side = 0; side < 2; ++side) {
+            const int32_t node = side ? P.wj[e] : P.wi[e];
+            const int64_t q = 2 * e + side;
+            q_sub[q] = part[node];
+            q_loc[q] = P.iperm[node] - P.sub_off[part[node]];
+        }
+    }
+    std::vector<int64_t> order(np);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        if (q_sub[a] != q_sub[b]) return q_sub[a] < q_sub[b];
+        if (q_loc[a] != q_loc[b]) return q_loc[a] < q_loc[b];
+        return a < b;
+    });
+    P.port_off.assign(S + 1, 0);
+    P.port_node.resize(np);
+    P.port_slot.resize(np);
+    P.port_twin.resize(np);
+    P.abi2port.resize(np);
+    P.pc.resize(np);
+    P.pbeta.resize(np);
+    P.pgamma.resize(np);
+    P.dmod.assign(n, 0.0);
+    P.max_slot = 0;
+    for (int64_t p = 0; p < np; ++p) {
+        const int64_t q = order[p];
+        P.abi2port[q] = int32_t(p);
+        P.port_off[q_sub[q] + 1]++;
+        P.port_node[p] = q_loc[q];
+        P.port_slot[p] = (p > 0 && q_sub[order[p - 1]] == q_sub[q] && q_loc[order[p - 1]] == q_loc[q])
+                             ? P.port_slot[p - 1] + 1
+                             : 0;
+        P.max_slot = std::max(P.max_slot, P.port_slot[p]);
+        const int64_t e = q / 2;
+        const PortCoef k = port_coef(P.wg[e], P.wW[e]);
+        P.pc[p] = k.c;
+        P.pbeta[p] = k.beta;
+        P.pgamma[p] = k.gamma;
+        const int32_t node = (q & 1) ? P.wj[e] : P.wi[e];
+        P.dmod[P.iperm[node]] += k.G - P.wg[e];
+    }
+    for (int64_t s = 0; s < S; ++s) P.port_off[s + 1] += P.port_off[s];
+    for (int64_t q = 0; q < np; ++q) P.port_twin[P.abi2port[q]] = P.abi2port[q ^ 1];
+
+    // ---- renumbered untorn matrix ------------------------------------------------
+    P.rowptr.assign(n + 1, 0);
+    P.col.resize(ment.size());
+    P.val.resize(ment.size());
+    {
+        std::vector<Entry> row;
+        int64_t w = 0;
+        for (int64_t r = 0; r < n; ++r) {
+            const int32_t i = P.perm[r];
+            row.clear();
+            for (int64_t k = mrow[i]; k < mrow[i + 1]; ++k) row.push_back({P.iperm[ment[k].c], ment[k].v});
+            std::sort(row.begin(), row.end(), [](const Entry& a, const Entry& b) { return a.c < b.c; });
+            for (const Entry& e : row) {
+                P.col[w] = e.c;
+                P.val[w] = e.v;
+                ++w;
+            }
+            P.rowptr[r + 1] = int32_t(w);
+        }
+    }
+    return VTM_OK;
+}
+
+void transpose_csr(const Plan& P, std::vector<int32_t>& rowptr, std::vector<int32_t>& col,
+                   std::vector<double>& val) {
+    const int64_t n = P.n, nnz = int64_t(P.col.size());
+    rowptr.assign(n + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k) rowptr[P.col[k] + 1]++;
+    for (int64_t i = 0; i < n; ++i) rowptr[i + 1] += rowptr[i];
+    col.resize(nnz);
+    val.resize(nnz);
+    std::vector<int32_t> fill(rowptr.begin(), rowptr.end() - 1);
+    for (int64_t r = 0; r < n; ++r)  // rows ascending -> columns of A^T come out sorted
+        for (int32_t k = P.rowptr[r]; k < P.rowptr[r + 1]; ++k) {
+            const int32_t w = fill[P.col[k]]++;
+            col[w] = int32_t(r);
+            val[w] = P.val[k];
+        }
+}
+
+}  // namespace vtm

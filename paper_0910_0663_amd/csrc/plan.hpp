@@ -1,0 +1,63 @@
+// Host tearing planner: turns (A, node partition, Z) into the per-sub-circuit
+// data the device kernels consume.  Integer work plus the per-wire port
+// coefficients; no device calls.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "vtm.h"
+
+namespace vtm {
+
+struct Plan {
+    int64_t n = 0;        // nodes
+    int64_t S = 0;        // sub-circuits
+    int64_t nwires = 0;   // cut wires
+    int64_t nports = 0;   // 2 * nwires
+    int32_t max_ns = 0;   // largest sub-circuit
+    int32_t max_slot = 0; // most ports on one node, minus one
+    bool symmetric = false;
+
+    // Sub-circuit-major renumbering: new id = position after a stable sort by label.
+    std::vector<int32_t> perm;     // new -> old
+    std::vector<int32_t> iperm;    // old -> new
+    std::vector<int32_t> sub_off;  // [S + 1] first new id of each sub-circuit
+    std::vector<int64_t> kofs;     // [S + 1] element offset of each dense inverse
+
+    // Cut wires in canonical order (lower node, then upper node, ascending; old ids).
+    std::vector<int32_t> wi, wj;
+    std::vector<double> wg;        // branch conductance g = -A_ij
+    std::vector<double> wW;        // line admittance W = 1 / Z
+
+    // Ports: two per wire, grouped by sub-circuit, inside one by (local node, wire).
+    std::vector<int32_t> port_off;   // [S + 1]
+    std::vector<int32_t> port_node;  // local node index inside its sub-circuit
+    std::vector<int32_t> port_slot;  // rank among the ports of the same node
+    std::vector<int32_t> port_twin;  // the other port of the same wire
+    std::vector<int32_t> abi2port;   // [2 * nwires]: ABI port (2e lower, 2e+1 upper) -> port
+    std::vector<double> pc, pbeta, pgamma;  // per port: c, beta, gamma
+
+    std::vector<double> dmod;      // per new node: sum over its ports of (G - g)
+
+    // The untorn A renumbered (rows and columns), duplicates merged, columns sorted.
+    std::vector<int32_t> rowptr, col;
+    std::vector<double> val;
+};
+
+// Builds the plan; on failure returns the status and sets err.
+vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, int64_t nZ,
+                      Plan& plan, std::string& err);
+
+// Renumbered A^T in compressed rows (columns sorted).
+void transpose_csr(const Plan& plan, std::vector<int32_t>& rowptr, std::vector<int32_t>& col,
+                   std::vector<double>& val);
+
+// Port coefficients of a cut wire with conductance g and line admittance W.
+struct PortCoef {
+    double G, c, beta, gamma;
+};
+PortCoef port_coef(double g, double W);
+
+}  // namespace vtm

@@ -1,0 +1,246 @@
+"""Parity of the HIP path (called through the C ABI) with the CPU oracle.
+
+Tolerances (FP64 path): iterates are compared element by element after the
+same number of sweeps.  Each sweep rounds a dense dot product of at most n_s
+terms (relative error <= n_s * 2^-53 ~ 3e-14 for n_s = 256) and the iteration
+contracts errors by rho < 1 per sweep, so the accumulated difference stays
+below n_s * 2^-53 / (1 - rho); with rho <= 0.99 that is <= 3e-12.  The tests
+use 1e-11 relative to max |x|.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+ITER_RTOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU tests need a HIP device"
+    return T
+
+
+def vtm():
+    import paper_0910_0663_amd as v
+    return v
+
+
+def to_dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def oracle_iterates(w, ks, b=None, transpose=False):
+    A = w.A.T.tocsr() if transpose else w.A
+    torn = oracle.tear_wires(A, w.part, w.Z)
+    sw = oracle.Sweeper(torn)
+    b = w.b if b is None else b
+    f = torn.src @ b.T
+    a = np.zeros((2, torn.n_lines, b.shape[0]))
+    out = {}
+    for k in range(1, max(ks) + 1):
+        u, a = sw.sweep(f, a)
+        if k in ks:
+            out[k] = (torn.out @ u).T
+    return out
+
+
+def gpu_iterate(torch, w, k, b=None, adjoint=False, nrhs_max=None):
+    """x^k of the HIP path: max_sweeps = k with an unreachable tolerance."""
+    b = w.b if b is None else b
+    s = vtm().Solver(w.A, w.part, w.Z, nrhs_max=nrhs_max or b.shape[0], check_every=1, max_sweeps=k)
+    x = torch.empty((b.shape[0], w.n), dtype=torch.float64, device="cuda")
+    fn = s.solve_adjoint if adjoint else s.solve
+    with pytest.raises(vtm().VTMError) as ei:
+        fn(to_dev(torch, b), 1e-300, x)
+    assert ei.value.name == "VTM_E_MAXITER"
+    assert ei.value.report.sweeps == k
+    s.close()
+    return x.cpu().numpy()
+
+
+def assert_close(x, ref, rtol=ITER_RTOL):
+    scale = np.abs(ref).max()
+    err = np.abs(x - ref).max()
+    assert err <= rtol * scale, f"max err {err:.3e} vs scale {scale:.3e}"
+
+
+@pytest.mark.parametrize("cfg,kw", [
+    (1, dict()),
+    (3, dict(dims=(16, 16, 16))),
+    (4, dict(dims=(64, 64), nrhs=3)),
+    (2, dict(dims=(64, 64))),
+])
+def test_iterates_match_oracle(torch, cfg, kw):
+    """x^k of the GPU equals the oracle's x^k element by element (several tiles,
+    uneven sub-circuits, an unsymmetric circuit, several right-hand sides)."""
+    w = workloads.make(cfg, **kw)
+    ks = [1, 2, 7, 40]
+    ref = oracle_iterates(w, ks)
+    for k in ks:
+        assert_close(gpu_iterate(torch, w, k), ref[k])
+
+
+def test_config1_sweeps_and_solution(torch):
+    """64x64 grid, 4x4 sub-circuits of 16x16, tol 1e-10, residual checked every
+    sweep: the same sweep count as the oracle (within one for rounding at the
+    threshold), the same iterate, and the fixed point of the direct solve."""
+    w = workloads.make(1)
+    r = oracle.vtm_solve(oracle.tear_wires(w.A, w.part, w.Z), w.A, w.b, w.tol)
+    s = vtm().Solver(w.A, w.part, w.Z, check_every=1)
+    x, rep = s.solve(to_dev(torch, w.b), w.tol)
+    assert abs(rep.sweeps - r.sweeps) <= 1
+    ref = oracle_iterates(w, [rep.sweeps])[rep.sweeps]
+    assert_close(x.cpu().numpy(), ref)
+    assert oracle.relative_residual(w.A, w.b, x.cpu().numpy()).max() <= w.tol
+    xs = oracle.direct_solve(w.A, w.b)
+    assert np.abs(x.cpu().numpy() - xs).max() <= 1e-8 * np.abs(xs).max()
+
+
+def test_config2_shape_scaled(torch):
+    """The 8x8-sub-circuit, log-uniform-conductance workload at 256x256 with a
+    check every 8 sweeps: the GPU stops within [oracle, oracle + 7] sweeps and
+    its iterate matches the oracle's at that count."""
+    w = workloads.make(2, dims=(256, 256))
+    r = oracle.vtm_solve(oracle.tear_wires(w.A, w.part, w.Z), w.A, w.b, w.tol)
+    s = vtm().Solver(w.A, w.part, w.Z, check_every=8)
+    x, rep = s.solve(to_dev(torch, w.b), w.tol)
+    assert r.sweeps <= rep.sweeps <= r.sweeps + 7
+    ref = oracle_iterates(w, [rep.sweeps])[rep.sweeps]
+    assert_close(x.cpu().numpy(), ref)
+
+
+def test_zero_rhs_and_single_subcircuit(torch):
+    w = workloads.make(1, dims=(32, 32))
+    s = vtm().Solver(w.A, w.part, w.Z)
+    x, rep = s.solve(torch.zeros((1, w.n), dtype=torch.float64, device="cuda"), 1e-10)
+    assert rep.sweeps == 0 and not x.any().item()
+    one = vtm().Solver(w.A, np.zeros(w.n, np.int32), 1.0, check_every=1)
+    assert one.n_wires == 0
+    x1, rep1 = one.solve(to_dev(torch, w.b), 1e-13)
+    assert rep1.sweeps == 1
+    assert_close(x1.cpu().numpy(), np.linalg.solve(w.A.toarray(), w.b.ravel())[None], rtol=1e-12)
+
+
+def test_maxiter_divergence_and_arguments(torch):
+    V = vtm()
+    w = workloads.make(1, dims=(32, 32))
+    s = V.Solver(w.A, w.part, w.Z, check_every=4, max_sweeps=10)
+    with pytest.raises(V.VTMError) as ei:
+        s.solve(to_dev(torch, w.b), 1e-12)
+    assert ei.value.name == "VTM_E_MAXITER" and ei.value.report.sweeps == 10
+    # divergence forced from the host: any residual above 1e-3 counts as diverged,
+    # and the first iterate's residual is far above that
+    d = V.Solver(w.A, w.part, w.Z, check_every=1, divergence=1e-3)
+    with pytest.raises(V.VTMError) as ei:
+        d.solve(to_dev(torch, w.b), 1e-12)
+    assert ei.value.name == "VTM_E_DIVERGED" and ei.value.report.sweeps == 1
+    with pytest.raises(V.VTMError) as ei:
+        s.solve(to_dev(torch, np.ones((2, w.n))), 1e-8)   # nrhs above nrhs_max
+    assert ei.value.name == "VTM_E_ARG"
+    A = w.A.tolil()
+    A[0, 900] = 0.2
+    with pytest.raises(V.VTMError) as ei:
+        V.Solver(A.tocsr(), w.part, w.Z)
+    assert ei.value.name == "VTM_E_UNTEARABLE"
+
+
+def test_resume_from_waves_is_bitwise_continuation(torch):
+    """The iteration state is the wave vector: stopping after 24 sweeps,
+    exporting and re-importing the waves, and continuing gives bitwise the same
+    iterate as an uninterrupted run."""
+    V = vtm()
+    w = workloads.make(1)
+    b = to_dev(torch, w.b)
+    full = V.Solver(w.A, w.part, w.Z, check_every=8)
+    x_full, rep_full = full.solve(b, w.tol)
+    part = V.Solver(w.A, w.part, w.Z, check_every=8, max_sweeps=24)
+    x_tmp = torch.empty_like(b)
+    with pytest.raises(V.VTMError):
+        part.solve(b, w.tol, x_tmp)
+    waves = part.get_waves()
+    cont = V.Solver(w.A, w.part, w.Z, check_every=8)
+    cont.set_waves(waves)
+    x_cont, rep_cont = cont.solve(b, w.tol)
+    assert rep_cont.sweeps + 24 == rep_full.sweeps
+    assert torch.equal(x_cont, x_full)
+
+
+def test_repeat_runs_are_bitwise_identical(torch):
+    V = vtm()
+    w = workloads.make(4, dims=(96, 96), nrhs=2)
+    s = V.Solver(w.A, w.part, w.Z, nrhs_max=2)
+    b = to_dev(torch, w.b)
+    x1, r1 = s.solve(b, 1e-9)
+    x2, r2 = s.solve(b, 1e-9)
+    assert r1.sweeps == r2.sweeps and torch.equal(x1, x2)
+
+
+def test_adjoint_matches_oracle_on_unsymmetric_circuit(torch):
+    """VTM on A^T with the stored inverses read transposed: iterates equal the
+    oracle's VTM on the torn A^T, and the converged result is A^-T g."""
+    w = workloads.make(3, dims=(16, 16, 16))
+    g = np.random.default_rng(5).standard_normal((1, w.n))
+    ks = [1, 3, 25]
+    ref = oracle_iterates(w, ks, b=g, transpose=True)
+    for k in ks:
+        assert_close(gpu_iterate(torch, w, k, b=g, adjoint=True), ref[k])
+    s = vtm().Solver(w.A, w.part, w.Z)
+    lam, rep = s.solve_adjoint(to_dev(torch, g), 1e-11)
+    lam_ref = oracle.direct_adjoint(w.A, g)
+    assert np.abs(lam.cpu().numpy() - lam_ref).max() <= 1e-8 * np.abs(lam_ref).max()
+
+
+@pytest.mark.parametrize("cfg,dims", [(3, (16, 16, 32)), (5, (128, 128))])
+def test_fp32_refinement_reaches_fp64_tolerance(torch, cfg, dims):
+    """FP32 inverses and sweeps inside FP64 refinement reach relative residual
+    1e-8 (recomputed here in FP64 on the host) and the direct solution within
+    the conditioning bound of that residual."""
+    w = workloads.make(cfg, dims=dims)
+    s = vtm().Solver(w.A, w.part, w.Z, precision="fp32_refine")
+    x, rep = s.solve(to_dev(torch, w.b), w.tol)
+    xh = x.cpu().numpy()
+    assert oracle.relative_residual(w.A, w.b, xh).max() <= w.tol
+    assert rep.outer >= 1
+    xs = oracle.direct_solve(w.A, w.b)
+    assert np.abs(xh - xs).max() <= 2e-6 * np.abs(xs).max()
+
+
+def test_gradient_through_autograd_matches_oracle(torch):
+    """dL/db and dL/dg for L = sum over probes of x^2 through VTMSolve, against the
+    oracle's adjoint formula with direct solves."""
+    from paper_0910_0663_amd import Circuit, VTMSolve
+    w = workloads.make(5, dims=(64, 64), n_probes=256)
+    circ = Circuit(w.n, w.edges, w.ground, w.part, w.Z, tol=1e-10, precision="fp64")
+    g = torch.tensor(w.g, dtype=torch.float64, device="cuda", requires_grad=True)
+    b = torch.tensor(w.b[0], dtype=torch.float64, device="cuda", requires_grad=True)
+    x = VTMSolve.apply(b, g, circ)
+    probes = torch.as_tensor(w.probes, device="cuda")
+    loss = (x[probes] ** 2).sum()
+    loss.backward()
+    xs = oracle.direct_solve(w.A, w.b)
+    dLdx = np.zeros_like(xs)
+    dLdx[:, w.probes] = 2 * xs[:, w.probes]
+    lam = oracle.direct_adjoint(w.A, dLdx)
+    gref = oracle.branch_gradient(w.edges, xs, lam)
+    assert np.abs(b.grad.cpu().numpy() - lam[0]).max() <= 1e-7 * np.abs(lam).max()
+    assert np.abs(g.grad.cpu().numpy() - gref).max() <= 1e-7 * np.abs(gref).max()
+
+
+def test_full_size_config2_residual(torch):
+    """The bench workload at full size (2048^2 nodes, 65,536 sub-circuits of 8x8,
+    check every 8 sweeps): the returned x meets the FP64 relative residual 1e-8
+    recomputed on the host from the untorn A."""
+    w = workloads.make(2)
+    s = vtm().Solver(w.A, w.part, w.Z, check_every=8)
+    x, rep = s.solve(to_dev(torch, w.b), w.tol)
+    print(f"full-size sweeps {rep.sweeps} relres {rep.relres_max:.3e} solve_ms {rep.solve_ms:.1f}", flush=True)
+    rel = oracle.relative_residual(w.A, w.b, x.cpu().numpy()).max()
+    assert rel <= w.tol
+    assert abs(rel - rep.relres_max) <= 1e-3 * rel

@@ -90,6 +90,9 @@ def main():
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="for rocprofv3 --pmc: 16 sweeps of the workload, then a 1 GiB device copy "
+                         "(known bytes) to calibrate the counters; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the VTM path here is built and measured on a single "
@@ -114,6 +117,18 @@ def main():
     log(f"setup {setup_s:.2f} s: wires={s.n_wires} inverse bytes={s.inverse_bytes}")
     b = torch.as_tensor(w.b, dtype=torch.float64, device="cuda")
     x = torch.empty_like(b)
+    if args.counters:
+        c = vtm.Solver(w.A, w.part, w.Z, check_every=16, max_sweeps=16)
+        try:
+            c.solve(b, w.tol, x)
+        except vtm.VTMError as e:
+            log(f"counter run: {e.name} after {e.report.sweeps} sweeps")
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read, 1 GiB written")
+        return
     for k in range(args.warmup):
         _, rep = s.solve(b, w.tol, x)
         log(f"warmup {k}: sweeps {rep.sweeps} relres {rep.relres_max:.3e} {rep.solve_ms:.1f} ms")

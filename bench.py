@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "VTM time-to-1e-8 residual and sweeps/s; mixed/batched vs plain FP64 speedup"
 COUNTERS = os.path.join(ROOT, "profiles", "sweep_cfg2_counters.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_0910_0663_amd", "csrc", "kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_0910_0663_amd", "csrc", "sweep.hip")
 
 
 def log(*a):

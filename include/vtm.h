@@ -75,6 +75,11 @@ typedef struct {
                                (1e-5 for FP32, 1e-2 for BF16)                        */
     int32_t use_graph;      /* replay each check interval as one captured hipGraph   */
     int32_t timing;         /* 1: time every sweep launch with HIP events (report)   */
+    int32_t adaptive_checks;/* 1: once the residual falls steadily, skip checks that
+                               cannot reach tol: the next check comes after half the
+                               predicted remaining sweeps (a multiple of check_every,
+                               at most 64 of them); 0: check every check_every      */
+    int32_t reserved;
 } vtm_options;
 
 typedef struct {
@@ -91,7 +96,8 @@ typedef struct {
 typedef struct vtm_handle_s *vtm_handle;
 
 /* Fills *opt with defaults: FP64, nrhs_max 1, check_every 8, max_outer 30,
- * max_sweeps 1000000, divergence 1e6, inner_drop 0, use_graph 0, timing 0. */
+ * max_sweeps 1000000, divergence 1e6, inner_drop 0, use_graph 0, timing 0,
+ * adaptive_checks 1. */
 void vtm_default_options(vtm_options *opt);
 
 /*
@@ -131,7 +137,10 @@ vtm_status vtm_setup(const vtm_csr *A, const int32_t *part, const double *Z, int
  *
  * A zero column converges at once with x = 0.  With a refining precision the
  * sweeps run in FP32/BF16 on A d = r and x += d, r = b - A x in FP64, until
- * the FP64 residual meets tol (VTM_E_MAXITER after opt.max_outer).
+ * the FP64 residual meets tol (VTM_E_MAXITER after opt.max_outer).  Each inner
+ * solve starts from zero waves and stops when ||r - A d|| / ||r|| falls below
+ * max(inner_drop, tol * ||b|| / (2 ||r||)) for every column, or when three
+ * checks in a row bring no 1% improvement.
  */
 vtm_status vtm_solve(vtm_handle h, const double *b, double *x, int32_t nrhs, double tol,
                      vtm_report *rep);

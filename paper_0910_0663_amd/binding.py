@@ -43,7 +43,8 @@ class Csr(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("nrhs_max", C.c_int32), ("check_every", C.c_int32),
                 ("max_outer", C.c_int32), ("max_sweeps", C.c_int64), ("divergence", C.c_double),
-                ("inner_drop", C.c_double), ("use_graph", C.c_int32), ("timing", C.c_int32)]
+                ("inner_drop", C.c_double), ("use_graph", C.c_int32), ("timing", C.c_int32),
+                ("adaptive_checks", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -162,7 +163,7 @@ class Solver:
 
     def __init__(self, A, part, Z, precision="fp64", nrhs_max=1, check_every=8,
                  max_sweeps=1_000_000, divergence=1e6, inner_drop=0.0, max_outer=30,
-                 use_graph=False, timing=False, stream=None):
+                 use_graph=False, timing=False, adaptive_checks=True, stream=None):
         import torch
         L = lib()
         if not torch.cuda.is_available():
@@ -179,6 +180,7 @@ class Solver:
         opt.max_outer = int(max_outer)
         opt.use_graph = 1 if use_graph else 0
         opt.timing = 1 if timing else 0
+        opt.adaptive_checks = 1 if adaptive_checks else 0
         self.precision = precision
         self.nrhs_max = int(nrhs_max)
         self.stream = stream if stream is not None else torch.cuda.current_stream()

@@ -178,12 +178,46 @@ struct IterOut {
     vtm_status status = VTM_OK;
 };
 
-// Plain FP64 VTM on (bp -> xp), checking every m sweeps.  Waves start at zero
-// unless resume is set.
+// Where the next residual check goes.  With adaptive checks, once two checks
+// show the residual falling, the per-sweep rate predicts the sweeps left to the
+// target; the next check comes after half of them (a multiple of m, at most
+// 64 m), so checks thin out far from the target and return to every m sweeps
+// near it.
+struct Cadence {
+    int64_t m = 1;
+    bool adaptive = false;
+    int64_t s_prev = -1, s_last = -1;
+    double r_prev = 0.0, r_last = 0.0;
+    void record(int64_t s, double r) {
+        s_prev = s_last;
+        r_prev = r_last;
+        s_last = s;
+        r_last = r;
+    }
+    int64_t next(double target) const {
+        if (!adaptive || s_prev < 0 || !(r_last < r_prev) || !(r_last > 0.0) || !(target > 0.0) ||
+            !(r_last > target))
+            return m;
+        const double rate = std::log(r_last / r_prev) / double(s_last - s_prev);  // < 0
+        const double left = std::log(target / r_last) / rate;                       // > 0
+        const int64_t k = int64_t(0.5 * left / double(m)) * m;
+        return std::min<int64_t>(std::max<int64_t>(k, m), 64 * m);
+    }
+};
+
+double max_of(const std::vector<double>& v) {
+    double mx = 0.0;
+    for (double x : v) mx = std::isnan(x) ? x : std::max(mx, x);
+    return mx;
+}
+
+// Plain FP64 VTM on (bp -> xp).  Waves start at zero unless resume is set.
 vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resume, IterOut& out) {
     const vtm::Plan& P = h->plan;
     const int64_t np = P.nports * nrhs;
-    const int m = h->opt.check_every;
+    Cadence cad;
+    cad.m = h->opt.check_every;
+    cad.adaptive = h->opt.adaptive_checks != 0;
     int cur = 0;
     if (!resume) VTM_HIP(vtm::launch_fill<double>(np, 0.0, h->a64[0].p, h->stream));
     VTM_HIP(vtm::launch_fill<double>(P.n * nrhs, 0.0, h->xp.p, h->stream));
@@ -197,8 +231,9 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
         return true;
     };
     if (done(out.rel)) return VTM_OK;
+    if (!resume) cad.record(0, max_of(out.rel));
     while (true) {
-        const int64_t chunk = std::min<int64_t>(m, h->opt.max_sweeps - out.sweeps);
+        const int64_t chunk = std::min<int64_t>(cad.next(tol), h->opt.max_sweeps - out.sweeps);
         for (int64_t k = 0; k < chunk; ++k) {
             st = sweep_once(h, false, nrhs, h->bp.p, h->xp.p, cur, adjoint);
             if (st != VTM_OK) return st;
@@ -221,6 +256,7 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
             out.status = VTM_E_MAXITER;
             break;
         }
+        cad.record(out.sweeps, max_of(out.rel));
     }
     // leave the latest waves in buffer 0 for export / resume
     if (cur == 1)
@@ -233,18 +269,17 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
 vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut& out) {
     const vtm::Plan& P = h->plan;
     const int64_t nv = P.n * nrhs, np = P.nports * nrhs;
-    const int m = h->opt.check_every;
     double drop = h->opt.inner_drop;
     if (!(drop > 0.0)) drop = h->opt.precision == VTM_BF16_REFINE ? 1e-2 : 1e-5;
     VTM_HIP(vtm::launch_fill<double>(nv, 0.0, h->xp.p, h->stream));
-    std::vector<double> rel, rnorm, e;
-    auto all_le = [](const std::vector<double>& v, double t) {
-        for (double x : v)
-            if (!(x <= t)) return false;
+    std::vector<double> rel, e, target(nrhs);
+    auto all_le = [](const std::vector<double>& v, const std::vector<double>& t) {
+        for (size_t i = 0; i < v.size(); ++i)
+            if (!(v[i] <= t[i])) return false;
         return true;
     };
     for (int outer = 0;; ++outer) {
-        // r = b - A x (FP64), stored for the inner solve
+        // r = b - A x (FP64), kept for the inner solve
         vtm_status st = residual<double>(h, h->bp.p, h->xp.p, nrhs, h->rp.p, rel, adjoint);
         if (st != VTM_OK) return st;
         ++out.checks;
@@ -254,19 +289,27 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
                 out.status = VTM_E_DIVERGED;
                 return VTM_OK;
             }
-        if (all_le(rel, tol)) return VTM_OK;
+        if (all_le(rel, std::vector<double>(nrhs, tol))) return VTM_OK;
         if (outer >= h->opt.max_outer) {
             out.status = VTM_E_MAXITER;
             return VTM_OK;
         }
+        // inner target relative to ||r||: enough for the outer tolerance, at most drop
+        for (int r = 0; r < nrhs; ++r) target[r] = rel[r] > 0.0 ? std::max(drop, 0.5 * tol / rel[r]) : 1.0;
         VTM_HIP((vtm::launch_convert<double, float>(nv, h->rp.p, h->b32.p, h->stream)));
         VTM_HIP(vtm::launch_fill<float>(np, 0.0f, h->a32[0].p, h->stream));
+        Cadence cad;
+        cad.m = h->opt.check_every;
+        cad.adaptive = h->opt.adaptive_checks != 0;
+        cad.record(0, 1.0);
+        double goal = 1.0;
+        for (int r = 0; r < nrhs; ++r) goal = std::min(goal, target[r]);
         int cur = 0;
         int64_t inner = 0;
         std::vector<double> best(nrhs, INFINITY);
         int since = 0;
         while (true) {
-            const int64_t chunk = std::min<int64_t>(m, h->opt.max_sweeps - inner);
+            const int64_t chunk = std::min<int64_t>(cad.next(goal), h->opt.max_sweeps - inner);
             for (int64_t k = 0; k < chunk; ++k) {
                 st = sweep_once(h, true, nrhs, h->b32.p, h->d32.p, cur, adjoint);
                 if (st != VTM_OK) return st;
@@ -292,7 +335,8 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
                 return VTM_OK;
             }
             since = improved ? 0 : since + 1;
-            if (all_le(e, drop) || since >= 3 || inner >= h->opt.max_sweeps) break;
+            if (all_le(e, target) || since >= 3 || inner >= h->opt.max_sweeps) break;
+            cad.record(inner, max_of(e));
         }
         out.sweeps += inner;
         VTM_HIP(vtm::launch_add<float>(nv, h->d32.p, h->xp.p, h->stream));
@@ -326,9 +370,7 @@ vtm_status solve_common(vtm_handle h, const double* b, double* x, int32_t nrhs, 
         rep->sweeps = out.sweeps;
         rep->outer = out.outer;
         rep->checks = out.checks;
-        double mx = 0.0;
-        for (double v : out.rel) mx = std::isnan(v) ? v : std::max(mx, v);
-        rep->relres_max = mx;
+        rep->relres_max = max_of(out.rel);
         rep->solve_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
         rep->sweep_kernel_ms = out.sweep_ms;
         rep->sweep_launches = out.launches;
@@ -356,6 +398,7 @@ void vtm_default_options(vtm_options* opt) {
     opt->inner_drop = 0.0;
     opt->use_graph = 0;
     opt->timing = 0;
+    opt->adaptive_checks = 1;
 }
 
 const char* vtm_status_str(vtm_status s) {
@@ -464,8 +507,11 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
         VTM_HIP(h->a64[1].alloc(P.nports * nr));
         VTM_HIP(vtm::launch_fill<double>(P.nports * nr, 0.0, h->a64[0].p, s));
         VTM_HIP(h->K64.alloc(nk));
+        DevBuf<double> scratch;
+        if (P.max_ns > vtm::kLdsSetupMax) VTM_HIP(scratch.alloc(nk));
         VTM_HIP(vtm::launch_setup<double>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
-                                          h->val.p, h->dmod.p, h->K64.p, h->K64.p, h->flag.p, s));
+                                          h->val.p, h->dmod.p, h->K64.p, scratch.p, h->flag.p, s));
+        VTM_HIP(hipStreamSynchronize(s));
     } else {
         VTM_HIP(h->c32.upload(to_float(P.pc), s));
         VTM_HIP(h->beta32.upload(to_float(P.pbeta), s));

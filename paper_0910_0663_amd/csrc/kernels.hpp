@@ -21,11 +21,11 @@ struct PortArrays {
 
 // ---- setup ----------------------------------------------------------------
 // Forms K_s = A_ss + diag(dmod) (the cut branch g replaced by the port
-// conductance G at every port node) for every sub-circuit and writes K_s^-1,
-// column-major, into out + kofs[s].  Sub-circuits with ns <= kLdsSetupMax are
-// inverted in LDS; larger ones are assembled into scratch64 (FP64, same
-// offsets; may equal out when TO is double) and inverted there by a blocked
-// Gauss-Jordan elimination with partial pivoting.  flag bit 0 = singular.
+// conductance G at every port node) for every sub-circuit and writes K_s^-1 in
+// the column-group layout of layout.hpp into out + kofs[s].  Sub-circuits with
+// ns <= kLdsSetupMax are inverted in LDS; larger ones are assembled into
+// scratch64 (FP64, same offsets, must be non-null then) and inverted there by a
+// blocked Gauss-Jordan elimination with partial pivoting.  flag bit 0 = singular.
 template <typename TO>
 hipError_t launch_setup(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs,
                         const int32_t* rowptr, const int32_t* col, const double* val,
@@ -33,10 +33,11 @@ hipError_t launch_setup(int S, int max_ns, const int32_t* sub_off, const int64_t
                         hipStream_t st);
 
 // ---- sweep ----------------------------------------------------------------
-// One VTM sweep for every sub-circuit (one workgroup each): right-hand side
-// b + c * a at the port nodes, x = K^-1 rhs (K^-T when adjoint), then the
-// outgoing wave beta * x + gamma * a sent to the twin port in a_next.
-// Vectors are [rows][nrhs] (right-hand side fastest).
+// One VTM sweep for every sub-circuit (one workgroup each, per block of up to 8
+// right-hand sides): right-hand side b + c * a at the port nodes,
+// x = K^-1 rhs (K^-T when adjoint), then the outgoing wave beta * x + gamma * a
+// sent to the twin port in a_next.  Vectors are [rows][nrhs] (right-hand side
+// fastest).
 template <typename TO, typename TV>
 hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t* kofs,
                         const int32_t* sub_off, PortArrays ports, const TV* pc, const TV* pbeta,

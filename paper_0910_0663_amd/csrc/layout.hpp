@@ -1,0 +1,35 @@
+// Storage layout of the per-sub-circuit inverses, shared by the setup kernels
+// (writers) and the sweep kernels (readers).
+//
+// An n x n inverse Kinv is stored in "column groups" of G = 16 / sizeof(T)
+// columns: for every group g the n rows follow one another, each row holding
+// its G consecutive entries, so one 16-byte load gives lane r the entries
+// (r, gG .. gG+G-1) and a wavefront's loads are contiguous.  Columns beyond the
+// last full group are stored column-major after the groups.  Each sub-circuit's
+// block starts at a multiple of 4 elements (16-byte aligned for FP32 and FP64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace vtm {
+
+template <typename T>
+struct Group {
+    static constexpr int G = 16 / int(sizeof(T));
+};
+
+// element offset of Kinv(r, c) inside a sub-circuit's block
+template <typename T>
+__host__ __device__ inline int64_t inv_offset(int n, int r, int c) {
+    constexpr int G = Group<T>::G;
+    const int full = (n / G) * G;
+    if (c < full) return (int64_t(c / G) * n + r) * G + (c % G);
+    return int64_t(full) * n + int64_t(c - full) * n + r;
+}
+
+// elements reserved for an n x n block (rounded up to a multiple of 4)
+__host__ __device__ inline int64_t inv_block_elems(int n) { return (int64_t(n) * n + 3) & ~int64_t(3); }
+
+}  // namespace vtm

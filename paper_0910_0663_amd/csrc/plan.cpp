@@ -102,8 +102,9 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
             P.iperm[i] = r;
         }
     }
+    // inverse blocks start 16-byte aligned (multiples of 4 elements), as the sweep's loads need
     P.kofs.assign(S + 1, 0);
-    for (int64_t s = 0; s < S; ++s) P.kofs[s + 1] = P.kofs[s] + int64_t(count[s]) * count[s];
+    for (int64_t s = 0; s < S; ++s) P.kofs[s + 1] = P.kofs[s] + ((int64_t(count[s]) * count[s] + 3) & ~int64_t(3));
 
     // ---- rows with merged duplicates and sorted columns (old numbering) -------
     std::vector<int64_t> mrow(n + 1, 0);

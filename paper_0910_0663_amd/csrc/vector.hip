@@ -1,0 +1,142 @@
+// Vector utilities: renumbering gathers/scatters, fills, precision casts,
+// the refinement update, wave import/export and the branch gradient.
+#include "kernels.hpp"
+
+namespace vtm {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ void k_gather(int n, int nrhs, const int32_t* __restrict__ perm, const double* __restrict__ src,
+                         double* __restrict__ dst) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(n) * nrhs) return;
+    const int64_t i = t / nrhs;
+    const int r = int(t - i * nrhs);
+    dst[t] = src[int64_t(r) * n + perm[i]];
+}
+
+__global__ void k_scatter(int n, int nrhs, const int32_t* __restrict__ iperm, const double* __restrict__ src,
+                          double* __restrict__ dst) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(n) * nrhs) return;
+    const int r = int(t / n);
+    const int64_t j = t - int64_t(r) * n;
+    dst[t] = src[int64_t(iperm[j]) * nrhs + r];
+}
+
+template <typename T>
+__global__ void k_fill(int64_t count, T value, T* __restrict__ dst) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < count) dst[t] = value;
+}
+
+template <typename TS, typename TD>
+__global__ void k_convert(int64_t count, const TS* __restrict__ src, TD* __restrict__ dst) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < count) dst[t] = TD(src[t]);
+}
+
+template <typename TD>
+__global__ void k_add(int64_t count, const TD* __restrict__ d, double* __restrict__ x) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < count) x[t] += double(d[t]);
+}
+
+template <typename TV>
+__global__ void k_waves_io(int64_t np, int nrhs, const int32_t* __restrict__ abi2port, TV* __restrict__ a,
+                           double* __restrict__ abi, int to_abi) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= np * nrhs) return;
+    const int r = int(t / np);
+    const int64_t q = t - int64_t(r) * np;
+    const int64_t k = int64_t(abi2port[q]) * nrhs + r;
+    if (to_abi)
+        abi[t] = double(a[k]);
+    else
+        a[k] = TV(abi[t]);
+}
+
+__global__ void k_grad(int64_t m, int n, int nrhs, const double* __restrict__ x, const double* __restrict__ lam,
+                       const int32_t* __restrict__ ij, double* __restrict__ out) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const int i = ij[2 * e], j = ij[2 * e + 1];
+    if (i < 0 || i >= n || j < 0 || j >= n) {  // a branch naming no node: no read, NaN out
+        out[e] = __builtin_nan("");
+        return;
+    }
+    double acc = 0.0;
+    for (int r = 0; r < nrhs; ++r) {
+        const int64_t o = int64_t(r) * n;
+        acc += (lam[o + i] - lam[o + j]) * (x[o + i] - x[o + j]);
+    }
+    out[e] = -acc;
+}
+
+inline unsigned blocks_for(int64_t count, int bs = kBlock) { return unsigned((count + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_gather(int n, int nrhs, const int32_t* perm, const double* src, double* dst,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(int64_t(n) * nrhs)), dim3(kBlock), 0, st, n, nrhs, perm, src,
+                       dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(int n, int nrhs, const int32_t* iperm, const double* src, double* dst,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(int64_t(n) * nrhs)), dim3(kBlock), 0, st, n, nrhs, iperm,
+                       src, dst);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(int64_t count, T value, T* dst, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<T>, dim3(blocks_for(count)), dim3(kBlock), 0, st, count, value, dst);
+    return hipGetLastError();
+}
+
+template <typename TS, typename TD>
+hipError_t launch_convert(int64_t count, const TS* src, TD* dst, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_convert<TS, TD>), dim3(blocks_for(count)), dim3(kBlock), 0, st, count, src, dst);
+    return hipGetLastError();
+}
+
+template <typename TD>
+hipError_t launch_add(int64_t count, const TD* d, double* x, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add<TD>, dim3(blocks_for(count)), dim3(kBlock), 0, st, count, d, x);
+    return hipGetLastError();
+}
+
+template <typename TV>
+hipError_t launch_waves_io(int64_t np, int nrhs, const int32_t* abi2port, TV* a, double* abi, bool to_abi,
+                           hipStream_t st) {
+    if (np * nrhs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_waves_io<TV>, dim3(blocks_for(np * nrhs)), dim3(kBlock), 0, st, np, nrhs, abi2port, a,
+                       abi, to_abi ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(int64_t m, int n, int nrhs, const double* x, const double* lam, const int32_t* ij,
+                       double* dL_dg, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grad, dim3(blocks_for(m)), dim3(kBlock), 0, st, m, n, nrhs, x, lam, ij, dL_dg);
+    return hipGetLastError();
+}
+
+template hipError_t launch_fill<double>(int64_t, double, double*, hipStream_t);
+template hipError_t launch_fill<float>(int64_t, float, float*, hipStream_t);
+template hipError_t launch_convert<double, float>(int64_t, const double*, float*, hipStream_t);
+template hipError_t launch_convert<float, double>(int64_t, const float*, double*, hipStream_t);
+template hipError_t launch_add<float>(int64_t, const float*, double*, hipStream_t);
+template hipError_t launch_add<double>(int64_t, const double*, double*, hipStream_t);
+template hipError_t launch_waves_io<double>(int64_t, int, const int32_t*, double*, double*, bool, hipStream_t);
+template hipError_t launch_waves_io<float>(int64_t, int, const int32_t*, float*, double*, bool, hipStream_t);
+
+}  // namespace vtm

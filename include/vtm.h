@@ -79,6 +79,10 @@ typedef struct {
                                cannot reach tol: the next check comes after half the
                                predicted remaining sweeps (a multiple of check_every,
                                at most 64 of them); 0: check every check_every      */
+    int32_t batch_row_tiles;/* batched (MFMA) sweep: 16-row tiles each wavefront holds
+                               per pass, 3 or 5; 0 = chosen by the autotuner at setup */
+    int32_t batch_rhs_block;/* batched sweep: right-hand sides per workgroup, 16, 32,
+                               48 or 64; 0 = chosen by the autotuner at setup        */
     int32_t reserved;
 } vtm_options;
 
@@ -90,6 +94,8 @@ typedef struct {
     double solve_ms;        /* wall time of the call                                 */
     double sweep_kernel_ms; /* opt.timing: summed duration of the sweep launches     */
     int64_t sweep_launches; /* opt.timing: number of sweep launches timed            */
+    int32_t batch_row_tiles;/* batched sweep shape in use (0 when not batched)       */
+    int32_t batch_rhs_block;
     double *relres;         /* optional caller array [nrhs]: final per-column value  */
 } vtm_report;
 
@@ -97,7 +103,7 @@ typedef struct vtm_handle_s *vtm_handle;
 
 /* Fills *opt with defaults: FP64, nrhs_max 1, check_every 8, max_outer 30,
  * max_sweeps 1000000, divergence 1e6, inner_drop 0, use_graph 0, timing 0,
- * adaptive_checks 1. */
+ * adaptive_checks 1, batch_row_tiles 0, batch_rhs_block 0. */
 void vtm_default_options(vtm_options *opt);
 
 /*
@@ -139,8 +145,9 @@ vtm_status vtm_setup(const vtm_csr *A, const int32_t *part, const double *Z, int
  * sweeps run in FP32/BF16 on A d = r and x += d, r = b - A x in FP64, until
  * the FP64 residual meets tol (VTM_E_MAXITER after opt.max_outer).  Each inner
  * solve starts from zero waves and stops when ||r - A d|| / ||r|| falls below
- * max(inner_drop, tol * ||b|| / (2 ||r||)) for every column, or when three
- * checks in a row bring no 1% improvement.
+ * max(inner_drop, tol * ||b|| / (2 ||r||)) for every column, or when two
+ * checks in a row bring no column 20% below its best (the low-precision
+ * inverse bounds how far an inner solve can go).
  */
 vtm_status vtm_solve(vtm_handle h, const double *b, double *x, int32_t nrhs, double tol,
                      vtm_report *rep);

@@ -44,13 +44,15 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("nrhs_max", C.c_int32), ("check_every", C.c_int32),
                 ("max_outer", C.c_int32), ("max_sweeps", C.c_int64), ("divergence", C.c_double),
                 ("inner_drop", C.c_double), ("use_graph", C.c_int32), ("timing", C.c_int32),
-                ("adaptive_checks", C.c_int32), ("reserved", C.c_int32)]
+                ("adaptive_checks", C.c_int32), ("batch_row_tiles", C.c_int32),
+                ("batch_rhs_block", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Report(C.Structure):
     _fields_ = [("sweeps", C.c_int64), ("outer", C.c_int32), ("checks", C.c_int32),
                 ("relres_max", C.c_double), ("solve_ms", C.c_double), ("sweep_kernel_ms", C.c_double),
-                ("sweep_launches", C.c_int64), ("relres", C.POINTER(C.c_double))]
+                ("sweep_launches", C.c_int64), ("batch_row_tiles", C.c_int32), ("batch_rhs_block", C.c_int32),
+                ("relres", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -149,6 +151,7 @@ class SolveReport:
     relres: np.ndarray
     sweep_kernel_ms: float = 0.0
     sweep_launches: int = 0
+    batch_shape: tuple = (0, 0)
 
 
 def _ptr(t) -> int:
@@ -163,7 +166,7 @@ class Solver:
 
     def __init__(self, A, part, Z, precision="fp64", nrhs_max=1, check_every=8,
                  max_sweeps=1_000_000, divergence=1e6, inner_drop=0.0, max_outer=30,
-                 use_graph=False, timing=False, adaptive_checks=True, stream=None):
+                 use_graph=False, timing=False, adaptive_checks=True, batch_shape=(0, 0), stream=None):
         import torch
         L = lib()
         if not torch.cuda.is_available():
@@ -181,6 +184,7 @@ class Solver:
         opt.use_graph = 1 if use_graph else 0
         opt.timing = 1 if timing else 0
         opt.adaptive_checks = 1 if adaptive_checks else 0
+        opt.batch_row_tiles, opt.batch_rhs_block = int(batch_shape[0]), int(batch_shape[1])
         self.precision = precision
         self.nrhs_max = int(nrhs_max)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -219,7 +223,7 @@ class Solver:
         with self._torch.cuda.stream(self.stream):
             st = fn(self._h, C.c_void_p(_ptr(b)), C.c_void_p(_ptr(x)), nrhs, float(tol), C.byref(rep))
         r = SolveReport(rep.sweeps, rep.outer, rep.checks, rep.relres_max, rep.solve_ms, rel.copy(),
-                        rep.sweep_kernel_ms, rep.sweep_launches)
+                        rep.sweep_kernel_ms, rep.sweep_launches, (rep.batch_row_tiles, rep.batch_rhs_block))
         _check(st, r)
         return x, r
 

@@ -68,13 +68,20 @@ struct vtm_handle_s {
     DevBuf<double> dmod;
     DevBuf<double> c64, beta64, gamma64;
     DevBuf<float> c32, beta32, gamma32;
-    // stored inverses
+    // stored inverses: column groups (K64 / K32), or MFMA tiles (K64 / Kbf) when tiles is set
     DevBuf<double> K64;
     DevBuf<float> K32;
+    DevBuf<__bf16> Kbf;
+    DevBuf<int64_t> mofs;
+    bool tiles = false;
+    size_t lds_limit = 65536;
+    int mfma_variant = 0;                 // chosen by the autotuner
+    int mfma_rc = 0;
     // work vectors, [rows][nrhs]
     DevBuf<double> bp, xp, rp;            // FP64: permuted b, x, residual
     DevBuf<double> a64[2];                // FP64 waves
     DevBuf<float> b32, d32, a32[2];       // low-precision inner solve
+    DevBuf<__bf16> b16;                   // its right-hand side in BF16 (batched BF16 form)
     DevBuf<double> partial, norms;
     DevBuf<int> flag;
     double* h_norms = nullptr;            // pinned
@@ -144,13 +151,23 @@ vtm_status timing_collect(vtm_handle h, double& ms, int64_t& launches) {
     return VTM_OK;
 }
 
-// One sweep on the FP64 or FP32 buffers; cur selects the wave buffer read.
-vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, int cur, bool adjoint) {
+vtm_status launch_one(vtm_handle h, bool low, int nrhs, const void* b, void* x, int cur, bool adjoint, int variant,
+                      int rc, bool write_x) {
     const vtm::Plan& P = h->plan;
-    hipEvent_t e0, e1;
-    if (h->opt.timing) {
-        vtm_status st = timing_event(h, &e0);
-        if (st != VTM_OK) return st;
+    if (h->tiles) {
+        if (adjoint) return fail(VTM_E_UNSUPPORTED, "the batched (MFMA tile) layout has no adjoint form");
+        if (!low)
+            VTM_HIP(vtm::launch_sweep_mfma<double>(int(P.S), P.max_ns, P.max_ports, nrhs, variant, rc, h->lds_limit,
+                                                   h->K64.p, h->mofs.p, h->sub_off.p, h->ports(), h->c64.p,
+                                                   h->beta64.p, h->gamma64.p, static_cast<const double*>(b),
+                                                   h->a64[cur].p, h->a64[cur ^ 1].p, static_cast<double*>(x), write_x,
+                                                   h->stream));
+        else
+            VTM_HIP(vtm::launch_sweep_mfma<__bf16>(int(P.S), P.max_ns, P.max_ports, nrhs, variant, rc, h->lds_limit,
+                                                   h->Kbf.p, h->mofs.p, h->sub_off.p, h->ports(), h->c32.p,
+                                                   h->beta32.p, h->gamma32.p, h->b16.p, h->a32[cur].p,
+                                                   h->a32[cur ^ 1].p, static_cast<float*>(x), write_x, h->stream));
+        return VTM_OK;
     }
     if (!low) {
         VTM_HIP((vtm::launch_sweep<double, double>(int(P.S), P.max_ns, nrhs, h->K64.p, h->kofs.p, h->sub_off.p,
@@ -164,8 +181,71 @@ vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
                                                  static_cast<const float*>(b), h->a32[cur].p, h->a32[cur ^ 1].p,
                                                  static_cast<float*>(x), adjoint, h->stream)));
     }
+    return VTM_OK;
+}
+
+// One sweep on the FP64 or FP32/BF16 buffers; cur selects the wave buffer read.
+// write_x: the sweep's x must be complete (the last sweep before a check).
+vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, int cur, bool adjoint,
+                      bool write_x) {
+    hipEvent_t e0, e1;
+    vtm_status st;
+    if (h->opt.timing && (st = timing_event(h, &e0)) != VTM_OK) return st;
+    if ((st = launch_one(h, low, nrhs, b, x, cur, adjoint, h->mfma_variant, h->mfma_rc, write_x)) != VTM_OK)
+        return st;
     if (h->opt.timing) return timing_event(h, &e1);
     return VTM_OK;
+}
+
+// Autotuner of the batched kernel: on this handle's own sub-circuits (zero
+// vectors: timing does not depend on values), time every candidate launch
+// shape -- row tiles per wavefront per pass (3 or 5) x right-hand sides per
+// workgroup (64, 48, 32, 16) -- over three sweeps after one warm-up, keep the
+// fastest.
+vtm_status autotune(vtm_handle h) {
+    const vtm::Plan& P = h->plan;
+    const bool low = h->opt.precision != VTM_FP64;
+    const int nrhs = h->nrhs_max;
+    const void* b = low ? static_cast<const void*>(h->b32.p) : static_cast<const void*>(h->bp.p);
+    void* x = low ? static_cast<void*>(h->d32.p) : static_cast<void*>(h->xp.p);
+    if (low) {
+        VTM_HIP(vtm::launch_fill<__bf16>(P.n * nrhs, __bf16(0.0f), h->b16.p, h->stream));
+        VTM_HIP(vtm::launch_fill<float>(P.nports * nrhs, 0.0f, h->a32[0].p, h->stream));
+        VTM_HIP(vtm::launch_fill<float>(P.nports * nrhs, 0.0f, h->a32[1].p, h->stream));
+    } else {
+        VTM_HIP(vtm::launch_fill<double>(P.n * nrhs, 0.0, h->bp.p, h->stream));
+        VTM_HIP(vtm::launch_fill<double>(P.nports * nrhs, 0.0, h->a64[0].p, h->stream));
+        VTM_HIP(vtm::launch_fill<double>(P.nports * nrhs, 0.0, h->a64[1].p, h->stream));
+    }
+    hipEvent_t t0, t1;
+    VTM_HIP(hipEventCreate(&t0));
+    VTM_HIP(hipEventCreate(&t1));
+    float best = INFINITY;
+    vtm_status st = VTM_OK;
+    const int v_lo = h->opt.batch_row_tiles == 5 ? 1 : 0, v_hi = h->opt.batch_row_tiles == 3 ? 0 : 1;
+    for (int variant = v_lo; variant <= v_hi && st == VTM_OK; ++variant)
+        for (int rc = 64; rc >= 16 && st == VTM_OK; rc -= 16) {
+            if (rc > 16 && rc >= nrhs + 16) continue;  // wider than the right-hand sides
+            if (h->opt.batch_rhs_block > 0 && rc != h->opt.batch_rhs_block) continue;
+            st = launch_one(h, low, nrhs, b, x, 0, false, variant, rc, false);
+            if (st != VTM_OK) break;
+            if (hipEventRecord(t0, h->stream) != hipSuccess) st = fail(VTM_E_HIP, "event record");
+            for (int k = 0; k < 3 && st == VTM_OK; ++k)
+                st = launch_one(h, low, nrhs, b, x, k & 1, false, variant, rc, false);
+            if (st != VTM_OK) break;
+            float ms = 0.f;
+            if (hipEventRecord(t1, h->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+                hipEventElapsedTime(&ms, t0, t1) != hipSuccess)
+                st = fail(VTM_E_HIP, "autotune timing");
+            else if (ms < best) {
+                best = ms;
+                h->mfma_variant = variant;
+                h->mfma_rc = rc;
+            }
+        }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    return st;
 }
 
 struct IterOut {
@@ -235,7 +315,7 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
     while (true) {
         const int64_t chunk = std::min<int64_t>(cad.next(tol), h->opt.max_sweeps - out.sweeps);
         for (int64_t k = 0; k < chunk; ++k) {
-            st = sweep_once(h, false, nrhs, h->bp.p, h->xp.p, cur, adjoint);
+            st = sweep_once(h, false, nrhs, h->bp.p, h->xp.p, cur, adjoint, k + 1 == chunk);
             if (st != VTM_OK) return st;
             cur ^= 1;
         }
@@ -296,7 +376,10 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
         }
         // inner target relative to ||r||: enough for the outer tolerance, at most drop
         for (int r = 0; r < nrhs; ++r) target[r] = rel[r] > 0.0 ? std::max(drop, 0.5 * tol / rel[r]) : 1.0;
-        VTM_HIP((vtm::launch_convert<double, float>(nv, h->rp.p, h->b32.p, h->stream)));
+        if (h->tiles)
+            VTM_HIP((vtm::launch_convert<double, __bf16>(nv, h->rp.p, h->b16.p, h->stream)));
+        else
+            VTM_HIP((vtm::launch_convert<double, float>(nv, h->rp.p, h->b32.p, h->stream)));
         VTM_HIP(vtm::launch_fill<float>(np, 0.0f, h->a32[0].p, h->stream));
         Cadence cad;
         cad.m = h->opt.check_every;
@@ -309,9 +392,12 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
         std::vector<double> best(nrhs, INFINITY);
         int since = 0;
         while (true) {
-            const int64_t chunk = std::min<int64_t>(cad.next(goal), h->opt.max_sweeps - inner);
+            // an inner solve may stall above its target (the low-precision inverse
+            // bounds the reachable reduction), so its checks grow to at most 4 m
+            const int64_t chunk =
+                std::min<int64_t>(std::min<int64_t>(cad.next(goal), 4 * cad.m), h->opt.max_sweeps - inner);
             for (int64_t k = 0; k < chunk; ++k) {
-                st = sweep_once(h, true, nrhs, h->b32.p, h->d32.p, cur, adjoint);
+                st = sweep_once(h, true, nrhs, h->b32.p, h->d32.p, cur, adjoint, k + 1 == chunk);
                 if (st != VTM_OK) return st;
                 cur ^= 1;
             }
@@ -321,13 +407,12 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
             if (st != VTM_OK) return st;
             ++out.checks;
             if ((st = timing_collect(h, out.sweep_ms, out.launches)) != VTM_OK) return st;
+            // progress: some column fell by at least 20% since its best check
             bool improved = false, bad = false;
             for (int r = 0; r < nrhs; ++r) {
                 if (!std::isfinite(e[r])) bad = true;
-                if (e[r] < 0.99 * best[r]) {
-                    best[r] = e[r];
-                    improved = true;
-                }
+                if (e[r] < 0.8 * best[r]) improved = true;
+                best[r] = std::min(best[r], e[r]);
             }
             if (bad) {
                 out.sweeps += inner;
@@ -335,7 +420,7 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
                 return VTM_OK;
             }
             since = improved ? 0 : since + 1;
-            if (all_le(e, target) || since >= 3 || inner >= h->opt.max_sweeps) break;
+            if (all_le(e, target) || since >= 2 || inner >= h->opt.max_sweeps) break;
             cad.record(inner, max_of(e));
         }
         out.sweeps += inner;
@@ -374,6 +459,8 @@ vtm_status solve_common(vtm_handle h, const double* b, double* x, int32_t nrhs, 
         rep->solve_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
         rep->sweep_kernel_ms = out.sweep_ms;
         rep->sweep_launches = out.launches;
+        rep->batch_row_tiles = h->tiles ? (h->mfma_variant ? 5 : 3) : 0;
+        rep->batch_rhs_block = h->tiles ? h->mfma_rc : 0;
         if (rep->relres)
             for (int r = 0; r < nrhs; ++r) rep->relres[r] = out.rel[r];
     }
@@ -399,6 +486,8 @@ void vtm_default_options(vtm_options* opt) {
     opt->use_graph = 0;
     opt->timing = 0;
     opt->adaptive_checks = 1;
+    opt->batch_row_tiles = 0;
+    opt->batch_rhs_block = 0;
 }
 
 const char* vtm_status_str(vtm_status s) {
@@ -451,10 +540,12 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     if (opt) o = *opt;
     if (o.precision < VTM_FP64 || o.precision > VTM_BF16_REFINE)
         return fail(VTM_E_ARG, "unknown precision");
-    if (o.precision == VTM_BF16_REFINE) return fail(VTM_E_UNSUPPORTED, "BF16 path not built");
     if (o.nrhs_max < 1 || o.nrhs_max > 256) return fail(VTM_E_ARG, "nrhs_max outside 1..256");
     if (o.check_every < 1 || o.max_sweeps < 1 || o.max_outer < 0 || !(o.divergence > 0.0))
         return fail(VTM_E_ARG, "bad iteration limits");
+    if ((o.batch_row_tiles != 0 && o.batch_row_tiles != 3 && o.batch_row_tiles != 5) ||
+        (o.batch_rhs_block != 0 && (o.batch_rhs_block % 16 != 0 || o.batch_rhs_block > 64 || o.batch_rhs_block < 0)))
+        return fail(VTM_E_ARG, "bad batched kernel shape");
 
     auto h = std::make_unique<vtm_handle_s>();
     h->opt = o;
@@ -499,6 +590,18 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     VTM_HIP(h->partial.alloc(size_t(vtm::kResidBlocks) * nr * 2));
     VTM_HIP(h->norms.alloc(size_t(2) * nr));
     VTM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->h_norms), sizeof(double) * 2 * nr));
+    int lds = 0;
+    VTM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+    h->lds_limit = size_t(lds > 0 ? lds : 65536);
+    // batched form: MFMA tiles for BF16, and for FP64 handles sized for 16+ right-hand sides
+    h->tiles = o.precision == VTM_BF16_REFINE || (o.precision == VTM_FP64 && nr >= 16);
+    if (h->tiles) {
+        if (nr > 64 && o.precision == VTM_BF16_REFINE) return fail(VTM_E_UNSUPPORTED, "BF16 path takes at most 64 RHS");
+        VTM_HIP(h->mofs.upload(P.mofs, s));
+    }
+    const int64_t nm = P.mofs[P.S];
+    DevBuf<double> scratch;
+    if (h->tiles || P.max_ns > vtm::kLdsSetupMax) VTM_HIP(scratch.alloc(nk));
     if (o.precision == VTM_FP64) {
         VTM_HIP(h->c64.upload(P.pc, s));
         VTM_HIP(h->beta64.upload(P.pbeta, s));
@@ -506,12 +609,16 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
         VTM_HIP(h->a64[0].alloc(P.nports * nr));
         VTM_HIP(h->a64[1].alloc(P.nports * nr));
         VTM_HIP(vtm::launch_fill<double>(P.nports * nr, 0.0, h->a64[0].p, s));
-        VTM_HIP(h->K64.alloc(nk));
-        DevBuf<double> scratch;
-        if (P.max_ns > vtm::kLdsSetupMax) VTM_HIP(scratch.alloc(nk));
-        VTM_HIP(vtm::launch_setup<double>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
-                                          h->val.p, h->dmod.p, h->K64.p, scratch.p, h->flag.p, s));
-        VTM_HIP(hipStreamSynchronize(s));
+        if (h->tiles) {
+            VTM_HIP(h->K64.alloc(nm));
+            VTM_HIP(vtm::launch_setup_tiles<double>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->mofs.p,
+                                                    h->rowptr.p, h->col.p, h->val.p, h->dmod.p, h->K64.p, scratch.p,
+                                                    h->flag.p, s));
+        } else {
+            VTM_HIP(h->K64.alloc(nk));
+            VTM_HIP(vtm::launch_setup<double>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
+                                              h->val.p, h->dmod.p, h->K64.p, scratch.p, h->flag.p, s));
+        }
     } else {
         VTM_HIP(h->c32.upload(to_float(P.pc), s));
         VTM_HIP(h->beta32.upload(to_float(P.pbeta), s));
@@ -520,19 +627,32 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
         VTM_HIP(h->a32[1].alloc(P.nports * nr));
         VTM_HIP(vtm::launch_fill<float>(P.nports * nr, 0.0f, h->a32[0].p, s));
         VTM_HIP(h->rp.alloc(P.n * nr));
-        VTM_HIP(h->b32.alloc(P.n * nr));
+        if (h->tiles)
+            VTM_HIP(h->b16.alloc(P.n * nr));
+        else
+            VTM_HIP(h->b32.alloc(P.n * nr));
         VTM_HIP(h->d32.alloc(P.n * nr));
-        VTM_HIP(h->K32.alloc(nk));
-        DevBuf<double> scratch;
-        if (P.max_ns > vtm::kLdsSetupMax) VTM_HIP(scratch.alloc(nk));
-        VTM_HIP(vtm::launch_setup<float>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
-                                         h->val.p, h->dmod.p, h->K32.p, scratch.p, h->flag.p, s));
-        VTM_HIP(hipStreamSynchronize(s));
+        if (h->tiles) {
+            VTM_HIP(h->Kbf.alloc(nm));
+            VTM_HIP(vtm::launch_setup_tiles<__bf16>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->mofs.p,
+                                                    h->rowptr.p, h->col.p, h->val.p, h->dmod.p, h->Kbf.p, scratch.p,
+                                                    h->flag.p, s));
+        } else {
+            VTM_HIP(h->K32.alloc(nk));
+            VTM_HIP(vtm::launch_setup<float>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
+                                             h->val.p, h->dmod.p, h->K32.p, scratch.p, h->flag.p, s));
+        }
     }
+    VTM_HIP(hipStreamSynchronize(s));
     int flag = 0;
     VTM_HIP(hipMemcpyAsync(&flag, h->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
     VTM_HIP(hipStreamSynchronize(s));
     if (flag & 1) return fail(VTM_E_SINGULAR, "a sub-circuit matrix is singular");
+    if (h->tiles) {
+        st = autotune(h.get());
+        if (st != VTM_OK) return st;
+        VTM_HIP(hipStreamSynchronize(s));
+    }
     *out = h.release();
     return VTM_OK;
 }
@@ -586,8 +706,11 @@ vtm_status vtm_info(vtm_handle h, int64_t* n, int64_t* n_sub, int64_t* n_wires, 
     if (n) *n = h->plan.n;
     if (n_sub) *n_sub = h->plan.S;
     if (n_wires) *n_wires = h->plan.nwires;
-    if (inverse_bytes)
-        *inverse_bytes = h->plan.kofs[h->plan.S] * (h->opt.precision == VTM_FP64 ? 8 : 4);
+    if (inverse_bytes) {
+        const int64_t elems = h->tiles ? h->plan.mofs[h->plan.S] : h->plan.kofs[h->plan.S];
+        const int64_t esize = h->opt.precision == VTM_FP64 ? 8 : (h->opt.precision == VTM_FP32_REFINE ? 4 : 2);
+        *inverse_bytes = elems * esize;
+    }
     return VTM_OK;
 }
 

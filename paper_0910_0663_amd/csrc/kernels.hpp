@@ -4,7 +4,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
+
+#include "tiles.hpp"
 
 namespace vtm {
 
@@ -32,6 +35,15 @@ hipError_t launch_setup(int S, int max_ns, const int32_t* sub_off, const int64_t
                         const double* dmod, TO* out, double* scratch64, int* flag,
                         hipStream_t st);
 
+// Same matrices, written as zero-padded MFMA operand tiles (tiles.hpp) of T
+// (BF16 or FP64) at out + mofs[s]; every sub-circuit passes through FP64
+// column-major scratch64 (kofs offsets, required).
+template <typename T>
+hipError_t launch_setup_tiles(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs,
+                              const int64_t* mofs, const int32_t* rowptr, const int32_t* col,
+                              const double* val, const double* dmod, T* out, double* scratch64, int* flag,
+                              hipStream_t st);
+
 // ---- sweep ----------------------------------------------------------------
 // One VTM sweep for every sub-circuit (one workgroup each, per block of up to 8
 // right-hand sides): right-hand side b + c * a at the port nodes,
@@ -43,6 +55,22 @@ hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t*
                         const int32_t* sub_off, PortArrays ports, const TV* pc, const TV* pbeta,
                         const TV* pgamma, const TV* b, const TV* a_cur, TV* a_next, TV* x,
                         bool adjoint, hipStream_t st);
+
+// Batched sweep on MFMA (mfma.hip) with the inverses in tile layout: per
+// sub-circuit X = Kinv [b + c a] for blocks of up to 64 right-hand sides, then
+// the outgoing waves.  variant: 0 gives each wavefront 3 row tiles per pass, 1
+// gives it 5; rc_req: right-hand sides per workgroup (multiple of 16; 0 =
+// widest that fits lds_limit).  write_x = false stores x on port rows only (enough
+// for the waves; pass true on the last sweep before a residual check).  The
+// BF16 form reads b in BF16.  No adjoint form.
+template <typename T>
+hipError_t launch_sweep_mfma(int S, int max_ns, int max_ports, int nrhs, int variant, int rc_req,
+                             size_t lds_limit, const T* K, const int64_t* mofs, const int32_t* sub_off,
+                             PortArrays ports, const typename MfmaTypes<T>::TV* pc,
+                             const typename MfmaTypes<T>::TV* pbeta, const typename MfmaTypes<T>::TV* pgamma,
+                             const typename MfmaTypes<T>::TB* b, const typename MfmaTypes<T>::TV* a_cur,
+                             typename MfmaTypes<T>::TV* a_next, typename MfmaTypes<T>::TV* x, bool write_x,
+                             hipStream_t st);
 
 // ---- residual -------------------------------------------------------------
 // r = b - A x in FP64 on the untorn (renumbered) A; per right-hand side

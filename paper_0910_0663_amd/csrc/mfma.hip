@@ -1,0 +1,307 @@
+// Batched sweep on the matrix cores: for every sub-circuit s,
+//   X_s = Kinv_s [b + c * a]_s        (n_s x n_s times n_s x nrhs)
+// as a GEMM on MFMA, then the outgoing waves beta * X + gamma * a for every
+// port and right-hand side (eq. 11 applied column by column).
+//
+// Two element types:
+//   BF16 inverse x BF16 right-hand sides, FP32 accumulate (v_mfma_f32_16x16x32_bf16),
+//        vectors and waves in FP32 (the inner solve of the BF16 refinement);
+//   FP64 inverse x FP64 right-hand sides (v_mfma_f64_16x16x4f64), vectors in FP64.
+//
+// Inverses are stored in A-operand tile order (tiles.hpp): one 16-byte load per
+// lane fetches a whole operand, a wavefront's load is 1 KiB contiguous.  The
+// right-hand-side block of the sub-circuit is staged once in LDS and feeds the
+// B operand.  Each wavefront holds the accumulators of RT 16-row tiles of X and
+// walks k: per k tile one LDS read per B fragment serves all RT row tiles, and
+// the next k tile's RT A-tiles are in flight while this one's MFMAs issue.
+#include "kernels.hpp"
+#include "tiles.hpp"
+
+namespace vtm {
+
+namespace {
+
+constexpr int kWaves = 8;                 // wavefronts per workgroup
+constexpr int kBlock = kWaves * 64;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef double double2v __attribute__((ext_vector_type(2)));
+
+// per element type: A fragment, accumulator, B staging and the MFMA step
+template <typename T>
+struct Mma;
+
+template <>
+struct Mma<__bf16> {
+    using TV = float;
+    using AFrag = bf16x8;     // 8 bf16: A[m = l%16][k = 8(l/16) .. +7] of a 16 x 32 tile
+    using Acc = floatx4;      // D[m = 4(l/16) + v][n = l%16]
+    static constexpr int KT = 32;   // k per A tile
+    // B staged as rhsT[n][k] (k contiguous), row stride np + 8
+    static __device__ int bstride(int np) { return np + 8; }
+    static __device__ size_t lds_bytes(int np, int rc) { return size_t(rc) * (np + 8) * sizeof(__bf16); }
+    static __device__ void stage(__bf16* sb, int np, int rc, int k, int n, float v) {
+        sb[n * (np + 8) + k] = static_cast<__bf16>(v);
+    }
+    using BFrag = bf16x8;     // B[k = 8(l/16) .. +7][n = l%16] of a 32 x 16 tile
+    static __device__ BFrag bfrag(const __bf16* sb, int np, int kt, int nt) {
+        const int l = threadIdx.x & 63;
+        return *reinterpret_cast<const bf16x8*>(sb + (nt * 16 + (l & 15)) * (np + 8) + kt * 32 + 8 * (l >> 4));
+    }
+    static __device__ Acc mma(const AFrag& a, const BFrag& b, Acc acc) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+    static __device__ int out_row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+template <>
+struct Mma<double> {
+    using TV = double;
+    using AFrag = double2v;   // A[m = l%16][k = 8kp + l/16] and A[m][k = 8kp + 4 + l/16]
+    using Acc = doublex4;     // D[m = (l/16) + 4v][n = l%16]
+    static constexpr int KT = 8;
+    // B staged as rhs[k][n] (n contiguous), row stride rc
+    static __device__ void stage(double* sb, int np, int rc, int k, int n, double v) { sb[k * rc + n] = v; }
+    using BFrag = double2v;   // B[k = 8kp + l/16][n = l%16] and B[k + 4][n]
+    static __device__ BFrag bfrag(const double* sb, int rc, int kp, int nt) {
+        const int l = threadIdx.x & 63;
+        const int n = nt * 16 + (l & 15), k = kp * 8 + (l >> 4);
+        BFrag b;
+        b.x = sb[k * rc + n];
+        b.y = sb[(k + 4) * rc + n];
+        return b;
+    }
+    static __device__ Acc mma(const AFrag& a, const BFrag& b, Acc acc) {
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, acc, 0, 0, 0);
+    }
+    static __device__ int out_row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+
+// Block (y, s): sub-circuit s, right-hand sides [r0, r0 + w), w <= rc <= 16 * NT.
+// TB: element type of the right-hand side b (BF16 for the BF16 path: the staged
+// operand is BF16 anyway).  write_x = 0 stores x only on port rows (all the
+// wave update needs); the last sweep before a residual check passes 1.
+template <typename T, typename TB, int NT, int RT>
+__global__ void __launch_bounds__(kBlock)
+    k_sweep_mfma(const T* __restrict__ K, const int64_t* __restrict__ mofs, const int32_t* __restrict__ sub_off,
+                 const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_node,
+                 const int32_t* __restrict__ port_twin, const typename Mma<T>::TV* __restrict__ pc,
+                 const typename Mma<T>::TV* __restrict__ pbeta, const typename Mma<T>::TV* __restrict__ pgamma,
+                 const TB* __restrict__ b, const typename Mma<T>::TV* __restrict__ a_cur,
+                 typename Mma<T>::TV* __restrict__ a_next, typename Mma<T>::TV* __restrict__ x, int nrhs, int rc,
+                 int write_x) {
+    using M = Mma<T>;
+    using TV = typename M::TV;
+    extern __shared__ char smem[];
+    T* sb = reinterpret_cast<T*>(smem);
+    const int s = blockIdx.y;
+    const int r0 = blockIdx.x * rc;
+    const int w = min(rc, nrhs - r0);
+    const int off = sub_off[s];
+    const int ns = sub_off[s + 1] - off;
+    const int np = tile_pad(ns);
+    const int p0 = port_off[s], p1 = port_off[s + 1];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+
+    // 1. stage B = b + c * a.  Ports of a node are consecutive (slot order);
+    //    pfirst/pcount give each row its port range.  b is read V values at a time.
+    constexpr int V = 16 / int(sizeof(TB));
+    int* pnode = reinterpret_cast<int*>(smem + tile_lds_bytes<T>(np, rc));
+    const int nps = p1 - p0;
+    short* pfirst = reinterpret_cast<short*>(pnode + nps);
+    unsigned char* pcount = reinterpret_cast<unsigned char*>(pfirst + np);
+    for (int k = tid; k < np; k += kBlock) pcount[k] = 0;
+    for (int p = p0 + tid; p < p1; p += kBlock) pnode[p - p0] = port_node[p];
+    __syncthreads();
+    for (int q = tid; q < nps; q += kBlock) {
+        const int k = pnode[q];
+        if (q == 0 || pnode[q - 1] != k) {
+            int e = q;
+            while (e < nps && pnode[e] == k) ++e;
+            pfirst[k] = short(q);
+            pcount[k] = static_cast<unsigned char>(e - q);
+        }
+    }
+    __syncthreads();
+    const bool vec = (nrhs % V) == 0;
+    const int rv = rc / V;
+    for (int t = tid; t < np * rv; t += kBlock) {
+        const int k = t / rv, n0 = (t - k * rv) * V;
+        TV v[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) v[j] = TV(0);
+        if (k < ns && n0 < w) {
+            const TB* bp = b + int64_t(off + k) * nrhs + r0 + n0;
+            if (vec) {
+                TB tmp[V];
+                *reinterpret_cast<uint4*>(tmp) = *reinterpret_cast<const uint4*>(bp);
+#pragma unroll
+                for (int j = 0; j < V; ++j) v[j] = TV(tmp[j]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < V; ++j)
+                    if (n0 + j < w) v[j] = TV(bp[j]);
+            }
+            const int cnt = pcount[k];
+            for (int q = 0; q < cnt; ++q) {
+                const int p = p0 + pfirst[k] + q;
+                const TV c = pc[p];
+                const TV* ap = a_cur + int64_t(p) * nrhs + r0 + n0;
+#pragma unroll
+                for (int j = 0; j < V; ++j)
+                    if (n0 + j < w) v[j] += c * ap[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) M::stage(sb, np, rc, k, n0 + j, v[j]);
+    }
+    __syncthreads();
+
+    // 2. X = Kinv B.  A wavefront takes up to RT row tiles
+    //    (mt = wave, wave + W, ...) per pass and walks k: per k tile it loads the
+    //    NT B fragments once from LDS and its row tiles' A tiles from HBM (the
+    //    next k tile's A tiles are already in flight), then issues the MFMAs.
+    const int MT = np / 16, KT = np / M::KT;
+    const typename M::AFrag* A0 = reinterpret_cast<const typename M::AFrag*>(K + mofs[s]) + lane;
+    const int bsel = sizeof(T) == 2 ? np : rc;
+    for (int g0 = 0; g0 < MT; g0 += kWaves * RT) {
+        int mts[RT];
+        int nmy = 0;
+#pragma unroll
+        for (int j = 0; j < RT; ++j) {
+            mts[j] = g0 + wave + j * kWaves;
+            if (mts[j] < MT) nmy = j + 1;
+        }
+        if (nmy == 0) continue;
+        typename M::Acc acc[RT][NT];
+#pragma unroll
+        for (int j = 0; j < RT; ++j)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[j][nt][v] = 0;
+        typename M::AFrag abuf[2][RT];
+#pragma unroll
+        for (int j = 0; j < RT; ++j)
+            if (j < nmy) abuf[0][j] = A0[int64_t(mts[j]) * KT * 64];
+        for (int kt = 0; kt < KT; kt += 2) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = kt + h;
+                if (k < KT) {
+                    if (k + 1 < KT) {
+#pragma unroll
+                        for (int j = 0; j < RT; ++j)
+                            if (j < nmy) abuf[h ^ 1][j] = A0[(int64_t(mts[j]) * KT + k + 1) * 64];
+                    }
+                    typename M::BFrag bf[NT];
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) bf[nt] = M::bfrag(sb, bsel, k, nt);
+#pragma unroll
+                    for (int j = 0; j < RT; ++j)
+                        if (j < nmy)
+#pragma unroll
+                            for (int nt = 0; nt < NT; ++nt)
+                                if (nt * 16 < w) acc[j][nt] = M::mma(abuf[h][j], bf[nt], acc[j][nt]);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < RT; ++j) {
+            if (j >= nmy) continue;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int n = nt * 16 + (lane & 15);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = mts[j] * 16 + M::out_row(lane, v);
+                    if (row < ns && n < w && (write_x || pcount[row]))
+                        x[int64_t(off + row) * nrhs + r0 + n] = TV(acc[j][nt][v]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // 3. outgoing waves, read back x of the port nodes (written by this workgroup), 4 columns at a time
+    const int w4 = (w + 3) / 4;
+    for (int t = tid; t < nps * w4; t += kBlock) {
+        const int q = t / w4, n0 = (t - q * w4) * 4;
+        const int p = p0 + q;
+        const TV be = pbeta[p], ga = pgamma[p];
+        const TV* xr = x + int64_t(off + pnode[q]) * nrhs + r0;
+        const TV* ar = a_cur + int64_t(p) * nrhs + r0;
+        TV* nr = a_next + int64_t(port_twin[p]) * nrhs + r0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (n0 + j < w) nr[n0 + j] = be * xr[n0 + j] + ga * ar[n0 + j];
+    }
+}
+
+template <typename T, int NT, int RT>
+hipError_t launch_t(int S, int nrhs, int rc, size_t lds, const T* K, const int64_t* mofs, const int32_t* sub_off,
+                    PortArrays ports, const typename Mma<T>::TV* pc, const typename Mma<T>::TV* pbeta,
+                    const typename Mma<T>::TV* pgamma, const typename MfmaTypes<T>::TB* b,
+                    const typename Mma<T>::TV* a_cur, typename Mma<T>::TV* a_next, typename Mma<T>::TV* x,
+                    bool write_x, hipStream_t st) {
+    auto kern = k_sweep_mfma<T, typename MfmaTypes<T>::TB, NT, RT>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    const unsigned ny = unsigned((nrhs + rc - 1) / rc);
+    hipLaunchKernelGGL(kern, dim3(ny, S), dim3(kBlock), lds, st, K, mofs, sub_off, ports.off, ports.node,
+                       ports.twin, pc, pbeta, pgamma, b, a_cur, a_next, x, nrhs, rc, write_x ? 1 : 0);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_sweep_mfma(int S, int max_ns, int max_ports, int nrhs, int variant, int rc_req, size_t lds_limit,
+                             const T* K,
+                             const int64_t* mofs, const int32_t* sub_off, PortArrays ports,
+                             const typename MfmaTypes<T>::TV* pc, const typename MfmaTypes<T>::TV* pbeta,
+                             const typename MfmaTypes<T>::TV* pgamma, const typename MfmaTypes<T>::TB* b,
+                             const typename MfmaTypes<T>::TV* a_cur, typename MfmaTypes<T>::TV* a_next,
+                             typename MfmaTypes<T>::TV* x, bool write_x, hipStream_t st) {
+    const int np = tile_pad(max_ns);
+    // widest right-hand-side block (a multiple of 16, at most 64) whose staging fits the LDS limit
+    int rc = rc_req > 0 ? ((rc_req + 15) / 16) * 16 : 64;
+    if (rc > 64) rc = 64;
+    // staged B, the port-node list, and per row its first port (short) and port count (byte)
+    auto need = [&](int r) { return tile_lds_bytes<T>(np, r) + size_t(max_ports) * 4 + size_t(np) * 3 + 4; };
+    while (rc > 16 && need(rc) > lds_limit) rc -= 16;
+    const size_t lds = need(rc);
+    if (lds > lds_limit) return hipErrorInvalidValue;
+    if (rc > nrhs) rc = ((nrhs + 15) / 16) * 16 < rc ? ((nrhs + 15) / 16) * 16 : rc;
+    const int nt = (rc + 15) / 16;
+    const bool deep = variant != 0;
+#define VTM_MFMA_CASE(NTV)                                                                                      \
+    if (nt == NTV)                                                                                              \
+        return deep ? launch_t<T, NTV, 5>(S, nrhs, rc, lds, K, mofs, sub_off, ports, pc, pbeta, pgamma, b, a_cur, \
+                                          a_next, x, write_x, st)                                               \
+                    : launch_t<T, NTV, 3>(S, nrhs, rc, lds, K, mofs, sub_off, ports, pc, pbeta, pgamma, b, a_cur, \
+                                          a_next, x, write_x, st);
+    VTM_MFMA_CASE(1)
+    VTM_MFMA_CASE(2)
+    VTM_MFMA_CASE(3)
+    VTM_MFMA_CASE(4)
+#undef VTM_MFMA_CASE
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_sweep_mfma<__bf16>(int, int, int, int, int, int, size_t, const __bf16*, const int64_t*,
+                                             const int32_t*, PortArrays, const float*, const float*, const float*,
+                                             const __bf16*, const float*, float*, float*, bool, hipStream_t);
+template hipError_t launch_sweep_mfma<double>(int, int, int, int, int, int, size_t, const double*, const int64_t*,
+                                             const int32_t*, PortArrays, const double*, const double*,
+                                             const double*, const double*, const double*, double*, double*, bool,
+                                             hipStream_t);
+
+}  // namespace vtm

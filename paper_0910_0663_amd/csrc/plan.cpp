@@ -105,6 +105,12 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
     // inverse blocks start 16-byte aligned (multiples of 4 elements), as the sweep's loads need
     P.kofs.assign(S + 1, 0);
     for (int64_t s = 0; s < S; ++s) P.kofs[s + 1] = P.kofs[s] + ((int64_t(count[s]) * count[s] + 3) & ~int64_t(3));
+    // MFMA tile blocks: each sub-circuit padded to a multiple of 32 rows and columns
+    P.mofs.assign(S + 1, 0);
+    for (int64_t s = 0; s < S; ++s) {
+        const int64_t np = (int64_t(count[s]) + 31) & ~int64_t(31);
+        P.mofs[s + 1] = P.mofs[s] + np * np;
+    }
 
     // ---- rows with merged duplicates and sorted columns (old numbering) -------
     std::vector<int64_t> mrow(n + 1, 0);
@@ -238,7 +244,10 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
         const int32_t node = (q & 1) ? P.wj[e] : P.wi[e];
         P.dmod[P.iperm[node]] += k.G - P.wg[e];
     }
-    for (int64_t s = 0; s < S; ++s) P.port_off[s + 1] += P.port_off[s];
+    for (int64_t s = 0; s < S; ++s) {
+        P.max_ports = std::max<int32_t>(P.max_ports, P.port_off[s + 1]);
+        P.port_off[s + 1] += P.port_off[s];
+    }
     for (int64_t q = 0; q < np; ++q) P.port_twin[P.abi2port[q]] = P.abi2port[q ^ 1];
 
     // ---- renumbered untorn matrix ------------------------------------------------

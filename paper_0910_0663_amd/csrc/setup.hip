@@ -9,6 +9,7 @@
 
 #include "kernels.hpp"
 #include "layout.hpp"
+#include "tiles.hpp"
 
 namespace vtm {
 
@@ -85,7 +86,7 @@ __device__ void store_layout(const double* Mcm, int n, TO* dst) {
 // LDS path: one workgroup per sub-circuit with n <= kLdsSetupMax.  M holds K^T
 // row-major, so the in-place inverse is Kinv column-major.
 // ---------------------------------------------------------------------------
-template <typename TO>
+template <typename TO, bool COLMAJOR>
 __global__ void __launch_bounds__(kBlock)
     k_setup_lds(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs,
                 const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -154,7 +155,11 @@ __global__ void __launch_bounds__(kBlock)
             }
         __syncthreads();
     }
-    store_layout<TO>(M, n, out + kofs[s]);
+    if constexpr (COLMAJOR) {
+        for (int t = tid; t < n * n; t += bs) out[kofs[s] + t] = TO(M[t]);
+    } else {
+        store_layout<TO>(M, n, out + kofs[s]);
+    }
     if (bad && tid == 0) atomicOr(flag, 1);
 }
 
@@ -296,20 +301,32 @@ __global__ void __launch_bounds__(kBlock)
     store_layout<TO>(src + kofs[s], n, dst + kofs[s]);
 }
 
-}  // namespace
+// column-major FP64 scratch -> zero-padded MFMA operand tiles (tiles.hpp)
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_to_tiles(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs,
+               const int64_t* __restrict__ mofs, const double* __restrict__ src, T* __restrict__ dst) {
+    const int s = blockIdx.x;
+    const int n = sub_off[s + 1] - sub_off[s];
+    const int np = tile_pad(n);
+    const double* M = src + kofs[s];
+    T* o = dst + mofs[s];
+    const int64_t cnt = int64_t(np) * np;
+    for (int64_t d = threadIdx.x; d < cnt; d += blockDim.x) {
+        int r, c;
+        tile_rc<T>(np, d, r, c);
+        o[d] = (r < n && c < n) ? static_cast<T>(M[int64_t(c) * n + r]) : static_cast<T>(0.0);
+    }
+}
 
-template <typename TO>
-hipError_t launch_setup(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, const int32_t* rowptr,
-                        const int32_t* col, const double* val, const double* dmod, TO* out, double* scratch64,
-                        int* flag, hipStream_t st) {
-    hipLaunchKernelGGL(k_setup_lds<TO>, dim3(S), dim3(kBlock), 0, st, sub_off, kofs, rowptr, col, val, dmod, out,
-                       flag);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || max_ns <= kLdsSetupMax) return e;
+// the large sub-circuits: assemble and invert in FP64 scratch (column-major)
+hipError_t invert_large(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, const int32_t* rowptr,
+                        const int32_t* col, const double* val, const double* dmod, double* scratch64, int* flag,
+                        hipStream_t st) {
     if (!scratch64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_assemble, dim3(S), dim3(kBlock), 0, st, sub_off, kofs, rowptr, col, val, dmod,
-                       scratch64);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_assemble, dim3(S), dim3(kBlock), 0, st, sub_off, kofs, rowptr, col, val, dmod, scratch64);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     // panel width: as many columns as fit next to the pivot bookkeeping in 64 KiB of LDS
     constexpr int kLds = 65536;
     const int fixed = max_ns * (8 + 4) + 64;
@@ -318,7 +335,38 @@ hipError_t launch_setup(int S, int max_ns, const int32_t* sub_off, const int64_t
     nb = nb > 16 ? 16 : nb;
     const size_t lds = size_t(max_ns) * nb * 8 + fixed;
     hipLaunchKernelGGL(k_gj_global<16>, dim3(S), dim3(kBlock), lds, st, sub_off, kofs, scratch64, nb, flag);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_setup_tiles(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, const int64_t* mofs,
+                              const int32_t* rowptr, const int32_t* col, const double* val, const double* dmod,
+                              T* out, double* scratch64, int* flag, hipStream_t st) {
+    if (!scratch64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_setup_lds<double, true>), dim3(S), dim3(kBlock), 0, st, sub_off, kofs, rowptr, col, val,
+                       dmod, scratch64, flag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (max_ns > kLdsSetupMax) {
+        e = invert_large(S, max_ns, sub_off, kofs, rowptr, col, val, dmod, scratch64, flag, st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_to_tiles<T>, dim3(S), dim3(kBlock), 0, st, sub_off, kofs, mofs, scratch64, out);
+    return hipGetLastError();
+}
+
+template <typename TO>
+hipError_t launch_setup(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, const int32_t* rowptr,
+                        const int32_t* col, const double* val, const double* dmod, TO* out, double* scratch64,
+                        int* flag, hipStream_t st) {
+    hipLaunchKernelGGL((k_setup_lds<TO, false>), dim3(S), dim3(kBlock), 0, st, sub_off, kofs, rowptr, col, val,
+                       dmod, out, flag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || max_ns <= kLdsSetupMax) return e;
+    e = invert_large(S, max_ns, sub_off, kofs, rowptr, col, val, dmod, scratch64, flag, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_to_layout<TO>, dim3(S), dim3(kBlock), 0, st, sub_off, kofs, scratch64, out);
     return hipGetLastError();
 }
@@ -327,5 +375,11 @@ template hipError_t launch_setup<double>(int, int, const int32_t*, const int64_t
                                          const double*, const double*, double*, double*, int*, hipStream_t);
 template hipError_t launch_setup<float>(int, int, const int32_t*, const int64_t*, const int32_t*, const int32_t*,
                                         const double*, const double*, float*, double*, int*, hipStream_t);
+template hipError_t launch_setup_tiles<__bf16>(int, int, const int32_t*, const int64_t*, const int64_t*,
+                                              const int32_t*, const int32_t*, const double*, const double*, __bf16*,
+                                              double*, int*, hipStream_t);
+template hipError_t launch_setup_tiles<double>(int, int, const int32_t*, const int64_t*, const int64_t*,
+                                              const int32_t*, const int32_t*, const double*, const double*, double*,
+                                              double*, int*, hipStream_t);
 
 }  // namespace vtm

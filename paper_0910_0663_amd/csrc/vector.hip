@@ -35,7 +35,13 @@ __global__ void k_fill(int64_t count, T value, T* __restrict__ dst) {
 template <typename TS, typename TD>
 __global__ void k_convert(int64_t count, const TS* __restrict__ src, TD* __restrict__ dst) {
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t < count) dst[t] = TD(src[t]);
+    if (t < count) dst[t] = static_cast<TD>(static_cast<float>(src[t]));
+}
+
+template <>
+__global__ void k_convert<float, double>(int64_t count, const float* __restrict__ src, double* __restrict__ dst) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < count) dst[t] = double(src[t]);
 }
 
 template <typename TD>
@@ -134,6 +140,8 @@ template hipError_t launch_fill<double>(int64_t, double, double*, hipStream_t);
 template hipError_t launch_fill<float>(int64_t, float, float*, hipStream_t);
 template hipError_t launch_convert<double, float>(int64_t, const double*, float*, hipStream_t);
 template hipError_t launch_convert<float, double>(int64_t, const float*, double*, hipStream_t);
+template hipError_t launch_convert<double, __bf16>(int64_t, const double*, __bf16*, hipStream_t);
+template hipError_t launch_fill<__bf16>(int64_t, __bf16, __bf16*, hipStream_t);
 template hipError_t launch_add<float>(int64_t, const float*, double*, hipStream_t);
 template hipError_t launch_add<double>(int64_t, const double*, double*, hipStream_t);
 template hipError_t launch_waves_io<double>(int64_t, int, const int32_t*, double*, double*, bool, hipStream_t);

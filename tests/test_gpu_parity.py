@@ -247,3 +247,47 @@ def test_full_size_config2_residual(torch):
     rel = oracle.relative_residual(w.A, w.b, x.cpu().numpy()).max()
     assert rel <= w.tol
     assert abs(rel - rep.relres_max) <= 1e-3 * rel
+
+
+# ----------------------------------------------------------------------------- batched (MFMA) forms
+def test_batched_fp64_mfma_iterates_match_oracle(torch):
+    """FP64 handles sized for 16+ right-hand sides store the inverses as MFMA
+    tiles (v_mfma_f64_16x16x4f64); their iterates equal the oracle's, on uneven
+    sub-circuits padded to the tile size, including a ragged last block of
+    right-hand sides and a single right-hand side."""
+    w = workloads.make(4, dims=(96, 96), nrhs=20)
+    ks = [1, 3, 17]
+    ref = oracle_iterates(w, ks)
+    for k in ks:
+        assert_close(gpu_iterate(torch, w, k, nrhs_max=20), ref[k])
+    w1 = workloads.make(4, dims=(96, 96), nrhs=1)
+    ref1 = oracle_iterates(w1, [5])
+    assert_close(gpu_iterate(torch, w1, 5, nrhs_max=16), ref1[5])
+    # checks every 8 sweeps: sweeps in between store x on port rows only
+    s = vtm().Solver(w.A, w.part, w.Z, nrhs_max=20, check_every=8, adaptive_checks=False)
+    x, rep = s.solve(to_dev(torch, w.b), 1e-9)
+    assert rep.sweeps % 8 == 0
+    assert_close(x.cpu().numpy(), oracle_iterates(w, [rep.sweeps])[rep.sweeps])
+
+
+def test_batched_bf16_refinement_reaches_fp64_tolerance(torch):
+    """BF16 inverses x BF16 right-hand sides on MFMA with FP32 accumulation,
+    inside FP64 refinement: every column reaches relative residual 1e-8
+    (recomputed in FP64 on the host) and the direct solution."""
+    w = workloads.make(4, dims=(192, 192), nrhs=32)
+    s = vtm().Solver(w.A, w.part, w.Z, precision="bf16_refine", nrhs_max=32)
+    x, rep = s.solve(to_dev(torch, w.b), w.tol)
+    xh = x.cpu().numpy()
+    assert oracle.relative_residual(w.A, w.b, xh).max() <= w.tol
+    assert rep.outer >= 3
+    xs = oracle.direct_solve(w.A, w.b)
+    assert np.abs(xh - xs).max() <= 2e-6 * np.abs(xs).max()
+
+
+def test_batched_layout_has_no_adjoint(torch):
+    V = vtm()
+    w = workloads.make(4, dims=(64, 64), nrhs=16)
+    s = V.Solver(w.A, w.part, w.Z, nrhs_max=16)
+    with pytest.raises(V.VTMError) as ei:
+        s.solve_adjoint(to_dev(torch, w.b), 1e-8)
+    assert ei.value.name == "VTM_E_UNSUPPORTED"

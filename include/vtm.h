@@ -73,8 +73,12 @@ typedef struct {
     double divergence;      /* a relative residual above this means divergence       */
     double inner_drop;      /* refinement: inner target ||r - A d|| / ||r||; 0 = default
                                (1e-5 for FP32, 1e-2 for BF16)                        */
-    int32_t use_graph;      /* replay each check interval as one captured hipGraph   */
-    int32_t timing;         /* 1: time every sweep launch with HIP events (report)   */
+    int32_t use_graph;      /* 1: each check interval (its sweeps, the FP64 residual
+                               and the copy of its sums to the host) is captured once
+                               per shape and replayed as one hipGraph launch; check
+                               intervals are then check_every times a power of two */
+    int32_t timing;         /* 1: time every sweep launch with HIP events (report;
+                               not available with use_graph)                         */
     int32_t adaptive_checks;/* 1: once the residual falls steadily, skip checks that
                                cannot reach tol: the next check comes after half the
                                predicted remaining sweeps (a multiple of check_every,

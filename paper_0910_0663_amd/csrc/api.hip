@@ -2,7 +2,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -89,10 +91,18 @@ struct vtm_handle_s {
     // per-launch timing of the sweep kernel (opt.timing)
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;
+    // captured check intervals (opt.use_graph), keyed by everything their launches depend on
+    std::map<std::array<int, 6>, hipGraphExec_t> graphs;
+    bool capturing = false;               // no per-sweep timing events inside a capture
+    hipStream_t gstream = nullptr;        // private non-blocking stream the graphs run on
+    hipEvent_t gready = nullptr;          // orders it after the caller's stream
 
     ~vtm_handle_s() {
         if (h_norms) (void)hipHostFree(h_norms);
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        if (gready) (void)hipEventDestroy(gready);
+        if (gstream) (void)hipStreamDestroy(gstream);
     }
 
     vtm::PortArrays ports() const {
@@ -104,11 +114,11 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// FP64 residual of x against b (both [n][nrhs] renumbered) -> relres per column.
-// With transpose set the residual is taken on A^T (the adjoint system).
+// FP64 residual of x against b (both [n][nrhs] renumbered): launches the
+// residual and the copy of its per-column sums into pinned host memory.  With
+// transpose set the residual is taken on A^T (the adjoint system).
 template <typename TX>
-vtm_status residual(vtm_handle h, const double* b, const TX* x, int nrhs, double* r_out,
-                    std::vector<double>& rel, bool transpose) {
+vtm_status residual_launch(vtm_handle h, const double* b, const TX* x, int nrhs, double* r_out, bool transpose) {
     const vtm::Plan& P = h->plan;
     const bool useT = transpose && !P.symmetric;
     VTM_HIP(vtm::launch_residual<TX>(int(P.n), nrhs, useT ? h->rowptrT.p : h->rowptr.p,
@@ -116,6 +126,11 @@ vtm_status residual(vtm_handle h, const double* b, const TX* x, int nrhs, double
                                      h->partial.p, h->norms.p, h->stream));
     VTM_HIP(hipMemcpyAsync(h->h_norms, h->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost,
                            h->stream));
+    return VTM_OK;
+}
+
+// waits for the stream, then relres per column from the copied sums
+vtm_status residual_finish(vtm_handle h, int nrhs, std::vector<double>& rel) {
     VTM_HIP(hipStreamSynchronize(h->stream));
     rel.resize(nrhs);
     for (int r = 0; r < nrhs; ++r) {
@@ -123,6 +138,14 @@ vtm_status residual(vtm_handle h, const double* b, const TX* x, int nrhs, double
         rel[r] = bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr);
     }
     return VTM_OK;
+}
+
+template <typename TX>
+vtm_status residual(vtm_handle h, const double* b, const TX* x, int nrhs, double* r_out,
+                    std::vector<double>& rel, bool transpose) {
+    vtm_status st = residual_launch<TX>(h, b, x, nrhs, r_out, transpose);
+    if (st != VTM_OK) return st;
+    return residual_finish(h, nrhs, rel);
 }
 
 struct IterOut;
@@ -190,10 +213,11 @@ vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
                       bool write_x) {
     hipEvent_t e0, e1;
     vtm_status st;
-    if (h->opt.timing && (st = timing_event(h, &e0)) != VTM_OK) return st;
+    const bool timed = h->opt.timing && !h->capturing;
+    if (timed && (st = timing_event(h, &e0)) != VTM_OK) return st;
     if ((st = launch_one(h, low, nrhs, b, x, cur, adjoint, h->mfma_variant, h->mfma_rc, write_x)) != VTM_OK)
         return st;
-    if (h->opt.timing) return timing_event(h, &e1);
+    if (timed) return timing_event(h, &e1);
     return VTM_OK;
 }
 
@@ -248,6 +272,67 @@ vtm_status autotune(vtm_handle h) {
     return st;
 }
 
+// One check interval: `chunk` sweeps from wave buffer `cur`, then the FP64
+// residual check.  Plain form: b = bp, x = xp, check of b - A x.  Inner form
+// (low precision): x = d32, check of r - A d.  With opt.use_graph the
+// interval is captured once per (form, nrhs, adjoint, length, start buffer)
+// and replayed as one hipGraph launch.
+vtm_status run_chunk(vtm_handle h, bool low, int nrhs, bool adjoint, int64_t chunk, int cur,
+                     std::vector<double>& rel) {
+    const void* b = low ? (h->tiles ? static_cast<const void*>(h->b16.p) : static_cast<const void*>(h->b32.p))
+                        : static_cast<const void*>(h->bp.p);
+    void* x = low ? static_cast<void*>(h->d32.p) : static_cast<void*>(h->xp.p);
+    auto enqueue = [&]() -> vtm_status {
+        for (int64_t k = 0; k < chunk; ++k) {
+            vtm_status st = sweep_once(h, low, nrhs, b, x, (cur + int(k)) & 1, adjoint, k + 1 == chunk);
+            if (st != VTM_OK) return st;
+        }
+        return low ? residual_launch<float>(h, h->rp.p, h->d32.p, nrhs, nullptr, adjoint)
+                   : residual_launch<double>(h, h->bp.p, h->xp.p, nrhs, nullptr, adjoint);
+    };
+    if (!h->opt.use_graph) {
+        vtm_status st = enqueue();
+        if (st != VTM_OK) return st;
+        return residual_finish(h, nrhs, rel);
+    }
+    // graphs run on the handle's own non-blocking stream (the caller's may be the
+    // legacy null stream, which cannot be captured), after the caller's work
+    if (!h->gstream) {
+        VTM_HIP(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+        VTM_HIP(hipEventCreateWithFlags(&h->gready, hipEventDisableTiming));
+    }
+    VTM_HIP(hipEventRecord(h->gready, h->stream));
+    VTM_HIP(hipStreamWaitEvent(h->gstream, h->gready, 0));
+    struct Swap {
+        vtm_handle h;
+        hipStream_t saved;
+        ~Swap() { h->stream = saved; }
+    } swap{h, h->stream};
+    h->stream = h->gstream;
+    const std::array<int, 6> key{int(low), nrhs, int(adjoint), int(chunk), cur, 0};
+    auto it = h->graphs.find(key);
+    if (it == h->graphs.end()) {
+        VTM_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        h->capturing = true;
+        vtm_status st = enqueue();
+        h->capturing = false;
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(h->stream, &g);
+        if (st != VTM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail(VTM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return fail(VTM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+        it = h->graphs.emplace(key, ex).first;
+    }
+    VTM_HIP(hipGraphLaunch(it->second, h->stream));
+    return residual_finish(h, nrhs, rel);
+}
+
 struct IterOut {
     int64_t sweeps = 0;
     int checks = 0;
@@ -291,6 +376,15 @@ double max_of(const std::vector<double>& v) {
     return mx;
 }
 
+// With graphs, check intervals are m times a power of two (a few graphs cover them all).
+int64_t graph_length(vtm_handle h, int64_t k) {
+    if (!h->opt.use_graph) return k;
+    const int64_t m = h->opt.check_every;
+    int64_t len = m;
+    while (2 * len <= k) len *= 2;
+    return len;
+}
+
 // Plain FP64 VTM on (bp -> xp).  Waves start at zero unless resume is set.
 vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resume, IterOut& out) {
     const vtm::Plan& P = h->plan;
@@ -313,15 +407,11 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
     if (done(out.rel)) return VTM_OK;
     if (!resume) cad.record(0, max_of(out.rel));
     while (true) {
-        const int64_t chunk = std::min<int64_t>(cad.next(tol), h->opt.max_sweeps - out.sweeps);
-        for (int64_t k = 0; k < chunk; ++k) {
-            st = sweep_once(h, false, nrhs, h->bp.p, h->xp.p, cur, adjoint, k + 1 == chunk);
-            if (st != VTM_OK) return st;
-            cur ^= 1;
-        }
-        out.sweeps += chunk;
-        st = residual<double>(h, h->bp.p, h->xp.p, nrhs, nullptr, out.rel, adjoint);
+        const int64_t chunk = std::min<int64_t>(graph_length(h, cad.next(tol)), h->opt.max_sweeps - out.sweeps);
+        st = run_chunk(h, false, nrhs, adjoint, chunk, cur, out.rel);
         if (st != VTM_OK) return st;
+        cur ^= int(chunk & 1);
+        out.sweeps += chunk;
         ++out.checks;
         if ((st = timing_collect(h, out.sweep_ms, out.launches)) != VTM_OK) return st;
         bool bad = false;
@@ -394,17 +484,13 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
         while (true) {
             // an inner solve may stall above its target (the low-precision inverse
             // bounds the reachable reduction), so its checks grow to at most 4 m
-            const int64_t chunk =
-                std::min<int64_t>(std::min<int64_t>(cad.next(goal), 4 * cad.m), h->opt.max_sweeps - inner);
-            for (int64_t k = 0; k < chunk; ++k) {
-                st = sweep_once(h, true, nrhs, h->b32.p, h->d32.p, cur, adjoint, k + 1 == chunk);
-                if (st != VTM_OK) return st;
-                cur ^= 1;
-            }
-            inner += chunk;
-            // ||r - A d|| / ||r|| in FP64
-            st = residual<float>(h, h->rp.p, h->d32.p, nrhs, nullptr, e, adjoint);
+            const int64_t chunk = std::min<int64_t>(
+                graph_length(h, std::min<int64_t>(cad.next(goal), 4 * cad.m)), h->opt.max_sweeps - inner);
+            // sweeps, then ||r - A d|| / ||r|| in FP64
+            st = run_chunk(h, true, nrhs, adjoint, chunk, cur, e);
             if (st != VTM_OK) return st;
+            cur ^= int(chunk & 1);
+            inner += chunk;
             ++out.checks;
             if ((st = timing_collect(h, out.sweep_ms, out.launches)) != VTM_OK) return st;
             // progress: some column fell by at least 20% since its best check

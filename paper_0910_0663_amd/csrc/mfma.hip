@@ -249,10 +249,14 @@ hipError_t launch_t(int S, int nrhs, int rc, size_t lds, const T* K, const int64
                     const typename Mma<T>::TV* a_cur, typename Mma<T>::TV* a_next, typename Mma<T>::TV* x,
                     bool write_x, hipStream_t st) {
     auto kern = k_sweep_mfma<T, typename MfmaTypes<T>::TB, NT, RT>;
-    if (lds > 65536) {
+    // raise the dynamic LDS limit once per instantiation (the first launch comes from
+    // the setup's autotuner, never from inside a graph capture)
+    static size_t lds_set = 65536;
+    if (lds > lds_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
+        lds_set = lds;
     }
     const unsigned ny = unsigned((nrhs + rc - 1) / rc);
     hipLaunchKernelGGL(kern, dim3(ny, S), dim3(kBlock), lds, st, K, mofs, sub_off, ports.off, ports.node,

@@ -291,3 +291,29 @@ def test_batched_layout_has_no_adjoint(torch):
     with pytest.raises(V.VTMError) as ei:
         s.solve_adjoint(to_dev(torch, w.b), 1e-8)
     assert ei.value.name == "VTM_E_UNSUPPORTED"
+
+
+# ----------------------------------------------------------------------------- hipGraph replay
+@pytest.mark.parametrize("cfg,kw,prec,nr", [
+    (1, dict(), "fp64", 1),
+    (5, dict(dims=(128, 128)), "fp32_refine", 1),
+    (4, dict(dims=(96, 96), nrhs=16), "bf16_refine", 16),
+])
+def test_graph_replay_matches_eager_bitwise(torch, cfg, kw, prec, nr):
+    """Check intervals replayed as captured hipGraphs give bitwise the eager
+    result with the same check schedule, solve after solve (each solve replays
+    its graphs many times, with the host's own eager work and synchronisations
+    in between)."""
+    V = vtm()
+    w = workloads.make(cfg, **kw)
+    b = to_dev(torch, w.b)
+    common = dict(precision=prec, nrhs_max=nr, check_every=4, adaptive_checks=False)
+    eager = V.Solver(w.A, w.part, w.Z, use_graph=False, **common)
+    graph = V.Solver(w.A, w.part, w.Z, use_graph=True, **common)
+    xe, re = eager.solve(b, w.tol)
+    for _ in range(3):
+        xg, rg = graph.solve(b, w.tol)
+        torch.cuda.synchronize()
+        assert rg.sweeps == re.sweeps and rg.outer == re.outer
+        assert torch.equal(xg, xe)
+    assert oracle.relative_residual(w.A, w.b, xe.cpu().numpy()).max() <= w.tol

@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "VTM time-to-1e-8 residual and sweeps/s; mixed/batched vs plain FP64 speedup"
 COUNTERS = os.path.join(ROOT, "profiles", "sweep_cfg2_counters.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_0910_0663_amd", "csrc", "sweep.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_0910_0663_amd", "csrc", "ports.hip")
 
 
 def log(*a):
@@ -38,6 +38,14 @@ def sweep_bytes(n, n_sub, n_wires, inverse_bytes):
     wave written (16 B), its c/beta/gamma (24 B) and node/slot/twin indices
     (12 B), and 16 B of offsets per sub-circuit."""
     return inverse_bytes + 16 * n + 2 * n_wires * 52 + 16 * n_sub
+
+
+def pp_bytes(n_sub, n_wires, operator_bytes):
+    """Algorithmic bytes of one port-to-port sweep launch: every port operator
+    once, per port the incident wave and h read, the twin index read and the
+    outgoing wave written (8 + 8 + 4 + 8 = 28 B), 12 B of offsets per
+    sub-circuit."""
+    return operator_bytes + 2 * n_wires * 28 + 12 * n_sub
 
 
 def kernel_hash():
@@ -82,6 +90,56 @@ def cpu_baseline(seconds):
                       f"single-threaded SuperLU and scipy.sparse"}
 
 
+def timed_solve(vtm, torch, w, precision, nrhs_max, reps=2):
+    """Setup (untimed here), one warm solve, then the mean of `reps` solves."""
+    s = vtm.Solver(w.A, w.part, w.Z, precision=precision, nrhs_max=nrhs_max)
+    b = torch.as_tensor(w.b, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(b)
+    s.solve(b, w.tol, x)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        _, rep = s.solve(b, w.tol, x)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) / reps * 1e3
+    s.close()
+    return ms, rep, x
+
+
+def mixed_and_batched(vtm, torch, oracle, workloads):
+    """The precision/batching forms against plain FP64 VTM on the same GPU, each
+    solved to relative residual 1e-8 (recomputed on the host in FP64)."""
+    res = {}
+    w = workloads.make(4)
+    t16, r16, x16 = timed_solve(vtm, torch, w, "bf16_refine", 64)
+    t64, r64, x64 = timed_solve(vtm, torch, w, "fp64", 64)
+    rel16 = float(oracle.relative_residual(w.A, w.b, x16.cpu().numpy()).max())
+    rel64 = float(oracle.relative_residual(w.A, w.b, x64.cpu().numpy()).max())
+    assert rel16 <= w.tol and rel64 <= w.tol, (rel16, rel64)
+    diff = float(((x16 - x64).norm(dim=1) / x64.norm(dim=1)).max())
+    res["batched_bf16_vs_fp64"] = {
+        "workload": f"1024x1024 grid, {w.n_sub} uneven sub-circuits (8..24 nodes a side), 64 RHS N(0,1), tol 1e-8",
+        "bf16_refine_ms": round(t16, 2), "fp64_batched_ms": round(t64, 2), "speedup": round(t64 / t16, 3),
+        "bf16_sweeps": r16.sweeps, "bf16_outer": r16.outer, "fp64_sweeps": r64.sweeps,
+        "bf16_relres": rel16, "fp64_relres": rel64, "bf16_vs_fp64_rel_error": diff,
+        "batch_shape_bf16": list(r16.batch_shape), "batch_shape_fp64": list(r64.batch_shape)}
+    log(f"cfg4: bf16 {t16:.1f} ms ({r16.sweeps} sweeps, {r16.outer} outer) vs fp64 batched {t64:.1f} ms "
+        f"({r64.sweeps} sweeps): x{t64 / t16:.2f}")
+    w = workloads.make(5)
+    t32, r32, x32 = timed_solve(vtm, torch, w, "fp32_refine", 1, reps=5)
+    t64, r64, x64 = timed_solve(vtm, torch, w, "fp64", 1, reps=5)
+    rel32 = float(oracle.relative_residual(w.A, w.b, x32.cpu().numpy()).max())
+    rel64 = float(oracle.relative_residual(w.A, w.b, x64.cpu().numpy()).max())
+    assert rel32 <= w.tol and rel64 <= w.tol, (rel32, rel64)
+    res["fp32_vs_fp64"] = {
+        "workload": "512x512 grid, 1,024 sub-circuits of 16x16, 1 RHS, tol 1e-8",
+        "fp32_refine_ms": round(t32, 3), "fp64_ms": round(t64, 3), "speedup": round(t64 / t32, 3),
+        "fp32_sweeps": r32.sweeps, "fp32_outer": r32.outer, "fp64_sweeps": r64.sweeps,
+        "fp32_relres": rel32, "fp64_relres": rel64}
+    log(f"cfg5: fp32 refine {t32:.2f} ms vs fp64 {t64:.2f} ms: x{t64 / t32:.2f}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +148,7 @@ def main():
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision / batched comparison")
     ap.add_argument("--counters", action="store_true",
                     help="for rocprofv3 --pmc: 16 sweeps of the workload, then a 1 GiB device copy "
                          "(known bytes) to calibrate the counters; prints no JSON")
@@ -145,12 +204,23 @@ def main():
     sweeps = sum(r.sweeps for r in reps)
     launches = sum(r.sweep_launches for r in reps)
     kern_ms = sum(r.sweep_kernel_ms for r in reps)
+    pp_launches = sum(r.pp_launches for r in reps)
+    pp_ms = sum(r.pp_kernel_ms for r in reps)
     host_rel = float(oracle.relative_residual(w.A, w.b, x.cpu().numpy()).max())
-    log(f"host-checked relres {host_rel:.3e}")
+    log(f"host-checked relres {host_rel:.3e}; full sweeps {launches}, port-to-port sweeps {pp_launches}")
     assert host_rel <= w.tol, host_rel
 
-    per_launch = sweep_bytes(w.n, s.n_sub, s.n_wires, s.inverse_bytes)
-    avg_launch_s = kern_ms / launches / 1e3
+    full_bytes = sweep_bytes(w.n, s.n_sub, s.n_wires, s.inverse_bytes)
+    full_s = kern_ms / launches / 1e3
+    roof_full = {"bound": "hbm", "kernel": "k_sweep1<double,double>", "achieved": round(full_bytes / full_s / 1e9, 1),
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(full_bytes / full_s / 1e9 / HBM_PEAK_GBS, 4),
+                 "bytes_per_launch": full_bytes, "avg_launch_us": round(full_s * 1e6, 2), "launches_timed": launches}
+    if pp_launches:
+        per_launch = pp_bytes(s.n_sub, s.n_wires, s.port_operator_bytes)
+        avg_launch_s = pp_ms / pp_launches / 1e3
+        kernel, n_timed = "k_sweep_pp<double,double>", pp_launches
+    else:
+        per_launch, avg_launch_s, kernel, n_timed = full_bytes, full_s, roof_full["kernel"], launches
     achieved = per_launch / avg_launch_s / 1e9
     traffic = measured_traffic(per_launch)
     out = {
@@ -169,7 +239,9 @@ def main():
         "config": {
             "workload": "2048x2048 5-point resistor grid, log-uniform g in [0.1,10] S, 0.01 S ground, "
                         "65,536 sub-circuits of 8x8 (dense FP64 inverse each), Z = 1/mean(g), "
-                        "1 RHS N(0,1), tol 1e-8, FP64",
+                        "1 RHS N(0,1), tol 1e-8, FP64; port-to-port sweeps with a full sweep "
+                        "before every residual check",
+            "port_operator_bytes": s.port_operator_bytes,
             "n": w.n,
             "sub_circuits": s.n_sub,
             "cut_wires": s.n_wires,
@@ -181,7 +253,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep<double,double>",
+            "kernel": kernel,
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -189,9 +261,13 @@ def main():
             "traffic": traffic,
             "bytes_per_launch": per_launch,
             "avg_launch_us": round(avg_launch_s * 1e6, 2),
-            "launches_timed": launches,
+            "launches_timed": n_timed,
         },
+        "roofline_full_sweep": roof_full,
     }
+    if not args.no_mixed:
+        log("mixed-precision and batched forms vs plain FP64 ...")
+        out["mixed_batched"] = mixed_and_batched(vtm, torch, oracle, workloads)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -87,7 +87,16 @@ typedef struct {
                                per pass, 3 or 5; 0 = chosen by the autotuner at setup */
     int32_t batch_rhs_block;/* batched sweep: right-hand sides per workgroup, 16, 32,
                                48 or 64; 0 = chosen by the autotuner at setup        */
-    int32_t reserved;
+    int32_t local_form;     /* 0: every sweep applies the full local inverse;
+                               1: port-to-port form (the interface-only iteration of
+                               the Appendix, eqs. 23-26): a sweep streams only the
+                               q x q operator between a sub-circuit's ports,
+                               M = diag(beta) K^-1[ports, ports] diag(c) + diag(gamma),
+                               plus h = beta K^-1 b; full sweeps remain for the first
+                               sweep of a solve and the last before each residual
+                               check.  Used for one right-hand side, FP64 or FP32,
+                               forward (and adjoint when A is symmetric), not on
+                               resume; otherwise the full form runs.                */
 } vtm_options;
 
 typedef struct {
@@ -100,6 +109,8 @@ typedef struct {
     int64_t sweep_launches; /* opt.timing: number of sweep launches timed            */
     int32_t batch_row_tiles;/* batched sweep shape in use (0 when not batched)       */
     int32_t batch_rhs_block;
+    double pp_kernel_ms;    /* opt.timing: summed duration of the port-to-port sweeps */
+    int64_t pp_launches;    /* opt.timing: number of port-to-port sweeps timed       */
     double *relres;         /* optional caller array [nrhs]: final per-column value  */
 } vtm_report;
 
@@ -107,7 +118,7 @@ typedef struct vtm_handle_s *vtm_handle;
 
 /* Fills *opt with defaults: FP64, nrhs_max 1, check_every 8, max_outer 30,
  * max_sweeps 1000000, divergence 1e6, inner_drop 0, use_graph 0, timing 0,
- * adaptive_checks 1, batch_row_tiles 0, batch_rhs_block 0. */
+ * adaptive_checks 1, batch_row_tiles 0, batch_rhs_block 0, local_form 1. */
 void vtm_default_options(vtm_options *opt);
 
 /*
@@ -188,9 +199,10 @@ vtm_status vtm_grad(vtm_handle h, const double *x, const double *lambda, int32_t
 vtm_status vtm_get_waves(vtm_handle h, double *waves, int32_t nrhs);
 vtm_status vtm_set_waves(vtm_handle h, const double *waves, int32_t nrhs);
 
-/* Sizes of a handle: nodes, sub-circuits, cut wires, bytes of stored inverses. */
+/* Sizes of a handle: nodes, sub-circuits, cut wires, bytes of the stored
+ * inverses and of the port-to-port operators (0 when not built).  NULLs skipped. */
 vtm_status vtm_info(vtm_handle h, int64_t *n, int64_t *n_sub, int64_t *n_wires,
-                    int64_t *inverse_bytes);
+                    int64_t *inverse_bytes, int64_t *port_operator_bytes);
 
 void vtm_destroy(vtm_handle h);
 const char *vtm_status_str(vtm_status s);

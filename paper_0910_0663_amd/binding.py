@@ -45,14 +45,14 @@ class Options(C.Structure):
                 ("max_outer", C.c_int32), ("max_sweeps", C.c_int64), ("divergence", C.c_double),
                 ("inner_drop", C.c_double), ("use_graph", C.c_int32), ("timing", C.c_int32),
                 ("adaptive_checks", C.c_int32), ("batch_row_tiles", C.c_int32),
-                ("batch_rhs_block", C.c_int32), ("reserved", C.c_int32)]
+                ("batch_rhs_block", C.c_int32), ("local_form", C.c_int32)]
 
 
 class Report(C.Structure):
     _fields_ = [("sweeps", C.c_int64), ("outer", C.c_int32), ("checks", C.c_int32),
                 ("relres_max", C.c_double), ("solve_ms", C.c_double), ("sweep_kernel_ms", C.c_double),
                 ("sweep_launches", C.c_int64), ("batch_row_tiles", C.c_int32), ("batch_rhs_block", C.c_int32),
-                ("relres", C.POINTER(C.c_double))]
+                ("pp_kernel_ms", C.c_double), ("pp_launches", C.c_int64), ("relres", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -82,7 +82,7 @@ def lib() -> C.CDLL:
     L.vtm_get_waves.restype = C.c_int
     L.vtm_set_waves.argtypes = [vp, vp, i32]
     L.vtm_set_waves.restype = C.c_int
-    L.vtm_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    L.vtm_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     L.vtm_info.restype = C.c_int
     L.vtm_destroy.argtypes = [vp]
     L.vtm_destroy.restype = None
@@ -152,6 +152,8 @@ class SolveReport:
     sweep_kernel_ms: float = 0.0
     sweep_launches: int = 0
     batch_shape: tuple = (0, 0)
+    pp_kernel_ms: float = 0.0
+    pp_launches: int = 0
 
 
 def _ptr(t) -> int:
@@ -166,7 +168,8 @@ class Solver:
 
     def __init__(self, A, part, Z, precision="fp64", nrhs_max=1, check_every=8,
                  max_sweeps=1_000_000, divergence=1e6, inner_drop=0.0, max_outer=30,
-                 use_graph=False, timing=False, adaptive_checks=True, batch_shape=(0, 0), stream=None):
+                 use_graph=False, timing=False, adaptive_checks=True, batch_shape=(0, 0), local_form="port",
+                 stream=None):
         import torch
         L = lib()
         if not torch.cuda.is_available():
@@ -185,6 +188,7 @@ class Solver:
         opt.timing = 1 if timing else 0
         opt.adaptive_checks = 1 if adaptive_checks else 0
         opt.batch_row_tiles, opt.batch_rhs_block = int(batch_shape[0]), int(batch_shape[1])
+        opt.local_form = {"full": 0, "port": 1}[local_form] if isinstance(local_form, str) else int(local_form)
         self.precision = precision
         self.nrhs_max = int(nrhs_max)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -198,9 +202,10 @@ class Solver:
         _check(L.vtm_setup(C.byref(hc.s), part.ctypes.data_as(C.POINTER(C.c_int32)), zp, nz, C.byref(opt),
                            C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
-        n, ns, nw, kb = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
-        _check(L.vtm_info(h, C.byref(n), C.byref(ns), C.byref(nw), C.byref(kb)))
+        n, ns, nw, kb, pb = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(L.vtm_info(h, C.byref(n), C.byref(ns), C.byref(nw), C.byref(kb), C.byref(pb)))
         self.n_sub, self.n_wires, self.inverse_bytes = ns.value, nw.value, kb.value
+        self.port_operator_bytes = pb.value
 
     # -- helpers ---------------------------------------------------------------
     def _vec(self, t, name):
@@ -223,7 +228,8 @@ class Solver:
         with self._torch.cuda.stream(self.stream):
             st = fn(self._h, C.c_void_p(_ptr(b)), C.c_void_p(_ptr(x)), nrhs, float(tol), C.byref(rep))
         r = SolveReport(rep.sweeps, rep.outer, rep.checks, rep.relres_max, rep.solve_ms, rel.copy(),
-                        rep.sweep_kernel_ms, rep.sweep_launches, (rep.batch_row_tiles, rep.batch_rhs_block))
+                        rep.sweep_kernel_ms, rep.sweep_launches, (rep.batch_row_tiles, rep.batch_rhs_block),
+                        rep.pp_kernel_ms, rep.pp_launches)
         _check(st, r)
         return x, r
 

@@ -76,6 +76,11 @@ struct vtm_handle_s {
     DevBuf<__bf16> Kbf;
     DevBuf<int64_t> mofs;
     bool tiles = false;
+    // port-to-port operators (opt.local_form = 1): M_s per sub-circuit and h per solve
+    bool pp = false;
+    DevBuf<int64_t> pofs;
+    DevBuf<double> M64, h64;
+    DevBuf<float> M32, h32;
     size_t lds_limit = 65536;
     int mfma_variant = 0;                 // chosen by the autotuner
     int mfma_rc = 0;
@@ -90,6 +95,7 @@ struct vtm_handle_s {
     bool waves_set = false;               // next solve resumes from the stored waves
     // per-launch timing of the sweep kernel (opt.timing)
     std::vector<hipEvent_t> ev;
+    std::vector<char> ev_tag;             // per event pair: 0 full sweep, 1 port-to-port sweep
     size_t ev_used = 0;
     // captured check intervals (opt.use_graph), keyed by everything their launches depend on
     std::map<std::array<int, 6>, hipGraphExec_t> graphs;
@@ -148,27 +154,44 @@ vtm_status residual(vtm_handle h, const double* b, const TX* x, int nrhs, double
     return residual_finish(h, nrhs, rel);
 }
 
-struct IterOut;
+struct IterOut {
+    int64_t sweeps = 0;
+    int checks = 0;
+    int outer = 0;
+    double sweep_ms = 0.0;   // full sweeps (opt.timing)
+    int64_t launches = 0;
+    double pp_ms = 0.0;      // port-to-port sweeps (opt.timing)
+    int64_t pp_launches = 0;
+    std::vector<double> rel;
+    vtm_status status = VTM_OK;
+};
 
-// Event pair around one sweep launch (opt.timing); events are reused per check interval.
-vtm_status timing_event(vtm_handle h, hipEvent_t* out) {
+// Event around a sweep launch (opt.timing); pairs are reused per check interval.
+vtm_status timing_event(vtm_handle h, hipEvent_t* out, char tag) {
     if (h->ev_used == h->ev.size()) {
         hipEvent_t e;
         VTM_HIP(hipEventCreate(&e));
         h->ev.push_back(e);
+        h->ev_tag.push_back(0);
     }
+    h->ev_tag[h->ev_used] = tag;
     *out = h->ev[h->ev_used++];
     VTM_HIP(hipEventRecord(*out, h->stream));
     return VTM_OK;
 }
 
 // Sums the durations of the recorded event pairs (after a stream sync) and resets them.
-vtm_status timing_collect(vtm_handle h, double& ms, int64_t& launches) {
+vtm_status timing_collect(vtm_handle h, IterOut& out) {
     for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
         float t = 0.f;
         VTM_HIP(hipEventElapsedTime(&t, h->ev[k], h->ev[k + 1]));
-        ms += t;
-        ++launches;
+        if (h->ev_tag[k]) {
+            out.pp_ms += t;
+            ++out.pp_launches;
+        } else {
+            out.sweep_ms += t;
+            ++out.launches;
+        }
     }
     h->ev_used = 0;
     return VTM_OK;
@@ -209,15 +232,39 @@ vtm_status launch_one(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
 
 // One sweep on the FP64 or FP32/BF16 buffers; cur selects the wave buffer read.
 // write_x: the sweep's x must be complete (the last sweep before a check).
+// pp: a port-to-port sweep (waves only; needs h of this right-hand side).
 vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, int cur, bool adjoint,
-                      bool write_x) {
+                      bool write_x, bool pp = false) {
     hipEvent_t e0, e1;
     vtm_status st;
     const bool timed = h->opt.timing && !h->capturing;
-    if (timed && (st = timing_event(h, &e0)) != VTM_OK) return st;
-    if ((st = launch_one(h, low, nrhs, b, x, cur, adjoint, h->mfma_variant, h->mfma_rc, write_x)) != VTM_OK)
+    if (timed && (st = timing_event(h, &e0, pp ? 1 : 0)) != VTM_OK) return st;
+    if (pp) {
+        const vtm::Plan& P = h->plan;
+        if (!low)
+            VTM_HIP((vtm::launch_sweep_pp<double, double>(int(P.S), P.max_ports, h->M64.p, h->pofs.p, h->port_off.p,
+                                                          h->port_twin.p, h->h64.p, h->a64[cur].p, h->a64[cur ^ 1].p,
+                                                          h->stream)));
+        else
+            VTM_HIP((vtm::launch_sweep_pp<float, float>(int(P.S), P.max_ports, h->M32.p, h->pofs.p, h->port_off.p,
+                                                        h->port_twin.p, h->h32.p, h->a32[cur].p, h->a32[cur ^ 1].p,
+                                                        h->stream)));
+    } else if ((st = launch_one(h, low, nrhs, b, x, cur, adjoint, h->mfma_variant, h->mfma_rc, write_x)) != VTM_OK) {
         return st;
-    if (timed) return timing_event(h, &e1);
+    }
+    if (timed) return timing_event(h, &e1, pp ? 1 : 0);
+    return VTM_OK;
+}
+
+// h_p = beta_p x_i(p) from the x just computed (x = K^-1 b: the first sweep from zero waves)
+vtm_status port_h(vtm_handle h, bool low) {
+    const vtm::Plan& P = h->plan;
+    if (!low)
+        VTM_HIP(vtm::launch_port_h<double>(int(P.S), h->sub_off.p, h->port_off.p, h->port_node.p, h->beta64.p,
+                                           h->xp.p, h->h64.p, h->stream));
+    else
+        VTM_HIP(vtm::launch_port_h<float>(int(P.S), h->sub_off.p, h->port_off.p, h->port_node.p, h->beta32.p,
+                                          h->d32.p, h->h32.p, h->stream));
     return VTM_OK;
 }
 
@@ -274,18 +321,22 @@ vtm_status autotune(vtm_handle h) {
 
 // One check interval: `chunk` sweeps from wave buffer `cur`, then the FP64
 // residual check.  Plain form: b = bp, x = xp, check of b - A x.  Inner form
-// (low precision): x = d32, check of r - A d.  With opt.use_graph the
-// interval is captured once per (form, nrhs, adjoint, length, start buffer)
-// and replayed as one hipGraph launch.
+// (low precision): x = d32, check of r - A d.  pp: sweeps in between are
+// port-to-port, the last one is a full sweep (it rebuilds x for the check);
+// first: the interval starts the solve from zero waves, so its first sweep is
+// a full one and yields h.  With opt.use_graph the interval is captured once
+// per shape and replayed as one hipGraph launch.
 vtm_status run_chunk(vtm_handle h, bool low, int nrhs, bool adjoint, int64_t chunk, int cur,
-                     std::vector<double>& rel) {
+                     std::vector<double>& rel, bool pp, bool first) {
     const void* b = low ? (h->tiles ? static_cast<const void*>(h->b16.p) : static_cast<const void*>(h->b32.p))
                         : static_cast<const void*>(h->bp.p);
     void* x = low ? static_cast<void*>(h->d32.p) : static_cast<void*>(h->xp.p);
     auto enqueue = [&]() -> vtm_status {
         for (int64_t k = 0; k < chunk; ++k) {
-            vtm_status st = sweep_once(h, low, nrhs, b, x, (cur + int(k)) & 1, adjoint, k + 1 == chunk);
+            const bool full = !pp || k + 1 == chunk || (first && k == 0);
+            vtm_status st = sweep_once(h, low, nrhs, b, x, (cur + int(k)) & 1, adjoint, k + 1 == chunk, !full);
             if (st != VTM_OK) return st;
+            if (pp && first && k == 0 && (st = port_h(h, low)) != VTM_OK) return st;
         }
         return low ? residual_launch<float>(h, h->rp.p, h->d32.p, nrhs, nullptr, adjoint)
                    : residual_launch<double>(h, h->bp.p, h->xp.p, nrhs, nullptr, adjoint);
@@ -309,7 +360,7 @@ vtm_status run_chunk(vtm_handle h, bool low, int nrhs, bool adjoint, int64_t chu
         ~Swap() { h->stream = saved; }
     } swap{h, h->stream};
     h->stream = h->gstream;
-    const std::array<int, 6> key{int(low), nrhs, int(adjoint), int(chunk), cur, 0};
+    const std::array<int, 6> key{int(low), nrhs, int(adjoint), int(chunk), cur, int(pp) * 2 + int(first)};
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
         VTM_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
@@ -333,15 +384,6 @@ vtm_status run_chunk(vtm_handle h, bool low, int nrhs, bool adjoint, int64_t chu
     return residual_finish(h, nrhs, rel);
 }
 
-struct IterOut {
-    int64_t sweeps = 0;
-    int checks = 0;
-    int outer = 0;
-    double sweep_ms = 0.0;
-    int64_t launches = 0;
-    std::vector<double> rel;
-    vtm_status status = VTM_OK;
-};
 
 // Where the next residual check goes.  With adaptive checks, once two checks
 // show the residual falling, the per-sweep rate predicts the sweeps left to the
@@ -406,14 +448,15 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
     };
     if (done(out.rel)) return VTM_OK;
     if (!resume) cad.record(0, max_of(out.rel));
+    const bool pp = h->pp && nrhs == 1 && (!adjoint || P.symmetric) && !resume;
     while (true) {
         const int64_t chunk = std::min<int64_t>(graph_length(h, cad.next(tol)), h->opt.max_sweeps - out.sweeps);
-        st = run_chunk(h, false, nrhs, adjoint, chunk, cur, out.rel);
+        st = run_chunk(h, false, nrhs, adjoint, chunk, cur, out.rel, pp, out.sweeps == 0);
         if (st != VTM_OK) return st;
         cur ^= int(chunk & 1);
         out.sweeps += chunk;
         ++out.checks;
-        if ((st = timing_collect(h, out.sweep_ms, out.launches)) != VTM_OK) return st;
+        if ((st = timing_collect(h, out)) != VTM_OK) return st;
         bool bad = false;
         for (double v : out.rel)
             if (!std::isfinite(v) || v > h->opt.divergence) bad = true;
@@ -443,6 +486,7 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
     if (!(drop > 0.0)) drop = h->opt.precision == VTM_BF16_REFINE ? 1e-2 : 1e-5;
     VTM_HIP(vtm::launch_fill<double>(nv, 0.0, h->xp.p, h->stream));
     std::vector<double> rel, e, target(nrhs);
+    const bool pp = h->pp && nrhs == 1 && (!adjoint || P.symmetric);
     auto all_le = [](const std::vector<double>& v, const std::vector<double>& t) {
         for (size_t i = 0; i < v.size(); ++i)
             if (!(v[i] <= t[i])) return false;
@@ -487,12 +531,12 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
             const int64_t chunk = std::min<int64_t>(
                 graph_length(h, std::min<int64_t>(cad.next(goal), 4 * cad.m)), h->opt.max_sweeps - inner);
             // sweeps, then ||r - A d|| / ||r|| in FP64
-            st = run_chunk(h, true, nrhs, adjoint, chunk, cur, e);
+            st = run_chunk(h, true, nrhs, adjoint, chunk, cur, e, pp, inner == 0);
             if (st != VTM_OK) return st;
             cur ^= int(chunk & 1);
             inner += chunk;
             ++out.checks;
-            if ((st = timing_collect(h, out.sweep_ms, out.launches)) != VTM_OK) return st;
+            if ((st = timing_collect(h, out)) != VTM_OK) return st;
             // progress: some column fell by at least 20% since its best check
             bool improved = false, bad = false;
             for (int r = 0; r < nrhs; ++r) {
@@ -545,6 +589,8 @@ vtm_status solve_common(vtm_handle h, const double* b, double* x, int32_t nrhs, 
         rep->solve_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
         rep->sweep_kernel_ms = out.sweep_ms;
         rep->sweep_launches = out.launches;
+        rep->pp_kernel_ms = out.pp_ms;
+        rep->pp_launches = out.pp_launches;
         rep->batch_row_tiles = h->tiles ? (h->mfma_variant ? 5 : 3) : 0;
         rep->batch_rhs_block = h->tiles ? h->mfma_rc : 0;
         if (rep->relres)
@@ -574,6 +620,7 @@ void vtm_default_options(vtm_options* opt) {
     opt->adaptive_checks = 1;
     opt->batch_row_tiles = 0;
     opt->batch_rhs_block = 0;
+    opt->local_form = 1;
 }
 
 const char* vtm_status_str(vtm_status s) {
@@ -629,6 +676,7 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     if (o.nrhs_max < 1 || o.nrhs_max > 256) return fail(VTM_E_ARG, "nrhs_max outside 1..256");
     if (o.check_every < 1 || o.max_sweeps < 1 || o.max_outer < 0 || !(o.divergence > 0.0))
         return fail(VTM_E_ARG, "bad iteration limits");
+    if (o.local_form != 0 && o.local_form != 1) return fail(VTM_E_ARG, "local_form must be 0 or 1");
     if ((o.batch_row_tiles != 0 && o.batch_row_tiles != 3 && o.batch_row_tiles != 5) ||
         (o.batch_rhs_block != 0 && (o.batch_rhs_block % 16 != 0 || o.batch_rhs_block > 64 || o.batch_rhs_block < 0)))
         return fail(VTM_E_ARG, "bad batched kernel shape");
@@ -688,10 +736,10 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     const int64_t nm = P.mofs[P.S];
     DevBuf<double> scratch;
     if (h->tiles || P.max_ns > vtm::kLdsSetupMax) VTM_HIP(scratch.alloc(nk));
+    VTM_HIP(h->c64.upload(P.pc, s));
+    VTM_HIP(h->beta64.upload(P.pbeta, s));
+    VTM_HIP(h->gamma64.upload(P.pgamma, s));
     if (o.precision == VTM_FP64) {
-        VTM_HIP(h->c64.upload(P.pc, s));
-        VTM_HIP(h->beta64.upload(P.pbeta, s));
-        VTM_HIP(h->gamma64.upload(P.pgamma, s));
         VTM_HIP(h->a64[0].alloc(P.nports * nr));
         VTM_HIP(h->a64[1].alloc(P.nports * nr));
         VTM_HIP(vtm::launch_fill<double>(P.nports * nr, 0.0, h->a64[0].p, s));
@@ -734,6 +782,26 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     VTM_HIP(hipMemcpyAsync(&flag, h->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
     VTM_HIP(hipStreamSynchronize(s));
     if (flag & 1) return fail(VTM_E_SINGULAR, "a sub-circuit matrix is singular");
+    // port-to-port operators from the stored inverses
+    h->pp = o.local_form == 1 && !h->tiles && P.nports > 0;
+    if (h->pp) {
+        VTM_HIP(h->pofs.upload(P.pofs, s));
+        const int64_t npm = P.pofs[P.S];
+        if (o.precision == VTM_FP64) {
+            VTM_HIP(h->M64.alloc(npm));
+            VTM_HIP(h->h64.alloc(P.nports));
+            VTM_HIP(vtm::launch_port_matrix<double>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p, h->port_node.p,
+                                                    h->c64.p, h->beta64.p, h->gamma64.p, h->K64.p, h->pofs.p,
+                                                    h->M64.p, s));
+        } else {
+            VTM_HIP(h->M32.alloc(npm));
+            VTM_HIP(h->h32.alloc(P.nports));
+            VTM_HIP(vtm::launch_port_matrix<float>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p, h->port_node.p,
+                                                   h->c64.p, h->beta64.p, h->gamma64.p, h->K32.p, h->pofs.p,
+                                                   h->M32.p, s));
+        }
+        VTM_HIP(hipStreamSynchronize(s));
+    }
     if (h->tiles) {
         st = autotune(h.get());
         if (st != VTM_OK) return st;
@@ -787,16 +855,15 @@ vtm_status vtm_set_waves(vtm_handle h, const double* waves, int32_t nrhs) {
     return VTM_OK;
 }
 
-vtm_status vtm_info(vtm_handle h, int64_t* n, int64_t* n_sub, int64_t* n_wires, int64_t* inverse_bytes) {
+vtm_status vtm_info(vtm_handle h, int64_t* n, int64_t* n_sub, int64_t* n_wires, int64_t* inverse_bytes,
+                    int64_t* port_operator_bytes) {
     if (!h) return fail(VTM_E_ARG, "null handle");
+    const int64_t esize = h->opt.precision == VTM_FP64 ? 8 : (h->opt.precision == VTM_FP32_REFINE ? 4 : 2);
     if (n) *n = h->plan.n;
     if (n_sub) *n_sub = h->plan.S;
     if (n_wires) *n_wires = h->plan.nwires;
-    if (inverse_bytes) {
-        const int64_t elems = h->tiles ? h->plan.mofs[h->plan.S] : h->plan.kofs[h->plan.S];
-        const int64_t esize = h->opt.precision == VTM_FP64 ? 8 : (h->opt.precision == VTM_FP32_REFINE ? 4 : 2);
-        *inverse_bytes = elems * esize;
-    }
+    if (inverse_bytes) *inverse_bytes = (h->tiles ? h->plan.mofs[h->plan.S] : h->plan.kofs[h->plan.S]) * esize;
+    if (port_operator_bytes) *port_operator_bytes = h->pp ? h->plan.pofs[h->plan.S] * esize : 0;
     return VTM_OK;
 }
 

@@ -72,6 +72,23 @@ hipError_t launch_sweep_mfma(int S, int max_ns, int max_ports, int nrhs, int var
                              typename MfmaTypes<T>::TV* a_next, typename MfmaTypes<T>::TV* x, bool write_x,
                              hipStream_t st);
 
+// ---- port-to-port form (ports.hip) -------------------------------------------
+// M_s = diag(beta) K^-1[i(P), i(P)] diag(c) + diag(gamma) for every sub-circuit,
+// from the stored inverses (column-group layout), into M + pofs[s] (same layout,
+// n = q_s).  Coefficients in FP64.
+template <typename TO>
+hipError_t launch_port_matrix(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* port_off,
+                              const int32_t* port_node, const double* pc, const double* pbeta,
+                              const double* pgamma, const TO* K, const int64_t* pofs, TO* M, hipStream_t st);
+// h_p = beta_p x_i(p) (one right-hand side; x renumbered)
+template <typename TV>
+hipError_t launch_port_h(int S, const int32_t* sub_off, const int32_t* port_off, const int32_t* port_node,
+                         const TV* pbeta, const TV* x, TV* h, hipStream_t st);
+// a_next[twin(p)] = h_p + (M_s a_cur)_p for every port (one right-hand side)
+template <typename TO, typename TV>
+hipError_t launch_sweep_pp(int S, int max_q, const TO* M, const int64_t* pofs, const int32_t* port_off,
+                           const int32_t* port_twin, const TV* h, const TV* a_cur, TV* a_next, hipStream_t st);
+
 // ---- residual -------------------------------------------------------------
 // r = b - A x in FP64 on the untorn (renumbered) A; per right-hand side
 // sums of r^2 and b^2 land in norms[2 * rhs + {0, 1}] (fixed summation order).

@@ -29,6 +29,23 @@ __host__ __device__ inline int64_t inv_offset(int n, int r, int c) {
     return int64_t(full) * n + int64_t(c - full) * n + r;
 }
 
+// (r, c) of the d-th stored element of an n x n block (inverse of inv_offset)
+template <typename T>
+__host__ __device__ inline void inv_rc(int n, int64_t d, int& r, int& c) {
+    constexpr int G = Group<T>::G;
+    const int full = (n / G) * G;
+    const int64_t head = int64_t(full) * n;
+    if (d < head) {
+        const int64_t g = d / (int64_t(n) * G), rem = d - g * int64_t(n) * G;
+        r = int(rem / G);
+        c = int(g) * G + int(rem % G);
+    } else {
+        const int64_t e = d - head;
+        c = full + int(e / n);
+        r = int(e % n);
+    }
+}
+
 // elements reserved for an n x n block (rounded up to a multiple of 4)
 __host__ __device__ inline int64_t inv_block_elems(int n) { return (int64_t(n) * n + 3) & ~int64_t(3); }
 

@@ -26,6 +26,7 @@ struct Plan {
     std::vector<int32_t> sub_off;  // [S + 1] first new id of each sub-circuit
     std::vector<int64_t> kofs;     // [S + 1] element offset of each dense inverse
     std::vector<int64_t> mofs;     // [S + 1] element offset of each padded MFMA tile block
+    std::vector<int64_t> pofs;     // [S + 1] element offset of each port-to-port operator (q_s x q_s)
     int32_t max_ports = 0;         // most ports on one sub-circuit
 
     // Cut wires in canonical order (lower node, then upper node, ascending; old ids).

@@ -53,23 +53,6 @@ __device__ int block_argmax(const double* colp, int stride, int lo, int n, doubl
     return p;
 }
 
-// (r, c) of the d-th stored element of an n x n block (inverse of inv_offset)
-template <typename T>
-__device__ inline void inv_rc(int n, int64_t d, int& r, int& c) {
-    constexpr int G = Group<T>::G;
-    const int full = (n / G) * G;
-    const int64_t head = int64_t(full) * n;
-    if (d < head) {
-        const int64_t g = d / (int64_t(n) * G), rem = d - g * int64_t(n) * G;
-        r = int(rem / G);
-        c = int(g) * G + int(rem % G);
-    } else {
-        const int64_t e = d - head;
-        c = full + int(e / n);
-        r = int(e % n);
-    }
-}
-
 // Writes the column-major FP64 inverse Mcm (Mcm[c * n + r] = Kinv(r, c)) into
 // dst in the column-group layout; destination-ordered, so stores are coalesced.
 template <typename TO>

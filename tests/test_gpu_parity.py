@@ -51,10 +51,12 @@ def oracle_iterates(w, ks, b=None, transpose=False):
     return out
 
 
-def gpu_iterate(torch, w, k, b=None, adjoint=False, nrhs_max=None):
-    """x^k of the HIP path: max_sweeps = k with an unreachable tolerance."""
+def gpu_iterate(torch, w, k, b=None, adjoint=False, nrhs_max=None, check_every=1, **kw):
+    """x^k of the HIP path: max_sweeps = k with an unreachable tolerance.  With
+    check_every = k the sweeps between the first and the last are port-to-port."""
     b = w.b if b is None else b
-    s = vtm().Solver(w.A, w.part, w.Z, nrhs_max=nrhs_max or b.shape[0], check_every=1, max_sweeps=k)
+    s = vtm().Solver(w.A, w.part, w.Z, nrhs_max=nrhs_max or b.shape[0], check_every=check_every, max_sweeps=k,
+                     adaptive_checks=False, **kw)
     x = torch.empty((b.shape[0], w.n), dtype=torch.float64, device="cuda")
     fn = s.solve_adjoint if adjoint else s.solve
     with pytest.raises(vtm().VTMError) as ei:
@@ -85,6 +87,37 @@ def test_iterates_match_oracle(torch, cfg, kw):
     ref = oracle_iterates(w, ks)
     for k in ks:
         assert_close(gpu_iterate(torch, w, k), ref[k])
+
+
+@pytest.mark.parametrize("cfg,kw,prec", [
+    (1, dict(), "fp64"),
+    (2, dict(dims=(64, 64)), "fp64"),
+    (3, dict(dims=(16, 16, 16)), "fp64"),
+    (4, dict(dims=(64, 64)), "fp64"),
+])
+def test_port_to_port_iterates_match_oracle(torch, cfg, kw, prec):
+    """Sweeps that stream only the port-to-port operator (Appendix, eqs. 23-26)
+    give the oracle's iterates: x^k after a first full sweep, k - 2 port-to-port
+    sweeps and a last full sweep."""
+    w = workloads.make(cfg, **kw)
+    ks = [2, 9, 40]
+    ref = oracle_iterates(w, ks)
+    for k in ks:
+        assert_close(gpu_iterate(torch, w, k, check_every=k, local_form="port"), ref[k])
+
+
+def test_port_to_port_and_full_forms_agree(torch):
+    """The two local forms reach the tolerance after the same sweeps and agree."""
+    w = workloads.make(2, dims=(256, 256))
+    xs = []
+    for form in ("full", "port"):
+        s = vtm().Solver(w.A, w.part, w.Z, check_every=8, adaptive_checks=False, local_form=form, timing=True)
+        x, rep = s.solve(to_dev(torch, w.b), w.tol)
+        xs.append((x.cpu().numpy(), rep))
+    (xf, rf), (xp, rp) = xs
+    assert rf.sweeps == rp.sweeps
+    assert rp.pp_launches > 0 and rf.pp_launches == 0
+    assert_close(xp, xf)
 
 
 def test_config1_sweeps_and_solution(torch):
@@ -156,18 +189,20 @@ def test_maxiter_divergence_and_arguments(torch):
 def test_resume_from_waves_is_bitwise_continuation(torch):
     """The iteration state is the wave vector: stopping after 24 sweeps,
     exporting and re-importing the waves, and continuing gives bitwise the same
-    iterate as an uninterrupted run."""
+    iterate as an uninterrupted run (full local form throughout: a resumed solve
+    has no zero-wave first sweep to take the port-to-port source term from)."""
     V = vtm()
     w = workloads.make(1)
     b = to_dev(torch, w.b)
-    full = V.Solver(w.A, w.part, w.Z, check_every=8, adaptive_checks=False)
+    kw = dict(check_every=8, adaptive_checks=False, local_form="full")
+    full = V.Solver(w.A, w.part, w.Z, **kw)
     x_full, rep_full = full.solve(b, w.tol)
-    part = V.Solver(w.A, w.part, w.Z, check_every=8, max_sweeps=24, adaptive_checks=False)
+    part = V.Solver(w.A, w.part, w.Z, max_sweeps=24, **kw)
     x_tmp = torch.empty_like(b)
     with pytest.raises(V.VTMError):
         part.solve(b, w.tol, x_tmp)
     waves = part.get_waves()
-    cont = V.Solver(w.A, w.part, w.Z, check_every=8, adaptive_checks=False)
+    cont = V.Solver(w.A, w.part, w.Z, **kw)
     cont.set_waves(waves)
     x_cont, rep_cont = cont.solve(b, w.tol)
     assert rep_cont.sweeps + 24 == rep_full.sweeps

@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision / batched comparison")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="for profiling: only the mixed-precision / batched comparison; prints its JSON")
     ap.add_argument("--counters", action="store_true",
                     help="for rocprofv3 --pmc: 16 sweeps of the workload, then a 1 GiB device copy "
                          "(known bytes) to calibrate the counters; prints no JSON")
@@ -165,6 +167,9 @@ def main():
     import paper_0910_0663_amd as vtm
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.batched_only:
+        print(json.dumps(mixed_and_batched(vtm, torch, oracle, workloads)), flush=True)
+        return
     t = time.perf_counter()
     w = workloads.make(2)
     log(f"workload {w.name}: n={w.n} sub-circuits={w.n_sub} ({time.perf_counter() - t:.1f} s to generate)")

@@ -40,14 +40,6 @@ def sweep_bytes(n, n_sub, n_wires, inverse_bytes):
     return inverse_bytes + 16 * n + 2 * n_wires * 52 + 16 * n_sub
 
 
-def pp_bytes(n_sub, n_wires, operator_bytes):
-    """Algorithmic bytes of one port-to-port sweep launch: every port operator
-    once, per port the incident wave and h read, the twin index read and the
-    outgoing wave written (8 + 8 + 4 + 8 = 28 B), 12 B of offsets per
-    sub-circuit."""
-    return operator_bytes + 2 * n_wires * 28 + 12 * n_sub
-
-
 def kernel_hash():
     with open(KERNEL_SRC, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
@@ -221,9 +213,9 @@ def main():
                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(full_bytes / full_s / 1e9 / HBM_PEAK_GBS, 4),
                  "bytes_per_launch": full_bytes, "avg_launch_us": round(full_s * 1e6, 2), "launches_timed": launches}
     if pp_launches:
-        per_launch = pp_bytes(s.n_sub, s.n_wires, s.port_operator_bytes)
+        per_launch = s.port_sweep_bytes
         avg_launch_s = pp_ms / pp_launches / 1e3
-        kernel, n_timed = "k_sweep_pp<double,double>", pp_launches
+        kernel, n_timed = "k_sweep_pps<double,double>", pp_launches
     else:
         per_launch, avg_launch_s, kernel, n_timed = full_bytes, full_s, roof_full["kernel"], launches
     achieved = per_launch / avg_launch_s / 1e9
@@ -244,8 +236,8 @@ def main():
         "config": {
             "workload": "2048x2048 5-point resistor grid, log-uniform g in [0.1,10] S, 0.01 S ground, "
                         "65,536 sub-circuits of 8x8 (dense FP64 inverse each), Z = 1/mean(g), "
-                        "1 RHS N(0,1), tol 1e-8, FP64; port-to-port sweeps with a full sweep "
-                        "before every residual check",
+                        "1 RHS N(0,1), tol 1e-8, FP64; port-to-port sweeps on the packed symmetric "
+                        "port-node operators, a full sweep before every residual check",
             "port_operator_bytes": s.port_operator_bytes,
             "n": w.n,
             "sub_circuits": s.n_sub,

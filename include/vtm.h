@@ -96,7 +96,11 @@ typedef struct {
                                sweep of a solve and the last before each residual
                                check.  Used for one right-hand side, FP64 or FP32,
                                forward (and adjoint when A is symmetric), not on
-                               resume; otherwise the full form runs.                */
+                               resume; otherwise the full form runs.  When A is
+                               symmetric the operator is stored once per port node
+                               pair as the packed upper triangle of K^-1 (half the
+                               bytes; beta and gamma formed from c on the fly);
+                               2: the same with the dense q x q operator M always. */
 } vtm_options;
 
 typedef struct {
@@ -200,9 +204,14 @@ vtm_status vtm_get_waves(vtm_handle h, double *waves, int32_t nrhs);
 vtm_status vtm_set_waves(vtm_handle h, const double *waves, int32_t nrhs);
 
 /* Sizes of a handle: nodes, sub-circuits, cut wires, bytes of the stored
- * inverses and of the port-to-port operators (0 when not built).  NULLs skipped. */
+ * inverses and of the port-to-port operators (0 when not built), and the
+ * algorithmic bytes one port-to-port sweep moves (operators once; per port the
+ * incident wave, h, c when packed, the outgoing wave and the twin index; per
+ * port node and sub-circuit their offsets).  NULLs skipped.  For symmetric A
+ * the operator is the packed upper triangle of K^-1 over a sub-circuit's port
+ * nodes (beta = 2 W c and gamma = 1 - 2 c are then formed on the fly). */
 vtm_status vtm_info(vtm_handle h, int64_t *n, int64_t *n_sub, int64_t *n_wires,
-                    int64_t *inverse_bytes, int64_t *port_operator_bytes);
+                    int64_t *inverse_bytes, int64_t *port_operator_bytes, int64_t *port_sweep_bytes);
 
 void vtm_destroy(vtm_handle h);
 const char *vtm_status_str(vtm_status s);

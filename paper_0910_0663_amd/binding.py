@@ -82,7 +82,8 @@ def lib() -> C.CDLL:
     L.vtm_get_waves.restype = C.c_int
     L.vtm_set_waves.argtypes = [vp, vp, i32]
     L.vtm_set_waves.restype = C.c_int
-    L.vtm_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    L.vtm_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
+                           C.POINTER(i64)]
     L.vtm_info.restype = C.c_int
     L.vtm_destroy.argtypes = [vp]
     L.vtm_destroy.restype = None
@@ -188,7 +189,7 @@ class Solver:
         opt.timing = 1 if timing else 0
         opt.adaptive_checks = 1 if adaptive_checks else 0
         opt.batch_row_tiles, opt.batch_rhs_block = int(batch_shape[0]), int(batch_shape[1])
-        opt.local_form = {"full": 0, "port": 1}[local_form] if isinstance(local_form, str) else int(local_form)
+        opt.local_form = {"full": 0, "port": 1, "port_dense": 2}[local_form] if isinstance(local_form, str) else int(local_form)
         self.precision = precision
         self.nrhs_max = int(nrhs_max)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -202,10 +203,10 @@ class Solver:
         _check(L.vtm_setup(C.byref(hc.s), part.ctypes.data_as(C.POINTER(C.c_int32)), zp, nz, C.byref(opt),
                            C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
-        n, ns, nw, kb, pb = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
-        _check(L.vtm_info(h, C.byref(n), C.byref(ns), C.byref(nw), C.byref(kb), C.byref(pb)))
+        n, ns, nw, kb, pb, sb = (C.c_int64() for _ in range(6))
+        _check(L.vtm_info(h, C.byref(n), C.byref(ns), C.byref(nw), C.byref(kb), C.byref(pb), C.byref(sb)))
         self.n_sub, self.n_wires, self.inverse_bytes = ns.value, nw.value, kb.value
-        self.port_operator_bytes = pb.value
+        self.port_operator_bytes, self.port_sweep_bytes = pb.value, sb.value
 
     # -- helpers ---------------------------------------------------------------
     def _vec(self, t, name):

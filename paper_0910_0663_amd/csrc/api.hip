@@ -81,6 +81,12 @@ struct vtm_handle_s {
     DevBuf<int64_t> pofs;
     DevBuf<double> M64, h64;
     DevBuf<float> M32, h32;
+    // symmetric A: packed port-node operators instead of M
+    bool pps = false;
+    DevBuf<int32_t> pn_off, pn_node, pn_pfirst;
+    DevBuf<int64_t> sofs;
+    DevBuf<double> S64, W64p;
+    DevBuf<float> S32, W32p;
     size_t lds_limit = 65536;
     int mfma_variant = 0;                 // chosen by the autotuner
     int mfma_rc = 0;
@@ -239,7 +245,20 @@ vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
     vtm_status st;
     const bool timed = h->opt.timing && !h->capturing;
     if (timed && (st = timing_event(h, &e0, pp ? 1 : 0)) != VTM_OK) return st;
-    if (pp) {
+    if (pp && h->pps) {
+        const vtm::Plan& P = h->plan;
+        const double W = P.nwires ? P.wW[0] : 0.0;
+        if (!low)
+            VTM_HIP((vtm::launch_sweep_pps<double, double>(int(P.S), P.max_npn, P.max_ports, h->S64.p, h->sofs.p, h->pn_off.p,
+                                                           h->pn_pfirst.p, h->port_off.p, h->port_twin.p, h->c64.p,
+                                                           h->W64p.p, W, h->h64.p, h->a64[cur].p, h->a64[cur ^ 1].p,
+                                                           h->stream)));
+        else
+            VTM_HIP((vtm::launch_sweep_pps<float, float>(int(P.S), P.max_npn, P.max_ports, h->S32.p, h->sofs.p, h->pn_off.p,
+                                                         h->pn_pfirst.p, h->port_off.p, h->port_twin.p, h->c32.p,
+                                                         h->W32p.p, float(W), h->h32.p, h->a32[cur].p,
+                                                         h->a32[cur ^ 1].p, h->stream)));
+    } else if (pp) {
         const vtm::Plan& P = h->plan;
         if (!low)
             VTM_HIP((vtm::launch_sweep_pp<double, double>(int(P.S), P.max_ports, h->M64.p, h->pofs.p, h->port_off.p,
@@ -676,7 +695,7 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     if (o.nrhs_max < 1 || o.nrhs_max > 256) return fail(VTM_E_ARG, "nrhs_max outside 1..256");
     if (o.check_every < 1 || o.max_sweeps < 1 || o.max_outer < 0 || !(o.divergence > 0.0))
         return fail(VTM_E_ARG, "bad iteration limits");
-    if (o.local_form != 0 && o.local_form != 1) return fail(VTM_E_ARG, "local_form must be 0 or 1");
+    if (o.local_form < 0 || o.local_form > 2) return fail(VTM_E_ARG, "local_form must be 0, 1 or 2");
     if ((o.batch_row_tiles != 0 && o.batch_row_tiles != 3 && o.batch_row_tiles != 5) ||
         (o.batch_rhs_block != 0 && (o.batch_rhs_block % 16 != 0 || o.batch_rhs_block > 64 || o.batch_rhs_block < 0)))
         return fail(VTM_E_ARG, "bad batched kernel shape");
@@ -783,8 +802,34 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     VTM_HIP(hipStreamSynchronize(s));
     if (flag & 1) return fail(VTM_E_SINGULAR, "a sub-circuit matrix is singular");
     // port-to-port operators from the stored inverses
-    h->pp = o.local_form == 1 && !h->tiles && P.nports > 0;
-    if (h->pp) {
+    h->pp = o.local_form >= 1 && !h->tiles && P.nports > 0;
+    h->pps = h->pp && o.local_form == 1 && P.symmetric && P.max_npn <= 64 && P.max_ports <= 64;
+    if (h->pps) {
+        VTM_HIP(h->pn_off.upload(P.pn_off, s));
+        VTM_HIP(h->pn_node.upload(P.pn_node, s));
+        VTM_HIP(h->pn_pfirst.upload(P.pn_pfirst, s));
+        VTM_HIP(h->sofs.upload(P.sofs, s));
+        std::vector<double> Wp;
+        if (!P.uniform_W) {  // line admittance per port (both ports of a wire share it)
+            Wp.resize(P.nports);
+            for (int64_t q = 0; q < P.nports; ++q) Wp[P.abi2port[q]] = P.wW[q / 2];
+        }
+        const int64_t nsp = P.sofs[P.S];
+        if (o.precision == VTM_FP64) {
+            VTM_HIP(h->S64.alloc(nsp));
+            VTM_HIP(h->h64.alloc(P.nports));
+            if (!P.uniform_W) VTM_HIP(h->W64p.upload(Wp, s));
+            VTM_HIP(vtm::launch_port_node_matrix<double>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p,
+                                                         h->pn_node.p, h->K64.p, h->sofs.p, h->S64.p, s));
+        } else {
+            VTM_HIP(h->S32.alloc(nsp));
+            VTM_HIP(h->h32.alloc(P.nports));
+            if (!P.uniform_W) VTM_HIP(h->W32p.upload(to_float(Wp), s));
+            VTM_HIP(vtm::launch_port_node_matrix<float>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p,
+                                                        h->pn_node.p, h->K32.p, h->sofs.p, h->S32.p, s));
+        }
+        VTM_HIP(hipStreamSynchronize(s));
+    } else if (h->pp) {
         VTM_HIP(h->pofs.upload(P.pofs, s));
         const int64_t npm = P.pofs[P.S];
         if (o.precision == VTM_FP64) {
@@ -856,14 +901,27 @@ vtm_status vtm_set_waves(vtm_handle h, const double* waves, int32_t nrhs) {
 }
 
 vtm_status vtm_info(vtm_handle h, int64_t* n, int64_t* n_sub, int64_t* n_wires, int64_t* inverse_bytes,
-                    int64_t* port_operator_bytes) {
+                    int64_t* port_operator_bytes, int64_t* port_sweep_bytes) {
     if (!h) return fail(VTM_E_ARG, "null handle");
+    const vtm::Plan& P = h->plan;
     const int64_t esize = h->opt.precision == VTM_FP64 ? 8 : (h->opt.precision == VTM_FP32_REFINE ? 4 : 2);
-    if (n) *n = h->plan.n;
-    if (n_sub) *n_sub = h->plan.S;
-    if (n_wires) *n_wires = h->plan.nwires;
-    if (inverse_bytes) *inverse_bytes = (h->tiles ? h->plan.mofs[h->plan.S] : h->plan.kofs[h->plan.S]) * esize;
-    if (port_operator_bytes) *port_operator_bytes = h->pp ? h->plan.pofs[h->plan.S] * esize : 0;
+    if (n) *n = P.n;
+    if (n_sub) *n_sub = P.S;
+    if (n_wires) *n_wires = P.nwires;
+    if (inverse_bytes) *inverse_bytes = (h->tiles ? P.mofs[P.S] : P.kofs[P.S]) * esize;
+    const int64_t op = h->pps ? P.sofs[P.S] * esize : (h->pp ? P.pofs[P.S] * esize : 0);
+    if (port_operator_bytes) *port_operator_bytes = op;
+    if (port_sweep_bytes) {
+        // operators once; per port the wave in, h in, wave out (and c for the packed form) plus
+        // the twin index; per port node its first port; per sub-circuit its offsets
+        if (h->pps)
+            *port_sweep_bytes = op + P.nports * (4 * esize + 4 + (P.uniform_W ? 0 : esize)) +
+                                int64_t(P.pn_node.size()) * 4 + P.S * 16;
+        else if (h->pp)
+            *port_sweep_bytes = op + P.nports * (3 * esize + 4) + P.S * 12;
+        else
+            *port_sweep_bytes = 0;
+    }
     return VTM_OK;
 }
 

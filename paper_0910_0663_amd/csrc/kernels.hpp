@@ -89,6 +89,24 @@ template <typename TO, typename TV>
 hipError_t launch_sweep_pp(int S, int max_q, const TO* M, const int64_t* pofs, const int32_t* port_off,
                            const int32_t* port_twin, const TV* h, const TV* a_cur, TV* a_next, hipStream_t st);
 
+// Symmetric A: upper triangle of S = K^-1[port nodes, port nodes] per
+// sub-circuit, stored by diagonals (diagonal d from d k - d (d - 1) / 2, k port
+// nodes), block start 16-byte aligned, at Sp + sofs[s] ...
+template <typename TO>
+hipError_t launch_port_node_matrix(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* pn_off,
+                                   const int32_t* pn_node, const TO* K, const int64_t* sofs, TO* Sp,
+                                   hipStream_t st);
+// ... and the port-to-port sweep on it: t_n = sum_{p at n} c_p a_p, z = S t,
+// a_next[twin(p)] = 2 W_p c_p z_n(p) + (1 - 2 c_p) a_p + h_p (pW null: W for
+// every port).  Needs at most 64 port nodes and 64 ports per sub-circuit (else
+// hipErrorInvalidValue); two sub-circuits share a wavefront when both maxima
+// are at most 32.
+template <typename TO, typename TV>
+hipError_t launch_sweep_pps(int S, int max_npn, int max_ports, const TO* Sp, const int64_t* sofs,
+                            const int32_t* pn_off, const int32_t* pn_pfirst, const int32_t* port_off,
+                            const int32_t* port_twin, const TV* pc, const TV* pW, TV W, const TV* h,
+                            const TV* a_cur, TV* a_next, hipStream_t st);
+
 // ---- residual -------------------------------------------------------------
 // r = b - A x in FP64 on the untorn (renumbered) A; per right-hand side
 // sums of r^2 and b^2 land in norms[2 * rhs + {0, 1}] (fixed summation order).

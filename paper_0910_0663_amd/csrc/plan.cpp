@@ -252,6 +252,27 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
         P.port_off[s + 1] += P.port_off[s];
     }
     for (int64_t q = 0; q < np; ++q) P.port_twin[P.abi2port[q]] = P.abi2port[q ^ 1];
+    for (int64_t e = 1; e < nw; ++e)
+        if (P.wW[e] != P.wW[0]) P.uniform_W = false;
+
+    // port nodes (runs of equal local node inside each sub-circuit's port range)
+    P.pn_off.assign(S + 1, 0);
+    P.pn_node.clear();
+    P.pn_pfirst.clear();
+    P.sofs.assign(S + 1, 0);
+    P.max_npn = 0;
+    for (int64_t s = 0; s < S; ++s) {
+        for (int32_t p = P.port_off[s]; p < P.port_off[s + 1]; ++p)
+            if (p == P.port_off[s] || P.port_node[p] != P.port_node[p - 1]) {
+                P.pn_node.push_back(P.port_node[p]);
+                P.pn_pfirst.push_back(p);
+            }
+        P.pn_off[s + 1] = int32_t(P.pn_node.size());
+        const int64_t k = P.pn_off[s + 1] - P.pn_off[s];
+        P.max_npn = std::max<int32_t>(P.max_npn, int32_t(k));
+        P.sofs[s + 1] = P.sofs[s] + ((k * (k + 1) / 2 + 3) & ~int64_t(3));
+    }
+    P.pn_pfirst.push_back(int32_t(np));
 
     // ---- renumbered untorn matrix ------------------------------------------------
     P.rowptr.assign(n + 1, 0);

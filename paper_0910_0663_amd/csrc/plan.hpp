@@ -27,6 +27,15 @@ struct Plan {
     std::vector<int64_t> kofs;     // [S + 1] element offset of each dense inverse
     std::vector<int64_t> mofs;     // [S + 1] element offset of each padded MFMA tile block
     std::vector<int64_t> pofs;     // [S + 1] element offset of each port-to-port operator (q_s x q_s)
+    // Port nodes: the distinct nodes carrying ports, per sub-circuit in port order.
+    std::vector<int32_t> pn_off;    // [S + 1] first port node of each sub-circuit
+    std::vector<int32_t> pn_node;   // local node of each port node
+    std::vector<int32_t> pn_pfirst; // [n_port_nodes + 1] first port of each port node (ports of one
+                                    // node are consecutive; the last entry is nports)
+    std::vector<int64_t> sofs;      // [S + 1] element offset of each packed symmetric block
+    int32_t max_npn = 0;            // most port nodes on one sub-circuit
+    bool uniform_W = true;          // one line admittance for every wire
+
     int32_t max_ports = 0;         // most ports on one sub-circuit
 
     // Cut wires in canonical order (lower node, then upper node, ascending; old ids).

@@ -178,3 +178,164 @@ template hipError_t launch_sweep_pp<float, float>(int, int, const float*, const 
                                                   const int32_t*, const float*, const float*, float*, hipStream_t);
 
 }  // namespace vtm
+
+// ---------------------------------------------------------------------------
+// Symmetric A: the port-node form.  K^-1 restricted to the port nodes,
+// S = K^-1[N, N], is symmetric, and with beta = 2 W c and gamma = 1 - 2 c the
+// outgoing waves are
+//     o_p = 2 W_p c_p z_n(p) + (1 - 2 c_p) a_p + h_p,   z = S t,  t_n = sum_{p at n} c_p a_p,
+// so a sweep streams only the upper triangle of S besides the per-port wave,
+// c, h and twin.  The triangle of a sub-circuit with k port nodes is stored by
+// diagonals: diagonal d (entries S(r, r + d), r = 0 .. k - d - 1) starts at
+// d k - d (d - 1) / 2, so lane r reads entry r of every diagonal with
+// coalesced loads and receives S(r - d, r) from lane r - d.
+// ---------------------------------------------------------------------------
+namespace vtm {
+namespace {
+
+__host__ __device__ inline int diag_start(int k, int d) { return d * k - (d * (d - 1)) / 2; }
+
+template <typename TO>
+__global__ void __launch_bounds__(256)
+    k_port_node_matrix(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs,
+                       const int32_t* __restrict__ pn_off, const int32_t* __restrict__ pn_node,
+                       const TO* __restrict__ K, const int64_t* __restrict__ sofs, TO* __restrict__ Sp) {
+    const int s = blockIdx.x;
+    const int ns = sub_off[s + 1] - sub_off[s];
+    const int k0 = pn_off[s], k = pn_off[s + 1] - k0;
+    const TO* Ks = K + kofs[s];
+    TO* out = Sp + sofs[s];
+    for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
+        const int r = t / k, c = t - r * k;
+        if (r <= c) out[diag_start(k, c - r) + r] = Ks[inv_offset<TO>(ns, pn_node[k0 + r], pn_node[k0 + c])];
+    }
+}
+
+// One wavefront per sub-circuit (HALF: two, 32 lanes each).  Lane r owns port
+// node r and port r of its sub-circuit; every global load of the sweep is
+// issued before the first barrier, and the diagonals stream CH at a time with
+// the next CH in flight.
+template <typename TO, typename TV, bool HALF>
+__global__ void __launch_bounds__(64)
+    k_sweep_pps(int S, const TO* __restrict__ Sp, const int64_t* __restrict__ sofs,
+                const int32_t* __restrict__ pn_off, const int32_t* __restrict__ pn_pfirst,
+                const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_twin,
+                const TV* __restrict__ pc, const TV* __restrict__ pW, TV W, const TV* __restrict__ h,
+                const TV* __restrict__ a_cur, TV* __restrict__ a_next) {
+    constexpr int L = HALF ? 32 : 64;
+    constexpr int CH = 8;
+    __shared__ TV ca[64], tv[64], zv[64];
+    __shared__ int32_t pnode[64];
+    const int tid = threadIdx.x, r = tid % L, hb = tid - r;
+    const int s = blockIdx.x * (64 / L) + tid / L;
+    int k = 0, q = 0, n0 = 0, p0 = 0;
+    int64_t e0 = 0;
+    if (s < S) {
+        n0 = pn_off[s];
+        k = pn_off[s + 1] - n0;
+        p0 = port_off[s];
+        q = port_off[s + 1] - p0;
+        e0 = sofs[s];
+    }
+    const TO* blk = Sp + e0;
+    const bool has_port = r < q;
+    TV c = TV(0), a = TV(0), hp = TV(0), w = W;
+    int tw = 0;
+    if (has_port) {
+        const int p = p0 + r;
+        c = pc[p];
+        a = a_cur[p];
+        hp = h[p];
+        tw = port_twin[p];
+        if (pW) w = pW[p];
+        ca[hb + r] = c * a;
+    }
+    int f0 = 0, f1 = 0;
+    if (r < k) {
+        f0 = pn_pfirst[n0 + r] - p0;
+        f1 = pn_pfirst[n0 + r + 1] - p0;
+    }
+    int kmax = k;
+    if (HALF) kmax = max(k, __shfl_xor(k, 32));
+    TO v[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) v[j] = (r + j < k) ? blk[diag_start(k, j) + r] : TO(0);
+    __syncthreads();
+    // t_n = sum of c_p a_p over the ports at n, in port order
+    if (r < k) {
+        TV acc = TV(0);
+        for (int i = f0; i < f1; ++i) {
+            acc += ca[hb + i];
+            pnode[hb + i] = r;
+        }
+        tv[hb + r] = acc;
+    }
+    __syncthreads();
+    // z_r = sum_d S(r, r + d) t_{r+d} + sum_{d>0} S(r - d, r) t_{r-d}
+    TV acc = TV(0);
+    for (int d0 = 0; d0 < kmax; d0 += CH) {
+        TO nv[CH];
+        const bool more = d0 + CH < kmax;
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int d = d0 + CH + j;
+            nv[j] = (more && r + d < k) ? blk[diag_start(k, d) + r] : TO(0);
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int d = d0 + j;
+            const TO up = __shfl(v[j], tid - d);  // lane r - d's entry of diagonal d
+            if (r + d < k) acc += TV(v[j]) * tv[hb + r + d];
+            if (d > 0 && r >= d && r < k) acc += TV(up) * tv[hb + r - d];
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j) v[j] = nv[j];
+    }
+    if (r < k) zv[hb + r] = acc;
+    __syncthreads();
+    if (has_port) a_next[tw] = TV(2) * w * c * zv[hb + pnode[hb + r]] + (TV(1) - TV(2) * c) * a + hp;
+}
+
+}  // namespace
+
+template <typename TO>
+hipError_t launch_port_node_matrix(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* pn_off,
+                                   const int32_t* pn_node, const TO* K, const int64_t* sofs, TO* Sp,
+                                   hipStream_t st) {
+    hipLaunchKernelGGL(k_port_node_matrix<TO>, dim3(S), dim3(256), 0, st, sub_off, kofs, pn_off, pn_node, K, sofs,
+                       Sp);
+    return hipGetLastError();
+}
+
+template <typename TO, typename TV>
+hipError_t launch_sweep_pps(int S, int max_npn, int max_ports, const TO* Sp, const int64_t* sofs,
+                            const int32_t* pn_off, const int32_t* pn_pfirst, const int32_t* port_off,
+                            const int32_t* port_twin, const TV* pc, const TV* pW, TV W, const TV* h,
+                            const TV* a_cur, TV* a_next, hipStream_t st) {
+    if (max_npn > 64 || max_ports > 64) return hipErrorInvalidValue;
+    if (S == 0) return hipSuccess;
+    if (max_npn <= 32 && max_ports <= 32)
+        hipLaunchKernelGGL((k_sweep_pps<TO, TV, true>), dim3((S + 1) / 2), dim3(64), 0, st, S, Sp, sofs, pn_off,
+                           pn_pfirst, port_off, port_twin, pc, pW, W, h, a_cur, a_next);
+    else
+        hipLaunchKernelGGL((k_sweep_pps<TO, TV, false>), dim3(S), dim3(64), 0, st, S, Sp, sofs, pn_off, pn_pfirst,
+                           port_off, port_twin, pc, pW, W, h, a_cur, a_next);
+    return hipGetLastError();
+}
+
+template hipError_t launch_port_node_matrix<double>(int, const int32_t*, const int64_t*, const int32_t*,
+                                                    const int32_t*, const double*, const int64_t*, double*,
+                                                    hipStream_t);
+template hipError_t launch_port_node_matrix<float>(int, const int32_t*, const int64_t*, const int32_t*,
+                                                   const int32_t*, const float*, const int64_t*, float*,
+                                                   hipStream_t);
+template hipError_t launch_sweep_pps<double, double>(int, int, int, const double*, const int64_t*,
+                                                     const int32_t*, const int32_t*, const int32_t*, const int32_t*,
+                                                     const double*, const double*, double, const double*,
+                                                     const double*, double*, hipStream_t);
+template hipError_t launch_sweep_pps<float, float>(int, int, int, const float*, const int64_t*, const int32_t*,
+                                                   const int32_t*, const int32_t*, const int32_t*, const float*,
+                                                   const float*, float, const float*, const float*, float*,
+                                                   hipStream_t);
+
+}  // namespace vtm

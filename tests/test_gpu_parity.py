@@ -103,21 +103,26 @@ def test_port_to_port_iterates_match_oracle(torch, cfg, kw, prec):
     ks = [2, 9, 40]
     ref = oracle_iterates(w, ks)
     for k in ks:
-        assert_close(gpu_iterate(torch, w, k, check_every=k, local_form="port"), ref[k])
+        for form in ("port", "port_dense"):
+            assert_close(gpu_iterate(torch, w, k, check_every=k, local_form=form), ref[k])
 
 
 def test_port_to_port_and_full_forms_agree(torch):
-    """The two local forms reach the tolerance after the same sweeps and agree."""
+    """The local forms (full inverse, packed symmetric port-node operator, dense
+    port operator) reach the tolerance after the same sweeps and agree."""
     w = workloads.make(2, dims=(256, 256))
     xs = []
-    for form in ("full", "port"):
+    for form in ("full", "port", "port_dense"):
         s = vtm().Solver(w.A, w.part, w.Z, check_every=8, adaptive_checks=False, local_form=form, timing=True)
         x, rep = s.solve(to_dev(torch, w.b), w.tol)
-        xs.append((x.cpu().numpy(), rep))
-    (xf, rf), (xp, rp) = xs
-    assert rf.sweeps == rp.sweeps
-    assert rp.pp_launches > 0 and rf.pp_launches == 0
+        xs.append((x.cpu().numpy(), rep, s.port_operator_bytes))
+    (xf, rf, bf), (xp, rp, bp), (xd, rd, bd) = xs
+    assert rf.sweeps == rp.sweeps == rd.sweeps
+    assert rp.pp_launches > 0 and rd.pp_launches > 0 and rf.pp_launches == 0
+    # 8 x 8 blocks: 28 port nodes (406 packed entries) against 32 ports (1024)
+    assert bf == 0 and bp < bd / 2
     assert_close(xp, xf)
+    assert_close(xd, xf)
 
 
 def test_config1_sweeps_and_solution(torch):

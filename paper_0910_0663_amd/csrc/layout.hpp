@@ -46,6 +46,19 @@ __host__ __device__ inline void inv_rc(int n, int64_t d, int& r, int& c) {
     }
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2): block
+// b of a grid of n runs on XCD b % 8.  xcd_block renumbers them so that each XCD
+// takes one contiguous range of logical blocks, and sub-circuits that exchange
+// waves (neighbours in the block order) share an L2.  A bijection on [0, n).
+#ifndef VTM_XCD
+#define VTM_XCD 1
+#endif
+__device__ inline int xcd_block(int b, int n) {
+    if (!VTM_XCD) return b;
+    const int x = b & 7, q = n >> 3, r = n & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // elements reserved for an n x n block (rounded up to a multiple of 4)
 __host__ __device__ inline int64_t inv_block_elems(int n) { return (int64_t(n) * n + 3) & ~int64_t(3); }
 

@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(256)
     constexpr int G = Group<TO>::G;
     extern __shared__ char smem[];
     TV* av = reinterpret_cast<TV*>(smem);
-    const int s = blockIdx.x;
+    const int s = xcd_block(blockIdx.x, gridDim.x);
     const int p0 = port_off[s], q = port_off[s + 1] - p0;
     const int lane = threadIdx.x;
     const TO* Ms = M + pofs[s];
@@ -190,6 +190,22 @@ template hipError_t launch_sweep_pp<float, float>(int, int, const float*, const 
 // d k - d (d - 1) / 2, so lane r reads entry r of every diagonal with
 // coalesced loads and receives S(r - d, r) from lane r - d.
 // ---------------------------------------------------------------------------
+// diagonals each lane holds in flight in the packed sweep (two sub-circuits
+// per wavefront / one)
+#ifndef VTM_PPS_CH_HALF
+#define VTM_PPS_CH_HALF 8
+#endif
+#ifndef VTM_PPS_CH
+#define VTM_PPS_CH 8
+#endif
+// chunks issued before the first barrier (the rest stream that far ahead)
+#ifndef VTM_PPS_PRE_HALF
+#define VTM_PPS_PRE_HALF 1
+#endif
+#ifndef VTM_PPS_PRE
+#define VTM_PPS_PRE 1
+#endif
+
 namespace vtm {
 namespace {
 
@@ -212,32 +228,38 @@ __global__ void __launch_bounds__(256)
 }
 
 // One wavefront per sub-circuit (HALF: two, 32 lanes each).  Lane r owns port
-// node r and port r of its sub-circuit; every global load of the sweep is
-// issued before the first barrier, and the diagonals stream CH at a time with
-// the next CH in flight.
+// node r and port r of its sub-circuit.  The offsets come from scalar loads of
+// a wave-uniform base; every other global load of the sweep is issued before
+// the first barrier, PRE chunks of CH diagonals among them, and the rest
+// stream PRE chunks ahead of use.  The diagonal loop has no branches: a lane
+// past the end of a diagonal loads a valid entry (the block's first) and
+// multiplies it by a zero of the padded t (each sub-circuit's t takes a
+// 64-entry region, zero beyond its k port nodes), so the compiler can keep
+// loads in flight across it.
 template <typename TO, typename TV, bool HALF>
-__global__ void __launch_bounds__(64)
-    k_sweep_pps(int S, const TO* __restrict__ Sp, const int64_t* __restrict__ sofs,
-                const int32_t* __restrict__ pn_off, const int32_t* __restrict__ pn_pfirst,
-                const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_twin,
-                const TV* __restrict__ pc, const TV* __restrict__ pW, TV W, const TV* __restrict__ h,
-                const TV* __restrict__ a_cur, TV* __restrict__ a_next) {
+__device__ inline void pps_unit(int unit, int S, const TO* __restrict__ Sp, const int64_t* __restrict__ sofs,
+                                const int32_t* __restrict__ pn_off, const int32_t* __restrict__ pn_pfirst,
+                                const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_twin,
+                                const TV* __restrict__ pc, const TV* __restrict__ pW, TV W,
+                                const TV* __restrict__ h, const TV* __restrict__ a_cur, TV* __restrict__ a_next,
+                                TV* ca, TV* tv, TV* zv, int32_t* pnode) {
     constexpr int L = HALF ? 32 : 64;
-    constexpr int CH = 8;
-    __shared__ TV ca[64], tv[64], zv[64];
-    __shared__ int32_t pnode[64];
-    const int tid = threadIdx.x, r = tid % L, hb = tid - r;
-    const int s = blockIdx.x * (64 / L) + tid / L;
-    int k = 0, q = 0, n0 = 0, p0 = 0;
-    int64_t e0 = 0;
-    if (s < S) {
-        n0 = pn_off[s];
-        k = pn_off[s + 1] - n0;
-        p0 = port_off[s];
-        q = port_off[s + 1] - p0;
-        e0 = sofs[s];
-    }
-    const TO* blk = Sp + e0;
+    constexpr int CH = HALF ? VTM_PPS_CH_HALF : VTM_PPS_CH;
+    constexpr int NCH = L / CH;
+    constexpr int PRE = HALF ? VTM_PPS_PRE_HALF : VTM_PPS_PRE;
+    static_assert(L % CH == 0 && PRE >= 1 && PRE <= NCH, "diagonal chunks must tile the lanes");
+    const int tid = threadIdx.x, r = tid % L, hb = tid - r, half = tid / L;
+    const int tb = half * 64;  // this sub-circuit's t region
+    // wave-uniform offsets of the (one or two) sub-circuits, indices clamped to S
+    const int sb = unit * (64 / L);
+    const int sa = min(sb, S), sm = min(sb + 1, S), sz = min(sb + 2, S);
+    const int nA = pn_off[sa], nB = pn_off[sm], nC = HALF ? pn_off[sz] : 0;
+    const int pA = port_off[sa], pB = port_off[sm], pC = HALF ? port_off[sz] : 0;
+    const int64_t eA = sofs[sa], eB = HALF ? sofs[sm] : 0;
+    const bool valid = sb + half < S;
+    const int n0 = half ? nB : nA, k = valid ? (half ? nC - nB : nB - nA) : 0;
+    const int p0 = half ? pB : pA, q = valid ? (half ? pC - pB : pB - pA) : 0;
+    const TO* blk = Sp + (valid ? (half ? eB : eA) : 0);
     const bool has_port = r < q;
     TV c = TV(0), a = TV(0), hp = TV(0), w = W;
     int tw = 0;
@@ -257,9 +279,18 @@ __global__ void __launch_bounds__(64)
     }
     int kmax = k;
     if (HALF) kmax = max(k, __shfl_xor(k, 32));
-    TO v[CH];
+    TO buf[L];  // diagonal d of this lane's row (compile-time indices only)
+    auto load = [&](int ci) {
 #pragma unroll
-    for (int j = 0; j < CH; ++j) v[j] = (r + j < k) ? blk[diag_start(k, j) + r] : TO(0);
+        for (int j = 0; j < CH; ++j) {
+            const int d = ci * CH + j;
+            buf[d] = blk[(r + d < k) ? diag_start(k, d) + r : 0];
+        }
+    };
+#pragma unroll
+    for (int ci = 0; ci < PRE; ++ci) load(ci);
+    tv[tid] = TV(0);
+    tv[tid + 64] = TV(0);
     __syncthreads();
     // t_n = sum of c_p a_p over the ports at n, in port order
     if (r < k) {
@@ -268,32 +299,44 @@ __global__ void __launch_bounds__(64)
             acc += ca[hb + i];
             pnode[hb + i] = r;
         }
-        tv[hb + r] = acc;
+        tv[tb + r] = acc;
     }
     __syncthreads();
-    // z_r = sum_d S(r, r + d) t_{r+d} + sum_{d>0} S(r - d, r) t_{r-d}
+    // z_r = sum_d S(r, r + d) t_{r+d} + sum_{d>0} S(r - d, r) t_{r-d}; the second
+    // product is formed by lane r - d (which holds S(r - d, r)) and shuffled up.
+    // d < L keeps tb + r + d inside tv.
+    const TV tr = tv[tb + r];
     TV acc = TV(0);
-    for (int d0 = 0; d0 < kmax; d0 += CH) {
-        TO nv[CH];
-        const bool more = d0 + CH < kmax;
+#pragma unroll
+    for (int ci = 0; ci < NCH; ++ci) {
+        if (ci * CH >= kmax) break;
+        if (ci + PRE < NCH) load(ci + PRE);
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
-            const int d = d0 + CH + j;
-            nv[j] = (more && r + d < k) ? blk[diag_start(k, d) + r] : TO(0);
+            const int d = ci * CH + j;
+            const TV sv = TV(buf[d]);
+            acc += sv * tv[tb + r + d];
+            const TV up = __shfl(sv * tr, tid - d);
+            acc += (d > 0 && r >= d) ? up : TV(0);
         }
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            const int d = d0 + j;
-            const TO up = __shfl(v[j], tid - d);  // lane r - d's entry of diagonal d
-            if (r + d < k) acc += TV(v[j]) * tv[hb + r + d];
-            if (d > 0 && r >= d && r < k) acc += TV(up) * tv[hb + r - d];
-        }
-#pragma unroll
-        for (int j = 0; j < CH; ++j) v[j] = nv[j];
     }
     if (r < k) zv[hb + r] = acc;
     __syncthreads();
     if (has_port) a_next[tw] = TV(2) * w * c * zv[hb + pnode[hb + r]] + (TV(1) - TV(2) * c) * a + hp;
+}
+
+// One workgroup (one wavefront) per unit: a pair of sub-circuits when HALF.
+template <typename TO, typename TV, bool HALF>
+__global__ void __launch_bounds__(64)
+    k_sweep_pps(int S, const TO* __restrict__ Sp, const int64_t* __restrict__ sofs,
+                const int32_t* __restrict__ pn_off, const int32_t* __restrict__ pn_pfirst,
+                const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_twin,
+                const TV* __restrict__ pc, const TV* __restrict__ pW, TV W, const TV* __restrict__ h,
+                const TV* __restrict__ a_cur, TV* __restrict__ a_next) {
+    __shared__ TV ca[64], tv[128], zv[64];
+    __shared__ int32_t pnode[64];
+    pps_unit<TO, TV, HALF>(xcd_block(blockIdx.x, gridDim.x), S, Sp, sofs, pn_off, pn_pfirst, port_off, port_twin,
+                           pc, pW, W, h, a_cur, a_next, ca, tv, zv, pnode);
 }
 
 }  // namespace
@@ -307,6 +350,16 @@ hipError_t launch_port_node_matrix(int S, const int32_t* sub_off, const int64_t*
     return hipGetLastError();
 }
 
+template <typename TO, typename TV, bool HALF>
+hipError_t launch_pps(int S, const TO* Sp, const int64_t* sofs, const int32_t* pn_off, const int32_t* pn_pfirst,
+                      const int32_t* port_off, const int32_t* port_twin, const TV* pc, const TV* pW, TV W,
+                      const TV* h, const TV* a_cur, TV* a_next, hipStream_t st) {
+    const int units = HALF ? (S + 1) / 2 : S;
+    hipLaunchKernelGGL((k_sweep_pps<TO, TV, HALF>), dim3(units), dim3(64), 0, st, S, Sp, sofs, pn_off, pn_pfirst,
+                       port_off, port_twin, pc, pW, W, h, a_cur, a_next);
+    return hipGetLastError();
+}
+
 template <typename TO, typename TV>
 hipError_t launch_sweep_pps(int S, int max_npn, int max_ports, const TO* Sp, const int64_t* sofs,
                             const int32_t* pn_off, const int32_t* pn_pfirst, const int32_t* port_off,
@@ -315,12 +368,10 @@ hipError_t launch_sweep_pps(int S, int max_npn, int max_ports, const TO* Sp, con
     if (max_npn > 64 || max_ports > 64) return hipErrorInvalidValue;
     if (S == 0) return hipSuccess;
     if (max_npn <= 32 && max_ports <= 32)
-        hipLaunchKernelGGL((k_sweep_pps<TO, TV, true>), dim3((S + 1) / 2), dim3(64), 0, st, S, Sp, sofs, pn_off,
-                           pn_pfirst, port_off, port_twin, pc, pW, W, h, a_cur, a_next);
-    else
-        hipLaunchKernelGGL((k_sweep_pps<TO, TV, false>), dim3(S), dim3(64), 0, st, S, Sp, sofs, pn_off, pn_pfirst,
-                           port_off, port_twin, pc, pW, W, h, a_cur, a_next);
-    return hipGetLastError();
+        return launch_pps<TO, TV, true>(S, Sp, sofs, pn_off, pn_pfirst, port_off, port_twin, pc, pW, W, h, a_cur,
+                                        a_next, st);
+    return launch_pps<TO, TV, false>(S, Sp, sofs, pn_off, pn_pfirst, port_off, port_twin, pc, pW, W, h, a_cur,
+                                     a_next, st);
 }
 
 template hipError_t launch_port_node_matrix<double>(int, const int32_t*, const int64_t*, const int32_t*,

@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(kBlock)
     extern __shared__ char smem[];
     TV* rhs = reinterpret_cast<TV*>(smem);   // [max_ns]
     TV* xs = rhs + max_ns;                   // [max_ns]
-    const int s = blockIdx.x;
+    const int s = xcd_block(blockIdx.x, gridDim.x);
     const int off = sub_off[s];
     const int ns = sub_off[s + 1] - off;
     const int p0 = port_off[s], p1 = port_off[s + 1];

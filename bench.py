@@ -117,6 +117,20 @@ def mixed_and_batched(vtm, torch, oracle, workloads):
         "batch_shape_bf16": list(r16.batch_shape), "batch_shape_fp64": list(r64.batch_shape)}
     log(f"cfg4: bf16 {t16:.1f} ms ({r16.sweeps} sweeps, {r16.outer} outer) vs fp64 batched {t64:.1f} ms "
         f"({r64.sweeps} sweeps): x{t64 / t16:.2f}")
+    w = workloads.make(3)
+    t32, r32, x32 = timed_solve(vtm, torch, w, "fp32_refine", 1, reps=2)
+    t64, r64, x64 = timed_solve(vtm, torch, w, "fp64", 1, reps=2)
+    rel32 = float(oracle.relative_residual(w.A, w.b, x32.cpu().numpy()).max())
+    rel64 = float(oracle.relative_residual(w.A, w.b, x64.cpu().numpy()).max())
+    assert rel32 <= w.tol and rel64 <= w.tol, (rel32, rel64)
+    res["fp32_vs_fp64_3d"] = {
+        "workload": f"128^3 7-point grid with {w.vccs[0].size} controlled sources (unsymmetric), "
+                    f"{w.n_sub} sub-circuits of 8^3, 1 RHS, tol 1e-8; dense port-to-port operators",
+        "fp32_refine_ms": round(t32, 2), "fp64_ms": round(t64, 2), "speedup": round(t64 / t32, 3),
+        "fp32_sweeps": r32.sweeps, "fp32_outer": r32.outer, "fp64_sweeps": r64.sweeps,
+        "fp32_relres": rel32, "fp64_relres": rel64}
+    log(f"cfg3: fp32 refine {t32:.1f} ms vs fp64 {t64:.1f} ms: x{t64 / t32:.2f}")
+    del x32, x64
     w = workloads.make(5)
     t32, r32, x32 = timed_solve(vtm, torch, w, "fp32_refine", 1, reps=5)
     t64, r64, x64 = timed_solve(vtm, torch, w, "fp64", 1, reps=5)

@@ -289,6 +289,31 @@ def test_full_size_config2_residual(torch):
     assert abs(rel - rep.relres_max) <= 1e-3 * rel
 
 
+@pytest.mark.parametrize("cfg,centres,R,k,kw", [
+    # the bench workload: corner, edge and interior sub-circuits; one full sweep,
+    # port-to-port sweeps on the packed symmetric operator, one full sweep
+    (2, [0, 128, 256 * 128 + 128, 65535], 8, 9, dict()),
+    # 128^3 with controlled sources (unsymmetric): dense port-to-port operators
+    # between 384 ports of 8^3 sub-circuits; corner, interior and far corner
+    (3, [0, 8 * 256 + 8 * 16 + 8, 4095], 2, 3, dict(precision="fp64")),
+    # 64 right-hand sides on uneven sub-circuits: FP64 inverses as MFMA tiles
+    (4, [0, "mid", -1], 3, 4, dict(nrhs_max=64)),
+])
+def test_full_size_sampled_iterates_match_windowed_oracle(torch, cfg, centres, R, k, kw):
+    """At full size, x^k on sampled sub-circuits equals the oracle's, run on the
+    window of sub-circuits within R >= k - 1 hops of each sample (exact for
+    k <= R + 1: the oracle side is pinned against the whole-problem oracle on
+    smaller grids)."""
+    from oracle_window import window_iterate
+    w = workloads.make(cfg)
+    print(f"{w.name}: n={w.n} subs={w.n_sub} nrhs={w.nrhs} k={k}", flush=True)
+    x = gpu_iterate(torch, w, k, check_every=k, **kw)
+    for c in centres:
+        c = w.n_sub // 2 if c == "mid" else c % w.n_sub
+        nodes = np.nonzero(w.part == c)[0]
+        assert_close(x[:, nodes], window_iterate(w, c, R, k))
+
+
 # ----------------------------------------------------------------------------- batched (MFMA) forms
 def test_batched_fp64_mfma_iterates_match_oracle(torch):
     """FP64 handles sized for 16+ right-hand sides store the inverses as MFMA

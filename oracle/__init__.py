@@ -24,6 +24,7 @@ from .vtm import (  # noqa: F401
     relative_residual,
     eliminate_twins,
     vtm_solve_eliminated,
+    interface_residual,
     direct_solve,
     direct_adjoint,
     branch_gradient,

@@ -440,6 +440,7 @@ class Eliminated:
     beta: np.ndarray
     gamma: np.ndarray
     G: np.ndarray
+    g: np.ndarray          # conductance of the port's cut wire
 
 
 def eliminate_twins(A, part, Z) -> Eliminated:
@@ -465,12 +466,13 @@ def eliminate_twins(A, part, Z) -> Eliminated:
         K.append(Ks)
     rep = lambda v: np.repeat(v, 2)
     return Eliminated(subs=subs, K=K, port_node=port_node, c=rep(c), beta=rep(beta),
-                      gamma=rep(gamma), G=rep(G))
+                      gamma=rep(gamma), G=rep(G), g=rep(g))
 
 
-def vtm_solve_eliminated(el: Eliminated, A, b, n_sweeps):
+def vtm_solve_eliminated(el: Eliminated, A, b, n_sweeps, waves=None):
     """Run ``n_sweeps`` sweeps of the eliminated-twin form from zero waves; returns
-    the iterates x^1..x^n (one column right-hand side)."""
+    the iterates x^1..x^n (one column right-hand side).  A list passed as
+    ``waves`` receives, per sweep, the incident and outgoing wave of every port."""
     b = np.asarray(b, dtype=np.float64).ravel()
     n = b.size
     P = el.port_node.size
@@ -484,9 +486,30 @@ def vtm_solve_eliminated(el: Eliminated, A, b, n_sweeps):
         for nodes, Ks in zip(el.subs, el.K):
             x[nodes] = np.linalg.solve(Ks, rhs[nodes])
         out = el.beta * x[el.port_node] + el.gamma * a
+        if waves is not None:
+            waves.append((a, out))
         a = out[twin]
         xs.append(x)
     return xs
+
+
+def interface_residual(el: Eliminated, n, a, out):
+    """b - A x^k of the eliminated form's iterate, from port quantities alone.
+
+    Each local solve satisfies its sub-circuit's rows of K x = b + sum c a, and
+    K differs from A's diagonal block only by G - g at port nodes, while the
+    only couplings of A across sub-circuits are the cut wires (-g to the far
+    node j).  So row i of b - A x vanishes off the port nodes, and at a port
+    node it is the sum over its ports of (G - g) x_i + g x_j - c a.  The node
+    voltages follow from the waves of the same sweep (out = beta x_i + gamma a):
+    x_i = (out_p - gamma_p a_p) / beta_p, and x_j from the twin port.
+    ``a``/``out``: incident and outgoing waves of every port in that sweep."""
+    twin = np.arange(el.port_node.size) ^ 1
+    xi = (out - el.gamma * a) / el.beta
+    d = (el.G - el.g) * xi + el.g * xi[twin] - el.c * a
+    r = np.zeros(n)
+    np.add.at(r, el.port_node, d)
+    return r
 
 
 # --------------------------------------------------------------------------- #

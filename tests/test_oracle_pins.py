@@ -399,3 +399,23 @@ def test_refinement_reaches_tolerance():
     assert rr.status == "ok" and rr.relres.max() <= 1e-8 and rr.outer >= 2
     xs = oracle.direct_solve(w.A, w.b)
     assert np.abs(rr.x - xs).max() <= 1e-6 * np.abs(xs).max()
+
+
+@pytest.mark.parametrize("cfg,kw", [(1, dict()), (3, dict(dims=(16, 16, 16))), (4, dict(dims=(48, 48)))])
+def test_interface_residual_equals_untorn_residual(cfg, kw):
+    """The residual of a VTM iterate lives on the port nodes: computed from the
+    waves of the sweep alone, it equals b - A x^k on the untorn A (zero off the
+    port nodes), for symmetric and unsymmetric A alike."""
+    w = workloads.make(cfg, **kw)
+    el = oracle.eliminate_twins(w.A, w.part, w.Z)
+    waves = []
+    xs = oracle.vtm_solve_eliminated(el, w.A, w.b[0], 12, waves=waves)
+    ports = np.zeros(w.n, bool)
+    ports[el.port_node] = True
+    for k in (0, 3, 11):
+        r = w.b[0] - w.A @ xs[k]
+        ri = oracle.interface_residual(el, w.n, *waves[k])
+        scale = np.abs(w.b[0]).max()
+        assert np.abs(r[~ports]).max() <= 1e-12 * scale
+        assert np.abs(ri - r).max() <= 1e-11 * scale
+        assert np.abs(ri[ports]).max() > 1e-6 * scale    # not trivially zero

@@ -251,7 +251,8 @@ def main():
             "workload": "2048x2048 5-point resistor grid, log-uniform g in [0.1,10] S, 0.01 S ground, "
                         "65,536 sub-circuits of 8x8 (dense FP64 inverse each), Z = 1/mean(g), "
                         "1 RHS N(0,1), tol 1e-8, FP64; port-to-port sweeps on the packed symmetric "
-                        "port-node operators, a full sweep before every residual check",
+                        "port-node operators; residual checks from port quantities, confirmed on A after "
+                        "one full sweep",
             "port_operator_bytes": s.port_operator_bytes,
             "n": w.n,
             "sub_circuits": s.n_sub,

@@ -92,9 +92,13 @@ typedef struct {
                                the Appendix, eqs. 23-26): a sweep streams only the
                                q x q operator between a sub-circuit's ports,
                                M = diag(beta) K^-1[ports, ports] diag(c) + diag(gamma),
-                               plus h = beta K^-1 b; full sweeps remain for the first
-                               sweep of a solve and the last before each residual
-                               check.  Used for one right-hand side, FP64 or FP32,
+                               plus h = beta K^-1 b; a full sweep remains for the
+                               first sweep of a solve.  Residual checks then use the
+                               port quantities alone (a local solve meets every
+                               interior row, so b - A x lives on the port nodes);
+                               once that residual passes, and at the end, x is
+                               rebuilt by a full sweep from the same waves and the
+                               residual on A decides.  Used for one right-hand side, FP64 or FP32,
                                forward (and adjoint when A is symmetric), not on
                                resume; otherwise the full form runs.  When A is
                                symmetric the operator is stored once per port node

@@ -84,6 +84,8 @@ struct vtm_handle_s {
     // symmetric A: packed port-node operators instead of M
     bool pps = false;
     DevBuf<int32_t> pn_off, pn_node, pn_pfirst;
+    // residual checks from port quantities (port-to-port form): g and G - g per port
+    DevBuf<double> pg64, pgd64;
     DevBuf<int64_t> sofs;
     DevBuf<double> S64, W64p;
     DevBuf<float> S32, W32p;
@@ -158,6 +160,23 @@ vtm_status residual(vtm_handle h, const double* b, const TX* x, int nrhs, double
     vtm_status st = residual_launch<TX>(h, b, x, nrhs, r_out, transpose);
     if (st != VTM_OK) return st;
     return residual_finish(h, nrhs, rel);
+}
+
+// Residual check from port quantities after a sweep that read waves cur and
+// wrote cur ^ 1 (one right-hand side); the sum of squares lands in h_norms[0].
+vtm_status port_residual_launch(vtm_handle h, bool low, int cur) {
+    const vtm::Plan& P = h->plan;
+    const int64_t nn = int64_t(P.pn_pfirst.size()) - 1;
+    if (!low)
+        VTM_HIP(vtm::launch_port_residual<double>(nn, h->pn_pfirst.p, h->port_twin.p, h->a64[cur].p,
+                                                  h->a64[cur ^ 1].p, h->c64.p, h->beta64.p, h->gamma64.p,
+                                                  h->pgd64.p, h->pg64.p, h->partial.p, h->norms.p, h->stream));
+    else
+        VTM_HIP(vtm::launch_port_residual<float>(nn, h->pn_pfirst.p, h->port_twin.p, h->a32[cur].p,
+                                                 h->a32[cur ^ 1].p, h->c64.p, h->beta64.p, h->gamma64.p,
+                                                 h->pgd64.p, h->pg64.p, h->partial.p, h->norms.p, h->stream));
+    VTM_HIP(hipMemcpyAsync(h->h_norms, h->norms.p, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    return VTM_OK;
 }
 
 struct IterOut {
@@ -345,25 +364,36 @@ vtm_status autotune(vtm_handle h) {
 // first: the interval starts the solve from zero waves, so its first sweep is
 // a full one and yields h.  With opt.use_graph the interval is captured once
 // per shape and replayed as one hipGraph launch.
+// `chunk` sweeps from waves `cur`, then a residual check.  pp: the sweeps are
+// port-to-port except the first of a solve (which also forms h) and, unless
+// iface, the last (which rebuilds x for the residual on A).  iface: the check
+// is the residual from port quantities, relative to sqrt(bb).
 vtm_status run_chunk(vtm_handle h, bool low, int nrhs, bool adjoint, int64_t chunk, int cur,
-                     std::vector<double>& rel, bool pp, bool first) {
+                     std::vector<double>& rel, bool pp, bool first, bool iface = false, double bb = 1.0) {
     const void* b = low ? (h->tiles ? static_cast<const void*>(h->b16.p) : static_cast<const void*>(h->b32.p))
                         : static_cast<const void*>(h->bp.p);
     void* x = low ? static_cast<void*>(h->d32.p) : static_cast<void*>(h->xp.p);
     auto enqueue = [&]() -> vtm_status {
         for (int64_t k = 0; k < chunk; ++k) {
-            const bool full = !pp || k + 1 == chunk || (first && k == 0);
+            const bool full = !pp || (k + 1 == chunk && !iface) || (first && k == 0);
             vtm_status st = sweep_once(h, low, nrhs, b, x, (cur + int(k)) & 1, adjoint, k + 1 == chunk, !full);
             if (st != VTM_OK) return st;
             if (pp && first && k == 0 && (st = port_h(h, low)) != VTM_OK) return st;
         }
+        if (iface) return port_residual_launch(h, low, (cur + int(chunk) - 1) & 1);
         return low ? residual_launch<float>(h, h->rp.p, h->d32.p, nrhs, nullptr, adjoint)
                    : residual_launch<double>(h, h->bp.p, h->xp.p, nrhs, nullptr, adjoint);
+    };
+    auto finish = [&]() -> vtm_status {
+        if (!iface) return residual_finish(h, nrhs, rel);
+        VTM_HIP(hipStreamSynchronize(h->stream));
+        rel.assign(1, bb > 0.0 ? std::sqrt(h->h_norms[0] / bb) : std::sqrt(h->h_norms[0]));
+        return VTM_OK;
     };
     if (!h->opt.use_graph) {
         vtm_status st = enqueue();
         if (st != VTM_OK) return st;
-        return residual_finish(h, nrhs, rel);
+        return finish();
     }
     // graphs run on the handle's own non-blocking stream (the caller's may be the
     // legacy null stream, which cannot be captured), after the caller's work
@@ -379,7 +409,8 @@ vtm_status run_chunk(vtm_handle h, bool low, int nrhs, bool adjoint, int64_t chu
         ~Swap() { h->stream = saved; }
     } swap{h, h->stream};
     h->stream = h->gstream;
-    const std::array<int, 6> key{int(low), nrhs, int(adjoint), int(chunk), cur, int(pp) * 2 + int(first)};
+    const std::array<int, 6> key{int(low), nrhs, int(adjoint), int(chunk), cur,
+                                 int(pp) * 4 + int(iface) * 2 + int(first)};
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
         VTM_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
@@ -400,7 +431,7 @@ vtm_status run_chunk(vtm_handle h, bool low, int nrhs, bool adjoint, int64_t chu
         it = h->graphs.emplace(key, ex).first;
     }
     VTM_HIP(hipGraphLaunch(it->second, h->stream));
-    return residual_finish(h, nrhs, rel);
+    return finish();
 }
 
 
@@ -467,10 +498,22 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
     };
     if (done(out.rel)) return VTM_OK;
     if (!resume) cad.record(0, max_of(out.rel));
+    const double bb = h->h_norms[1];  // ||b||^2 (the port-residual checks have one right-hand side)
     const bool pp = h->pp && nrhs == 1 && (!adjoint || P.symmetric) && !resume;
+    // port-to-port sweeps check the residual from port quantities; once it passes
+    // (and at the end), x^k is rebuilt by a full sweep from the same waves and
+    // the residual on A decides
+    const bool iface = pp;
+    auto rebuild = [&]() -> vtm_status {
+        vtm_status s2 = sweep_once(h, false, nrhs, h->bp.p, h->xp.p, cur ^ 1, adjoint, true, false);
+        if (s2 != VTM_OK) return s2;
+        if ((s2 = residual<double>(h, h->bp.p, h->xp.p, nrhs, nullptr, out.rel, adjoint)) != VTM_OK) return s2;
+        ++out.checks;
+        return timing_collect(h, out);
+    };
     while (true) {
         const int64_t chunk = std::min<int64_t>(graph_length(h, cad.next(tol)), h->opt.max_sweeps - out.sweeps);
-        st = run_chunk(h, false, nrhs, adjoint, chunk, cur, out.rel, pp, out.sweeps == 0);
+        st = run_chunk(h, false, nrhs, adjoint, chunk, cur, out.rel, pp, out.sweeps == 0, iface, bb);
         if (st != VTM_OK) return st;
         cur ^= int(chunk & 1);
         out.sweeps += chunk;
@@ -480,11 +523,17 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
         for (double v : out.rel)
             if (!std::isfinite(v) || v > h->opt.divergence) bad = true;
         if (bad) {
+            if (iface && (st = rebuild()) != VTM_OK) return st;
             out.status = VTM_E_DIVERGED;
             break;
         }
-        if (done(out.rel)) break;
+        if (done(out.rel)) {
+            if (!iface) break;
+            if ((st = rebuild()) != VTM_OK) return st;
+            if (done(out.rel)) break;
+        }
         if (out.sweeps >= h->opt.max_sweeps) {
+            if (iface && (st = rebuild()) != VTM_OK) return st;
             out.status = VTM_E_MAXITER;
             break;
         }
@@ -529,6 +578,7 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
         }
         // inner target relative to ||r||: enough for the outer tolerance, at most drop
         for (int r = 0; r < nrhs; ++r) target[r] = rel[r] > 0.0 ? std::max(drop, 0.5 * tol / rel[r]) : 1.0;
+        const double rr = h->h_norms[0];  // ||r||^2 (port-residual inner checks have one right-hand side)
         if (h->tiles)
             VTM_HIP((vtm::launch_convert<double, __bf16>(nv, h->rp.p, h->b16.p, h->stream)));
         else
@@ -549,8 +599,8 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
             // bounds the reachable reduction), so its checks grow to at most 4 m
             const int64_t chunk = std::min<int64_t>(
                 graph_length(h, std::min<int64_t>(cad.next(goal), 4 * cad.m)), h->opt.max_sweeps - inner);
-            // sweeps, then ||r - A d|| / ||r|| in FP64
-            st = run_chunk(h, true, nrhs, adjoint, chunk, cur, e, pp, inner == 0);
+            // sweeps, then ||r - A d|| / ||r|| in FP64 (from port quantities with pp)
+            st = run_chunk(h, true, nrhs, adjoint, chunk, cur, e, pp, inner == 0, pp, rr);
             if (st != VTM_OK) return st;
             cur ^= int(chunk & 1);
             inner += chunk;
@@ -573,6 +623,11 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
             cad.record(inner, max_of(e));
         }
         out.sweeps += inner;
+        if (pp) {  // d from the last sweep's waves, by a full sweep
+            if ((st = sweep_once(h, true, nrhs, h->b32.p, h->d32.p, cur ^ 1, adjoint, true, false)) != VTM_OK)
+                return st;
+            if ((st = timing_collect(h, out)) != VTM_OK) return st;
+        }
         VTM_HIP(vtm::launch_add<float>(nv, h->d32.p, h->xp.p, h->stream));
         ++out.outer;
     }
@@ -804,10 +859,14 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     // port-to-port operators from the stored inverses
     h->pp = o.local_form >= 1 && !h->tiles && P.nports > 0;
     h->pps = h->pp && o.local_form == 1 && P.symmetric && P.max_npn <= 64 && P.max_ports <= 64;
+    if (h->pp) {
+        VTM_HIP(h->pn_pfirst.upload(P.pn_pfirst, s));
+        VTM_HIP(h->pg64.upload(P.pg, s));
+        VTM_HIP(h->pgd64.upload(P.pgd, s));
+    }
     if (h->pps) {
         VTM_HIP(h->pn_off.upload(P.pn_off, s));
         VTM_HIP(h->pn_node.upload(P.pn_node, s));
-        VTM_HIP(h->pn_pfirst.upload(P.pn_pfirst, s));
         VTM_HIP(h->sofs.upload(P.sofs, s));
         std::vector<double> Wp;
         if (!P.uniform_W) {  // line admittance per port (both ports of a wire share it)

@@ -108,6 +108,14 @@ hipError_t launch_sweep_pps(int S, int max_npn, int max_ports, const TO* Sp, con
                             const TV* a_cur, TV* a_next, hipStream_t st);
 
 // ---- residual -------------------------------------------------------------
+// Sum of squares of b - A x for the iterate of the sweep that read a_cur and
+// wrote a_next, from port quantities alone (one right-hand side): norms[0].
+// pn_pfirst[n] .. pn_pfirst[n + 1] are the ports of port node n (n < count).
+// partial must hold 2 * kResidBlocks doubles.
+template <typename TV>
+hipError_t launch_port_residual(int64_t n_port_nodes, const int32_t* pn_pfirst, const int32_t* twin, const TV* a_cur,
+                                const TV* a_next, const double* c, const double* beta, const double* gamma,
+                                const double* gd, const double* g, double* partial, double* norms, hipStream_t st);
 // r = b - A x in FP64 on the untorn (renumbered) A; per right-hand side
 // sums of r^2 and b^2 land in norms[2 * rhs + {0, 1}] (fixed summation order).
 // r_out may be null.  partial must hold kResidBlocks * nrhs * 2 doubles.

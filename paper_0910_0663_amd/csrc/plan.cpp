@@ -225,6 +225,8 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
     P.pc.resize(np);
     P.pbeta.resize(np);
     P.pgamma.resize(np);
+    P.pg.resize(np);
+    P.pgd.resize(np);
     P.dmod.assign(n, 0.0);
     P.max_slot = 0;
     for (int64_t p = 0; p < np; ++p) {
@@ -241,6 +243,8 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
         P.pc[p] = k.c;
         P.pbeta[p] = k.beta;
         P.pgamma[p] = k.gamma;
+        P.pg[p] = P.wg[e];
+        P.pgd[p] = k.G - P.wg[e];
         const int32_t node = (q & 1) ? P.wj[e] : P.wi[e];
         P.dmod[P.iperm[node]] += k.G - P.wg[e];
     }

@@ -50,6 +50,7 @@ struct Plan {
     std::vector<int32_t> port_twin;  // the other port of the same wire
     std::vector<int32_t> abi2port;   // [2 * nwires]: ABI port (2e lower, 2e+1 upper) -> port
     std::vector<double> pc, pbeta, pgamma;  // per port: c, beta, gamma
+    std::vector<double> pg, pgd;            // per port: wire conductance g and G - g
 
     std::vector<double> dmod;      // per new node: sum over its ports of (G - g)
 

@@ -62,7 +62,64 @@ __global__ void __launch_bounds__(kBlock)
     if (tid == 0) norms[j] = s[0];
 }
 
+// b - A x of a sweep's iterate from port quantities alone (a local solve meets
+// every interior row exactly; A couples sub-circuits only through cut wires):
+// per port node n, r_n = sum over its ports p of (G_p - g_p) x_n + g_p x_j(p)
+// - c_p a_p, where x_n = (o_p0 - gamma_p0 a_p0) / beta_p0 from its first port,
+// x_j(p) likewise from the twin port q, and the outgoing wave o_p of port p is
+// a_next[twin(p)].  One right-hand side; partial sums as in k_resid.
+template <typename TV>
+__global__ void __launch_bounds__(kBlock)
+    k_port_resid(int64_t nn, const int32_t* __restrict__ pn_pfirst, const int32_t* __restrict__ twin,
+                 const TV* __restrict__ a_cur, const TV* __restrict__ a_next, const double* __restrict__ c,
+                 const double* __restrict__ beta, const double* __restrict__ gamma, const double* __restrict__ gd,
+                 const double* __restrict__ g, double* __restrict__ partial) {
+    __shared__ double s[kBlock];
+    const int tid = threadIdx.x;
+    double rr = 0.0;
+    for (int64_t n = int64_t(blockIdx.x) * kBlock + tid; n < nn; n += int64_t(gridDim.x) * kBlock) {
+        const int p0 = pn_pfirst[n], p1 = pn_pfirst[n + 1];
+        const double xn = (double(a_next[twin[p0]]) - gamma[p0] * double(a_cur[p0])) / beta[p0];
+        double r = 0.0;
+        for (int p = p0; p < p1; ++p) {
+            const int q = twin[p];
+            const double xj = (double(a_next[p]) - gamma[q] * double(a_cur[q])) / beta[q];
+            r += gd[p] * xn + g[p] * xj - c[p] * double(a_cur[p]);
+        }
+        rr += r * r;
+    }
+    s[tid] = rr;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if (tid < h) s[tid] += s[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        partial[int64_t(blockIdx.x) * 2 + 0] = s[0];
+        partial[int64_t(blockIdx.x) * 2 + 1] = 0.0;
+    }
+}
+
 }  // namespace
+
+template <typename TV>
+hipError_t launch_port_residual(int64_t n_port_nodes, const int32_t* pn_pfirst, const int32_t* twin, const TV* a_cur,
+                                const TV* a_next, const double* c, const double* beta, const double* gamma,
+                                const double* gd, const double* g, double* partial, double* norms, hipStream_t st) {
+    hipLaunchKernelGGL(k_port_resid<TV>, dim3(kResidBlocks), dim3(kBlock), 0, st, n_port_nodes, pn_pfirst, twin,
+                       a_cur, a_next, c, beta, gamma, gd, g, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(kBlock), 0, st, kResidBlocks, 1, partial, norms);
+    return hipGetLastError();
+}
+
+template hipError_t launch_port_residual<double>(int64_t, const int32_t*, const int32_t*, const double*,
+                                                 const double*, const double*, const double*, const double*,
+                                                 const double*, const double*, double*, double*, hipStream_t);
+template hipError_t launch_port_residual<float>(int64_t, const int32_t*, const int32_t*, const float*, const float*,
+                                                const double*, const double*, const double*, const double*,
+                                                const double*, double*, double*, hipStream_t);
 
 template <typename TX>
 hipError_t launch_residual(int n, int nrhs, const int32_t* rowptr, const int32_t* col, const double* val,

@@ -208,8 +208,9 @@ vtm_status vtm_get_waves(vtm_handle h, double *waves, int32_t nrhs);
 vtm_status vtm_set_waves(vtm_handle h, const double *waves, int32_t nrhs);
 
 /* Sizes of a handle: nodes, sub-circuits, cut wires, bytes of the stored
- * inverses and of the port-to-port operators (0 when not built), and the
- * algorithmic bytes one port-to-port sweep moves (operators once; per port the
+ * inverses and of the port-to-port operators as allocated (0 when not built),
+ * and the algorithmic bytes one port-to-port sweep moves (operator entries once,
+ * without layout padding; per port the
  * incident wave, h, c when packed, the outgoing wave and the twin index; per
  * port node and sub-circuit their offsets).  NULLs skipped.  For symmetric A
  * the operator is the packed upper triangle of K^-1 over a sub-circuit's port

@@ -205,8 +205,9 @@ vtm_status timing_event(vtm_handle h, hipEvent_t* out, char tag) {
     return VTM_OK;
 }
 
-// Sums the durations of the recorded event pairs (after a stream sync) and resets them.
+// Sums the durations of the recorded event pairs and resets them (waits for the last).
 vtm_status timing_collect(vtm_handle h, IterOut& out) {
+    if (h->ev_used > 0) VTM_HIP(hipEventSynchronize(h->ev[h->ev_used - 1]));
     for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
         float t = 0.f;
         VTM_HIP(hipEventElapsedTime(&t, h->ev[k], h->ev[k + 1]));
@@ -878,12 +879,14 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
             VTM_HIP(h->S64.alloc(nsp));
             VTM_HIP(h->h64.alloc(P.nports));
             if (!P.uniform_W) VTM_HIP(h->W64p.upload(Wp, s));
+            VTM_HIP(vtm::launch_fill<double>(nsp, double(0), h->S64.p, s));  // pads stay zero
             VTM_HIP(vtm::launch_port_node_matrix<double>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p,
                                                          h->pn_node.p, h->K64.p, h->sofs.p, h->S64.p, s));
         } else {
             VTM_HIP(h->S32.alloc(nsp));
             VTM_HIP(h->h32.alloc(P.nports));
             if (!P.uniform_W) VTM_HIP(h->W32p.upload(to_float(Wp), s));
+            VTM_HIP(vtm::launch_fill<float>(nsp, float(0), h->S32.p, s));  // pads stay zero
             VTM_HIP(vtm::launch_port_node_matrix<float>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p,
                                                         h->pn_node.p, h->K32.p, h->sofs.p, h->S32.p, s));
         }
@@ -971,13 +974,14 @@ vtm_status vtm_info(vtm_handle h, int64_t* n, int64_t* n_sub, int64_t* n_wires, 
     const int64_t op = h->pps ? P.sofs[P.S] * esize : (h->pp ? P.pofs[P.S] * esize : 0);
     if (port_operator_bytes) *port_operator_bytes = op;
     if (port_sweep_bytes) {
-        // operators once; per port the wave in, h in, wave out (and c for the packed form) plus
-        // the twin index; per port node its first port; per sub-circuit its offsets
+        // operator entries once (without layout padding); per port the wave in, h in, wave
+        // out (and c for the packed form) plus the twin index; per port node its first port;
+        // per sub-circuit its offsets
         if (h->pps)
-            *port_sweep_bytes = op + P.nports * (4 * esize + 4 + (P.uniform_W ? 0 : esize)) +
+            *port_sweep_bytes = P.tri_entries * esize + P.nports * (4 * esize + 4 + (P.uniform_W ? 0 : esize)) +
                                 int64_t(P.pn_node.size()) * 4 + P.S * 16;
         else if (h->pp)
-            *port_sweep_bytes = op + P.nports * (3 * esize + 4) + P.S * 12;
+            *port_sweep_bytes = P.sq_entries * esize + P.nports * (3 * esize + 4) + P.S * 12;
         else
             *port_sweep_bytes = 0;
     }

@@ -90,8 +90,8 @@ hipError_t launch_sweep_pp(int S, int max_q, const TO* M, const int64_t* pofs, c
                            const int32_t* port_twin, const TV* h, const TV* a_cur, TV* a_next, hipStream_t st);
 
 // Symmetric A: upper triangle of S = K^-1[port nodes, port nodes] per
-// sub-circuit, stored by diagonals (diagonal d from d k - d (d - 1) / 2, k port
-// nodes), block start 16-byte aligned, at Sp + sofs[s] ...
+// sub-circuit as row-interleaved pairs of diagonals (pair m from 2m (k - m + 1),
+// k port nodes; pads zero), block start 16-byte aligned, at Sp + sofs[s] ...
 template <typename TO>
 hipError_t launch_port_node_matrix(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* pn_off,
                                    const int32_t* pn_node, const TO* K, const int64_t* sofs, TO* Sp,

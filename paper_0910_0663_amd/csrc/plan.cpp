@@ -253,6 +253,7 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
         const int64_t q = P.port_off[s + 1];
         P.max_ports = std::max<int32_t>(P.max_ports, int32_t(q));
         P.pofs[s + 1] = P.pofs[s] + ((q * q + 3) & ~int64_t(3));
+        P.sq_entries += q * q;
         P.port_off[s + 1] += P.port_off[s];
     }
     for (int64_t q = 0; q < np; ++q) P.port_twin[P.abi2port[q]] = P.abi2port[q ^ 1];
@@ -274,7 +275,11 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
         P.pn_off[s + 1] = int32_t(P.pn_node.size());
         const int64_t k = P.pn_off[s + 1] - P.pn_off[s];
         P.max_npn = std::max<int32_t>(P.max_npn, int32_t(k));
-        P.sofs[s + 1] = P.sofs[s] + ((k * (k + 1) / 2 + 3) & ~int64_t(3));
+        // upper triangle stored as pairs of diagonals, row-interleaved (the last row of a
+        // pair pads its second entry): k (k + 2) / 2 entries for even k, (k + 1)^2 / 2 for odd
+        const int64_t pairs = (k % 2 == 0) ? k * (k + 2) / 2 : (k + 1) * (k + 1) / 2;
+        P.tri_entries += k * (k + 1) / 2;
+        P.sofs[s + 1] = P.sofs[s] + ((pairs + 3) & ~int64_t(3));
     }
     P.pn_pfirst.push_back(int32_t(np));
 

@@ -34,6 +34,8 @@ struct Plan {
                                     // node are consecutive; the last entry is nports)
     std::vector<int64_t> sofs;      // [S + 1] element offset of each packed symmetric block
     int32_t max_npn = 0;            // most port nodes on one sub-circuit
+    int64_t tri_entries = 0;        // sum over sub-circuits of k (k + 1) / 2 (packed triangles, no padding)
+    int64_t sq_entries = 0;         // sum over sub-circuits of q^2 (dense port operators, no padding)
     bool uniform_W = true;          // one line admittance for every wire
 
     int32_t max_ports = 0;         // most ports on one sub-circuit

@@ -10,6 +10,8 @@
 #include "kernels.hpp"
 #include "layout.hpp"
 
+#include <type_traits>
+
 namespace vtm {
 
 namespace {
@@ -185,13 +187,15 @@ template hipError_t launch_sweep_pp<float, float>(int, int, const float*, const 
 // outgoing waves are
 //     o_p = 2 W_p c_p z_n(p) + (1 - 2 c_p) a_p + h_p,   z = S t,  t_n = sum_{p at n} c_p a_p,
 // so a sweep streams only the upper triangle of S besides the per-port wave,
-// c, h and twin.  The triangle of a sub-circuit with k port nodes is stored by
-// diagonals: diagonal d (entries S(r, r + d), r = 0 .. k - d - 1) starts at
-// d k - d (d - 1) / 2, so lane r reads entry r of every diagonal with
-// coalesced loads and receives S(r - d, r) from lane r - d.
+// c, h and twin.  The triangle of a sub-circuit with k port nodes is stored as
+// pairs of diagonals: pair m holds, for rows r = 0 .. k - 2m - 1, the two
+// entries S(r, r + 2m) and S(r, r + 2m + 1) side by side (the second is zero
+// in the pair's last row), and starts at 2m (k - m + 1).  Lane r reads both
+// entries of every pair with one coalesced 16-byte (FP64) load and receives
+// S(r - d, r) from lane r - d.
 // ---------------------------------------------------------------------------
 // diagonals each lane holds in flight in the packed sweep (two sub-circuits
-// per wavefront / one)
+// per wavefront / one); even: whole pairs
 #ifndef VTM_PPS_CH_HALF
 #define VTM_PPS_CH_HALF 8
 #endif
@@ -209,7 +213,8 @@ template hipError_t launch_sweep_pp<float, float>(int, int, const float*, const 
 namespace vtm {
 namespace {
 
-__host__ __device__ inline int diag_start(int k, int d) { return d * k - (d * (d - 1)) / 2; }
+// pair m of diagonals (2m, 2m + 1), rows r = 0 .. k - 2m - 1 each holding both entries
+__host__ __device__ inline int pair_start(int k, int m) { return 2 * m * (k - m + 1); }
 
 template <typename TO>
 __global__ void __launch_bounds__(256)
@@ -223,7 +228,9 @@ __global__ void __launch_bounds__(256)
     TO* out = Sp + sofs[s];
     for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
         const int r = t / k, c = t - r * k;
-        if (r <= c) out[diag_start(k, c - r) + r] = Ks[inv_offset<TO>(ns, pn_node[k0 + r], pn_node[k0 + c])];
+        if (r <= c)
+            out[pair_start(k, (c - r) >> 1) + 2 * r + ((c - r) & 1)] =
+                Ks[inv_offset<TO>(ns, pn_node[k0 + r], pn_node[k0 + c])];
     }
 }
 
@@ -231,11 +238,12 @@ __global__ void __launch_bounds__(256)
 // node r and port r of its sub-circuit.  The offsets come from scalar loads of
 // a wave-uniform base; every other global load of the sweep is issued before
 // the first barrier, PRE chunks of CH diagonals among them, and the rest
-// stream PRE chunks ahead of use.  The diagonal loop has no branches: a lane
-// past the end of a diagonal loads a valid entry (the block's first) and
+// stream PRE chunks ahead of use.  Inside a chunk there are no branches: a
+// lane past the end of a pair loads a valid entry (the block's first two) and
 // multiplies it by a zero of the padded t (each sub-circuit's t takes a
 // 64-entry region, zero beyond its k port nodes), so the compiler can keep
-// loads in flight across it.
+// loads in flight across it; the only branch, a wave-uniform exit once the
+// chunks pass the larger k of the wavefront, is scalar.
 template <typename TO, typename TV, bool HALF>
 __device__ inline void pps_unit(int unit, int S, const TO* __restrict__ Sp, const int64_t* __restrict__ sofs,
                                 const int32_t* __restrict__ pn_off, const int32_t* __restrict__ pn_pfirst,
@@ -277,14 +285,17 @@ __device__ inline void pps_unit(int unit, int S, const TO* __restrict__ Sp, cons
         f0 = pn_pfirst[n0 + r] - p0;
         f1 = pn_pfirst[n0 + r + 1] - p0;
     }
-    int kmax = k;
-    if (HALF) kmax = max(k, __shfl_xor(k, 32));
     TO buf[L];  // diagonal d of this lane's row (compile-time indices only)
+    // CH / 2 pairs per chunk, one 16-byte (FP64) load each: S(r, r + 2m), S(r, r + 2m + 1)
+    static_assert(CH % 2 == 0, "chunks hold whole pairs");
+    using V2 = typename std::conditional<sizeof(TO) == 8, double2, float2>::type;
     auto load = [&](int ci) {
 #pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            const int d = ci * CH + j;
-            buf[d] = blk[(r + d < k) ? diag_start(k, d) + r : 0];
+        for (int j = 0; j < CH / 2; ++j) {
+            const int m = ci * (CH / 2) + j;
+            const V2 v2 = *reinterpret_cast<const V2*>(blk + ((r + 2 * m < k) ? pair_start(k, m) + 2 * r : 0));
+            buf[2 * m] = v2.x;
+            buf[2 * m + 1] = v2.y;
         }
     };
 #pragma unroll
@@ -307,6 +318,9 @@ __device__ inline void pps_unit(int unit, int S, const TO* __restrict__ Sp, cons
     // d < L keeps tb + r + d inside tv.
     const TV tr = tv[tb + r];
     TV acc = TV(0);
+    int kmax = k;
+    if (HALF) kmax = max(k, __shfl_xor(k, 32));
+    kmax = __builtin_amdgcn_readfirstlane(kmax);  // wave-uniform: the chunk loop branches on scalars
 #pragma unroll
     for (int ci = 0; ci < NCH; ++ci) {
         if (ci * CH >= kmax) break;

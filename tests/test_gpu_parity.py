@@ -254,6 +254,20 @@ def test_fp32_refinement_reaches_fp64_tolerance(torch, cfg, dims):
     assert np.abs(xh - xs).max() <= 2e-6 * np.abs(xs).max()
 
 
+@pytest.mark.parametrize("form", ["port", "port_dense", "full"])
+def test_fp32_refinement_with_timing_in_every_local_form(torch, form):
+    """Timed FP32 refinement (per-launch events on every sweep, including the
+    full sweep that rebuilds each correction) reaches the FP64 tolerance in
+    every local form and reports its port-to-port launches."""
+    w = workloads.make(5, dims=(128, 128))
+    s = vtm().Solver(w.A, w.part, w.Z, precision="fp32_refine", local_form=form, timing=True)
+    x, rep = s.solve(to_dev(torch, w.b), w.tol)
+    assert oracle.relative_residual(w.A, w.b, x.cpu().numpy()).max() <= w.tol
+    assert rep.outer >= 1 and rep.sweep_launches >= 1
+    assert (rep.pp_launches > 0) == (form != "full")
+    s.close()
+
+
 def test_gradient_through_autograd_matches_oracle(torch):
     """dL/db and dL/dg for L = sum over probes of x^2 through VTMSolve, against the
     oracle's adjoint formula with direct solves."""

@@ -86,6 +86,11 @@ struct vtm_handle_s {
     DevBuf<int32_t> pn_off, pn_node, pn_pfirst;
     // residual checks from port quantities (port-to-port form): g and G - g per port
     DevBuf<double> pg64, pgd64;
+    // batched port-to-port form (MFMA tiles): q x q operators in A-tile order
+    bool ppb = false;
+    DevBuf<int64_t> qmofs;
+    DevBuf<__bf16> Mbt;
+    DevBuf<double> M64t;
     DevBuf<int64_t> sofs;
     DevBuf<double> S64, W64p;
     DevBuf<float> S32, W32p;
@@ -163,19 +168,19 @@ vtm_status residual(vtm_handle h, const double* b, const TX* x, int nrhs, double
 }
 
 // Residual check from port quantities after a sweep that read waves cur and
-// wrote cur ^ 1 (one right-hand side); the sum of squares lands in h_norms[0].
-vtm_status port_residual_launch(vtm_handle h, bool low, int cur) {
+// wrote cur ^ 1; per right-hand side r the sum of squares lands in h_norms[2 r].
+vtm_status port_residual_launch(vtm_handle h, bool low, int cur, int nrhs) {
     const vtm::Plan& P = h->plan;
     const int64_t nn = int64_t(P.pn_pfirst.size()) - 1;
     if (!low)
-        VTM_HIP(vtm::launch_port_residual<double>(nn, h->pn_pfirst.p, h->port_twin.p, h->a64[cur].p,
+        VTM_HIP(vtm::launch_port_residual<double>(nn, nrhs, h->pn_pfirst.p, h->port_twin.p, h->a64[cur].p,
                                                   h->a64[cur ^ 1].p, h->c64.p, h->beta64.p, h->gamma64.p,
                                                   h->pgd64.p, h->pg64.p, h->partial.p, h->norms.p, h->stream));
     else
-        VTM_HIP(vtm::launch_port_residual<float>(nn, h->pn_pfirst.p, h->port_twin.p, h->a32[cur].p,
+        VTM_HIP(vtm::launch_port_residual<float>(nn, nrhs, h->pn_pfirst.p, h->port_twin.p, h->a32[cur].p,
                                                  h->a32[cur ^ 1].p, h->c64.p, h->beta64.p, h->gamma64.p,
                                                  h->pgd64.p, h->pg64.p, h->partial.p, h->norms.p, h->stream));
-    VTM_HIP(hipMemcpyAsync(h->h_norms, h->norms.p, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    VTM_HIP(hipMemcpyAsync(h->h_norms, h->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, h->stream));
     return VTM_OK;
 }
 
@@ -265,7 +270,19 @@ vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
     vtm_status st;
     const bool timed = h->opt.timing && !h->capturing;
     if (timed && (st = timing_event(h, &e0, pp ? 1 : 0)) != VTM_OK) return st;
-    if (pp && h->pps) {
+    if (pp && h->tiles) {
+        const vtm::Plan& P = h->plan;
+        if (!low)
+            VTM_HIP(vtm::launch_sweep_mfma_pp<double>(int(P.S), P.max_ports, nrhs, h->mfma_variant, h->mfma_rc,
+                                                      h->lds_limit, h->M64t.p, h->qmofs.p, h->port_off.p,
+                                                      h->port_twin.p, h->h64.p, h->a64[cur].p, h->a64[cur ^ 1].p,
+                                                      h->stream));
+        else
+            VTM_HIP(vtm::launch_sweep_mfma_pp<__bf16>(int(P.S), P.max_ports, nrhs, h->mfma_variant, h->mfma_rc,
+                                                      h->lds_limit, h->Mbt.p, h->qmofs.p, h->port_off.p,
+                                                      h->port_twin.p, h->h32.p, h->a32[cur].p, h->a32[cur ^ 1].p,
+                                                      h->stream));
+    } else if (pp && h->pps) {
         const vtm::Plan& P = h->plan;
         const double W = P.nwires ? P.wW[0] : 0.0;
         if (!low)
@@ -296,13 +313,13 @@ vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
 }
 
 // h_p = beta_p x_i(p) from the x just computed (x = K^-1 b: the first sweep from zero waves)
-vtm_status port_h(vtm_handle h, bool low) {
+vtm_status port_h(vtm_handle h, bool low, int nrhs) {
     const vtm::Plan& P = h->plan;
     if (!low)
-        VTM_HIP(vtm::launch_port_h<double>(int(P.S), h->sub_off.p, h->port_off.p, h->port_node.p, h->beta64.p,
+        VTM_HIP(vtm::launch_port_h<double>(int(P.S), nrhs, h->sub_off.p, h->port_off.p, h->port_node.p, h->beta64.p,
                                            h->xp.p, h->h64.p, h->stream));
     else
-        VTM_HIP(vtm::launch_port_h<float>(int(P.S), h->sub_off.p, h->port_off.p, h->port_node.p, h->beta32.p,
+        VTM_HIP(vtm::launch_port_h<float>(int(P.S), nrhs, h->sub_off.p, h->port_off.p, h->port_node.p, h->beta32.p,
                                           h->d32.p, h->h32.p, h->stream));
     return VTM_OK;
 }
@@ -370,7 +387,8 @@ vtm_status autotune(vtm_handle h) {
 // iface, the last (which rebuilds x for the residual on A).  iface: the check
 // is the residual from port quantities, relative to sqrt(bb).
 vtm_status run_chunk(vtm_handle h, bool low, int nrhs, bool adjoint, int64_t chunk, int cur,
-                     std::vector<double>& rel, bool pp, bool first, bool iface = false, double bb = 1.0) {
+                     std::vector<double>& rel, bool pp, bool first, bool iface = false,
+                     const std::vector<double>* bb = nullptr) {
     const void* b = low ? (h->tiles ? static_cast<const void*>(h->b16.p) : static_cast<const void*>(h->b32.p))
                         : static_cast<const void*>(h->bp.p);
     void* x = low ? static_cast<void*>(h->d32.p) : static_cast<void*>(h->xp.p);
@@ -379,16 +397,20 @@ vtm_status run_chunk(vtm_handle h, bool low, int nrhs, bool adjoint, int64_t chu
             const bool full = !pp || (k + 1 == chunk && !iface) || (first && k == 0);
             vtm_status st = sweep_once(h, low, nrhs, b, x, (cur + int(k)) & 1, adjoint, k + 1 == chunk, !full);
             if (st != VTM_OK) return st;
-            if (pp && first && k == 0 && (st = port_h(h, low)) != VTM_OK) return st;
+            if (pp && first && k == 0 && (st = port_h(h, low, nrhs)) != VTM_OK) return st;
         }
-        if (iface) return port_residual_launch(h, low, (cur + int(chunk) - 1) & 1);
+        if (iface) return port_residual_launch(h, low, (cur + int(chunk) - 1) & 1, nrhs);
         return low ? residual_launch<float>(h, h->rp.p, h->d32.p, nrhs, nullptr, adjoint)
                    : residual_launch<double>(h, h->bp.p, h->xp.p, nrhs, nullptr, adjoint);
     };
     auto finish = [&]() -> vtm_status {
         if (!iface) return residual_finish(h, nrhs, rel);
         VTM_HIP(hipStreamSynchronize(h->stream));
-        rel.assign(1, bb > 0.0 ? std::sqrt(h->h_norms[0] / bb) : std::sqrt(h->h_norms[0]));
+        rel.resize(nrhs);
+        for (int r = 0; r < nrhs; ++r) {
+            const double d = bb ? (*bb)[r] : 1.0, rr = h->h_norms[2 * r];
+            rel[r] = d > 0.0 ? std::sqrt(rr / d) : std::sqrt(rr);
+        }
         return VTM_OK;
     };
     if (!h->opt.use_graph) {
@@ -499,8 +521,9 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
     };
     if (done(out.rel)) return VTM_OK;
     if (!resume) cad.record(0, max_of(out.rel));
-    const double bb = h->h_norms[1];  // ||b||^2 (the port-residual checks have one right-hand side)
-    const bool pp = h->pp && nrhs == 1 && (!adjoint || P.symmetric) && !resume;
+    std::vector<double> bb(nrhs);  // ||b||^2 per right-hand side, for the port-residual checks
+    for (int r = 0; r < nrhs; ++r) bb[r] = h->h_norms[2 * r + 1];
+    const bool pp = ((h->pp && nrhs == 1) || h->ppb) && (!adjoint || P.symmetric) && !resume;
     // port-to-port sweeps check the residual from port quantities; once it passes
     // (and at the end), x^k is rebuilt by a full sweep from the same waves and
     // the residual on A decides
@@ -514,7 +537,7 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
     };
     while (true) {
         const int64_t chunk = std::min<int64_t>(graph_length(h, cad.next(tol)), h->opt.max_sweeps - out.sweeps);
-        st = run_chunk(h, false, nrhs, adjoint, chunk, cur, out.rel, pp, out.sweeps == 0, iface, bb);
+        st = run_chunk(h, false, nrhs, adjoint, chunk, cur, out.rel, pp, out.sweeps == 0, iface, &bb);
         if (st != VTM_OK) return st;
         cur ^= int(chunk & 1);
         out.sweeps += chunk;
@@ -555,7 +578,7 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
     if (!(drop > 0.0)) drop = h->opt.precision == VTM_BF16_REFINE ? 1e-2 : 1e-5;
     VTM_HIP(vtm::launch_fill<double>(nv, 0.0, h->xp.p, h->stream));
     std::vector<double> rel, e, target(nrhs);
-    const bool pp = h->pp && nrhs == 1 && (!adjoint || P.symmetric);
+    const bool pp = ((h->pp && nrhs == 1) || h->ppb) && (!adjoint || P.symmetric);
     auto all_le = [](const std::vector<double>& v, const std::vector<double>& t) {
         for (size_t i = 0; i < v.size(); ++i)
             if (!(v[i] <= t[i])) return false;
@@ -579,7 +602,8 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
         }
         // inner target relative to ||r||: enough for the outer tolerance, at most drop
         for (int r = 0; r < nrhs; ++r) target[r] = rel[r] > 0.0 ? std::max(drop, 0.5 * tol / rel[r]) : 1.0;
-        const double rr = h->h_norms[0];  // ||r||^2 (port-residual inner checks have one right-hand side)
+        std::vector<double> rr(nrhs);  // ||r||^2 per right-hand side, for the port-residual inner checks
+        for (int r = 0; r < nrhs; ++r) rr[r] = h->h_norms[2 * r];
         if (h->tiles)
             VTM_HIP((vtm::launch_convert<double, __bf16>(nv, h->rp.p, h->b16.p, h->stream)));
         else
@@ -601,7 +625,7 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
             const int64_t chunk = std::min<int64_t>(
                 graph_length(h, std::min<int64_t>(cad.next(goal), 4 * cad.m)), h->opt.max_sweeps - inner);
             // sweeps, then ||r - A d|| / ||r|| in FP64 (from port quantities with pp)
-            st = run_chunk(h, true, nrhs, adjoint, chunk, cur, e, pp, inner == 0, pp, rr);
+            st = run_chunk(h, true, nrhs, adjoint, chunk, cur, e, pp, inner == 0, pp, &rr);
             if (st != VTM_OK) return st;
             cur ^= int(chunk & 1);
             inner += chunk;
@@ -625,7 +649,8 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
         }
         out.sweeps += inner;
         if (pp) {  // d from the last sweep's waves, by a full sweep
-            if ((st = sweep_once(h, true, nrhs, h->b32.p, h->d32.p, cur ^ 1, adjoint, true, false)) != VTM_OK)
+            const void* bl = h->tiles ? static_cast<const void*>(h->b16.p) : static_cast<const void*>(h->b32.p);
+            if ((st = sweep_once(h, true, nrhs, bl, h->d32.p, cur ^ 1, adjoint, true, false)) != VTM_OK)
                 return st;
             if ((st = timing_collect(h, out)) != VTM_OK) return st;
         }
@@ -860,7 +885,30 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     // port-to-port operators from the stored inverses
     h->pp = o.local_form >= 1 && !h->tiles && P.nports > 0;
     h->pps = h->pp && o.local_form == 1 && P.symmetric && P.max_npn <= 64 && P.max_ports <= 64;
-    if (h->pp) {
+    // batched form: port-to-port operators in tile order, built from the FP64 inverses in scratch
+    const int qpad = vtm::tile_pad(P.max_ports);
+    h->ppb = o.local_form >= 1 && h->tiles && P.nports > 0 &&
+             (o.precision == VTM_FP64 ? vtm::tile_lds_bytes<double>(qpad, 16)
+                                      : vtm::tile_lds_bytes<__bf16>(qpad, 16)) <= h->lds_limit;
+    if (h->ppb) {
+        VTM_HIP(h->qmofs.upload(P.qmofs, s));
+        const int64_t nq = P.qmofs[P.S];
+        if (o.precision == VTM_FP64) {
+            VTM_HIP(h->M64t.alloc(nq));
+            VTM_HIP(h->h64.alloc(P.nports * nr));
+            VTM_HIP(vtm::launch_port_matrix_tiles<double>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p,
+                                                          h->port_node.p, h->c64.p, h->beta64.p, h->gamma64.p,
+                                                          scratch.p, h->qmofs.p, h->M64t.p, s));
+        } else {
+            VTM_HIP(h->Mbt.alloc(nq));
+            VTM_HIP(h->h32.alloc(P.nports * nr));
+            VTM_HIP(vtm::launch_port_matrix_tiles<__bf16>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p,
+                                                          h->port_node.p, h->c64.p, h->beta64.p, h->gamma64.p,
+                                                          scratch.p, h->qmofs.p, h->Mbt.p, s));
+        }
+        VTM_HIP(hipStreamSynchronize(s));
+    }
+    if (h->pp || h->ppb) {
         VTM_HIP(h->pn_pfirst.upload(P.pn_pfirst, s));
         VTM_HIP(h->pg64.upload(P.pg, s));
         VTM_HIP(h->pgd64.upload(P.pgd, s));
@@ -971,13 +1019,17 @@ vtm_status vtm_info(vtm_handle h, int64_t* n, int64_t* n_sub, int64_t* n_wires, 
     if (n_sub) *n_sub = P.S;
     if (n_wires) *n_wires = P.nwires;
     if (inverse_bytes) *inverse_bytes = (h->tiles ? P.mofs[P.S] : P.kofs[P.S]) * esize;
-    const int64_t op = h->pps ? P.sofs[P.S] * esize : (h->pp ? P.pofs[P.S] * esize : 0);
+    const int64_t op = h->ppb ? P.qmofs[P.S] * esize
+                              : (h->pps ? P.sofs[P.S] * esize : (h->pp ? P.pofs[P.S] * esize : 0));
     if (port_operator_bytes) *port_operator_bytes = op;
     if (port_sweep_bytes) {
         // operator entries once (without layout padding); per port the wave in, h in, wave
         // out (and c for the packed form) plus the twin index; per port node its first port;
         // per sub-circuit its offsets
-        if (h->pps)
+        const int64_t tv = h->opt.precision == VTM_FP64 ? 8 : 4;  // waves (FP32 for the BF16 form)
+        if (h->ppb)
+            *port_sweep_bytes = P.sq_entries * esize + P.nports * (4 + int64_t(h->nrhs_max) * 3 * tv) + P.S * 16;
+        else if (h->pps)
             *port_sweep_bytes = P.tri_entries * esize + P.nports * (4 * esize + 4 + (P.uniform_W ? 0 : esize)) +
                                 int64_t(P.pn_node.size()) * 4 + P.S * 16;
         else if (h->pp)

@@ -71,6 +71,22 @@ hipError_t launch_sweep_mfma(int S, int max_ns, int max_ports, int nrhs, int var
                              const typename MfmaTypes<T>::TB* b, const typename MfmaTypes<T>::TV* a_cur,
                              typename MfmaTypes<T>::TV* a_next, typename MfmaTypes<T>::TV* x, bool write_x,
                              hipStream_t st);
+// Batched port-to-port sweep: a_next[twin(p)][r] = h[p][r] + (M_s a_cur)_p[r] per
+// sub-circuit, M_s (q x q) in A-tile order at Mop + qmofs[s] (padded to
+// roundup(q, 32)); variant and rc_req as above.
+template <typename T>
+hipError_t launch_sweep_mfma_pp(int S, int max_ports, int nrhs, int variant, int rc_req, size_t lds_limit,
+                                const T* Mop, const int64_t* qmofs, const int32_t* port_off,
+                                const int32_t* port_twin, const typename MfmaTypes<T>::TV* h,
+                                const typename MfmaTypes<T>::TV* a_cur, typename MfmaTypes<T>::TV* a_next,
+                                hipStream_t st);
+// M_s = diag(beta) Kinv[P, P] diag(c) + diag(gamma) in A-tile order from the FP64
+// column-major inverses at Kinv + kofs[s] (coefficients FP64, rounded to T once).
+template <typename T>
+hipError_t launch_port_matrix_tiles(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* port_off,
+                                    const int32_t* port_node, const double* pc, const double* pbeta,
+                                    const double* pgamma, const double* Kinv, const int64_t* qmofs, T* out,
+                                    hipStream_t st);
 
 // ---- port-to-port form (ports.hip) -------------------------------------------
 // M_s = diag(beta) K^-1[i(P), i(P)] diag(c) + diag(gamma) for every sub-circuit,
@@ -82,7 +98,7 @@ hipError_t launch_port_matrix(int S, const int32_t* sub_off, const int64_t* kofs
                               const double* pgamma, const TO* K, const int64_t* pofs, TO* M, hipStream_t st);
 // h_p = beta_p x_i(p) (one right-hand side; x renumbered)
 template <typename TV>
-hipError_t launch_port_h(int S, const int32_t* sub_off, const int32_t* port_off, const int32_t* port_node,
+hipError_t launch_port_h(int S, int nrhs, const int32_t* sub_off, const int32_t* port_off, const int32_t* port_node,
                          const TV* pbeta, const TV* x, TV* h, hipStream_t st);
 // a_next[twin(p)] = h_p + (M_s a_cur)_p for every port (one right-hand side)
 template <typename TO, typename TV>
@@ -108,14 +124,15 @@ hipError_t launch_sweep_pps(int S, int max_npn, int max_ports, const TO* Sp, con
                             const TV* a_cur, TV* a_next, hipStream_t st);
 
 // ---- residual -------------------------------------------------------------
-// Sum of squares of b - A x for the iterate of the sweep that read a_cur and
-// wrote a_next, from port quantities alone (one right-hand side): norms[0].
-// pn_pfirst[n] .. pn_pfirst[n + 1] are the ports of port node n (n < count).
-// partial must hold 2 * kResidBlocks doubles.
+// Per right-hand side, the sum of squares of b - A x for the iterate of the
+// sweep that read a_cur and wrote a_next ([ports][nrhs]), from port quantities
+// alone: norms[2 r] (norms[2 r + 1] = 0).  pn_pfirst[n] .. pn_pfirst[n + 1] are
+// the ports of port node n (n < count).  partial: kResidBlocks * nrhs * 2 doubles.
 template <typename TV>
-hipError_t launch_port_residual(int64_t n_port_nodes, const int32_t* pn_pfirst, const int32_t* twin, const TV* a_cur,
-                                const TV* a_next, const double* c, const double* beta, const double* gamma,
-                                const double* gd, const double* g, double* partial, double* norms, hipStream_t st);
+hipError_t launch_port_residual(int64_t n_port_nodes, int nrhs, const int32_t* pn_pfirst, const int32_t* twin,
+                                const TV* a_cur, const TV* a_next, const double* c, const double* beta,
+                                const double* gamma, const double* gd, const double* g, double* partial, double* norms,
+                                hipStream_t st);
 // r = b - A x in FP64 on the untorn (renumbered) A; per right-hand side
 // sums of r^2 and b^2 land in norms[2 * rhs + {0, 1}] (fixed summation order).
 // r_out may be null.  partial must hold kResidBlocks * nrhs * 2 doubles.

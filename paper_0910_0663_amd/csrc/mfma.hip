@@ -80,6 +80,73 @@ struct Mma<double> {
     static __device__ int out_row(int l, int v) { return (l >> 4) + 4 * v; }
 };
 
+// The GEMM core of the batched sweeps: D = A B for one padded np x np block A
+// (tile order, tiles.hpp) and the staged np x w block B in LDS.  A wavefront
+// takes up to RT row tiles (mt = wave, wave + W, ...) per pass and walks k: per
+// k tile it loads the NT B fragments once from LDS and its row tiles' A tiles
+// from HBM (the next k tile's A tiles are already in flight), then issues the
+// MFMAs.  epi(row, n, value) receives every element of D (rows < np, n < 16 NT).
+template <typename T, int NT, int RT, typename Epi>
+__device__ inline void tile_gemm(const T* Ablk, int np, const T* sb, int bsel, int w, Epi epi) {
+    using M = Mma<T>;
+    using TV = typename M::TV;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int MT = np / 16, KT = np / M::KT;
+    const typename M::AFrag* A0 = reinterpret_cast<const typename M::AFrag*>(Ablk) + lane;
+    for (int g0 = 0; g0 < MT; g0 += kWaves * RT) {
+        int mts[RT];
+        int nmy = 0;
+#pragma unroll
+        for (int j = 0; j < RT; ++j) {
+            mts[j] = g0 + wave + j * kWaves;
+            if (mts[j] < MT) nmy = j + 1;
+        }
+        if (nmy == 0) continue;
+        typename M::Acc acc[RT][NT];
+#pragma unroll
+        for (int j = 0; j < RT; ++j)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[j][nt][v] = 0;
+        typename M::AFrag abuf[2][RT];
+#pragma unroll
+        for (int j = 0; j < RT; ++j)
+            if (j < nmy) abuf[0][j] = A0[int64_t(mts[j]) * KT * 64];
+        for (int kt = 0; kt < KT; kt += 2) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = kt + h;
+                if (k < KT) {
+                    if (k + 1 < KT) {
+#pragma unroll
+                        for (int j = 0; j < RT; ++j)
+                            if (j < nmy) abuf[h ^ 1][j] = A0[(int64_t(mts[j]) * KT + k + 1) * 64];
+                    }
+                    typename M::BFrag bf[NT];
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) bf[nt] = M::bfrag(sb, bsel, k, nt);
+#pragma unroll
+                    for (int j = 0; j < RT; ++j)
+                        if (j < nmy)
+#pragma unroll
+                            for (int nt = 0; nt < NT; ++nt)
+                                if (nt * 16 < w) acc[j][nt] = M::mma(abuf[h][j], bf[nt], acc[j][nt]);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < RT; ++j) {
+            if (j >= nmy) continue;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    epi(mts[j] * 16 + M::out_row(lane, v), nt * 16 + (lane & 15), TV(acc[j][nt][v]));
+        }
+    }
+}
+
 // Block (y, s): sub-circuit s, right-hand sides [r0, r0 + w), w <= rc <= 16 * NT.
 // TB: element type of the right-hand side b (BF16 for the BF16 path: the staged
 // operand is BF16 anyway).  write_x = 0 stores x only on port rows (all the
@@ -105,7 +172,6 @@ __global__ void __launch_bounds__(kBlock)
     const int np = tile_pad(ns);
     const int p0 = port_off[s], p1 = port_off[s + 1];
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
 
     // 1. stage B = b + c * a.  Ports of a node are consecutive (slot order);
     //    pfirst/pcount give each row its port range.  b is read V values at a time.
@@ -161,70 +227,10 @@ __global__ void __launch_bounds__(kBlock)
     }
     __syncthreads();
 
-    // 2. X = Kinv B.  A wavefront takes up to RT row tiles
-    //    (mt = wave, wave + W, ...) per pass and walks k: per k tile it loads the
-    //    NT B fragments once from LDS and its row tiles' A tiles from HBM (the
-    //    next k tile's A tiles are already in flight), then issues the MFMAs.
-    const int MT = np / 16, KT = np / M::KT;
-    const typename M::AFrag* A0 = reinterpret_cast<const typename M::AFrag*>(K + mofs[s]) + lane;
-    const int bsel = sizeof(T) == 2 ? np : rc;
-    for (int g0 = 0; g0 < MT; g0 += kWaves * RT) {
-        int mts[RT];
-        int nmy = 0;
-#pragma unroll
-        for (int j = 0; j < RT; ++j) {
-            mts[j] = g0 + wave + j * kWaves;
-            if (mts[j] < MT) nmy = j + 1;
-        }
-        if (nmy == 0) continue;
-        typename M::Acc acc[RT][NT];
-#pragma unroll
-        for (int j = 0; j < RT; ++j)
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[j][nt][v] = 0;
-        typename M::AFrag abuf[2][RT];
-#pragma unroll
-        for (int j = 0; j < RT; ++j)
-            if (j < nmy) abuf[0][j] = A0[int64_t(mts[j]) * KT * 64];
-        for (int kt = 0; kt < KT; kt += 2) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int k = kt + h;
-                if (k < KT) {
-                    if (k + 1 < KT) {
-#pragma unroll
-                        for (int j = 0; j < RT; ++j)
-                            if (j < nmy) abuf[h ^ 1][j] = A0[(int64_t(mts[j]) * KT + k + 1) * 64];
-                    }
-                    typename M::BFrag bf[NT];
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) bf[nt] = M::bfrag(sb, bsel, k, nt);
-#pragma unroll
-                    for (int j = 0; j < RT; ++j)
-                        if (j < nmy)
-#pragma unroll
-                            for (int nt = 0; nt < NT; ++nt)
-                                if (nt * 16 < w) acc[j][nt] = M::mma(abuf[h][j], bf[nt], acc[j][nt]);
-                }
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < RT; ++j) {
-            if (j >= nmy) continue;
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int n = nt * 16 + (lane & 15);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = mts[j] * 16 + M::out_row(lane, v);
-                    if (row < ns && n < w && (write_x || pcount[row]))
-                        x[int64_t(off + row) * nrhs + r0 + n] = TV(acc[j][nt][v]);
-                }
-            }
-        }
-    }
+    // 2. X = Kinv B, x stored on the rows the wave update reads (all rows with write_x)
+    tile_gemm<T, NT, RT>(K + mofs[s], np, sb, sizeof(T) == 2 ? np : rc, w, [&](int row, int n, TV v) {
+        if (row < ns && n < w && (write_x || pcount[row])) x[int64_t(off + row) * nrhs + r0 + n] = v;
+    });
     __syncthreads();
 
     // 3. outgoing waves, read back x of the port nodes (written by this workgroup), 4 columns at a time
@@ -240,6 +246,89 @@ __global__ void __launch_bounds__(kBlock)
         for (int j = 0; j < 4; ++j)
             if (n0 + j < w) nr[n0 + j] = be * xr[n0 + j] + ga * ar[n0 + j];
     }
+}
+
+// Batched port-to-port sweep (the Appendix's interface-only iteration, eqs.
+// 23-26, for many right-hand sides): block (y, s) forms
+//   a_next[twin(p)][r] = h[p][r] + sum_p' M_s[p][p'] a_cur[p'][r]
+// for the ports p of sub-circuit s and right-hand sides [r0, r0 + w).  M_s
+// (q x q, zero-padded to qp = roundup(q, 32)) is stored in A-tile order; the
+// block of incident waves is staged in LDS as the B operand (BF16 for the BF16
+// path, FP32 accumulate).
+template <typename T, int NT, int RT>
+__global__ void __launch_bounds__(kBlock)
+    k_sweep_mfma_pp(const T* __restrict__ Mop, const int64_t* __restrict__ qmofs,
+                    const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_twin,
+                    const typename Mma<T>::TV* __restrict__ h, const typename Mma<T>::TV* __restrict__ a_cur,
+                    typename Mma<T>::TV* __restrict__ a_next, int nrhs, int rc) {
+    using M = Mma<T>;
+    using TV = typename M::TV;
+    extern __shared__ char smem[];
+    T* sb = reinterpret_cast<T*>(smem);
+    const int s = blockIdx.y;
+    const int r0 = blockIdx.x * rc;
+    const int w = min(rc, nrhs - r0);
+    const int p0 = port_off[s], q = port_off[s + 1] - p0;
+    const int qp = tile_pad(q);
+    const int tid = threadIdx.x;
+    for (int t = tid; t < qp * rc; t += kBlock) {
+        const int k = t / rc, n = t - k * rc;
+        const TV v = (k < q && n < w) ? a_cur[int64_t(p0 + k) * nrhs + r0 + n] : TV(0);
+        M::stage(sb, qp, rc, k, n, v);
+    }
+    __syncthreads();
+    tile_gemm<T, NT, RT>(Mop + qmofs[s], qp, sb, sizeof(T) == 2 ? qp : rc, w, [&](int row, int n, TV v) {
+        if (row < q && n < w) {
+            const int p = p0 + row;
+            a_next[int64_t(port_twin[p]) * nrhs + r0 + n] = v + h[int64_t(p) * nrhs + r0 + n];
+        }
+    });
+}
+
+// M_s = diag(beta) Kinv[P, P] diag(c) + diag(gamma) in A-tile order, from the
+// FP64 inverses (column-major at kofs[s]) that the batched setup leaves in scratch.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_port_matrix_tiles(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs,
+                        const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_node,
+                        const double* __restrict__ pc, const double* __restrict__ pbeta,
+                        const double* __restrict__ pgamma, const double* __restrict__ Kinv,
+                        const int64_t* __restrict__ qmofs, T* __restrict__ out) {
+    const int s = blockIdx.x;
+    const int ns = sub_off[s + 1] - sub_off[s];
+    const int p0 = port_off[s], q = port_off[s + 1] - p0;
+    const int qp = tile_pad(q);
+    const double* Ks = Kinv + kofs[s];
+    T* o = out + qmofs[s];
+    const int64_t cnt = int64_t(qp) * qp;
+    for (int64_t d = threadIdx.x; d < cnt; d += blockDim.x) {
+        int r, c;
+        tile_rc<T>(qp, d, r, c);
+        double v = 0.0;
+        if (r < q && c < q) {
+            const int i = port_node[p0 + r], j = port_node[p0 + c];
+            v = pbeta[p0 + r] * Ks[int64_t(j) * ns + i] * pc[p0 + c] + (r == c ? pgamma[p0 + r] : 0.0);
+        }
+        o[d] = static_cast<T>(v);
+    }
+}
+
+template <typename T, int NT, int RT>
+hipError_t launch_pp_t(int S, int nrhs, int rc, size_t lds, const T* Mop, const int64_t* qmofs,
+                       const int32_t* port_off, const int32_t* port_twin, const typename Mma<T>::TV* h,
+                       const typename Mma<T>::TV* a_cur, typename Mma<T>::TV* a_next, hipStream_t st) {
+    auto kern = k_sweep_mfma_pp<T, NT, RT>;
+    static size_t lds_set = 65536;
+    if (lds > lds_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        lds_set = lds;
+    }
+    const unsigned ny = unsigned((nrhs + rc - 1) / rc);
+    hipLaunchKernelGGL(kern, dim3(ny, S), dim3(kBlock), lds, st, Mop, qmofs, port_off, port_twin, h, a_cur, a_next,
+                       nrhs, rc);
+    return hipGetLastError();
 }
 
 template <typename T, int NT, int RT>
@@ -300,6 +389,57 @@ hipError_t launch_sweep_mfma(int S, int max_ns, int max_ports, int nrhs, int var
     return hipErrorInvalidValue;
 }
 
+template <typename T>
+hipError_t launch_sweep_mfma_pp(int S, int max_ports, int nrhs, int variant, int rc_req, size_t lds_limit,
+                                const T* Mop, const int64_t* qmofs, const int32_t* port_off,
+                                const int32_t* port_twin, const typename MfmaTypes<T>::TV* h,
+                                const typename MfmaTypes<T>::TV* a_cur, typename MfmaTypes<T>::TV* a_next,
+                                hipStream_t st) {
+    const int qp = tile_pad(max_ports);
+    int rc = rc_req > 0 ? ((rc_req + 15) / 16) * 16 : 64;
+    if (rc > 64) rc = 64;
+    while (rc > 16 && tile_lds_bytes<T>(qp, rc) > lds_limit) rc -= 16;
+    const size_t lds = tile_lds_bytes<T>(qp, rc);
+    if (lds > lds_limit) return hipErrorInvalidValue;
+    if (rc > nrhs) rc = ((nrhs + 15) / 16) * 16 < rc ? ((nrhs + 15) / 16) * 16 : rc;
+    const int nt = (rc + 15) / 16;
+    const bool deep = variant != 0;
+#define VTM_MFMA_PP_CASE(NTV)                                                                                    \
+    if (nt == NTV)                                                                                               \
+        return deep ? launch_pp_t<T, NTV, 5>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur, a_next,   \
+                                             st)                                                                 \
+                    : launch_pp_t<T, NTV, 3>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur, a_next,   \
+                                             st);
+    VTM_MFMA_PP_CASE(1)
+    VTM_MFMA_PP_CASE(2)
+    VTM_MFMA_PP_CASE(3)
+    VTM_MFMA_PP_CASE(4)
+#undef VTM_MFMA_PP_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_port_matrix_tiles(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* port_off,
+                                    const int32_t* port_node, const double* pc, const double* pbeta,
+                                    const double* pgamma, const double* Kinv, const int64_t* qmofs, T* out,
+                                    hipStream_t st) {
+    hipLaunchKernelGGL(k_port_matrix_tiles<T>, dim3(S), dim3(kBlock), 0, st, sub_off, kofs, port_off, port_node, pc,
+                       pbeta, pgamma, Kinv, qmofs, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_sweep_mfma_pp<__bf16>(int, int, int, int, int, size_t, const __bf16*, const int64_t*,
+                                                const int32_t*, const int32_t*, const float*, const float*, float*,
+                                                hipStream_t);
+template hipError_t launch_sweep_mfma_pp<double>(int, int, int, int, int, size_t, const double*, const int64_t*,
+                                                const int32_t*, const int32_t*, const double*, const double*,
+                                                double*, hipStream_t);
+template hipError_t launch_port_matrix_tiles<__bf16>(int, const int32_t*, const int64_t*, const int32_t*,
+                                                    const int32_t*, const double*, const double*, const double*,
+                                                    const double*, const int64_t*, __bf16*, hipStream_t);
+template hipError_t launch_port_matrix_tiles<double>(int, const int32_t*, const int64_t*, const int32_t*,
+                                                    const int32_t*, const double*, const double*, const double*,
+                                                    const double*, const int64_t*, double*, hipStream_t);
 template hipError_t launch_sweep_mfma<__bf16>(int, int, int, int, int, int, size_t, const __bf16*, const int64_t*,
                                              const int32_t*, PortArrays, const float*, const float*, const float*,
                                              const __bf16*, const float*, float*, float*, bool, hipStream_t);

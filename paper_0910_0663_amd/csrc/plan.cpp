@@ -249,11 +249,14 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
         P.dmod[P.iperm[node]] += k.G - P.wg[e];
     }
     P.pofs.assign(S + 1, 0);
+    P.qmofs.assign(S + 1, 0);
     for (int64_t s = 0; s < S; ++s) {
         const int64_t q = P.port_off[s + 1];
         P.max_ports = std::max<int32_t>(P.max_ports, int32_t(q));
         P.pofs[s + 1] = P.pofs[s] + ((q * q + 3) & ~int64_t(3));
         P.sq_entries += q * q;
+        const int64_t qp = (q + 31) & ~int64_t(31);
+        P.qmofs[s + 1] = P.qmofs[s] + qp * qp;
         P.port_off[s + 1] += P.port_off[s];
     }
     for (int64_t q = 0; q < np; ++q) P.port_twin[P.abi2port[q]] = P.abi2port[q ^ 1];

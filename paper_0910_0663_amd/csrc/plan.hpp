@@ -27,6 +27,7 @@ struct Plan {
     std::vector<int64_t> kofs;     // [S + 1] element offset of each dense inverse
     std::vector<int64_t> mofs;     // [S + 1] element offset of each padded MFMA tile block
     std::vector<int64_t> pofs;     // [S + 1] element offset of each port-to-port operator (q_s x q_s)
+    std::vector<int64_t> qmofs;    // [S + 1] element offset of each port operator in MFMA tiles (padded q_s)
     // Port nodes: the distinct nodes carrying ports, per sub-circuit in port order.
     std::vector<int32_t> pn_off;    // [S + 1] first port node of each sub-circuit
     std::vector<int32_t> pn_node;   // local node of each port node

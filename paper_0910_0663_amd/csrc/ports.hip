@@ -41,16 +41,20 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
-// h_p = beta_p x_i(p) for x = K^-1 b (one right-hand side)
+// h_p = beta_p x_i(p) for x = K^-1 b, per right-hand side (x and h are
+// [rows][nrhs], right-hand side fastest)
 template <typename TV>
 __global__ void __launch_bounds__(kBlock)
-    k_port_h(int S, const int32_t* __restrict__ sub_off, const int32_t* __restrict__ port_off,
+    k_port_h(int nrhs, const int32_t* __restrict__ sub_off, const int32_t* __restrict__ port_off,
              const int32_t* __restrict__ port_node, const TV* __restrict__ pbeta, const TV* __restrict__ x,
              TV* __restrict__ h) {
     const int s = blockIdx.x;
-    const int off = sub_off[s];
-    for (int p = port_off[s] + threadIdx.x; p < port_off[s + 1]; p += blockDim.x)
-        h[p] = pbeta[p] * x[off + port_node[p]];
+    const int off = sub_off[s], p0 = port_off[s];
+    const int cnt = (port_off[s + 1] - p0) * nrhs;
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+        const int p = p0 + t / nrhs, r = t % nrhs;
+        h[int64_t(p) * nrhs + r] = pbeta[p] * x[int64_t(off + port_node[p]) * nrhs + r];
+    }
 }
 
 template <typename T>
@@ -143,9 +147,10 @@ hipError_t launch_port_matrix(int S, const int32_t* sub_off, const int64_t* kofs
 }
 
 template <typename TV>
-hipError_t launch_port_h(int S, const int32_t* sub_off, const int32_t* port_off, const int32_t* port_node,
+hipError_t launch_port_h(int S, int nrhs, const int32_t* sub_off, const int32_t* port_off, const int32_t* port_node,
                          const TV* pbeta, const TV* x, TV* h, hipStream_t st) {
-    hipLaunchKernelGGL(k_port_h<TV>, dim3(S), dim3(64), 0, st, S, sub_off, port_off, port_node, pbeta, x, h);
+    hipLaunchKernelGGL(k_port_h<TV>, dim3(S), dim3(nrhs > 1 ? 256 : 64), 0, st, nrhs, sub_off, port_off, port_node,
+                       pbeta, x, h);
     return hipGetLastError();
 }
 
@@ -169,9 +174,9 @@ template hipError_t launch_port_matrix<double>(int, const int32_t*, const int64_
 template hipError_t launch_port_matrix<float>(int, const int32_t*, const int64_t*, const int32_t*, const int32_t*,
                                               const double*, const double*, const double*, const float*,
                                               const int64_t*, float*, hipStream_t);
-template hipError_t launch_port_h<double>(int, const int32_t*, const int32_t*, const int32_t*, const double*,
+template hipError_t launch_port_h<double>(int, int, const int32_t*, const int32_t*, const int32_t*, const double*,
                                           const double*, double*, hipStream_t);
-template hipError_t launch_port_h<float>(int, const int32_t*, const int32_t*, const int32_t*, const float*,
+template hipError_t launch_port_h<float>(int, int, const int32_t*, const int32_t*, const int32_t*, const float*,
                                          const float*, float*, hipStream_t);
 template hipError_t launch_sweep_pp<double, double>(int, int, const double*, const int64_t*, const int32_t*,
                                                     const int32_t*, const double*, const double*, double*,

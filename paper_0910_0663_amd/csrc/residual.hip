@@ -67,57 +67,67 @@ __global__ void __launch_bounds__(kBlock)
 // per port node n, r_n = sum over its ports p of (G_p - g_p) x_n + g_p x_j(p)
 // - c_p a_p, where x_n = (o_p0 - gamma_p0 a_p0) / beta_p0 from its first port,
 // x_j(p) likewise from the twin port q, and the outgoing wave o_p of port p is
-// a_next[twin(p)].  One right-hand side; partial sums as in k_resid.
+// a_next[twin(p)].  Waves are [ports][nrhs]; thread (node slot, rhs) as in
+// k_resid, partial sums per column in the same layout.
 template <typename TV>
 __global__ void __launch_bounds__(kBlock)
-    k_port_resid(int64_t nn, const int32_t* __restrict__ pn_pfirst, const int32_t* __restrict__ twin,
+    k_port_resid(int64_t nn, int nrhs, const int32_t* __restrict__ pn_pfirst, const int32_t* __restrict__ twin,
                  const TV* __restrict__ a_cur, const TV* __restrict__ a_next, const double* __restrict__ c,
                  const double* __restrict__ beta, const double* __restrict__ gamma, const double* __restrict__ gd,
                  const double* __restrict__ g, double* __restrict__ partial) {
-    __shared__ double s[kBlock];
+    __shared__ double s_rr[kBlock];
     const int tid = threadIdx.x;
+    const int per = blockDim.x / nrhs;
+    const int used = per * nrhs;
     double rr = 0.0;
-    for (int64_t n = int64_t(blockIdx.x) * kBlock + tid; n < nn; n += int64_t(gridDim.x) * kBlock) {
-        const int p0 = pn_pfirst[n], p1 = pn_pfirst[n + 1];
-        const double xn = (double(a_next[twin[p0]]) - gamma[p0] * double(a_cur[p0])) / beta[p0];
-        double r = 0.0;
-        for (int p = p0; p < p1; ++p) {
-            const int q = twin[p];
-            const double xj = (double(a_next[p]) - gamma[q] * double(a_cur[q])) / beta[q];
-            r += gd[p] * xn + g[p] * xj - c[p] * double(a_cur[p]);
+    if (tid < used) {
+        const int rhs = tid % nrhs, rl = tid / nrhs;
+        for (int64_t n = int64_t(blockIdx.x) * per + rl; n < nn; n += int64_t(gridDim.x) * per) {
+            const int p0 = pn_pfirst[n], p1 = pn_pfirst[n + 1];
+            const double xn =
+                (double(a_next[int64_t(twin[p0]) * nrhs + rhs]) - gamma[p0] * double(a_cur[int64_t(p0) * nrhs + rhs])) /
+                beta[p0];
+            double r = 0.0;
+            for (int p = p0; p < p1; ++p) {
+                const int q = twin[p];
+                const double xj =
+                    (double(a_next[int64_t(p) * nrhs + rhs]) - gamma[q] * double(a_cur[int64_t(q) * nrhs + rhs])) /
+                    beta[q];
+                r += gd[p] * xn + g[p] * xj - c[p] * double(a_cur[int64_t(p) * nrhs + rhs]);
+            }
+            rr += r * r;
         }
-        rr += r * r;
     }
-    s[tid] = rr;
+    s_rr[tid] = rr;
     __syncthreads();
-    for (int h = kBlock / 2; h > 0; h >>= 1) {
-        if (tid < h) s[tid] += s[tid + h];
-        __syncthreads();
-    }
-    if (tid == 0) {
-        partial[int64_t(blockIdx.x) * 2 + 0] = s[0];
-        partial[int64_t(blockIdx.x) * 2 + 1] = 0.0;
+    for (int j = tid; j < nrhs; j += blockDim.x) {
+        double a = 0.0;
+        for (int q = 0; q < per; ++q) a += s_rr[q * nrhs + j];
+        partial[(int64_t(blockIdx.x) * nrhs + j) * 2 + 0] = a;
+        partial[(int64_t(blockIdx.x) * nrhs + j) * 2 + 1] = 0.0;
     }
 }
 
 }  // namespace
 
 template <typename TV>
-hipError_t launch_port_residual(int64_t n_port_nodes, const int32_t* pn_pfirst, const int32_t* twin, const TV* a_cur,
-                                const TV* a_next, const double* c, const double* beta, const double* gamma,
-                                const double* gd, const double* g, double* partial, double* norms, hipStream_t st) {
-    hipLaunchKernelGGL(k_port_resid<TV>, dim3(kResidBlocks), dim3(kBlock), 0, st, n_port_nodes, pn_pfirst, twin,
+hipError_t launch_port_residual(int64_t n_port_nodes, int nrhs, const int32_t* pn_pfirst, const int32_t* twin,
+                                const TV* a_cur, const TV* a_next, const double* c, const double* beta,
+                                const double* gamma, const double* gd, const double* g, double* partial, double* norms,
+                                hipStream_t st) {
+    if (nrhs < 1 || nrhs > kBlock) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_port_resid<TV>, dim3(kResidBlocks), dim3(kBlock), 0, st, n_port_nodes, nrhs, pn_pfirst, twin,
                        a_cur, a_next, c, beta, gamma, gd, g, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(kBlock), 0, st, kResidBlocks, 1, partial, norms);
+    hipLaunchKernelGGL(k_norms_final, dim3(2 * nrhs), dim3(kBlock), 0, st, kResidBlocks, nrhs, partial, norms);
     return hipGetLastError();
 }
 
-template hipError_t launch_port_residual<double>(int64_t, const int32_t*, const int32_t*, const double*,
+template hipError_t launch_port_residual<double>(int64_t, int, const int32_t*, const int32_t*, const double*,
                                                  const double*, const double*, const double*, const double*,
                                                  const double*, const double*, double*, double*, hipStream_t);
-template hipError_t launch_port_residual<float>(int64_t, const int32_t*, const int32_t*, const float*, const float*,
+template hipError_t launch_port_residual<float>(int64_t, int, const int32_t*, const int32_t*, const float*, const float*,
                                                 const double*, const double*, const double*, const double*,
                                                 const double*, double*, double*, hipStream_t);
 

@@ -115,8 +115,28 @@ def mixed_and_batched(vtm, torch, oracle, workloads):
         "bf16_sweeps": r16.sweeps, "bf16_outer": r16.outer, "fp64_sweeps": r64.sweeps,
         "bf16_relres": rel16, "fp64_relres": rel64, "bf16_vs_fp64_rel_error": diff,
         "batch_shape_bf16": list(r16.batch_shape), "batch_shape_fp64": list(r64.batch_shape)}
+    # the same 64 right-hand sides as 64 single-column FP64 solves (port-to-port form)
+    s1 = vtm.Solver(w.A, w.part, w.Z, precision="fp64", nrhs_max=1)
+    bcols = [torch.as_tensor(w.b[r:r + 1], dtype=torch.float64, device="cuda") for r in range(w.nrhs)]
+    xcols = [torch.empty_like(c) for c in bcols]
+    s1.solve(bcols[0], w.tol, xcols[0])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sweeps1 = 0
+    for c, xc in zip(bcols, xcols):
+        _, rep1 = s1.solve(c, w.tol, xc)
+        sweeps1 += rep1.sweeps
+    torch.cuda.synchronize()
+    t1 = (time.perf_counter() - t) * 1e3
+    s1.close()
+    x1 = torch.cat(xcols).cpu().numpy()
+    rel1 = float(oracle.relative_residual(w.A, w.b, x1).max())
+    assert rel1 <= w.tol, rel1
+    res["batched_bf16_vs_fp64"].update({
+        "fp64_single_rhs_x64_ms": round(t1, 1), "fp64_single_rhs_sweeps_total": sweeps1,
+        "fp64_single_rhs_relres": rel1, "speedup_vs_single_rhs": round(t1 / t16, 2)})
     log(f"cfg4: bf16 {t16:.1f} ms ({r16.sweeps} sweeps, {r16.outer} outer) vs fp64 batched {t64:.1f} ms "
-        f"({r64.sweeps} sweeps): x{t64 / t16:.2f}")
+        f"({r64.sweeps} sweeps): x{t64 / t16:.2f}; vs 64 single-RHS fp64 solves {t1:.0f} ms: x{t1 / t16:.1f}")
     w = workloads.make(3)
     t32, r32, x32 = timed_solve(vtm, torch, w, "fp32_refine", 1, reps=2)
     t64, r64, x64 = timed_solve(vtm, torch, w, "fp64", 1, reps=2)

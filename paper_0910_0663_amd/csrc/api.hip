@@ -88,6 +88,7 @@ struct vtm_handle_s {
     DevBuf<double> pg64, pgd64;
     // batched port-to-port form (MFMA tiles): q x q operators in A-tile order
     bool ppb = false;
+    int pp_variant = 0, pp_rc = 0;  // its launch shape (autotuned like the full batched sweep)
     DevBuf<int64_t> qmofs;
     DevBuf<__bf16> Mbt;
     DevBuf<double> M64t;
@@ -273,12 +274,12 @@ vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
     if (pp && h->tiles) {
         const vtm::Plan& P = h->plan;
         if (!low)
-            VTM_HIP(vtm::launch_sweep_mfma_pp<double>(int(P.S), P.max_ports, nrhs, h->mfma_variant, h->mfma_rc,
+            VTM_HIP(vtm::launch_sweep_mfma_pp<double>(int(P.S), P.max_ports, nrhs, h->pp_variant, h->pp_rc,
                                                       h->lds_limit, h->M64t.p, h->qmofs.p, h->port_off.p,
                                                       h->port_twin.p, h->h64.p, h->a64[cur].p, h->a64[cur ^ 1].p,
                                                       h->stream));
         else
-            VTM_HIP(vtm::launch_sweep_mfma_pp<__bf16>(int(P.S), P.max_ports, nrhs, h->mfma_variant, h->mfma_rc,
+            VTM_HIP(vtm::launch_sweep_mfma_pp<__bf16>(int(P.S), P.max_ports, nrhs, h->pp_variant, h->pp_rc,
                                                       h->lds_limit, h->Mbt.p, h->qmofs.p, h->port_off.p,
                                                       h->port_twin.p, h->h32.p, h->a32[cur].p, h->a32[cur ^ 1].p,
                                                       h->stream));
@@ -348,6 +349,7 @@ vtm_status autotune(vtm_handle h) {
     VTM_HIP(hipEventCreate(&t0));
     VTM_HIP(hipEventCreate(&t1));
     float best = INFINITY;
+    int bv = 0, brc = 0;
     vtm_status st = VTM_OK;
     const int v_lo = h->opt.batch_row_tiles == 5 ? 1 : 0, v_hi = h->opt.batch_row_tiles == 3 ? 0 : 1;
     for (int variant = v_lo; variant <= v_hi && st == VTM_OK; ++variant)
@@ -370,6 +372,40 @@ vtm_status autotune(vtm_handle h) {
                 h->mfma_rc = rc;
             }
         }
+    // the batched port-to-port sweep: the same candidates on its q x q operators
+    if (st == VTM_OK && h->ppb) {
+        const int32_t timing = h->opt.timing;  // no per-launch events while tuning
+        h->opt.timing = 0;
+        if (low)
+            VTM_HIP(vtm::launch_fill<float>(P.nports * nrhs, 0.0f, h->h32.p, h->stream));
+        else
+            VTM_HIP(vtm::launch_fill<double>(P.nports * nrhs, 0.0, h->h64.p, h->stream));
+        float best_pp = INFINITY;
+        for (int variant = v_lo; variant <= v_hi && st == VTM_OK; ++variant)
+            for (int rc = 64; rc >= 16 && st == VTM_OK; rc -= 16) {
+                if (rc > 16 && rc >= nrhs + 16) continue;
+                if (h->opt.batch_rhs_block > 0 && rc != h->opt.batch_rhs_block) continue;
+                h->pp_variant = variant;
+                h->pp_rc = rc;
+                st = sweep_once(h, low, nrhs, b, x, 0, false, false, true);
+                if (st != VTM_OK) break;
+                if (hipEventRecord(t0, h->stream) != hipSuccess) st = fail(VTM_E_HIP, "event record");
+                for (int k = 0; k < 3 && st == VTM_OK; ++k) st = sweep_once(h, low, nrhs, b, x, k & 1, false, false, true);
+                if (st != VTM_OK) break;
+                float ms = 0.f;
+                if (hipEventRecord(t1, h->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, t0, t1) != hipSuccess)
+                    st = fail(VTM_E_HIP, "autotune timing");
+                else if (ms < best_pp) {
+                    best_pp = ms;
+                    bv = variant;
+                    brc = rc;
+                }
+            }
+        h->pp_variant = bv;
+        h->pp_rc = brc;
+        h->opt.timing = timing;
+    }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     return st;

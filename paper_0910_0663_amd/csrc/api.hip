@@ -381,8 +381,9 @@ vtm_status autotune(vtm_handle h) {
         else
             VTM_HIP(vtm::launch_fill<double>(P.nports * nrhs, 0.0, h->h64.p, h->stream));
         float best_pp = INFINITY;
-        for (int variant = v_lo; variant <= v_hi && st == VTM_OK; ++variant)
+        for (int variant = 0; variant < 4 && st == VTM_OK; ++variant)
             for (int rc = 64; rc >= 16 && st == VTM_OK; rc -= 16) {
+                if ((variant & 1) < v_lo || (variant & 1) > v_hi) continue;
                 if (rc > 16 && rc >= nrhs + 16) continue;
                 if (h->opt.batch_rhs_block > 0 && rc != h->opt.batch_rhs_block) continue;
                 h->pp_variant = variant;

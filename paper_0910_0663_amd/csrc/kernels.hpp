@@ -73,7 +73,8 @@ hipError_t launch_sweep_mfma(int S, int max_ns, int max_ports, int nrhs, int var
                              hipStream_t st);
 // Batched port-to-port sweep: a_next[twin(p)][r] = h[p][r] + (M_s a_cur)_p[r] per
 // sub-circuit, M_s (q x q) in A-tile order at Mop + qmofs[s] (padded to
-// roundup(q, 32)); variant and rc_req as above.
+// roundup(q, 32)); variant bit 0 as above (5 row tiles per pass, else 3), bit 1
+// = 8 wavefronts per workgroup (else 4); rc_req as above.
 template <typename T>
 hipError_t launch_sweep_mfma_pp(int S, int max_ports, int nrhs, int variant, int rc_req, size_t lds_limit,
                                 const T* Mop, const int64_t* qmofs, const int32_t* port_off,

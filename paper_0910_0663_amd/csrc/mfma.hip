@@ -86,19 +86,19 @@ struct Mma<double> {
 // k tile it loads the NT B fragments once from LDS and its row tiles' A tiles
 // from HBM (the next k tile's A tiles are already in flight), then issues the
 // MFMAs.  epi(row, n, value) receives every element of D (rows < np, n < 16 NT).
-template <typename T, int NT, int RT, typename Epi>
+template <typename T, int NT, int RT, int WAVES, typename Epi>
 __device__ inline void tile_gemm(const T* Ablk, int np, const T* sb, int bsel, int w, Epi epi) {
     using M = Mma<T>;
     using TV = typename M::TV;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int MT = np / 16, KT = np / M::KT;
     const typename M::AFrag* A0 = reinterpret_cast<const typename M::AFrag*>(Ablk) + lane;
-    for (int g0 = 0; g0 < MT; g0 += kWaves * RT) {
+    for (int g0 = 0; g0 < MT; g0 += WAVES * RT) {
         int mts[RT];
         int nmy = 0;
 #pragma unroll
         for (int j = 0; j < RT; ++j) {
-            mts[j] = g0 + wave + j * kWaves;
+            mts[j] = g0 + wave + j * WAVES;
             if (mts[j] < MT) nmy = j + 1;
         }
         if (nmy == 0) continue;
@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(kBlock)
     __syncthreads();
 
     // 2. X = Kinv B, x stored on the rows the wave update reads (all rows with write_x)
-    tile_gemm<T, NT, RT>(K + mofs[s], np, sb, sizeof(T) == 2 ? np : rc, w, [&](int row, int n, TV v) {
+    tile_gemm<T, NT, RT, kWaves>(K + mofs[s], np, sb, sizeof(T) == 2 ? np : rc, w, [&](int row, int n, TV v) {
         if (row < ns && n < w && (write_x || pcount[row])) x[int64_t(off + row) * nrhs + r0 + n] = v;
     });
     __syncthreads();
@@ -254,9 +254,10 @@ __global__ void __launch_bounds__(kBlock)
 // for the ports p of sub-circuit s and right-hand sides [r0, r0 + w).  M_s
 // (q x q, zero-padded to qp = roundup(q, 32)) is stored in A-tile order; the
 // block of incident waves is staged in LDS as the B operand (BF16 for the BF16
-// path, FP32 accumulate).
-template <typename T, int NT, int RT>
-__global__ void __launch_bounds__(kBlock)
+// path, FP32 accumulate).  WAVES wavefronts per workgroup (the operators are
+// small: 64 ports make four 16-row tiles).
+template <typename T, int NT, int RT, int WAVES>
+__global__ void __launch_bounds__(WAVES * 64)
     k_sweep_mfma_pp(const T* __restrict__ Mop, const int64_t* __restrict__ qmofs,
                     const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_twin,
                     const typename Mma<T>::TV* __restrict__ h, const typename Mma<T>::TV* __restrict__ a_cur,
@@ -271,13 +272,13 @@ __global__ void __launch_bounds__(kBlock)
     const int p0 = port_off[s], q = port_off[s + 1] - p0;
     const int qp = tile_pad(q);
     const int tid = threadIdx.x;
-    for (int t = tid; t < qp * rc; t += kBlock) {
+    for (int t = tid; t < qp * rc; t += WAVES * 64) {
         const int k = t / rc, n = t - k * rc;
         const TV v = (k < q && n < w) ? a_cur[int64_t(p0 + k) * nrhs + r0 + n] : TV(0);
         M::stage(sb, qp, rc, k, n, v);
     }
     __syncthreads();
-    tile_gemm<T, NT, RT>(Mop + qmofs[s], qp, sb, sizeof(T) == 2 ? qp : rc, w, [&](int row, int n, TV v) {
+    tile_gemm<T, NT, RT, WAVES>(Mop + qmofs[s], qp, sb, sizeof(T) == 2 ? qp : rc, w, [&](int row, int n, TV v) {
         if (row < q && n < w) {
             const int p = p0 + row;
             a_next[int64_t(port_twin[p]) * nrhs + r0 + n] = v + h[int64_t(p) * nrhs + r0 + n];
@@ -313,11 +314,11 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
-template <typename T, int NT, int RT>
+template <typename T, int NT, int RT, int WAVES>
 hipError_t launch_pp_t(int S, int nrhs, int rc, size_t lds, const T* Mop, const int64_t* qmofs,
                        const int32_t* port_off, const int32_t* port_twin, const typename Mma<T>::TV* h,
                        const typename Mma<T>::TV* a_cur, typename Mma<T>::TV* a_next, hipStream_t st) {
-    auto kern = k_sweep_mfma_pp<T, NT, RT>;
+    auto kern = k_sweep_mfma_pp<T, NT, RT, WAVES>;
     static size_t lds_set = 65536;
     if (lds > lds_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -326,8 +327,8 @@ hipError_t launch_pp_t(int S, int nrhs, int rc, size_t lds, const T* Mop, const 
         lds_set = lds;
     }
     const unsigned ny = unsigned((nrhs + rc - 1) / rc);
-    hipLaunchKernelGGL(kern, dim3(ny, S), dim3(kBlock), lds, st, Mop, qmofs, port_off, port_twin, h, a_cur, a_next,
-                       nrhs, rc);
+    hipLaunchKernelGGL(kern, dim3(ny, S), dim3(WAVES * 64), lds, st, Mop, qmofs, port_off, port_twin, h, a_cur,
+                       a_next, nrhs, rc);
     return hipGetLastError();
 }
 
@@ -403,13 +404,20 @@ hipError_t launch_sweep_mfma_pp(int S, int max_ports, int nrhs, int variant, int
     if (lds > lds_limit) return hipErrorInvalidValue;
     if (rc > nrhs) rc = ((nrhs + 15) / 16) * 16 < rc ? ((nrhs + 15) / 16) * 16 : rc;
     const int nt = (rc + 15) / 16;
-    const bool deep = variant != 0;
+    // variant: bit 0 = 5 row tiles per pass (else 3), bit 1 = 8 wavefronts per workgroup (else 4)
+    const bool deep = (variant & 1) != 0, wide = (variant & 2) != 0;
 #define VTM_MFMA_PP_CASE(NTV)                                                                                    \
-    if (nt == NTV)                                                                                               \
-        return deep ? launch_pp_t<T, NTV, 5>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur, a_next,   \
-                                             st)                                                                 \
-                    : launch_pp_t<T, NTV, 3>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur, a_next,   \
-                                             st);
+    if (nt == NTV) {                                                                                             \
+        if (wide)                                                                                                \
+            return deep ? launch_pp_t<T, NTV, 5, 8>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,   \
+                                                    a_next, st)                                                  \
+                        : launch_pp_t<T, NTV, 3, 8>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,   \
+                                                    a_next, st);                                                 \
+        return deep ? launch_pp_t<T, NTV, 5, 4>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,       \
+                                                a_next, st)                                                      \
+                    : launch_pp_t<T, NTV, 3, 4>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,       \
+                                                a_next, st);                                                     \
+    }
     VTM_MFMA_PP_CASE(1)
     VTM_MFMA_PP_CASE(2)
     VTM_MFMA_PP_CASE(3)

@@ -83,6 +83,11 @@ struct vtm_handle_s {
     DevBuf<float> M32, h32;
     // symmetric A: packed port-node operators instead of M
     bool pps = false;
+    // any A: K^-1 over the port nodes (k x k) when that is smaller than M
+    bool ppn = false;
+    DevBuf<int64_t> nofs;
+    DevBuf<double> N64;
+    DevBuf<float> N32;
     DevBuf<int32_t> pn_off, pn_node, pn_pfirst;
     // residual checks from port quantities (port-to-port form): g and G - g per port
     DevBuf<double> pg64, pgd64;
@@ -283,6 +288,18 @@ vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
                                                       h->lds_limit, h->Mbt.p, h->qmofs.p, h->port_off.p,
                                                       h->port_twin.p, h->h32.p, h->a32[cur].p, h->a32[cur ^ 1].p,
                                                       h->stream));
+    } else if (pp && h->ppn) {
+        const vtm::Plan& P = h->plan;
+        if (!low)
+            VTM_HIP((vtm::launch_sweep_ppn<double, double>(int(P.S), P.max_npn, P.max_ports, h->N64.p, h->nofs.p,
+                                                           h->pn_off.p, h->pn_pfirst.p, h->port_off.p, h->port_twin.p,
+                                                           h->c64.p, h->beta64.p, h->gamma64.p, h->h64.p,
+                                                           h->a64[cur].p, h->a64[cur ^ 1].p, h->stream)));
+        else
+            VTM_HIP((vtm::launch_sweep_ppn<float, float>(int(P.S), P.max_npn, P.max_ports, h->N32.p, h->nofs.p,
+                                                         h->pn_off.p, h->pn_pfirst.p, h->port_off.p, h->port_twin.p,
+                                                         h->c32.p, h->beta32.p, h->gamma32.p, h->h32.p,
+                                                         h->a32[cur].p, h->a32[cur ^ 1].p, h->stream)));
     } else if (pp && h->pps) {
         const vtm::Plan& P = h->plan;
         const double W = P.nwires ? P.wW[0] : 0.0;
@@ -922,6 +939,8 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     // port-to-port operators from the stored inverses
     h->pp = o.local_form >= 1 && !h->tiles && P.nports > 0;
     h->pps = h->pp && o.local_form == 1 && P.symmetric && P.max_npn <= 64 && P.max_ports <= 64;
+    const size_t ppn_lds = 2 * size_t(P.max_npn) * (o.precision == VTM_FP64 ? 8 : 4) + size_t(P.max_ports) * 4;
+    h->ppn = h->pp && !h->pps && o.local_form == 1 && P.sqn_entries < P.sq_entries && ppn_lds <= 65536;
     // batched form: port-to-port operators in tile order, built from the FP64 inverses in scratch
     const int qpad = vtm::tile_pad(P.max_ports);
     h->ppb = o.local_form >= 1 && h->tiles && P.nports > 0 &&
@@ -950,7 +969,24 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
         VTM_HIP(h->pg64.upload(P.pg, s));
         VTM_HIP(h->pgd64.upload(P.pgd, s));
     }
-    if (h->pps) {
+    if (h->ppn) {
+        VTM_HIP(h->pn_off.upload(P.pn_off, s));
+        VTM_HIP(h->pn_node.upload(P.pn_node, s));
+        VTM_HIP(h->nofs.upload(P.nofs, s));
+        const int64_t nn = P.nofs[P.S];
+        if (o.precision == VTM_FP64) {
+            VTM_HIP(h->N64.alloc(nn));
+            VTM_HIP(h->h64.alloc(P.nports));
+            VTM_HIP(vtm::launch_port_node_dense<double>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p, h->pn_node.p,
+                                                        h->K64.p, h->nofs.p, h->N64.p, s));
+        } else {
+            VTM_HIP(h->N32.alloc(nn));
+            VTM_HIP(h->h32.alloc(P.nports));
+            VTM_HIP(vtm::launch_port_node_dense<float>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p, h->pn_node.p,
+                                                       h->K32.p, h->nofs.p, h->N32.p, s));
+        }
+        VTM_HIP(hipStreamSynchronize(s));
+    } else if (h->pps) {
         VTM_HIP(h->pn_off.upload(P.pn_off, s));
         VTM_HIP(h->pn_node.upload(P.pn_node, s));
         VTM_HIP(h->sofs.upload(P.sofs, s));
@@ -1056,8 +1092,11 @@ vtm_status vtm_info(vtm_handle h, int64_t* n, int64_t* n_sub, int64_t* n_wires, 
     if (n_sub) *n_sub = P.S;
     if (n_wires) *n_wires = P.nwires;
     if (inverse_bytes) *inverse_bytes = (h->tiles ? P.mofs[P.S] : P.kofs[P.S]) * esize;
-    const int64_t op = h->ppb ? P.qmofs[P.S] * esize
-                              : (h->pps ? P.sofs[P.S] * esize : (h->pp ? P.pofs[P.S] * esize : 0));
+    const int64_t op = h->ppb   ? P.qmofs[P.S] * esize
+                       : h->ppn ? P.nofs[P.S] * esize
+                       : h->pps ? P.sofs[P.S] * esize
+                       : h->pp  ? P.pofs[P.S] * esize
+                                : 0;
     if (port_operator_bytes) *port_operator_bytes = op;
     if (port_sweep_bytes) {
         // operator entries once (without layout padding); per port the wave in, h in, wave
@@ -1066,6 +1105,9 @@ vtm_status vtm_info(vtm_handle h, int64_t* n, int64_t* n_sub, int64_t* n_wires, 
         const int64_t tv = h->opt.precision == VTM_FP64 ? 8 : 4;  // waves (FP32 for the BF16 form)
         if (h->ppb)
             *port_sweep_bytes = P.sq_entries * esize + P.nports * (4 + int64_t(h->nrhs_max) * 3 * tv) + P.S * 16;
+        else if (h->ppn)
+            *port_sweep_bytes = P.sqn_entries * esize + P.nports * (6 * esize + 4) +
+                                int64_t(P.pn_node.size()) * 4 + P.S * 16;
         else if (h->pps)
             *port_sweep_bytes = P.tri_entries * esize + P.nports * (4 * esize + 4 + (P.uniform_W ? 0 : esize)) +
                                 int64_t(P.pn_node.size()) * 4 + P.S * 16;

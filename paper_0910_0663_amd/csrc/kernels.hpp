@@ -106,6 +106,20 @@ template <typename TO, typename TV>
 hipError_t launch_sweep_pp(int S, int max_q, const TO* M, const int64_t* pofs, const int32_t* port_off,
                            const int32_t* port_twin, const TV* h, const TV* a_cur, TV* a_next, hipStream_t st);
 
+// Port-node form for any A: K^-1[N, N] over a sub-circuit's k port nodes in the
+// column-group layout (n = k) at Sn + nofs[s] ...
+template <typename TO>
+hipError_t launch_port_node_dense(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* pn_off,
+                                  const int32_t* pn_node, const TO* K, const int64_t* nofs, TO* Sn, hipStream_t st);
+// ... and its sweep: t_n = sum_{p at n} c_p a_p, z = K^-1[N, N] t,
+// a_next[twin(p)] = beta_p z_n(p) + gamma_p a_p + h_p (LDS 2 max_npn values +
+// 4 max_ports bytes, at most 64 KiB, else hipErrorInvalidValue).
+template <typename TO, typename TV>
+hipError_t launch_sweep_ppn(int S, int max_npn, int max_ports, const TO* Sn, const int64_t* nofs,
+                            const int32_t* pn_off, const int32_t* pn_pfirst, const int32_t* port_off,
+                            const int32_t* port_twin, const TV* pc, const TV* pbeta, const TV* pgamma, const TV* h,
+                            const TV* a_cur, TV* a_next, hipStream_t st);
+
 // Symmetric A: upper triangle of S = K^-1[port nodes, port nodes] per
 // sub-circuit as row-interleaved pairs of diagonals (pair m from 2m (k - m + 1),
 // k port nodes; pads zero), block start 16-byte aligned, at Sp + sofs[s] ...

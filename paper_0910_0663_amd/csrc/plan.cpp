@@ -268,6 +268,7 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
     P.pn_node.clear();
     P.pn_pfirst.clear();
     P.sofs.assign(S + 1, 0);
+    P.nofs.assign(S + 1, 0);
     P.max_npn = 0;
     for (int64_t s = 0; s < S; ++s) {
         for (int32_t p = P.port_off[s]; p < P.port_off[s + 1]; ++p)
@@ -282,6 +283,8 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
         // pair pads its second entry): k (k + 2) / 2 entries for even k, (k + 1)^2 / 2 for odd
         const int64_t pairs = (k % 2 == 0) ? k * (k + 2) / 2 : (k + 1) * (k + 1) / 2;
         P.tri_entries += k * (k + 1) / 2;
+        P.sqn_entries += k * k;
+        P.nofs[s + 1] = P.nofs[s] + ((k * k + 3) & ~int64_t(3));
         P.sofs[s + 1] = P.sofs[s] + ((pairs + 3) & ~int64_t(3));
     }
     P.pn_pfirst.push_back(int32_t(np));

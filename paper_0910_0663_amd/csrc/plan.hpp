@@ -37,6 +37,8 @@ struct Plan {
     int32_t max_npn = 0;            // most port nodes on one sub-circuit
     int64_t tri_entries = 0;        // sum over sub-circuits of k (k + 1) / 2 (packed triangles, no padding)
     int64_t sq_entries = 0;         // sum over sub-circuits of q^2 (dense port operators, no padding)
+    int64_t sqn_entries = 0;        // sum over sub-circuits of k^2 (port-node operators, no padding)
+    std::vector<int64_t> nofs;      // [S + 1] element offset of each k x k port-node operator
     bool uniform_W = true;          // one line admittance for every wire
 
     int32_t max_ports = 0;         // most ports on one sub-circuit

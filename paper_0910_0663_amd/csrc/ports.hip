@@ -10,6 +10,8 @@
 #include "kernels.hpp"
 #include "layout.hpp"
 
+#include <algorithm>
+
 #include <type_traits>
 
 namespace vtm {
@@ -135,7 +137,118 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// Port-node form for any A (the packed kernel below needs A symmetric): with
+// z = K^-1[N, N] t over the k port nodes N of a sub-circuit and
+// t_n = sum_{p at n} c_p a_p, the outgoing wave of port p is
+// o_p = beta_p z_n(p) + gamma_p a_p + h_p.  K^-1[N, N] (k x k, fewer than the
+// q x q entries of M when nodes carry several ports) is stored in the column-
+// group layout (n = k) at Sn + nofs[s].
+template <typename TO>
+__global__ void __launch_bounds__(kBlock)
+    k_port_node_dense(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs,
+                      const int32_t* __restrict__ pn_off, const int32_t* __restrict__ pn_node,
+                      const TO* __restrict__ K, const int64_t* __restrict__ nofs, TO* __restrict__ Sn) {
+    const int s = blockIdx.x;
+    const int ns = sub_off[s + 1] - sub_off[s];
+    const int k0 = pn_off[s], k = pn_off[s + 1] - k0;
+    const TO* Ks = K + kofs[s];
+    TO* out = Sn + nofs[s];
+    for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
+        const int r = t / k, c = t - r * k;
+        out[inv_offset<TO>(k, r, c)] = Ks[inv_offset<TO>(ns, pn_node[k0 + r], pn_node[k0 + c])];
+    }
+}
+
+// One workgroup per sub-circuit, one port node (row of K^-1[N, N]) per thread.
+template <typename TO, typename TV>
+__global__ void __launch_bounds__(512)
+    k_sweep_ppn(const TO* __restrict__ Sn, const int64_t* __restrict__ nofs, const int32_t* __restrict__ pn_off,
+                const int32_t* __restrict__ pn_pfirst, const int32_t* __restrict__ port_off,
+                const int32_t* __restrict__ port_twin, const TV* __restrict__ pc, const TV* __restrict__ pbeta,
+                const TV* __restrict__ pgamma, const TV* __restrict__ h, const TV* __restrict__ a_cur,
+                TV* __restrict__ a_next, int max_npn) {
+    constexpr int G = Group<TO>::G;
+    extern __shared__ char smem[];
+    TV* tv = reinterpret_cast<TV*>(smem);
+    TV* zv = tv + max_npn;
+    int32_t* pnode = reinterpret_cast<int32_t*>(zv + max_npn);
+    const int s = xcd_block(blockIdx.x, gridDim.x);
+    const int k0 = pn_off[s], k = pn_off[s + 1] - k0;
+    const int p0 = port_off[s], p1 = port_off[s + 1];
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const TO* Ss = Sn + nofs[s];
+    // t per port node, in port order
+    for (int j = tid; j < k; j += bs) {
+        const int f0 = pn_pfirst[k0 + j], f1 = pn_pfirst[k0 + j + 1];
+        TV acc = TV(0);
+        for (int p = f0; p < f1; ++p) {
+            acc += pc[p] * a_cur[p];
+            pnode[p - p0] = j;
+        }
+        tv[j] = acc;
+    }
+    __syncthreads();
+    // z = K^-1[N, N] t
+    const int ng = k / G, full = ng * G;
+    for (int row = tid; row < k; row += bs) {
+        TV acc[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) acc[j] = TV(0);
+#pragma unroll 4
+        for (int g = 0; g < ng; ++g) {
+            TO v[G];
+            load16p<TO>(Ss + (int64_t(g) * k + row) * G, v);
+#pragma unroll
+            for (int j = 0; j < G; ++j) acc[j] += TV(v[j]) * tv[g * G + j];
+        }
+        for (int c = full; c < k; ++c) acc[0] += TV(Ss[int64_t(full) * k + int64_t(c - full) * k + row]) * tv[c];
+        TV v = acc[0];
+#pragma unroll
+        for (int j = 1; j < G; ++j) v += acc[j];
+        zv[row] = v;
+    }
+    __syncthreads();
+    for (int p = p0 + tid; p < p1; p += bs)
+        a_next[port_twin[p]] = pbeta[p] * zv[pnode[p - p0]] + pgamma[p] * a_cur[p] + h[p];
+}
+
 }  // namespace
+
+template <typename TO>
+hipError_t launch_port_node_dense(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* pn_off,
+                                  const int32_t* pn_node, const TO* K, const int64_t* nofs, TO* Sn, hipStream_t st) {
+    hipLaunchKernelGGL(k_port_node_dense<TO>, dim3(S), dim3(kBlock), 0, st, sub_off, kofs, pn_off, pn_node, K, nofs,
+                       Sn);
+    return hipGetLastError();
+}
+
+template <typename TO, typename TV>
+hipError_t launch_sweep_ppn(int S, int max_npn, int max_ports, const TO* Sn, const int64_t* nofs,
+                            const int32_t* pn_off, const int32_t* pn_pfirst, const int32_t* port_off,
+                            const int32_t* port_twin, const TV* pc, const TV* pbeta, const TV* pgamma, const TV* h,
+                            const TV* a_cur, TV* a_next, hipStream_t st) {
+    const size_t lds = 2 * size_t(max_npn) * sizeof(TV) + size_t(max_ports) * 4;
+    if (lds > 65536) return hipErrorInvalidValue;
+    // one pass over the rows where possible
+    const int bs = std::min(512, std::max(64, ((max_npn + 63) / 64) * 64));
+    hipLaunchKernelGGL((k_sweep_ppn<TO, TV>), dim3(S), dim3(bs), lds, st, Sn, nofs, pn_off, pn_pfirst, port_off,
+                       port_twin, pc, pbeta, pgamma, h, a_cur, a_next, max_npn);
+    return hipGetLastError();
+}
+
+template hipError_t launch_port_node_dense<double>(int, const int32_t*, const int64_t*, const int32_t*,
+                                                   const int32_t*, const double*, const int64_t*, double*,
+                                                   hipStream_t);
+template hipError_t launch_port_node_dense<float>(int, const int32_t*, const int64_t*, const int32_t*,
+                                                  const int32_t*, const float*, const int64_t*, float*, hipStream_t);
+template hipError_t launch_sweep_ppn<double, double>(int, int, int, const double*, const int64_t*, const int32_t*,
+                                                     const int32_t*, const int32_t*, const int32_t*, const double*,
+                                                     const double*, const double*, const double*, const double*,
+                                                     double*, hipStream_t);
+template hipError_t launch_sweep_ppn<float, float>(int, int, int, const float*, const int64_t*, const int32_t*,
+                                                   const int32_t*, const int32_t*, const int32_t*, const float*,
+                                                   const float*, const float*, const float*, const float*, float*,
+                                                   hipStream_t);
 
 template <typename TO>
 hipError_t launch_port_matrix(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* port_off,

@@ -164,7 +164,55 @@ def mixed_and_batched(vtm, torch, oracle, workloads):
         "fp32_sweeps": r32.sweeps, "fp32_outer": r32.outer, "fp64_sweeps": r64.sweeps,
         "fp32_relres": rel32, "fp64_relres": rel64}
     log(f"cfg5: fp32 refine {t32:.2f} ms vs fp64 {t64:.2f} ms: x{t64 / t32:.2f}")
+    res["gradient"] = gradient_path(vtm, torch, oracle, workloads)
     return res
+
+
+def gradient_path(vtm, torch, oracle, workloads, reps=5):
+    """The IR-drop loss L = sum of x^2 over 4,096 probe nodes of the 512x512 grid:
+    forward solve, adjoint solve with g = dL/dx = 2 x at the probes, then
+    dL/dg_e = -(lambda_i - lambda_j)(x_i - x_j) for every branch; FP32 sweeps
+    with FP64 refinement to 1e-8, each stage timed on its own."""
+    w = workloads.make(5)
+    s = vtm.Solver(w.A, w.part, w.Z, precision="fp32_refine")
+    b = torch.as_tensor(w.b, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(b)
+    lam = torch.empty_like(b)
+    ij = torch.as_tensor(w.edges, dtype=torch.int32, device="cuda")
+    probes = torch.as_tensor(w.probes, dtype=torch.int64, device="cuda")
+    t = {"forward": 0.0, "adjoint": 0.0, "grad": 0.0}
+    for k in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.solve(b, w.tol, x)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = torch.zeros_like(x)
+        g[0, probes] = 2.0 * x[0, probes]
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        s.solve_adjoint(g, w.tol, lam)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        dg = s.grad(x, lam, ij)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        if k:  # the first pass is a warm-up
+            t["forward"] += (t1 - t0) / reps
+            t["adjoint"] += (t3 - t2) / reps
+            t["grad"] += (t4 - t3) / reps
+    s.close()
+    rel_f = float(oracle.relative_residual(w.A, w.b, x.cpu().numpy()).max())
+    rel_a = float(oracle.relative_residual(w.A.T.tocsr(), g.cpu().numpy(), lam.cpu().numpy()).max())
+    assert rel_f <= w.tol and rel_a <= w.tol and bool(torch.isfinite(dg).all()), (rel_f, rel_a)
+    out = {"workload": f"512x512 grid, 1,024 sub-circuits of 16x16, loss over {w.probes.size} probes, "
+                       f"{ij.shape[0]:,} branches; FP32 sweeps + FP64 refinement to 1e-8",
+           "forward_ms": round(t["forward"] * 1e3, 3), "adjoint_ms": round(t["adjoint"] * 1e3, 3),
+           "grad_ms": round(t["grad"] * 1e3, 3),
+           "total_ms": round(sum(t.values()) * 1e3, 3), "forward_relres": rel_f, "adjoint_relres": rel_a}
+    log(f"cfg5 gradient: forward {out['forward_ms']} ms, adjoint {out['adjoint_ms']} ms, "
+        f"dL/dg {out['grad_ms']} ms")
+    return out
 
 
 def main():

@@ -87,24 +87,26 @@ typedef struct {
                                per pass, 3 or 5; 0 = chosen by the autotuner at setup */
     int32_t batch_rhs_block;/* batched sweep: right-hand sides per workgroup, 16, 32,
                                48 or 64; 0 = chosen by the autotuner at setup        */
-    int32_t local_form;     /* 0: every sweep applies the full local inverse;
+    int32_t local_form;     /* 0: every sweep applies the full local inverse.
                                1: port-to-port form (the interface-only iteration of
-                               the Appendix, eqs. 23-26): a sweep streams only the
-                               q x q operator between a sub-circuit's ports,
-                               M = diag(beta) K^-1[ports, ports] diag(c) + diag(gamma),
-                               plus h = beta K^-1 b; a full sweep remains for the
-                               first sweep of a solve.  Residual checks then use the
-                               port quantities alone (a local solve meets every
-                               interior row, so b - A x lives on the port nodes);
-                               once that residual passes, and at the end, x is
-                               rebuilt by a full sweep from the same waves and the
-                               residual on A decides.  Used for one right-hand side, FP64 or FP32,
-                               forward (and adjoint when A is symmetric), not on
-                               resume; otherwise the full form runs.  When A is
-                               symmetric the operator is stored once per port node
-                               pair as the packed upper triangle of K^-1 (half the
-                               bytes; beta and gamma formed from c on the fly);
-                               2: the same with the dense q x q operator M always. */
+                               the Appendix, eqs. 23-26): the waves leaving a
+                               sub-circuit are an affine function of those arriving,
+                               with h = beta K^-1 b at the ports from a first full
+                               sweep, so later sweeps stream only an operator between
+                               ports.  The smallest that applies is used: the upper
+                               triangle of K^-1 over the port nodes, packed (A
+                               symmetric, <= 64 port nodes and ports per sub-circuit);
+                               K^-1 over the port nodes (k x k, when smaller than
+                               q x q; the adjoint of an unsymmetric A uses its
+                               transpose); else M = diag(beta) K^-1[ports, ports]
+                               diag(c) + diag(gamma).  Handles with MFMA tiles use M in
+                               tile order for all right-hand sides.  Residual checks
+                               use the port quantities alone (a local solve meets
+                               every interior row, so b - A x lives on the port
+                               nodes); once that residual passes, and at the end, x
+                               is rebuilt by a full sweep from the same waves and the
+                               residual on A decides.  Resumed solves run the full
+                               form.  2: as 1 with M always.                        */
 } vtm_options;
 
 typedef struct {

@@ -86,8 +86,8 @@ struct vtm_handle_s {
     // any A: K^-1 over the port nodes (k x k) when that is smaller than M
     bool ppn = false;
     DevBuf<int64_t> nofs;
-    DevBuf<double> N64;
-    DevBuf<float> N32;
+    DevBuf<double> N64, N64T;  // T: transposed, for the adjoint of an unsymmetric A
+    DevBuf<float> N32, N32T;
     DevBuf<int32_t> pn_off, pn_node, pn_pfirst;
     // residual checks from port quantities (port-to-port form): g and G - g per port
     DevBuf<double> pg64, pgd64;
@@ -291,12 +291,14 @@ vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
     } else if (pp && h->ppn) {
         const vtm::Plan& P = h->plan;
         if (!low)
-            VTM_HIP((vtm::launch_sweep_ppn<double, double>(int(P.S), P.max_npn, P.max_ports, h->N64.p, h->nofs.p,
+            VTM_HIP((vtm::launch_sweep_ppn<double, double>(int(P.S), P.max_npn, P.max_ports,
+                                                           adjoint && !P.symmetric ? h->N64T.p : h->N64.p, h->nofs.p,
                                                            h->pn_off.p, h->pn_pfirst.p, h->port_off.p, h->port_twin.p,
                                                            h->c64.p, h->beta64.p, h->gamma64.p, h->h64.p,
                                                            h->a64[cur].p, h->a64[cur ^ 1].p, h->stream)));
         else
-            VTM_HIP((vtm::launch_sweep_ppn<float, float>(int(P.S), P.max_npn, P.max_ports, h->N32.p, h->nofs.p,
+            VTM_HIP((vtm::launch_sweep_ppn<float, float>(int(P.S), P.max_npn, P.max_ports,
+                                                         adjoint && !P.symmetric ? h->N32T.p : h->N32.p, h->nofs.p,
                                                          h->pn_off.p, h->pn_pfirst.p, h->port_off.p, h->port_twin.p,
                                                          h->c32.p, h->beta32.p, h->gamma32.p, h->h32.p,
                                                          h->a32[cur].p, h->a32[cur ^ 1].p, h->stream)));
@@ -577,7 +579,7 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
     if (!resume) cad.record(0, max_of(out.rel));
     std::vector<double> bb(nrhs);  // ||b||^2 per right-hand side, for the port-residual checks
     for (int r = 0; r < nrhs; ++r) bb[r] = h->h_norms[2 * r + 1];
-    const bool pp = ((h->pp && nrhs == 1) || h->ppb) && (!adjoint || P.symmetric) && !resume;
+    const bool pp = ((h->pp && nrhs == 1) || h->ppb) && (!adjoint || P.symmetric || h->ppn) && !resume;
     // port-to-port sweeps check the residual from port quantities; once it passes
     // (and at the end), x^k is rebuilt by a full sweep from the same waves and
     // the residual on A decides
@@ -632,7 +634,7 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
     if (!(drop > 0.0)) drop = h->opt.precision == VTM_BF16_REFINE ? 1e-2 : 1e-5;
     VTM_HIP(vtm::launch_fill<double>(nv, 0.0, h->xp.p, h->stream));
     std::vector<double> rel, e, target(nrhs);
-    const bool pp = ((h->pp && nrhs == 1) || h->ppb) && (!adjoint || P.symmetric);
+    const bool pp = ((h->pp && nrhs == 1) || h->ppb) && (!adjoint || P.symmetric || h->ppn);
     auto all_le = [](const std::vector<double>& v, const std::vector<double>& t) {
         for (size_t i = 0; i < v.size(); ++i)
             if (!(v[i] <= t[i])) return false;
@@ -978,12 +980,22 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
             VTM_HIP(h->N64.alloc(nn));
             VTM_HIP(h->h64.alloc(P.nports));
             VTM_HIP(vtm::launch_port_node_dense<double>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p, h->pn_node.p,
-                                                        h->K64.p, h->nofs.p, h->N64.p, s));
+                                                        h->K64.p, h->nofs.p, h->N64.p, false, s));
+            if (!P.symmetric) {
+                VTM_HIP(h->N64T.alloc(nn));
+                VTM_HIP(vtm::launch_port_node_dense<double>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p,
+                                                            h->pn_node.p, h->K64.p, h->nofs.p, h->N64T.p, true, s));
+            }
         } else {
             VTM_HIP(h->N32.alloc(nn));
             VTM_HIP(h->h32.alloc(P.nports));
             VTM_HIP(vtm::launch_port_node_dense<float>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p, h->pn_node.p,
-                                                       h->K32.p, h->nofs.p, h->N32.p, s));
+                                                       h->K32.p, h->nofs.p, h->N32.p, false, s));
+            if (!P.symmetric) {
+                VTM_HIP(h->N32T.alloc(nn));
+                VTM_HIP(vtm::launch_port_node_dense<float>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p,
+                                                           h->pn_node.p, h->K32.p, h->nofs.p, h->N32T.p, true, s));
+            }
         }
         VTM_HIP(hipStreamSynchronize(s));
     } else if (h->pps) {

@@ -107,10 +107,12 @@ hipError_t launch_sweep_pp(int S, int max_q, const TO* M, const int64_t* pofs, c
                            const int32_t* port_twin, const TV* h, const TV* a_cur, TV* a_next, hipStream_t st);
 
 // Port-node form for any A: K^-1[N, N] over a sub-circuit's k port nodes in the
-// column-group layout (n = k) at Sn + nofs[s] ...
+// column-group layout (n = k) at Sn + nofs[s] (transpose: K^-T[N, N], for the
+// adjoint of an unsymmetric A) ...
 template <typename TO>
 hipError_t launch_port_node_dense(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* pn_off,
-                                  const int32_t* pn_node, const TO* K, const int64_t* nofs, TO* Sn, hipStream_t st);
+                                  const int32_t* pn_node, const TO* K, const int64_t* nofs, TO* Sn, bool transpose,
+                                  hipStream_t st);
 // ... and its sweep: t_n = sum_{p at n} c_p a_p, z = K^-1[N, N] t,
 // a_next[twin(p)] = beta_p z_n(p) + gamma_p a_p + h_p (LDS 2 max_npn values +
 // 4 max_ports bytes, at most 64 KiB, else hipErrorInvalidValue).

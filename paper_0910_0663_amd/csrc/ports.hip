@@ -147,7 +147,8 @@ template <typename TO>
 __global__ void __launch_bounds__(kBlock)
     k_port_node_dense(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs,
                       const int32_t* __restrict__ pn_off, const int32_t* __restrict__ pn_node,
-                      const TO* __restrict__ K, const int64_t* __restrict__ nofs, TO* __restrict__ Sn) {
+                      const TO* __restrict__ K, const int64_t* __restrict__ nofs, TO* __restrict__ Sn,
+                      int transpose) {
     const int s = blockIdx.x;
     const int ns = sub_off[s + 1] - sub_off[s];
     const int k0 = pn_off[s], k = pn_off[s + 1] - k0;
@@ -155,7 +156,8 @@ __global__ void __launch_bounds__(kBlock)
     TO* out = Sn + nofs[s];
     for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
         const int r = t / k, c = t - r * k;
-        out[inv_offset<TO>(k, r, c)] = Ks[inv_offset<TO>(ns, pn_node[k0 + r], pn_node[k0 + c])];
+        const int i = pn_node[k0 + (transpose ? c : r)], j = pn_node[k0 + (transpose ? r : c)];
+        out[inv_offset<TO>(k, r, c)] = Ks[inv_offset<TO>(ns, i, j)];
     }
 }
 
@@ -216,9 +218,10 @@ __global__ void __launch_bounds__(512)
 
 template <typename TO>
 hipError_t launch_port_node_dense(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* pn_off,
-                                  const int32_t* pn_node, const TO* K, const int64_t* nofs, TO* Sn, hipStream_t st) {
+                                  const int32_t* pn_node, const TO* K, const int64_t* nofs, TO* Sn, bool transpose,
+                                  hipStream_t st) {
     hipLaunchKernelGGL(k_port_node_dense<TO>, dim3(S), dim3(kBlock), 0, st, sub_off, kofs, pn_off, pn_node, K, nofs,
-                       Sn);
+                       Sn, transpose ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -237,10 +240,11 @@ hipError_t launch_sweep_ppn(int S, int max_npn, int max_ports, const TO* Sn, con
 }
 
 template hipError_t launch_port_node_dense<double>(int, const int32_t*, const int64_t*, const int32_t*,
-                                                   const int32_t*, const double*, const int64_t*, double*,
+                                                   const int32_t*, const double*, const int64_t*, double*, bool,
                                                    hipStream_t);
 template hipError_t launch_port_node_dense<float>(int, const int32_t*, const int64_t*, const int32_t*,
-                                                  const int32_t*, const float*, const int64_t*, float*, hipStream_t);
+                                                  const int32_t*, const float*, const int64_t*, float*, bool,
+                                                  hipStream_t);
 template hipError_t launch_sweep_ppn<double, double>(int, int, int, const double*, const int64_t*, const int32_t*,
                                                      const int32_t*, const int32_t*, const int32_t*, const double*,
                                                      const double*, const double*, const double*, const double*,

@@ -232,7 +232,10 @@ def test_adjoint_matches_oracle_on_unsymmetric_circuit(torch):
     ks = [1, 3, 25]
     ref = oracle_iterates(w, ks, b=g, transpose=True)
     for k in ks:
+        # port-node sweeps on the transposed operator, checked every sweep or only at k; full sweeps
         assert_close(gpu_iterate(torch, w, k, b=g, adjoint=True), ref[k])
+        assert_close(gpu_iterate(torch, w, k, b=g, adjoint=True, check_every=k), ref[k])
+        assert_close(gpu_iterate(torch, w, k, b=g, adjoint=True, local_form="full"), ref[k])
     s = vtm().Solver(w.A, w.part, w.Z)
     lam, rep = s.solve_adjoint(to_dev(torch, g), 1e-11)
     lam_ref = oracle.direct_adjoint(w.A, g)

@@ -125,6 +125,40 @@ def test_port_to_port_and_full_forms_agree(torch):
     assert_close(xd, xf)
 
 
+def _with_isolated_component(nrhs):
+    """A 32x32 grid cut into 4x4 sub-circuits of 8x8, plus a separate 8x8 grid
+    that forms one sub-circuit with no cut wire (k = q = 0 ports), 17 sub-circuits
+    in all (an odd count leaves the last pair of the packed sweep half empty)."""
+    import types
+    rng = np.random.default_rng(11)
+    e1 = workloads.grid2d_edges(32, 32)
+    e2 = workloads.grid2d_edges(8, 8) + 32 * 32
+    edges = np.concatenate([e1, e2])
+    n = 32 * 32 + 64
+    g = rng.uniform(0.5, 2.0, size=edges.shape[0])
+    A = workloads.nodal_matrix(n, edges, g, np.full(n, workloads.GROUND_S))
+    part = np.concatenate([workloads.block_partition_2d(32, 32, 8, 8), np.full(64, 16)]).astype(np.int32)
+    b = rng.standard_normal((nrhs, n))
+    return types.SimpleNamespace(A=A, b=b, part=part, Z=1.0 / g.mean(), n=n, tol=1e-10)
+
+
+@pytest.mark.parametrize("nrhs", [1, 20])
+def test_sub_circuit_without_ports_in_every_form(torch, nrhs):
+    """A sub-circuit with no cut wire next to ordinary ones: every local form
+    (packed, port-node, port operator, full; MFMA tiles for 20 right-hand sides)
+    gives the oracle's iterates, and the solve reaches its tolerance."""
+    w = _with_isolated_component(nrhs)
+    ks = [1, 2, 7]
+    ref = oracle_iterates(w, ks)
+    for form in ("port", "port_dense", "full"):
+        for k in ks:
+            assert_close(gpu_iterate(torch, w, k, check_every=k, local_form=form), ref[k])
+    s = vtm().Solver(w.A, w.part, w.Z, nrhs_max=nrhs)
+    x, rep = s.solve(to_dev(torch, w.b), w.tol)
+    assert oracle.relative_residual(w.A, w.b, x.cpu().numpy()).max() <= w.tol
+    s.close()
+
+
 def test_config1_sweeps_and_solution(torch):
     """64x64 grid, 4x4 sub-circuits of 16x16, tol 1e-10, residual checked every
     sweep: the same sweep count as the oracle (within one for rounding at the

@@ -15,4 +15,5 @@ from .grids import (  # noqa: F401
     block_partition_2d,
     block_partition_3d,
     random_cut_widths,
+    GROUND_S,
 )

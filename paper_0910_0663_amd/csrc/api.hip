@@ -884,7 +884,15 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     VTM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
     h->lds_limit = size_t(lds > 0 ? lds : 65536);
     // batched form: MFMA tiles for BF16, and for FP64 handles sized for 16+ right-hand sides
-    h->tiles = o.precision == VTM_BF16_REFINE || (o.precision == VTM_FP64 && nr >= 16);
+    // when a 16-column block of the largest sub-circuit fits the LDS staging of the batched
+    // sweep (else FP64 keeps the column-group layout; BF16 has no other form)
+    const int npad = vtm::tile_pad(P.max_ns);
+    const size_t mfma_extra = size_t(P.max_ports) * 4 + size_t(npad) * 3 + 4;
+    const bool fits64 = vtm::tile_lds_bytes<double>(npad, 16) + mfma_extra <= h->lds_limit;
+    const bool fits16 = vtm::tile_lds_bytes<__bf16>(npad, 16) + mfma_extra <= h->lds_limit;
+    if (o.precision == VTM_BF16_REFINE && !fits16)
+        return fail(VTM_E_UNSUPPORTED, "BF16 path: a sub-circuit is too large for the batched sweep's LDS staging");
+    h->tiles = o.precision == VTM_BF16_REFINE || (o.precision == VTM_FP64 && nr >= 16 && fits64);
     if (h->tiles) {
         if (nr > 64 && o.precision == VTM_BF16_REFINE) return fail(VTM_E_UNSUPPORTED, "BF16 path takes at most 64 RHS");
         VTM_HIP(h->mofs.upload(P.mofs, s));

@@ -159,6 +159,37 @@ def test_sub_circuit_without_ports_in_every_form(torch, nrhs):
     s.close()
 
 
+def test_singular_sub_circuit_is_reported(torch):
+    """A node with no branch and no ground, alone in its sub-circuit, makes that
+    sub-circuit's matrix singular: setup fails with VTM_E_SINGULAR, for FP64 and
+    for the batched (MFMA tile) setup alike."""
+    base = workloads.make(1, dims=(16, 16), block=(8, 8))
+    n = base.n + 1
+    A = sp.bmat([[base.A, None], [None, sp.csr_matrix((1, 1))]], format="csr")
+    part = np.concatenate([base.part, [base.n_sub]]).astype(np.int32)
+    for kw in (dict(), dict(nrhs_max=16), dict(precision="fp32_refine")):
+        with pytest.raises(vtm().VTMError) as ei:
+            vtm().Solver(A, part, base.Z, **kw)
+        assert ei.value.name == "VTM_E_SINGULAR", kw
+    assert n == A.shape[0]
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(nrhs=16)])
+def test_largest_sub_circuits(torch, kw):
+    """Two sub-circuits of 2,048 nodes (the largest a handle takes, inverted in
+    blocked global-memory Gauss-Jordan): iterates equal the oracle's in the
+    port (64 port nodes, one sub-circuit per wavefront) and full forms; with 16
+    right-hand sides the FP64 handle keeps the column-group layout because a
+    2,048-row block does not fit the batched sweep's LDS staging."""
+    w = workloads.make(1, dims=(64, 64), block=(64, 32), **kw)
+    assert w.n_sub == 2 and np.bincount(w.part).max() == 2048
+    ks = [3]  # each handle inverts two 2,048 x 2,048 blocks on two CUs: keep the handles few
+    ref = oracle_iterates(w, ks)
+    for form in ("port", "full"):
+        for k in ks:
+            assert_close(gpu_iterate(torch, w, k, check_every=k, local_form=form), ref[k])
+
+
 def test_config1_sweeps_and_solution(torch):
     """64x64 grid, 4x4 sub-circuits of 16x16, tol 1e-10, residual checked every
     sweep: the same sweep count as the oracle (within one for rounding at the

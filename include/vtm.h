@@ -66,7 +66,14 @@ typedef struct {
 
 typedef struct {
     int32_t precision;      /* vtm_precision                                         */
-    int32_t nrhs_max;       /* widest solve this handle will run (sizes work space)  */
+    int32_t nrhs_max;       /* widest solve this handle will run (sizes work space).
+                               FP64 handles with nrhs_max >= 16 store the inverses
+                               as MFMA tiles (batched sweeps) when a 16-column block
+                               of the largest sub-circuit fits the sweep's LDS
+                               staging (up to ~1,100 nodes), else the column-group
+                               layout; BF16 handles always use tiles (at most 64
+                               right-hand sides, VTM_E_UNSUPPORTED when the
+                               largest sub-circuit does not fit)                 */
     int32_t check_every;    /* sweeps between FP64 residual checks (>= 1)            */
     int32_t max_outer;      /* refinement: most outer corrections                    */
     int64_t max_sweeps;     /* per plain solve, or per inner solve when refining     */
@@ -149,8 +156,10 @@ void vtm_default_options(vtm_options *opt);
  * Every pair (i, j) in different sub-circuits with a nonzero entry must have
  * A_ij == A_ji < 0 (a two-terminal conductance g = -A_ij), else
  * VTM_E_UNTEARABLE.  Sub-circuits may not exceed 2048 nodes
- * (VTM_E_UNSUPPORTED).  n and nnz must fit int32.  Returns after the setup
- * kernels finish.
+ * (VTM_E_UNSUPPORTED).  n and nnz must fit int32.  A sub-circuit matrix
+ * (with its port conductances) whose elimination meets an exactly zero or
+ * non-finite pivot gives VTM_E_SINGULAR.  Returns after the setup kernels
+ * finish.
  */
 vtm_status vtm_setup(const vtm_csr *A, const int32_t *part, const double *Z, int64_t nZ,
                      const vtm_options *opt, void *stream, vtm_handle *out);

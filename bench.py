@@ -82,6 +82,25 @@ def cpu_baseline(seconds):
                       f"single-threaded SuperLU and scipy.sparse"}
 
 
+def measured_read_peak(torch, gib=4, reps=5):
+    """Streaming-read bandwidth of this GPU's HBM, measured here: a sum over a
+    4 GiB buffer (one read of every byte, a negligible write), best of reps."""
+    buf = torch.ones((gib << 30) // 8, dtype=torch.float64, device="cuda")
+    buf.sum()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        buf.sum()
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del buf
+    torch.cuda.empty_cache()
+    return (gib << 30) / best / 1e9
+
+
 def timed_solve(vtm, torch, w, precision, nrhs_max, reps=2):
     """Setup (untimed here), one warm solve, then the mean of `reps` solves."""
     s = vtm.Solver(w.A, w.part, w.Z, precision=precision, nrhs_max=nrhs_max)
@@ -303,6 +322,8 @@ def main():
         per_launch, avg_launch_s, kernel, n_timed = full_bytes, full_s, roof_full["kernel"], launches
     achieved = per_launch / avg_launch_s / 1e9
     traffic = measured_traffic(per_launch)
+    read_peak = measured_read_peak(torch)
+    roof_full["frac_of_measured_read"] = round(roof_full["achieved"] / read_peak, 4)
     out = {
         "metric": METRIC,
         "value": round(sweeps / elapsed, 2),
@@ -343,6 +364,8 @@ def main():
             "bytes_per_launch": per_launch,
             "avg_launch_us": round(avg_launch_s * 1e6, 2),
             "launches_timed": n_timed,
+            "read_peak_measured": round(read_peak, 1),
+            "frac_of_measured_read": round(achieved / read_peak, 4),
         },
         "roofline_full_sweep": roof_full,
     }

@@ -269,7 +269,9 @@ def main():
     log(f"workload {w.name}: n={w.n} sub-circuits={w.n_sub} ({time.perf_counter() - t:.1f} s to generate)")
     torch.cuda.synchronize()
     t = time.perf_counter()
-    s = vtm.Solver(w.A, w.part, w.Z, check_every=args.check_every, timing=True)
+    # timing 2: one HIP event pair per run of port-to-port sweeps (events around every
+    # launch would slow the timed solve itself)
+    s = vtm.Solver(w.A, w.part, w.Z, check_every=args.check_every, timing=2)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t
     log(f"setup {setup_s:.2f} s: wires={s.n_wires} inverse bytes={s.inverse_bytes}")

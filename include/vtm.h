@@ -84,8 +84,12 @@ typedef struct {
                                and the copy of its sums to the host) is captured once
                                per shape and replayed as one hipGraph launch; check
                                intervals are then check_every times a power of two */
-    int32_t timing;         /* 1: time every sweep launch with HIP events (report;
-                               not available with use_graph)                         */
+    int32_t timing;         /* 1: HIP events around every sweep launch (report);
+                               2: events around full sweeps and around each run of
+                               consecutive port-to-port sweeps (their average then
+                               includes the gaps between launches; the events
+                               themselves perturb the run far less than 1 does).
+                               Not available with use_graph.                      */
     int32_t adaptive_checks;/* 1: once the residual falls steadily, skip checks that
                                cannot reach tol: the next check comes after half the
                                predicted remaining sweeps (a multiple of check_every,
@@ -232,6 +236,33 @@ vtm_status vtm_info(vtm_handle h, int64_t *n, int64_t *n_sub, int64_t *n_wires,
 void vtm_destroy(vtm_handle h);
 const char *vtm_status_str(vtm_status s);
 const char *vtm_last_error(void);
+
+/* Line admittance rules for vtm_line_admittance (the preconditioners of
+ * Section VIII).  With wire tearing each cut wire's interfacial node is its
+ * midpoint m (a branch g becomes 2g + 2g through m); the two twins of m are
+ * not coupled to any other interface node, so the interface block C of either
+ * side is diagonal with the twin's 2g, and every rule below gives one W per
+ * wire.  The coupled Schur-complement approximation (rule 5 of Section VIII)
+ * is not provided. */
+typedef enum {
+    VTM_W_SCALED_MEAN = 0,  /* W_e = alpha * mean conductance of A's branches      */
+    VTM_W_IDENTITY = 1,     /* W = alpha I (rule 1), alpha in siemens               */
+    VTM_W_OB = 2,           /* W = C, the overlapped block (rule 3): W_e = 2 g_e;
+                               the diagonal rule (2) gives the same here          */
+    VTM_W_WOB = 3           /* W = alpha C, weighted overlapped block (rule 4)       */
+} vtm_admittance_rule;
+
+/*
+ * vtm_line_admittance -- host-only: the characteristic admittance W_e of every
+ * cut wire of the partition under one of the rules of Section VIII, in the
+ * canonical wire order of vtm_setup (pass Z_e = 1 / W_e with nZ = n_wires).
+ * A and part as for vtm_setup (host); W: host double[n_wires], caller-owned;
+ * n_wires must equal the partition's cut-wire count (vtm_plan).  "Branches"
+ * of A are its symmetric negative off-diagonal pairs.  Errors: VTM_E_ARG (bad
+ * rule, alpha <= 0, count mismatch), the vtm_setup tearing errors.
+ */
+vtm_status vtm_line_admittance(const vtm_csr *A, const int32_t *part, int32_t kind, double alpha, double *W,
+                               int64_t n_wires);
 
 /*
  * vtm_plan -- host-only tearing plan (no device work), for inspection and tests.

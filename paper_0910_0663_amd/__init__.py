@@ -8,12 +8,13 @@ from .binding import (  # noqa: F401
     SolveReport,
     VTMError,
     plan,
+    line_admittance,
     lib,
     LIB_PATH,
     EXPORTS,
 )
 
-__all__ = ["Solver", "SolveReport", "VTMError", "plan", "lib", "LIB_PATH", "EXPORTS", "VTMSolve", "Circuit"]
+__all__ = ["Solver", "SolveReport", "VTMError", "plan", "line_admittance", "lib", "LIB_PATH", "EXPORTS", "VTMSolve", "Circuit"]
 
 
 def __getattr__(name):

@@ -24,7 +24,7 @@ STATUS = ["VTM_OK", "VTM_E_ARG", "VTM_E_UNTEARABLE", "VTM_E_SINGULAR", "VTM_E_DI
 
 EXPORTS = ["vtm_default_options", "vtm_setup", "vtm_solve", "vtm_solve_adjoint", "vtm_grad",
            "vtm_get_waves", "vtm_set_waves", "vtm_info", "vtm_destroy", "vtm_status_str",
-           "vtm_last_error", "vtm_plan"]
+           "vtm_last_error", "vtm_plan", "vtm_line_admittance"]
 
 
 class VTMError(RuntimeError):
@@ -94,6 +94,8 @@ def lib() -> C.CDLL:
     L.vtm_plan.argtypes = [C.POINTER(Csr), C.POINTER(C.c_int32), dp, i64, C.POINTER(i64), C.POINTER(i64),
                            C.POINTER(C.c_int32), dp]
     L.vtm_plan.restype = C.c_int
+    L.vtm_line_admittance.argtypes = [C.POINTER(Csr), C.POINTER(C.c_int32), C.c_int32, C.c_double, dp, i64]
+    L.vtm_line_admittance.restype = C.c_int
     _lib = L
     return L
 
@@ -142,6 +144,23 @@ def plan(A, part, Z) -> dict:
                 gamma=coef[:, 3])
 
 
+ADMITTANCE_RULES = {"scaled_mean": 0, "identity": 1, "ob": 2, "wob": 3}
+
+
+def line_admittance(A, part, rule="scaled_mean", alpha=1.0):
+    """Characteristic admittance of every cut wire under a rule of Section VIII
+    (vtm_line_admittance), in the canonical wire order; pass Z = 1 / W."""
+    L = lib()
+    hc = _HostCsr(A)
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    pp = part.ctypes.data_as(C.POINTER(C.c_int32))
+    nw = plan(A, part, 1.0)["wires"].shape[0]
+    W = np.zeros(nw, dtype=np.float64)
+    _check(L.vtm_line_admittance(C.byref(hc.s), pp, ADMITTANCE_RULES[rule], float(alpha),
+                                 W.ctypes.data_as(C.POINTER(C.c_double)), nw))
+    return W
+
+
 @dataclass
 class SolveReport:
     sweeps: int
@@ -186,7 +205,7 @@ class Solver:
         opt.inner_drop = float(inner_drop)
         opt.max_outer = int(max_outer)
         opt.use_graph = 1 if use_graph else 0
-        opt.timing = 1 if timing else 0
+        opt.timing = int(timing) if isinstance(timing, int) and not isinstance(timing, bool) else (1 if timing else 0)
         opt.adaptive_checks = 1 if adaptive_checks else 0
         opt.batch_row_tiles, opt.batch_rhs_block = int(batch_shape[0]), int(batch_shape[1])
         opt.local_form = {"full": 0, "port": 1, "port_dense": 2}[local_form] if isinstance(local_form, str) else int(local_form)

@@ -114,7 +114,8 @@ struct vtm_handle_s {
     bool waves_set = false;               // next solve resumes from the stored waves
     // per-launch timing of the sweep kernel (opt.timing)
     std::vector<hipEvent_t> ev;
-    std::vector<char> ev_tag;             // per event pair: 0 full sweep, 1 port-to-port sweep
+    std::vector<char> ev_tag;             // per event pair: 0 full sweep, 1 port-to-port sweep(s)
+    std::vector<int> ev_count;            // per event pair: launches it brackets
     size_t ev_used = 0;
     // captured check intervals (opt.use_graph), keyed by everything their launches depend on
     std::map<std::array<int, 6>, hipGraphExec_t> graphs;
@@ -209,8 +210,10 @@ vtm_status timing_event(vtm_handle h, hipEvent_t* out, char tag) {
         VTM_HIP(hipEventCreate(&e));
         h->ev.push_back(e);
         h->ev_tag.push_back(0);
+        h->ev_count.push_back(1);
     }
     h->ev_tag[h->ev_used] = tag;
+    h->ev_count[h->ev_used] = 1;
     *out = h->ev[h->ev_used++];
     VTM_HIP(hipEventRecord(*out, h->stream));
     return VTM_OK;
@@ -224,10 +227,10 @@ vtm_status timing_collect(vtm_handle h, IterOut& out) {
         VTM_HIP(hipEventElapsedTime(&t, h->ev[k], h->ev[k + 1]));
         if (h->ev_tag[k]) {
             out.pp_ms += t;
-            ++out.pp_launches;
+            out.pp_launches += h->ev_count[k];
         } else {
             out.sweep_ms += t;
-            ++out.launches;
+            out.launches += h->ev_count[k];
         }
     }
     h->ev_used = 0;
@@ -274,7 +277,9 @@ vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
                       bool write_x, bool pp = false) {
     hipEvent_t e0, e1;
     vtm_status st;
-    const bool timed = h->opt.timing && !h->capturing;
+    // timing 1: events around every launch; 2: only full sweeps here (runs of
+    // port-to-port sweeps get one pair in run_chunk)
+    const bool timed = !h->capturing && (h->opt.timing == 1 || (h->opt.timing == 2 && !pp));
     if (timed && (st = timing_event(h, &e0, pp ? 1 : 0)) != VTM_OK) return st;
     if (pp && h->tiles) {
         const vtm::Plan& P = h->plan;
@@ -449,11 +454,34 @@ vtm_status run_chunk(vtm_handle h, bool low, int nrhs, bool adjoint, int64_t chu
                         : static_cast<const void*>(h->bp.p);
     void* x = low ? static_cast<void*>(h->d32.p) : static_cast<void*>(h->xp.p);
     auto enqueue = [&]() -> vtm_status {
+        const bool bracket = h->opt.timing == 2 && !h->capturing;
+        hipEvent_t r0 = nullptr, r1 = nullptr;
+        size_t r0_slot = 0;
+        int run = 0;  // port-to-port sweeps since r0
+        auto close_run = [&]() -> vtm_status {
+            if (run == 0) return VTM_OK;
+            vtm_status st = timing_event(h, &r1, 1);
+            if (st != VTM_OK) return st;
+            h->ev_count[r0_slot] = run;
+            run = 0;
+            return VTM_OK;
+        };
         for (int64_t k = 0; k < chunk; ++k) {
             const bool full = !pp || (k + 1 == chunk && !iface) || (first && k == 0);
-            vtm_status st = sweep_once(h, low, nrhs, b, x, (cur + int(k)) & 1, adjoint, k + 1 == chunk, !full);
+            vtm_status st;
+            if (bracket && full && (st = close_run()) != VTM_OK) return st;
+            if (bracket && !full && run == 0) {
+                r0_slot = h->ev_used;
+                if ((st = timing_event(h, &r0, 1)) != VTM_OK) return st;
+            }
+            st = sweep_once(h, low, nrhs, b, x, (cur + int(k)) & 1, adjoint, k + 1 == chunk, !full);
             if (st != VTM_OK) return st;
+            if (!full) ++run;
             if (pp && first && k == 0 && (st = port_h(h, low, nrhs)) != VTM_OK) return st;
+        }
+        if (bracket) {
+            vtm_status st = close_run();
+            if (st != VTM_OK) return st;
         }
         if (iface) return port_residual_launch(h, low, (cur + int(chunk) - 1) & 1, nrhs);
         return low ? residual_launch<float>(h, h->rp.p, h->d32.p, nrhs, nullptr, adjoint)
@@ -820,6 +848,50 @@ vtm_status vtm_plan(const vtm_csr* A, const int32_t* part, const double* Z, int6
     return VTM_OK;
 }
 
+vtm_status vtm_line_admittance(const vtm_csr* A, const int32_t* part, int32_t kind, double alpha, double* W,
+                               int64_t n_wires) {
+    if (!W) return fail(VTM_E_ARG, "null output");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(VTM_E_ARG, "alpha must be positive");
+    if (kind < VTM_W_SCALED_MEAN || kind > VTM_W_WOB) return fail(VTM_E_ARG, "unknown admittance rule");
+    vtm::Plan P;
+    std::string err;
+    const double one = 1.0;
+    vtm_status st = vtm::build_plan(A, part, &one, 1, P, err);
+    if (st != VTM_OK) return fail(st, err);
+    if (n_wires != P.nwires) return fail(VTM_E_ARG, "n_wires does not match the partition's cut wires");
+    double mean = 0.0;
+    if (kind == VTM_W_SCALED_MEAN) {
+        // every two-terminal branch of A: a symmetric negative off-diagonal pair, counted once
+        double sum = 0.0;
+        int64_t cnt = 0;
+        for (int64_t i = 0; i < A->n; ++i)
+            for (int64_t q = A->rowptr[i]; q < A->rowptr[i + 1]; ++q) {
+                const int64_t j = A->col[q];
+                const double v = A->val[q];
+                if (j <= i || !(v < 0.0)) continue;
+                double vt = 0.0;
+                for (int64_t r = A->rowptr[j]; r < A->rowptr[j + 1]; ++r)
+                    if (A->col[r] == i) vt += A->val[r];
+                if (vt == v) {
+                    sum += -v;
+                    ++cnt;
+                }
+            }
+        if (cnt == 0) return fail(VTM_E_ARG, "A has no two-terminal branch");
+        mean = sum / double(cnt);
+    }
+    for (int64_t e = 0; e < P.nwires; ++e) {
+        const double g = P.wg[e];
+        switch (kind) {
+            case VTM_W_SCALED_MEAN: W[e] = alpha * mean; break;
+            case VTM_W_IDENTITY: W[e] = alpha; break;
+            case VTM_W_OB: W[e] = 2.0 * g; break;
+            default: W[e] = alpha * 2.0 * g; break;
+        }
+    }
+    return VTM_OK;
+}
+
 vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int64_t nZ,
                      const vtm_options* opt, void* stream, vtm_handle* out) {
     if (!out) return fail(VTM_E_ARG, "null output handle");
@@ -833,6 +905,7 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     if (o.check_every < 1 || o.max_sweeps < 1 || o.max_outer < 0 || !(o.divergence > 0.0))
         return fail(VTM_E_ARG, "bad iteration limits");
     if (o.local_form < 0 || o.local_form > 2) return fail(VTM_E_ARG, "local_form must be 0, 1 or 2");
+    if (o.timing < 0 || o.timing > 2) return fail(VTM_E_ARG, "timing must be 0, 1 or 2");
     if ((o.batch_row_tiles != 0 && o.batch_row_tiles != 3 && o.batch_row_tiles != 5) ||
         (o.batch_rhs_block != 0 && (o.batch_rhs_block % 16 != 0 || o.batch_rhs_block > 64 || o.batch_rhs_block < 0)))
         return fail(VTM_E_ARG, "bad batched kernel shape");

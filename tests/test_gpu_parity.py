@@ -190,6 +190,41 @@ def test_largest_sub_circuits(torch, kw):
             assert_close(gpu_iterate(torch, w, k, check_every=k, local_form=form), ref[k])
 
 
+@pytest.mark.parametrize("cfg,kw,rule,alpha", [
+    (1, dict(), "ob", 1.0),                        # packed sweep with a different W per port
+    (1, dict(), "wob", 0.125),
+    (3, dict(dims=(16, 16, 16)), "wob", 0.25),     # port-node form, controlled sources
+    (4, dict(dims=(64, 64), nrhs=20), "wob", 0.25),  # MFMA tiles
+])
+def test_per_wire_admittance_iterates_match_oracle(torch, cfg, kw, rule, alpha):
+    """Lines of different admittance (Section VIII's overlapped-block rules,
+    one W per wire from vtm_line_admittance): iterates equal the oracle's in the
+    port-to-port and full forms."""
+    w = workloads.make(cfg, **kw)
+    w.Z = 1.0 / vtm().line_admittance(w.A, w.part, rule, alpha)
+    ks = [1, 5, 20]
+    ref = oracle_iterates(w, ks)
+    for form in ("port", "full"):
+        for k in ks:
+            assert_close(gpu_iterate(torch, w, k, check_every=k, local_form=form), ref[k])
+
+
+def test_timing_modes_count_every_launch(torch):
+    """Per-launch events (timing 1) and one event pair per run of port-to-port
+    sweeps (timing 2) count the same launches: the first and the rebuilding
+    full sweep, and every other sweep as port-to-port; both give the same x."""
+    w = workloads.make(2, dims=(256, 256))
+    xs = []
+    for mode in (1, 2):
+        s = vtm().Solver(w.A, w.part, w.Z, check_every=8, timing=mode)
+        x, rep = s.solve(to_dev(torch, w.b), w.tol)
+        assert rep.sweep_launches == 2 and rep.pp_launches == rep.sweeps - 1, (mode, rep)
+        assert rep.pp_kernel_ms > 0 and rep.sweep_kernel_ms > 0
+        xs.append(x.cpu().numpy())
+        s.close()
+    assert np.array_equal(xs[0], xs[1])
+
+
 def test_config1_sweeps_and_solution(torch):
     """64x64 grid, 4x4 sub-circuits of 16x16, tol 1e-10, residual checked every
     sweep: the same sweep count as the oracle (within one for rounding at the

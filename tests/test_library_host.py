@@ -1,6 +1,7 @@
 """Host-side checks of the C-ABI library: it loads, exports every symbol that
 include/vtm.h declares, and its tearing planner (host code, no device work)
 agrees with the oracle's independently derived eliminated-twin form."""
+import ctypes
 import os
 import re
 
@@ -11,6 +12,7 @@ import scipy.sparse as sp
 import oracle
 import workloads
 import paper_0910_0663_amd as vtm
+from paper_0910_0663_amd import binding
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -118,3 +120,37 @@ def test_plan_merges_duplicates_and_ignores_row_order():
     p2 = vtm.plan(A2, w.part, w.Z)
     assert np.array_equal(p1["wires"], p2["wires"])
     assert np.allclose(p1["G"], p2["G"], rtol=1e-15)
+
+
+@pytest.mark.parametrize("cfg,kw", [(1, dict()), (2, dict(dims=(64, 64))), (4, dict(dims=(96, 96)))])
+def test_line_admittance_rules(cfg, kw):
+    """Section VIII's rules per cut wire.  The scaled mean reproduces the
+    generator's own W = mean branch conductance; the overlapped block W = C is
+    each twin's own diagonal in the oracle's tear (2g of the split midpoint, on
+    both sides); the weighted block and alpha I scale as stated."""
+    w = workloads.make(cfg, **kw)
+    W_mean = vtm.line_admittance(w.A, w.part, "scaled_mean", 1.0)
+    assert np.allclose(W_mean, 1.0 / w.Z, rtol=1e-13, atol=0)
+    assert np.allclose(vtm.line_admittance(w.A, w.part, "scaled_mean", 0.25), 0.25 / w.Z, rtol=1e-13, atol=0)
+    torn = oracle.tear_wires(w.A, w.part, w.Z)
+    T = torn.T.tocsr()
+    W_ob = vtm.line_admittance(w.A, w.part, "ob")
+    assert np.allclose(W_ob, T[torn.pa, torn.pa].A1, rtol=1e-14, atol=0)
+    assert np.allclose(W_ob, T[torn.pb, torn.pb].A1, rtol=1e-14, atol=0)
+    assert np.allclose(vtm.line_admittance(w.A, w.part, "wob", 0.125), 0.125 * W_ob, rtol=1e-15, atol=0)
+    assert np.all(vtm.line_admittance(w.A, w.part, "identity", 0.7) == 0.7)
+
+
+def test_line_admittance_bad_arguments():
+    w = workloads.make(1)
+    L = vtm.lib()
+    assert _status_of(lambda: vtm.line_admittance(w.A, w.part, "ob", 0.0)) == "VTM_E_ARG"
+    hc = binding._HostCsr(w.A)
+    part = np.ascontiguousarray(w.part, dtype=np.int32)
+    out = np.zeros(10)
+    st = L.vtm_line_admittance(ctypes.byref(hc.s), part.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 2, 1.0,
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 10)
+    assert L.vtm_status_str(st).decode() == "VTM_E_ARG"    # wrong wire count
+    st = L.vtm_line_admittance(ctypes.byref(hc.s), part.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 7, 1.0,
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 10)
+    assert L.vtm_status_str(st).decode() == "VTM_E_ARG"    # unknown rule

@@ -184,6 +184,7 @@ def mixed_and_batched(vtm, torch, oracle, workloads):
         "fp32_relres": rel32, "fp64_relres": rel64}
     log(f"cfg5: fp32 refine {t32:.2f} ms vs fp64 {t64:.2f} ms: x{t64 / t32:.2f}")
     res["gradient"] = gradient_path(vtm, torch, oracle, workloads)
+    res["line_admittance_rules_2048sq"] = preconditioners(vtm, torch, oracle, workloads)
     return res
 
 
@@ -231,6 +232,31 @@ def gradient_path(vtm, torch, oracle, workloads, reps=5):
            "total_ms": round(sum(t.values()) * 1e3, 3), "forward_relres": rel_f, "adjoint_relres": rel_a}
     log(f"cfg5 gradient: forward {out['forward_ms']} ms, adjoint {out['adjoint_ms']} ms, "
         f"dL/dg {out['grad_ms']} ms")
+    return out
+
+
+def preconditioners(vtm, torch, oracle, workloads):
+    """Section VIII's line admittances on the bench grid (2048x2048, FP64, 1e-8):
+    the workload's own W = mean conductance, a scaled mean, and the weighted
+    overlapped block W = alpha C (C = each twin's 2g); sweeps and solve time."""
+    w = workloads.make(2)
+    b = torch.as_tensor(w.b, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(b)
+    out = []
+    for rule, alpha in (("scaled_mean", 1.0), ("scaled_mean", 0.25), ("ob", 1.0), ("wob", 0.0625)):
+        W = vtm.line_admittance(w.A, w.part, rule, alpha)
+        s = vtm.Solver(w.A, w.part, 1.0 / W)
+        s.solve(b, w.tol, x)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, rep = s.solve(b, w.tol, x)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3
+        s.close()
+        rel = float(oracle.relative_residual(w.A, w.b, x.cpu().numpy()).max())
+        assert rel <= w.tol, (rule, alpha, rel)
+        out.append({"rule": rule, "alpha": alpha, "sweeps": rep.sweeps, "ms": round(ms, 2), "relres": rel})
+        log(f"cfg2 W {rule} x{alpha}: {rep.sweeps} sweeps, {ms:.1f} ms")
     return out
 
 

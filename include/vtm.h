@@ -169,6 +169,49 @@ vtm_status vtm_setup(const vtm_csr *A, const int32_t *part, const double *Z, int
                      const vtm_options *opt, void *stream, vtm_handle *out);
 
 /*
+ * vtm_setup_vertex -- level-one wire tearing at interfacial nodes (Section V,
+ * Steps 1-4; Fig. 4): every interfacial node is split into a pair of twins,
+ * one in each of the two sub-circuits it borders, joined by a virtual line of
+ * admittance W.  The twins are unknowns of their sub-circuits; the line is a
+ * port with W on the twin's diagonal, incident current a, and outgoing wave
+ * 2 W u_twin - a (Section VI).
+ *
+ *   A       host CSR of the untorn system, n x n (duplicates summed).
+ *   label   host int32[n]: sub-circuit of every inner node (entries of
+ *           interfacial nodes are ignored).
+ *   iface   host int32[n_iface]: the interfacial nodes (Step 1), distinct.
+ *   sides   host int32[n_iface][2]: the two distinct sub-circuits each
+ *           interfacial node borders; the twin in sides[l][0] keeps the node's
+ *           id, the other is a new node.  Labels 0..S-1, each used.
+ *   W       host: nW == 1 -> one line admittance (S, > 0) for every line;
+ *           nW == n_iface -> one per interfacial node, in iface order.
+ *   opt, stream, out   as for vtm_setup.
+ *
+ * Step 3 (what moves to which twin), read from the example of Section IX: a
+ * two-terminal branch (A_vw == A_wv < 0) from interfacial node v to an inner
+ * node w joins w to the twin of v on w's side, conductance and all; a
+ * one-sided entry (a controlled source) between v and an inner node w also
+ * goes to the twin on w's side; the rest of A_vv (ground), the source b_v and
+ * branches between two interfacial nodes of the same two sub-circuits are
+ * split in equal halves.  An inner node coupled to an interfacial node of
+ * sub-circuits it does not belong to, any coupling between inner nodes of
+ * different sub-circuits, or two coupled interfacial nodes that border
+ * different pairs of sub-circuits give VTM_E_UNTEARABLE.  Other limits and
+ * errors as for vtm_setup, on the torn system of n + n_iface nodes.
+ *
+ * vtm_solve takes and returns vectors over the caller's n nodes; the value of
+ * an interfacial node is the mean of its twins (equal at the fixed point), and
+ * the stop rule is the residual on the caller's A.  Interim checks always use
+ * that residual (the port identity of the wire-cut form does not apply).
+ * vtm_solve_adjoint gives VTM_E_UNSUPPORTED; vtm_get_waves / vtm_set_waves
+ * address ports 2l (twin in sides[l][0]) and 2l+1; vtm_info reports the torn
+ * system's size.
+ */
+vtm_status vtm_setup_vertex(const vtm_csr *A, const int32_t *label, const int32_t *iface,
+                            const int32_t *sides, int64_t n_iface, const double *W, int64_t nW,
+                            const vtm_options *opt, void *stream, vtm_handle *out);
+
+/*
  * vtm_solve -- run VTM sweeps (Section VI, eqs. 11 and 14) from zero boundary
  * variables until every column has ||b - A x||_2 / ||b||_2 <= tol, the
  * residual taken on the untorn A in FP64 every opt.check_every sweeps.
@@ -263,6 +306,23 @@ typedef enum {
  */
 vtm_status vtm_line_admittance(const vtm_csr *A, const int32_t *part, int32_t kind, double alpha, double *W,
                                int64_t n_wires);
+
+/*
+ * vtm_split_vertex -- host-only: the system torn at interfacial nodes as
+ * vtm_setup_vertex builds it (Section V, Steps 2-3), before any renumbering
+ * and without the lines of Step 4.  Node i < n keeps its id (for an
+ * interfacial node that is its twin in sides[l][0]); node n + l is the twin of
+ * iface[l] in sides[l][1].  The torn right-hand side is b_i for inner nodes
+ * and b_v / 2 for each twin of v.  Call once with NULL arrays for the sizes.
+ *   n_torn   n + n_iface;  nnz  entries of the torn matrix.
+ *   rowptr   int64 [n_torn + 1], col int32 [nnz], val double [nnz]: the torn
+ *            matrix (CSR; duplicates possible, to be summed).
+ *   part     int32 [n_torn]: sub-circuit of every torn node.
+ * Errors: those of vtm_setup_vertex's tearing.
+ */
+vtm_status vtm_split_vertex(const vtm_csr *A, const int32_t *label, const int32_t *iface,
+                            const int32_t *sides, int64_t n_iface, int64_t *n_torn, int64_t *nnz,
+                            int64_t *rowptr, int32_t *col, double *val, int32_t *part);
 
 /*
  * vtm_plan -- host-only tearing plan (no device work), for inspection and tests.

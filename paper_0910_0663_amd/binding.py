@@ -24,7 +24,8 @@ STATUS = ["VTM_OK", "VTM_E_ARG", "VTM_E_UNTEARABLE", "VTM_E_SINGULAR", "VTM_E_DI
 
 EXPORTS = ["vtm_default_options", "vtm_setup", "vtm_solve", "vtm_solve_adjoint", "vtm_grad",
            "vtm_get_waves", "vtm_set_waves", "vtm_info", "vtm_destroy", "vtm_status_str",
-           "vtm_last_error", "vtm_plan", "vtm_line_admittance"]
+           "vtm_last_error", "vtm_plan", "vtm_line_admittance", "vtm_setup_vertex",
+           "vtm_split_vertex"]
 
 
 class VTMError(RuntimeError):
@@ -72,6 +73,9 @@ def lib() -> C.CDLL:
     L.vtm_setup.argtypes = [C.POINTER(Csr), C.POINTER(C.c_int32), dp, i64, C.POINTER(Options), vp,
                             C.POINTER(vp)]
     L.vtm_setup.restype = C.c_int
+    L.vtm_setup_vertex.argtypes = [C.POINTER(Csr), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32), i64, dp, i64, C.POINTER(Options), vp, C.POINTER(vp)]
+    L.vtm_setup_vertex.restype = C.c_int
     for name in ("vtm_solve", "vtm_solve_adjoint"):
         f = getattr(L, name)
         f.argtypes = [vp, vp, vp, i32, C.c_double, C.POINTER(Report)]
@@ -96,6 +100,10 @@ def lib() -> C.CDLL:
     L.vtm_plan.restype = C.c_int
     L.vtm_line_admittance.argtypes = [C.POINTER(Csr), C.POINTER(C.c_int32), C.c_int32, C.c_double, dp, i64]
     L.vtm_line_admittance.restype = C.c_int
+    L.vtm_split_vertex.argtypes = [C.POINTER(Csr), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32), i64, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
+                                   C.POINTER(C.c_int32), dp, C.POINTER(C.c_int32)]
+    L.vtm_split_vertex.restype = C.c_int
     _lib = L
     return L
 
@@ -144,6 +152,33 @@ def plan(A, part, Z) -> dict:
                 gamma=coef[:, 3])
 
 
+def split_vertex(A, label, iface, sides):
+    """Host-only: the system torn at interfacial nodes (vtm_split_vertex), as a
+    scipy CSR matrix of n + len(iface) nodes (duplicates summed) and its
+    sub-circuit labels."""
+    import scipy.sparse as sp
+    L = lib()
+    hc = _HostCsr(A)
+    i32p = C.POINTER(C.c_int32)
+    label = np.ascontiguousarray(label, dtype=np.int32)
+    iface = np.ascontiguousarray(iface, dtype=np.int32)
+    sides = np.ascontiguousarray(sides, dtype=np.int32).reshape(-1, 2)
+    args = (C.byref(hc.s), label.ctypes.data_as(i32p), iface.ctypes.data_as(i32p), sides.ctypes.data_as(i32p),
+            iface.size)
+    nt, nnz = C.c_int64(), C.c_int64()
+    _check(L.vtm_split_vertex(*args, C.byref(nt), C.byref(nnz), None, None, None, None))
+    rowptr = np.zeros(nt.value + 1, dtype=np.int64)
+    col = np.zeros(nnz.value, dtype=np.int32)
+    val = np.zeros(nnz.value, dtype=np.float64)
+    part = np.zeros(nt.value, dtype=np.int32)
+    _check(L.vtm_split_vertex(*args, None, None, rowptr.ctypes.data_as(C.POINTER(C.c_int64)),
+                              col.ctypes.data_as(i32p), val.ctypes.data_as(C.POINTER(C.c_double)),
+                              part.ctypes.data_as(i32p)))
+    M = sp.csr_matrix((val, col, rowptr), shape=(nt.value, nt.value))
+    M.sum_duplicates()
+    return M, part
+
+
 ADMITTANCE_RULES = {"scaled_mean": 0, "identity": 1, "ob": 2, "wob": 3}
 
 
@@ -184,12 +219,16 @@ class Solver:
     """A torn circuit on the current HIP device (vtm_setup).
 
     A: scipy sparse (host), part: int labels per node, Z: scalar or per cut wire.
+    With ``iface`` and ``sides`` given, the circuit is torn at those interfacial
+    nodes instead (vtm_setup_vertex): ``part`` then labels the inner nodes and
+    ``Z`` is the impedance of each twin-joining line (scalar or per interfacial
+    node).
     """
 
     def __init__(self, A, part, Z, precision="fp64", nrhs_max=1, check_every=8,
                  max_sweeps=1_000_000, divergence=1e6, inner_drop=0.0, max_outer=30,
                  use_graph=False, timing=False, adaptive_checks=True, batch_shape=(0, 0), local_form="port",
-                 stream=None):
+                 stream=None, iface=None, sides=None):
         import torch
         L = lib()
         if not torch.cuda.is_available():
@@ -217,10 +256,21 @@ class Solver:
         part = np.ascontiguousarray(part, dtype=np.int32)
         if part.size != self.n:
             raise ValueError("part must have one label per node")
-        z, zp, nz = _z_array(Z)
         h = C.c_void_p()
-        _check(L.vtm_setup(C.byref(hc.s), part.ctypes.data_as(C.POINTER(C.c_int32)), zp, nz, C.byref(opt),
-                           C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        if iface is None:
+            z, zp, nz = _z_array(Z)
+            _check(L.vtm_setup(C.byref(hc.s), part.ctypes.data_as(C.POINTER(C.c_int32)), zp, nz, C.byref(opt),
+                               C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        else:
+            iface = np.ascontiguousarray(iface, dtype=np.int32)
+            sides = np.ascontiguousarray(sides, dtype=np.int32).reshape(-1, 2)
+            if sides.shape[0] != iface.size:
+                raise ValueError("sides must hold two sub-circuits per interfacial node")
+            w, wp, nw_ = _z_array(1.0 / np.asarray(Z, dtype=np.float64))
+            i32p = C.POINTER(C.c_int32)
+            _check(L.vtm_setup_vertex(C.byref(hc.s), part.ctypes.data_as(i32p), iface.ctypes.data_as(i32p),
+                                      sides.ctypes.data_as(i32p), iface.size, wp, nw_, C.byref(opt),
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
         n, ns, nw, kb, pb, sb = (C.c_int64() for _ in range(6))
         _check(L.vtm_info(h, C.byref(n), C.byref(ns), C.byref(nw), C.byref(kb), C.byref(pb), C.byref(sb)))

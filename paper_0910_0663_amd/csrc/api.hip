@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <numeric>
 #include <array>
 #include <chrono>
 #include <map>
@@ -89,6 +90,11 @@ struct vtm_handle_s {
     DevBuf<double> N64, N64T;  // T: transposed, for the adjoint of an unsymmetric A
     DevBuf<float> N32, N32T;
     DevBuf<int32_t> pn_off, pn_node, pn_pfirst;
+    // tearing at interfacial nodes: maps between plan rows and the caller's nodes, the
+    // caller's A, and right-hand side / residual / solution in the caller's node order
+    DevBuf<int32_t> vx_src, vr0, vr1, orow, ocol, oid;
+    DevBuf<double> vx_w, oval, bo, ro, xo;
+    const double* b_user = nullptr;
     // residual checks from port quantities (port-to-port form): g and G - g per port
     DevBuf<double> pg64, pgd64;
     // batched port-to-port form (MFMA tiles): q x q operators in A-tile order
@@ -146,6 +152,20 @@ using Clock = std::chrono::steady_clock;
 template <typename TX>
 vtm_status residual_launch(vtm_handle h, const double* b, const TX* x, int nrhs, double* r_out, bool transpose) {
     const vtm::Plan& P = h->plan;
+    if (P.vertex) {
+        // the untorn system in the caller's numbering: x of an interfacial node is the mean
+        // of its twins; b is the solve's right-hand side, or the outer residual for an inner check
+        const int no = int(P.n_orig);
+        const double* bo = b == h->bp.p ? h->bo.p : h->ro.p;
+        VTM_HIP(vtm::launch_restrict<TX>(no, nrhs, h->vr0.p, h->vr1.p, x, h->xo.p, false, h->stream));
+        VTM_HIP(vtm::launch_residual<double>(no, nrhs, h->orow.p, h->ocol.p, h->oval.p, bo, h->xo.p,
+                                             r_out ? h->ro.p : nullptr, h->partial.p, h->norms.p, h->stream));
+        if (r_out)
+            VTM_HIP(vtm::launch_expand(int(P.n), nrhs, no, h->vx_src.p, h->vx_w.p, h->ro.p, false, r_out, h->stream));
+        VTM_HIP(hipMemcpyAsync(h->h_norms, h->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost,
+                               h->stream));
+        return VTM_OK;
+    }
     const bool useT = transpose && !P.symmetric;
     VTM_HIP(vtm::launch_residual<TX>(int(P.n), nrhs, useT ? h->rowptrT.p : h->rowptr.p,
                                      useT ? h->colT.p : h->col.p, useT ? h->valT.p : h->val.p, b, x, r_out,
@@ -611,7 +631,7 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
     // port-to-port sweeps check the residual from port quantities; once it passes
     // (and at the end), x^k is rebuilt by a full sweep from the same waves and
     // the residual on A decides
-    const bool iface = pp;
+    const bool iface = pp && !P.vertex;  // the port identity holds for cut branches only
     auto rebuild = [&]() -> vtm_status {
         vtm_status s2 = sweep_once(h, false, nrhs, h->bp.p, h->xp.p, cur ^ 1, adjoint, true, false);
         if (s2 != VTM_OK) return s2;
@@ -709,7 +729,7 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
             const int64_t chunk = std::min<int64_t>(
                 graph_length(h, std::min<int64_t>(cad.next(goal), 4 * cad.m)), h->opt.max_sweeps - inner);
             // sweeps, then ||r - A d|| / ||r|| in FP64 (from port quantities with pp)
-            st = run_chunk(h, true, nrhs, adjoint, chunk, cur, e, pp, inner == 0, pp, &rr);
+            st = run_chunk(h, true, nrhs, adjoint, chunk, cur, e, pp, inner == 0, pp && !P.vertex, &rr);
             if (st != VTM_OK) return st;
             cur ^= int(chunk & 1);
             inner += chunk;
@@ -732,7 +752,7 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
             cad.record(inner, max_of(e));
         }
         out.sweeps += inner;
-        if (pp) {  // d from the last sweep's waves, by a full sweep
+        if (pp && !P.vertex) {  // d from the last sweep's waves, by a full sweep
             const void* bl = h->tiles ? static_cast<const void*>(h->b16.p) : static_cast<const void*>(h->b32.p);
             if ((st = sweep_once(h, true, nrhs, bl, h->d32.p, cur ^ 1, adjoint, true, false)) != VTM_OK)
                 return st;
@@ -753,7 +773,15 @@ vtm_status solve_common(vtm_handle h, const double* b, double* x, int32_t nrhs, 
     if (!(tol > 0.0)) return fail(VTM_E_ARG, "tol must be positive");
     VTM_HIP(hipSetDevice(h->device));
     const vtm::Plan& P = h->plan;
-    VTM_HIP(vtm::launch_gather(int(P.n), nrhs, h->perm.p, b, h->bp.p, h->stream));
+    if (P.vertex) {
+        if (adjoint) return fail(VTM_E_UNSUPPORTED, "tearing at interfacial nodes has no adjoint form here");
+        // interfacial sources split between the twins; b also kept in node order for the residual
+        VTM_HIP(vtm::launch_expand(int(P.n), nrhs, int(P.n_orig), h->vx_src.p, h->vx_w.p, b, true, h->bp.p,
+                                   h->stream));
+        VTM_HIP(vtm::launch_gather(int(P.n_orig), nrhs, h->oid.p, b, h->bo.p, h->stream));
+    } else {
+        VTM_HIP(vtm::launch_gather(int(P.n), nrhs, h->perm.p, b, h->bp.p, h->stream));
+    }
     IterOut out;
     vtm_status st;
     if (h->opt.precision == VTM_FP64) {
@@ -763,7 +791,10 @@ vtm_status solve_common(vtm_handle h, const double* b, double* x, int32_t nrhs, 
     }
     h->waves_set = false;
     if (st != VTM_OK) return st;
-    VTM_HIP(vtm::launch_scatter(int(P.n), nrhs, h->iperm.p, h->xp.p, x, h->stream));
+    if (P.vertex)
+        VTM_HIP(vtm::launch_restrict<double>(int(P.n_orig), nrhs, h->vr0.p, h->vr1.p, h->xp.p, x, true, h->stream));
+    else
+        VTM_HIP(vtm::launch_scatter(int(P.n), nrhs, h->iperm.p, h->xp.p, x, h->stream));
     VTM_HIP(hipStreamSynchronize(h->stream));
     if (rep) {
         rep->sweeps = out.sweeps;
@@ -848,6 +879,22 @@ vtm_status vtm_plan(const vtm_csr* A, const int32_t* part, const double* Z, int6
     return VTM_OK;
 }
 
+vtm_status vtm_split_vertex(const vtm_csr* A, const int32_t* label, const int32_t* iface, const int32_t* sides,
+                            int64_t n_iface, int64_t* n_torn, int64_t* nnz, int64_t* rowptr, int32_t* col,
+                            double* val, int32_t* part) {
+    vtm::VertexSplit X;
+    std::string err;
+    vtm_status st = vtm::split_at_vertices(A, label, iface, sides, n_iface, X, err);
+    if (st != VTM_OK) return fail(st, err);
+    if (n_torn) *n_torn = X.n + X.L;
+    if (nnz) *nnz = int64_t(X.col.size());
+    if (rowptr) std::copy(X.rowptr.begin(), X.rowptr.end(), rowptr);
+    if (col) std::copy(X.col.begin(), X.col.end(), col);
+    if (val) std::copy(X.val.begin(), X.val.end(), val);
+    if (part) std::copy(X.part.begin(), X.part.end(), part);
+    return VTM_OK;
+}
+
 vtm_status vtm_line_admittance(const vtm_csr* A, const int32_t* part, int32_t kind, double alpha, double* W,
                                int64_t n_wires) {
     if (!W) return fail(VTM_E_ARG, "null output");
@@ -892,6 +939,9 @@ vtm_status vtm_line_admittance(const vtm_csr* A, const int32_t* part, int32_t ki
     return VTM_OK;
 }
 
+vtm_status check_options(const vtm_options& o);
+vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* out);
+
 vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int64_t nZ,
                      const vtm_options* opt, void* stream, vtm_handle* out) {
     if (!out) return fail(VTM_E_ARG, "null output handle");
@@ -899,6 +949,57 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     vtm_options o;
     vtm_default_options(&o);
     if (opt) o = *opt;
+    vtm_status st = check_options(o);
+    if (st != VTM_OK) return st;
+    auto h = std::make_unique<vtm_handle_s>();
+    h->opt = o;
+    h->nrhs_max = o.nrhs_max;
+    h->stream = static_cast<hipStream_t>(stream);
+    std::string err;
+    st = vtm::build_plan(A, part, Z, nZ, h->plan, err);
+    if (st != VTM_OK) return fail(st, err);
+    return setup_from_plan(std::move(h), out);
+}
+
+vtm_status vtm_setup_vertex(const vtm_csr* A, const int32_t* label, const int32_t* iface, const int32_t* sides,
+                            int64_t n_iface, const double* W, int64_t nW, const vtm_options* opt, void* stream,
+                            vtm_handle* out) {
+    if (!out) return fail(VTM_E_ARG, "null output handle");
+    *out = nullptr;
+    vtm_options o;
+    vtm_default_options(&o);
+    if (opt) o = *opt;
+    vtm_status st = check_options(o);
+    if (st != VTM_OK) return st;
+    auto h = std::make_unique<vtm_handle_s>();
+    h->opt = o;
+    h->nrhs_max = o.nrhs_max;
+    h->stream = static_cast<hipStream_t>(stream);
+    std::string err;
+    st = vtm::build_plan_vertex(A, label, iface, sides, n_iface, W, nW, h->plan, err);
+    if (st != VTM_OK) return fail(st, err);
+    const vtm::Plan& P = h->plan;
+    hipStream_t s = h->stream;
+    VTM_HIP(hipGetDevice(&h->device));
+    std::vector<int32_t> id(P.n_orig);
+    std::iota(id.begin(), id.end(), 0);
+    const int64_t no = P.n_orig * o.nrhs_max;
+    VTM_HIP(h->vx_src.upload(P.vx_src, s));
+    VTM_HIP(h->vx_w.upload(P.vx_w, s));
+    VTM_HIP(h->vr0.upload(P.vr0, s));
+    VTM_HIP(h->vr1.upload(P.vr1, s));
+    VTM_HIP(h->orow.upload(P.orow, s));
+    VTM_HIP(h->ocol.upload(P.ocol, s));
+    VTM_HIP(h->oval.upload(P.oval, s));
+    VTM_HIP(h->oid.upload(id, s));
+    VTM_HIP(h->bo.alloc(no));
+    VTM_HIP(h->ro.alloc(no));
+    VTM_HIP(h->xo.alloc(no));
+    VTM_HIP(hipStreamSynchronize(s));
+    return setup_from_plan(std::move(h), out);
+}
+
+vtm_status check_options(const vtm_options& o) {
     if (o.precision < VTM_FP64 || o.precision > VTM_BF16_REFINE)
         return fail(VTM_E_ARG, "unknown precision");
     if (o.nrhs_max < 1 || o.nrhs_max > 256) return fail(VTM_E_ARG, "nrhs_max outside 1..256");
@@ -909,14 +1010,12 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     if ((o.batch_row_tiles != 0 && o.batch_row_tiles != 3 && o.batch_row_tiles != 5) ||
         (o.batch_rhs_block != 0 && (o.batch_rhs_block % 16 != 0 || o.batch_rhs_block > 64 || o.batch_rhs_block < 0)))
         return fail(VTM_E_ARG, "bad batched kernel shape");
+    return VTM_OK;
+}
 
-    auto h = std::make_unique<vtm_handle_s>();
-    h->opt = o;
-    h->nrhs_max = o.nrhs_max;
-    h->stream = static_cast<hipStream_t>(stream);
-    std::string err;
-    vtm_status st = vtm::build_plan(A, part, Z, nZ, h->plan, err);
-    if (st != VTM_OK) return fail(st, err);
+vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* out) {
+    const vtm_options& o = h->opt;
+    vtm_status st = VTM_OK;
     VTM_HIP(hipGetDevice(&h->device));
     const vtm::Plan& P = h->plan;
     hipStream_t s = h->stream;
@@ -1147,7 +1246,8 @@ vtm_status vtm_grad(vtm_handle h, const double* x, const double* lambda, int32_t
     if (m < 0 || nrhs < 1 || (m > 0 && (!x || !lambda || !branch_ij || !dL_dg)))
         return fail(VTM_E_ARG, "bad gradient arguments");
     VTM_HIP(hipSetDevice(h->device));
-    VTM_HIP(vtm::launch_grad(m, int(h->plan.n), nrhs, x, lambda, branch_ij, dL_dg, h->stream));
+    const int64_t nn = h->plan.vertex ? h->plan.n_orig : h->plan.n;  // the caller's nodes
+    VTM_HIP(vtm::launch_grad(m, int(nn), nrhs, x, lambda, branch_ij, dL_dg, h->stream));
     VTM_HIP(hipStreamSynchronize(h->stream));
     return VTM_OK;
 }

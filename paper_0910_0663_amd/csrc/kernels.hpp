@@ -161,6 +161,14 @@ hipError_t launch_residual(int n, int nrhs, const int32_t* rowptr, const int32_t
 
 // ---- vector utilities -------------------------------------------------------
 // dst[i][r] = src[r][perm[i]]   (column-major caller layout -> renumbered rows)
+// Vertex tearing: out[r][j] = w[r] * in(src[r], j) per plan row r, the input a
+// caller's [nrhs][n_in] vector (in_rhs_major) or [n_in][nrhs] ...
+hipError_t launch_expand(int rows, int nrhs, int n_in, const int32_t* src, const double* w, const double* in,
+                         bool in_rhs_major, double* out, hipStream_t st);
+// ... and back: out(i, j) = x[r0[i]][j], or the mean with x[r1[i]][j] when r1[i] >= 0.
+template <typename TX>
+hipError_t launch_restrict(int n, int nrhs, const int32_t* r0, const int32_t* r1, const TX* x, double* out,
+                           bool out_rhs_major, hipStream_t st);
 hipError_t launch_gather(int n, int nrhs, const int32_t* perm, const double* src, double* dst,
                          hipStream_t st);
 // dst[r][j] = src[iperm[j]][r]

@@ -33,7 +33,8 @@ struct Entry {
 }  // namespace
 
 vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, int64_t nZ,
-                      Plan& P, std::string& err) {
+                      Plan& P, std::string& err, const int32_t* line_a, const int32_t* line_b, int64_t n_lines) {
+    const bool explicit_lines = line_a != nullptr;
     if (!A || !part || !Z || !A->rowptr || (!A->col && A->nnz) || (!A->val && A->nnz)) {
         err = "null argument";
         return VTM_E_ARG;
@@ -164,6 +165,11 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
         for (int64_t k = mrow[i]; k < mrow[i + 1]; ++k) {
             const int32_t j = ment[k].c;
             if (part[i] == part[j]) continue;
+            if (explicit_lines) {
+                err = "nodes " + std::to_string(i) + " and " + std::to_string(j) +
+                      " in different sub-circuits are coupled directly, not through an interfacial node";
+                return VTM_E_UNTEARABLE;
+            }
             double vt;
             if (!find(j, int32_t(i), vt) || vt != ment[k].v) {
                 err = "coupling between nodes " + std::to_string(i) + " and " + std::to_string(j) +
@@ -181,6 +187,23 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
                 P.wg.push_back(-ment[k].v);
             }
         }
+    if (explicit_lines) {
+        if (!line_b || n_lines < 0) {
+            err = "bad line list";
+            return VTM_E_ARG;
+        }
+        for (int64_t e = 0; e < n_lines; ++e) {
+            const int32_t a = line_a[e], b = line_b[e];
+            if (a < 0 || a >= n || b < 0 || b >= n || part[a] == part[b]) {
+                err = "a line must join two nodes of different sub-circuits";
+                return VTM_E_ARG;
+            }
+            P.wi.push_back(a);
+            P.wj.push_back(b);
+            P.wg.push_back(0.0);
+        }
+        P.vertex = true;
+    }
     const int64_t nw = int64_t(P.wi.size());
     P.nwires = nw;
     P.nports = 2 * nw;
@@ -239,7 +262,10 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
                              : 0;
         P.max_slot = std::max(P.max_slot, P.port_slot[p]);
         const int64_t e = q / 2;
-        const PortCoef k = port_coef(P.wg[e], P.wW[e]);
+        // a line between twins has no branch: its port adds W to the twin's row, the
+        // wave enters whole (c = 1) and leaves as 2 W u - a (beta = 2 W, gamma = -1),
+        // the limit of a cut branch whose g grows without bound
+        const PortCoef k = P.vertex ? PortCoef{P.wW[e], 1.0, 2.0 * P.wW[e], -1.0} : port_coef(P.wg[e], P.wW[e]);
         P.pc[p] = k.c;
         P.pbeta[p] = k.beta;
         P.pgamma[p] = k.gamma;
@@ -309,6 +335,228 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
             P.rowptr[r + 1] = int32_t(w);
         }
     }
+    return VTM_OK;
+}
+
+// ---- tearing at interfacial nodes ---------------------------------------------
+// Step 1 names the interfacial nodes, Steps 2-3 split each into two twins and
+// distribute what touches it, Step 4 joins the twins by a line.  The split
+// (reading of Step 3 and of the op-amp example, eqs. 15-17): an entry between
+// an interfacial node v and a non-interfacial node w stays whole and moves to
+// the twin of v on w's side; a two-terminal branch (A_vw == A_wv < 0) also
+// moves its conductance to that twin's diagonal; what remains of A_vv (the
+// ground conductance and the branches between interfacial nodes), the entries
+// between two interfacial nodes (split between the twins of each side) and the
+// source at v are shared in equal halves.  Twin a of line l keeps v's number,
+// twin b is node n + l of the expanded system.
+vtm_status split_at_vertices(const vtm_csr* A, const int32_t* label, const int32_t* iface, const int32_t* sides,
+                             int64_t L, VertexSplit& out, std::string& err) {
+    if (!A || !label || !A->rowptr || (!A->col && A->nnz) || (!A->val && A->nnz) || L < 0 ||
+        (L > 0 && (!iface || !sides))) {
+        err = "null argument";
+        return VTM_E_ARG;
+    }
+    const int64_t n = A->n;
+    if (n <= 0 || A->nnz < 0 || A->rowptr[0] != 0 || A->rowptr[n] != A->nnz) {
+        err = "malformed CSR";
+        return VTM_E_ARG;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (A->rowptr[i + 1] < A->rowptr[i]) {
+            err = "rowptr must be non-decreasing";
+            return VTM_E_ARG;
+        }
+    if (n + L > std::numeric_limits<int32_t>::max()) {
+        err = "n plus the interfacial nodes must fit int32";
+        return VTM_E_UNSUPPORTED;
+    }
+    std::vector<int64_t> line_of(n, -1);
+    for (int64_t l = 0; l < L; ++l) {
+        const int32_t v = iface[l];
+        if (v < 0 || v >= n || line_of[v] >= 0) {
+            err = "interfacial nodes must be distinct node ids";
+            return VTM_E_ARG;
+        }
+        if (sides[2 * l] < 0 || sides[2 * l + 1] < 0 || sides[2 * l] == sides[2 * l + 1]) {
+            err = "each interfacial node needs two distinct sub-circuits";
+            return VTM_E_ARG;
+        }
+        line_of[v] = l;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (line_of[i] < 0 && label[i] < 0) {
+            err = "negative sub-circuit label";
+            return VTM_E_ARG;
+        }
+    for (int64_t k = 0; k < A->nnz; ++k)
+        if (A->col[k] < 0 || A->col[k] >= n || !std::isfinite(A->val[k])) {
+            err = "column index out of range or non-finite entry";
+            return VTM_E_ARG;
+        }
+    // the caller's A with duplicates merged and columns sorted: the split reads it,
+    // and the residual of the untorn system uses it
+    std::vector<int32_t> orow(n + 1, 0), ocol;
+    std::vector<double> oval;
+    {
+        std::vector<std::pair<int32_t, double>> row;
+        for (int64_t i = 0; i < n; ++i) {
+            row.clear();
+            for (int64_t q = A->rowptr[i]; q < A->rowptr[i + 1]; ++q) row.push_back({A->col[q], A->val[q]});
+            std::sort(row.begin(), row.end());
+            for (size_t k = 0; k < row.size(); ++k) {
+                if (k > 0 && row[k].first == row[k - 1].first) {
+                    oval.back() += row[k].second;
+                } else {
+                    ocol.push_back(row[k].first);
+                    oval.push_back(row[k].second);
+                }
+            }
+            orow[i + 1] = int32_t(ocol.size());
+        }
+    }
+    auto entry = [&](int64_t r, int64_t c, double& v) -> bool {  // A[r, c]
+        auto lo = ocol.begin() + orow[r], hi = ocol.begin() + orow[r + 1];
+        auto it = std::lower_bound(lo, hi, int32_t(c));
+        if (it == hi || *it != c) return false;
+        v = oval[it - ocol.begin()];
+        return true;
+    };
+    // the twin of interfacial node v (line l) in sub-circuit s, or -1
+    auto twin_in = [&](int64_t l, int32_t s) -> int64_t {
+        if (sides[2 * l] == s) return iface[l];
+        if (sides[2 * l + 1] == s) return n + l;
+        return -1;
+    };
+    const int64_t N = n + L;
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(N);
+    std::vector<double> remainder(L, 0.0);  // what of A_vv is split in halves
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t li = line_of[i];
+        for (int64_t q = orow[i]; q < orow[i + 1]; ++q) {
+            const int64_t j = ocol[q];
+            const int64_t lj = line_of[j];
+            const double v = oval[q];
+            if (v == 0.0 && i != j) continue;
+            if (li < 0 && lj < 0) {
+                if (label[i] != label[j]) {
+                    err = "nodes " + std::to_string(i) + " and " + std::to_string(j) +
+                          " of different sub-circuits are coupled directly, not through an interfacial node";
+                    return VTM_E_UNTEARABLE;
+                }
+                rows[i].push_back({int32_t(j), v});
+            } else if (li < 0) {  // row i inner, column j interfacial
+                const int64_t t = twin_in(lj, label[i]);
+                if (t < 0) {
+                    err = "node " + std::to_string(i) + " is coupled to interfacial node " + std::to_string(j) +
+                          " of sub-circuits it does not belong to";
+                    return VTM_E_UNTEARABLE;
+                }
+                rows[i].push_back({int32_t(t), v});
+            } else if (lj < 0) {  // row i interfacial, column j inner
+                const int64_t t = twin_in(li, label[j]);
+                if (t < 0) {
+                    err = "interfacial node " + std::to_string(i) + " is coupled to node " + std::to_string(j) +
+                          " of a sub-circuit it does not border";
+                    return VTM_E_UNTEARABLE;
+                }
+                rows[t].push_back({int32_t(j), v});
+                double vt;
+                if (v < 0.0 && entry(j, i, vt) && vt == v) rows[t].push_back({int32_t(t), -v});  // branch g
+            } else if (i == j) {
+                remainder[li] += v;
+            } else {  // two interfacial nodes: the same two sub-circuits, half on each side
+                const int32_t s0 = sides[2 * li], s1 = sides[2 * li + 1];
+                const int64_t a0 = twin_in(lj, s0), a1 = twin_in(lj, s1);
+                if (a0 < 0 || a1 < 0) {
+                    err = "interfacial nodes " + std::to_string(i) + " and " + std::to_string(j) +
+                          " border different sub-circuits";
+                    return VTM_E_UNTEARABLE;
+                }
+                rows[iface[li]].push_back({int32_t(a0), 0.5 * v});
+                rows[n + li].push_back({int32_t(a1), 0.5 * v});
+            }
+        }
+    }
+    // the interfacial node's diagonal less the branch conductances moved to its twins
+    for (int64_t l = 0; l < L; ++l) {
+        const int64_t v = iface[l];
+        double moved = 0.0;
+        for (int64_t q = orow[v]; q < orow[v + 1]; ++q) {
+            const int64_t j = ocol[q];
+            double vt;
+            if (line_of[j] < 0 && oval[q] < 0.0 && entry(j, v, vt) && vt == oval[q]) moved += -oval[q];
+        }
+        const double half = 0.5 * (remainder[l] - moved);
+        rows[v].push_back({int32_t(v), half});
+        rows[n + l].push_back({int32_t(n + l), half});
+    }
+    // expanded CSR and partition
+    out.n = n;
+    out.L = L;
+    out.rowptr.assign(N + 1, 0);
+    out.col.clear();
+    out.val.clear();
+    for (int64_t r = 0; r < N; ++r) {
+        for (const auto& e : rows[r]) {
+            out.col.push_back(e.first);
+            out.val.push_back(e.second);
+        }
+        out.rowptr[r + 1] = int64_t(out.col.size());
+    }
+    out.part.resize(N);
+    for (int64_t i = 0; i < n; ++i) out.part[i] = line_of[i] < 0 ? label[i] : sides[2 * line_of[i]];
+    for (int64_t l = 0; l < L; ++l) out.part[n + l] = sides[2 * l + 1];
+    out.orow = std::move(orow);
+    out.ocol = std::move(ocol);
+    out.oval = std::move(oval);
+    return VTM_OK;
+}
+
+vtm_status build_plan_vertex(const vtm_csr* A, const int32_t* label, const int32_t* iface, const int32_t* sides,
+                             int64_t L, const double* W, int64_t nW, Plan& P, std::string& err) {
+    if (!W || (nW != 1 && nW != L)) {
+        err = "nW must be 1 or the number of interfacial nodes";
+        return VTM_E_ARG;
+    }
+    VertexSplit X;
+    vtm_status st = split_at_vertices(A, label, iface, sides, L, X, err);
+    if (st != VTM_OK) return st;
+    const int64_t n = X.n, N = n + L;
+    std::vector<int32_t> la(L), lb(L);
+    std::vector<double> Z(nW);
+    for (int64_t l = 0; l < L; ++l) {
+        la[l] = iface[l];
+        lb[l] = int32_t(n + l);
+    }
+    for (int64_t l = 0; l < nW; ++l) {
+        if (!(W[l] > 0.0) || !std::isfinite(W[l])) {
+            err = "line admittance must be positive and finite";
+            return VTM_E_ARG;
+        }
+        Z[l] = 1.0 / W[l];
+    }
+    vtm_csr XA{N, int64_t(X.col.size()), X.rowptr.data(), X.col.data(), X.val.data()};
+    st = build_plan(&XA, X.part.data(), Z.data(), nW, P, err, la.data(), lb.data(), L);
+    if (st != VTM_OK) return st;
+    // maps between the plan rows and the caller's nodes
+    P.n_orig = n;
+    std::vector<char> is_if(n, 0);
+    for (int64_t l = 0; l < L; ++l) is_if[iface[l]] = 1;
+    P.vx_src.resize(N);
+    P.vx_w.resize(N);
+    for (int64_t r = 0; r < N; ++r) {
+        const int64_t e = P.perm[r];  // expanded node
+        const bool twin = e >= n || is_if[e];
+        P.vx_src[r] = int32_t(e >= n ? iface[e - n] : e);
+        P.vx_w[r] = twin ? 0.5 : 1.0;
+    }
+    P.vr0.resize(n);
+    P.vr1.assign(n, -1);
+    for (int64_t i = 0; i < n; ++i) P.vr0[i] = P.iperm[i];
+    for (int64_t l = 0; l < L; ++l) P.vr1[iface[l]] = P.iperm[n + l];
+    P.orow = std::move(X.orow);
+    P.ocol = std::move(X.ocol);
+    P.oval = std::move(X.oval);
     return VTM_OK;
 }
 

@@ -62,11 +62,52 @@ struct Plan {
     // The untorn A renumbered (rows and columns), duplicates merged, columns sorted.
     std::vector<int32_t> rowptr, col;
     std::vector<double> val;
+
+    // Tearing at interfacial nodes (build_plan_vertex): the plan above describes the
+    // expanded system (every interfacial node replaced by two twins); these map it
+    // to and from the caller's n_orig nodes.
+    bool vertex = false;
+    int64_t n_orig = 0;
+    std::vector<int32_t> vx_src;   // per plan row: the original node it comes from
+    std::vector<double> vx_w;      // per plan row: its share of that node's source (1 or 1/2)
+    std::vector<int32_t> vr0, vr1; // per original node: its plan row(s); vr1 = -1 unless a twin pair
+    std::vector<int32_t> orow, ocol;  // the caller's A, duplicates merged (residual on the untorn system)
+    std::vector<double> oval;
 };
 
-// Builds the plan; on failure returns the status and sets err.
+// Builds the plan; on failure returns the status and sets err.  With lines
+// (line_a, line_b: n_lines pairs of nodes in different sub-circuits, not coupled
+// by A) the lines are those pairs, each a line with no branch (vertex tearing),
+// and A may couple no two sub-circuits; without, the lines are A's cut branches.
 vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, int64_t nZ,
-                      Plan& plan, std::string& err);
+                      Plan& plan, std::string& err, const int32_t* line_a = nullptr,
+                      const int32_t* line_b = nullptr, int64_t n_lines = 0);
+
+// The system torn at interfacial nodes, before renumbering: nodes 0..n-1 keep
+// their ids (an interfacial node's id now names its twin in sides[2l]); node n + l
+// is the twin of iface[l] in sides[2l + 1].
+struct VertexSplit {
+    int64_t n = 0, L = 0;
+    std::vector<int64_t> rowptr;   // n + L + 1
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    std::vector<int32_t> part;     // n + L sub-circuit labels
+    std::vector<int32_t> orow, ocol;  // the caller's A, duplicates merged, columns sorted
+    std::vector<double> oval;
+};
+
+// Steps 2-3 of the vertex tearing below (no lines yet); err set on failure.
+vtm_status split_at_vertices(const vtm_csr* A, const int32_t* label, const int32_t* iface,
+                             const int32_t* sides, int64_t n_iface, VertexSplit& out, std::string& err);
+
+// Tearing at interfacial nodes (Section V, Steps 1-4, as the paper tears):
+// every node iface[l] is split into two twins, one in each of the sub-circuits
+// sides[2l] and sides[2l + 1], joined by a line of admittance W[l] (nW == 1: one
+// W for all).  Other nodes keep label[i].  The plan describes the expanded
+// system and carries the maps back to the caller's nodes.
+vtm_status build_plan_vertex(const vtm_csr* A, const int32_t* label, const int32_t* iface,
+                             const int32_t* sides, int64_t n_iface, const double* W, int64_t nW,
+                             Plan& plan, std::string& err);
 
 // Renumbered A^T in compressed rows (columns sorted).
 void transpose_csr(const Plan& plan, std::vector<int32_t>& rowptr, std::vector<int32_t>& col,

@@ -26,6 +26,41 @@ __global__ void k_scatter(int n, int nrhs, const int32_t* __restrict__ iperm, co
     dst[t] = src[int64_t(iperm[j]) * nrhs + r];
 }
 
+// Vertex tearing: plan row r takes w[r] times its original node src[r]'s entry
+// (an interfacial node's source is split between its twins); the input is a
+// caller's [nrhs][n_in] vector or an [n_in][nrhs] one.
+__global__ void k_expand(int rows, int nrhs, int n_in, const int32_t* __restrict__ src,
+                         const double* __restrict__ w, const double* __restrict__ in, int in_rhs_major,
+                         double* __restrict__ out) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(rows) * nrhs) return;
+    const int64_t r = t / nrhs;
+    const int j = int(t - r * nrhs);
+    const int64_t s = src[r];
+    out[t] = w[r] * (in_rhs_major ? in[int64_t(j) * n_in + s] : in[s * nrhs + j]);
+}
+
+// The original nodes' values from the plan rows: the row itself, or the mean of
+// an interfacial node's two twins (r1 >= 0); output [nrhs][n] or [n][nrhs].
+template <typename TX>
+__global__ void k_restrict(int n, int nrhs, const int32_t* __restrict__ r0, const int32_t* __restrict__ r1,
+                           const TX* __restrict__ x, double* __restrict__ out, int out_rhs_major) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(n) * nrhs) return;
+    int64_t i;
+    int j;
+    if (out_rhs_major) {
+        j = int(t / n);
+        i = t - int64_t(j) * n;
+    } else {
+        i = t / nrhs;
+        j = int(t - i * nrhs);
+    }
+    double v = double(x[int64_t(r0[i]) * nrhs + j]);
+    if (r1[i] >= 0) v = 0.5 * (v + double(x[int64_t(r1[i]) * nrhs + j]));
+    out[t] = v;
+}
+
 template <typename T>
 __global__ void k_fill(int64_t count, T value, T* __restrict__ dst) {
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -84,6 +119,29 @@ __global__ void k_grad(int64_t m, int n, int nrhs, const double* __restrict__ x,
 inline unsigned blocks_for(int64_t count, int bs = kBlock) { return unsigned((count + bs - 1) / bs); }
 
 }  // namespace
+
+hipError_t launch_expand(int rows, int nrhs, int n_in, const int32_t* src, const double* w, const double* in,
+                         bool in_rhs_major, double* out, hipStream_t st) {
+    const int64_t total = int64_t(rows) * nrhs;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_expand, dim3(unsigned((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, rows, nrhs, n_in,
+                       src, w, in, in_rhs_major ? 1 : 0, out);
+    return hipGetLastError();
+}
+
+template <typename TX>
+hipError_t launch_restrict(int n, int nrhs, const int32_t* r0, const int32_t* r1, const TX* x, double* out,
+                           bool out_rhs_major, hipStream_t st) {
+    const int64_t total = int64_t(n) * nrhs;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_restrict<TX>, dim3(unsigned((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, nrhs, r0,
+                       r1, x, out, out_rhs_major ? 1 : 0);
+    return hipGetLastError();
+}
+template hipError_t launch_restrict<double>(int, int, const int32_t*, const int32_t*, const double*, double*, bool,
+                                            hipStream_t);
+template hipError_t launch_restrict<float>(int, int, const int32_t*, const int32_t*, const float*, double*, bool,
+                                           hipStream_t);
 
 hipError_t launch_gather(int n, int nrhs, const int32_t* perm, const double* src, double* dst,
                          hipStream_t st) {

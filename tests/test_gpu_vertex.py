@@ -1,0 +1,189 @@
+"""Parity of tearing at interfacial nodes (vtm_setup_vertex, through the C ABI)
+with the oracle's level-one vertex tear (Section V, Steps 1-4; Section IX).
+
+Iterates are compared element by element after the same number of sweeps, to
+the FP64 bound of the edge-cut tests (1e-11 of max |x|): each sweep rounds
+dense dot products of at most a few hundred terms and the iteration contracts.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+ITER_RTOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU tests need a HIP device"
+    return T
+
+
+def vtm():
+    import paper_0910_0663_amd as v
+    return v
+
+
+def to_dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def strips(dims, width, law="loguniform", seed=0, nrhs=1, vccs=False):
+    """A grid circuit cut into strips by separator layers of interfacial nodes."""
+    if vccs:
+        w = workloads.make(3, dims=dims, nrhs=nrhs, seed=seed)
+        A, b = w.A, w.b
+    else:
+        rng = np.random.default_rng(seed)
+        edges = workloads.grid2d_edges(*dims) if len(dims) == 2 else workloads.grid3d_edges(*dims)
+        m = edges.shape[0]
+        g = 10.0 ** rng.uniform(-1, 1, m) if law == "loguniform" else rng.uniform(0.5, 2.0, m)
+        n = int(np.prod(dims))
+        A = workloads.nodal_matrix(n, edges, g, np.full(n, workloads.GROUND_S))
+        b = rng.standard_normal((nrhs, n))
+    label, iface, sides = workloads.separator_strips(dims, width)
+    off = A.tocoo()
+    br = (off.row != off.col) & (off.data < 0)
+    W = float(np.mean(-off.data[br]))   # mean branch conductance, as for the wire-cut workloads
+    return A, b, label, iface, sides, W
+
+
+def oracle_iterates(A, b, label, iface, sides, W, ks):
+    torn = oracle.tear_at_vertices(A, label, iface, sides, W)
+    sw = oracle.Sweeper(torn)
+    f = torn.src @ b.T
+    a = np.zeros((2, torn.n_lines, b.shape[0]))
+    out = {}
+    for k in range(1, max(ks) + 1):
+        u, a = sw.sweep(f, a)
+        if k in ks:
+            out[k] = (torn.out @ u).T
+    return out
+
+
+def solver(A, label, iface, sides, W, **kw):
+    Z = 1.0 / np.asarray(W, dtype=np.float64)
+    return vtm().Solver(A, label, Z, iface=iface, sides=sides, **kw)
+
+
+def gpu_iterate(torch, A, b, label, iface, sides, W, k, check_every=1, **kw):
+    s = solver(A, label, iface, sides, W, nrhs_max=b.shape[0], check_every=check_every, max_sweeps=k,
+               adaptive_checks=False, **kw)
+    x = torch.empty(b.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(vtm().VTMError) as ei:
+        s.solve(to_dev(torch, b), 1e-300, x)
+    assert ei.value.name == "VTM_E_MAXITER"
+    assert ei.value.report.sweeps == k
+    s.close()
+    return x.cpu().numpy()
+
+
+def assert_close(x, ref, rtol=ITER_RTOL):
+    scale = np.abs(ref).max()
+    err = np.abs(x - ref).max()
+    assert err <= rtol * scale, f"max err {err:.3e} vs scale {scale:.3e}"
+
+
+@pytest.fixture(scope="module")
+def opamp(golden_dir):
+    with open(os.path.join(golden_dir, "opamp_example.json")) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("form", ["full", "port", "port_dense"])
+def test_opamp_example_converges_with_papers_W(torch, opamp, form):
+    """Section IX: the op-amp circuit of eq. (15), nodes 2 and 3 split, W2 = 0.5,
+    W3 = 20000: VTM reaches A^-1 I although Jacobi and Gauss-Seidel diverge."""
+    A = sp.csr_matrix(np.array(opamp["A_eq15"], dtype=np.float64))
+    label, iface, sides = np.array([0, -1, -1, 1]), np.array([1, 2]), np.array([[0, 1], [0, 1]])
+    W = np.array([opamp["W2"], opamp["W3"]])
+    b = np.array([[1.0, 1.0, 1.0, 1.0], [0.3, -1.1, 0.7, 2.0]])
+    s = solver(A, label, iface, sides, W, nrhs_max=2, check_every=1, adaptive_checks=False, local_form=form)
+    x, rep = s.solve(to_dev(torch, b), 1e-12)
+    xs = np.linalg.solve(A.toarray(), b.T).T
+    assert np.allclose(x.cpu().numpy(), xs, rtol=1e-10, atol=1e-12)
+    ref = oracle.vtm_solve(oracle.tear_at_vertices(A, label, iface, sides, W), A, b, 1e-12, max_sweeps=100)
+    assert ref.status == "ok" and abs(rep.sweeps - ref.sweeps) <= 1
+    with pytest.raises(vtm().VTMError) as ei:
+        s.solve_adjoint(to_dev(torch, b), 1e-12)
+    assert ei.value.name == "VTM_E_UNSUPPORTED"
+
+
+def test_opamp_example_diverges_with_poor_W(torch, opamp):
+    """Section VIII: with both admittances 0.5 the same tear diverges."""
+    A = sp.csr_matrix(np.array(opamp["A_eq15"], dtype=np.float64))
+    s = solver(A, np.array([0, -1, -1, 1]), np.array([1, 2]), np.array([[0, 1], [0, 1]]), np.array([0.5, 0.5]),
+               check_every=1)
+    with pytest.raises(vtm().VTMError) as ei:
+        s.solve(to_dev(torch, np.ones(4)), 1e-12)
+    assert ei.value.name == "VTM_E_DIVERGED"
+
+
+@pytest.mark.parametrize("dims,width,kw", [
+    ((24, 47), 10, dict()),                                 # 2-D strips of 24 x 10: packed port-node form
+    ((24, 47), 10, dict(local_form="full")),
+    ((24, 47), 10, dict(local_form="port_dense")),
+    ((40, 47), 10, dict()),                                 # 80 ports per strip: dense port-to-port form
+    ((12, 12, 23), 5, dict()),                              # 3-D slabs of 12 x 12 x 5
+])
+def test_separator_strip_iterates_match_oracle(torch, dims, width, kw):
+    A, b, label, iface, sides, W = strips(dims, width)
+    ks = [1, 2, 7]
+    ref = oracle_iterates(A, b, label, iface, sides, W, ks)
+    for k in ks:
+        assert_close(gpu_iterate(torch, A, b, label, iface, sides, W, k, **kw), ref[k])
+    # port-to-port sweeps between the first and the last
+    assert_close(gpu_iterate(torch, A, b, label, iface, sides, W, 7, check_every=7, **kw), ref[7])
+
+
+def test_per_line_admittance_and_several_rhs(torch):
+    A, b, label, iface, sides, _ = strips((24, 35), 8, nrhs=3, seed=4)
+    W = np.random.default_rng(1).uniform(0.3, 3.0, iface.size)
+    ref = oracle_iterates(A, b, label, iface, sides, W, [5])
+    assert_close(gpu_iterate(torch, A, b, label, iface, sides, W, 5), ref[5])
+
+
+def test_batched_mfma_layout_iterates_match_oracle(torch):
+    A, b, label, iface, sides, W = strips((16, 35), 8, nrhs=16, seed=6)
+    ref = oracle_iterates(A, b, label, iface, sides, W, [4])
+    assert_close(gpu_iterate(torch, A, b, label, iface, sides, W, 4, check_every=4), ref[4])
+
+
+def test_unsymmetric_slabs_iterate_and_converge(torch):
+    """Controlled sources inside the slabs (unsymmetric A)."""
+    A, b, label, iface, sides, W = strips((6, 10, 23), 5, vccs=True)
+    ref = oracle_iterates(A, b, label, iface, sides, W, [6])
+    assert_close(gpu_iterate(torch, A, b, label, iface, sides, W, 6, check_every=3), ref[6])
+    r = oracle.vtm_solve(oracle.tear_at_vertices(A, label, iface, sides, W), A, b, 1e-9, max_sweeps=5000)
+    assert r.status == "ok"
+    s = solver(A, label, iface, sides, W, check_every=1, adaptive_checks=False)
+    x, rep = s.solve(to_dev(torch, b), 1e-9)
+    assert abs(rep.sweeps - r.sweeps) <= 1
+    assert rep.relres_max <= 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+def test_separator_strips_solve_to_tolerance(torch, prec):
+    """Sweep count of the FP64 path that of the oracle (within one, for rounding at the threshold);
+    both precisions reach the FP64 tolerance on the untorn A."""
+    A, b, label, iface, sides, W = strips((48, 59), 11, seed=2)
+    tol = 1e-10
+    r = oracle.vtm_solve(oracle.tear_at_vertices(A, label, iface, sides, W), A, b, tol, max_sweeps=20000)
+    assert r.status == "ok"
+    s = solver(A, label, iface, sides, W, precision=prec, check_every=1 if prec == "fp64" else 8,
+               adaptive_checks=False)
+    x, rep = s.solve(to_dev(torch, b), tol)
+    assert rep.relres_max <= tol
+    xs = spla.spsolve(A.tocsc(), b[0])
+    assert np.abs(x.cpu().numpy()[0] - xs).max() <= 1e-7 * np.abs(xs).max()
+    if prec == "fp64":
+        assert abs(rep.sweeps - r.sweeps) <= 1

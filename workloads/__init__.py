@@ -15,5 +15,6 @@ from .grids import (  # noqa: F401
     block_partition_2d,
     block_partition_3d,
     random_cut_widths,
+    separator_strips,
     GROUND_S,
 )

@@ -111,6 +111,39 @@ def block_partition_3d(nz: int, ny: int, nx: int, bz: int, by: int, bx: int) -> 
     return lab.ravel().astype(np.int32)
 
 
+def separator_strips(dims, width: int):
+    """Node separators for tearing at interfacial nodes (Section V, Step 1):
+    the grid (2-D or 3-D, node numbering as in :func:`grid2d_edges` /
+    :func:`grid3d_edges`) is cut along its last axis into strips (slabs) of
+    ``width`` inner layers, consecutive strips divided by one layer of
+    interfacial nodes (the last strip takes what is left).  Every interfacial
+    node borders exactly the two strips on either side of its layer.
+
+    Returns ``label`` (int32 [n]: strip of every inner node, -1 on separator
+    layers), ``iface`` (int32, ascending node ids) and ``sides`` (int32
+    [len(iface), 2]: the strips before and after the node's layer)."""
+    dims = tuple(int(d) for d in dims)
+    nx = dims[-1]
+    lay = np.full(nx, -1, dtype=np.int64)     # strip of each layer, -1 for a separator
+    sep_of = np.full(nx, -1, dtype=np.int64)  # index of each separator layer
+    x, strip, sep = 0, 0, 0
+    while x < nx:
+        w = min(width, nx - x)
+        lay[x:x + w] = strip
+        x += w
+        if x < nx - 1:                        # a separator needs a strip after it
+            sep_of[x] = sep
+            sep += 1
+            x += 1
+        strip += 1
+    xs = np.broadcast_to(np.arange(nx), dims).ravel()
+    label = lay[xs].astype(np.int32)
+    iface = np.nonzero(label < 0)[0].astype(np.int32)
+    k = sep_of[xs[iface]]
+    sides = np.stack([k, k + 1], axis=1).astype(np.int32)
+    return label, iface, sides
+
+
 def _widths(length: int, b):
     if isinstance(b, (int, np.integer)):
         full, rest = divmod(length, int(b))

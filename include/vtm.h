@@ -212,6 +212,48 @@ vtm_status vtm_setup_vertex(const vtm_csr *A, const int32_t *label, const int32_
                             const vtm_options *opt, void *stream, vtm_handle *out);
 
 /*
+ * vtm_setup_vertex_coupled -- as vtm_setup_vertex, with coupled lines: one
+ * characteristic admittance matrix W over the interfacial nodes (eqs. 4-5;
+ * the overlapped-block rules of Section VIII give such a W).
+ *
+ *   W   host CSR, n_iface x n_iface, in iface order (duplicates summed):
+ *       symmetric, positive diagonal; W_lm != 0 (l != m) only where iface[l]
+ *       and iface[m] border the same two sub-circuits in the same order
+ *       (sides[l] == sides[m]), else VTM_E_ARG.  W should be positive
+ *       definite (the paper's requirement for resistor networks); it is not
+ *       checked, an indefinite W may make a sub-circuit singular or the
+ *       iteration diverge.
+ *
+ * W joins the twins of each side inside their sub-circuit (its block is added
+ * to the sub-circuit matrix), and the outgoing waves of a sub-circuit are
+ * 2 W u_twins - a (the oracle's coupled-line sweep).  The port-to-port form is
+ * the dense one (local_form 1 and 2 alike); the packed and port-node forms
+ * need diagonal lines.  Everything else as for vtm_setup_vertex.
+ */
+vtm_status vtm_setup_vertex_coupled(const vtm_csr *A, const int32_t *label, const int32_t *iface,
+                                    const int32_t *sides, int64_t n_iface, const vtm_csr *W,
+                                    const vtm_options *opt, void *stream, vtm_handle *out);
+
+/*
+ * vtm_vertex_admittance -- host-only: W for tearing at interfacial nodes under
+ * a rule of Section VIII, as an n_iface x n_iface CSR in iface order for
+ * vtm_setup_vertex_coupled.  C is the interface block of one side of the
+ * torn system (vtm_split_vertex): the entries between the twins that lie in
+ * sides[l][side] (the paper's C_1 for side 0, C_2 for side 1), symmetrized
+ * as (C + C^T) / 2 (C itself when A is symmetric).
+ *   kind  VTM_W_SCALED_MEAN: alpha * (mean conductance of A's branches) * I;
+ *         VTM_W_IDENTITY: alpha I;  VTM_W_DIAG: diag(C);  VTM_W_OB: C;
+ *         VTM_W_WOB: alpha C.
+ *   nnz, rowptr [n_iface + 1], col [nnz], val [nnz]: outputs, caller-owned,
+ *         NULLs skipped (call once with NULL arrays for nnz); columns sorted.
+ * Errors: VTM_E_ARG (alpha <= 0, bad kind or side, a non-positive diagonal of
+ * C), the tearing errors of vtm_setup_vertex.
+ */
+vtm_status vtm_vertex_admittance(const vtm_csr *A, const int32_t *label, const int32_t *iface,
+                                 const int32_t *sides, int64_t n_iface, int32_t kind, double alpha,
+                                 int32_t side, int64_t *nnz, int64_t *rowptr, int32_t *col, double *val);
+
+/*
  * vtm_solve -- run VTM sweeps (Section VI, eqs. 11 and 14) from zero boundary
  * variables until every column has ||b - A x||_2 / ||b||_2 <= tol, the
  * residual taken on the untorn A in FP64 every opt.check_every sweeps.
@@ -280,19 +322,22 @@ void vtm_destroy(vtm_handle h);
 const char *vtm_status_str(vtm_status s);
 const char *vtm_last_error(void);
 
-/* Line admittance rules for vtm_line_admittance (the preconditioners of
- * Section VIII).  With wire tearing each cut wire's interfacial node is its
- * midpoint m (a branch g becomes 2g + 2g through m); the two twins of m are
- * not coupled to any other interface node, so the interface block C of either
- * side is diagonal with the twin's 2g, and every rule below gives one W per
- * wire.  The coupled Schur-complement approximation (rule 5 of Section VIII)
- * is not provided. */
+/* Line admittance rules for vtm_line_admittance and vtm_vertex_admittance
+ * (the preconditioners of Section VIII).  With the cut-wire tearing of
+ * vtm_setup each cut wire's interfacial node is its midpoint m (a branch g
+ * becomes 2g + 2g through m); the two twins of m are not coupled to any other
+ * interface node, so the interface block C of either side is diagonal with
+ * the twin's 2g, and every rule below gives one W per wire (DIAG = OB there).
+ * Tearing at interfacial nodes gives a C with off-diagonal entries (branches
+ * between interfacial nodes), hence coupled lines for OB and WOB.  The
+ * Schur-complement approximation (rule 5) is not provided. */
 typedef enum {
     VTM_W_SCALED_MEAN = 0,  /* W_e = alpha * mean conductance of A's branches      */
     VTM_W_IDENTITY = 1,     /* W = alpha I (rule 1), alpha in siemens               */
     VTM_W_OB = 2,           /* W = C, the overlapped block (rule 3): W_e = 2 g_e;
                                the diagonal rule (2) gives the same here          */
-    VTM_W_WOB = 3           /* W = alpha C, weighted overlapped block (rule 4)       */
+    VTM_W_WOB = 3,          /* W = alpha C, weighted overlapped block (rule 4)       */
+    VTM_W_DIAG = 4          /* W = diag(C), the diagonal preconditioner (rule 2)      */
 } vtm_admittance_rule;
 
 /*

@@ -25,7 +25,7 @@ STATUS = ["VTM_OK", "VTM_E_ARG", "VTM_E_UNTEARABLE", "VTM_E_SINGULAR", "VTM_E_DI
 EXPORTS = ["vtm_default_options", "vtm_setup", "vtm_solve", "vtm_solve_adjoint", "vtm_grad",
            "vtm_get_waves", "vtm_set_waves", "vtm_info", "vtm_destroy", "vtm_status_str",
            "vtm_last_error", "vtm_plan", "vtm_line_admittance", "vtm_setup_vertex",
-           "vtm_split_vertex"]
+           "vtm_split_vertex", "vtm_setup_vertex_coupled", "vtm_vertex_admittance"]
 
 
 class VTMError(RuntimeError):
@@ -104,6 +104,14 @@ def lib() -> C.CDLL:
                                    C.POINTER(C.c_int32), i64, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
                                    C.POINTER(C.c_int32), dp, C.POINTER(C.c_int32)]
     L.vtm_split_vertex.restype = C.c_int
+    L.vtm_setup_vertex_coupled.argtypes = [C.POINTER(Csr), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                           C.POINTER(C.c_int32), i64, C.POINTER(Csr), C.POINTER(Options), vp,
+                                           C.POINTER(vp)]
+    L.vtm_setup_vertex_coupled.restype = C.c_int
+    L.vtm_vertex_admittance.argtypes = [C.POINTER(Csr), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_int32), i64, C.c_int32, C.c_double, C.c_int32,
+                                        C.POINTER(i64), C.POINTER(i64), C.POINTER(C.c_int32), dp]
+    L.vtm_vertex_admittance.restype = C.c_int
     _lib = L
     return L
 
@@ -179,7 +187,29 @@ def split_vertex(A, label, iface, sides):
     return M, part
 
 
-ADMITTANCE_RULES = {"scaled_mean": 0, "identity": 1, "ob": 2, "wob": 3}
+ADMITTANCE_RULES = {"scaled_mean": 0, "identity": 1, "ob": 2, "wob": 3, "diag": 4}
+
+
+def vertex_admittance(A, label, iface, sides, rule="ob", alpha=1.0, side=0):
+    """W over the interfacial nodes under a rule of Section VIII
+    (vtm_vertex_admittance), as a scipy CSR matrix in iface order."""
+    import scipy.sparse as sp
+    L = lib()
+    hc = _HostCsr(A)
+    i32p = C.POINTER(C.c_int32)
+    label = np.ascontiguousarray(label, dtype=np.int32)
+    iface = np.ascontiguousarray(iface, dtype=np.int32)
+    sides = np.ascontiguousarray(sides, dtype=np.int32).reshape(-1, 2)
+    args = (C.byref(hc.s), label.ctypes.data_as(i32p), iface.ctypes.data_as(i32p), sides.ctypes.data_as(i32p),
+            iface.size, ADMITTANCE_RULES[rule], float(alpha), int(side))
+    nnz = C.c_int64()
+    _check(L.vtm_vertex_admittance(*args, C.byref(nnz), None, None, None))
+    rowptr = np.zeros(iface.size + 1, dtype=np.int64)
+    col = np.zeros(nnz.value, dtype=np.int32)
+    val = np.zeros(nnz.value, dtype=np.float64)
+    _check(L.vtm_vertex_admittance(*args, None, rowptr.ctypes.data_as(C.POINTER(C.c_int64)),
+                                   col.ctypes.data_as(i32p), val.ctypes.data_as(C.POINTER(C.c_double))))
+    return sp.csr_matrix((val, col, rowptr), shape=(iface.size, iface.size))
 
 
 def line_admittance(A, part, rule="scaled_mean", alpha=1.0):
@@ -222,13 +252,14 @@ class Solver:
     With ``iface`` and ``sides`` given, the circuit is torn at those interfacial
     nodes instead (vtm_setup_vertex): ``part`` then labels the inner nodes and
     ``Z`` is the impedance of each twin-joining line (scalar or per interfacial
-    node).
+    node); or ``W``, a scipy sparse admittance matrix over the interfacial
+    nodes, couples the lines (vtm_setup_vertex_coupled; Z is then ignored).
     """
 
     def __init__(self, A, part, Z, precision="fp64", nrhs_max=1, check_every=8,
                  max_sweeps=1_000_000, divergence=1e6, inner_drop=0.0, max_outer=30,
                  use_graph=False, timing=False, adaptive_checks=True, batch_shape=(0, 0), local_form="port",
-                 stream=None, iface=None, sides=None):
+                 stream=None, iface=None, sides=None, W=None):
         import torch
         L = lib()
         if not torch.cuda.is_available():
@@ -266,11 +297,18 @@ class Solver:
             sides = np.ascontiguousarray(sides, dtype=np.int32).reshape(-1, 2)
             if sides.shape[0] != iface.size:
                 raise ValueError("sides must hold two sub-circuits per interfacial node")
-            w, wp, nw_ = _z_array(1.0 / np.asarray(Z, dtype=np.float64))
             i32p = C.POINTER(C.c_int32)
-            _check(L.vtm_setup_vertex(C.byref(hc.s), part.ctypes.data_as(i32p), iface.ctypes.data_as(i32p),
-                                      sides.ctypes.data_as(i32p), iface.size, wp, nw_, C.byref(opt),
-                                      C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+            if W is not None:
+                wc = _HostCsr(W)
+                _check(L.vtm_setup_vertex_coupled(C.byref(hc.s), part.ctypes.data_as(i32p),
+                                                  iface.ctypes.data_as(i32p), sides.ctypes.data_as(i32p),
+                                                  iface.size, C.byref(wc.s), C.byref(opt),
+                                                  C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+            else:
+                w, wp, nw_ = _z_array(1.0 / np.asarray(Z, dtype=np.float64))
+                _check(L.vtm_setup_vertex(C.byref(hc.s), part.ctypes.data_as(i32p), iface.ctypes.data_as(i32p),
+                                          sides.ctypes.data_as(i32p), iface.size, wp, nw_, C.byref(opt),
+                                          C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
         n, ns, nw, kb, pb, sb = (C.c_int64() for _ in range(6))
         _check(L.vtm_info(h, C.byref(n), C.byref(ns), C.byref(nw), C.byref(kb), C.byref(pb), C.byref(sb)))

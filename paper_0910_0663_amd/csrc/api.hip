@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <numeric>
+#include <type_traits>
 #include <array>
 #include <chrono>
 #include <map>
@@ -95,6 +96,10 @@ struct vtm_handle_s {
     DevBuf<int32_t> vx_src, vr0, vr1, orow, ocol, oid;
     DevBuf<double> vx_w, oval, bo, ro, xo;
     const double* b_user = nullptr;
+    // coupled lines: B = 2 W over the ports (CSR) and each port's plan row
+    DevBuf<int32_t> brow, bcol, port_row;
+    DevBuf<double> bval64;
+    DevBuf<float> bval32;
     // residual checks from port quantities (port-to-port form): g and G - g per port
     DevBuf<double> pg64, pgd64;
     // batched port-to-port form (MFMA tiles): q x q operators in A-tile order
@@ -135,6 +140,19 @@ struct vtm_handle_s {
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
         if (gready) (void)hipEventDestroy(gready);
         if (gstream) (void)hipStreamDestroy(gstream);
+    }
+
+    template <typename T>
+    vtm::Coupling<T> coupling() const {
+        vtm::Coupling<T> B;
+        if (!plan.coupled) return B;
+        B.row = brow.p;
+        B.col = bcol.p;
+        if constexpr (std::is_same_v<T, double>)
+            B.val = bval64.p;
+        else
+            B.val = bval32.p;
+        return B;
     }
 
     vtm::PortArrays ports() const {
@@ -350,8 +368,20 @@ vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
             VTM_HIP((vtm::launch_sweep_pp<float, float>(int(P.S), P.max_ports, h->M32.p, h->pofs.p, h->port_off.p,
                                                         h->port_twin.p, h->h32.p, h->a32[cur].p, h->a32[cur ^ 1].p,
                                                         h->stream)));
-    } else if ((st = launch_one(h, low, nrhs, b, x, cur, adjoint, h->mfma_variant, h->mfma_rc, write_x)) != VTM_OK) {
-        return st;
+    } else {
+        if ((st = launch_one(h, low, nrhs, b, x, cur, adjoint, h->mfma_variant, h->mfma_rc, write_x)) != VTM_OK)
+            return st;
+        const vtm::Plan& P = h->plan;
+        if (P.coupled) {  // the waves of coupled lines need W over the port rows of x
+            if (!low)
+                VTM_HIP(vtm::launch_wave_coupled<double>(int(P.nports), nrhs, h->coupling<double>(), h->port_row.p,
+                                                         h->gamma64.p, h->port_twin.p, static_cast<const double*>(x),
+                                                         h->a64[cur].p, h->a64[cur ^ 1].p, h->stream));
+            else
+                VTM_HIP(vtm::launch_wave_coupled<float>(int(P.nports), nrhs, h->coupling<float>(), h->port_row.p,
+                                                        h->gamma32.p, h->port_twin.p, static_cast<const float*>(x),
+                                                        h->a32[cur].p, h->a32[cur ^ 1].p, h->stream));
+        }
     }
     if (timed) return timing_event(h, &e1, pp ? 1 : 0);
     return VTM_OK;
@@ -362,10 +392,10 @@ vtm_status port_h(vtm_handle h, bool low, int nrhs) {
     const vtm::Plan& P = h->plan;
     if (!low)
         VTM_HIP(vtm::launch_port_h<double>(int(P.S), nrhs, h->sub_off.p, h->port_off.p, h->port_node.p, h->beta64.p,
-                                           h->xp.p, h->h64.p, h->stream));
+                                           h->xp.p, h->h64.p, h->stream, h->coupling<double>()));
     else
         VTM_HIP(vtm::launch_port_h<float>(int(P.S), nrhs, h->sub_off.p, h->port_off.p, h->port_node.p, h->beta32.p,
-                                          h->d32.p, h->h32.p, h->stream));
+                                          h->d32.p, h->h32.p, h->stream, h->coupling<float>()));
     return VTM_OK;
 }
 
@@ -895,11 +925,34 @@ vtm_status vtm_split_vertex(const vtm_csr* A, const int32_t* label, const int32_
     return VTM_OK;
 }
 
+// mean conductance of A's two-terminal branches (symmetric negative off-diagonal
+// pairs, each counted once); false when there is none
+static bool mean_branch(const vtm_csr* A, double& mean) {
+    double sum = 0.0;
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < A->n; ++i)
+        for (int64_t q = A->rowptr[i]; q < A->rowptr[i + 1]; ++q) {
+            const int64_t j = A->col[q];
+            const double v = A->val[q];
+            if (j <= i || !(v < 0.0)) continue;
+            double vt = 0.0;
+            for (int64_t r = A->rowptr[j]; r < A->rowptr[j + 1]; ++r)
+                if (A->col[r] == i) vt += A->val[r];
+            if (vt == v) {
+                sum += -v;
+                ++cnt;
+            }
+        }
+    if (cnt == 0) return false;
+    mean = sum / double(cnt);
+    return true;
+}
+
 vtm_status vtm_line_admittance(const vtm_csr* A, const int32_t* part, int32_t kind, double alpha, double* W,
                                int64_t n_wires) {
     if (!W) return fail(VTM_E_ARG, "null output");
     if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(VTM_E_ARG, "alpha must be positive");
-    if (kind < VTM_W_SCALED_MEAN || kind > VTM_W_WOB) return fail(VTM_E_ARG, "unknown admittance rule");
+    if (kind < VTM_W_SCALED_MEAN || kind > VTM_W_DIAG) return fail(VTM_E_ARG, "unknown admittance rule");
     vtm::Plan P;
     std::string err;
     const double one = 1.0;
@@ -907,40 +960,70 @@ vtm_status vtm_line_admittance(const vtm_csr* A, const int32_t* part, int32_t ki
     if (st != VTM_OK) return fail(st, err);
     if (n_wires != P.nwires) return fail(VTM_E_ARG, "n_wires does not match the partition's cut wires");
     double mean = 0.0;
-    if (kind == VTM_W_SCALED_MEAN) {
-        // every two-terminal branch of A: a symmetric negative off-diagonal pair, counted once
-        double sum = 0.0;
-        int64_t cnt = 0;
-        for (int64_t i = 0; i < A->n; ++i)
-            for (int64_t q = A->rowptr[i]; q < A->rowptr[i + 1]; ++q) {
-                const int64_t j = A->col[q];
-                const double v = A->val[q];
-                if (j <= i || !(v < 0.0)) continue;
-                double vt = 0.0;
-                for (int64_t r = A->rowptr[j]; r < A->rowptr[j + 1]; ++r)
-                    if (A->col[r] == i) vt += A->val[r];
-                if (vt == v) {
-                    sum += -v;
-                    ++cnt;
-                }
-            }
-        if (cnt == 0) return fail(VTM_E_ARG, "A has no two-terminal branch");
-        mean = sum / double(cnt);
-    }
+    if (kind == VTM_W_SCALED_MEAN && !mean_branch(A, mean)) return fail(VTM_E_ARG, "A has no two-terminal branch");
     for (int64_t e = 0; e < P.nwires; ++e) {
         const double g = P.wg[e];
         switch (kind) {
             case VTM_W_SCALED_MEAN: W[e] = alpha * mean; break;
             case VTM_W_IDENTITY: W[e] = alpha; break;
-            case VTM_W_OB: W[e] = 2.0 * g; break;
+            case VTM_W_OB:
+            case VTM_W_DIAG: W[e] = 2.0 * g; break;
             default: W[e] = alpha * 2.0 * g; break;
         }
     }
     return VTM_OK;
 }
 
-vtm_status check_options(const vtm_options& o);
-vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* out);
+vtm_status vtm_vertex_admittance(const vtm_csr* A, const int32_t* label, const int32_t* iface, const int32_t* sides,
+                                 int64_t n_iface, int32_t kind, double alpha, int32_t side, int64_t* nnz,
+                                 int64_t* rowptr, int32_t* col, double* val) {
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(VTM_E_ARG, "alpha must be positive");
+    if (kind < VTM_W_SCALED_MEAN || kind > VTM_W_DIAG) return fail(VTM_E_ARG, "unknown admittance rule");
+    if (side != 0 && side != 1) return fail(VTM_E_ARG, "side must be 0 or 1");
+    vtm::VertexSplit X;
+    std::string err;
+    vtm_status st = vtm::split_at_vertices(A, label, iface, sides, n_iface, X, err);
+    if (st != VTM_OK) return fail(st, err);
+    const int64_t n = X.n, L = n_iface;
+    // C: the block of the torn matrix over the twins on the chosen side (line ids),
+    // symmetrized (W must be symmetric; C is when A is)
+    std::vector<std::map<int32_t, double>> C(L);
+    if (kind == VTM_W_SCALED_MEAN || kind == VTM_W_IDENTITY) {
+        double mean = 1.0;
+        if (kind == VTM_W_SCALED_MEAN && !mean_branch(A, mean)) return fail(VTM_E_ARG, "A has no two-terminal branch");
+        for (int64_t l = 0; l < L; ++l) C[l][int32_t(l)] = alpha * mean;
+    } else {
+        std::vector<int64_t> line_of(n + L, -1);
+        for (int64_t l = 0; l < L; ++l) line_of[side ? n + l : iface[l]] = l;
+        for (int64_t l = 0; l < L; ++l) {
+            const int64_t r = side ? n + l : iface[l];
+            for (int64_t q = X.rowptr[r]; q < X.rowptr[r + 1]; ++q) {
+                const int64_t m = line_of[X.col[q]];
+                if (m < 0 || (kind == VTM_W_DIAG && m != l)) continue;
+                const double w = (kind == VTM_W_WOB ? alpha : 1.0) * 0.5 * X.val[q];
+                C[l][int32_t(m)] += w;
+                C[m][int32_t(l)] += w;
+            }
+        }
+        for (int64_t l = 0; l < L; ++l)
+            if (!(C[l][int32_t(l)] > 0.0)) return fail(VTM_E_ARG, "the interface block has a non-positive diagonal");
+    }
+    int64_t k = 0;
+    if (rowptr) rowptr[0] = 0;
+    for (int64_t l = 0; l < L; ++l) {
+        for (const auto& e : C[l]) {
+            if (col) col[k] = e.first;
+            if (val) val[k] = e.second;
+            ++k;
+        }
+        if (rowptr) rowptr[l + 1] = k;
+    }
+    if (nnz) *nnz = k;
+    return VTM_OK;
+}
+
+static vtm_status check_options(const vtm_options& o);
+static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* out);
 
 vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int64_t nZ,
                      const vtm_options* opt, void* stream, vtm_handle* out) {
@@ -961,9 +1044,19 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     return setup_from_plan(std::move(h), out);
 }
 
+static vtm_status setup_vertex_common(const vtm_csr* A, const int32_t* label, const int32_t* iface, const int32_t* sides,
+                               int64_t n_iface, const double* W, int64_t nW, const vtm_csr* Wc,
+                               const vtm_options* opt, void* stream, vtm_handle* out);
+
 vtm_status vtm_setup_vertex(const vtm_csr* A, const int32_t* label, const int32_t* iface, const int32_t* sides,
                             int64_t n_iface, const double* W, int64_t nW, const vtm_options* opt, void* stream,
                             vtm_handle* out) {
+    return setup_vertex_common(A, label, iface, sides, n_iface, W, nW, nullptr, opt, stream, out);
+}
+
+static vtm_status setup_vertex_common(const vtm_csr* A, const int32_t* label, const int32_t* iface, const int32_t* sides,
+                               int64_t n_iface, const double* W, int64_t nW, const vtm_csr* Wc,
+                               const vtm_options* opt, void* stream, vtm_handle* out) {
     if (!out) return fail(VTM_E_ARG, "null output handle");
     *out = nullptr;
     vtm_options o;
@@ -976,7 +1069,7 @@ vtm_status vtm_setup_vertex(const vtm_csr* A, const int32_t* label, const int32_
     h->nrhs_max = o.nrhs_max;
     h->stream = static_cast<hipStream_t>(stream);
     std::string err;
-    st = vtm::build_plan_vertex(A, label, iface, sides, n_iface, W, nW, h->plan, err);
+    st = vtm::build_plan_vertex(A, label, iface, sides, n_iface, W, nW, h->plan, err, Wc);
     if (st != VTM_OK) return fail(st, err);
     const vtm::Plan& P = h->plan;
     hipStream_t s = h->stream;
@@ -999,7 +1092,14 @@ vtm_status vtm_setup_vertex(const vtm_csr* A, const int32_t* label, const int32_
     return setup_from_plan(std::move(h), out);
 }
 
-vtm_status check_options(const vtm_options& o) {
+vtm_status vtm_setup_vertex_coupled(const vtm_csr* A, const int32_t* label, const int32_t* iface,
+                                    const int32_t* sides, int64_t n_iface, const vtm_csr* W, const vtm_options* opt,
+                                    void* stream, vtm_handle* out) {
+    if (!W) return fail(VTM_E_ARG, "null W");
+    return setup_vertex_common(A, label, iface, sides, n_iface, nullptr, 0, W, opt, stream, out);
+}
+
+static vtm_status check_options(const vtm_options& o) {
     if (o.precision < VTM_FP64 || o.precision > VTM_BF16_REFINE)
         return fail(VTM_E_ARG, "unknown precision");
     if (o.nrhs_max < 1 || o.nrhs_max > 256) return fail(VTM_E_ARG, "nrhs_max outside 1..256");
@@ -1013,7 +1113,7 @@ vtm_status check_options(const vtm_options& o) {
     return VTM_OK;
 }
 
-vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* out) {
+static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* out) {
     const vtm_options& o = h->opt;
     vtm_status st = VTM_OK;
     VTM_HIP(hipGetDevice(&h->device));
@@ -1075,6 +1175,13 @@ vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* out) {
     VTM_HIP(h->c64.upload(P.pc, s));
     VTM_HIP(h->beta64.upload(P.pbeta, s));
     VTM_HIP(h->gamma64.upload(P.pgamma, s));
+    if (P.coupled) {
+        VTM_HIP(h->brow.upload(P.brow, s));
+        VTM_HIP(h->bcol.upload(P.bcol, s));
+        VTM_HIP(h->port_row.upload(P.port_row, s));
+        VTM_HIP(h->bval64.upload(P.bval, s));
+        if (o.precision != VTM_FP64) VTM_HIP(h->bval32.upload(to_float(P.bval), s));
+    }
     if (o.precision == VTM_FP64) {
         VTM_HIP(h->a64[0].alloc(P.nports * nr));
         VTM_HIP(h->a64[1].alloc(P.nports * nr));
@@ -1120,9 +1227,11 @@ vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* out) {
     if (flag & 1) return fail(VTM_E_SINGULAR, "a sub-circuit matrix is singular");
     // port-to-port operators from the stored inverses
     h->pp = o.local_form >= 1 && !h->tiles && P.nports > 0;
-    h->pps = h->pp && o.local_form == 1 && P.symmetric && P.max_npn <= 64 && P.max_ports <= 64;
+    // the port-node forms assume diagonal lines (beta and gamma per port)
+    h->pps = h->pp && !P.coupled && o.local_form == 1 && P.symmetric && P.max_npn <= 64 && P.max_ports <= 64;
     const size_t ppn_lds = 2 * size_t(P.max_npn) * (o.precision == VTM_FP64 ? 8 : 4) + size_t(P.max_ports) * 4;
-    h->ppn = h->pp && !h->pps && o.local_form == 1 && P.sqn_entries < P.sq_entries && ppn_lds <= 65536;
+    h->ppn = h->pp && !h->pps && !P.coupled && o.local_form == 1 && P.sqn_entries < P.sq_entries &&
+             ppn_lds <= 65536;
     // batched form: port-to-port operators in tile order, built from the FP64 inverses in scratch
     const int qpad = vtm::tile_pad(P.max_ports);
     h->ppb = o.local_form >= 1 && h->tiles && P.nports > 0 &&
@@ -1136,13 +1245,13 @@ vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* out) {
             VTM_HIP(h->h64.alloc(P.nports * nr));
             VTM_HIP(vtm::launch_port_matrix_tiles<double>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p,
                                                           h->port_node.p, h->c64.p, h->beta64.p, h->gamma64.p,
-                                                          scratch.p, h->qmofs.p, h->M64t.p, s));
+                                                          scratch.p, h->qmofs.p, h->M64t.p, s, h->coupling<double>()));
         } else {
             VTM_HIP(h->Mbt.alloc(nq));
             VTM_HIP(h->h32.alloc(P.nports * nr));
             VTM_HIP(vtm::launch_port_matrix_tiles<__bf16>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p,
                                                           h->port_node.p, h->c64.p, h->beta64.p, h->gamma64.p,
-                                                          scratch.p, h->qmofs.p, h->Mbt.p, s));
+                                                          scratch.p, h->qmofs.p, h->Mbt.p, s, h->coupling<double>()));
         }
         VTM_HIP(hipStreamSynchronize(s));
     }
@@ -1212,13 +1321,13 @@ vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* out) {
             VTM_HIP(h->h64.alloc(P.nports));
             VTM_HIP(vtm::launch_port_matrix<double>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p, h->port_node.p,
                                                     h->c64.p, h->beta64.p, h->gamma64.p, h->K64.p, h->pofs.p,
-                                                    h->M64.p, s));
+                                                    h->M64.p, s, h->coupling<double>()));
         } else {
             VTM_HIP(h->M32.alloc(npm));
             VTM_HIP(h->h32.alloc(P.nports));
             VTM_HIP(vtm::launch_port_matrix<float>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p, h->port_node.p,
                                                    h->c64.p, h->beta64.p, h->gamma64.p, h->K32.p, h->pofs.p,
-                                                   h->M32.p, s));
+                                                   h->M32.p, s, h->coupling<double>()));
         }
         VTM_HIP(hipStreamSynchronize(s));
     }

@@ -14,6 +14,16 @@ namespace vtm {
 // Largest sub-circuit whose local matrix is factored entirely in LDS.
 constexpr int kLdsSetupMax = 80;
 
+// Coupled lines: the outgoing wave of port p is sum_k val[k] x_node(col[k]) +
+// gamma_p a_p over k in [row[p], row[p + 1]) (B = 2 W over the ports of p's
+// sub-circuit).  row == nullptr: diagonal lines, B = diag(beta).
+template <typename T>
+struct Coupling {
+    const int32_t* row = nullptr;
+    const int32_t* col = nullptr;
+    const T* val = nullptr;
+};
+
 struct PortArrays {
     const int32_t* off;    // [S + 1]
     const int32_t* node;   // local node of each port
@@ -87,7 +97,7 @@ template <typename T>
 hipError_t launch_port_matrix_tiles(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* port_off,
                                     const int32_t* port_node, const double* pc, const double* pbeta,
                                     const double* pgamma, const double* Kinv, const int64_t* qmofs, T* out,
-                                    hipStream_t st);
+                                    hipStream_t st, Coupling<double> B = {});
 
 // ---- port-to-port form (ports.hip) -------------------------------------------
 // M_s = diag(beta) K^-1[i(P), i(P)] diag(c) + diag(gamma) for every sub-circuit,
@@ -96,11 +106,18 @@ hipError_t launch_port_matrix_tiles(int S, const int32_t* sub_off, const int64_t
 template <typename TO>
 hipError_t launch_port_matrix(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* port_off,
                               const int32_t* port_node, const double* pc, const double* pbeta,
-                              const double* pgamma, const TO* K, const int64_t* pofs, TO* M, hipStream_t st);
-// h_p = beta_p x_i(p) (one right-hand side; x renumbered)
+                              const double* pgamma, const TO* K, const int64_t* pofs, TO* M, hipStream_t st,
+                              Coupling<double> B = {});
+// h_p = beta_p x_i(p), or (B x)_p with coupled lines (x renumbered)
 template <typename TV>
 hipError_t launch_port_h(int S, int nrhs, const int32_t* sub_off, const int32_t* port_off, const int32_t* port_node,
-                         const TV* pbeta, const TV* x, TV* h, hipStream_t st);
+                         const TV* pbeta, const TV* x, TV* h, hipStream_t st, Coupling<TV> B = {});
+// Coupled lines, after a full sweep: a_next[twin(p)] = sum_m B_pm x_row(m) +
+// gamma_p a_cur[p] for every port and right-hand side (replaces the diagonal
+// waves the sweep wrote; x and waves [rows][nrhs]).
+template <typename TV>
+hipError_t launch_wave_coupled(int n_ports, int nrhs, Coupling<TV> B, const int32_t* port_row, const TV* pgamma,
+                               const int32_t* port_twin, const TV* x, const TV* a_cur, TV* a_next, hipStream_t st);
 // a_next[twin(p)] = h_p + (M_s a_cur)_p for every port (one right-hand side)
 template <typename TO, typename TV>
 hipError_t launch_sweep_pp(int S, int max_q, const TO* M, const int64_t* pofs, const int32_t* port_off,

@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(kBlock)
                         const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_node,
                         const double* __restrict__ pc, const double* __restrict__ pbeta,
                         const double* __restrict__ pgamma, const double* __restrict__ Kinv,
-                        const int64_t* __restrict__ qmofs, T* __restrict__ out) {
+                        const int64_t* __restrict__ qmofs, T* __restrict__ out, Coupling<double> B) {
     const int s = blockIdx.x;
     const int ns = sub_off[s + 1] - sub_off[s];
     const int p0 = port_off[s], q = port_off[s + 1] - p0;
@@ -308,7 +308,14 @@ __global__ void __launch_bounds__(kBlock)
         double v = 0.0;
         if (r < q && c < q) {
             const int i = port_node[p0 + r], j = port_node[p0 + c];
-            v = pbeta[p0 + r] * Ks[int64_t(j) * ns + i] * pc[p0 + c] + (r == c ? pgamma[p0 + r] : 0.0);
+            if (B.row) {  // (B Kinv[P, P])_{r c} with B's row r over this sub-circuit's ports
+                for (int k = B.row[p0 + r]; k < B.row[p0 + r + 1]; ++k)
+                    v += B.val[k] * Ks[int64_t(j) * ns + port_node[B.col[k]]];
+                v *= pc[p0 + c];
+            } else {
+                v = pbeta[p0 + r] * Ks[int64_t(j) * ns + i] * pc[p0 + c];
+            }
+            if (r == c) v += pgamma[p0 + r];
         }
         o[d] = static_cast<T>(v);
     }
@@ -430,9 +437,9 @@ template <typename T>
 hipError_t launch_port_matrix_tiles(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* port_off,
                                     const int32_t* port_node, const double* pc, const double* pbeta,
                                     const double* pgamma, const double* Kinv, const int64_t* qmofs, T* out,
-                                    hipStream_t st) {
+                                    hipStream_t st, Coupling<double> B) {
     hipLaunchKernelGGL(k_port_matrix_tiles<T>, dim3(S), dim3(kBlock), 0, st, sub_off, kofs, port_off, port_node, pc,
-                       pbeta, pgamma, Kinv, qmofs, out);
+                       pbeta, pgamma, Kinv, qmofs, out, B);
     return hipGetLastError();
 }
 
@@ -444,10 +451,12 @@ template hipError_t launch_sweep_mfma_pp<double>(int, int, int, int, int, size_t
                                                 double*, hipStream_t);
 template hipError_t launch_port_matrix_tiles<__bf16>(int, const int32_t*, const int64_t*, const int32_t*,
                                                     const int32_t*, const double*, const double*, const double*,
-                                                    const double*, const int64_t*, __bf16*, hipStream_t);
+                                                    const double*, const int64_t*, __bf16*, hipStream_t,
+                                                    Coupling<double>);
 template hipError_t launch_port_matrix_tiles<double>(int, const int32_t*, const int64_t*, const int32_t*,
                                                     const int32_t*, const double*, const double*, const double*,
-                                                    const double*, const int64_t*, double*, hipStream_t);
+                                                    const double*, const int64_t*, double*, hipStream_t,
+                                                    Coupling<double>);
 template hipError_t launch_sweep_mfma<__bf16>(int, int, int, int, int, int, size_t, const __bf16*, const int64_t*,
                                              const int32_t*, PortArrays, const float*, const float*, const float*,
                                              const __bf16*, const float*, float*, float*, bool, hipStream_t);

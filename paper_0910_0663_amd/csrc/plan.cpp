@@ -12,6 +12,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <limits>
 #include <numeric>
@@ -265,7 +266,8 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
         // a line between twins has no branch: its port adds W to the twin's row, the
         // wave enters whole (c = 1) and leaves as 2 W u - a (beta = 2 W, gamma = -1),
         // the limit of a cut branch whose g grows without bound
-        const PortCoef k = P.vertex ? PortCoef{P.wW[e], 1.0, 2.0 * P.wW[e], -1.0} : port_coef(P.wg[e], P.wW[e]);
+        const PortCoef k = P.vertex ? PortCoef{P.coupled ? 0.0 : P.wW[e], 1.0, 2.0 * P.wW[e], -1.0}
+                                    : port_coef(P.wg[e], P.wW[e]);
         P.pc[p] = k.c;
         P.pbeta[p] = k.beta;
         P.pgamma[p] = k.gamma;
@@ -513,8 +515,8 @@ vtm_status split_at_vertices(const vtm_csr* A, const int32_t* label, const int32
 }
 
 vtm_status build_plan_vertex(const vtm_csr* A, const int32_t* label, const int32_t* iface, const int32_t* sides,
-                             int64_t L, const double* W, int64_t nW, Plan& P, std::string& err) {
-    if (!W || (nW != 1 && nW != L)) {
+                             int64_t L, const double* W, int64_t nW, Plan& P, std::string& err, const vtm_csr* Wc) {
+    if (!Wc && (!W || (nW != 1 && nW != L))) {
         err = "nW must be 1 or the number of interfacial nodes";
         return VTM_E_ARG;
     }
@@ -523,21 +525,110 @@ vtm_status build_plan_vertex(const vtm_csr* A, const int32_t* label, const int32
     if (st != VTM_OK) return st;
     const int64_t n = X.n, N = n + L;
     std::vector<int32_t> la(L), lb(L);
-    std::vector<double> Z(nW);
     for (int64_t l = 0; l < L; ++l) {
         la[l] = iface[l];
         lb[l] = int32_t(n + l);
     }
-    for (int64_t l = 0; l < nW; ++l) {
-        if (!(W[l] > 0.0) || !std::isfinite(W[l])) {
-            err = "line admittance must be positive and finite";
+    std::vector<double> Z(Wc ? L : nW);
+    std::vector<int32_t> wr, wc;  // coupled W, merged and sorted (rows over lines)
+    std::vector<double> wv;
+    if (Wc) {
+        if (Wc->n != L || !Wc->rowptr || (Wc->nnz && (!Wc->col || !Wc->val)) || Wc->rowptr[0] != 0 ||
+            Wc->rowptr[L] != Wc->nnz) {
+            err = "W must be an n_iface x n_iface CSR";
             return VTM_E_ARG;
         }
-        Z[l] = 1.0 / W[l];
+        std::map<std::pair<int32_t, int32_t>, double> ent;
+        for (int64_t l = 0; l < L; ++l) {
+            if (Wc->rowptr[l + 1] < Wc->rowptr[l]) {
+                err = "W: rowptr must be non-decreasing";
+                return VTM_E_ARG;
+            }
+            for (int64_t q = Wc->rowptr[l]; q < Wc->rowptr[l + 1]; ++q) {
+                const int32_t m = Wc->col[q];
+                if (m < 0 || m >= L || !std::isfinite(Wc->val[q])) {
+                    err = "W: column out of range or non-finite entry";
+                    return VTM_E_ARG;
+                }
+                if (sides[2 * l] != sides[2 * m] || sides[2 * l + 1] != sides[2 * m + 1]) {
+                    err = "W couples interfacial nodes " + std::to_string(iface[l]) + " and " +
+                          std::to_string(iface[m]) + ", which do not border the same two sub-circuits in the same order";
+                    return VTM_E_ARG;
+                }
+                ent[{int32_t(l), m}] += Wc->val[q];
+            }
+        }
+        wr.assign(L + 1, 0);
+        for (const auto& e : ent) {
+            auto it = ent.find({e.first.second, e.first.first});
+            if (it == ent.end() || it->second != e.second) {
+                err = "W must be symmetric";
+                return VTM_E_ARG;
+            }
+            wc.push_back(e.first.second);
+            wv.push_back(e.second);
+            wr[e.first.first + 1]++;
+        }
+        for (int64_t l = 0; l < L; ++l) wr[l + 1] += wr[l];
+        for (int64_t l = 0; l < L; ++l) {
+            auto it = ent.find({int32_t(l), int32_t(l)});
+            if (it == ent.end() || !(it->second > 0.0)) {
+                err = "W needs a positive diagonal";
+                return VTM_E_ARG;
+            }
+            Z[l] = 1.0 / it->second;
+        }
+        // W between the twins on each side: rows of the torn matrix
+        std::vector<std::vector<std::pair<int32_t, double>>> rows(N);
+        for (int64_t r = 0; r < N; ++r)
+            for (int64_t q = X.rowptr[r]; q < X.rowptr[r + 1]; ++q) rows[r].push_back({X.col[q], X.val[q]});
+        for (int64_t l = 0; l < L; ++l)
+            for (int32_t q = wr[l]; q < wr[l + 1]; ++q) {
+                rows[la[l]].push_back({la[wc[q]], wv[q]});
+                rows[lb[l]].push_back({lb[wc[q]], wv[q]});
+            }
+        X.col.clear();
+        X.val.clear();
+        for (int64_t r = 0; r < N; ++r) {
+            for (const auto& e : rows[r]) {
+                X.col.push_back(e.first);
+                X.val.push_back(e.second);
+            }
+            X.rowptr[r + 1] = int64_t(X.col.size());
+        }
+        P.coupled = true;
+    } else {
+        for (int64_t l = 0; l < nW; ++l) {
+            if (!(W[l] > 0.0) || !std::isfinite(W[l])) {
+                err = "line admittance must be positive and finite";
+                return VTM_E_ARG;
+            }
+            Z[l] = 1.0 / W[l];
+        }
     }
     vtm_csr XA{N, int64_t(X.col.size()), X.rowptr.data(), X.col.data(), X.val.data()};
-    st = build_plan(&XA, X.part.data(), Z.data(), nW, P, err, la.data(), lb.data(), L);
+    st = build_plan(&XA, X.part.data(), Z.data(), int64_t(Z.size()), P, err, la.data(), lb.data(), L);
     if (st != VTM_OK) return st;
+    if (P.coupled) {
+        // B = 2 W over plan ports: port 2l + s (ABI) couples to 2m + s
+        const int64_t np = P.nports;
+        std::vector<int32_t> abi_of(np);
+        for (int64_t q = 0; q < np; ++q) abi_of[P.abi2port[q]] = int32_t(q);
+        P.brow.assign(np + 1, 0);
+        P.bcol.clear();
+        P.bval.clear();
+        for (int64_t p = 0; p < np; ++p) {
+            const int32_t q = abi_of[p], l = q >> 1, side = q & 1;
+            for (int32_t k = wr[l]; k < wr[l + 1]; ++k) {
+                P.bcol.push_back(P.abi2port[2 * wc[k] + side]);
+                P.bval.push_back(2.0 * wv[k]);
+            }
+            P.brow[p + 1] = int32_t(P.bcol.size());
+        }
+        P.port_row.resize(np);
+        for (int64_t s = 0; s < P.S; ++s)
+            for (int32_t p = P.port_off[s]; p < P.port_off[s + 1]; ++p) P.port_row[p] = P.sub_off[s] + P.port_node[p];
+    }
     // maps between the plan rows and the caller's nodes
     P.n_orig = n;
     std::vector<char> is_if(n, 0);

@@ -73,6 +73,16 @@ struct Plan {
     std::vector<int32_t> vr0, vr1; // per original node: its plan row(s); vr1 = -1 unless a twin pair
     std::vector<int32_t> orow, ocol;  // the caller's A, duplicates merged (residual on the untorn system)
     std::vector<double> oval;
+
+    // Coupled lines (a non-diagonal W over the interfacial nodes, eqs. 4-5): W is
+    // part of the torn matrix (added between the twins of each side), so the
+    // ports add no conductance (G = 0, c = 1, gamma = -1), and the outgoing wave
+    // of port p is sum_m B_pm u_node(m) - a_p with B = 2 W, rows and columns
+    // over the plan's ports (m in p's sub-circuit).  pbeta keeps B's diagonal.
+    bool coupled = false;
+    std::vector<int32_t> brow, bcol;  // CSR of B over plan ports
+    std::vector<double> bval;
+    std::vector<int32_t> port_row;    // plan row of every port's node
 };
 
 // Builds the plan; on failure returns the status and sets err.  With lines
@@ -105,9 +115,12 @@ vtm_status split_at_vertices(const vtm_csr* A, const int32_t* label, const int32
 // sides[2l] and sides[2l + 1], joined by a line of admittance W[l] (nW == 1: one
 // W for all).  Other nodes keep label[i].  The plan describes the expanded
 // system and carries the maps back to the caller's nodes.
+// With Wc (an n_iface x n_iface CSR, symmetric, positive diagonal, coupling
+// only lines whose twins lie in the same two sub-circuits, in the same order)
+// the lines are coupled and W, nW are ignored.
 vtm_status build_plan_vertex(const vtm_csr* A, const int32_t* label, const int32_t* iface,
                              const int32_t* sides, int64_t n_iface, const double* W, int64_t nW,
-                             Plan& plan, std::string& err);
+                             Plan& plan, std::string& err, const vtm_csr* Wc = nullptr);
 
 // Renumbered A^T in compressed rows (columns sorted).
 void transpose_csr(const Plan& plan, std::vector<int32_t>& rowptr, std::vector<int32_t>& col,

@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(kBlock)
     k_port_matrix(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs,
                   const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_node,
                   const double* __restrict__ pc, const double* __restrict__ pbeta, const double* __restrict__ pgamma,
-                  const TO* __restrict__ K, const int64_t* __restrict__ pofs, TO* __restrict__ M) {
+                  const TO* __restrict__ K, const int64_t* __restrict__ pofs, TO* __restrict__ M, Coupling<double> B) {
     const int s = blockIdx.x;
     const int ns = sub_off[s + 1] - sub_off[s];
     const int p0 = port_off[s], q = port_off[s + 1] - p0;
@@ -37,7 +37,16 @@ __global__ void __launch_bounds__(kBlock)
         int r, c;
         inv_rc<TO>(q, d, r, c);
         const int pr = p0 + r, pcol = p0 + c;
-        double v = pbeta[pr] * double(Ks[inv_offset<TO>(ns, port_node[pr], port_node[pcol])]) * pc[pcol];
+        const int j = port_node[pcol];
+        double v;
+        if (B.row) {  // (B K^-1[i(P), i(P)])_{r c}: B's row r over the ports of this sub-circuit
+            v = 0.0;
+            for (int k = B.row[pr]; k < B.row[pr + 1]; ++k)
+                v += B.val[k] * double(Ks[inv_offset<TO>(ns, port_node[B.col[k]], j)]);
+            v *= pc[pcol];
+        } else {
+            v = pbeta[pr] * double(Ks[inv_offset<TO>(ns, port_node[pr], j)]) * pc[pcol];
+        }
         if (r == c) v += pgamma[pr];
         Ms[d] = TO(v);
     }
@@ -49,14 +58,36 @@ template <typename TV>
 __global__ void __launch_bounds__(kBlock)
     k_port_h(int nrhs, const int32_t* __restrict__ sub_off, const int32_t* __restrict__ port_off,
              const int32_t* __restrict__ port_node, const TV* __restrict__ pbeta, const TV* __restrict__ x,
-             TV* __restrict__ h) {
+             TV* __restrict__ h, Coupling<TV> B) {
     const int s = blockIdx.x;
     const int off = sub_off[s], p0 = port_off[s];
     const int cnt = (port_off[s + 1] - p0) * nrhs;
     for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
         const int p = p0 + t / nrhs, r = t % nrhs;
-        h[int64_t(p) * nrhs + r] = pbeta[p] * x[int64_t(off + port_node[p]) * nrhs + r];
+        TV v;
+        if (B.row) {
+            v = TV(0);
+            for (int k = B.row[p]; k < B.row[p + 1]; ++k)
+                v += B.val[k] * x[int64_t(off + port_node[B.col[k]]) * nrhs + r];
+        } else {
+            v = pbeta[p] * x[int64_t(off + port_node[p]) * nrhs + r];
+        }
+        h[int64_t(p) * nrhs + r] = v;
     }
+}
+
+// coupled lines: the outgoing waves from the x of a full sweep
+template <typename TV>
+__global__ void __launch_bounds__(kBlock)
+    k_wave_coupled(int n_ports, int nrhs, Coupling<TV> B, const int32_t* __restrict__ port_row,
+                   const TV* __restrict__ pgamma, const int32_t* __restrict__ port_twin, const TV* __restrict__ x,
+                   const TV* __restrict__ a_cur, TV* __restrict__ a_next) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(n_ports) * nrhs) return;
+    const int p = int(t / nrhs), r = int(t - int64_t(p) * nrhs);
+    TV v = pgamma[p] * a_cur[t];
+    for (int k = B.row[p]; k < B.row[p + 1]; ++k) v += B.val[k] * x[int64_t(port_row[B.col[k]]) * nrhs + r];
+    a_next[int64_t(port_twin[p]) * nrhs + r] = v;
 }
 
 template <typename T>
@@ -257,19 +288,34 @@ template hipError_t launch_sweep_ppn<float, float>(int, int, int, const float*, 
 template <typename TO>
 hipError_t launch_port_matrix(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* port_off,
                               const int32_t* port_node, const double* pc, const double* pbeta, const double* pgamma,
-                              const TO* K, const int64_t* pofs, TO* M, hipStream_t st) {
+                              const TO* K, const int64_t* pofs, TO* M, hipStream_t st, Coupling<double> B) {
     hipLaunchKernelGGL(k_port_matrix<TO>, dim3(S), dim3(kBlock), 0, st, sub_off, kofs, port_off, port_node, pc,
-                       pbeta, pgamma, K, pofs, M);
+                       pbeta, pgamma, K, pofs, M, B);
     return hipGetLastError();
 }
 
 template <typename TV>
 hipError_t launch_port_h(int S, int nrhs, const int32_t* sub_off, const int32_t* port_off, const int32_t* port_node,
-                         const TV* pbeta, const TV* x, TV* h, hipStream_t st) {
+                         const TV* pbeta, const TV* x, TV* h, hipStream_t st, Coupling<TV> B) {
     hipLaunchKernelGGL(k_port_h<TV>, dim3(S), dim3(nrhs > 1 ? 256 : 64), 0, st, nrhs, sub_off, port_off, port_node,
-                       pbeta, x, h);
+                       pbeta, x, h, B);
     return hipGetLastError();
 }
+
+template <typename TV>
+hipError_t launch_wave_coupled(int n_ports, int nrhs, Coupling<TV> B, const int32_t* port_row, const TV* pgamma,
+                               const int32_t* port_twin, const TV* x, const TV* a_cur, TV* a_next, hipStream_t st) {
+    const int64_t total = int64_t(n_ports) * nrhs;
+    if (total == 0) return hipSuccess;
+    if (!B.row) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_wave_coupled<TV>, dim3(unsigned((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       n_ports, nrhs, B, port_row, pgamma, port_twin, x, a_cur, a_next);
+    return hipGetLastError();
+}
+template hipError_t launch_wave_coupled<double>(int, int, Coupling<double>, const int32_t*, const double*,
+                                                const int32_t*, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_wave_coupled<float>(int, int, Coupling<float>, const int32_t*, const float*,
+                                               const int32_t*, const float*, const float*, float*, hipStream_t);
 
 template <typename TO, typename TV>
 hipError_t launch_sweep_pp(int S, int max_q, const TO* M, const int64_t* pofs, const int32_t* port_off,
@@ -287,14 +333,14 @@ hipError_t launch_sweep_pp(int S, int max_q, const TO* M, const int64_t* pofs, c
 
 template hipError_t launch_port_matrix<double>(int, const int32_t*, const int64_t*, const int32_t*, const int32_t*,
                                                const double*, const double*, const double*, const double*,
-                                               const int64_t*, double*, hipStream_t);
+                                               const int64_t*, double*, hipStream_t, Coupling<double>);
 template hipError_t launch_port_matrix<float>(int, const int32_t*, const int64_t*, const int32_t*, const int32_t*,
                                               const double*, const double*, const double*, const float*,
-                                              const int64_t*, float*, hipStream_t);
+                                              const int64_t*, float*, hipStream_t, Coupling<double>);
 template hipError_t launch_port_h<double>(int, int, const int32_t*, const int32_t*, const int32_t*, const double*,
-                                          const double*, double*, hipStream_t);
+                                          const double*, double*, hipStream_t, Coupling<double>);
 template hipError_t launch_port_h<float>(int, int, const int32_t*, const int32_t*, const int32_t*, const float*,
-                                         const float*, float*, hipStream_t);
+                                         const float*, float*, hipStream_t, Coupling<float>);
 template hipError_t launch_sweep_pp<double, double>(int, int, const double*, const int64_t*, const int32_t*,
                                                     const int32_t*, const double*, const double*, double*,
                                                     hipStream_t);

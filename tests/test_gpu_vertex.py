@@ -57,8 +57,12 @@ def strips(dims, width, law="loguniform", seed=0, nrhs=1, vccs=False):
     return A, b, label, iface, sides, W
 
 
+def dense(W):
+    return W.toarray() if sp.issparse(W) else W
+
+
 def oracle_iterates(A, b, label, iface, sides, W, ks):
-    torn = oracle.tear_at_vertices(A, label, iface, sides, W)
+    torn = oracle.tear_at_vertices(A, label, iface, sides, dense(W))
     sw = oracle.Sweeper(torn)
     f = torn.src @ b.T
     a = np.zeros((2, torn.n_lines, b.shape[0]))
@@ -71,6 +75,9 @@ def oracle_iterates(A, b, label, iface, sides, W, ks):
 
 
 def solver(A, label, iface, sides, W, **kw):
+    """vtm_setup_vertex for a scalar or per-line W, vtm_setup_vertex_coupled for a sparse matrix."""
+    if sp.issparse(W):
+        return vtm().Solver(A, label, None, iface=iface, sides=sides, W=W, **kw)
     Z = 1.0 / np.asarray(W, dtype=np.float64)
     return vtm().Solver(A, label, Z, iface=iface, sides=sides, **kw)
 
@@ -187,3 +194,100 @@ def test_separator_strips_solve_to_tolerance(torch, prec):
     assert np.abs(x.cpu().numpy()[0] - xs).max() <= 1e-7 * np.abs(xs).max()
     if prec == "fp64":
         assert abs(rep.sweeps - r.sweeps) <= 1
+
+
+# ---------------------------------------------------------------- coupled lines
+def coupled(dims, width, rule, alpha=1.0, **kw):
+    A, b, label, iface, sides, _ = strips(dims, width, **kw)
+    W = vtm().vertex_admittance(A, label, iface, sides, rule, alpha)
+    return A, b, label, iface, sides, W
+
+
+@pytest.mark.parametrize("rule,alpha,kw", [
+    ("ob", 1.0, dict()),                                    # dense port-to-port form with B = 2 W
+    ("ob", 1.0, dict(local_form="full")),
+    ("wob", 0.3, dict(local_form="port_dense")),
+    ("diag", 1.0, dict()),
+])
+def test_coupled_line_iterates_match_oracle(torch, rule, alpha, kw):
+    """Section VIII rules 2-4 as coupled lines (eqs. 4-5): W over each
+    separator's interfacial nodes, with the branches between them."""
+    A, b, label, iface, sides, W = coupled((24, 47), 10, rule, alpha)
+    ks = [1, 2, 7]
+    ref = oracle_iterates(A, b, label, iface, sides, W, ks)
+    for k in ks:
+        assert_close(gpu_iterate(torch, A, b, label, iface, sides, W, k, **kw), ref[k])
+    assert_close(gpu_iterate(torch, A, b, label, iface, sides, W, 7, check_every=7, **kw), ref[7])
+
+
+def test_diagonal_W_as_coupled_lines_equals_per_line_W(torch):
+    A, b, label, iface, sides, W = coupled((24, 47), 10, "diag")
+    x1 = gpu_iterate(torch, A, b, label, iface, sides, W, 9, check_every=3)
+    x2 = gpu_iterate(torch, A, b, label, iface, sides, W.diagonal().copy(), 9, check_every=3)
+    assert_close(x1, x2)
+
+
+def test_coupled_lines_batched_and_three_dimensional(torch):
+    A, b, label, iface, sides, W = coupled((16, 35), 8, "ob", nrhs=16, seed=6)
+    ref = oracle_iterates(A, b, label, iface, sides, W, [5])
+    assert_close(gpu_iterate(torch, A, b, label, iface, sides, W, 5, check_every=5), ref[5])
+    A, b, label, iface, sides, W = coupled((8, 9, 23), 5, "wob", 0.5, law="uniform")
+    ref = oracle_iterates(A, b, label, iface, sides, W, [6])
+    assert_close(gpu_iterate(torch, A, b, label, iface, sides, W, 6, check_every=3), ref[6])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+def test_coupled_lines_solve_to_tolerance(torch, prec):
+    A, b, label, iface, sides, W = coupled((48, 59), 11, "wob", 0.3, seed=2)
+    tol = 1e-10
+    r = oracle.vtm_solve(oracle.tear_at_vertices(A, label, iface, sides, dense(W)), A, b, tol, max_sweeps=20000)
+    assert r.status == "ok"
+    s = solver(A, label, iface, sides, W, precision=prec, check_every=1 if prec == "fp64" else 8,
+               adaptive_checks=False)
+    x, rep = s.solve(to_dev(torch, b), tol)
+    assert rep.relres_max <= tol
+    if prec == "fp64":
+        assert abs(rep.sweeps - r.sweeps) <= 1
+
+
+def test_table2_ordering_on_the_gpu(torch):
+    """Table II, qualitatively, on a 100 x 100 unit resistor grid cut into
+    strips of 100 x 18 by five separator columns (2000 nodes per torn strip
+    with its twins): the GPU's sweep counts are the oracle's, and diagonal >
+    overlapped block > weighted overlapped block."""
+    dims = (100, 100)
+    e = workloads.grid2d_edges(*dims)
+    n = int(np.prod(dims))
+    A = workloads.nodal_matrix(n, e, np.ones(e.shape[0]), np.full(n, workloads.GROUND_S))
+    b = np.random.default_rng(0).standard_normal((1, n))
+    label, iface, sides = workloads.separator_strips(dims, 18)
+    sweeps = {}
+    for rule, alpha in (("diag", 1.0), ("ob", 1.0), ("wob", 0.3)):
+        W = vtm().vertex_admittance(A, label, iface, sides, rule, alpha)
+        r = oracle.vtm_solve(oracle.tear_at_vertices(A, label, iface, sides, W.toarray()), A, b, 1e-8,
+                             max_sweeps=5000)
+        s = solver(A, label, iface, sides, W, check_every=1, adaptive_checks=False)
+        x, rep = s.solve(to_dev(torch, b), 1e-8)
+        assert abs(rep.sweeps - r.sweeps) <= 1
+        sweeps[rule] = rep.sweeps
+    assert sweeps["diag"] > sweeps["ob"] > sweeps["wob"]
+
+
+def test_coupled_W_is_checked(torch):
+    A, b, label, iface, sides, W = coupled((12, 23), 5, "ob")
+    def status(Wbad):
+        with pytest.raises(vtm().VTMError) as ei:
+            solver(A, label, iface, sides, sp.csr_matrix(Wbad))
+        return ei.value.name
+    Wd = W.toarray()
+    # lines of different separators (different pairs of strips) coupled
+    a, c = 0, int(np.nonzero(sides[:, 0] != sides[0, 0])[0][0])
+    X = Wd.copy()
+    X[a, c] = X[c, a] = -0.1
+    assert status(X) == "VTM_E_ARG"
+    X = Wd.copy()
+    X[0, 1] += 0.1                                  # not symmetric
+    assert status(X) == "VTM_E_ARG"
+    X = Wd.copy()
+    X[3, 3] = 0.0                                   # no positive diagonal
+    assert status(X) == "VTM_E_ARG"

@@ -111,3 +111,51 @@ def test_split_errors():
     with pytest.raises(binding.VTMError) as ei:
         binding.split_vertex(B.tocsr(), label, iface, sides)
     assert ei.value.name == "VTM_E_UNTEARABLE"
+
+
+def unit_grid(dims):
+    e = workloads.grid2d_edges(*dims) if len(dims) == 2 else workloads.grid3d_edges(*dims)
+    n = int(np.prod(dims))
+    return workloads.nodal_matrix(n, e, np.ones(e.shape[0]), np.full(n, workloads.GROUND_S))
+
+
+@pytest.mark.parametrize("side", [0, 1])
+def test_vertex_admittance_rules_are_the_interface_block(side):
+    """Section VIII rules 1-4 on tearing at interfacial nodes: C is the block of
+    the oracle's torn matrix over one side's twins (C_1 or C_2)."""
+    w = workloads.make(4, dims=(14, 23))
+    label, iface, sides = workloads.separator_strips(w.dims, 5)
+    torn = oracle.tear_at_vertices(w.A, label, iface, sides, 1.0)
+    pos = torn.pa if side == 0 else torn.pb
+    Cref = torn.T.tocsr()[pos][:, pos].toarray()
+    assert np.count_nonzero(Cref - np.diag(np.diag(Cref))) > 0     # branches between interfacial nodes
+    W = {r: binding.vertex_admittance(w.A, label, iface, sides, r, 0.3, side).toarray()
+         for r in ("ob", "wob", "diag", "identity", "scaled_mean")}
+    assert np.abs(W["ob"] - Cref).max() <= 1e-15 * np.abs(Cref).max()
+    assert np.abs(W["wob"] - 0.3 * Cref).max() <= 1e-15 * np.abs(Cref).max()
+    assert np.array_equal(W["diag"], np.diag(np.diag(W["ob"])))
+    assert np.array_equal(W["identity"], 0.3 * np.eye(iface.size))
+    assert np.allclose(W["scaled_mean"], 0.3 * np.mean(w.g) * np.eye(iface.size), rtol=1e-14, atol=0)
+    with pytest.raises(binding.VTMError):
+        binding.vertex_admittance(w.A, label, iface, sides, "ob", 1.0, 2)
+
+
+def test_table2_ordering_of_preconditioners_on_a_grid2d_like_circuit():
+    """Table II (Grid2d column), qualitatively: a 100 x 100 resistor grid torn
+    into two sub-circuits at one separator column of 100 interfacial nodes.
+    The diagonal preconditioner needs about twice the sweeps of the overlapped
+    block (963 vs 491 in the paper), and a weighted overlapped block needs
+    fewer still (296)."""
+    dims = (100, 100)
+    A = unit_grid(dims)
+    b = np.random.default_rng(0).standard_normal((1, A.shape[0]))
+    label, iface, sides = workloads.separator_strips(dims, 49)
+    assert iface.size == 100 and label.max() == 1
+    sweeps = {}
+    for rule, alpha in (("diag", 1.0), ("ob", 1.0), ("wob", 0.3)):
+        W = binding.vertex_admittance(A, label, iface, sides, rule, alpha).toarray()
+        r = oracle.vtm_solve(oracle.tear_at_vertices(A, label, iface, sides, W), A, b, 1e-8, max_sweeps=5000)
+        assert r.status == "ok"
+        sweeps[rule] = r.sweeps
+    assert sweeps["diag"] > sweeps["ob"] > sweeps["wob"]
+    assert 1.5 <= sweeps["diag"] / sweeps["ob"] <= 2.5

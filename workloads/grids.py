@@ -116,7 +116,8 @@ def separator_strips(dims, width: int):
     the grid (2-D or 3-D, node numbering as in :func:`grid2d_edges` /
     :func:`grid3d_edges`) is cut along its last axis into strips (slabs) of
     ``width`` inner layers, consecutive strips divided by one layer of
-    interfacial nodes (the last strip takes what is left).  Every interfacial
+    interfacial nodes (the last strip takes what is left, and one more layer
+    when a single layer would remain).  Every interfacial
     node borders exactly the two strips on either side of its layer.
 
     Returns ``label`` (int32 [n]: strip of every inner node, -1 on separator
@@ -129,9 +130,11 @@ def separator_strips(dims, width: int):
     x, strip, sep = 0, 0, 0
     while x < nx:
         w = min(width, nx - x)
+        if nx - (x + w) == 1:                 # a lone last layer joins this strip
+            w += 1
         lay[x:x + w] = strip
         x += w
-        if x < nx - 1:                        # a separator needs a strip after it
+        if x < nx:                            # at least two layers left: separator, strip
             sep_of[x] = sep
             sep += 1
             x += 1

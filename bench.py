@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -30,6 +32,16 @@ KERNEL_SRC = os.path.join(ROOT, "paper_0910_0663_amd", "csrc", "ports.hip")
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def host_relres(A, b, x):
+    """||b - A x|| / ||b|| per column on the host in FP64 (b, x: [nrhs, n]) -- an
+    independent check of the library's own stop rule."""
+    b = np.atleast_2d(b)
+    x = np.atleast_2d(x)
+    r = b - (A @ x.T).T
+    bn = np.linalg.norm(b, axis=1)
+    return np.linalg.norm(r, axis=1) / np.where(bn > 0, bn, 1.0)
 
 
 def sweep_bytes(n, n_sub, n_wires, inverse_bytes):
@@ -117,15 +129,15 @@ def timed_solve(vtm, torch, w, precision, nrhs_max, reps=2):
     return ms, rep, x
 
 
-def mixed_and_batched(vtm, torch, oracle, workloads):
+def mixed_and_batched(vtm, torch, workloads):
     """The precision/batching forms against plain FP64 VTM on the same GPU, each
     solved to relative residual 1e-8 (recomputed on the host in FP64)."""
     res = {}
     w = workloads.make(4)
     t16, r16, x16 = timed_solve(vtm, torch, w, "bf16_refine", 64)
     t64, r64, x64 = timed_solve(vtm, torch, w, "fp64", 64)
-    rel16 = float(oracle.relative_residual(w.A, w.b, x16.cpu().numpy()).max())
-    rel64 = float(oracle.relative_residual(w.A, w.b, x64.cpu().numpy()).max())
+    rel16 = float(host_relres(w.A, w.b, x16.cpu().numpy()).max())
+    rel64 = float(host_relres(w.A, w.b, x64.cpu().numpy()).max())
     assert rel16 <= w.tol and rel64 <= w.tol, (rel16, rel64)
     diff = float(((x16 - x64).norm(dim=1) / x64.norm(dim=1)).max())
     res["batched_bf16_vs_fp64"] = {
@@ -149,7 +161,7 @@ def mixed_and_batched(vtm, torch, oracle, workloads):
     t1 = (time.perf_counter() - t) * 1e3
     s1.close()
     x1 = torch.cat(xcols).cpu().numpy()
-    rel1 = float(oracle.relative_residual(w.A, w.b, x1).max())
+    rel1 = float(host_relres(w.A, w.b, x1).max())
     assert rel1 <= w.tol, rel1
     res["batched_bf16_vs_fp64"].update({
         "fp64_single_rhs_x64_ms": round(t1, 1), "fp64_single_rhs_sweeps_total": sweeps1,
@@ -159,8 +171,8 @@ def mixed_and_batched(vtm, torch, oracle, workloads):
     w = workloads.make(3)
     t32, r32, x32 = timed_solve(vtm, torch, w, "fp32_refine", 1, reps=2)
     t64, r64, x64 = timed_solve(vtm, torch, w, "fp64", 1, reps=2)
-    rel32 = float(oracle.relative_residual(w.A, w.b, x32.cpu().numpy()).max())
-    rel64 = float(oracle.relative_residual(w.A, w.b, x64.cpu().numpy()).max())
+    rel32 = float(host_relres(w.A, w.b, x32.cpu().numpy()).max())
+    rel64 = float(host_relres(w.A, w.b, x64.cpu().numpy()).max())
     assert rel32 <= w.tol and rel64 <= w.tol, (rel32, rel64)
     res["fp32_vs_fp64_3d"] = {
         "workload": f"128^3 7-point grid with {w.vccs[0].size} controlled sources (unsymmetric), "
@@ -174,8 +186,8 @@ def mixed_and_batched(vtm, torch, oracle, workloads):
     w = workloads.make(5)
     t32, r32, x32 = timed_solve(vtm, torch, w, "fp32_refine", 1, reps=5)
     t64, r64, x64 = timed_solve(vtm, torch, w, "fp64", 1, reps=5)
-    rel32 = float(oracle.relative_residual(w.A, w.b, x32.cpu().numpy()).max())
-    rel64 = float(oracle.relative_residual(w.A, w.b, x64.cpu().numpy()).max())
+    rel32 = float(host_relres(w.A, w.b, x32.cpu().numpy()).max())
+    rel64 = float(host_relres(w.A, w.b, x64.cpu().numpy()).max())
     assert rel32 <= w.tol and rel64 <= w.tol, (rel32, rel64)
     res["fp32_vs_fp64"] = {
         "workload": "512x512 grid, 1,024 sub-circuits of 16x16, 1 RHS, tol 1e-8",
@@ -183,12 +195,13 @@ def mixed_and_batched(vtm, torch, oracle, workloads):
         "fp32_sweeps": r32.sweeps, "fp32_outer": r32.outer, "fp64_sweeps": r64.sweeps,
         "fp32_relres": rel32, "fp64_relres": rel64}
     log(f"cfg5: fp32 refine {t32:.2f} ms vs fp64 {t64:.2f} ms: x{t64 / t32:.2f}")
-    res["gradient"] = gradient_path(vtm, torch, oracle, workloads)
-    res["line_admittance_rules_2048sq"] = preconditioners(vtm, torch, oracle, workloads)
+    res["gradient"] = gradient_path(vtm, torch, workloads)
+    res["line_admittance_rules_2048sq"] = preconditioners(vtm, torch, workloads)
+    res["vertex_tearing"] = vertex_tearing(vtm, torch, workloads)
     return res
 
 
-def gradient_path(vtm, torch, oracle, workloads, reps=5):
+def gradient_path(vtm, torch, workloads, reps=5):
     """The IR-drop loss L = sum of x^2 over 4,096 probe nodes of the 512x512 grid:
     forward solve, adjoint solve with g = dL/dx = 2 x at the probes, then
     dL/dg_e = -(lambda_i - lambda_j)(x_i - x_j) for every branch; FP32 sweeps
@@ -222,8 +235,8 @@ def gradient_path(vtm, torch, oracle, workloads, reps=5):
             t["adjoint"] += (t3 - t2) / reps
             t["grad"] += (t4 - t3) / reps
     s.close()
-    rel_f = float(oracle.relative_residual(w.A, w.b, x.cpu().numpy()).max())
-    rel_a = float(oracle.relative_residual(w.A.T.tocsr(), g.cpu().numpy(), lam.cpu().numpy()).max())
+    rel_f = float(host_relres(w.A, w.b, x.cpu().numpy()).max())
+    rel_a = float(host_relres(w.A.T.tocsr(), g.cpu().numpy(), lam.cpu().numpy()).max())
     assert rel_f <= w.tol and rel_a <= w.tol and bool(torch.isfinite(dg).all()), (rel_f, rel_a)
     out = {"workload": f"512x512 grid, 1,024 sub-circuits of 16x16, loss over {w.probes.size} probes, "
                        f"{ij.shape[0]:,} branches; FP32 sweeps + FP64 refinement to 1e-8",
@@ -235,7 +248,7 @@ def gradient_path(vtm, torch, oracle, workloads, reps=5):
     return out
 
 
-def preconditioners(vtm, torch, oracle, workloads):
+def preconditioners(vtm, torch, workloads):
     """Section VIII's line admittances on the bench grid (2048x2048, FP64, 1e-8):
     the workload's own W = mean conductance, a scaled mean, and the weighted
     overlapped block W = alpha C (C = each twin's 2g); sweeps and solve time."""
@@ -253,10 +266,51 @@ def preconditioners(vtm, torch, oracle, workloads):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t) * 1e3
         s.close()
-        rel = float(oracle.relative_residual(w.A, w.b, x.cpu().numpy()).max())
+        rel = float(host_relres(w.A, w.b, x.cpu().numpy()).max())
         assert rel <= w.tol, (rule, alpha, rel)
         out.append({"rule": rule, "alpha": alpha, "sweeps": rep.sweeps, "ms": round(ms, 2), "relres": rel})
         log(f"cfg2 W {rule} x{alpha}: {rep.sweeps} sweeps, {ms:.1f} ms")
+    return out
+
+
+def vertex_tearing(vtm, torch, workloads):
+    """Tearing at interfacial nodes (Section V) with the admittance rules of
+    Section VIII as coupled lines, on unit resistor grids like Table I's Grid2d
+    and Grid3d (0.01 S to ground everywhere), cut into strips / slabs by
+    separator layers small enough for the 2048-node sub-circuit limit: sweeps
+    and time to 1e-8, setup time, residual checked on the host."""
+    out = {}
+    for name, dims, width in (("grid2d_100x100_strips_of_18", (100, 100), 18),
+                              ("grid3d_20x20x40_slabs_of_2", (20, 20, 40), 2)):
+        e = workloads.grid2d_edges(*dims) if len(dims) == 2 else workloads.grid3d_edges(*dims)
+        n = int(np.prod(dims))
+        A = workloads.nodal_matrix(n, e, np.ones(e.shape[0]), np.full(n, workloads.GROUND_S))
+        bh = np.random.default_rng(0).standard_normal((1, n))
+        b = torch.as_tensor(bh, dtype=torch.float64, device="cuda")
+        x = torch.empty_like(b)
+        label, iface, sides = workloads.separator_strips(dims, width)
+        rows = []
+        for rule, alpha in (("identity", 1.0), ("diag", 1.0), ("ob", 1.0), ("wob", 0.3)):
+            W = vtm.vertex_admittance(A, label, iface, sides, rule, alpha)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            s = vtm.Solver(A, label, None, iface=iface, sides=sides, W=W)
+            torch.cuda.synchronize()
+            setup_ms = (time.perf_counter() - t) * 1e3
+            s.solve(b, 1e-8, x)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, rep = s.solve(b, 1e-8, x)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1e3
+            s.close()
+            rel = float(host_relres(A, bh, x.cpu().numpy()).max())
+            assert rel <= 1e-8, (name, rule, rel)
+            rows.append({"rule": rule, "alpha": alpha, "sweeps": rep.sweeps, "ms": round(ms, 3),
+                         "setup_ms": round(setup_ms, 1), "relres": rel})
+            log(f"{name} W {rule} x{alpha}: {rep.sweeps} sweeps, {ms:.2f} ms (setup {setup_ms:.0f} ms)")
+        out[name] = {"n": n, "interfacial_nodes": int(iface.size), "sub_circuits": int(label.max()) + 1,
+                     "rules": rows}
     return out
 
 
@@ -269,6 +323,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision / batched comparison")
+    ap.add_argument("--vertex-only", action="store_true",
+                    help="for profiling: only the tearing at interfacial nodes; prints its JSON")
     ap.add_argument("--batched-only", action="store_true",
                     help="for profiling: only the mixed-precision / batched comparison; prints its JSON")
     ap.add_argument("--counters", action="store_true",
@@ -280,15 +336,16 @@ def main():
               "MI355X (multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    import oracle
     import workloads
     import paper_0910_0663_amd as vtm
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.vertex_only:
+        print(json.dumps(vertex_tearing(vtm, torch, workloads)), flush=True)
+        return
     if args.batched_only:
-        print(json.dumps(mixed_and_batched(vtm, torch, oracle, workloads)), flush=True)
+        print(json.dumps(mixed_and_batched(vtm, torch, workloads)), flush=True)
         return
     t = time.perf_counter()
     w = workloads.make(2)
@@ -333,7 +390,7 @@ def main():
     kern_ms = sum(r.sweep_kernel_ms for r in reps)
     pp_launches = sum(r.pp_launches for r in reps)
     pp_ms = sum(r.pp_kernel_ms for r in reps)
-    host_rel = float(oracle.relative_residual(w.A, w.b, x.cpu().numpy()).max())
+    host_rel = float(host_relres(w.A, w.b, x.cpu().numpy()).max())
     log(f"host-checked relres {host_rel:.3e}; full sweeps {launches}, port-to-port sweeps {pp_launches}")
     assert host_rel <= w.tol, host_rel
 
@@ -399,7 +456,7 @@ def main():
     }
     if not args.no_mixed:
         log("mixed-precision and batched forms vs plain FP64 ...")
-        out["mixed_batched"] = mixed_and_batched(vtm, torch, oracle, workloads)
+        out["mixed_batched"] = mixed_and_batched(vtm, torch, workloads)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

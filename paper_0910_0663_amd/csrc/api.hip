@@ -1170,8 +1170,13 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
         VTM_HIP(h->mofs.upload(P.mofs, s));
     }
     const int64_t nm = P.mofs[P.S];
-    DevBuf<double> scratch;
+    DevBuf<double> scratch, panel;  // setup only: FP64 inverses, and the elimination's panels
+    DevBuf<int32_t> ipiv;
     if (h->tiles || P.max_ns > vtm::kLdsSetupMax) VTM_HIP(scratch.alloc(nk));
+    if (P.max_ns > vtm::kLdsSetupMax) {
+        VTM_HIP(panel.alloc(P.n * 32));
+        VTM_HIP(ipiv.alloc(P.n));
+    }
     VTM_HIP(h->c64.upload(P.pc, s));
     VTM_HIP(h->beta64.upload(P.pbeta, s));
     VTM_HIP(h->gamma64.upload(P.pgamma, s));
@@ -1190,11 +1195,12 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
             VTM_HIP(h->K64.alloc(nm));
             VTM_HIP(vtm::launch_setup_tiles<double>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->mofs.p,
                                                     h->rowptr.p, h->col.p, h->val.p, h->dmod.p, h->K64.p, scratch.p,
-                                                    h->flag.p, s));
+                                                    panel.p, ipiv.p, h->flag.p, s));
         } else {
             VTM_HIP(h->K64.alloc(nk));
             VTM_HIP(vtm::launch_setup<double>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
-                                              h->val.p, h->dmod.p, h->K64.p, scratch.p, h->flag.p, s));
+                                              h->val.p, h->dmod.p, h->K64.p, scratch.p, panel.p, ipiv.p, h->flag.p,
+                                              s));
         }
     } else {
         VTM_HIP(h->c32.upload(to_float(P.pc), s));
@@ -1213,11 +1219,12 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
             VTM_HIP(h->Kbf.alloc(nm));
             VTM_HIP(vtm::launch_setup_tiles<__bf16>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->mofs.p,
                                                     h->rowptr.p, h->col.p, h->val.p, h->dmod.p, h->Kbf.p, scratch.p,
-                                                    h->flag.p, s));
+                                                    panel.p, ipiv.p, h->flag.p, s));
         } else {
             VTM_HIP(h->K32.alloc(nk));
             VTM_HIP(vtm::launch_setup<float>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
-                                             h->val.p, h->dmod.p, h->K32.p, scratch.p, h->flag.p, s));
+                                             h->val.p, h->dmod.p, h->K32.p, scratch.p, panel.p, ipiv.p, h->flag.p,
+                                             s));
         }
     }
     VTM_HIP(hipStreamSynchronize(s));

@@ -38,12 +38,14 @@ struct PortArrays {
 // the column-group layout of layout.hpp into out + kofs[s].  Sub-circuits with
 // ns <= kLdsSetupMax are inverted in LDS; larger ones are assembled into
 // scratch64 (FP64, same offsets, must be non-null then) and inverted there by a
-// blocked Gauss-Jordan elimination with partial pivoting.  flag bit 0 = singular.
+// blocked Gauss-Jordan elimination with partial pivoting, whose panels use
+// panel (n x 32 doubles) and ipiv (n ints), both non-null then.  flag bit 0 =
+// singular.
 template <typename TO>
 hipError_t launch_setup(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs,
                         const int32_t* rowptr, const int32_t* col, const double* val,
-                        const double* dmod, TO* out, double* scratch64, int* flag,
-                        hipStream_t st);
+                        const double* dmod, TO* out, double* scratch64, double* panel, int32_t* ipiv,
+                        int* flag, hipStream_t st);
 
 // Same matrices, written as zero-padded MFMA operand tiles (tiles.hpp) of T
 // (BF16 or FP64) at out + mofs[s]; every sub-circuit passes through FP64
@@ -51,8 +53,8 @@ hipError_t launch_setup(int S, int max_ns, const int32_t* sub_off, const int64_t
 template <typename T>
 hipError_t launch_setup_tiles(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs,
                               const int64_t* mofs, const int32_t* rowptr, const int32_t* col,
-                              const double* val, const double* dmod, T* out, double* scratch64, int* flag,
-                              hipStream_t st);
+                              const double* val, const double* dmod, T* out, double* scratch64, double* panel,
+                              int32_t* ipiv, int* flag, hipStream_t st);
 
 // ---- sweep ----------------------------------------------------------------
 // One VTM sweep for every sub-circuit (one workgroup each, per block of up to 8

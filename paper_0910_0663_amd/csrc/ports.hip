@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(kBlock)
     const TO* Ks = K + kofs[s];
     TO* Ms = M + pofs[s];
     const int64_t cnt = int64_t(q) * q;
-    for (int64_t d = threadIdx.x; d < cnt; d += blockDim.x) {
+    for (int64_t d = int64_t(blockIdx.y) * blockDim.x + threadIdx.x; d < cnt; d += int64_t(blockDim.x) * gridDim.y) {
         int r, c;
         inv_rc<TO>(q, d, r, c);
         const int pr = p0 + r, pcol = p0 + c;
@@ -108,7 +108,8 @@ __device__ inline void load16p(const T* p, T (&v)[Group<T>::G]) {
 // One port-to-port sweep, one workgroup per sub-circuit (a_next[twin(p)] =
 // h_p + (M a)_p).  SPLIT = 2 (q <= 32, one wavefront): lane l takes row l % 32
 // and half the column groups, and the halves are added with a cross-lane
-// shuffle.  SPLIT = 1: one row per thread (64 or 256 threads).
+// shuffle.  SPLIT = 1: one row per thread (64 or 256 threads); with few large
+// sub-circuits the rows of each are also spread over gridDim.y workgroups.
 template <typename TO, typename TV, int SPLIT>
 __global__ void __launch_bounds__(256)
     k_sweep_pp(const TO* __restrict__ M, const int64_t* __restrict__ pofs, const int32_t* __restrict__ port_off,
@@ -123,6 +124,7 @@ __global__ void __launch_bounds__(256)
     const TO* Ms = M + pofs[s];
     const int ng = q / G, full = ng * G;
     const int bs = blockDim.x;
+    if (int(blockIdx.y) * bs >= q) return;  // no rows for this block (whole workgroup leaves)
     for (int t = lane; t < q; t += bs) av[t] = a_cur[p0 + t];
     __syncthreads();
     if constexpr (SPLIT == 2) {
@@ -148,7 +150,7 @@ __global__ void __launch_bounds__(256)
         v += __shfl_down(v, 32, 64);
         if (half == 0 && row < q) a_next[port_twin[p0 + row]] = h[p0 + row] + v;
     } else {
-        for (int row = lane; row < q; row += bs) {
+        for (int row = int(blockIdx.y) * bs + lane; row < q; row += bs * int(gridDim.y)) {
             TV acc[G];
 #pragma unroll
             for (int j = 0; j < G; ++j) acc[j] = TV(0);
@@ -289,8 +291,10 @@ template <typename TO>
 hipError_t launch_port_matrix(int S, const int32_t* sub_off, const int64_t* kofs, const int32_t* port_off,
                               const int32_t* port_node, const double* pc, const double* pbeta, const double* pgamma,
                               const TO* K, const int64_t* pofs, TO* M, hipStream_t st, Coupling<double> B) {
-    hipLaunchKernelGGL(k_port_matrix<TO>, dim3(S), dim3(kBlock), 0, st, sub_off, kofs, port_off, port_node, pc,
-                       pbeta, pgamma, K, pofs, M, B);
+    // few sub-circuits: several workgroups each
+    const int parts = S < 2048 ? (2048 + S - 1) / S : 1;
+    hipLaunchKernelGGL(k_port_matrix<TO>, dim3(S, parts), dim3(kBlock), 0, st, sub_off, kofs, port_off, port_node,
+                       pc, pbeta, pgamma, K, pofs, M, B);
     return hipGetLastError();
 }
 
@@ -325,9 +329,15 @@ hipError_t launch_sweep_pp(int S, int max_q, const TO* M, const int64_t* pofs, c
     if (max_q <= 32)
         hipLaunchKernelGGL((k_sweep_pp<TO, TV, 2>), dim3(S), dim3(64), lds, st, M, pofs, port_off, port_twin, h,
                            a_cur, a_next, max_q);
-    else
-        hipLaunchKernelGGL((k_sweep_pp<TO, TV, 1>), dim3(S), dim3(max_q <= 64 ? 64 : 256), lds, st, M, pofs,
-                           port_off, port_twin, h, a_cur, a_next, max_q);
+    else {
+        // few sub-circuits with many ports: one-wavefront blocks, each sub-circuit's rows
+        // spread over several
+        const bool split = S < 1024 && max_q > 64;
+        const int bs = split || max_q <= 64 ? 64 : 256;
+        const int ry = split ? (max_q + bs - 1) / bs : 1;
+        hipLaunchKernelGGL((k_sweep_pp<TO, TV, 1>), dim3(S, ry), dim3(bs), lds, st, M, pofs, port_off, port_twin,
+                           h, a_cur, a_next, max_q);
+    }
     return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 // "C + W" block of eq. 11 once the twin is eliminated).  Inverted by
 // Gauss-Jordan elimination with partial pivoting, in FP64, then written in the
 // working precision and the column-group layout of layout.hpp.
+#include <algorithm>
 #include <climits>
 
 #include "kernels.hpp"
@@ -56,9 +57,9 @@ __device__ int block_argmax(const double* colp, int stride, int lo, int n, doubl
 // Writes the column-major FP64 inverse Mcm (Mcm[c * n + r] = Kinv(r, c)) into
 // dst in the column-group layout; destination-ordered, so stores are coalesced.
 template <typename TO>
-__device__ void store_layout(const double* Mcm, int n, TO* dst) {
+__device__ void store_layout(const double* Mcm, int n, TO* dst, int part = 0, int parts = 1) {
     const int64_t cnt = int64_t(n) * n;
-    for (int64_t d = threadIdx.x; d < cnt; d += blockDim.x) {
+    for (int64_t d = int64_t(part) * blockDim.x + threadIdx.x; d < cnt; d += int64_t(blockDim.x) * parts) {
         int r, c;
         inv_rc<TO>(n, d, r, c);
         dst[d] = TO(Mcm[int64_t(c) * n + r]);
@@ -170,107 +171,138 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
-// ... and invert it in place, nb columns at a time.  The panel is eliminated in
-// LDS (pivot search over all rows below the diagonal); its row swaps and its
-// elimination steps are then applied to every other column as one rank-kb
-// update: R <- P R + (E_J - I_J) (P R)_J, where E_J are the panel columns after
-// elimination and P the panel's row swaps.  Columns are unscrambled at the end.
-template <int NB>
-__global__ void __launch_bounds__(kBlock)
-    k_gj_global(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs,
-                double* __restrict__ base, int nb, int* flag) {
-    extern __shared__ double sm[];
+// ... and invert it in place, kNB columns at a time (blocked Gauss-Jordan with
+// partial pivoting).  Each panel step is two launches, so that a few large
+// sub-circuits still spread over the whole chip.  k_gj_panel (one workgroup per
+// sub-circuit) eliminates the panel's columns (pivot search over all rows below
+// the diagonal; the panel E_J in global memory, [n][kNB] at panel + 2 kNB
+// sub_off[s]), applies the panel's row swaps P to every other column and keeps
+// their pivot rows (P R)_J ([kNB][n] right after E_J).  k_gj_update then
+// applies the elimination to every other column as one rank-kb update,
+// R <- P R + (E_J - I_J) (P R)_J, over a grid of column blocks x row blocks.
+// k_gj_unscramble undoes the pivoting's column order at the end.
+constexpr int kNB = 16;
+constexpr int kMaxLarge = 2048;   // largest sub-circuit (the planner's limit)
+constexpr int kPanelBlock = 512;
+constexpr int kUpdateRows = 128;  // rows per thread of the update
+
+__global__ void __launch_bounds__(kPanelBlock)
+    k_gj_panel(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
+               int k0, double* __restrict__ panel, int32_t* __restrict__ ipiv, int* flag) {
+    __shared__ double fcol[kMaxLarge];
+    __shared__ double red_v[kPanelBlock / 64];
+    __shared__ int red_i[kPanelBlock / 64];
+    __shared__ int piv[kNB];
     const int s = blockIdx.x;
-    const int n = sub_off[s + 1] - sub_off[s];
-    if (n <= kLdsSetupMax) return;
+    const int off = sub_off[s], n = sub_off[s + 1] - off;
+    if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;
+    const int kb = min(kNB, n - k0);
     double* M = base + kofs[s];
-    double* Pn = sm;                 // [n][nb]
-    double* fcol = Pn + n * nb;      // [n]
-    double* red_v = fcol + n;        // [4]
-    int* red_i = reinterpret_cast<int*>(red_v + 4);
-    int* ipiv = red_i + 4;           // [n]
+    double* Pn = panel + int64_t(off) * 2 * kNB;
+    double* R = Pn + int64_t(n) * kNB;
     const int tid = threadIdx.x, bs = blockDim.x;
     bool bad = false;
-
-    for (int k0 = 0; k0 < n; k0 += nb) {
-        const int kb = min(nb, n - k0);
-        for (int t = tid; t < n * kb; t += bs) {
-            const int i = t / kb, jj = t - i * kb;
-            Pn[i * nb + jj] = M[int64_t(i) * n + k0 + jj];
+    for (int t = tid; t < n * kb; t += bs) {
+        const int i = t / kb, jj = t - i * kb;
+        Pn[i * kNB + jj] = M[int64_t(i) * n + k0 + jj];
+    }
+    __syncthreads();
+    for (int kk = 0; kk < kb; ++kk) {
+        const int k = k0 + kk;
+        int p = block_argmax(Pn + kk, kNB, k, n, red_v, red_i);
+        if (p == INT_MAX) {
+            bad = true;
+            p = k;
         }
+        if (tid == 0) {
+            ipiv[off + k] = p;
+            piv[kk] = p;
+        }
+        if (p != k)
+            for (int jj = tid; jj < kb; jj += bs) {
+                const double t = Pn[k * kNB + jj];
+                Pn[k * kNB + jj] = Pn[p * kNB + jj];
+                Pn[p * kNB + jj] = t;
+            }
         __syncthreads();
-        for (int kk = 0; kk < kb; ++kk) {
-            const int k = k0 + kk;
-            int p = block_argmax(Pn + kk, nb, k, n, red_v, red_i);
-            if (p == INT_MAX) {
-                bad = true;
-                p = k;
-            }
-            if (tid == 0) ipiv[k] = p;
-            if (p != k)
-                for (int jj = tid; jj < kb; jj += bs) {
-                    const double t = Pn[k * nb + jj];
-                    Pn[k * nb + jj] = Pn[p * nb + jj];
-                    Pn[p * nb + jj] = t;
-                }
-            __syncthreads();
-            double pv = Pn[k * nb + kk];
-            if (pv == 0.0 || !isfinite(pv)) {
-                bad = true;
-                pv = 1.0;
-            }
-            for (int i = tid; i < n; i += bs) fcol[i] = Pn[i * nb + kk];
-            __syncthreads();
-            for (int jj = tid; jj < kb; jj += bs) Pn[k * nb + jj] = (jj == kk ? 1.0 : Pn[k * nb + jj]) / pv;
-            __syncthreads();
-            for (int t = tid; t < n * kb; t += bs) {
-                const int i = t / kb, jj = t - i * kb;
-                if (i != k) Pn[i * nb + jj] = (jj == kk ? 0.0 : Pn[i * nb + jj]) - fcol[i] * Pn[k * nb + jj];
-            }
-            __syncthreads();
+        double pv = Pn[k * kNB + kk];
+        if (pv == 0.0 || !isfinite(pv)) {
+            bad = true;
+            pv = 1.0;
         }
-        for (int c = tid; c < n; c += bs) {
-            if (c >= k0 && c < k0 + kb) continue;
-            double rj[NB];
-#pragma unroll
-            for (int kk = 0; kk < NB; ++kk) {
-                if (kk < kb) {
-                    const int k = k0 + kk, p = ipiv[k];
-                    if (p != k) {
-                        const double t = M[int64_t(k) * n + c];
-                        M[int64_t(k) * n + c] = M[int64_t(p) * n + c];
-                        M[int64_t(p) * n + c] = t;
-                    }
-                }
-            }
-#pragma unroll
-            for (int kk = 0; kk < NB; ++kk) rj[kk] = kk < kb ? M[int64_t(k0 + kk) * n + c] : 0.0;
-            for (int i = 0; i < n; ++i) {
-                double acc = M[int64_t(i) * n + c];
-#pragma unroll
-                for (int kk = 0; kk < NB; ++kk)
-                    if (kk < kb) acc += (Pn[i * nb + kk] - (i == k0 + kk ? 1.0 : 0.0)) * rj[kk];
-                M[int64_t(i) * n + c] = acc;
-            }
-        }
+        for (int i = tid; i < n; i += bs) fcol[i] = Pn[i * kNB + kk];
+        __syncthreads();
+        for (int jj = tid; jj < kb; jj += bs) Pn[k * kNB + jj] = (jj == kk ? 1.0 : Pn[k * kNB + jj]) / pv;
         __syncthreads();
         for (int t = tid; t < n * kb; t += bs) {
             const int i = t / kb, jj = t - i * kb;
-            M[int64_t(i) * n + k0 + jj] = Pn[i * nb + jj];
+            if (i != k) Pn[i * kNB + jj] = (jj == kk ? 0.0 : Pn[i * kNB + jj]) - fcol[i] * Pn[k * kNB + jj];
         }
         __syncthreads();
     }
-    for (int k = n - 1; k >= 0; --k) {
-        const int p = ipiv[k];
-        if (p != k)
-            for (int i = tid; i < n; i += bs) {
-                const double t = M[int64_t(i) * n + k];
-                M[int64_t(i) * n + k] = M[int64_t(i) * n + p];
-                M[int64_t(i) * n + p] = t;
+    // the panel's columns are final for this step; every other column gets the row
+    // swaps, and its pivot rows are kept for the update
+    for (int t = tid; t < n * kb; t += bs) {
+        const int i = t / kb, jj = t - i * kb;
+        M[int64_t(i) * n + k0 + jj] = Pn[i * kNB + jj];
+    }
+    for (int c = tid; c < n; c += bs) {
+        if (c >= k0 && c < k0 + kb) continue;
+        for (int kk = 0; kk < kb; ++kk) {
+            const int k = k0 + kk, p = piv[kk];
+            if (p != k) {
+                const double t = M[int64_t(k) * n + c];
+                M[int64_t(k) * n + c] = M[int64_t(p) * n + c];
+                M[int64_t(p) * n + c] = t;
             }
-        __syncthreads();
+        }
+        for (int kk = 0; kk < kb; ++kk) R[int64_t(kk) * n + c] = M[int64_t(k0 + kk) * n + c];
     }
     if (bad && tid == 0) atomicOr(flag, 1);
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_gj_update(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
+                int k0, const double* __restrict__ panel) {
+    const int s = blockIdx.x;
+    const int off = sub_off[s], n = sub_off[s + 1] - off;
+    if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;
+    const int kb = min(kNB, n - k0);
+    const int c = blockIdx.y * blockDim.x + threadIdx.x;
+    const int i0 = blockIdx.z * kUpdateRows, i1 = min(n, i0 + kUpdateRows);
+    if (c >= n || (c >= k0 && c < k0 + kb) || i0 >= n) return;
+    double* M = base + kofs[s];
+    const double* Pn = panel + int64_t(off) * 2 * kNB;
+    const double* R = Pn + int64_t(n) * kNB;
+    double rj[kNB];
+#pragma unroll
+    for (int kk = 0; kk < kNB; ++kk) rj[kk] = kk < kb ? R[int64_t(kk) * n + c] : 0.0;
+    for (int i = i0; i < i1; ++i) {
+        double acc = M[int64_t(i) * n + c];
+#pragma unroll
+        for (int kk = 0; kk < kNB; ++kk)
+            if (kk < kb) acc += (Pn[i * kNB + kk] - (i == k0 + kk ? 1.0 : 0.0)) * rj[kk];
+        M[int64_t(i) * n + c] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_gj_unscramble(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
+                    const int32_t* __restrict__ ipiv) {
+    const int s = blockIdx.x;
+    const int off = sub_off[s], n = sub_off[s + 1] - off;
+    if (n <= kLdsSetupMax || n > kMaxLarge) return;
+    const int i = blockIdx.y * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double* row = base + kofs[s] + int64_t(i) * n;
+    for (int k = n - 1; k >= 0; --k) {
+        const int p = ipiv[off + k];
+        if (p != k) {
+            const double t = row[k];
+            row[k] = row[p];
+            row[p] = t;
+        }
+    }
 }
 
 // column-major FP64 scratch -> working precision, column-group layout
@@ -281,7 +313,7 @@ __global__ void __launch_bounds__(kBlock)
     const int s = blockIdx.x;
     const int n = sub_off[s + 1] - sub_off[s];
     if (n <= kLdsSetupMax) return;
-    store_layout<TO>(src + kofs[s], n, dst + kofs[s]);
+    store_layout<TO>(src + kofs[s], n, dst + kofs[s], int(blockIdx.y), int(gridDim.y));
 }
 
 // column-major FP64 scratch -> zero-padded MFMA operand tiles (tiles.hpp)
@@ -295,29 +327,38 @@ __global__ void __launch_bounds__(kBlock)
     const double* M = src + kofs[s];
     T* o = dst + mofs[s];
     const int64_t cnt = int64_t(np) * np;
-    for (int64_t d = threadIdx.x; d < cnt; d += blockDim.x) {
+    for (int64_t d = int64_t(blockIdx.y) * blockDim.x + threadIdx.x; d < cnt; d += int64_t(blockDim.x) * gridDim.y) {
         int r, c;
         tile_rc<T>(np, d, r, c);
         o[d] = (r < n && c < n) ? static_cast<T>(M[int64_t(c) * n + r]) : static_cast<T>(0.0);
     }
 }
 
+// workgroups per sub-circuit for an n x n copy: enough for some 2048 workgroups in all
+int copy_parts(int S, int n) {
+    const int64_t per = (int64_t(n) * n + 4095) / 4096;  // at 16 elements per thread
+    const int64_t want = (2048 + S - 1) / S;
+    return int(std::max<int64_t>(1, std::min<int64_t>(per, want)));
+}
+
 // the large sub-circuits: assemble and invert in FP64 scratch (column-major)
 hipError_t invert_large(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, const int32_t* rowptr,
-                        const int32_t* col, const double* val, const double* dmod, double* scratch64, int* flag,
-                        hipStream_t st) {
-    if (!scratch64) return hipErrorInvalidValue;
+                        const int32_t* col, const double* val, const double* dmod, double* scratch64, double* panel,
+                        int32_t* ipiv, int* flag, hipStream_t st) {
+    if (!scratch64 || !panel || !ipiv || max_ns > kMaxLarge) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_assemble, dim3(S), dim3(kBlock), 0, st, sub_off, kofs, rowptr, col, val, dmod, scratch64);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // panel width: as many columns as fit next to the pivot bookkeeping in 64 KiB of LDS
-    constexpr int kLds = 65536;
-    const int fixed = max_ns * (8 + 4) + 64;
-    int nb = (kLds - fixed) / (8 * max_ns);
-    if (nb < 1) return hipErrorInvalidValue;
-    nb = nb > 16 ? 16 : nb;
-    const size_t lds = size_t(max_ns) * nb * 8 + fixed;
-    hipLaunchKernelGGL(k_gj_global<16>, dim3(S), dim3(kBlock), lds, st, sub_off, kofs, scratch64, nb, flag);
+    const dim3 cols(unsigned(S), unsigned((max_ns + kBlock - 1) / kBlock));
+    const dim3 tiles(unsigned(S), cols.y, unsigned((max_ns + kUpdateRows - 1) / kUpdateRows));
+    for (int k0 = 0; k0 < max_ns; k0 += kNB) {
+        hipLaunchKernelGGL(k_gj_panel, dim3(S), dim3(kPanelBlock), 0, st, sub_off, kofs, scratch64, k0, panel, ipiv,
+                           flag);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gj_update, tiles, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_gj_unscramble, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, ipiv);
     return hipGetLastError();
 }
 
@@ -326,43 +367,47 @@ hipError_t invert_large(int S, int max_ns, const int32_t* sub_off, const int64_t
 template <typename T>
 hipError_t launch_setup_tiles(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, const int64_t* mofs,
                               const int32_t* rowptr, const int32_t* col, const double* val, const double* dmod,
-                              T* out, double* scratch64, int* flag, hipStream_t st) {
+                              T* out, double* scratch64, double* panel, int32_t* ipiv, int* flag, hipStream_t st) {
     if (!scratch64) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_setup_lds<double, true>), dim3(S), dim3(kBlock), 0, st, sub_off, kofs, rowptr, col, val,
                        dmod, scratch64, flag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (max_ns > kLdsSetupMax) {
-        e = invert_large(S, max_ns, sub_off, kofs, rowptr, col, val, dmod, scratch64, flag, st);
+        e = invert_large(S, max_ns, sub_off, kofs, rowptr, col, val, dmod, scratch64, panel, ipiv, flag, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_to_tiles<T>, dim3(S), dim3(kBlock), 0, st, sub_off, kofs, mofs, scratch64, out);
+    hipLaunchKernelGGL(k_to_tiles<T>, dim3(S, copy_parts(S, tile_pad(max_ns))), dim3(kBlock), 0, st, sub_off, kofs,
+                       mofs, scratch64, out);
     return hipGetLastError();
 }
 
 template <typename TO>
 hipError_t launch_setup(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, const int32_t* rowptr,
                         const int32_t* col, const double* val, const double* dmod, TO* out, double* scratch64,
-                        int* flag, hipStream_t st) {
+                        double* panel, int32_t* ipiv, int* flag, hipStream_t st) {
     hipLaunchKernelGGL((k_setup_lds<TO, false>), dim3(S), dim3(kBlock), 0, st, sub_off, kofs, rowptr, col, val,
                        dmod, out, flag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || max_ns <= kLdsSetupMax) return e;
-    e = invert_large(S, max_ns, sub_off, kofs, rowptr, col, val, dmod, scratch64, flag, st);
+    e = invert_large(S, max_ns, sub_off, kofs, rowptr, col, val, dmod, scratch64, panel, ipiv, flag, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_to_layout<TO>, dim3(S), dim3(kBlock), 0, st, sub_off, kofs, scratch64, out);
+    hipLaunchKernelGGL(k_to_layout<TO>, dim3(S, copy_parts(S, max_ns)), dim3(kBlock), 0, st, sub_off, kofs, scratch64,
+                       out);
     return hipGetLastError();
 }
 
 template hipError_t launch_setup<double>(int, int, const int32_t*, const int64_t*, const int32_t*, const int32_t*,
-                                         const double*, const double*, double*, double*, int*, hipStream_t);
+                                         const double*, const double*, double*, double*, double*, int32_t*, int*,
+                                         hipStream_t);
 template hipError_t launch_setup<float>(int, int, const int32_t*, const int64_t*, const int32_t*, const int32_t*,
-                                        const double*, const double*, float*, double*, int*, hipStream_t);
+                                        const double*, const double*, float*, double*, double*, int32_t*, int*,
+                                        hipStream_t);
 template hipError_t launch_setup_tiles<__bf16>(int, int, const int32_t*, const int64_t*, const int64_t*,
                                               const int32_t*, const int32_t*, const double*, const double*, __bf16*,
-                                              double*, int*, hipStream_t);
+                                              double*, double*, int32_t*, int*, hipStream_t);
 template hipError_t launch_setup_tiles<double>(int, int, const int32_t*, const int64_t*, const int64_t*,
                                               const int32_t*, const int32_t*, const double*, const double*, double*,
-                                              double*, int*, hipStream_t);
+                                              double*, double*, int32_t*, int*, hipStream_t);
 
 }  // namespace vtm

@@ -160,6 +160,10 @@ __global__ void __launch_bounds__(kBlock)
     const int full = (ns / G) * G;
     const int ngroups = full / G;
     const int nch = (ngroups + CH - 1) / CH;
+    // rows of this block: [y * bs, y * bs + bs) + k * bs * gridDim.y (gridDim.y > 1 spreads the
+    // rows of a few large sub-circuits over several workgroups)
+    const int row0 = int(blockIdx.y) * bs, rstep = bs * int(gridDim.y);
+    if (row0 >= ns) return;  // uniform over the workgroup
 
     TO buf0[CH][G], buf1[CH][G];
     auto load_chunk = [&](TO (&buf)[CH][G], int ch, int row) {
@@ -174,7 +178,7 @@ __global__ void __launch_bounds__(kBlock)
             }
         }
     };
-    if (tid < ns) load_chunk(buf0, 0, tid);
+    if (row0 + tid < ns) load_chunk(buf0, 0, row0 + tid);
 
     for (int t = tid; t < ns; t += bs) rhs[t] = b[off + t];
     __syncthreads();
@@ -191,8 +195,8 @@ __global__ void __launch_bounds__(kBlock)
         }
     }
 
-    for (int row = tid; row < ns; row += bs) {
-        if (row != tid) load_chunk(buf0, 0, row);
+    for (int row = row0 + tid; row < ns; row += rstep) {
+        if (row != row0 + tid) load_chunk(buf0, 0, row);
         TV acc[G];
 #pragma unroll
         for (int q = 0; q < G; ++q) acc[q] = TV(0);
@@ -221,7 +225,11 @@ __global__ void __launch_bounds__(kBlock)
         x[off + row] = v;
     }
     __syncthreads();
-    for (int p = p0 + tid; p < p1; p += bs) a_next[port_twin[p]] = pbeta[p] * xs[port_node[p]] + pgamma[p] * a_cur[p];
+    for (int p = p0 + tid; p < p1; p += bs) {
+        const int node = port_node[p];
+        if ((node / bs) % int(gridDim.y) == int(blockIdx.y))  // x of this node was formed here
+            a_next[port_twin[p]] = pbeta[p] * xs[node] + pgamma[p] * a_cur[p];
+    }
 }
 
 template <typename TO, typename TV, int R>
@@ -246,9 +254,12 @@ hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t*
     // right-hand sides per block: rhs and x of the sub-circuit must fit 64 KiB of LDS
     auto fits = [&](int r) { return size_t(2) * max_ns * r * sizeof(TV) <= 65536; };
     if (kSweepChunk > 0 && nrhs == 1 && !adjoint && fits(1)) {
-        const int bs = max_ns <= 64 ? 64 : kBlock;
+        // few sub-circuits: one-wavefront blocks, each sub-circuit's rows spread over several
+        const bool split = S < 1024 && max_ns > 64;
+        const int bs = split || max_ns <= 64 ? 64 : kBlock;
+        const int ry = split ? (max_ns + bs - 1) / bs : 1;
         const size_t lds = size_t(2) * max_ns * sizeof(TV);
-        hipLaunchKernelGGL((k_sweep1<TO, TV, (kSweepChunk > 0 ? kSweepChunk : 1)>), dim3(S), dim3(bs), lds, st, K, kofs, sub_off, ports.off,
+        hipLaunchKernelGGL((k_sweep1<TO, TV, (kSweepChunk > 0 ? kSweepChunk : 1)>), dim3(S, ry), dim3(bs), lds, st, K, kofs, sub_off, ports.off,
                            ports.node, ports.slot, ports.twin, pc, pbeta, pgamma, b, a_cur, a_next, x, max_ns,
                            ports.max_slot);
         return hipGetLastError();

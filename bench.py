@@ -276,11 +276,13 @@ def preconditioners(vtm, torch, workloads):
 def vertex_tearing(vtm, torch, workloads):
     """Tearing at interfacial nodes (Section V) with the admittance rules of
     Section VIII as coupled lines, on unit resistor grids like Table I's Grid2d
-    and Grid3d (0.01 S to ground everywhere), cut into strips / slabs by
-    separator layers small enough for the 2048-node sub-circuit limit: sweeps
+    and Grid3d (0.01 S to ground everywhere), torn in two by one separator
+    layer (Table II's setting) or cut into strips / slabs by several: sweeps
     and time to 1e-8, setup time, residual checked on the host."""
     out = {}
-    for name, dims, width in (("grid2d_100x100_strips_of_18", (100, 100), 18),
+    for name, dims, width in (("grid2d_100x100_one_separator", (100, 100), 49),
+                              ("grid2d_100x100_strips_of_18", (100, 100), 18),
+                              ("grid3d_20x20x20_one_separator", (20, 20, 20), 9),
                               ("grid3d_20x20x40_slabs_of_2", (20, 20, 40), 2)):
         e = workloads.grid2d_edges(*dims) if len(dims) == 2 else workloads.grid3d_edges(*dims)
         n = int(np.prod(dims))

@@ -159,7 +159,7 @@ void vtm_default_options(vtm_options *opt);
  *
  * Every pair (i, j) in different sub-circuits with a nonzero entry must have
  * A_ij == A_ji < 0 (a two-terminal conductance g = -A_ij), else
- * VTM_E_UNTEARABLE.  Sub-circuits may not exceed 2048 nodes
+ * VTM_E_UNTEARABLE.  Sub-circuits may not exceed 8192 nodes
  * (VTM_E_UNSUPPORTED).  n and nnz must fit int32.  A sub-circuit matrix
  * (with its port conductances) whose elimination meets an exactly zero or
  * non-finite pivot gives VTM_E_SINGULAR.  Returns after the setup kernels

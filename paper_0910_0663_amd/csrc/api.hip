@@ -298,12 +298,12 @@ vtm_status launch_one(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
                                                    h->ports(), h->c64.p, h->beta64.p, h->gamma64.p,
                                                    static_cast<const double*>(b), h->a64[cur].p,
                                                    h->a64[cur ^ 1].p, static_cast<double*>(x), adjoint,
-                                                   h->stream)));
+                                                   h->lds_limit, h->stream)));
     } else {
         VTM_HIP((vtm::launch_sweep<float, float>(int(P.S), P.max_ns, nrhs, h->K32.p, h->kofs.p, h->sub_off.p,
                                                  h->ports(), h->c32.p, h->beta32.p, h->gamma32.p,
                                                  static_cast<const float*>(b), h->a32[cur].p, h->a32[cur ^ 1].p,
-                                                 static_cast<float*>(x), adjoint, h->stream)));
+                                                 static_cast<float*>(x), adjoint, h->lds_limit, h->stream)));
     }
     return VTM_OK;
 }
@@ -1174,7 +1174,7 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
     DevBuf<int32_t> ipiv;
     if (h->tiles || P.max_ns > vtm::kLdsSetupMax) VTM_HIP(scratch.alloc(nk));
     if (P.max_ns > vtm::kLdsSetupMax) {
-        VTM_HIP(panel.alloc(P.n * 32));
+        VTM_HIP(panel.alloc(P.n * 33));
         VTM_HIP(ipiv.alloc(P.n));
     }
     VTM_HIP(h->c64.upload(P.pc, s));

@@ -39,7 +39,7 @@ struct PortArrays {
 // ns <= kLdsSetupMax are inverted in LDS; larger ones are assembled into
 // scratch64 (FP64, same offsets, must be non-null then) and inverted there by a
 // blocked Gauss-Jordan elimination with partial pivoting, whose panels use
-// panel (n x 32 doubles) and ipiv (n ints), both non-null then.  flag bit 0 =
+// panel (n x 33 doubles) and ipiv (n ints), both non-null then.  flag bit 0 =
 // singular.
 template <typename TO>
 hipError_t launch_setup(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs,
@@ -66,7 +66,7 @@ template <typename TO, typename TV>
 hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t* kofs,
                         const int32_t* sub_off, PortArrays ports, const TV* pc, const TV* pbeta,
                         const TV* pgamma, const TV* b, const TV* a_cur, TV* a_next, TV* x,
-                        bool adjoint, hipStream_t st);
+                        bool adjoint, size_t lds_limit, hipStream_t st);
 
 // Batched sweep on MFMA (mfma.hip) with the inverses in tile layout: per
 // sub-circuit X = Kinv [b + c a] for blocks of up to 64 right-hand sides, then

@@ -90,8 +90,8 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
     P.sub_off.assign(S + 1, 0);
     for (int64_t s = 0; s < S; ++s) P.sub_off[s + 1] = P.sub_off[s] + count[s];
     P.max_ns = *std::max_element(count.begin(), count.end());
-    if (P.max_ns > 2048) {
-        err = "a sub-circuit has more than 2048 nodes";
+    if (P.max_ns > kMaxSubCircuit) {
+        err = "a sub-circuit has more than " + std::to_string(kMaxSubCircuit) + " nodes";
         return VTM_E_UNSUPPORTED;
     }
     P.perm.resize(n);

@@ -177,19 +177,19 @@ __global__ void __launch_bounds__(kBlock)
 // sub-circuit) eliminates the panel's columns (pivot search over all rows below
 // the diagonal; the panel E_J in global memory, [n][kNB] at panel + 2 kNB
 // sub_off[s]), applies the panel's row swaps P to every other column and keeps
-// their pivot rows (P R)_J ([kNB][n] right after E_J).  k_gj_update then
+// their pivot rows (P R)_J ([kNB][n] right after E_J; then n doubles of
+// scratch for the pivot column).  k_gj_update then
 // applies the elimination to every other column as one rank-kb update,
 // R <- P R + (E_J - I_J) (P R)_J, over a grid of column blocks x row blocks.
 // k_gj_unscramble undoes the pivoting's column order at the end.
 constexpr int kNB = 16;
-constexpr int kMaxLarge = 2048;   // largest sub-circuit (the planner's limit)
+constexpr int kMaxLarge = 8192;   // largest sub-circuit (the planner's limit)
 constexpr int kPanelBlock = 512;
 constexpr int kUpdateRows = 128;  // rows per thread of the update
 
 __global__ void __launch_bounds__(kPanelBlock)
     k_gj_panel(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
                int k0, double* __restrict__ panel, int32_t* __restrict__ ipiv, int* flag) {
-    __shared__ double fcol[kMaxLarge];
     __shared__ double red_v[kPanelBlock / 64];
     __shared__ int red_i[kPanelBlock / 64];
     __shared__ int piv[kNB];
@@ -198,8 +198,9 @@ __global__ void __launch_bounds__(kPanelBlock)
     if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;
     const int kb = min(kNB, n - k0);
     double* M = base + kofs[s];
-    double* Pn = panel + int64_t(off) * 2 * kNB;
+    double* Pn = panel + int64_t(off) * (2 * kNB + 1);
     double* R = Pn + int64_t(n) * kNB;
+    double* fcol = R + int64_t(n) * kNB;
     const int tid = threadIdx.x, bs = blockDim.x;
     bool bad = false;
     for (int t = tid; t < n * kb; t += bs) {
@@ -272,7 +273,7 @@ __global__ void __launch_bounds__(kBlock)
     const int i0 = blockIdx.z * kUpdateRows, i1 = min(n, i0 + kUpdateRows);
     if (c >= n || (c >= k0 && c < k0 + kb) || i0 >= n) return;
     double* M = base + kofs[s];
-    const double* Pn = panel + int64_t(off) * 2 * kNB;
+    const double* Pn = panel + int64_t(off) * (2 * kNB + 1);
     const double* R = Pn + int64_t(n) * kNB;
     double rj[kNB];
 #pragma unroll

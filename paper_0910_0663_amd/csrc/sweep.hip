@@ -239,6 +239,9 @@ hipError_t launch_r(int S, int max_ns, int nrhs, const TO* K, const int64_t* kof
     const int bs = max_ns <= 64 ? 64 : kBlock;
     const size_t lds = size_t(2) * max_ns * R * sizeof(TV);
     const unsigned ny = unsigned((nrhs + R - 1) / R);
+    if (lds > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep<TO, TV, R>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     hipLaunchKernelGGL((k_sweep<TO, TV, R>), dim3(S, ny), dim3(bs), lds, st, K, kofs, sub_off, ports.off,
                        ports.node, ports.slot, ports.twin, pc, pbeta, pgamma, b, a_cur, a_next, x, nrhs, max_ns,
                        ports.max_slot, adjoint ? 1 : 0);
@@ -250,22 +253,28 @@ hipError_t launch_r(int S, int max_ns, int nrhs, const TO* K, const int64_t* kof
 template <typename TO, typename TV>
 hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t* kofs, const int32_t* sub_off,
                         PortArrays ports, const TV* pc, const TV* pbeta, const TV* pgamma, const TV* b,
-                        const TV* a_cur, TV* a_next, TV* x, bool adjoint, hipStream_t st) {
-    // right-hand sides per block: rhs and x of the sub-circuit must fit 64 KiB of LDS
+                        const TV* a_cur, TV* a_next, TV* x, bool adjoint, size_t lds_limit, hipStream_t st) {
+    // right-hand sides per block: rhs and x of the sub-circuit in 64 KiB of LDS; one
+    // right-hand side of a larger sub-circuit may use up to lds_limit
     auto fits = [&](int r) { return size_t(2) * max_ns * r * sizeof(TV) <= 65536; };
-    if (kSweepChunk > 0 && nrhs == 1 && !adjoint && fits(1)) {
+    const bool one = fits(1) || size_t(2) * max_ns * sizeof(TV) <= lds_limit;
+    if (kSweepChunk > 0 && nrhs == 1 && !adjoint && one) {
         // few sub-circuits: one-wavefront blocks, each sub-circuit's rows spread over several
         const bool split = S < 1024 && max_ns > 64;
         const int bs = split || max_ns <= 64 ? 64 : kBlock;
         const int ry = split ? (max_ns + bs - 1) / bs : 1;
         const size_t lds = size_t(2) * max_ns * sizeof(TV);
-        hipLaunchKernelGGL((k_sweep1<TO, TV, (kSweepChunk > 0 ? kSweepChunk : 1)>), dim3(S, ry), dim3(bs), lds, st, K, kofs, sub_off, ports.off,
+        constexpr int CH = kSweepChunk > 0 ? kSweepChunk : 1;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep1<TO, TV, CH>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        hipLaunchKernelGGL((k_sweep1<TO, TV, CH>), dim3(S, ry), dim3(bs), lds, st, K, kofs, sub_off, ports.off,
                            ports.node, ports.slot, ports.twin, pc, pbeta, pgamma, b, a_cur, a_next, x, max_ns,
                            ports.max_slot);
         return hipGetLastError();
     }
     if (nrhs == 1 || !fits(2))
-        return fits(1) ? launch_r<TO, TV, 1>(S, max_ns, nrhs, K, kofs, sub_off, ports, pc, pbeta, pgamma, b, a_cur,
+        return one ? launch_r<TO, TV, 1>(S, max_ns, nrhs, K, kofs, sub_off, ports, pc, pbeta, pgamma, b, a_cur,
                                              a_next, x, adjoint, st)
                        : hipErrorInvalidValue;
     if (nrhs == 2 || !fits(4))
@@ -280,10 +289,11 @@ hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t*
 
 template hipError_t launch_sweep<double, double>(int, int, int, const double*, const int64_t*, const int32_t*,
                                                  PortArrays, const double*, const double*, const double*,
-                                                 const double*, const double*, double*, double*, bool,
+                                                 const double*, const double*, double*, double*, bool, size_t,
                                                  hipStream_t);
 template hipError_t launch_sweep<float, float>(int, int, int, const float*, const int64_t*, const int32_t*,
                                                PortArrays, const float*, const float*, const float*,
-                                               const float*, const float*, float*, float*, bool, hipStream_t);
+                                               const float*, const float*, float*, float*, bool, size_t,
+                                               hipStream_t);
 
 }  // namespace vtm

@@ -176,14 +176,15 @@ def test_singular_sub_circuit_is_reported(torch):
 
 @pytest.mark.parametrize("kw", [dict(), dict(nrhs=16)])
 def test_largest_sub_circuits(torch, kw):
-    """Two sub-circuits of 2,048 nodes (the largest a handle takes, inverted in
-    blocked global-memory Gauss-Jordan): iterates equal the oracle's in the
-    port (64 port nodes, one sub-circuit per wavefront) and full forms; with 16
-    right-hand sides the FP64 handle keeps the column-group layout because a
-    2,048-row block does not fit the batched sweep's LDS staging."""
-    w = workloads.make(1, dims=(64, 64), block=(64, 32), **kw)
-    assert w.n_sub == 2 and np.bincount(w.part).max() == 2048
-    ks = [3]  # each handle inverts two 2,048 x 2,048 blocks on two CUs: keep the handles few
+    """Two sub-circuits of 8,192 nodes (the largest a handle takes, inverted in
+    blocked global-memory Gauss-Jordan; the full sweep stages 128 KiB of LDS):
+    iterates equal the oracle's in the port (128 ports each, dense operator)
+    and full forms; with 16 right-hand sides the FP64 handle keeps the
+    column-group layout because an 8,192-row block does not fit the batched
+    sweep's LDS staging."""
+    w = workloads.make(1, dims=(128, 128), block=(128, 64), **kw)
+    assert w.n_sub == 2 and np.bincount(w.part).max() == 8192
+    ks = [3]
     ref = oracle_iterates(w, ks)
     for form in ("port", "full"):
         for k in ks:

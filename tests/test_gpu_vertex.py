@@ -291,3 +291,28 @@ def test_coupled_W_is_checked(torch):
     X = Wd.copy()
     X[3, 3] = 0.0                                   # no positive diagonal
     assert status(X) == "VTM_E_ARG"
+
+
+def test_table2_two_sub_circuits_on_the_gpu(torch):
+    """Table II's Grid2d setting itself: a 100 x 100 unit resistor grid torn into
+    two sub-circuits at one separator column of 100 interfacial nodes (5,050
+    torn nodes each).  The GPU's sweep counts are the oracle's for the
+    diagonal, overlapped-block and weighted overlapped-block W, and x is the
+    direct solution."""
+    dims = (100, 100)
+    e = workloads.grid2d_edges(*dims)
+    n = int(np.prod(dims))
+    A = workloads.nodal_matrix(n, e, np.ones(e.shape[0]), np.full(n, workloads.GROUND_S))
+    b = np.random.default_rng(0).standard_normal((1, n))
+    label, iface, sides = workloads.separator_strips(dims, 49)
+    assert iface.size == 100 and label.max() == 1
+    xs = spla.spsolve(A.tocsc(), b[0])
+    for rule, alpha in (("diag", 1.0), ("ob", 1.0), ("wob", 0.3)):
+        W = vtm().vertex_admittance(A, label, iface, sides, rule, alpha)
+        r = oracle.vtm_solve(oracle.tear_at_vertices(A, label, iface, sides, W.toarray()), A, b, 1e-8,
+                             max_sweeps=5000)
+        s = solver(A, label, iface, sides, W, check_every=1, adaptive_checks=False)
+        x, rep = s.solve(to_dev(torch, b), 1e-8)
+        assert abs(rep.sweeps - r.sweeps) <= 1, (rule, rep.sweeps, r.sweeps)
+        assert np.abs(x.cpu().numpy()[0] - xs).max() <= 1e-6 * np.abs(xs).max()
+        s.close()

@@ -292,8 +292,11 @@ def vertex_tearing(vtm, torch, workloads):
         x = torch.empty_like(b)
         label, iface, sides = workloads.separator_strips(dims, width)
         rows = []
-        for rule, alpha in (("identity", 1.0), ("diag", 1.0), ("ob", 1.0), ("wob", 0.3)):
-            W = vtm.vertex_admittance(A, label, iface, sides, rule, alpha)
+        for rule, alpha in (("identity", 1.0), ("diag", 1.0), ("ob", 1.0), ("wob", 0.3), ("sca_depth", 2)):
+            t = time.perf_counter()
+            W = (vtm.vertex_sca(A, label, iface, sides, 0, alpha) if rule == "sca_depth"
+                 else vtm.vertex_admittance(A, label, iface, sides, rule, alpha))
+            w_ms = (time.perf_counter() - t) * 1e3
             torch.cuda.synchronize()
             t = time.perf_counter()
             s = vtm.Solver(A, label, None, iface=iface, sides=sides, W=W)
@@ -309,7 +312,7 @@ def vertex_tearing(vtm, torch, workloads):
             rel = float(host_relres(A, bh, x.cpu().numpy()).max())
             assert rel <= 1e-8, (name, rule, rel)
             rows.append({"rule": rule, "alpha": alpha, "sweeps": rep.sweeps, "ms": round(ms, 3),
-                         "setup_ms": round(setup_ms, 1), "relres": rel})
+                         "setup_ms": round(setup_ms, 1), "w_host_ms": round(w_ms, 1), "relres": rel})
             log(f"{name} W {rule} x{alpha}: {rep.sweeps} sweeps, {ms:.2f} ms (setup {setup_ms:.0f} ms)")
         out[name] = {"n": n, "interfacial_nodes": int(iface.size), "sub_circuits": int(label.max()) + 1,
                      "rules": rows}

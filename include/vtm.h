@@ -254,6 +254,28 @@ vtm_status vtm_vertex_admittance(const vtm_csr *A, const int32_t *label, const i
                                  int32_t side, int64_t *nnz, int64_t *rowptr, int32_t *col, double *val);
 
 /*
+ * vtm_vertex_sca -- host-only: rule 5 of Section VIII, the Schur complement
+ * approximation W = C - E~ D~^-1 F~ (the partial input admittance of one side),
+ * for vtm_setup_vertex_coupled.  Lines are grouped by the ordered pair of
+ * sub-circuits their twins lie in; per group, C, E~, F~, D~ are blocks of the
+ * torn system (vtm_split_vertex) over the group's twins on `side` (sides[l][0]
+ * for 0, sides[l][1] for 1) and D~ over the inner nodes of that sub-circuit
+ * within `depth` hops of those twins in the torn matrix's graph (depth < 0:
+ * every inner node, the exact Schur complement of Example 3; 0: W = C).  The
+ * result is symmetrized, (S + S^T) / 2, and an off-diagonal entry is dropped
+ * when |w_ij| < drop * sqrt(|w_ii w_jj|) (the paper drops small elements so
+ * that W keeps a pattern like C's; drop = 0 keeps every entry).  D~ is solved
+ * densely on the host (cost ~ m^3 for m chosen nodes per group).
+ *   nnz, rowptr [n_iface + 1], col [nnz], val [nnz]: outputs as for
+ *   vtm_vertex_admittance.
+ * Errors: VTM_E_ARG (bad side, drop < 0), VTM_E_SINGULAR (D~ singular), the
+ * tearing errors of vtm_setup_vertex.
+ */
+vtm_status vtm_vertex_sca(const vtm_csr *A, const int32_t *label, const int32_t *iface, const int32_t *sides,
+                          int64_t n_iface, int32_t side, int32_t depth, double drop, int64_t *nnz,
+                          int64_t *rowptr, int32_t *col, double *val);
+
+/*
  * vtm_solve -- run VTM sweeps (Section VI, eqs. 11 and 14) from zero boundary
  * variables until every column has ||b - A x||_2 / ||b||_2 <= tol, the
  * residual taken on the untorn A in FP64 every opt.check_every sweeps.

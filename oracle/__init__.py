@@ -19,6 +19,7 @@ from .vtm import (  # noqa: F401
     vtm_refine,
     sweep_operator,
     interface_schur,
+    partial_schur,
     reflection,
     spectral_radius,
     relative_residual,

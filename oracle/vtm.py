@@ -409,6 +409,64 @@ def interface_schur(torn: Torn, side: int) -> np.ndarray:
     return C - E @ np.linalg.solve(D, F)
 
 
+def partial_schur(torn: Torn, side: int, depth=None, drop: float = 0.0) -> np.ndarray:
+    """Rule 5 of Section VIII, the Schur complement approximation: for every
+    group of lines whose twins lie in the same two sub-circuits (in the same
+    order), W_group = C - E~ D~^-1 F~ over the twins of one side, where D~ keeps
+    only the inner nodes of that side's sub-circuit within ``depth`` hops of
+    those twins (in the torn matrix's graph; None keeps them all, which gives
+    the exact Schur complement S of Example 3, 0 keeps none, giving C).
+
+    Readings where the paper is silent: the submatrix is chosen by graph
+    distance from the interface; the result is symmetrized, (S~ + S~^T) / 2;
+    "dropping the small elements" sets an off-diagonal entry to zero when
+    |w_ij| < drop * sqrt(|w_ii w_jj|).  Returns a dense [L, L] matrix (zero
+    between lines of different groups)."""
+    P = torn.pa if side == 0 else torn.pb
+    L = P.size
+    N = torn.T.shape[0]
+    T = torn.T.tocsr()
+    G = (abs(T) + abs(T).T).tocsr()                     # adjacency, both directions
+    is_twin = np.zeros(N, dtype=bool)
+    is_twin[torn.pa] = True
+    is_twin[torn.pb] = True
+    W = np.zeros((L, L))
+    key = np.stack([torn.block_of[torn.pa], torn.block_of[torn.pb]], axis=1)
+    _, group = np.unique(key, axis=0, return_inverse=True)
+    for g in np.unique(group):
+        lines = np.nonzero(group == g)[0]
+        Pg = P[lines]
+        blk = torn.block_of[Pg[0]]
+        inner_ok = (torn.block_of == blk) & ~is_twin
+        # breadth-first search from the twins over inner nodes of the sub-circuit
+        chosen = np.zeros(N, dtype=bool)
+        frontier = Pg
+        hop = 0
+        while frontier.size and (depth is None or hop < depth):
+            nb = np.unique(G[frontier].indices)
+            nb = nb[inner_ok[nb] & ~chosen[nb]]
+            chosen[nb] = True
+            frontier = nb
+            hop += 1
+        Dn = np.nonzero(chosen)[0]
+        C = T[Pg][:, Pg].toarray()
+        if Dn.size:
+            E = T[Pg][:, Dn].toarray()
+            F = T[Dn][:, Pg].toarray()
+            D = T[Dn][:, Dn].toarray()
+            S = C - E @ np.linalg.solve(D, F)
+        else:
+            S = C
+        S = 0.5 * (S + S.T)
+        if drop > 0.0:
+            d = np.sqrt(np.abs(np.diag(S)))
+            small = np.abs(S) < drop * np.outer(d, d)
+            np.fill_diagonal(small, False)
+            S[small] = 0.0
+        W[np.ix_(lines, lines)] = S
+    return W
+
+
 def reflection(S: np.ndarray, W) -> np.ndarray:
     """Voltage reflection matrix T = (W - S)(W + S)^-1 (Section VIII)."""
     Wm = np.diag(W) if np.ndim(W) == 1 else np.asarray(W)

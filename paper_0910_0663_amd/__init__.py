@@ -11,12 +11,13 @@ from .binding import (  # noqa: F401
     line_admittance,
     split_vertex,
     vertex_admittance,
+    vertex_sca,
     lib,
     LIB_PATH,
     EXPORTS,
 )
 
-__all__ = ["Solver", "SolveReport", "VTMError", "plan", "line_admittance", "split_vertex", "vertex_admittance", "lib", "LIB_PATH", "EXPORTS", "VTMSolve", "Circuit"]
+__all__ = ["Solver", "SolveReport", "VTMError", "plan", "line_admittance", "split_vertex", "vertex_admittance", "vertex_sca", "lib", "LIB_PATH", "EXPORTS", "VTMSolve", "Circuit"]
 
 
 def __getattr__(name):

@@ -25,7 +25,7 @@ STATUS = ["VTM_OK", "VTM_E_ARG", "VTM_E_UNTEARABLE", "VTM_E_SINGULAR", "VTM_E_DI
 EXPORTS = ["vtm_default_options", "vtm_setup", "vtm_solve", "vtm_solve_adjoint", "vtm_grad",
            "vtm_get_waves", "vtm_set_waves", "vtm_info", "vtm_destroy", "vtm_status_str",
            "vtm_last_error", "vtm_plan", "vtm_line_admittance", "vtm_setup_vertex",
-           "vtm_split_vertex", "vtm_setup_vertex_coupled", "vtm_vertex_admittance"]
+           "vtm_split_vertex", "vtm_setup_vertex_coupled", "vtm_vertex_admittance", "vtm_vertex_sca"]
 
 
 class VTMError(RuntimeError):
@@ -112,6 +112,10 @@ def lib() -> C.CDLL:
                                         C.POINTER(C.c_int32), i64, C.c_int32, C.c_double, C.c_int32,
                                         C.POINTER(i64), C.POINTER(i64), C.POINTER(C.c_int32), dp]
     L.vtm_vertex_admittance.restype = C.c_int
+    L.vtm_vertex_sca.argtypes = [C.POINTER(Csr), C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                 i64, C.c_int32, C.c_int32, C.c_double, C.POINTER(i64), C.POINTER(i64),
+                                 C.POINTER(C.c_int32), dp]
+    L.vtm_vertex_sca.restype = C.c_int
     _lib = L
     return L
 
@@ -185,6 +189,29 @@ def split_vertex(A, label, iface, sides):
     M = sp.csr_matrix((val, col, rowptr), shape=(nt.value, nt.value))
     M.sum_duplicates()
     return M, part
+
+
+def vertex_sca(A, label, iface, sides, side=0, depth=1, drop=0.0):
+    """Schur complement approximation W over the interfacial nodes (rule 5 of
+    Section VIII; vtm_vertex_sca), as a scipy CSR matrix in iface order;
+    depth=None keeps every inner node (the exact Schur complement)."""
+    import scipy.sparse as sp
+    L = lib()
+    hc = _HostCsr(A)
+    i32p = C.POINTER(C.c_int32)
+    label = np.ascontiguousarray(label, dtype=np.int32)
+    iface = np.ascontiguousarray(iface, dtype=np.int32)
+    sides = np.ascontiguousarray(sides, dtype=np.int32).reshape(-1, 2)
+    args = (C.byref(hc.s), label.ctypes.data_as(i32p), iface.ctypes.data_as(i32p), sides.ctypes.data_as(i32p),
+            iface.size, int(side), -1 if depth is None else int(depth), float(drop))
+    nnz = C.c_int64()
+    _check(L.vtm_vertex_sca(*args, C.byref(nnz), None, None, None))
+    rowptr = np.zeros(iface.size + 1, dtype=np.int64)
+    col = np.zeros(nnz.value, dtype=np.int32)
+    val = np.zeros(nnz.value, dtype=np.float64)
+    _check(L.vtm_vertex_sca(*args, None, rowptr.ctypes.data_as(C.POINTER(C.c_int64)), col.ctypes.data_as(i32p),
+                            val.ctypes.data_as(C.POINTER(C.c_double))))
+    return sp.csr_matrix((val, col, rowptr), shape=(iface.size, iface.size))
 
 
 ADMITTANCE_RULES = {"scaled_mean": 0, "identity": 1, "ob": 2, "wob": 3, "diag": 4}

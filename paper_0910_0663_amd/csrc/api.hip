@@ -974,6 +974,32 @@ vtm_status vtm_line_admittance(const vtm_csr* A, const int32_t* part, int32_t ki
     return VTM_OK;
 }
 
+vtm_status vtm_vertex_sca(const vtm_csr* A, const int32_t* label, const int32_t* iface, const int32_t* sides,
+                          int64_t n_iface, int32_t side, int32_t depth, double drop, int64_t* nnz, int64_t* rowptr,
+                          int32_t* col, double* val) {
+    if (side != 0 && side != 1) return fail(VTM_E_ARG, "side must be 0 or 1");
+    if (!(drop >= 0.0) || !std::isfinite(drop)) return fail(VTM_E_ARG, "drop must be finite and non-negative");
+    vtm::VertexSplit X;
+    std::string err;
+    vtm_status st = vtm::split_at_vertices(A, label, iface, sides, n_iface, X, err);
+    if (st != VTM_OK) return fail(st, err);
+    std::vector<std::vector<std::pair<int32_t, double>>> W;
+    st = vtm::partial_schur_vertex(X, iface, sides, side, depth, drop, W, err);
+    if (st != VTM_OK) return fail(st, err);
+    int64_t k = 0;
+    if (rowptr) rowptr[0] = 0;
+    for (int64_t l = 0; l < n_iface; ++l) {
+        for (const auto& e : W[l]) {
+            if (col) col[k] = e.first;
+            if (val) val[k] = e.second;
+            ++k;
+        }
+        if (rowptr) rowptr[l + 1] = k;
+    }
+    if (nnz) *nnz = k;
+    return VTM_OK;
+}
+
 vtm_status vtm_vertex_admittance(const vtm_csr* A, const int32_t* label, const int32_t* iface, const int32_t* sides,
                                  int64_t n_iface, int32_t kind, double alpha, int32_t side, int64_t* nnz,
                                  int64_t* rowptr, int32_t* col, double* val) {

@@ -514,6 +514,116 @@ vtm_status split_at_vertices(const vtm_csr* A, const int32_t* label, const int32
     return VTM_OK;
 }
 
+vtm_status partial_schur_vertex(const VertexSplit& X, const int32_t* iface, const int32_t* sides, int side,
+                                int depth, double drop, std::vector<std::vector<std::pair<int32_t, double>>>& W,
+                                std::string& err) {
+    const int64_t n = X.n, L = X.L, N = n + L;
+    std::vector<char> is_twin(N, 0);
+    for (int64_t l = 0; l < L; ++l) {
+        is_twin[iface[l]] = 1;
+        is_twin[n + l] = 1;
+    }
+    // graph of the torn matrix, both directions
+    std::vector<std::vector<int32_t>> adj(N);
+    for (int64_t r = 0; r < N; ++r)
+        for (int64_t q = X.rowptr[r]; q < X.rowptr[r + 1]; ++q) {
+            const int32_t c = X.col[q];
+            if (c == r) continue;
+            adj[r].push_back(c);
+            adj[c].push_back(int32_t(r));
+        }
+    std::map<std::pair<int32_t, int32_t>, std::vector<int32_t>> groups;
+    for (int64_t l = 0; l < L; ++l) groups[{sides[2 * l], sides[2 * l + 1]}].push_back(int32_t(l));
+    W.assign(L, {});
+    std::vector<int32_t> loc(N, -1);  // index among the group's twins (< k) or chosen inner nodes (>= k)
+    for (const auto& grp : groups) {
+        const std::vector<int32_t>& lines = grp.second;
+        const int32_t blk = side ? grp.first.second : grp.first.first;
+        const int k = int(lines.size());
+        std::vector<int32_t> nodes(k);
+        for (int a = 0; a < k; ++a) {
+            nodes[a] = side ? int32_t(n + lines[a]) : iface[lines[a]];
+            loc[nodes[a]] = a;
+        }
+        // inner nodes of the sub-circuit within depth hops of the twins, breadth first
+        std::vector<int32_t> frontier(nodes), next;
+        for (int hop = 0; !frontier.empty() && (depth < 0 || hop < depth); ++hop) {
+            next.clear();
+            for (int32_t u : frontier)
+                for (int32_t v : adj[u])
+                    if (!is_twin[v] && X.part[v] == blk && loc[v] < 0) {
+                        loc[v] = int32_t(nodes.size());
+                        nodes.push_back(v);
+                        next.push_back(v);
+                    }
+            frontier.swap(next);
+        }
+        const int m = int(nodes.size()) - k;
+        // dense blocks: C (k x k), E (k x m), F (m x k), D (m x m), from the torn rows
+        std::vector<double> C(size_t(k) * k, 0.0), E(size_t(k) * m, 0.0), F(size_t(m) * k, 0.0),
+            D(size_t(m) * m, 0.0);
+        for (int a = 0; a < int(nodes.size()); ++a) {
+            const int32_t r = nodes[a];
+            for (int64_t q = X.rowptr[r]; q < X.rowptr[r + 1]; ++q) {
+                const int b = loc[X.col[q]];
+                if (b < 0) continue;
+                const double v = X.val[q];
+                if (a < k && b < k) C[size_t(a) * k + b] += v;
+                else if (a < k) E[size_t(a) * m + (b - k)] += v;
+                else if (b < k) F[size_t(a - k) * k + b] += v;
+                else D[size_t(a - k) * m + (b - k)] += v;
+            }
+        }
+        // F <- D^-1 F by Gaussian elimination with partial pivoting
+        for (int c = 0; c < m; ++c) {
+            int p = c;
+            for (int r = c + 1; r < m; ++r)
+                if (std::fabs(D[size_t(r) * m + c]) > std::fabs(D[size_t(p) * m + c])) p = r;
+            const double piv = D[size_t(p) * m + c];
+            if (piv == 0.0 || !std::isfinite(piv)) {
+                err = "the inner block of the Schur complement approximation is singular";
+                for (int32_t v : nodes) loc[v] = -1;
+                return VTM_E_SINGULAR;
+            }
+            if (p != c) {
+                for (int j = 0; j < m; ++j) std::swap(D[size_t(p) * m + j], D[size_t(c) * m + j]);
+                for (int j = 0; j < k; ++j) std::swap(F[size_t(p) * k + j], F[size_t(c) * k + j]);
+            }
+            for (int r = c + 1; r < m; ++r) {
+                const double f = D[size_t(r) * m + c] / piv;
+                if (f == 0.0) continue;
+                for (int j = c; j < m; ++j) D[size_t(r) * m + j] -= f * D[size_t(c) * m + j];
+                for (int j = 0; j < k; ++j) F[size_t(r) * k + j] -= f * F[size_t(c) * k + j];
+            }
+        }
+        for (int c = m - 1; c >= 0; --c) {
+            const double piv = D[size_t(c) * m + c];
+            for (int j = 0; j < k; ++j) {
+                double v = F[size_t(c) * k + j];
+                for (int t = c + 1; t < m; ++t) v -= D[size_t(c) * m + t] * F[size_t(t) * k + j];
+                F[size_t(c) * k + j] = v / piv;
+            }
+        }
+        // S = C - E (D^-1 F), symmetrized, small entries dropped
+        for (int a = 0; a < k; ++a)
+            for (int t = 0; t < m; ++t) {
+                const double e = E[size_t(a) * m + t];
+                if (e == 0.0) continue;
+                for (int j = 0; j < k; ++j) C[size_t(a) * k + j] -= e * F[size_t(t) * k + j];
+            }
+        for (int a = 0; a < k; ++a)
+            for (int j = 0; j < k; ++j) {
+                const double v = 0.5 * (C[size_t(a) * k + j] + C[size_t(j) * k + a]);
+                if (a != j && (v == 0.0 || std::fabs(v) < drop * std::sqrt(std::fabs(C[size_t(a) * k + a] *
+                                                                                      C[size_t(j) * k + j]))))
+                    continue;
+                W[lines[a]].push_back({lines[j], v});
+            }
+        for (int32_t v : nodes) loc[v] = -1;
+    }
+    return VTM_OK;
+}
+
 vtm_status build_plan_vertex(const vtm_csr* A, const int32_t* label, const int32_t* iface, const int32_t* sides,
                              int64_t L, const double* W, int64_t nW, Plan& P, std::string& err, const vtm_csr* Wc) {
     if (!Wc && (!W || (nW != 1 && nW != L))) {

@@ -114,6 +114,15 @@ struct VertexSplit {
 vtm_status split_at_vertices(const vtm_csr* A, const int32_t* label, const int32_t* iface,
                              const int32_t* sides, int64_t n_iface, VertexSplit& out, std::string& err);
 
+// Rule 5 of Section VIII on a torn system: per group of lines whose twins lie
+// in the same two sub-circuits (same order), W = C - E~ D~^-1 F~ over the twins
+// of one side, D~ the inner nodes of that side's sub-circuit within `depth`
+// hops of them (depth < 0: all), symmetrized, off-diagonal entries below
+// drop * sqrt(|w_ii w_jj|) dropped.  Rows (lines) of sorted (line, value).
+vtm_status partial_schur_vertex(const VertexSplit& X, const int32_t* iface, const int32_t* sides, int side,
+                                int depth, double drop, std::vector<std::vector<std::pair<int32_t, double>>>& W,
+                                std::string& err);
+
 // Tearing at interfacial nodes (Section V, Steps 1-4, as the paper tears):
 // every node iface[l] is split into two twins, one in each of the sub-circuits
 // sides[2l] and sides[2l + 1], joined by a line of admittance W[l] (nW == 1: one

@@ -297,8 +297,9 @@ def test_table2_two_sub_circuits_on_the_gpu(torch):
     """Table II's Grid2d setting itself: a 100 x 100 unit resistor grid torn into
     two sub-circuits at one separator column of 100 interfacial nodes (5,050
     torn nodes each).  The GPU's sweep counts are the oracle's for the
-    diagonal, overlapped-block and weighted overlapped-block W, and x is the
-    direct solution."""
+    diagonal, overlapped-block, weighted overlapped-block and Schur complement
+    approximation (two layers of the interior) W, and x is the direct
+    solution."""
     dims = (100, 100)
     e = workloads.grid2d_edges(*dims)
     n = int(np.prod(dims))
@@ -307,8 +308,9 @@ def test_table2_two_sub_circuits_on_the_gpu(torch):
     label, iface, sides = workloads.separator_strips(dims, 49)
     assert iface.size == 100 and label.max() == 1
     xs = spla.spsolve(A.tocsc(), b[0])
-    for rule, alpha in (("diag", 1.0), ("ob", 1.0), ("wob", 0.3)):
-        W = vtm().vertex_admittance(A, label, iface, sides, rule, alpha)
+    for rule, alpha in (("diag", 1.0), ("ob", 1.0), ("wob", 0.3), ("sca", 2)):
+        W = (vtm().vertex_sca(A, label, iface, sides, 0, alpha) if rule == "sca"
+             else vtm().vertex_admittance(A, label, iface, sides, rule, alpha))
         r = oracle.vtm_solve(oracle.tear_at_vertices(A, label, iface, sides, W.toarray()), A, b, 1e-8,
                              max_sweeps=5000)
         s = solver(A, label, iface, sides, W, check_every=1, adaptive_checks=False)
@@ -316,3 +318,29 @@ def test_table2_two_sub_circuits_on_the_gpu(torch):
         assert abs(rep.sweeps - r.sweeps) <= 1, (rule, rep.sweeps, r.sweeps)
         assert np.abs(x.cpu().numpy()[0] - xs).max() <= 1e-6 * np.abs(xs).max()
         s.close()
+
+
+@pytest.mark.parametrize("depth,drop,kw", [
+    (2, 0.0, dict()),
+    (3, 0.02, dict(local_form="full")),
+    (1, 0.0, dict(precision="fp32_refine")),
+])
+def test_schur_complement_approximation_iterates(torch, depth, drop, kw):
+    """Rule 5 of Section VIII (vtm_vertex_sca) as coupled lines: iterates equal
+    the oracle's with the oracle's own partial Schur complement as W."""
+    A, b, label, iface, sides, _ = strips((24, 47), 10, seed=3)
+    W = vtm().vertex_sca(A, label, iface, sides, 0, depth, drop)
+    torn = oracle.tear_at_vertices(A, label, iface, sides, 1.0)
+    Wo = oracle.partial_schur(torn, 0, depth, drop)
+    assert np.abs(W.toarray() - Wo).max() <= 1e-13 * np.abs(Wo).max()
+    if kw.get("precision") == "fp32_refine":
+        r = oracle.vtm_solve(oracle.tear_at_vertices(A, label, iface, sides, Wo), A, b, 1e-10, max_sweeps=5000)
+        s = solver(A, label, iface, sides, W, check_every=8, **kw)
+        x, rep = s.solve(to_dev(torch, b), 1e-10)
+        assert r.status == "ok" and rep.relres_max <= 1e-10
+        return
+    ks = [1, 2, 6]
+    ref = oracle_iterates(A, b, label, iface, sides, Wo, ks)
+    for k in ks:
+        assert_close(gpu_iterate(torch, A, b, label, iface, sides, W, k, **kw), ref[k])
+    assert_close(gpu_iterate(torch, A, b, label, iface, sides, W, 6, check_every=6, **kw), ref[6])

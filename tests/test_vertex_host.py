@@ -159,3 +159,89 @@ def test_table2_ordering_of_preconditioners_on_a_grid2d_like_circuit():
         sweeps[rule] = r.sweeps
     assert sweeps["diag"] > sweeps["ob"] > sweeps["wob"]
     assert 1.5 <= sweeps["diag"] / sweeps["ob"] <= 2.5
+
+
+# ----------------------------------------------------------- Schur complement approximation
+def test_partial_schur_reduces_to_its_special_cases():
+    """Rule 5 of Section VIII in the oracle: with every inner node kept it is
+    the exact Schur complement of Example 3 (computed by interface_schur over
+    the whole side), with none it is the interface block C, and a matched line
+    W = S_1 makes T_1 = 0, so two sweeps of the sweep operator vanish and VTM
+    converges in a few sweeps (Section VIII: one reflection)."""
+    dims = (12, 25)
+    A = unit_grid(dims)
+    label, iface, sides = workloads.separator_strips(dims, 12)
+    assert label.max() == 1
+    torn = oracle.tear_at_vertices(A, label, iface, sides, 1.0)
+    for side in (0, 1):
+        S = oracle.interface_schur(torn, side)
+        assert np.allclose(oracle.partial_schur(torn, side, None), 0.5 * (S + S.T), rtol=1e-12, atol=1e-14)
+        P = torn.pa if side == 0 else torn.pb
+        C = torn.T.tocsr()[P][:, P].toarray()
+        assert np.array_equal(oracle.partial_schur(torn, side, 0), 0.5 * (C + C.T))
+    W = oracle.partial_schur(torn, 0, None)
+    matched = oracle.tear_at_vertices(A, label, iface, sides, W)
+    M = oracle.sweep_operator(matched)
+    assert np.abs(M @ M).max() < 1e-9 * np.abs(M).max()
+    b = np.random.default_rng(2).standard_normal((1, A.shape[0]))
+    r = oracle.vtm_solve(matched, A, b, 1e-10, max_sweeps=50)
+    assert r.status == "ok" and r.sweeps <= 3
+
+
+def test_partial_schur_drops_small_entries():
+    dims = (10, 21)
+    A = unit_grid(dims)
+    label, iface, sides = workloads.separator_strips(dims, 10)
+    torn = oracle.tear_at_vertices(A, label, iface, sides, 1.0)
+    full = oracle.partial_schur(torn, 0, 3)
+    kept = oracle.partial_schur(torn, 0, 3, drop=0.05)
+    d = np.sqrt(np.diag(full))
+    big = np.abs(full) >= 0.05 * np.outer(d, d)
+    np.fill_diagonal(big, True)
+    assert np.array_equal(kept, np.where(big, full, 0.0))
+    assert 0 < np.count_nonzero(kept) < np.count_nonzero(full)
+
+
+def test_table2_sca_beats_the_overlapped_block():
+    """Table II, Grid2d column: the Schur complement approximation needs fewer
+    sweeps than the overlapped block (275 vs 491), and more of the interior in
+    D~ means fewer sweeps still (the exact complement needs a few)."""
+    dims = (100, 100)
+    A = unit_grid(dims)
+    b = np.random.default_rng(0).standard_normal((1, A.shape[0]))
+    label, iface, sides = workloads.separator_strips(dims, 49)
+    torn = oracle.tear_at_vertices(A, label, iface, sides, 1.0)
+    sweeps = []
+    for depth in (0, 1, 2, 4):
+        W = oracle.partial_schur(torn, 0, depth)
+        r = oracle.vtm_solve(oracle.tear_at_vertices(A, label, iface, sides, W), A, b, 1e-8, max_sweeps=5000)
+        assert r.status == "ok"
+        sweeps.append(r.sweeps)
+    assert sweeps == sorted(sweeps, reverse=True) and len(set(sweeps)) == 4
+
+
+@pytest.mark.parametrize("dims,width,side,depth,drop", [
+    ((14, 23), 5, 0, 1, 0.0),
+    ((14, 23), 5, 1, 2, 0.0),
+    ((14, 23), 5, 0, 3, 0.02),
+    ((14, 23), 5, 1, None, 0.0),
+    ((12, 12, 11), 5, 0, 2, 0.0),
+    ((12, 12, 11), 5, 1, 3, 0.02),
+])
+def test_vertex_sca_equals_the_oracle(dims, width, side, depth, drop):
+    """vtm_vertex_sca against the oracle's partial_schur: same entries (to
+    rounding of the dense solves) and the same pattern after dropping."""
+    if len(dims) == 2:
+        A = workloads.make(4, dims=dims).A
+    else:
+        e = workloads.grid3d_edges(*dims)
+        n = int(np.prod(dims))
+        A = workloads.nodal_matrix(n, e, np.random.default_rng(1).uniform(0.5, 2, e.shape[0]), np.full(n, 0.01))
+    label, iface, sides = workloads.separator_strips(dims, width)
+    torn = oracle.tear_at_vertices(A, label, iface, sides, 1.0)
+    Wo = oracle.partial_schur(torn, side, depth, drop)
+    Wl = binding.vertex_sca(A, label, iface, sides, side, depth, drop).toarray()
+    assert np.array_equal(Wo != 0, Wl != 0)
+    assert np.abs(Wo - Wl).max() <= 1e-13 * np.abs(Wo).max()
+    with pytest.raises(binding.VTMError):
+        binding.vertex_sca(A, label, iface, sides, side, depth, -1.0)

@@ -203,7 +203,10 @@ vtm_status vtm_setup(const vtm_csr *A, const int32_t *part, const double *Z, int
  * an interfacial node is the mean of its twins (equal at the fixed point), and
  * the stop rule is the residual on the caller's A.  Interim checks always use
  * that residual (the port identity of the wire-cut form does not apply).
- * vtm_solve_adjoint gives VTM_E_UNSUPPORTED; vtm_get_waves / vtm_set_waves
+ * vtm_solve_adjoint solves A^T lambda = g with the same tear: the split rule
+ * treats A_vw and A_wv alike, so the torn A^T is the transposed torn A and the
+ * stored inverses are read transposed (residual on the caller's A^T);
+ * vtm_get_waves / vtm_set_waves
  * address ports 2l (twin in sides[l][0]) and 2l+1; vtm_info reports the torn
  * system's size.
  */

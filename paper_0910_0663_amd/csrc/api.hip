@@ -93,8 +93,8 @@ struct vtm_handle_s {
     DevBuf<int32_t> pn_off, pn_node, pn_pfirst;
     // tearing at interfacial nodes: maps between plan rows and the caller's nodes, the
     // caller's A, and right-hand side / residual / solution in the caller's node order
-    DevBuf<int32_t> vx_src, vr0, vr1, orow, ocol, oid;
-    DevBuf<double> vx_w, oval, bo, ro, xo;
+    DevBuf<int32_t> vx_src, vr0, vr1, orow, ocol, oid, orowT, ocolT;
+    DevBuf<double> vx_w, oval, ovalT, bo, ro, xo;
     const double* b_user = nullptr;
     // coupled lines: B = 2 W over the ports (CSR) and each port's plan row
     DevBuf<int32_t> brow, bcol, port_row;
@@ -175,9 +175,11 @@ vtm_status residual_launch(vtm_handle h, const double* b, const TX* x, int nrhs,
         // of its twins; b is the solve's right-hand side, or the outer residual for an inner check
         const int no = int(P.n_orig);
         const double* bo = b == h->bp.p ? h->bo.p : h->ro.p;
+        const bool oT = transpose && !P.osymmetric;  // the adjoint's residual is on A^T
         VTM_HIP(vtm::launch_restrict<TX>(no, nrhs, h->vr0.p, h->vr1.p, x, h->xo.p, false, h->stream));
-        VTM_HIP(vtm::launch_residual<double>(no, nrhs, h->orow.p, h->ocol.p, h->oval.p, bo, h->xo.p,
-                                             r_out ? h->ro.p : nullptr, h->partial.p, h->norms.p, h->stream));
+        VTM_HIP(vtm::launch_residual<double>(no, nrhs, oT ? h->orowT.p : h->orow.p, oT ? h->ocolT.p : h->ocol.p,
+                                             oT ? h->ovalT.p : h->oval.p, bo, h->xo.p, r_out ? h->ro.p : nullptr,
+                                             h->partial.p, h->norms.p, h->stream));
         if (r_out)
             VTM_HIP(vtm::launch_expand(int(P.n), nrhs, no, h->vx_src.p, h->vx_w.p, h->ro.p, false, r_out, h->stream));
         VTM_HIP(hipMemcpyAsync(h->h_norms, h->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost,
@@ -804,7 +806,6 @@ vtm_status solve_common(vtm_handle h, const double* b, double* x, int32_t nrhs, 
     VTM_HIP(hipSetDevice(h->device));
     const vtm::Plan& P = h->plan;
     if (P.vertex) {
-        if (adjoint) return fail(VTM_E_UNSUPPORTED, "tearing at interfacial nodes has no adjoint form here");
         // interfacial sources split between the twins; b also kept in node order for the residual
         VTM_HIP(vtm::launch_expand(int(P.n), nrhs, int(P.n_orig), h->vx_src.p, h->vx_w.p, b, true, h->bp.p,
                                    h->stream));
@@ -1111,6 +1112,11 @@ static vtm_status setup_vertex_common(const vtm_csr* A, const int32_t* label, co
     VTM_HIP(h->ocol.upload(P.ocol, s));
     VTM_HIP(h->oval.upload(P.oval, s));
     VTM_HIP(h->oid.upload(id, s));
+    if (!P.osymmetric) {
+        VTM_HIP(h->orowT.upload(P.orowT, s));
+        VTM_HIP(h->ocolT.upload(P.ocolT, s));
+        VTM_HIP(h->ovalT.upload(P.ovalT, s));
+    }
     VTM_HIP(h->bo.alloc(no));
     VTM_HIP(h->ro.alloc(no));
     VTM_HIP(h->xo.alloc(no));

@@ -758,6 +758,25 @@ vtm_status build_plan_vertex(const vtm_csr* A, const int32_t* label, const int32
     P.orow = std::move(X.orow);
     P.ocol = std::move(X.ocol);
     P.oval = std::move(X.oval);
+    // the caller's A^T, sorted like A (rows ascending give sorted columns)
+    P.orowT.assign(n + 1, 0);
+    for (int32_t c : P.ocol) P.orowT[c + 1]++;
+    for (int64_t i = 0; i < n; ++i) P.orowT[i + 1] += P.orowT[i];
+    P.ocolT.resize(P.ocol.size());
+    P.ovalT.resize(P.oval.size());
+    std::vector<int32_t> fill(P.orowT.begin(), P.orowT.end() - 1);
+    for (int64_t r = 0; r < n; ++r)
+        for (int32_t k = P.orow[r]; k < P.orow[r + 1]; ++k) {
+            const int32_t w = fill[P.ocol[k]]++;
+            P.ocolT[w] = int32_t(r);
+            P.ovalT[w] = P.oval[k];
+        }
+    P.osymmetric = P.orowT == P.orow && P.ocolT == P.ocol && P.ovalT == P.oval;
+    if (P.osymmetric) {
+        P.orowT.clear();
+        P.ocolT.clear();
+        P.ovalT.clear();
+    }
     return VTM_OK;
 }
 

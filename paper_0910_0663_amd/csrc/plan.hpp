@@ -73,6 +73,9 @@ struct Plan {
     std::vector<int32_t> vr0, vr1; // per original node: its plan row(s); vr1 = -1 unless a twin pair
     std::vector<int32_t> orow, ocol;  // the caller's A, duplicates merged (residual on the untorn system)
     std::vector<double> oval;
+    bool osymmetric = true;            // the caller's A is symmetric; else its transpose follows
+    std::vector<int32_t> orowT, ocolT; // (for the adjoint's residual)
+    std::vector<double> ovalT;
 
     // Coupled lines (a non-diagonal W over the interfacial nodes, eqs. 4-5): W is
     // part of the torn matrix (added between the twins of each side), so the

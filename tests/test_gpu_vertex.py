@@ -120,9 +120,12 @@ def test_opamp_example_converges_with_papers_W(torch, opamp, form):
     assert np.allclose(x.cpu().numpy(), xs, rtol=1e-10, atol=1e-12)
     ref = oracle.vtm_solve(oracle.tear_at_vertices(A, label, iface, sides, W), A, b, 1e-12, max_sweeps=100)
     assert ref.status == "ok" and abs(rep.sweeps - ref.sweeps) <= 1
-    with pytest.raises(vtm().VTMError) as ei:
-        s.solve_adjoint(to_dev(torch, b), 1e-12)
-    assert ei.value.name == "VTM_E_UNSUPPORTED"
+    # the adjoint: the same tear of A^T (the oracle tears A^T itself)
+    At = A.T.tocsr()
+    lam, rep = s.solve_adjoint(to_dev(torch, b), 1e-12)
+    assert np.allclose(lam.cpu().numpy(), np.linalg.solve(At.toarray(), b.T).T, rtol=1e-10, atol=1e-12)
+    ref = oracle.vtm_solve(oracle.tear_at_vertices(At, label, iface, sides, W), At, b, 1e-12, max_sweeps=100)
+    assert ref.status == "ok" and abs(rep.sweeps - ref.sweeps) <= 1
 
 
 def test_opamp_example_diverges_with_poor_W(torch, opamp):
@@ -344,3 +347,30 @@ def test_schur_complement_approximation_iterates(torch, depth, drop, kw):
     for k in ks:
         assert_close(gpu_iterate(torch, A, b, label, iface, sides, W, k, **kw), ref[k])
     assert_close(gpu_iterate(torch, A, b, label, iface, sides, W, 6, check_every=6, **kw), ref[6])
+
+
+@pytest.mark.parametrize("case", ["symmetric", "controlled_sources", "coupled"])
+def test_adjoint_iterates_match_oracle_tear_of_the_transpose(torch, case):
+    """vtm_solve_adjoint with tearing at interfacial nodes: x^k of VTM on the
+    oracle's tear of A^T (which the split rule makes the transposed tear of A),
+    and the adjoint solution at the end."""
+    if case == "controlled_sources":
+        A, b, label, iface, sides, W = strips((6, 10, 23), 5, vccs=True)
+    elif case == "coupled":
+        A, b, label, iface, sides, W = coupled((24, 47), 10, "wob", 0.5, seed=5)
+    else:
+        A, b, label, iface, sides, W = strips((24, 47), 10, seed=5)
+    At = A.T.tocsr()
+    ref = oracle_iterates(At, b, label, iface, sides, W, [1, 4])
+    for k, ce in ((1, 1), (4, 1), (4, 4)):
+        s = solver(A, label, iface, sides, W, check_every=ce, max_sweeps=k, adaptive_checks=False)
+        lam = torch.empty(b.shape, dtype=torch.float64, device="cuda")
+        with pytest.raises(vtm().VTMError) as ei:
+            s.solve_adjoint(to_dev(torch, b), 1e-300, lam)
+        assert ei.value.name == "VTM_E_MAXITER" and ei.value.report.sweeps == k
+        assert_close(lam.cpu().numpy(), ref[k])
+    s = solver(A, label, iface, sides, W, check_every=8)
+    lam, rep = s.solve_adjoint(to_dev(torch, b), 1e-10)
+    ls = spla.spsolve(At.tocsc(), b[0])
+    assert rep.relres_max <= 1e-10
+    assert np.abs(lam.cpu().numpy()[0] - ls).max() <= 1e-7 * np.abs(ls).max()

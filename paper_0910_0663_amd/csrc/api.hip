@@ -354,12 +354,12 @@ vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
             VTM_HIP((vtm::launch_sweep_pps<double, double>(int(P.S), P.max_npn, P.max_ports, h->S64.p, h->sofs.p, h->pn_off.p,
                                                            h->pn_pfirst.p, h->port_off.p, h->port_twin.p, h->c64.p,
                                                            h->W64p.p, W, h->h64.p, h->a64[cur].p, h->a64[cur ^ 1].p,
-                                                           h->stream)));
+                                                           cur, h->stream)));
         else
             VTM_HIP((vtm::launch_sweep_pps<float, float>(int(P.S), P.max_npn, P.max_ports, h->S32.p, h->sofs.p, h->pn_off.p,
                                                          h->pn_pfirst.p, h->port_off.p, h->port_twin.p, h->c32.p,
                                                          h->W32p.p, float(W), h->h32.p, h->a32[cur].p,
-                                                         h->a32[cur ^ 1].p, h->stream)));
+                                                         h->a32[cur ^ 1].p, cur, h->stream)));
     } else if (pp) {
         const vtm::Plan& P = h->plan;
         if (!low)

@@ -152,12 +152,14 @@ hipError_t launch_port_node_matrix(int S, const int32_t* sub_off, const int64_t*
 // a_next[twin(p)] = 2 W_p c_p z_n(p) + (1 - 2 c_p) a_p + h_p (pW null: W for
 // every port).  Needs at most 64 port nodes and 64 ports per sub-circuit (else
 // hipErrorInvalidValue); two sub-circuits share a wavefront when both maxima
-// are at most 32.
+// are at most 32.  reverse != 0 walks the sub-circuits in reverse order (the
+// solver alternates it, so each sweep starts on the operators the previous one
+// read last); results do not depend on it.
 template <typename TO, typename TV>
 hipError_t launch_sweep_pps(int S, int max_npn, int max_ports, const TO* Sp, const int64_t* sofs,
                             const int32_t* pn_off, const int32_t* pn_pfirst, const int32_t* port_off,
                             const int32_t* port_twin, const TV* pc, const TV* pW, TV W, const TV* h,
-                            const TV* a_cur, TV* a_next, hipStream_t st);
+                            const TV* a_cur, TV* a_next, int reverse, hipStream_t st);
 
 // ---- residual -------------------------------------------------------------
 // Per right-hand side, the sum of squares of b - A x for the iterate of the

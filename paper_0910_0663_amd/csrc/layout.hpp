@@ -59,6 +59,15 @@ __device__ inline int xcd_block(int b, int n) {
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// The same ranges, each walked backwards: every XCD keeps its logical blocks
+// (and what its L2 holds of them), in the opposite order.
+__device__ inline int xcd_block_reversed(int b, int n) {
+    if (!VTM_XCD) return n - 1 - b;
+    const int x = b & 7, q = n >> 3, r = n & 7;
+    const int count = q + (x < r ? 1 : 0);  // blocks of XCD x
+    return x * q + (x < r ? x : r) + (count - 1 - (b >> 3));
+}
+
 // elements reserved for an n x n block (rounded up to a multiple of 4)
 __host__ __device__ inline int64_t inv_block_elems(int n) { return (int64_t(n) * n + 3) & ~int64_t(3); }
 

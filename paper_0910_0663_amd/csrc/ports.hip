@@ -387,6 +387,10 @@ template hipError_t launch_sweep_pp<float, float>(int, int, const float*, const 
 #ifndef VTM_PPS_PRE
 #define VTM_PPS_PRE 1
 #endif
+// walk the units in reverse order on every other sweep
+#ifndef VTM_PPS_ALTERNATE
+#define VTM_PPS_ALTERNATE 1
+#endif
 
 namespace vtm {
 namespace {
@@ -524,11 +528,16 @@ __global__ void __launch_bounds__(64)
                 const int32_t* __restrict__ pn_off, const int32_t* __restrict__ pn_pfirst,
                 const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_twin,
                 const TV* __restrict__ pc, const TV* __restrict__ pW, TV W, const TV* __restrict__ h,
-                const TV* __restrict__ a_cur, TV* __restrict__ a_next) {
+                const TV* __restrict__ a_cur, TV* __restrict__ a_next, int reverse) {
     __shared__ TV ca[64], tv[128], zv[64];
     __shared__ int32_t pnode[64];
-    pps_unit<TO, TV, HALF>(xcd_block(blockIdx.x, gridDim.x), S, Sp, sofs, pn_off, pn_pfirst, port_off, port_twin,
-                           pc, pW, W, h, a_cur, a_next, ca, tv, zv, pnode);
+    // every other sweep walks each XCD's units backwards, so that the operators it
+    // reads first are the ones the previous sweep read last (still in the
+    // memory-side cache), while each XCD keeps the same units (and its L2)
+    const int unit = VTM_PPS_ALTERNATE && reverse ? xcd_block_reversed(blockIdx.x, gridDim.x)
+                                                  : xcd_block(blockIdx.x, gridDim.x);
+    pps_unit<TO, TV, HALF>(unit, S, Sp, sofs, pn_off, pn_pfirst, port_off, port_twin, pc, pW, W, h, a_cur, a_next,
+                           ca, tv, zv, pnode);
 }
 
 }  // namespace
@@ -545,10 +554,10 @@ hipError_t launch_port_node_matrix(int S, const int32_t* sub_off, const int64_t*
 template <typename TO, typename TV, bool HALF>
 hipError_t launch_pps(int S, const TO* Sp, const int64_t* sofs, const int32_t* pn_off, const int32_t* pn_pfirst,
                       const int32_t* port_off, const int32_t* port_twin, const TV* pc, const TV* pW, TV W,
-                      const TV* h, const TV* a_cur, TV* a_next, hipStream_t st) {
+                      const TV* h, const TV* a_cur, TV* a_next, int reverse, hipStream_t st) {
     const int units = HALF ? (S + 1) / 2 : S;
     hipLaunchKernelGGL((k_sweep_pps<TO, TV, HALF>), dim3(units), dim3(64), 0, st, S, Sp, sofs, pn_off, pn_pfirst,
-                       port_off, port_twin, pc, pW, W, h, a_cur, a_next);
+                       port_off, port_twin, pc, pW, W, h, a_cur, a_next, reverse);
     return hipGetLastError();
 }
 
@@ -556,14 +565,14 @@ template <typename TO, typename TV>
 hipError_t launch_sweep_pps(int S, int max_npn, int max_ports, const TO* Sp, const int64_t* sofs,
                             const int32_t* pn_off, const int32_t* pn_pfirst, const int32_t* port_off,
                             const int32_t* port_twin, const TV* pc, const TV* pW, TV W, const TV* h,
-                            const TV* a_cur, TV* a_next, hipStream_t st) {
+                            const TV* a_cur, TV* a_next, int reverse, hipStream_t st) {
     if (max_npn > 64 || max_ports > 64) return hipErrorInvalidValue;
     if (S == 0) return hipSuccess;
     if (max_npn <= 32 && max_ports <= 32)
         return launch_pps<TO, TV, true>(S, Sp, sofs, pn_off, pn_pfirst, port_off, port_twin, pc, pW, W, h, a_cur,
-                                        a_next, st);
+                                        a_next, reverse, st);
     return launch_pps<TO, TV, false>(S, Sp, sofs, pn_off, pn_pfirst, port_off, port_twin, pc, pW, W, h, a_cur,
-                                     a_next, st);
+                                     a_next, reverse, st);
 }
 
 template hipError_t launch_port_node_matrix<double>(int, const int32_t*, const int64_t*, const int32_t*,
@@ -575,10 +584,10 @@ template hipError_t launch_port_node_matrix<float>(int, const int32_t*, const in
 template hipError_t launch_sweep_pps<double, double>(int, int, int, const double*, const int64_t*,
                                                      const int32_t*, const int32_t*, const int32_t*, const int32_t*,
                                                      const double*, const double*, double, const double*,
-                                                     const double*, double*, hipStream_t);
+                                                     const double*, double*, int, hipStream_t);
 template hipError_t launch_sweep_pps<float, float>(int, int, int, const float*, const int64_t*, const int32_t*,
                                                    const int32_t*, const int32_t*, const int32_t*, const float*,
-                                                   const float*, float, const float*, const float*, float*,
+                                                   const float*, float, const float*, const float*, float*, int,
                                                    hipStream_t);
 
 }  // namespace vtm

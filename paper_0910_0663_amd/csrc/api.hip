@@ -327,12 +327,12 @@ vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
             VTM_HIP(vtm::launch_sweep_mfma_pp<double>(int(P.S), P.max_ports, nrhs, h->pp_variant, h->pp_rc,
                                                       h->lds_limit, h->M64t.p, h->qmofs.p, h->port_off.p,
                                                       h->port_twin.p, h->h64.p, h->a64[cur].p, h->a64[cur ^ 1].p,
-                                                      h->stream));
+                                                      cur, h->stream));
         else
             VTM_HIP(vtm::launch_sweep_mfma_pp<__bf16>(int(P.S), P.max_ports, nrhs, h->pp_variant, h->pp_rc,
                                                       h->lds_limit, h->Mbt.p, h->qmofs.p, h->port_off.p,
                                                       h->port_twin.p, h->h32.p, h->a32[cur].p, h->a32[cur ^ 1].p,
-                                                      h->stream));
+                                                      cur, h->stream));
     } else if (pp && h->ppn) {
         const vtm::Plan& P = h->plan;
         if (!low)

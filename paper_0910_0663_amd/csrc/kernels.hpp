@@ -92,7 +92,7 @@ hipError_t launch_sweep_mfma_pp(int S, int max_ports, int nrhs, int variant, int
                                 const T* Mop, const int64_t* qmofs, const int32_t* port_off,
                                 const int32_t* port_twin, const typename MfmaTypes<T>::TV* h,
                                 const typename MfmaTypes<T>::TV* a_cur, typename MfmaTypes<T>::TV* a_next,
-                                hipStream_t st);
+                                int reverse, hipStream_t st);
 // M_s = diag(beta) Kinv[P, P] diag(c) + diag(gamma) in A-tile order from the FP64
 // column-major inverses at Kinv + kofs[s] (coefficients FP64, rounded to T once).
 template <typename T>

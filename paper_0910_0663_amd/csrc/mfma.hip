@@ -17,6 +17,11 @@
 #include "kernels.hpp"
 #include "tiles.hpp"
 
+// walk the sub-circuits in reverse order on every other port-to-port sweep
+#ifndef VTM_MFMA_ALTERNATE
+#define VTM_MFMA_ALTERNATE 1
+#endif
+
 namespace vtm {
 
 namespace {
@@ -261,12 +266,14 @@ __global__ void __launch_bounds__(WAVES * 64)
     k_sweep_mfma_pp(const T* __restrict__ Mop, const int64_t* __restrict__ qmofs,
                     const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_twin,
                     const typename Mma<T>::TV* __restrict__ h, const typename Mma<T>::TV* __restrict__ a_cur,
-                    typename Mma<T>::TV* __restrict__ a_next, int nrhs, int rc) {
+                    typename Mma<T>::TV* __restrict__ a_next, int nrhs, int rc, int reverse) {
     using M = Mma<T>;
     using TV = typename M::TV;
     extern __shared__ char smem[];
     T* sb = reinterpret_cast<T*>(smem);
-    const int s = blockIdx.y;
+    // every other sweep takes the sub-circuits in reverse order (what the previous
+    // sweep read last is still in the memory-side cache)
+    const int s = VTM_MFMA_ALTERNATE && reverse ? int(gridDim.y) - 1 - int(blockIdx.y) : int(blockIdx.y);
     const int r0 = blockIdx.x * rc;
     const int w = min(rc, nrhs - r0);
     const int p0 = port_off[s], q = port_off[s + 1] - p0;
@@ -324,7 +331,7 @@ __global__ void __launch_bounds__(kBlock)
 template <typename T, int NT, int RT, int WAVES>
 hipError_t launch_pp_t(int S, int nrhs, int rc, size_t lds, const T* Mop, const int64_t* qmofs,
                        const int32_t* port_off, const int32_t* port_twin, const typename Mma<T>::TV* h,
-                       const typename Mma<T>::TV* a_cur, typename Mma<T>::TV* a_next, hipStream_t st) {
+                       const typename Mma<T>::TV* a_cur, typename Mma<T>::TV* a_next, int reverse, hipStream_t st) {
     auto kern = k_sweep_mfma_pp<T, NT, RT, WAVES>;
     static size_t lds_set = 65536;
     if (lds > lds_set) {
@@ -335,7 +342,7 @@ hipError_t launch_pp_t(int S, int nrhs, int rc, size_t lds, const T* Mop, const 
     }
     const unsigned ny = unsigned((nrhs + rc - 1) / rc);
     hipLaunchKernelGGL(kern, dim3(ny, S), dim3(WAVES * 64), lds, st, Mop, qmofs, port_off, port_twin, h, a_cur,
-                       a_next, nrhs, rc);
+                       a_next, nrhs, rc, reverse);
     return hipGetLastError();
 }
 
@@ -402,7 +409,7 @@ hipError_t launch_sweep_mfma_pp(int S, int max_ports, int nrhs, int variant, int
                                 const T* Mop, const int64_t* qmofs, const int32_t* port_off,
                                 const int32_t* port_twin, const typename MfmaTypes<T>::TV* h,
                                 const typename MfmaTypes<T>::TV* a_cur, typename MfmaTypes<T>::TV* a_next,
-                                hipStream_t st) {
+                                int reverse, hipStream_t st) {
     const int qp = tile_pad(max_ports);
     int rc = rc_req > 0 ? ((rc_req + 15) / 16) * 16 : 64;
     if (rc > 64) rc = 64;
@@ -417,13 +424,13 @@ hipError_t launch_sweep_mfma_pp(int S, int max_ports, int nrhs, int variant, int
     if (nt == NTV) {                                                                                             \
         if (wide)                                                                                                \
             return deep ? launch_pp_t<T, NTV, 5, 8>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,   \
-                                                    a_next, st)                                                  \
+                                                    a_next, reverse, st)                                         \
                         : launch_pp_t<T, NTV, 3, 8>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,   \
-                                                    a_next, st);                                                 \
+                                                    a_next, reverse, st);                                        \
         return deep ? launch_pp_t<T, NTV, 5, 4>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,       \
-                                                a_next, st)                                                      \
+                                                a_next, reverse, st)                                             \
                     : launch_pp_t<T, NTV, 3, 4>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,       \
-                                                a_next, st);                                                     \
+                                                a_next, reverse, st);                                            \
     }
     VTM_MFMA_PP_CASE(1)
     VTM_MFMA_PP_CASE(2)
@@ -445,10 +452,10 @@ hipError_t launch_port_matrix_tiles(int S, const int32_t* sub_off, const int64_t
 
 template hipError_t launch_sweep_mfma_pp<__bf16>(int, int, int, int, int, size_t, const __bf16*, const int64_t*,
                                                 const int32_t*, const int32_t*, const float*, const float*, float*,
-                                                hipStream_t);
+                                                int, hipStream_t);
 template hipError_t launch_sweep_mfma_pp<double>(int, int, int, int, int, size_t, const double*, const int64_t*,
                                                 const int32_t*, const int32_t*, const double*, const double*,
-                                                double*, hipStream_t);
+                                                double*, int, hipStream_t);
 template hipError_t launch_port_matrix_tiles<__bf16>(int, const int32_t*, const int64_t*, const int32_t*,
                                                     const int32_t*, const double*, const double*, const double*,
                                                     const double*, const int64_t*, __bf16*, hipStream_t,

@@ -205,10 +205,9 @@ vtm_status vtm_setup(const vtm_csr *A, const int32_t *part, const double *Z, int
  * that residual (the port identity of the wire-cut form does not apply).
  * vtm_solve_adjoint solves A^T lambda = g with the same tear: the split rule
  * treats A_vw and A_wv alike, so the torn A^T is the transposed torn A and the
- * stored inverses are read transposed (residual on the caller's A^T);
- * vtm_get_waves / vtm_set_waves
- * address ports 2l (twin in sides[l][0]) and 2l+1; vtm_info reports the torn
- * system's size.
+ * stored inverses are read transposed (residual on the caller's A^T).
+ * vtm_get_waves / vtm_set_waves address ports 2l (twin in sides[l][0]) and
+ * 2l+1; vtm_info reports the torn system's size.
  */
 vtm_status vtm_setup_vertex(const vtm_csr *A, const int32_t *label, const int32_t *iface,
                             const int32_t *sides, int64_t n_iface, const double *W, int64_t nW,

@@ -328,6 +328,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision / batched comparison")
+    ap.add_argument("--mfma-counters", action="store_true",
+                    help="for MFMA counters: one BF16 and one FP64 batched solve of the 64-RHS workload")
     ap.add_argument("--vertex-only", action="store_true",
                     help="for profiling: only the tearing at interfacial nodes; prints its JSON")
     ap.add_argument("--batched-only", action="store_true",
@@ -346,6 +348,21 @@ def main():
     import paper_0910_0663_amd as vtm
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.mfma_counters:
+        # the 64-RHS workload once in BF16 refinement and once in FP64 batched form (MFMA tiles)
+        w4 = workloads.make(4)
+        b4 = torch.as_tensor(w4.b, dtype=torch.float64, device="cuda")
+        out = {}
+        for prec in ("bf16_refine", "fp64"):
+            s4 = vtm.Solver(w4.A, w4.part, w4.Z, precision=prec, nrhs_max=64)
+            x4, rep4 = s4.solve(b4, w4.tol)
+            torch.cuda.synchronize()
+            out[prec] = {"sweeps": rep4.sweeps, "outer": rep4.outer, "solve_ms": round(rep4.solve_ms, 2),
+                         "batch_shape": list(rep4.batch_shape), "port_operator_bytes": s4.port_operator_bytes,
+                         "relres": float(host_relres(w4.A, w4.b, x4.cpu().numpy()).max())}
+            s4.close()
+        print(json.dumps(out), flush=True)
+        return
     if args.vertex_only:
         print(json.dumps(vertex_tearing(vtm, torch, workloads)), flush=True)
         return

@@ -283,6 +283,7 @@ def vertex_tearing(vtm, torch, workloads):
     for name, dims, width in (("grid2d_100x100_one_separator", (100, 100), 49),
                               ("grid2d_100x100_strips_of_18", (100, 100), 18),
                               ("grid3d_20x20x20_one_separator", (20, 20, 20), 9),
+                              ("grid3d_30x30x30_one_separator", (30, 30, 30), 14),
                               ("grid3d_20x20x40_slabs_of_2", (20, 20, 40), 2)):
         e = workloads.grid2d_edges(*dims) if len(dims) == 2 else workloads.grid3d_edges(*dims)
         n = int(np.prod(dims))
@@ -292,7 +293,8 @@ def vertex_tearing(vtm, torch, workloads):
         x = torch.empty_like(b)
         label, iface, sides = workloads.separator_strips(dims, width)
         rows = []
-        for rule, alpha in (("identity", 1.0), ("diag", 1.0), ("ob", 1.0), ("wob", 0.3), ("sca_depth", 2)):
+        for rule, alpha in (("identity", 1.0), ("diag", 1.0), ("ob", 1.0), ("wob", 0.3),
+                            ("sca_depth", 1 if iface.size > 500 and label.max() == 1 else 2)):
             t = time.perf_counter()
             W = (vtm.vertex_sca(A, label, iface, sides, 0, alpha) if rule == "sca_depth"
                  else vtm.vertex_admittance(A, label, iface, sides, rule, alpha))

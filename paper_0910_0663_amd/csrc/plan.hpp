@@ -88,9 +88,11 @@ struct Plan {
     std::vector<int32_t> port_row;    // plan row of every port's node
 };
 
-// Largest sub-circuit a plan accepts (its FP64 inverse is 512 MiB; the full
-// sweep stages 16 bytes per node in LDS, within gfx950's 160 KiB per workgroup).
-constexpr int64_t kMaxSubCircuit = 8192;
+// Largest sub-circuit a plan accepts (its FP64 inverse is 2 GiB; a single
+// right-hand side's full sweep stages 8 bytes per node in LDS, within gfx950's
+// 160 KiB per workgroup; several right-hand sides or the adjoint need 16 bytes
+// per node per right-hand side, so at most 10,240 nodes).
+constexpr int64_t kMaxSubCircuit = 16384;
 
 // Builds the plan; on failure returns the status and sets err.  With lines
 // (line_a, line_b: n_lines pairs of nodes in different sub-circuits, not coupled

@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(kBlock)
 // R <- P R + (E_J - I_J) (P R)_J, over a grid of column blocks x row blocks.
 // k_gj_unscramble undoes the pivoting's column order at the end.
 constexpr int kNB = 16;
-constexpr int kMaxLarge = 8192;   // largest sub-circuit (the planner's limit)
+constexpr int kMaxLarge = 16384;  // largest sub-circuit (the planner's limit)
 constexpr int kPanelBlock = 512;
 constexpr int kUpdateRows = 128;  // rows per thread of the update
 

@@ -146,11 +146,11 @@ __global__ void __launch_bounds__(kBlock)
              const int32_t* __restrict__ port_slot, const int32_t* __restrict__ port_twin,
              const TV* __restrict__ pc, const TV* __restrict__ pbeta, const TV* __restrict__ pgamma,
              const TV* __restrict__ b, const TV* __restrict__ a_cur, TV* __restrict__ a_next, TV* __restrict__ x,
-             int max_ns, int max_slot) {
+             int max_ns, int max_slot, int xs_lds) {
     constexpr int G = Group<TO>::G;
     extern __shared__ char smem[];
     TV* rhs = reinterpret_cast<TV*>(smem);   // [max_ns]
-    TV* xs = rhs + max_ns;                   // [max_ns]
+    TV* xs = rhs + max_ns;                   // [max_ns] when xs_lds (else the waves read x back)
     const int s = xcd_block(blockIdx.x, gridDim.x);
     const int off = sub_off[s];
     const int ns = sub_off[s + 1] - off;
@@ -221,14 +221,14 @@ __global__ void __launch_bounds__(kBlock)
         TV v = acc[0];
 #pragma unroll
         for (int q = 1; q < G; ++q) v += acc[q];
-        xs[row] = v;
+        if (xs_lds) xs[row] = v;
         x[off + row] = v;
     }
     __syncthreads();
     for (int p = p0 + tid; p < p1; p += bs) {
         const int node = port_node[p];
         if ((node / bs) % int(gridDim.y) == int(blockIdx.y))  // x of this node was formed here
-            a_next[port_twin[p]] = pbeta[p] * xs[node] + pgamma[p] * a_cur[p];
+            a_next[port_twin[p]] = pbeta[p] * (xs_lds ? xs[node] : x[off + node]) + pgamma[p] * a_cur[p];
     }
 }
 
@@ -258,19 +258,21 @@ hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t*
     // right-hand side of a larger sub-circuit may use up to lds_limit
     auto fits = [&](int r) { return size_t(2) * max_ns * r * sizeof(TV) <= 65536; };
     const bool one = fits(1) || size_t(2) * max_ns * sizeof(TV) <= lds_limit;
-    if (kSweepChunk > 0 && nrhs == 1 && !adjoint && one) {
+    // the single right-hand-side sweep also runs with only rhs in LDS (x read back for the waves)
+    const bool xs_lds = size_t(2) * max_ns * sizeof(TV) <= lds_limit;
+    if (kSweepChunk > 0 && nrhs == 1 && !adjoint && size_t(max_ns) * sizeof(TV) <= lds_limit) {
         // few sub-circuits: one-wavefront blocks, each sub-circuit's rows spread over several
         const bool split = S < 1024 && max_ns > 64;
         const int bs = split || max_ns <= 64 ? 64 : kBlock;
         const int ry = split ? (max_ns + bs - 1) / bs : 1;
-        const size_t lds = size_t(2) * max_ns * sizeof(TV);
+        const size_t lds = size_t(xs_lds ? 2 : 1) * max_ns * sizeof(TV);
         constexpr int CH = kSweepChunk > 0 ? kSweepChunk : 1;
         if (lds > 65536)
             (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep1<TO, TV, CH>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         hipLaunchKernelGGL((k_sweep1<TO, TV, CH>), dim3(S, ry), dim3(bs), lds, st, K, kofs, sub_off, ports.off,
                            ports.node, ports.slot, ports.twin, pc, pbeta, pgamma, b, a_cur, a_next, x, max_ns,
-                           ports.max_slot);
+                           ports.max_slot, xs_lds ? 1 : 0);
         return hipGetLastError();
     }
     if (nrhs == 1 || !fits(2))

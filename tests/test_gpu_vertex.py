@@ -374,3 +374,32 @@ def test_adjoint_iterates_match_oracle_tear_of_the_transpose(torch, case):
     ls = spla.spsolve(At.tocsc(), b[0])
     assert rep.relres_max <= 1e-10
     assert np.abs(lam.cpu().numpy()[0] - ls).max() <= 1e-7 * np.abs(ls).max()
+
+
+def test_table2_grid3d_two_sub_circuits_on_the_gpu(torch):
+    """Table II's Grid3d setting: a 30^3 unit resistor grid torn in two at one
+    30 x 30 separator plane (900 interfacial nodes; 12,600 + 900 and 13,500 +
+    900 torn nodes, one right-hand side).  With W = 0.3 C the GPU needs the
+    oracle's sweeps and reaches the direct solution; handles this large take no
+    adjoint."""
+    dims = (30, 30, 30)
+    e = workloads.grid3d_edges(*dims)
+    n = int(np.prod(dims))
+    A = workloads.nodal_matrix(n, e, np.ones(e.shape[0]), np.full(n, workloads.GROUND_S))
+    b = np.random.default_rng(0).standard_normal((1, n))
+    label, iface, sides = workloads.separator_strips(dims, 14)
+    assert iface.size == 900 and label.max() == 1
+    W = vtm().vertex_admittance(A, label, iface, sides, "wob", 0.3)
+    r = oracle.vtm_solve(oracle.tear_at_vertices(A, label, iface, sides, W.toarray()), A, b, 1e-8, max_sweeps=500)
+    s = solver(A, label, iface, sides, W, check_every=1, adaptive_checks=False)
+    x, rep = s.solve(to_dev(torch, b), 1e-8)
+    assert r.status == "ok" and abs(rep.sweeps - r.sweeps) <= 1
+    xs = spla.spsolve(A.tocsc(), b[0])
+    assert np.abs(x.cpu().numpy()[0] - xs).max() <= 1e-6 * np.abs(xs).max()
+    with pytest.raises(vtm().VTMError) as ei:
+        s.solve_adjoint(to_dev(torch, b), 1e-8)
+    assert ei.value.name == "VTM_E_UNSUPPORTED"
+    s.close()
+    with pytest.raises(vtm().VTMError) as ei:
+        solver(A, label, iface, sides, W, nrhs_max=2)
+    assert ei.value.name == "VTM_E_UNSUPPORTED"

@@ -95,9 +95,9 @@ def test_plan_rejects_bad_input():
     C.data[3] = np.nan
     assert _status_of(lambda: vtm.plan(C, w.part, 1.0)) == "VTM_E_ARG"
     big = np.zeros(w.n, dtype=np.int32)
-    e = workloads.grid2d_edges(91, 91)   # one sub-circuit of 8,281 nodes: above the 8,192 limit
-    A91 = workloads.nodal_matrix(91 * 91, e, np.ones(e.shape[0]), np.full(91 * 91, 0.01))
-    assert _status_of(lambda: vtm.plan(A91, np.zeros(91 * 91, np.int32), 1.0)) == "VTM_E_UNSUPPORTED"
+    e = workloads.grid2d_edges(129, 129)   # one sub-circuit of 16,641 nodes: above the 16,384 limit
+    A129 = workloads.nodal_matrix(129 * 129, e, np.ones(e.shape[0]), np.full(129 * 129, 0.01))
+    assert _status_of(lambda: vtm.plan(A129, np.zeros(129 * 129, np.int32), 1.0)) == "VTM_E_UNSUPPORTED"
     assert big.size == w.n
 
 

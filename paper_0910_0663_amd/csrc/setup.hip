@@ -175,10 +175,10 @@ __global__ void __launch_bounds__(kBlock)
 // partial pivoting).  Each panel step is two launches, so that a few large
 // sub-circuits still spread over the whole chip.  k_gj_panel (one workgroup per
 // sub-circuit) eliminates the panel's columns (pivot search over all rows below
-// the diagonal; the panel E_J in global memory, [n][kNB] at panel + 2 kNB
-// sub_off[s]), applies the panel's row swaps P to every other column and keeps
-// their pivot rows (P R)_J ([kNB][n] right after E_J; then n doubles of
-// scratch for the pivot column).  k_gj_update then
+// the diagonal; the panel E_J in global memory, [n][kNB] at panel + (2 kNB + 1)
+// sub_off[s]); k_gj_swap applies the panel's row swaps P to every other column
+// and keeps their pivot rows (P R)_J ([kNB][n] right after E_J; then n doubles
+// of scratch for the pivot column), one column per thread.  k_gj_update then
 // applies the elimination to every other column as one rank-kb update,
 // R <- P R + (E_J - I_J) (P R)_J, over a grid of column blocks x row blocks.
 // k_gj_unscramble undoes the pivoting's column order at the end.
@@ -192,7 +192,6 @@ __global__ void __launch_bounds__(kPanelBlock)
                int k0, double* __restrict__ panel, int32_t* __restrict__ ipiv, int* flag) {
     __shared__ double red_v[kPanelBlock / 64];
     __shared__ int red_i[kPanelBlock / 64];
-    __shared__ int piv[kNB];
     const int s = blockIdx.x;
     const int off = sub_off[s], n = sub_off[s + 1] - off;
     if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;
@@ -215,10 +214,7 @@ __global__ void __launch_bounds__(kPanelBlock)
             bad = true;
             p = k;
         }
-        if (tid == 0) {
-            ipiv[off + k] = p;
-            piv[kk] = p;
-        }
+        if (tid == 0) ipiv[off + k] = p;
         if (p != k)
             for (int jj = tid; jj < kb; jj += bs) {
                 const double t = Pn[k * kNB + jj];
@@ -241,25 +237,35 @@ __global__ void __launch_bounds__(kPanelBlock)
         }
         __syncthreads();
     }
-    // the panel's columns are final for this step; every other column gets the row
-    // swaps, and its pivot rows are kept for the update
+    // the panel's columns are final for this step
     for (int t = tid; t < n * kb; t += bs) {
         const int i = t / kb, jj = t - i * kb;
         M[int64_t(i) * n + k0 + jj] = Pn[i * kNB + jj];
     }
-    for (int c = tid; c < n; c += bs) {
-        if (c >= k0 && c < k0 + kb) continue;
-        for (int kk = 0; kk < kb; ++kk) {
-            const int k = k0 + kk, p = piv[kk];
-            if (p != k) {
-                const double t = M[int64_t(k) * n + c];
-                M[int64_t(k) * n + c] = M[int64_t(p) * n + c];
-                M[int64_t(p) * n + c] = t;
-            }
-        }
-        for (int kk = 0; kk < kb; ++kk) R[int64_t(kk) * n + c] = M[int64_t(k0 + kk) * n + c];
-    }
     if (bad && tid == 0) atomicOr(flag, 1);
+}
+
+// every other column: the panel's row swaps, and its pivot rows kept for the update
+__global__ void __launch_bounds__(kBlock)
+    k_gj_swap(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
+              int k0, double* __restrict__ panel, const int32_t* __restrict__ ipiv) {
+    const int s = blockIdx.x;
+    const int off = sub_off[s], n = sub_off[s + 1] - off;
+    if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;
+    const int kb = min(kNB, n - k0);
+    const int c = blockIdx.y * blockDim.x + threadIdx.x;
+    if (c >= n || (c >= k0 && c < k0 + kb)) return;
+    double* M = base + kofs[s];
+    double* R = panel + int64_t(off) * (2 * kNB + 1) + int64_t(n) * kNB;
+    for (int kk = 0; kk < kb; ++kk) {
+        const int k = k0 + kk, p = ipiv[off + k];
+        if (p != k) {
+            const double t = M[int64_t(k) * n + c];
+            M[int64_t(k) * n + c] = M[int64_t(p) * n + c];
+            M[int64_t(p) * n + c] = t;
+        }
+    }
+    for (int kk = 0; kk < kb; ++kk) R[int64_t(kk) * n + c] = M[int64_t(k0 + kk) * n + c];
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -355,6 +361,8 @@ hipError_t invert_large(int S, int max_ns, const int32_t* sub_off, const int64_t
     for (int k0 = 0; k0 < max_ns; k0 += kNB) {
         hipLaunchKernelGGL(k_gj_panel, dim3(S), dim3(kPanelBlock), 0, st, sub_off, kofs, scratch64, k0, panel, ipiv,
                            flag);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gj_swap, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, ipiv);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(k_gj_update, tiles, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel);
         if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(kBlock)
 // k_gj_unscramble undoes the pivoting's column order at the end.
 constexpr int kNB = 16;
 constexpr int kMaxLarge = 16384;  // largest sub-circuit (the planner's limit)
-constexpr int kPanelBlock = 512;
+constexpr int kPanelBlock = 1024;
 constexpr int kUpdateRows = 128;  // rows per thread of the update
 
 __global__ void __launch_bounds__(kPanelBlock)

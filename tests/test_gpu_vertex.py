@@ -403,3 +403,23 @@ def test_table2_grid3d_two_sub_circuits_on_the_gpu(torch):
     with pytest.raises(vtm().VTMError) as ei:
         solver(A, label, iface, sides, W, nrhs_max=2)
     assert ei.value.name == "VTM_E_UNSUPPORTED"
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+def test_coupled_lines_graph_replay_matches_eager_bitwise(torch, prec):
+    """Check intervals of a solve torn at interfacial nodes with coupled lines
+    (b expanded to the twins, coupled waves after each full sweep, x the twins'
+    mean) replayed as captured hipGraphs give bitwise the eager result, solve
+    after solve."""
+    A, b, label, iface, sides, W = coupled((24, 47), 10, "wob", 0.3, seed=9)
+    common = dict(precision=prec, check_every=4, adaptive_checks=False)
+    eager = solver(A, label, iface, sides, W, use_graph=False, **common)
+    graph = solver(A, label, iface, sides, W, use_graph=True, **common)
+    bd = to_dev(torch, b)
+    xe, re = eager.solve(bd, 1e-10)
+    for _ in range(3):
+        xg, rg = graph.solve(bd, 1e-10)
+        torch.cuda.synchronize()
+        assert rg.sweeps == re.sweeps and rg.outer == re.outer
+        assert torch.equal(xg, xe)
+    assert re.relres_max <= 1e-10

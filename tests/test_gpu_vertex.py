@@ -423,3 +423,22 @@ def test_coupled_lines_graph_replay_matches_eager_bitwise(torch, prec):
         assert rg.sweeps == re.sweeps and rg.outer == re.outer
         assert torch.equal(xg, xe)
     assert re.relres_max <= 1e-10
+
+
+def test_no_interfacial_nodes_and_zero_columns(torch):
+    """Degenerate tears: with no interfacial node the circuit is one sub-circuit
+    and one sweep is the direct solve; a zero right-hand side column converges
+    at once with x = 0 beside a nonzero one."""
+    A, b, label, iface, sides, W = strips((12, 13), 5, nrhs=2)
+    one = np.zeros(A.shape[0], dtype=np.int32)
+    s = solver(A, one, np.zeros(0, np.int32), np.zeros((0, 2), np.int32), 1.0, nrhs_max=2, check_every=1)
+    x, rep = s.solve(to_dev(torch, b), 1e-12)
+    assert rep.sweeps == 1
+    xs = np.linalg.solve(A.toarray(), b.T).T
+    assert np.abs(x.cpu().numpy() - xs).max() <= 1e-12 * np.abs(xs).max()
+    b2 = b.copy()
+    b2[1] = 0.0
+    s = solver(A, label, iface, sides, W, nrhs_max=2, check_every=1)
+    x, rep = s.solve(to_dev(torch, b2), 1e-10)
+    xh = x.cpu().numpy()
+    assert np.all(xh[1] == 0.0) and rep.relres[0] <= 1e-10

@@ -21,6 +21,10 @@
 #ifndef VTM_MFMA_ALTERNATE
 #define VTM_MFMA_ALTERNATE 1
 #endif
+// batched port-to-port sweep: h loaded into registers before the product
+#ifndef VTM_MFMA_PP_PREFETCH_H
+#define VTM_MFMA_PP_PREFETCH_H 1
+#endif
 
 namespace vtm {
 
@@ -147,7 +151,8 @@ __device__ inline void tile_gemm(const T* Ablk, int np, const T* sb, int bsel, i
             for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    epi(mts[j] * 16 + M::out_row(lane, v), nt * 16 + (lane & 15), TV(acc[j][nt][v]));
+                    epi(mts[j] * 16 + M::out_row(lane, v), nt * 16 + (lane & 15), TV(acc[j][nt][v]),
+                        (j * NT + nt) * 4 + v);
         }
     }
 }
@@ -233,7 +238,7 @@ __global__ void __launch_bounds__(kBlock)
     __syncthreads();
 
     // 2. X = Kinv B, x stored on the rows the wave update reads (all rows with write_x)
-    tile_gemm<T, NT, RT, kWaves>(K + mofs[s], np, sb, sizeof(T) == 2 ? np : rc, w, [&](int row, int n, TV v) {
+    tile_gemm<T, NT, RT, kWaves>(K + mofs[s], np, sb, sizeof(T) == 2 ? np : rc, w, [&](int row, int n, TV v, int) {
         if (row < ns && n < w && (write_x || pcount[row])) x[int64_t(off + row) * nrhs + r0 + n] = v;
     });
     __syncthreads();
@@ -279,16 +284,35 @@ __global__ void __launch_bounds__(WAVES * 64)
     const int p0 = port_off[s], q = port_off[s + 1] - p0;
     const int qp = tile_pad(q);
     const int tid = threadIdx.x;
+    // FP64: h of the outputs this lane will produce, loaded before the product so that
+    // the epilogue does not wait on it (when one pass of row tiles covers the operator;
+    // in BF16 the extra registers cost more occupancy than the wait)
+    const int lane = tid & 63, wave = tid >> 6;
+    constexpr bool kPre = VTM_MFMA_PP_PREFETCH_H && sizeof(T) == 8;
+    const bool pre = kPre && qp / 16 <= WAVES * RT;
+    TV hreg[kPre ? RT * NT * 4 : 1];
+#pragma unroll
+    for (int j = 0; j < (kPre ? RT : 0); ++j)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = (wave + j * WAVES) * 16 + M::out_row(lane, v), n = nt * 16 + (lane & 15);
+                hreg[(j * NT + nt) * 4 + v] =
+                    pre && row < q && n < w ? h[int64_t(p0 + row) * nrhs + r0 + n] : TV(0);
+            }
     for (int t = tid; t < qp * rc; t += WAVES * 64) {
         const int k = t / rc, n = t - k * rc;
         const TV v = (k < q && n < w) ? a_cur[int64_t(p0 + k) * nrhs + r0 + n] : TV(0);
         M::stage(sb, qp, rc, k, n, v);
     }
     __syncthreads();
-    tile_gemm<T, NT, RT, WAVES>(Mop + qmofs[s], qp, sb, sizeof(T) == 2 ? qp : rc, w, [&](int row, int n, TV v) {
+    tile_gemm<T, NT, RT, WAVES>(Mop + qmofs[s], qp, sb, sizeof(T) == 2 ? qp : rc, w,
+                                [&](int row, int n, TV v, int idx) {
         if (row < q && n < w) {
             const int p = p0 + row;
-            a_next[int64_t(port_twin[p]) * nrhs + r0 + n] = v + h[int64_t(p) * nrhs + r0 + n];
+            const TV hv = pre ? hreg[kPre ? idx : 0] : h[int64_t(p) * nrhs + r0 + n];
+            a_next[int64_t(port_twin[p]) * nrhs + r0 + n] = v + hv;
         }
     });
 }

@@ -95,7 +95,8 @@ typedef struct {
                                predicted remaining sweeps (a multiple of check_every,
                                at most 64 of them); 0: check every check_every      */
     int32_t batch_row_tiles;/* batched (MFMA) sweep: 16-row tiles each wavefront holds
-                               per pass, 3 or 5; 0 = chosen by the autotuner at setup */
+                               per pass, 3 or 5; 0 = chosen by the autotuner at setup
+                               (which also tries 1: fewer registers, more wavefronts) */
     int32_t batch_rhs_block;/* batched sweep: right-hand sides per workgroup, 16, 32,
                                48 or 64; 0 = chosen by the autotuner at setup        */
     int32_t local_form;     /* 0: every sweep applies the full local inverse.

@@ -429,8 +429,10 @@ vtm_status autotune(vtm_handle h) {
     int bv = 0, brc = 0;
     vtm_status st = VTM_OK;
     const int v_lo = h->opt.batch_row_tiles == 5 ? 1 : 0, v_hi = h->opt.batch_row_tiles == 3 ? 0 : 1;
-    for (int variant = v_lo; variant <= v_hi && st == VTM_OK; ++variant)
+    // variants 0 and 1: 3 or 5 row tiles per pass; 2: one row tile (only when not forced)
+    for (int variant = v_lo; variant <= (h->opt.batch_row_tiles > 0 ? v_hi : 2) && st == VTM_OK; ++variant)
         for (int rc = 64; rc >= 16 && st == VTM_OK; rc -= 16) {
+            if (variant == 1 && v_hi == 0) continue;
             if (rc > 16 && rc >= nrhs + 16) continue;  // wider than the right-hand sides
             if (h->opt.batch_rhs_block > 0 && rc != h->opt.batch_rhs_block) continue;
             st = launch_one(h, low, nrhs, b, x, 0, false, variant, rc, false);
@@ -458,9 +460,12 @@ vtm_status autotune(vtm_handle h) {
         else
             VTM_HIP(vtm::launch_fill<double>(P.nports * nrhs, 0.0, h->h64.p, h->stream));
         float best_pp = INFINITY;
-        for (int variant = 0; variant < 4 && st == VTM_OK; ++variant)
+        // variants: bit 0 five row tiles, bit 1 eight wavefronts, bit 2 one row tile (bit 0 unused)
+        const bool forced_rows = h->opt.batch_row_tiles > 0;
+        for (int variant = 0; variant < 8 && st == VTM_OK; ++variant)
             for (int rc = 64; rc >= 16 && st == VTM_OK; rc -= 16) {
-                if ((variant & 1) < v_lo || (variant & 1) > v_hi) continue;
+                if ((variant & 5) == 5 || (forced_rows && (variant & 4))) continue;
+                if (!(variant & 4) && ((variant & 1) < v_lo || (variant & 1) > v_hi)) continue;
                 if (rc > 16 && rc >= nrhs + 16) continue;
                 if (h->opt.batch_rhs_block > 0 && rc != h->opt.batch_rhs_block) continue;
                 h->pp_variant = variant;
@@ -840,7 +845,7 @@ vtm_status solve_common(vtm_handle h, const double* b, double* x, int32_t nrhs, 
         rep->sweep_launches = out.launches;
         rep->pp_kernel_ms = out.pp_ms;
         rep->pp_launches = out.pp_launches;
-        rep->batch_row_tiles = h->tiles ? (h->mfma_variant ? 5 : 3) : 0;
+        rep->batch_row_tiles = h->tiles ? (h->mfma_variant == 1 ? 5 : (h->mfma_variant == 2 ? 1 : 3)) : 0;
         rep->batch_rhs_block = h->tiles ? h->mfma_rc : 0;
         if (rep->relres)
             for (int r = 0; r < nrhs; ++r) rep->relres[r] = out.rel[r];

@@ -413,13 +413,17 @@ hipError_t launch_sweep_mfma(int S, int max_ns, int max_ports, int nrhs, int var
     if (lds > lds_limit) return hipErrorInvalidValue;
     if (rc > nrhs) rc = ((nrhs + 15) / 16) * 16 < rc ? ((nrhs + 15) / 16) * 16 : rc;
     const int nt = (rc + 15) / 16;
-    const bool deep = variant != 0;
+    // variant 0: 3 row tiles per wavefront pass, 1: 5, 2: 1 (fewer registers, more wavefronts)
 #define VTM_MFMA_CASE(NTV)                                                                                      \
-    if (nt == NTV)                                                                                              \
-        return deep ? launch_t<T, NTV, 5>(S, nrhs, rc, lds, K, mofs, sub_off, ports, pc, pbeta, pgamma, b, a_cur, \
-                                          a_next, x, write_x, st)                                               \
-                    : launch_t<T, NTV, 3>(S, nrhs, rc, lds, K, mofs, sub_off, ports, pc, pbeta, pgamma, b, a_cur, \
-                                          a_next, x, write_x, st);
+    if (nt == NTV) {                                                                                            \
+        if (variant == 2)                                                                                       \
+            return launch_t<T, NTV, 1>(S, nrhs, rc, lds, K, mofs, sub_off, ports, pc, pbeta, pgamma, b, a_cur,  \
+                                       a_next, x, write_x, st);                                                 \
+        return variant == 1 ? launch_t<T, NTV, 5>(S, nrhs, rc, lds, K, mofs, sub_off, ports, pc, pbeta, pgamma, \
+                                                  b, a_cur, a_next, x, write_x, st)                             \
+                            : launch_t<T, NTV, 3>(S, nrhs, rc, lds, K, mofs, sub_off, ports, pc, pbeta, pgamma, \
+                                                  b, a_cur, a_next, x, write_x, st);                            \
+    }
     VTM_MFMA_CASE(1)
     VTM_MFMA_CASE(2)
     VTM_MFMA_CASE(3)
@@ -442,10 +446,16 @@ hipError_t launch_sweep_mfma_pp(int S, int max_ports, int nrhs, int variant, int
     if (lds > lds_limit) return hipErrorInvalidValue;
     if (rc > nrhs) rc = ((nrhs + 15) / 16) * 16 < rc ? ((nrhs + 15) / 16) * 16 : rc;
     const int nt = (rc + 15) / 16;
-    // variant: bit 0 = 5 row tiles per pass (else 3), bit 1 = 8 wavefronts per workgroup (else 4)
-    const bool deep = (variant & 1) != 0, wide = (variant & 2) != 0;
+    // variant: bit 0 = 5 row tiles per pass (else 3), bit 1 = 8 wavefronts per workgroup (else 4),
+    // bit 2 = 1 row tile per pass (small operators: fewer registers, more wavefronts in flight)
+    const bool deep = (variant & 1) != 0, wide = (variant & 2) != 0, thin = (variant & 4) != 0;
 #define VTM_MFMA_PP_CASE(NTV)                                                                                    \
     if (nt == NTV) {                                                                                             \
+        if (thin)                                                                                                \
+            return wide ? launch_pp_t<T, NTV, 1, 8>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,   \
+                                                    a_next, reverse, st)                                         \
+                        : launch_pp_t<T, NTV, 1, 4>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,   \
+                                                    a_next, reverse, st);                                        \
         if (wide)                                                                                                \
             return deep ? launch_pp_t<T, NTV, 5, 8>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,   \
                                                     a_next, reverse, st)                                         \

@@ -174,7 +174,15 @@ hipError_t launch_port_residual(int64_t n_port_nodes, int nrhs, const int32_t* p
 // r = b - A x in FP64 on the untorn (renumbered) A; per right-hand side
 // sums of r^2 and b^2 land in norms[2 * rhs + {0, 1}] (fixed summation order).
 // r_out may be null.  partial must hold kResidBlocks * nrhs * 2 doubles.
-constexpr int kResidBlocks = 1024;
+// Largest number of workgroups of the residual kernels.  They take one per 4,096
+// (row, right-hand side) pairs, at least 1,024: with many right-hand sides a
+// row's gathers are one wavefront's dependent loads, and more wavefronts hide
+// them; small problems keep fewer partial sums.
+constexpr int kResidBlocks = 4096;
+inline int resid_blocks(int64_t rows, int nrhs) {
+    const int64_t b = rows * nrhs / 4096;
+    return int(b < 1024 ? 1024 : (b > kResidBlocks ? kResidBlocks : b));
+}
 template <typename TX>
 hipError_t launch_residual(int n, int nrhs, const int32_t* rowptr, const int32_t* col,
                            const double* val, const double* b, const TX* x, double* r_out,

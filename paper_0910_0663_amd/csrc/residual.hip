@@ -116,11 +116,12 @@ hipError_t launch_port_residual(int64_t n_port_nodes, int nrhs, const int32_t* p
                                 const double* gamma, const double* gd, const double* g, double* partial, double* norms,
                                 hipStream_t st) {
     if (nrhs < 1 || nrhs > kBlock) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_port_resid<TV>, dim3(kResidBlocks), dim3(kBlock), 0, st, n_port_nodes, nrhs, pn_pfirst, twin,
+    const int blocks = resid_blocks(n_port_nodes, nrhs);
+    hipLaunchKernelGGL(k_port_resid<TV>, dim3(blocks), dim3(kBlock), 0, st, n_port_nodes, nrhs, pn_pfirst, twin,
                        a_cur, a_next, c, beta, gamma, gd, g, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_norms_final, dim3(2 * nrhs), dim3(kBlock), 0, st, kResidBlocks, nrhs, partial, norms);
+    hipLaunchKernelGGL(k_norms_final, dim3(2 * nrhs), dim3(kBlock), 0, st, blocks, nrhs, partial, norms);
     return hipGetLastError();
 }
 
@@ -136,11 +137,12 @@ hipError_t launch_residual(int n, int nrhs, const int32_t* rowptr, const int32_t
                            const double* b, const TX* x, double* r_out, double* partial, double* norms,
                            hipStream_t st) {
     if (nrhs < 1 || nrhs > kBlock) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_resid<TX>, dim3(kResidBlocks), dim3(kBlock), 0, st, n, nrhs, rowptr, col, val, b, x, r_out,
+    const int blocks = resid_blocks(n, nrhs);
+    hipLaunchKernelGGL(k_resid<TX>, dim3(blocks), dim3(kBlock), 0, st, n, nrhs, rowptr, col, val, b, x, r_out,
                        partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_norms_final, dim3(2 * nrhs), dim3(kBlock), 0, st, kResidBlocks, nrhs, partial, norms);
+    hipLaunchKernelGGL(k_norms_final, dim3(2 * nrhs), dim3(kBlock), 0, st, blocks, nrhs, partial, norms);
     return hipGetLastError();
 }
 

@@ -500,3 +500,16 @@ def test_graph_replay_matches_eager_bitwise(torch, cfg, kw, prec, nr):
         assert rg.sweeps == re.sweeps and rg.outer == re.outer
         assert torch.equal(xg, xe)
     assert oracle.relative_residual(w.A, w.b, xe.cpu().numpy()).max() <= w.tol
+
+
+@pytest.mark.parametrize("form", ["port", "full"])
+def test_adjoint_of_symmetric_circuit_is_the_forward_solve(torch, form):
+    """A symmetric A: vtm_solve_adjoint(g) is vtm_solve(g) (same sweeps, same
+    result to the rounding of reading the stored inverses transposed)."""
+    w = workloads.make(1)
+    s = vtm().Solver(w.A, w.part, w.Z, check_every=1, adaptive_checks=False, local_form=form)
+    b = to_dev(torch, w.b)
+    x, rx = s.solve(b, w.tol)
+    lam, rl = s.solve_adjoint(b, w.tol)
+    assert rx.sweeps == rl.sweeps
+    assert_close(lam.cpu().numpy(), x.cpu().numpy())

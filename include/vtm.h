@@ -45,7 +45,7 @@ typedef enum {
     VTM_E_MAXITER = 5,      /* opt.max_sweeps reached without convergence            */
     VTM_E_HIP = 6,          /* HIP runtime error                                     */
     VTM_E_OOM = 7,          /* device or pinned-host allocation failed               */
-    VTM_E_UNSUPPORTED = 8   /* valid input outside this build's limits               */
+    VTM_E_UNSUPPORTED = 8   /* valid input outside the library's limits             */
 } vtm_status;
 
 typedef enum {

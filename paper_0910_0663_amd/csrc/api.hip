@@ -1219,7 +1219,7 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
     DevBuf<int32_t> ipiv;
     if (h->tiles || P.max_ns > vtm::kLdsSetupMax) VTM_HIP(scratch.alloc(nk));
     if (P.max_ns > vtm::kLdsSetupMax) {
-        VTM_HIP(panel.alloc(P.n * 33));
+        VTM_HIP(panel.alloc(P.n * (2 * 16 + 1)));
         VTM_HIP(ipiv.alloc(P.n));
     }
     VTM_HIP(h->c64.upload(P.pc, s));

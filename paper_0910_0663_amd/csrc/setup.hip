@@ -171,18 +171,21 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
-// ... and invert it in place, kNB columns at a time (blocked Gauss-Jordan with
-// partial pivoting).  Each panel step is two launches, so that a few large
-// sub-circuits still spread over the whole chip.  k_gj_panel (one workgroup per
-// sub-circuit) eliminates the panel's columns (pivot search over all rows below
-// the diagonal; the panel E_J in global memory, [n][kNB] at panel + (2 kNB + 1)
-// sub_off[s]); k_gj_swap applies the panel's row swaps P to every other column
-// and keeps their pivot rows (P R)_J ([kNB][n] right after E_J; then n doubles
-// of scratch for the pivot column), one column per thread.  k_gj_update then
-// applies the elimination to every other column as one rank-kb update,
-// R <- P R + (E_J - I_J) (P R)_J, over a grid of column blocks x row blocks.
-// k_gj_unscramble undoes the pivoting's column order at the end.
+// ... and invert it in place, NB columns at a time (blocked Gauss-Jordan with
+// partial pivoting; NB = 16).  Each panel step is a few
+// launches, so that a few large sub-circuits still spread over the whole chip.
+// k_gj_panel (one workgroup per sub-circuit) eliminates the panel's columns
+// (pivot search over all rows below the diagonal; the panel E_J in global
+// memory, [n][NB] at panel + (2 NB + 1) sub_off[s]); k_gj_swap applies the
+// panel's row swaps P to every other column and keeps their pivot rows
+// (P R)_J ([NB][n] right after E_J; then n doubles of scratch for the pivot
+// column), one column per thread.  k_gj_update then applies the elimination to
+// every other column as one rank-kb update, R <- P R + (E_J - I_J) (P R)_J, over
+// a grid of column blocks x row blocks.  k_gj_unscramble undoes the pivoting's
+// column order at the end.
 constexpr int kNB = 16;
+constexpr int kWideNB = 16;       // panel width of the very large sub-circuits (32 measured no faster:
+                                  // the update is bound by its arithmetic, not by passes over K)
 constexpr int kMaxLarge = 16384;  // largest sub-circuit (the planner's limit)
 constexpr int kPanelBlock = 1024;
 constexpr int kUpdateRows = 128;  // rows per thread of the update
@@ -245,18 +248,100 @@ __global__ void __launch_bounds__(kPanelBlock)
     if (bad && tid == 0) atomicOr(flag, 1);
 }
 
+// The same panel elimination for a few very large sub-circuits, where one
+// workgroup's chain of 16 pivot steps over n rows is the setup's bottleneck:
+// each step is two launches, the pivot (search, row swap, scaling of the pivot
+// row; one workgroup per sub-circuit) and the elimination of every other row of
+// the panel (one row per thread over a grid of row blocks).  k_gjw_load and
+// k_gjw_store move the panel between K and the panel buffer.
+template <int NB>
+__global__ void __launch_bounds__(kBlock)
+    k_gjw_load(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs,
+               const double* __restrict__ base, int k0, double* __restrict__ panel, int store) {
+    const int s = blockIdx.x;
+    const int off = sub_off[s], n = sub_off[s + 1] - off;
+    if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;
+    const int i = blockIdx.y * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int kb = min(NB, n - k0);
+    double* M = const_cast<double*>(base) + kofs[s] + int64_t(i) * n + k0;
+    double* Pn = panel + int64_t(off) * (2 * NB + 1) + int64_t(i) * NB;
+    for (int jj = 0; jj < kb; ++jj) {
+        if (store)
+            M[jj] = Pn[jj];
+        else
+            Pn[jj] = M[jj];
+    }
+}
+
+template <int NB>
+__global__ void __launch_bounds__(kPanelBlock)
+    k_gjw_pivot(const int32_t* __restrict__ sub_off, int k0, int kk, double* __restrict__ panel,
+                int32_t* __restrict__ ipiv, int* flag) {
+    __shared__ double red_v[kPanelBlock / 64];
+    __shared__ int red_i[kPanelBlock / 64];
+    const int s = blockIdx.x;
+    const int off = sub_off[s], n = sub_off[s + 1] - off;
+    if (n <= kLdsSetupMax || n > kMaxLarge) return;
+    const int kb = min(NB, n - k0);
+    if (k0 >= n || kk >= kb) return;
+    const int k = k0 + kk;
+    double* Pn = panel + int64_t(off) * (2 * NB + 1);
+    const int tid = threadIdx.x, bs = blockDim.x;
+    int p = block_argmax(Pn + kk, NB, k, n, red_v, red_i);
+    bool bad = false;
+    if (p == INT_MAX) {
+        bad = true;
+        p = k;
+    }
+    if (tid == 0) ipiv[off + k] = p;
+    if (p != k)
+        for (int jj = tid; jj < kb; jj += bs) {
+            const double t = Pn[k * NB + jj];
+            Pn[k * NB + jj] = Pn[p * NB + jj];
+            Pn[p * NB + jj] = t;
+        }
+    __syncthreads();
+    double pv = Pn[k * NB + kk];
+    if (pv == 0.0 || !isfinite(pv)) {
+        bad = true;
+        pv = 1.0;
+    }
+    __syncthreads();  // every thread has read the pivot before row k is scaled
+    for (int jj = tid; jj < kb; jj += bs) Pn[k * NB + jj] = (jj == kk ? 1.0 : Pn[k * NB + jj]) / pv;
+    if (bad && tid == 0) atomicOr(flag, 1);
+}
+
+template <int NB>
+__global__ void __launch_bounds__(kBlock)
+    k_gjw_elim(const int32_t* __restrict__ sub_off, int k0, int kk, double* __restrict__ panel) {
+    const int s = blockIdx.x;
+    const int off = sub_off[s], n = sub_off[s + 1] - off;
+    if (n <= kLdsSetupMax || n > kMaxLarge) return;
+    const int kb = min(NB, n - k0);
+    if (k0 >= n || kk >= kb) return;
+    const int k = k0 + kk;
+    const int i = blockIdx.y * blockDim.x + threadIdx.x;
+    if (i >= n || i == k) return;
+    double* Pn = panel + int64_t(off) * (2 * NB + 1);
+    const double f = Pn[i * NB + kk];
+    for (int jj = 0; jj < kb; ++jj)
+        Pn[i * NB + jj] = (jj == kk ? 0.0 : Pn[i * NB + jj]) - f * Pn[k * NB + jj];
+}
+
 // every other column: the panel's row swaps, and its pivot rows kept for the update
+template <int NB>
 __global__ void __launch_bounds__(kBlock)
     k_gj_swap(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
               int k0, double* __restrict__ panel, const int32_t* __restrict__ ipiv) {
     const int s = blockIdx.x;
     const int off = sub_off[s], n = sub_off[s + 1] - off;
     if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;
-    const int kb = min(kNB, n - k0);
+    const int kb = min(NB, n - k0);
     const int c = blockIdx.y * blockDim.x + threadIdx.x;
     if (c >= n || (c >= k0 && c < k0 + kb)) return;
     double* M = base + kofs[s];
-    double* R = panel + int64_t(off) * (2 * kNB + 1) + int64_t(n) * kNB;
+    double* R = panel + int64_t(off) * (2 * NB + 1) + int64_t(n) * NB;
     for (int kk = 0; kk < kb; ++kk) {
         const int k = k0 + kk, p = ipiv[off + k];
         if (p != k) {
@@ -268,27 +353,28 @@ __global__ void __launch_bounds__(kBlock)
     for (int kk = 0; kk < kb; ++kk) R[int64_t(kk) * n + c] = M[int64_t(k0 + kk) * n + c];
 }
 
+template <int NB>
 __global__ void __launch_bounds__(kBlock)
     k_gj_update(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
                 int k0, const double* __restrict__ panel) {
     const int s = blockIdx.x;
     const int off = sub_off[s], n = sub_off[s + 1] - off;
     if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;
-    const int kb = min(kNB, n - k0);
+    const int kb = min(NB, n - k0);
     const int c = blockIdx.y * blockDim.x + threadIdx.x;
     const int i0 = blockIdx.z * kUpdateRows, i1 = min(n, i0 + kUpdateRows);
     if (c >= n || (c >= k0 && c < k0 + kb) || i0 >= n) return;
     double* M = base + kofs[s];
-    const double* Pn = panel + int64_t(off) * (2 * kNB + 1);
-    const double* R = Pn + int64_t(n) * kNB;
-    double rj[kNB];
+    const double* Pn = panel + int64_t(off) * (2 * NB + 1);
+    const double* R = Pn + int64_t(n) * NB;
+    double rj[NB];
 #pragma unroll
-    for (int kk = 0; kk < kNB; ++kk) rj[kk] = kk < kb ? R[int64_t(kk) * n + c] : 0.0;
+    for (int kk = 0; kk < NB; ++kk) rj[kk] = kk < kb ? R[int64_t(kk) * n + c] : 0.0;
     for (int i = i0; i < i1; ++i) {
         double acc = M[int64_t(i) * n + c];
 #pragma unroll
-        for (int kk = 0; kk < kNB; ++kk)
-            if (kk < kb) acc += (Pn[i * kNB + kk] - (i == k0 + kk ? 1.0 : 0.0)) * rj[kk];
+        for (int kk = 0; kk < NB; ++kk)
+            if (kk < kb) acc += (Pn[i * NB + kk] - (i == k0 + kk ? 1.0 : 0.0)) * rj[kk];
         M[int64_t(i) * n + c] = acc;
     }
 }
@@ -358,14 +444,36 @@ hipError_t invert_large(int S, int max_ns, const int32_t* sub_off, const int64_t
     if (e != hipSuccess) return e;
     const dim3 cols(unsigned(S), unsigned((max_ns + kBlock - 1) / kBlock));
     const dim3 tiles(unsigned(S), cols.y, unsigned((max_ns + kUpdateRows - 1) / kUpdateRows));
-    for (int k0 = 0; k0 < max_ns; k0 += kNB) {
-        hipLaunchKernelGGL(k_gj_panel, dim3(S), dim3(kPanelBlock), 0, st, sub_off, kofs, scratch64, k0, panel, ipiv,
-                           flag);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_gj_swap, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, ipiv);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_gj_update, tiles, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+    // above 2,048 nodes the panel's pivot steps are spread over the chip (two launches each)
+    if (max_ns > 2048) {
+        constexpr int NB = kWideNB;
+        for (int k0 = 0; k0 < max_ns; k0 += NB) {
+            hipLaunchKernelGGL(k_gjw_load<NB>, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, 0);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            for (int kk = 0; kk < NB; ++kk) {
+                hipLaunchKernelGGL(k_gjw_pivot<NB>, dim3(S), dim3(kPanelBlock), 0, st, sub_off, k0, kk, panel, ipiv,
+                                   flag);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+                hipLaunchKernelGGL(k_gjw_elim<NB>, cols, dim3(kBlock), 0, st, sub_off, k0, kk, panel);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
+            hipLaunchKernelGGL(k_gjw_load<NB>, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, 1);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_gj_swap<NB>, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, ipiv);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_gj_update<NB>, tiles, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    } else {
+        for (int k0 = 0; k0 < max_ns; k0 += kNB) {
+            hipLaunchKernelGGL(k_gj_panel, dim3(S), dim3(kPanelBlock), 0, st, sub_off, kofs, scratch64, k0, panel,
+                               ipiv, flag);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_gj_swap<kNB>, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, ipiv);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_gj_update<kNB>, tiles, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     hipLaunchKernelGGL(k_gj_unscramble, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, ipiv);
     return hipGetLastError();

@@ -133,6 +133,9 @@ typedef struct {
     int32_t batch_rhs_block;
     double pp_kernel_ms;    /* opt.timing: summed duration of the port-to-port sweeps */
     int64_t pp_launches;    /* opt.timing: number of port-to-port sweeps timed       */
+    int32_t pp_shape[3];    /* batched port-to-port sweep shape in use: 16-row tiles
+                               per wavefront pass, right-hand sides per workgroup,
+                               wavefronts per workgroup (zeros when not batched)     */
     double *relres;         /* optional caller array [nrhs]: final per-column value  */
 } vtm_report;
 

@@ -53,7 +53,8 @@ class Report(C.Structure):
     _fields_ = [("sweeps", C.c_int64), ("outer", C.c_int32), ("checks", C.c_int32),
                 ("relres_max", C.c_double), ("solve_ms", C.c_double), ("sweep_kernel_ms", C.c_double),
                 ("sweep_launches", C.c_int64), ("batch_row_tiles", C.c_int32), ("batch_rhs_block", C.c_int32),
-                ("pp_kernel_ms", C.c_double), ("pp_launches", C.c_int64), ("relres", C.POINTER(C.c_double))]
+                ("pp_kernel_ms", C.c_double), ("pp_launches", C.c_int64), ("pp_shape", C.c_int32 * 3),
+                ("relres", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -266,6 +267,7 @@ class SolveReport:
     batch_shape: tuple = (0, 0)
     pp_kernel_ms: float = 0.0
     pp_launches: int = 0
+    pp_shape: tuple = (0, 0, 0)
 
 
 def _ptr(t) -> int:
@@ -364,7 +366,7 @@ class Solver:
             st = fn(self._h, C.c_void_p(_ptr(b)), C.c_void_p(_ptr(x)), nrhs, float(tol), C.byref(rep))
         r = SolveReport(rep.sweeps, rep.outer, rep.checks, rep.relres_max, rep.solve_ms, rel.copy(),
                         rep.sweep_kernel_ms, rep.sweep_launches, (rep.batch_row_tiles, rep.batch_rhs_block),
-                        rep.pp_kernel_ms, rep.pp_launches)
+                        rep.pp_kernel_ms, rep.pp_launches, tuple(rep.pp_shape))
         _check(st, r)
         return x, r
 

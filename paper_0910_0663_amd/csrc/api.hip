@@ -847,6 +847,11 @@ vtm_status solve_common(vtm_handle h, const double* b, double* x, int32_t nrhs, 
         rep->pp_launches = out.pp_launches;
         rep->batch_row_tiles = h->tiles ? (h->mfma_variant == 1 ? 5 : (h->mfma_variant == 2 ? 1 : 3)) : 0;
         rep->batch_rhs_block = h->tiles ? h->mfma_rc : 0;
+        // pp variant bits: 0 five row tiles, 1 eight wavefronts, 2 one row tile
+        const int ppv = h->pp_variant;
+        rep->pp_shape[0] = h->ppb ? ((ppv & 4) ? 1 : (ppv & 1) ? 5 : 3) : 0;
+        rep->pp_shape[1] = h->ppb ? std::min(h->pp_rc, (nrhs + 15) / 16 * 16) : 0;
+        rep->pp_shape[2] = h->ppb ? ((ppv & 2) ? 8 : 4) : 0;
         if (rep->relres)
             for (int r = 0; r < nrhs; ++r) rep->relres[r] = out.rel[r];
     }
@@ -1287,8 +1292,8 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
     // batched form: port-to-port operators in tile order, built from the FP64 inverses in scratch
     const int qpad = vtm::tile_pad(P.max_ports);
     h->ppb = o.local_form >= 1 && h->tiles && P.nports > 0 &&
-             (o.precision == VTM_FP64 ? vtm::tile_lds_bytes<double>(qpad, 16)
-                                      : vtm::tile_lds_bytes<__bf16>(qpad, 16)) <= h->lds_limit;
+             (o.precision == VTM_FP64 ? vtm::pp_lds_bytes<double>(qpad, 16)
+                                      : vtm::pp_lds_bytes<__bf16>(qpad, 16)) <= h->lds_limit;
     if (h->ppb) {
         VTM_HIP(h->qmofs.upload(P.qmofs, s));
         const int64_t nq = P.qmofs[P.S];

@@ -15,15 +15,31 @@
 // walks k: per k tile one LDS read per B fragment serves all RT row tiles, and
 // the next k tile's RT A-tiles are in flight while this one's MFMAs issue.
 #include "kernels.hpp"
+#include "layout.hpp"
 #include "tiles.hpp"
 
 // walk the sub-circuits in reverse order on every other port-to-port sweep
 #ifndef VTM_MFMA_ALTERNATE
 #define VTM_MFMA_ALTERNATE 1
 #endif
-// batched port-to-port sweep: h loaded into registers before the product
+// batched port-to-port sweep: h loaded into registers before the product (FP64)
 #ifndef VTM_MFMA_PP_PREFETCH_H
 #define VTM_MFMA_PP_PREFETCH_H 1
+#endif
+// batched sweeps: k tiles of A in flight per wavefront (FP64, BF16)
+#ifndef VTM_MFMA_PD64
+#define VTM_MFMA_PD64 2
+#endif
+#ifndef VTM_MFMA_PD16
+#define VTM_MFMA_PD16 2
+#endif
+// batched sweeps: XCD-contiguous ranges of (sub-circuit, column block)
+#ifndef VTM_MFMA_XCD
+#define VTM_MFMA_XCD 1
+#endif
+// batched port-to-port sweep: 16-byte loads of the incident waves when aligned
+#ifndef VTM_MFMA_PP_VEC
+#define VTM_MFMA_PP_VEC 1
 #endif
 
 namespace vtm {
@@ -118,19 +134,23 @@ __device__ inline void tile_gemm(const T* Ablk, int np, const T* sb, int bsel, i
             for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[j][nt][v] = 0;
-        typename M::AFrag abuf[2][RT];
+        // ring of PD k tiles: tile k sits in abuf[k % PD]; the loads run PD - 1 tiles ahead
+        constexpr int PD = sizeof(T) == 8 ? VTM_MFMA_PD64 : VTM_MFMA_PD16;
+        typename M::AFrag abuf[PD][RT];
 #pragma unroll
-        for (int j = 0; j < RT; ++j)
-            if (j < nmy) abuf[0][j] = A0[int64_t(mts[j]) * KT * 64];
-        for (int kt = 0; kt < KT; kt += 2) {
+        for (int d = 0; d < PD - 1; ++d)
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int j = 0; j < RT; ++j)
+                if (j < nmy && d < KT) abuf[d][j] = A0[(int64_t(mts[j]) * KT + d) * 64];
+        for (int kt = 0; kt < KT; kt += PD) {
+#pragma unroll
+            for (int h = 0; h < PD; ++h) {
                 const int k = kt + h;
                 if (k < KT) {
-                    if (k + 1 < KT) {
+                    if (k + PD - 1 < KT) {
 #pragma unroll
                         for (int j = 0; j < RT; ++j)
-                            if (j < nmy) abuf[h ^ 1][j] = A0[(int64_t(mts[j]) * KT + k + 1) * 64];
+                            if (j < nmy) abuf[(h + PD - 1) % PD][j] = A0[(int64_t(mts[j]) * KT + k + PD - 1) * 64];
                     }
                     typename M::BFrag bf[NT];
 #pragma unroll
@@ -174,8 +194,12 @@ __global__ void __launch_bounds__(kBlock)
     using TV = typename M::TV;
     extern __shared__ char smem[];
     T* sb = reinterpret_cast<T*>(smem);
-    const int s = blockIdx.y;
-    const int r0 = blockIdx.x * rc;
+    // each XCD takes a contiguous range of (sub-circuit, column block): the column
+    // blocks of one sub-circuit read its inverse through one L2
+    const int nb = int(gridDim.x * gridDim.y), bl = int(blockIdx.x + gridDim.x * blockIdx.y);
+    const int u = VTM_MFMA_XCD ? xcd_block(bl, nb) : bl;
+    const int s = u / int(gridDim.x);
+    const int r0 = (u - s * int(gridDim.x)) * rc;
     const int w = min(rc, nrhs - r0);
     const int off = sub_off[s];
     const int ns = sub_off[s + 1] - off;
@@ -276,10 +300,16 @@ __global__ void __launch_bounds__(WAVES * 64)
     using TV = typename M::TV;
     extern __shared__ char smem[];
     T* sb = reinterpret_cast<T*>(smem);
-    // every other sweep takes the sub-circuits in reverse order (what the previous
-    // sweep read last is still in the memory-side cache)
-    const int s = VTM_MFMA_ALTERNATE && reverse ? int(gridDim.y) - 1 - int(blockIdx.y) : int(blockIdx.y);
-    const int r0 = blockIdx.x * rc;
+    // logical block u = (sub-circuit, column block): each XCD takes a contiguous range,
+    // so the column blocks of one sub-circuit (which read the same operator) and
+    // neighbouring sub-circuits share an L2; every other sweep walks each range
+    // backwards (what the previous sweep read last is still in the memory-side cache)
+    const int nb = int(gridDim.x * gridDim.y), b = int(blockIdx.x + gridDim.x * blockIdx.y);
+    const bool back = VTM_MFMA_ALTERNATE && reverse;
+    const int u = VTM_MFMA_XCD ? (back ? xcd_block_reversed(b, nb) : xcd_block(b, nb))
+                                  : (back ? nb - 1 - b : b);
+    const int s = u / int(gridDim.x);
+    const int r0 = (u - s * int(gridDim.x)) * rc;
     const int w = min(rc, nrhs - r0);
     const int p0 = port_off[s], q = port_off[s + 1] - p0;
     const int qp = tile_pad(q);
@@ -289,7 +319,8 @@ __global__ void __launch_bounds__(WAVES * 64)
     // in BF16 the extra registers cost more occupancy than the wait)
     const int lane = tid & 63, wave = tid >> 6;
     constexpr bool kPre = VTM_MFMA_PP_PREFETCH_H && sizeof(T) == 8;
-    const bool pre = kPre && qp / 16 <= WAVES * RT;
+    const bool one = qp / 16 <= WAVES * RT;   // one pass of row tiles covers the operator
+    const bool pre = kPre && one;
     TV hreg[kPre ? RT * NT * 4 : 1];
 #pragma unroll
     for (int j = 0; j < (kPre ? RT : 0); ++j)
@@ -301,20 +332,86 @@ __global__ void __launch_bounds__(WAVES * 64)
                 hreg[(j * NT + nt) * 4 + v] =
                     pre && row < q && n < w ? h[int64_t(p0 + row) * nrhs + r0 + n] : TV(0);
             }
-    for (int t = tid; t < qp * rc; t += WAVES * 64) {
-        const int k = t / rc, n = t - k * rc;
-        const TV v = (k < q && n < w) ? a_cur[int64_t(p0 + k) * nrhs + r0 + n] : TV(0);
-        M::stage(sb, qp, rc, k, n, v);
+    // twin port of each output row, loaded before the product (one pass of row tiles)
+    int twr[RT * 4];
+#pragma unroll
+    for (int j = 0; j < RT; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = (wave + j * WAVES) * 16 + M::out_row(lane, v);
+            twr[j * 4 + v] = one && row < q ? port_twin[p0 + row] : 0;
+        }
+    // BF16: h of this block staged in LDS beside the waves (its loads overlap theirs)
+    constexpr bool kHL = VTM_MFMA_PP_H_LDS && sizeof(T) == 2;
+    const int hst = rc + 16;
+    TV* hs = reinterpret_cast<TV*>(smem + tile_lds_bytes<T>(qp, rc));
+    const int sst = pp_stage_stride<T>(qp, rc);
+    // incident waves (and h) of rows k < qp: 16-byte loads when every row segment is
+    // 16-byte aligned (nrhs a multiple of the vector width; r0 and w are then too)
+    constexpr int VW = 16 / sizeof(TV);
+    struct alignas(16) Vec {
+        TV e[VW];
+    };
+    if (VTM_MFMA_PP_VEC && nrhs % VW == 0) {
+        // SU vectors per thread per round: all loads of a round are issued before its
+        // LDS stores, so a round costs one HBM round trip
+        constexpr int SU = 4;
+        const int rv = rc / VW, tot = qp * rv;
+        for (int t0 = tid; t0 < tot; t0 += SU * WAVES * 64) {
+            Vec v[SU], hv[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+#pragma unroll
+                for (int j = 0; j < VW; ++j) v[u].e[j] = hv[u].e[j] = TV(0);
+                const int t = t0 + u * WAVES * 64;
+                const int k = t / rv, n = (t - k * rv) * VW;
+                if (t < tot && k < q && n < w) {
+                    const int64_t o = int64_t(p0 + k) * nrhs + r0 + n;
+                    v[u] = *reinterpret_cast<const Vec*>(a_cur + o);
+                    if (kHL) hv[u] = *reinterpret_cast<const Vec*>(h + o);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int t = t0 + u * WAVES * 64;
+                const int k = t / rv, n = (t - k * rv) * VW;
+                if (t < tot) {
+#pragma unroll
+                    for (int j = 0; j < VW; ++j) M::stage(sb, qp, sst, k, n + j, v[u].e[j]);
+                    if (kHL) *reinterpret_cast<Vec*>(hs + k * hst + n) = hv[u];
+                }
+            }
+        }
+    } else {
+        for (int t = tid; t < qp * rc; t += WAVES * 64) {
+            const int k = t / rc, n = t - k * rc;
+            const bool in = k < q && n < w;
+            const int64_t o = int64_t(p0 + k) * nrhs + r0 + n;
+            M::stage(sb, qp, sst, k, n, in ? a_cur[o] : TV(0));
+            if (kHL) hs[k * hst + n] = in ? h[o] : TV(0);
+        }
     }
     __syncthreads();
-    tile_gemm<T, NT, RT, WAVES>(Mop + qmofs[s], qp, sb, sizeof(T) == 2 ? qp : rc, w,
-                                [&](int row, int n, TV v, int idx) {
+    // epilogue with the twin ports (and, FP64, h) already in registers: one pass of
+    // row tiles; idx indexes the register arrays statically once inlined
+    auto epi_reg = [&](int row, int n, TV v, int idx) __attribute__((always_inline)) {
+        if (row < q && n < w) {
+            const TV hv = kHL ? hs[row * hst + n] : kPre ? hreg[kPre ? idx : 0] : h[int64_t(p0 + row) * nrhs + r0 + n];
+            a_next[int64_t(twr[(idx / (NT * 4)) * 4 + (idx & 3)]) * nrhs + r0 + n] = v + hv;
+        }
+    };
+    // several passes of row tiles: twin ports and h read at the store
+    auto epi_mem = [&](int row, int n, TV v, int) __attribute__((always_inline)) {
         if (row < q && n < w) {
             const int p = p0 + row;
-            const TV hv = pre ? hreg[kPre ? idx : 0] : h[int64_t(p) * nrhs + r0 + n];
+            const TV hv = kHL ? hs[row * hst + n] : h[int64_t(p) * nrhs + r0 + n];
             a_next[int64_t(port_twin[p]) * nrhs + r0 + n] = v + hv;
         }
-    });
+    };
+    if (one)
+        tile_gemm<T, NT, RT, WAVES>(Mop + qmofs[s], qp, sb, sizeof(T) == 2 ? qp : sst, w, epi_reg);
+    else
+        tile_gemm<T, NT, RT, WAVES>(Mop + qmofs[s], qp, sb, sizeof(T) == 2 ? qp : sst, w, epi_mem);
 }
 
 // M_s = diag(beta) Kinv[P, P] diag(c) + diag(gamma) in A-tile order, from the
@@ -441,8 +538,8 @@ hipError_t launch_sweep_mfma_pp(int S, int max_ports, int nrhs, int variant, int
     const int qp = tile_pad(max_ports);
     int rc = rc_req > 0 ? ((rc_req + 15) / 16) * 16 : 64;
     if (rc > 64) rc = 64;
-    while (rc > 16 && tile_lds_bytes<T>(qp, rc) > lds_limit) rc -= 16;
-    const size_t lds = tile_lds_bytes<T>(qp, rc);
+    while (rc > 16 && pp_lds_bytes<T>(qp, rc) > lds_limit) rc -= 16;
+    const size_t lds = pp_lds_bytes<T>(qp, rc);
     if (lds > lds_limit) return hipErrorInvalidValue;
     if (rc > nrhs) rc = ((nrhs + 15) / 16) * 16 < rc ? ((nrhs + 15) / 16) * 16 : rc;
     const int nt = (rc + 15) / 16;

@@ -45,6 +45,36 @@ __host__ __device__ inline size_t tile_lds_bytes(int np, int rc) {
         return size_t(np) * rc * sizeof(T);         // [k][n]
 }
 
+// Batched port-to-port sweep: the BF16 path also stages h (FP32, row stride rc + 16,
+// so that the epilogue's four 16-lane row groups fall in disjoint LDS banks)
+#ifndef VTM_MFMA_PP_H_LDS
+#define VTM_MFMA_PP_H_LDS 1
+#endif
+// ... and the FP64 path pads the staged rows by this many doubles (bank spread of
+// the B-fragment reads, whose four 16-lane groups read four consecutive rows)
+#ifndef VTM_MFMA_PP_F64_PAD
+#define VTM_MFMA_PP_F64_PAD 0
+#endif
+
+// row stride of the staged incident waves of the batched port-to-port sweep
+template <typename T>
+__host__ __device__ inline int pp_stage_stride(int qp, int rc) {
+    if constexpr (sizeof(T) == 2)
+        return qp + 8;                         // [n][k]
+    else
+        return rc + VTM_MFMA_PP_F64_PAD;       // [k][n]
+}
+
+// LDS bytes of the batched port-to-port sweep: staged waves, then (BF16) h
+template <typename T>
+__host__ __device__ inline size_t pp_lds_bytes(int qp, int rc) {
+    if constexpr (sizeof(T) == 2)
+        return size_t(rc) * (qp + 8) * sizeof(T) +
+               (VTM_MFMA_PP_H_LDS ? size_t(qp) * (rc + 16) * sizeof(float) : 0);
+    else
+        return size_t(qp) * (rc + VTM_MFMA_PP_F64_PAD) * sizeof(T);
+}
+
 // (r, c) of the d-th stored element of a padded block
 template <typename T>
 __host__ __device__ inline void tile_rc(int np, int64_t d, int& r, int& c) {

@@ -356,6 +356,9 @@ def test_fp32_refinement_reaches_fp64_tolerance(torch, cfg, dims):
     assert rep.outer >= 1
     xs = oracle.direct_solve(w.A, w.b)
     assert np.abs(xh - xs).max() <= 2e-6 * np.abs(xs).max()
+    # a column count that is not a multiple of four (the staging's scalar path)
+    x6, rep6 = s.solve(to_dev(torch, w.b[:6]), w.tol)
+    assert oracle.relative_residual(w.A, w.b[:6], x6.cpu().numpy()).max() <= w.tol
 
 
 @pytest.mark.parametrize("form", ["port", "port_dense", "full"])

@@ -387,6 +387,11 @@ template hipError_t launch_sweep_pp<float, float>(int, int, const float*, const 
 #ifndef VTM_PPS_PRE
 #define VTM_PPS_PRE 1
 #endif
+// wavefronts per sub-circuit in the one-sub-circuit form (1: one wavefront, which
+// also streams its chunks; more: k_sweep_pps_split)
+#ifndef VTM_PPS_SPLIT
+#define VTM_PPS_SPLIT 8
+#endif
 // walk the units in reverse order on every other sweep
 #ifndef VTM_PPS_ALTERNATE
 #define VTM_PPS_ALTERNATE 1
@@ -540,6 +545,104 @@ __global__ void __launch_bounds__(64)
                            ca, tv, zv, pnode);
 }
 
+// One sub-circuit of up to 64 port nodes per workgroup of WV wavefronts: lane r of
+// every wavefront keeps row r, and wavefront v takes the diagonal chunks
+// v, v + WV, ...  All of a wavefront's operator loads are issued at once, before
+// the first barrier (WV times fewer per lane than with one wavefront, so the
+// sweep of few, large sub-circuits waits on fewer round trips); the partial
+// sums z_r of the wavefronts meet in LDS.
+template <typename TO, typename TV, int WV>
+__global__ void __launch_bounds__(64 * WV)
+    k_sweep_pps_split(const TO* __restrict__ Sp, const int64_t* __restrict__ sofs,
+                      const int32_t* __restrict__ pn_off, const int32_t* __restrict__ pn_pfirst,
+                      const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_twin,
+                      const TV* __restrict__ pc, const TV* __restrict__ pW, TV W, const TV* __restrict__ h,
+                      const TV* __restrict__ a_cur, TV* __restrict__ a_next, int reverse) {
+    constexpr int CH = VTM_PPS_CH, NCH = 64 / CH, LCH = NCH / WV;
+    static_assert(WV >= 2 && NCH % WV == 0 && CH % 2 == 0, "chunks must split evenly over the wavefronts");
+    __shared__ TV ca[64], tv[128], zp[WV][64];
+    __shared__ int32_t pnode[64];
+    const int s = VTM_PPS_ALTERNATE && reverse ? xcd_block_reversed(blockIdx.x, gridDim.x)
+                                               : xcd_block(blockIdx.x, gridDim.x);
+    const int tid = threadIdx.x, r = tid & 63, wv = tid >> 6;
+    const int n0 = pn_off[s], k = pn_off[s + 1] - n0;
+    const int p0 = port_off[s], q = port_off[s + 1] - p0;
+    const TO* blk = Sp + sofs[s];
+    // this wavefront's diagonals d = ci CH + j, ci = li WV + wv (pairs: one 16-byte
+    // FP64 load gives S(r, r + 2m) and S(r, r + 2m + 1))
+    using V2 = typename std::conditional<sizeof(TO) == 8, double2, float2>::type;
+    TO buf[LCH * CH];
+#pragma unroll
+    for (int li = 0; li < LCH; ++li) {
+        const int ci = li * WV + wv;
+        if (ci * CH < k) {
+#pragma unroll
+            for (int j = 0; j < CH / 2; ++j) {
+                const int m = ci * (CH / 2) + j;
+                const V2 v2 = *reinterpret_cast<const V2*>(blk + ((r + 2 * m < k) ? pair_start(k, m) + 2 * r : 0));
+                buf[li * CH + 2 * j] = v2.x;
+                buf[li * CH + 2 * j + 1] = v2.y;
+            }
+        }
+    }
+    // wavefront 0: the ports (lane r = port p0 + r) and each node's port range
+    TV c = TV(0), a = TV(0), hp = TV(0), w = W;
+    int tw = 0, f0 = 0, f1 = 0;
+    const bool has_port = wv == 0 && r < q;
+    if (has_port) {
+        const int p = p0 + r;
+        c = pc[p];
+        a = a_cur[p];
+        hp = h[p];
+        tw = port_twin[p];
+        if (pW) w = pW[p];
+        ca[r] = c * a;
+    }
+    if (wv == 0 && r < k) {
+        f0 = pn_pfirst[n0 + r] - p0;
+        f1 = pn_pfirst[n0 + r + 1] - p0;
+    }
+    if (tid < 128) tv[tid] = TV(0);
+    __syncthreads();
+    // t_n = sum of c_p a_p over the ports at node n, in port order
+    if (wv == 0 && r < k) {
+        TV acc = TV(0);
+        for (int i = f0; i < f1; ++i) {
+            acc += ca[i];
+            pnode[i] = r;
+        }
+        tv[r] = acc;
+    }
+    __syncthreads();
+    // partial z_r over this wavefront's diagonals: S(r, r + d) t_{r+d}, and for
+    // d > 0 S(r - d, r) t_{r-d}, formed by lane r - d and shuffled up
+    const TV tr = tv[r];
+    TV acc = TV(0);
+#pragma unroll
+    for (int li = 0; li < LCH; ++li) {
+        const int ci = li * WV + wv;
+        if (ci * CH < k) {
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int d = ci * CH + j;
+                const TV sv = TV(buf[li * CH + j]);
+                acc += sv * tv[r + d];
+                const TV up = __shfl(sv * tr, r - d);
+                acc += (d > 0 && r >= d) ? up : TV(0);
+            }
+        }
+    }
+    zp[wv][r] = acc;
+    __syncthreads();
+    if (has_port) {
+        const int n = pnode[r];
+        TV z = TV(0);
+#pragma unroll
+        for (int v = 0; v < WV; ++v) z += zp[v][n];
+        a_next[tw] = TV(2) * w * c * z + (TV(1) - TV(2) * c) * a + hp;
+    }
+}
+
 }  // namespace
 
 template <typename TO>
@@ -571,6 +674,12 @@ hipError_t launch_sweep_pps(int S, int max_npn, int max_ports, const TO* Sp, con
     if (max_npn <= 32 && max_ports <= 32)
         return launch_pps<TO, TV, true>(S, Sp, sofs, pn_off, pn_pfirst, port_off, port_twin, pc, pW, W, h, a_cur,
                                         a_next, reverse, st);
+    if (VTM_PPS_SPLIT > 1) {
+        hipLaunchKernelGGL((k_sweep_pps_split<TO, TV, (VTM_PPS_SPLIT > 1 ? VTM_PPS_SPLIT : 2)>), dim3(S),
+                           dim3(64 * VTM_PPS_SPLIT), 0, st, Sp, sofs, pn_off, pn_pfirst, port_off, port_twin, pc, pW,
+                           W, h, a_cur, a_next, reverse);
+        return hipGetLastError();
+    }
     return launch_pps<TO, TV, false>(S, Sp, sofs, pn_off, pn_pfirst, port_off, port_twin, pc, pW, W, h, a_cur,
                                      a_next, reverse, st);
 }

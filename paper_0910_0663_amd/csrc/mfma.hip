@@ -314,9 +314,9 @@ __global__ void __launch_bounds__(WAVES * 64)
     const int p0 = port_off[s], q = port_off[s + 1] - p0;
     const int qp = tile_pad(q);
     const int tid = threadIdx.x;
-    // FP64: h of the outputs this lane will produce, loaded before the product so that
-    // the epilogue does not wait on it (when one pass of row tiles covers the operator;
-    // in BF16 the extra registers cost more occupancy than the wait)
+    // FP64: h of the outputs this lane will produce, loaded into registers before the
+    // product so that the epilogue does not wait on it (when one pass of row tiles
+    // covers the operator); BF16 stages h in LDS instead (registers cost occupancy)
     const int lane = tid & 63, wave = tid >> 6;
     constexpr bool kPre = VTM_MFMA_PP_PREFETCH_H && sizeof(T) == 8;
     const bool one = qp / 16 <= WAVES * RT;   // one pass of row tiles covers the operator
@@ -360,25 +360,25 @@ __global__ void __launch_bounds__(WAVES * 64)
         for (int t0 = tid; t0 < tot; t0 += SU * WAVES * 64) {
             Vec v[SU], hv[SU];
 #pragma unroll
-            for (int u = 0; u < SU; ++u) {
+            for (int i = 0; i < SU; ++i) {
 #pragma unroll
-                for (int j = 0; j < VW; ++j) v[u].e[j] = hv[u].e[j] = TV(0);
-                const int t = t0 + u * WAVES * 64;
+                for (int j = 0; j < VW; ++j) v[i].e[j] = hv[i].e[j] = TV(0);
+                const int t = t0 + i * WAVES * 64;
                 const int k = t / rv, n = (t - k * rv) * VW;
                 if (t < tot && k < q && n < w) {
                     const int64_t o = int64_t(p0 + k) * nrhs + r0 + n;
-                    v[u] = *reinterpret_cast<const Vec*>(a_cur + o);
-                    if (kHL) hv[u] = *reinterpret_cast<const Vec*>(h + o);
+                    v[i] = *reinterpret_cast<const Vec*>(a_cur + o);
+                    if (kHL) hv[i] = *reinterpret_cast<const Vec*>(h + o);
                 }
             }
 #pragma unroll
-            for (int u = 0; u < SU; ++u) {
-                const int t = t0 + u * WAVES * 64;
+            for (int i = 0; i < SU; ++i) {
+                const int t = t0 + i * WAVES * 64;
                 const int k = t / rv, n = (t - k * rv) * VW;
                 if (t < tot) {
 #pragma unroll
-                    for (int j = 0; j < VW; ++j) M::stage(sb, qp, sst, k, n + j, v[u].e[j]);
-                    if (kHL) *reinterpret_cast<Vec*>(hs + k * hst + n) = hv[u];
+                    for (int j = 0; j < VW; ++j) M::stage(sb, qp, sst, k, n + j, v[i].e[j]);
+                    if (kHL) *reinterpret_cast<Vec*>(hs + k * hst + n) = hv[i];
                 }
             }
         }

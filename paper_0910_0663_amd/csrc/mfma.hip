@@ -33,6 +33,13 @@
 #ifndef VTM_MFMA_PD16
 #define VTM_MFMA_PD16 2
 #endif
+// full batched sweep: staging loads issued in rounds (aligned right-hand sides)
+#ifndef VTM_MFMA_FULL_ROUNDS
+#define VTM_MFMA_FULL_ROUNDS 1
+#endif
+#ifndef VTM_MFMA_FULL_SU
+#define VTM_MFMA_FULL_SU 2
+#endif
 // batched sweeps: XCD-contiguous ranges of (sub-circuit, column block)
 #ifndef VTM_MFMA_XCD
 #define VTM_MFMA_XCD 1
@@ -229,6 +236,54 @@ __global__ void __launch_bounds__(kBlock)
     __syncthreads();
     const bool vec = (nrhs % V) == 0;
     const int rv = rc / V;
+    if (VTM_MFMA_FULL_ROUNDS && vec) {
+        // SU items per thread per round; each item's b load is waited on only after
+        // its ports' loads are issued (b is added last), so a round costs about one
+        // HBM round trip
+        constexpr int SU = VTM_MFMA_FULL_SU;
+        const int tot = np * rv;
+        for (int t0 = tid; t0 < tot; t0 += SU * kBlock) {
+            TB bv[SU][V];
+            TV acc[SU][V];
+#pragma unroll
+            for (int i = 0; i < SU; ++i) {
+                const int t = t0 + i * kBlock;
+                const int k = t / rv, n0 = (t - k * rv) * V;
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    bv[i][j] = TB(0);
+                    acc[i][j] = TV(0);
+                }
+                if (t < tot && k < ns && n0 < w)
+                    *reinterpret_cast<uint4*>(bv[i]) =
+                        *reinterpret_cast<const uint4*>(b + int64_t(off + k) * nrhs + r0 + n0);
+            }
+#pragma unroll
+            for (int i = 0; i < SU; ++i) {
+                const int t = t0 + i * kBlock;
+                const int k = t / rv, n0 = (t - k * rv) * V;
+                if (t < tot && k < ns && n0 < w) {
+                    const int cnt = pcount[k];
+                    for (int q = 0; q < cnt; ++q) {
+                        const int p = p0 + pfirst[k] + q;
+                        const TV c = pc[p];
+                        const TV* ap = a_cur + int64_t(p) * nrhs + r0 + n0;
+#pragma unroll
+                        for (int j = 0; j < V; ++j) acc[i][j] += c * ap[j];
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < SU; ++i) {
+                const int t = t0 + i * kBlock;
+                const int k = t / rv, n0 = (t - k * rv) * V;
+                if (t < tot) {
+#pragma unroll
+                    for (int j = 0; j < V; ++j) M::stage(sb, np, rc, k, n0 + j, TV(bv[i][j]) + acc[i][j]);
+                }
+            }
+        }
+    } else
     for (int t = tid; t < np * rv; t += kBlock) {
         const int k = t / rv, n0 = (t - k * rv) * V;
         TV v[V];
@@ -269,6 +324,44 @@ __global__ void __launch_bounds__(kBlock)
 
     // 3. outgoing waves, read back x of the port nodes (written by this workgroup), 4 columns at a time
     const int w4 = (w + 3) / 4;
+    if (VTM_MFMA_FULL_ROUNDS && nrhs % 4 == 0) {
+        // whole 4-column chunks (w is a multiple of 4), two per thread per round, all
+        // loads of a round issued before its stores
+        struct alignas(16) C4 {
+            TV e[4];
+        };
+        constexpr int SU = 2;
+        const int tot = nps * w4;
+        for (int t0 = tid; t0 < tot; t0 += SU * kBlock) {
+            C4 xv[SU], av[SU];
+            TV be[SU], ga[SU];
+            int tw[SU];
+#pragma unroll
+            for (int i = 0; i < SU; ++i) {
+                const int t = t0 + i * kBlock;
+                if (t < tot) {
+                    const int q = t / w4, n0 = (t - q * w4) * 4;
+                    const int p = p0 + q;
+                    be[i] = pbeta[p];
+                    ga[i] = pgamma[p];
+                    tw[i] = port_twin[p];
+                    xv[i] = *reinterpret_cast<const C4*>(x + int64_t(off + pnode[q]) * nrhs + r0 + n0);
+                    av[i] = *reinterpret_cast<const C4*>(a_cur + int64_t(p) * nrhs + r0 + n0);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < SU; ++i) {
+                const int t = t0 + i * kBlock;
+                if (t < tot) {
+                    const int q = t / w4, n0 = (t - q * w4) * 4;
+                    C4 o;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) o.e[j] = be[i] * xv[i].e[j] + ga[i] * av[i].e[j];
+                    *reinterpret_cast<C4*>(a_next + int64_t(tw[i]) * nrhs + r0 + n0) = o;
+                }
+            }
+        }
+    } else
     for (int t = tid; t < nps * w4; t += kBlock) {
         const int q = t / w4, n0 = (t - q * w4) * 4;
         const int p = p0 + q;

@@ -26,6 +26,53 @@ __global__ void k_scatter(int n, int nrhs, const int32_t* __restrict__ iperm, co
     dst[t] = src[int64_t(iperm[j]) * nrhs + r];
 }
 
+// The same two renumberings for many right-hand sides, as transposes through an
+// LDS tile of 64 rows x 64 right-hand sides: each side of the tile is read or
+// written along its contiguous direction (the caller's [nrhs][n] rows, the
+// internal [n][nrhs] rows), where the one-element kernels above touch a
+// different cache line per lane on one side.
+constexpr int kTile = 64;
+
+__global__ void __launch_bounds__(kBlock)
+    k_gather_tiled(int n, int nrhs, const int32_t* __restrict__ perm, const double* __restrict__ src,
+                   double* __restrict__ dst) {
+    __shared__ double tile[kTile][kTile + 1];
+    const int i0 = blockIdx.x * kTile, r0 = blockIdx.y * kTile;
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    const int i = i0 + lx;
+    const int pi = i < n ? perm[i] : 0;
+#pragma unroll
+    for (int rr = ly; rr < kTile; rr += kBlock / 64) {
+        const int r = r0 + rr;
+        tile[rr][lx] = (i < n && r < nrhs) ? src[int64_t(r) * n + pi] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ii = ly; ii < kTile; ii += kBlock / 64) {
+        const int i2 = i0 + ii, r = r0 + lx;
+        if (i2 < n && r < nrhs) dst[int64_t(i2) * nrhs + r] = tile[lx][ii];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_scatter_tiled(int n, int nrhs, const int32_t* __restrict__ iperm, const double* __restrict__ src,
+                    double* __restrict__ dst) {
+    __shared__ double tile[kTile][kTile + 1];
+    const int j0 = blockIdx.x * kTile, r0 = blockIdx.y * kTile;
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+#pragma unroll
+    for (int jj = ly; jj < kTile; jj += kBlock / 64) {
+        const int j = j0 + jj, r = r0 + lx;
+        tile[jj][lx] = (j < n && r < nrhs) ? src[int64_t(iperm[j]) * nrhs + r] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = ly; rr < kTile; rr += kBlock / 64) {
+        const int r = r0 + rr, j = j0 + lx;
+        if (j < n && r < nrhs) dst[int64_t(r) * n + j] = tile[lx][rr];
+    }
+}
+
 // Vertex tearing: plan row r takes w[r] times its original node src[r]'s entry
 // (an interfacial node's source is split between its twins); the input is a
 // caller's [nrhs][n_in] vector or an [n_in][nrhs] one.
@@ -143,8 +190,18 @@ template hipError_t launch_restrict<double>(int, int, const int32_t*, const int3
 template hipError_t launch_restrict<float>(int, int, const int32_t*, const int32_t*, const float*, double*, bool,
                                            hipStream_t);
 
+// right-hand sides from which the renumberings go through LDS tiles
+#ifndef VTM_TILED_RHS
+#define VTM_TILED_RHS 16
+#endif
+
 hipError_t launch_gather(int n, int nrhs, const int32_t* perm, const double* src, double* dst,
                          hipStream_t st) {
+    if (nrhs >= VTM_TILED_RHS && n > 0) {
+        hipLaunchKernelGGL(k_gather_tiled, dim3(unsigned((n + kTile - 1) / kTile), unsigned((nrhs + kTile - 1) / kTile)),
+                           dim3(kBlock), 0, st, n, nrhs, perm, src, dst);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_gather, dim3(blocks_for(int64_t(n) * nrhs)), dim3(kBlock), 0, st, n, nrhs, perm, src,
                        dst);
     return hipGetLastError();
@@ -152,6 +209,11 @@ hipError_t launch_gather(int n, int nrhs, const int32_t* perm, const double* src
 
 hipError_t launch_scatter(int n, int nrhs, const int32_t* iperm, const double* src, double* dst,
                           hipStream_t st) {
+    if (nrhs >= VTM_TILED_RHS && n > 0) {
+        hipLaunchKernelGGL(k_scatter_tiled, dim3(unsigned((n + kTile - 1) / kTile), unsigned((nrhs + kTile - 1) / kTile)),
+                           dim3(kBlock), 0, st, n, nrhs, iperm, src, dst);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(int64_t(n) * nrhs)), dim3(kBlock), 0, st, n, nrhs, iperm,
                        src, dst);
     return hipGetLastError();

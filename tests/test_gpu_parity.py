@@ -456,6 +456,16 @@ def test_batched_fp64_mfma_iterates_match_oracle(torch):
     assert_close(x.cpu().numpy(), oracle_iterates(w, [rep.sweeps])[rep.sweeps])
 
 
+def test_batched_ragged_tiles_match_oracle(torch):
+    """A node count and a column count that are not multiples of the 64 x 64 tiles
+    of the renumbering transposes (8,100 nodes, 17 right-hand sides): the iterates
+    still equal the oracle's."""
+    w = workloads.make(4, dims=(90, 90), nrhs=17)
+    assert w.A.shape[0] % 64 != 0
+    ref = oracle_iterates(w, [4])
+    assert_close(gpu_iterate(torch, w, 4, nrhs_max=17), ref[4])
+
+
 def test_batched_bf16_refinement_reaches_fp64_tolerance(torch):
     """BF16 inverses x BF16 right-hand sides on MFMA with FP32 accumulation,
     inside FP64 refinement: every column reaches relative residual 1e-8

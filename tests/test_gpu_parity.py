@@ -410,6 +410,42 @@ def test_full_size_config2_residual(torch):
     assert abs(rel - rep.relres_max) <= 1e-3 * rel
 
 
+def test_full_size_config4_bf16_refinement_residual(torch):
+    """The batched bench workload at full size (1024^2 nodes, 4,290 uneven
+    sub-circuits, 64 right-hand sides): BF16 sweeps on the matrix cores inside
+    FP64 refinement give every column relative residual <= 1e-8, recomputed on the
+    host from the untorn A."""
+    w = workloads.make(4)
+    s = vtm().Solver(w.A, w.part, w.Z, precision="bf16_refine", nrhs_max=w.nrhs)
+    x, rep = s.solve(to_dev(torch, w.b), w.tol)
+    print(f"full-size bf16: sweeps {rep.sweeps} outer {rep.outer} relres {rep.relres_max:.3e}", flush=True)
+    rel = oracle.relative_residual(w.A, w.b, x.cpu().numpy())
+    assert rel.shape == (64,) and rel.max() <= w.tol
+    assert rep.outer >= 2
+
+
+def test_full_size_config5_gradient_matches_oracle(torch):
+    """The gradient bench workload at full size (512^2 grid, 4,096 probes, 523,264
+    branches; FP32 sweeps with FP64 refinement to 1e-8): dL/dg of every branch
+    against the oracle's adjoint formula with direct solves (whose formula a CPU
+    test pins by central differences).  The bound allows the solves' own error
+    (kappa(A) times the tolerance)."""
+    from paper_0910_0663_amd import Circuit, VTMSolve
+    w = workloads.make(5)
+    circ = Circuit(w.n, w.edges, w.ground, w.part, w.Z, tol=w.tol, precision="fp32_refine")
+    g = torch.tensor(w.g, dtype=torch.float64, device="cuda", requires_grad=True)
+    b = torch.tensor(w.b[0], dtype=torch.float64, device="cuda")
+    x = VTMSolve.apply(b, g, circ)
+    probes = torch.as_tensor(w.probes, device="cuda")
+    (x[probes] ** 2).sum().backward()
+    xs = oracle.direct_solve(w.A, w.b)
+    dLdx = np.zeros_like(xs)
+    dLdx[:, w.probes] = 2 * xs[:, w.probes]
+    gref = oracle.branch_gradient(w.edges, xs, oracle.direct_adjoint(w.A, dLdx))
+    assert g.grad.shape[0] == len(w.edges) == 523264
+    assert np.abs(g.grad.cpu().numpy() - gref).max() <= 1e-4 * np.abs(gref).max()
+
+
 @pytest.mark.parametrize("cfg,centres,R,k,kw", [
     # the bench workload: corner, edge and interior sub-circuits; one full sweep,
     # port-to-port sweeps on the packed symmetric operator, one full sweep

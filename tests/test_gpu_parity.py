@@ -424,6 +424,18 @@ def test_full_size_config4_bf16_refinement_residual(torch):
     assert rep.outer >= 2
 
 
+def test_full_size_config3_fp32_refinement_residual(torch):
+    """The unsymmetric bench workload at full size (128^3 nodes with 124,846
+    controlled sources, 4,096 sub-circuits of 8^3): FP32 sweeps inside FP64
+    refinement reach relative residual 1e-8, recomputed on the host."""
+    w = workloads.make(3)
+    s = vtm().Solver(w.A, w.part, w.Z, precision="fp32_refine")
+    x, rep = s.solve(to_dev(torch, w.b), w.tol)
+    print(f"full-size fp32 3-D: sweeps {rep.sweeps} outer {rep.outer} relres {rep.relres_max:.3e}", flush=True)
+    assert oracle.relative_residual(w.A, w.b, x.cpu().numpy()).max() <= w.tol
+    assert rep.outer >= 1
+
+
 def test_full_size_config5_gradient_matches_oracle(torch):
     """The gradient bench workload at full size (512^2 grid, 4,096 probes, 523,264
     branches; FP32 sweeps with FP64 refinement to 1e-8): dL/dg of every branch

@@ -3,14 +3,22 @@
 // formed in a fixed order, so results are bitwise reproducible.
 #include "kernels.hpp"
 
+// residuals of whole-wavefront right-hand-side blocks with wave-uniform rows
+#ifndef VTM_RESID_UNIFORM
+#define VTM_RESID_UNIFORM 1
+#endif
+
 namespace vtm {
 
 namespace {
 
 constexpr int kBlock = 256;
 
-// thread (row slot, rhs): the block's threads cover per = 256 / nrhs rows at a time
-template <typename TX>
+// thread (row slot, rhs): the block's threads cover per = 256 / nrhs rows at a time.
+// UNI (nrhs a multiple of 64): each wavefront holds whole rows of one row slot, so
+// the row index is wave-uniform and the row's index and value loads are scalar
+// loads, issued once per wavefront instead of once per lane.
+template <typename TX, bool UNI>
 __global__ void __launch_bounds__(kBlock)
     k_resid(int n, int nrhs, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
             const double* __restrict__ val, const double* __restrict__ b, const TX* __restrict__ x,
@@ -22,7 +30,9 @@ __global__ void __launch_bounds__(kBlock)
     double rr = 0.0, bb = 0.0;
     if (tid < used) {
         const int rhs = tid % nrhs, rl = tid / nrhs;
-        for (int64_t i = int64_t(blockIdx.x) * per + rl; i < n; i += int64_t(gridDim.x) * per) {
+        int i0 = blockIdx.x * per + rl;
+        if (UNI) i0 = __builtin_amdgcn_readfirstlane(i0);
+        for (int64_t i = i0; i < n; i += int64_t(gridDim.x) * per) {
             const double bv = b[i * nrhs + rhs];
             double acc = bv;
             for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc -= val[k] * double(x[int64_t(col[k]) * nrhs + rhs]);
@@ -69,7 +79,7 @@ __global__ void __launch_bounds__(kBlock)
 // x_j(p) likewise from the twin port q, and the outgoing wave o_p of port p is
 // a_next[twin(p)].  Waves are [ports][nrhs]; thread (node slot, rhs) as in
 // k_resid, partial sums per column in the same layout.
-template <typename TV>
+template <typename TV, bool UNI>
 __global__ void __launch_bounds__(kBlock)
     k_port_resid(int64_t nn, int nrhs, const int32_t* __restrict__ pn_pfirst, const int32_t* __restrict__ twin,
                  const TV* __restrict__ a_cur, const TV* __restrict__ a_next, const double* __restrict__ c,
@@ -82,7 +92,9 @@ __global__ void __launch_bounds__(kBlock)
     double rr = 0.0;
     if (tid < used) {
         const int rhs = tid % nrhs, rl = tid / nrhs;
-        for (int64_t n = int64_t(blockIdx.x) * per + rl; n < nn; n += int64_t(gridDim.x) * per) {
+        int n0 = blockIdx.x * per + rl;
+        if (UNI) n0 = __builtin_amdgcn_readfirstlane(n0);  // as in k_resid
+        for (int64_t n = n0; n < nn; n += int64_t(gridDim.x) * per) {
             const int p0 = pn_pfirst[n], p1 = pn_pfirst[n + 1];
             const double xn =
                 (double(a_next[int64_t(twin[p0]) * nrhs + rhs]) - gamma[p0] * double(a_cur[int64_t(p0) * nrhs + rhs])) /
@@ -117,8 +129,12 @@ hipError_t launch_port_residual(int64_t n_port_nodes, int nrhs, const int32_t* p
                                 hipStream_t st) {
     if (nrhs < 1 || nrhs > kBlock) return hipErrorInvalidValue;
     const int blocks = resid_blocks(n_port_nodes, nrhs);
-    hipLaunchKernelGGL(k_port_resid<TV>, dim3(blocks), dim3(kBlock), 0, st, n_port_nodes, nrhs, pn_pfirst, twin,
-                       a_cur, a_next, c, beta, gamma, gd, g, partial);
+    if (VTM_RESID_UNIFORM && nrhs % 64 == 0)
+        hipLaunchKernelGGL((k_port_resid<TV, true>), dim3(blocks), dim3(kBlock), 0, st, n_port_nodes, nrhs, pn_pfirst,
+                           twin, a_cur, a_next, c, beta, gamma, gd, g, partial);
+    else
+        hipLaunchKernelGGL((k_port_resid<TV, false>), dim3(blocks), dim3(kBlock), 0, st, n_port_nodes, nrhs,
+                           pn_pfirst, twin, a_cur, a_next, c, beta, gamma, gd, g, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_norms_final, dim3(2 * nrhs), dim3(kBlock), 0, st, blocks, nrhs, partial, norms);
@@ -138,8 +154,12 @@ hipError_t launch_residual(int n, int nrhs, const int32_t* rowptr, const int32_t
                            hipStream_t st) {
     if (nrhs < 1 || nrhs > kBlock) return hipErrorInvalidValue;
     const int blocks = resid_blocks(n, nrhs);
-    hipLaunchKernelGGL(k_resid<TX>, dim3(blocks), dim3(kBlock), 0, st, n, nrhs, rowptr, col, val, b, x, r_out,
-                       partial);
+    if (VTM_RESID_UNIFORM && nrhs % 64 == 0)
+        hipLaunchKernelGGL((k_resid<TX, true>), dim3(blocks), dim3(kBlock), 0, st, n, nrhs, rowptr, col, val, b, x,
+                           r_out, partial);
+    else
+        hipLaunchKernelGGL((k_resid<TX, false>), dim3(blocks), dim3(kBlock), 0, st, n, nrhs, rowptr, col, val, b, x,
+                           r_out, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_norms_final, dim3(2 * nrhs), dim3(kBlock), 0, st, blocks, nrhs, partial, norms);

@@ -107,6 +107,19 @@ def test_port_to_port_iterates_match_oracle(torch, cfg, kw, prec):
             assert_close(gpu_iterate(torch, w, k, check_every=k, local_form=form), ref[k])
 
 
+@pytest.mark.parametrize("dims,block", [((72, 72), (9, 9)), ((96, 96), (12, 12)), ((100, 100), (16, 16))])
+def test_packed_split_sweep_iterates_match_oracle(torch, dims, block):
+    """Sub-circuits with 32 to 64 port nodes (9x9, 12x12, 16x16 blocks, the last
+    grid with ragged edge blocks) take the packed sweep with one wavefront per
+    diagonal chunk; some chunks lie past a sub-circuit's last diagonal.  The
+    iterates equal the oracle's."""
+    w = workloads.make(2, dims=dims, block=block)
+    ks = [2, 9]
+    ref = oracle_iterates(w, ks)
+    for k in ks:
+        assert_close(gpu_iterate(torch, w, k, check_every=k, local_form="port"), ref[k])
+
+
 def test_port_to_port_and_full_forms_agree(torch):
     """The local forms (full inverse, packed symmetric port-node operator, dense
     port operator) reach the tolerance after the same sweeps and agree."""

@@ -1292,8 +1292,8 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
     // batched form: port-to-port operators in tile order, built from the FP64 inverses in scratch
     const int qpad = vtm::tile_pad(P.max_ports);
     h->ppb = o.local_form >= 1 && h->tiles && P.nports > 0 &&
-             (o.precision == VTM_FP64 ? vtm::pp_lds_bytes<double>(qpad, 16)
-                                      : vtm::pp_lds_bytes<__bf16>(qpad, 16)) <= h->lds_limit;
+             (o.precision == VTM_FP64 ? vtm::pp_lds_bytes<double>(qpad, 16, false)
+                                      : vtm::pp_lds_bytes<__bf16>(qpad, 16, false)) <= h->lds_limit;
     if (h->ppb) {
         VTM_HIP(h->qmofs.upload(P.qmofs, s));
         const int64_t nq = P.qmofs[P.S];

@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(kBlock)
 // block of incident waves is staged in LDS as the B operand (BF16 for the BF16
 // path, FP32 accumulate).  WAVES wavefronts per workgroup (the operators are
 // small: 64 ports make four 16-row tiles).
-template <typename T, int NT, int RT, int WAVES>
+template <typename T, int NT, int RT, int WAVES, bool HL>
 __global__ void __launch_bounds__(WAVES * 64)
     k_sweep_mfma_pp(const T* __restrict__ Mop, const int64_t* __restrict__ qmofs,
                     const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_twin,
@@ -434,8 +434,9 @@ __global__ void __launch_bounds__(WAVES * 64)
             const int row = (wave + j * WAVES) * 16 + M::out_row(lane, v);
             twr[j * 4 + v] = one && row < q ? port_twin[p0 + row] : 0;
         }
-    // BF16: h of this block staged in LDS beside the waves (its loads overlap theirs)
-    constexpr bool kHL = VTM_MFMA_PP_H_LDS && sizeof(T) == 2;
+    // BF16 (HL): h of this block staged in LDS beside the waves (its loads overlap
+    // theirs); the launch drops HL when there is no room for it (very large operators)
+    constexpr bool hl = HL && VTM_MFMA_PP_H_LDS && sizeof(T) == 2;
     const int hst = rc + 16;
     TV* hs = reinterpret_cast<TV*>(smem + tile_lds_bytes<T>(qp, rc));
     const int sst = pp_stage_stride<T>(qp, rc);
@@ -461,7 +462,7 @@ __global__ void __launch_bounds__(WAVES * 64)
                 if (t < tot && k < q && n < w) {
                     const int64_t o = int64_t(p0 + k) * nrhs + r0 + n;
                     v[i] = *reinterpret_cast<const Vec*>(a_cur + o);
-                    if (kHL) hv[i] = *reinterpret_cast<const Vec*>(h + o);
+                    if (hl) hv[i] = *reinterpret_cast<const Vec*>(h + o);
                 }
             }
 #pragma unroll
@@ -471,7 +472,7 @@ __global__ void __launch_bounds__(WAVES * 64)
                 if (t < tot) {
 #pragma unroll
                     for (int j = 0; j < VW; ++j) M::stage(sb, qp, sst, k, n + j, v[i].e[j]);
-                    if (kHL) *reinterpret_cast<Vec*>(hs + k * hst + n) = hv[i];
+                    if (hl) *reinterpret_cast<Vec*>(hs + k * hst + n) = hv[i];
                 }
             }
         }
@@ -481,7 +482,7 @@ __global__ void __launch_bounds__(WAVES * 64)
             const bool in = k < q && n < w;
             const int64_t o = int64_t(p0 + k) * nrhs + r0 + n;
             M::stage(sb, qp, sst, k, n, in ? a_cur[o] : TV(0));
-            if (kHL) hs[k * hst + n] = in ? h[o] : TV(0);
+            if (hl) hs[k * hst + n] = in ? h[o] : TV(0);
         }
     }
     __syncthreads();
@@ -489,7 +490,7 @@ __global__ void __launch_bounds__(WAVES * 64)
     // row tiles; idx indexes the register arrays statically once inlined
     auto epi_reg = [&](int row, int n, TV v, int idx) __attribute__((always_inline)) {
         if (row < q && n < w) {
-            const TV hv = kHL ? hs[row * hst + n] : kPre ? hreg[kPre ? idx : 0] : h[int64_t(p0 + row) * nrhs + r0 + n];
+            const TV hv = hl ? hs[row * hst + n] : kPre ? hreg[kPre ? idx : 0] : h[int64_t(p0 + row) * nrhs + r0 + n];
             a_next[int64_t(twr[(idx / (NT * 4)) * 4 + (idx & 3)]) * nrhs + r0 + n] = v + hv;
         }
     };
@@ -497,7 +498,7 @@ __global__ void __launch_bounds__(WAVES * 64)
     auto epi_mem = [&](int row, int n, TV v, int) __attribute__((always_inline)) {
         if (row < q && n < w) {
             const int p = p0 + row;
-            const TV hv = kHL ? hs[row * hst + n] : h[int64_t(p) * nrhs + r0 + n];
+            const TV hv = hl ? hs[row * hst + n] : h[int64_t(p) * nrhs + r0 + n];
             a_next[int64_t(port_twin[p]) * nrhs + r0 + n] = v + hv;
         }
     };
@@ -542,11 +543,11 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
-template <typename T, int NT, int RT, int WAVES>
-hipError_t launch_pp_t(int S, int nrhs, int rc, size_t lds, const T* Mop, const int64_t* qmofs,
+template <typename T, int NT, int RT, int WAVES, bool HL>
+hipError_t launch_pp_k(int S, int nrhs, int rc, size_t lds, const T* Mop, const int64_t* qmofs,
                        const int32_t* port_off, const int32_t* port_twin, const typename Mma<T>::TV* h,
                        const typename Mma<T>::TV* a_cur, typename Mma<T>::TV* a_next, int reverse, hipStream_t st) {
-    auto kern = k_sweep_mfma_pp<T, NT, RT, WAVES>;
+    auto kern = k_sweep_mfma_pp<T, NT, RT, WAVES, HL>;
     static size_t lds_set = 65536;
     if (lds > lds_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -558,6 +559,21 @@ hipError_t launch_pp_t(int S, int nrhs, int rc, size_t lds, const T* Mop, const 
     hipLaunchKernelGGL(kern, dim3(ny, S), dim3(WAVES * 64), lds, st, Mop, qmofs, port_off, port_twin, h, a_cur,
                        a_next, nrhs, rc, reverse);
     return hipGetLastError();
+}
+
+// h in LDS (BF16) is a compile-time choice: as a run-time one the epilogue read h
+// through generic (flat) addresses
+template <typename T, int NT, int RT, int WAVES>
+hipError_t launch_pp_t(int S, int nrhs, int rc, size_t lds, const T* Mop, const int64_t* qmofs,
+                       const int32_t* port_off, const int32_t* port_twin, const typename Mma<T>::TV* h,
+                       const typename Mma<T>::TV* a_cur, typename Mma<T>::TV* a_next, int reverse, int h_lds,
+                       hipStream_t st) {
+    if constexpr (sizeof(T) == 2)
+        if (h_lds)
+            return launch_pp_k<T, NT, RT, WAVES, true>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,
+                                                       a_next, reverse, st);
+    return launch_pp_k<T, NT, RT, WAVES, false>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur, a_next,
+                                                reverse, st);
 }
 
 template <typename T, int NT, int RT>
@@ -631,8 +647,10 @@ hipError_t launch_sweep_mfma_pp(int S, int max_ports, int nrhs, int variant, int
     const int qp = tile_pad(max_ports);
     int rc = rc_req > 0 ? ((rc_req + 15) / 16) * 16 : 64;
     if (rc > 64) rc = 64;
-    while (rc > 16 && pp_lds_bytes<T>(qp, rc) > lds_limit) rc -= 16;
-    const size_t lds = pp_lds_bytes<T>(qp, rc);
+    // h in LDS when some block width fits with it, else read at the store
+    const int h_lds = pp_lds_bytes<T>(qp, 16, true) <= lds_limit ? 1 : 0;
+    while (rc > 16 && pp_lds_bytes<T>(qp, rc, h_lds) > lds_limit) rc -= 16;
+    const size_t lds = pp_lds_bytes<T>(qp, rc, h_lds);
     if (lds > lds_limit) return hipErrorInvalidValue;
     if (rc > nrhs) rc = ((nrhs + 15) / 16) * 16 < rc ? ((nrhs + 15) / 16) * 16 : rc;
     const int nt = (rc + 15) / 16;
@@ -643,18 +661,18 @@ hipError_t launch_sweep_mfma_pp(int S, int max_ports, int nrhs, int variant, int
     if (nt == NTV) {                                                                                             \
         if (thin)                                                                                                \
             return wide ? launch_pp_t<T, NTV, 1, 8>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,   \
-                                                    a_next, reverse, st)                                         \
+                                                    a_next, reverse, h_lds, st)                                         \
                         : launch_pp_t<T, NTV, 1, 4>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,   \
-                                                    a_next, reverse, st);                                        \
+                                                    a_next, reverse, h_lds, st);                                        \
         if (wide)                                                                                                \
             return deep ? launch_pp_t<T, NTV, 5, 8>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,   \
-                                                    a_next, reverse, st)                                         \
+                                                    a_next, reverse, h_lds, st)                                         \
                         : launch_pp_t<T, NTV, 3, 8>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,   \
-                                                    a_next, reverse, st);                                        \
+                                                    a_next, reverse, h_lds, st);                                        \
         return deep ? launch_pp_t<T, NTV, 5, 4>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,       \
-                                                a_next, reverse, st)                                             \
+                                                a_next, reverse, h_lds, st)                                             \
                     : launch_pp_t<T, NTV, 3, 4>(S, nrhs, rc, lds, Mop, qmofs, port_off, port_twin, h, a_cur,       \
-                                                a_next, reverse, st);                                            \
+                                                a_next, reverse, h_lds, st);                                            \
     }
     VTM_MFMA_PP_CASE(1)
     VTM_MFMA_PP_CASE(2)

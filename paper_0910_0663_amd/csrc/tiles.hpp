@@ -65,12 +65,13 @@ __host__ __device__ inline int pp_stage_stride(int qp, int rc) {
         return rc + VTM_MFMA_PP_F64_PAD;       // [k][n]
 }
 
-// LDS bytes of the batched port-to-port sweep: staged waves, then (BF16) h
+// LDS bytes of the batched port-to-port sweep: staged waves, then (BF16, when
+// with_h) h
 template <typename T>
-__host__ __device__ inline size_t pp_lds_bytes(int qp, int rc) {
+__host__ __device__ inline size_t pp_lds_bytes(int qp, int rc, bool with_h = true) {
     if constexpr (sizeof(T) == 2)
         return size_t(rc) * (qp + 8) * sizeof(T) +
-               (VTM_MFMA_PP_H_LDS ? size_t(qp) * (rc + 16) * sizeof(float) : 0);
+               (VTM_MFMA_PP_H_LDS && with_h ? size_t(qp) * (rc + 16) * sizeof(float) : 0);
     else
         return size_t(qp) * (rc + VTM_MFMA_PP_F64_PAD) * sizeof(T);
 }

@@ -169,7 +169,8 @@ using Clock = std::chrono::steady_clock;
 // residual and the copy of its per-column sums into pinned host memory.  With
 // transpose set the residual is taken on A^T (the adjoint system).
 template <typename TX>
-vtm_status residual_launch(vtm_handle h, const double* b, const TX* x, int nrhs, double* r_out, bool transpose) {
+vtm_status residual_launch(vtm_handle h, const double* b, const TX* x, int nrhs, double* r_out, bool transpose,
+                           float* r32 = nullptr, __bf16* r16 = nullptr) {
     const vtm::Plan& P = h->plan;
     if (P.vertex) {
         // the untorn system in the caller's numbering: x of an interfacial node is the mean
@@ -180,17 +181,20 @@ vtm_status residual_launch(vtm_handle h, const double* b, const TX* x, int nrhs,
         VTM_HIP(vtm::launch_restrict<TX>(no, nrhs, h->vr0.p, h->vr1.p, x, h->xo.p, false, h->stream));
         VTM_HIP(vtm::launch_residual<double>(no, nrhs, oT ? h->orowT.p : h->orow.p, oT ? h->ocolT.p : h->ocol.p,
                                              oT ? h->ovalT.p : h->oval.p, bo, h->xo.p, r_out ? h->ro.p : nullptr,
-                                             h->partial.p, h->norms.p, h->stream));
+                                             nullptr, nullptr, h->partial.p, h->norms.p, h->stream));
         if (r_out)
             VTM_HIP(vtm::launch_expand(int(P.n), nrhs, no, h->vx_src.p, h->vx_w.p, h->ro.p, false, r_out, h->stream));
+        const int64_t nv = P.n * nrhs;  // the low-precision copies from the expanded residual
+        if (r_out && r32) VTM_HIP((vtm::launch_convert<double, float>(nv, r_out, r32, h->stream)));
+        if (r_out && r16) VTM_HIP((vtm::launch_convert<double, __bf16>(nv, r_out, r16, h->stream)));
         VTM_HIP(hipMemcpyAsync(h->h_norms, h->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost,
                                h->stream));
         return VTM_OK;
     }
     const bool useT = transpose && !P.symmetric;
     VTM_HIP(vtm::launch_residual<TX>(int(P.n), nrhs, useT ? h->rowptrT.p : h->rowptr.p,
-                                     useT ? h->colT.p : h->col.p, useT ? h->valT.p : h->val.p, b, x, r_out,
-                                     h->partial.p, h->norms.p, h->stream));
+                                     useT ? h->colT.p : h->col.p, useT ? h->valT.p : h->val.p, b, x, r_out, r32,
+                                     r16, h->partial.p, h->norms.p, h->stream));
     VTM_HIP(hipMemcpyAsync(h->h_norms, h->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost,
                            h->stream));
     return VTM_OK;
@@ -209,8 +213,8 @@ vtm_status residual_finish(vtm_handle h, int nrhs, std::vector<double>& rel) {
 
 template <typename TX>
 vtm_status residual(vtm_handle h, const double* b, const TX* x, int nrhs, double* r_out,
-                    std::vector<double>& rel, bool transpose) {
-    vtm_status st = residual_launch<TX>(h, b, x, nrhs, r_out, transpose);
+                    std::vector<double>& rel, bool transpose, float* r32 = nullptr, __bf16* r16 = nullptr) {
+    vtm_status st = residual_launch<TX>(h, b, x, nrhs, r_out, transpose, r32, r16);
     if (st != VTM_OK) return st;
     return residual_finish(h, nrhs, rel);
 }
@@ -727,8 +731,10 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
         return true;
     };
     for (int outer = 0;; ++outer) {
-        // r = b - A x (FP64), kept for the inner solve
-        vtm_status st = residual<double>(h, h->bp.p, h->xp.p, nrhs, h->rp.p, rel, adjoint);
+        // r = b - A x (FP64), kept for the inner solve, and its BF16 or FP32 copy (the
+        // inner right-hand side) written by the same pass
+        vtm_status st = residual<double>(h, h->bp.p, h->xp.p, nrhs, h->rp.p, rel, adjoint,
+                                         h->tiles ? nullptr : h->b32.p, h->tiles ? h->b16.p : nullptr);
         if (st != VTM_OK) return st;
         ++out.checks;
         out.rel = rel;
@@ -746,10 +752,6 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
         for (int r = 0; r < nrhs; ++r) target[r] = rel[r] > 0.0 ? std::max(drop, 0.5 * tol / rel[r]) : 1.0;
         std::vector<double> rr(nrhs);  // ||r||^2 per right-hand side, for the port-residual inner checks
         for (int r = 0; r < nrhs; ++r) rr[r] = h->h_norms[2 * r];
-        if (h->tiles)
-            VTM_HIP((vtm::launch_convert<double, __bf16>(nv, h->rp.p, h->b16.p, h->stream)));
-        else
-            VTM_HIP((vtm::launch_convert<double, float>(nv, h->rp.p, h->b32.p, h->stream)));
         VTM_HIP(vtm::launch_fill<float>(np, 0.0f, h->a32[0].p, h->stream));
         Cadence cad;
         cad.m = h->opt.check_every;

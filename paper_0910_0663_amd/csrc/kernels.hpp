@@ -183,10 +183,11 @@ inline int resid_blocks(int64_t rows, int nrhs) {
     const int64_t b = rows * nrhs / 4096;
     return int(b < 1024 ? 1024 : (b > kResidBlocks ? kResidBlocks : b));
 }
+// r_out (FP64), r32 (FP32) and r16 (BF16) are optional copies of r = b - A x
 template <typename TX>
 hipError_t launch_residual(int n, int nrhs, const int32_t* rowptr, const int32_t* col,
-                           const double* val, const double* b, const TX* x, double* r_out,
-                           double* partial, double* norms, hipStream_t st);
+                           const double* val, const double* b, const TX* x, double* r_out, float* r32,
+                           __bf16* r16, double* partial, double* norms, hipStream_t st);
 
 // ---- vector utilities -------------------------------------------------------
 // dst[i][r] = src[r][perm[i]]   (column-major caller layout -> renumbered rows)

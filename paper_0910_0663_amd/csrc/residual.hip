@@ -22,7 +22,8 @@ template <typename TX, bool UNI>
 __global__ void __launch_bounds__(kBlock)
     k_resid(int n, int nrhs, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
             const double* __restrict__ val, const double* __restrict__ b, const TX* __restrict__ x,
-            double* __restrict__ r_out, double* __restrict__ partial) {
+            double* __restrict__ r_out, float* __restrict__ r32, __bf16* __restrict__ r16,
+            double* __restrict__ partial) {
     __shared__ double s_rr[kBlock], s_bb[kBlock];
     const int tid = threadIdx.x;
     const int per = blockDim.x / nrhs;
@@ -37,6 +38,9 @@ __global__ void __launch_bounds__(kBlock)
             double acc = bv;
             for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc -= val[k] * double(x[int64_t(col[k]) * nrhs + rhs]);
             if (r_out) r_out[i * nrhs + rhs] = acc;
+            // the low-precision copies round as a separate cast pass would: via FP32
+            if (r32) r32[i * nrhs + rhs] = static_cast<float>(acc);
+            if (r16) r16[i * nrhs + rhs] = static_cast<__bf16>(static_cast<float>(acc));
             rr += acc * acc;
             bb += bv * bv;
         }
@@ -150,16 +154,16 @@ template hipError_t launch_port_residual<float>(int64_t, int, const int32_t*, co
 
 template <typename TX>
 hipError_t launch_residual(int n, int nrhs, const int32_t* rowptr, const int32_t* col, const double* val,
-                           const double* b, const TX* x, double* r_out, double* partial, double* norms,
-                           hipStream_t st) {
+                           const double* b, const TX* x, double* r_out, float* r32, __bf16* r16, double* partial,
+                           double* norms, hipStream_t st) {
     if (nrhs < 1 || nrhs > kBlock) return hipErrorInvalidValue;
     const int blocks = resid_blocks(n, nrhs);
     if (VTM_RESID_UNIFORM && nrhs % 64 == 0)
         hipLaunchKernelGGL((k_resid<TX, true>), dim3(blocks), dim3(kBlock), 0, st, n, nrhs, rowptr, col, val, b, x,
-                           r_out, partial);
+                           r_out, r32, r16, partial);
     else
         hipLaunchKernelGGL((k_resid<TX, false>), dim3(blocks), dim3(kBlock), 0, st, n, nrhs, rowptr, col, val, b, x,
-                           r_out, partial);
+                           r_out, r32, r16, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_norms_final, dim3(2 * nrhs), dim3(kBlock), 0, st, blocks, nrhs, partial, norms);
@@ -167,8 +171,8 @@ hipError_t launch_residual(int n, int nrhs, const int32_t* rowptr, const int32_t
 }
 
 template hipError_t launch_residual<double>(int, int, const int32_t*, const int32_t*, const double*, const double*,
-                                            const double*, double*, double*, double*, hipStream_t);
+                                            const double*, double*, float*, __bf16*, double*, double*, hipStream_t);
 template hipError_t launch_residual<float>(int, int, const int32_t*, const int32_t*, const double*, const double*,
-                                           const float*, double*, double*, double*, hipStream_t);
+                                           const float*, double*, float*, __bf16*, double*, double*, hipStream_t);
 
 }  // namespace vtm

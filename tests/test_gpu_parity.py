@@ -239,7 +239,7 @@ def test_timing_modes_count_every_launch(torch):
     assert np.array_equal(xs[0], xs[1])
 
 
-def test_config1_sweeps_and_solution(torch):
+def test_64sq_grid_sweeps_and_solution(torch):
     """64x64 grid, 4x4 sub-circuits of 16x16, tol 1e-10, residual checked every
     sweep: the same sweep count as the oracle (within one for rounding at the
     threshold), the same iterate, and the fixed point of the direct solve."""
@@ -256,7 +256,7 @@ def test_config1_sweeps_and_solution(torch):
 
 
 @pytest.mark.parametrize("adaptive", [False, True])
-def test_config2_shape_scaled(torch, adaptive):
+def test_log_uniform_grid_of_8x8_blocks_scaled_down(torch, adaptive):
     """The 8x8-sub-circuit, log-uniform-conductance workload at 256x256 with a
     check every 8 sweeps (and with checks thinned out far from the tolerance):
     the GPU stops within [oracle, oracle + 7] sweeps and its iterate matches the
@@ -409,7 +409,7 @@ def test_gradient_through_autograd_matches_oracle(torch):
     assert np.abs(g.grad.cpu().numpy() - gref).max() <= 1e-7 * np.abs(gref).max()
 
 
-def test_full_size_config2_residual(torch):
+def test_full_size_2048sq_residual(torch):
     """The bench workload at full size (2048^2 nodes, 65,536 sub-circuits of 8x8,
     check every 8 sweeps): the returned x meets the FP64 relative residual 1e-8
     recomputed on the host from the untorn A."""
@@ -423,7 +423,7 @@ def test_full_size_config2_residual(torch):
     assert abs(rel - rep.relres_max) <= 1e-3 * rel
 
 
-def test_full_size_config4_bf16_refinement_residual(torch):
+def test_full_size_1024sq_64rhs_bf16_refinement_residual(torch):
     """The batched bench workload at full size (1024^2 nodes, 4,290 uneven
     sub-circuits, 64 right-hand sides): BF16 sweeps on the matrix cores inside
     FP64 refinement give every column relative residual <= 1e-8, recomputed on the
@@ -437,7 +437,7 @@ def test_full_size_config4_bf16_refinement_residual(torch):
     assert rep.outer >= 2
 
 
-def test_full_size_config3_fp32_refinement_residual(torch):
+def test_full_size_128cube_fp32_refinement_residual(torch):
     """The unsymmetric bench workload at full size (128^3 nodes with 124,846
     controlled sources, 4,096 sub-circuits of 8^3): FP32 sweeps inside FP64
     refinement reach relative residual 1e-8, recomputed on the host."""
@@ -449,7 +449,7 @@ def test_full_size_config3_fp32_refinement_residual(torch):
     assert rep.outer >= 1
 
 
-def test_full_size_config5_gradient_matches_oracle(torch):
+def test_full_size_512sq_gradient_matches_oracle(torch):
     """The gradient bench workload at full size (512^2 grid, 4,096 probes, 523,264
     branches; FP32 sweeps with FP64 refinement to 1e-8): dL/dg of every branch
     against the oracle's adjoint formula with direct solves (whose formula a CPU

@@ -129,6 +129,38 @@ def timed_solve(vtm, torch, w, precision, nrhs_max, reps=2):
     return ms, rep, x
 
 
+def batched_pp_roofline(vtm, torch, w):
+    """HBM roofline of the batched port-to-port sweep (BF16 and FP64 operator tiles,
+    64 right-hand sides): algorithmic bytes per launch over the average launch time
+    from HIP events around each run of port-to-port sweeps (timing mode 2).
+    Bytes: the padded q_s x q_s operator of every sub-circuit once (q_s = cut wires
+    at s, padded to a multiple of 32; 2 or 8 bytes an entry), and per port and
+    right-hand side the incident wave, h and the outgoing wave (4 or 8 bytes each),
+    plus a 4-byte twin index per port."""
+    i, j = w.edges[:, 0], w.edges[:, 1]
+    cut = w.part[i] != w.part[j]
+    q = np.bincount(w.part[i[cut]], minlength=w.n_sub) + np.bincount(w.part[j[cut]], minlength=w.n_sub)
+    qp = (q + 31) // 32 * 32
+    ports = int(q.sum())
+    b = torch.as_tensor(w.b, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(b)
+    out = {}
+    for prec, e_op, e_vec in (("bf16_refine", 2, 4), ("fp64", 8, 8)):
+        s = vtm.Solver(w.A, w.part, w.Z, precision=prec, nrhs_max=w.nrhs, timing=2)
+        s.solve(b, w.tol, x)
+        _, rep = s.solve(b, w.tol, x)
+        s.close()
+        us = rep.pp_kernel_ms / max(rep.pp_launches, 1) * 1e3
+        nbytes = int((qp.astype(np.int64) ** 2).sum() * e_op + ports * w.nrhs * 3 * e_vec + ports * 4)
+        gbs = nbytes / (us * 1e-6) / 1e9
+        out["bf16" if prec == "bf16_refine" else "fp64"] = {
+            "bound": "hbm", "kernel": "k_sweep_mfma_pp", "achieved": round(gbs, 1), "peak": 8000.0,
+            "unit": "GB/s", "frac": round(gbs / 8000.0, 4), "bytes_per_launch": nbytes,
+            "avg_launch_us": round(us, 2), "launches_timed": int(rep.pp_launches),
+            "shape": list(rep.pp_shape)}
+    return out
+
+
 def mixed_and_batched(vtm, torch, workloads):
     """The precision/batching forms against plain FP64 VTM on the same GPU, each
     solved to relative residual 1e-8 (recomputed on the host in FP64)."""
@@ -168,6 +200,7 @@ def mixed_and_batched(vtm, torch, workloads):
         "fp64_single_rhs_relres": rel1, "speedup_vs_single_rhs": round(t1 / t16, 2)})
     log(f"cfg4: bf16 {t16:.1f} ms ({r16.sweeps} sweeps, {r16.outer} outer) vs fp64 batched {t64:.1f} ms "
         f"({r64.sweeps} sweeps): x{t64 / t16:.2f}; vs 64 single-RHS fp64 solves {t1:.0f} ms: x{t1 / t16:.1f}")
+    res["roofline_batched_pp"] = batched_pp_roofline(vtm, torch, w)
     w = workloads.make(3)
     t32, r32, x32 = timed_solve(vtm, torch, w, "fp32_refine", 1, reps=2)
     t64, r64, x64 = timed_solve(vtm, torch, w, "fp64", 1, reps=2)

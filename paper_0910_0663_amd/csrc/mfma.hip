@@ -33,6 +33,10 @@
 #ifndef VTM_MFMA_PD16
 #define VTM_MFMA_PD16 2
 #endif
+// full batched sweep: FP64 k tiles of A in flight per wavefront
+#ifndef VTM_MFMA_FULL_PD64
+#define VTM_MFMA_FULL_PD64 6
+#endif
 // full batched sweep: staging loads issued in rounds (aligned right-hand sides)
 #ifndef VTM_MFMA_FULL_ROUNDS
 #define VTM_MFMA_FULL_ROUNDS 1
@@ -118,7 +122,7 @@ struct Mma<double> {
 // k tile it loads the NT B fragments once from LDS and its row tiles' A tiles
 // from HBM (the next k tile's A tiles are already in flight), then issues the
 // MFMAs.  epi(row, n, value) receives every element of D (rows < np, n < 16 NT).
-template <typename T, int NT, int RT, int WAVES, typename Epi>
+template <typename T, int NT, int RT, int WAVES, int PD64 = VTM_MFMA_PD64, typename Epi>
 __device__ inline void tile_gemm(const T* Ablk, int np, const T* sb, int bsel, int w, Epi epi) {
     using M = Mma<T>;
     using TV = typename M::TV;
@@ -142,7 +146,7 @@ __device__ inline void tile_gemm(const T* Ablk, int np, const T* sb, int bsel, i
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[j][nt][v] = 0;
         // ring of PD k tiles: tile k sits in abuf[k % PD]; the loads run PD - 1 tiles ahead
-        constexpr int PD = sizeof(T) == 8 ? VTM_MFMA_PD64 : VTM_MFMA_PD16;
+        constexpr int PD = sizeof(T) == 8 ? PD64 : VTM_MFMA_PD16;
         typename M::AFrag abuf[PD][RT];
 #pragma unroll
         for (int d = 0; d < PD - 1; ++d)
@@ -317,7 +321,9 @@ __global__ void __launch_bounds__(kBlock)
     __syncthreads();
 
     // 2. X = Kinv B, x stored on the rows the wave update reads (all rows with write_x)
-    tile_gemm<T, NT, RT, kWaves>(K + mofs[s], np, sb, sizeof(T) == 2 ? np : rc, w, [&](int row, int n, TV v, int) {
+    // (the full inverses are long in k: FP64 keeps more of its tiles in flight)
+    tile_gemm<T, NT, RT, kWaves, VTM_MFMA_FULL_PD64>(K + mofs[s], np, sb, sizeof(T) == 2 ? np : rc, w,
+                                                     [&](int row, int n, TV v, int) {
         if (row < ns && n < w && (write_x || pcount[row])) x[int64_t(off + row) * nrhs + r0 + n] = v;
     });
     __syncthreads();

@@ -382,7 +382,7 @@ template hipError_t launch_sweep_pp<float, float>(int, int, const float*, const 
 #endif
 // chunks issued before the first barrier (the rest stream that far ahead)
 #ifndef VTM_PPS_PRE_HALF
-#define VTM_PPS_PRE_HALF 1
+#define VTM_PPS_PRE_HALF 2
 #endif
 #ifndef VTM_PPS_PRE
 #define VTM_PPS_PRE 1

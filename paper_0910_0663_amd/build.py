@@ -8,6 +8,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -29,22 +30,31 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = True) -> str:
-    """Compile every source and link libvtm.so next to this file.  Always rebuilds."""
+def build(verbose: bool = True, jobs: int = 0) -> str:
+    """Compile every source (in parallel, ``jobs`` at a time; 0 = one per CPU, at
+    most 8) and link libvtm.so next to this file.  Always rebuilds."""
     cc = hipcc()
     obj_dir = os.path.join(PKG, "_build")
     os.makedirs(obj_dir, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(obj_dir, src + ".o")
         cmd = [cc, *COMMON, "-c", path, "-o", obj]
         if src.endswith(".hip"):
             cmd[1:1] = DEVICE_FLAGS
+        cmds.append(cmd)
+        objs.append(obj)
+
+    def compile_one(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    jobs = jobs or min(8, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        for f in [pool.submit(compile_one, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [cc, *DEVICE_FLAGS, "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

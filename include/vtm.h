@@ -315,6 +315,30 @@ vtm_status vtm_solve_adjoint(vtm_handle h, const double *g, double *lambda, int3
                              double tol, vtm_report *rep);
 
 /*
+ * vtm_solve_noalloc -- vtm_solve for callers that cannot allocate device
+ * memory or create runtime objects during a solve (code under HIP graph
+ * capture elsewhere in the process, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and errors as vtm_solve; the same
+ * kernels run in the same order, so x and the report are bitwise those of
+ * vtm_solve.  The residual reductions keep their partial sums in a static
+ * device workspace of the library (4 MiB per device, held until the process
+ * ends) instead of the handle's buffers; the call makes no hipMalloc, hipFree,
+ * event, stream or graph.  Every check writes all of the workspace it reads,
+ * so a call does not depend on what an earlier call left there.
+ *
+ *   nrhs   1 .. min(opt.nrhs_max, 64); above 64: VTM_E_UNSUPPORTED.
+ *   The handle must have opt.use_graph == 0 and opt.timing == 0, else
+ *   VTM_E_UNSUPPORTED.
+ *
+ * All calls on one device share its workspace: two vtm_solve_noalloc calls
+ * that overlap in time on one device (from two host threads) race and give
+ * wrong results.  Calls run one after the other are safe; the call returns
+ * only after its work has finished.
+ */
+vtm_status vtm_solve_noalloc(vtm_handle h, const double *b, double *x, int32_t nrhs, double tol,
+                             vtm_report *rep);
+
+/*
  * vtm_grad -- derivative of a loss L(x) with respect to branch conductances,
  * from A x = b and A^T lambda = dL/dx:
  *     dL_dg[e] = - sum_r (lambda_i - lambda_j)(x_i - x_j),  branch e = (i, j).

@@ -25,7 +25,8 @@ STATUS = ["VTM_OK", "VTM_E_ARG", "VTM_E_UNTEARABLE", "VTM_E_SINGULAR", "VTM_E_DI
 EXPORTS = ["vtm_default_options", "vtm_setup", "vtm_solve", "vtm_solve_adjoint", "vtm_grad",
            "vtm_get_waves", "vtm_set_waves", "vtm_info", "vtm_destroy", "vtm_status_str",
            "vtm_last_error", "vtm_plan", "vtm_line_admittance", "vtm_setup_vertex",
-           "vtm_split_vertex", "vtm_setup_vertex_coupled", "vtm_vertex_admittance", "vtm_vertex_sca"]
+           "vtm_split_vertex", "vtm_setup_vertex_coupled", "vtm_vertex_admittance", "vtm_vertex_sca",
+           "vtm_solve_noalloc"]
 
 
 class VTMError(RuntimeError):
@@ -77,7 +78,7 @@ def lib() -> C.CDLL:
     L.vtm_setup_vertex.argtypes = [C.POINTER(Csr), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32), i64, dp, i64, C.POINTER(Options), vp, C.POINTER(vp)]
     L.vtm_setup_vertex.restype = C.c_int
-    for name in ("vtm_solve", "vtm_solve_adjoint"):
+    for name in ("vtm_solve", "vtm_solve_adjoint", "vtm_solve_noalloc"):
         f = getattr(L, name)
         f.argtypes = [vp, vp, vp, i32, C.c_double, C.POINTER(Report)]
         f.restype = C.c_int
@@ -374,6 +375,11 @@ class Solver:
     def solve(self, b, tol, x=None):
         """x with A x = b to relative residual tol (vtm_solve)."""
         return self._run(lib().vtm_solve, b, tol, x)
+
+    def solve_noalloc(self, b, tol, x=None):
+        """As solve, through vtm_solve_noalloc (no device allocation in the call;
+        at most 64 right-hand sides; x should be preallocated by the caller)."""
+        return self._run(lib().vtm_solve_noalloc, b, tol, x)
 
     def solve_adjoint(self, g, tol, lam=None):
         """lambda with A^T lambda = g (vtm_solve_adjoint)."""

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -53,6 +54,38 @@ struct DevBuf {
 };
 
 std::vector<float> to_float(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
+
+}  // namespace
+
+// Workspace of vtm_solve_noalloc, one copy per device, held until the process
+// ends: the residual reductions' per-workgroup partial sums (kResidBlocks
+// workgroups x kNoallocRhs columns x 2 sums) followed by the per-column sums
+// (2 x kNoallocRhs).  Every check writes all of what it then reads, so nothing
+// needs clearing between calls.  Host code never passes this name to a kernel:
+// it is a host-side stand-in; scratch_address() gives the device address.
+constexpr int kNoallocRhs = 64;
+constexpr size_t kNoallocDoubles = size_t(vtm::kResidBlocks) * kNoallocRhs * 2 + 2 * kNoallocRhs;
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_addr;  // device -> address of its copy of `scratch`
+
+// The address of `scratch` on device dev (which must be current), looked up
+// once per device.
+vtm_status scratch_address(int dev, double** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it == g_scratch_addr.end()) {
+        void* p = nullptr;
+        VTM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(VTM_E_HIP, "hipGetSymbolAddress returned no address for the static workspace");
+        it = g_scratch_addr.emplace(dev, static_cast<double*>(p)).first;
+    }
+    *out = it->second;
+    return VTM_OK;
+}
 
 }  // namespace
 
@@ -121,6 +154,11 @@ struct vtm_handle_s {
     DevBuf<float> b32, d32, a32[2];       // low-precision inner solve
     DevBuf<__bf16> b16;                   // its right-hand side in BF16 (batched BF16 form)
     DevBuf<double> partial, norms;
+    // where the residual reductions put their per-workgroup partial sums and
+    // per-column sums: the handle's partial / norms, or the static workspace of
+    // vtm_solve_noalloc for the duration of such a call
+    double* red_partial = nullptr;
+    double* red_norms = nullptr;
     DevBuf<int> flag;
     double* h_norms = nullptr;            // pinned
     bool waves_set = false;               // next solve resumes from the stored waves
@@ -181,21 +219,21 @@ vtm_status residual_launch(vtm_handle h, const double* b, const TX* x, int nrhs,
         VTM_HIP(vtm::launch_restrict<TX>(no, nrhs, h->vr0.p, h->vr1.p, x, h->xo.p, false, h->stream));
         VTM_HIP(vtm::launch_residual<double>(no, nrhs, oT ? h->orowT.p : h->orow.p, oT ? h->ocolT.p : h->ocol.p,
                                              oT ? h->ovalT.p : h->oval.p, bo, h->xo.p, r_out ? h->ro.p : nullptr,
-                                             nullptr, nullptr, h->partial.p, h->norms.p, h->stream));
+                                             nullptr, nullptr, h->red_partial, h->red_norms, h->stream));
         if (r_out)
             VTM_HIP(vtm::launch_expand(int(P.n), nrhs, no, h->vx_src.p, h->vx_w.p, h->ro.p, false, r_out, h->stream));
         const int64_t nv = P.n * nrhs;  // the low-precision copies from the expanded residual
         if (r_out && r32) VTM_HIP((vtm::launch_convert<double, float>(nv, r_out, r32, h->stream)));
         if (r_out && r16) VTM_HIP((vtm::launch_convert<double, __bf16>(nv, r_out, r16, h->stream)));
-        VTM_HIP(hipMemcpyAsync(h->h_norms, h->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost,
+        VTM_HIP(hipMemcpyAsync(h->h_norms, h->red_norms, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost,
                                h->stream));
         return VTM_OK;
     }
     const bool useT = transpose && !P.symmetric;
     VTM_HIP(vtm::launch_residual<TX>(int(P.n), nrhs, useT ? h->rowptrT.p : h->rowptr.p,
                                      useT ? h->colT.p : h->col.p, useT ? h->valT.p : h->val.p, b, x, r_out, r32,
-                                     r16, h->partial.p, h->norms.p, h->stream));
-    VTM_HIP(hipMemcpyAsync(h->h_norms, h->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost,
+                                     r16, h->red_partial, h->red_norms, h->stream));
+    VTM_HIP(hipMemcpyAsync(h->h_norms, h->red_norms, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost,
                            h->stream));
     return VTM_OK;
 }
@@ -227,12 +265,12 @@ vtm_status port_residual_launch(vtm_handle h, bool low, int cur, int nrhs) {
     if (!low)
         VTM_HIP(vtm::launch_port_residual<double>(nn, nrhs, h->pn_pfirst.p, h->port_twin.p, h->a64[cur].p,
                                                   h->a64[cur ^ 1].p, h->c64.p, h->beta64.p, h->gamma64.p,
-                                                  h->pgd64.p, h->pg64.p, h->partial.p, h->norms.p, h->stream));
+                                                  h->pgd64.p, h->pg64.p, h->red_partial, h->red_norms, h->stream));
     else
         VTM_HIP(vtm::launch_port_residual<float>(nn, nrhs, h->pn_pfirst.p, h->port_twin.p, h->a32[cur].p,
                                                  h->a32[cur ^ 1].p, h->c64.p, h->beta64.p, h->gamma64.p,
-                                                 h->pgd64.p, h->pg64.p, h->partial.p, h->norms.p, h->stream));
-    VTM_HIP(hipMemcpyAsync(h->h_norms, h->norms.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, h->stream));
+                                                 h->pgd64.p, h->pg64.p, h->red_partial, h->red_norms, h->stream));
+    VTM_HIP(hipMemcpyAsync(h->h_norms, h->red_norms, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, h->stream));
     return VTM_OK;
 }
 
@@ -1198,6 +1236,8 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
     VTM_HIP(h->xp.alloc(P.n * nr));
     VTM_HIP(h->partial.alloc(size_t(vtm::kResidBlocks) * nr * 2));
     VTM_HIP(h->norms.alloc(size_t(2) * nr));
+    h->red_partial = h->partial.p;
+    h->red_norms = h->norms.p;
     VTM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->h_norms), sizeof(double) * 2 * nr));
     int lds = 0;
     VTM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
@@ -1222,9 +1262,9 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
         VTM_HIP(h->mofs.upload(P.mofs, s));
     }
     const int64_t nm = P.mofs[P.S];
-    DevBuf<double> scratch, panel;  // setup only: FP64 inverses, and the elimination's panels
+    DevBuf<double> inv64, panel;  // setup only: FP64 inverses, and the elimination's panels
     DevBuf<int32_t> ipiv;
-    if (h->tiles || P.max_ns > vtm::kLdsSetupMax) VTM_HIP(scratch.alloc(nk));
+    if (h->tiles || P.max_ns > vtm::kLdsSetupMax) VTM_HIP(inv64.alloc(nk));
     if (P.max_ns > vtm::kLdsSetupMax) {
         VTM_HIP(panel.alloc(P.n * (2 * 16 + 1)));
         VTM_HIP(ipiv.alloc(P.n));
@@ -1246,12 +1286,12 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
         if (h->tiles) {
             VTM_HIP(h->K64.alloc(nm));
             VTM_HIP(vtm::launch_setup_tiles<double>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->mofs.p,
-                                                    h->rowptr.p, h->col.p, h->val.p, h->dmod.p, h->K64.p, scratch.p,
+                                                    h->rowptr.p, h->col.p, h->val.p, h->dmod.p, h->K64.p, inv64.p,
                                                     panel.p, ipiv.p, h->flag.p, s));
         } else {
             VTM_HIP(h->K64.alloc(nk));
             VTM_HIP(vtm::launch_setup<double>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
-                                              h->val.p, h->dmod.p, h->K64.p, scratch.p, panel.p, ipiv.p, h->flag.p,
+                                              h->val.p, h->dmod.p, h->K64.p, inv64.p, panel.p, ipiv.p, h->flag.p,
                                               s));
         }
     } else {
@@ -1270,12 +1310,12 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
         if (h->tiles) {
             VTM_HIP(h->Kbf.alloc(nm));
             VTM_HIP(vtm::launch_setup_tiles<__bf16>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->mofs.p,
-                                                    h->rowptr.p, h->col.p, h->val.p, h->dmod.p, h->Kbf.p, scratch.p,
+                                                    h->rowptr.p, h->col.p, h->val.p, h->dmod.p, h->Kbf.p, inv64.p,
                                                     panel.p, ipiv.p, h->flag.p, s));
         } else {
             VTM_HIP(h->K32.alloc(nk));
             VTM_HIP(vtm::launch_setup<float>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
-                                             h->val.p, h->dmod.p, h->K32.p, scratch.p, panel.p, ipiv.p, h->flag.p,
+                                             h->val.p, h->dmod.p, h->K32.p, inv64.p, panel.p, ipiv.p, h->flag.p,
                                              s));
         }
     }
@@ -1291,7 +1331,7 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
     const size_t ppn_lds = 2 * size_t(P.max_npn) * (o.precision == VTM_FP64 ? 8 : 4) + size_t(P.max_ports) * 4;
     h->ppn = h->pp && !h->pps && !P.coupled && o.local_form == 1 && P.sqn_entries < P.sq_entries &&
              ppn_lds <= 65536;
-    // batched form: port-to-port operators in tile order, built from the FP64 inverses in scratch
+    // batched form: port-to-port operators in tile order, built from the FP64 inverses in inv64
     const int qpad = vtm::tile_pad(P.max_ports);
     h->ppb = o.local_form >= 1 && h->tiles && P.nports > 0 &&
              (o.precision == VTM_FP64 ? vtm::pp_lds_bytes<double>(qpad, 16, false)
@@ -1304,13 +1344,13 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
             VTM_HIP(h->h64.alloc(P.nports * nr));
             VTM_HIP(vtm::launch_port_matrix_tiles<double>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p,
                                                           h->port_node.p, h->c64.p, h->beta64.p, h->gamma64.p,
-                                                          scratch.p, h->qmofs.p, h->M64t.p, s, h->coupling<double>()));
+                                                          inv64.p, h->qmofs.p, h->M64t.p, s, h->coupling<double>()));
         } else {
             VTM_HIP(h->Mbt.alloc(nq));
             VTM_HIP(h->h32.alloc(P.nports * nr));
             VTM_HIP(vtm::launch_port_matrix_tiles<__bf16>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p,
                                                           h->port_node.p, h->c64.p, h->beta64.p, h->gamma64.p,
-                                                          scratch.p, h->qmofs.p, h->Mbt.p, s, h->coupling<double>()));
+                                                          inv64.p, h->qmofs.p, h->Mbt.p, s, h->coupling<double>()));
         }
         VTM_HIP(hipStreamSynchronize(s));
     }
@@ -1406,6 +1446,26 @@ vtm_status vtm_solve(vtm_handle h, const double* b, double* x, int32_t nrhs, dou
 vtm_status vtm_solve_adjoint(vtm_handle h, const double* g, double* lambda, int32_t nrhs, double tol,
                              vtm_report* rep) {
     return solve_common(h, g, lambda, nrhs, tol, rep, true);
+}
+
+vtm_status vtm_solve_noalloc(vtm_handle h, const double* b, double* x, int32_t nrhs, double tol, vtm_report* rep) {
+    if (!h) return fail(VTM_E_ARG, "null handle");
+    if (nrhs > kNoallocRhs)
+        return fail(VTM_E_UNSUPPORTED, "vtm_solve_noalloc takes at most 64 right-hand sides (its static workspace "
+                                       "holds the residual sums of 64 columns)");
+    if (h->opt.use_graph || h->opt.timing)
+        return fail(VTM_E_UNSUPPORTED, "vtm_solve_noalloc needs use_graph = 0 and timing = 0 (graphs and timing "
+                                       "events are runtime objects created on first use)");
+    VTM_HIP(hipSetDevice(h->device));
+    double* ws = nullptr;
+    vtm_status st = scratch_address(h->device, &ws);
+    if (st != VTM_OK) return st;
+    h->red_partial = ws;
+    h->red_norms = ws + size_t(vtm::kResidBlocks) * kNoallocRhs * 2;
+    st = solve_common(h, b, x, nrhs, tol, rep, false);
+    h->red_partial = h->partial.p;
+    h->red_norms = h->norms.p;
+    return st;
 }
 
 vtm_status vtm_grad(vtm_handle h, const double* x, const double* lambda, int32_t nrhs, const int32_t* branch_ij,

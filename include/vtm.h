@@ -137,6 +137,18 @@ typedef struct {
                                per wavefront pass, right-hand sides per workgroup,
                                wavefronts per workgroup (zeros when not batched)     */
     double *relres;         /* optional caller array [nrhs]: final per-column value  */
+    /* Residual history.  A plain (FP64) solve records every residual check: the
+       check of x = 0 before any sweep, each check after a run of sweeps (from port
+       quantities in the port-to-port form, the same residual of the same iterate),
+       and the check on A after the sweep that rebuilds x.  A refining solve records
+       the FP64 residual ||b - A x|| / ||b|| at each outer step, before each
+       correction and the final one.  Each entry is the maximum over the columns. */
+    double *history;        /* optional caller array [history_cap]                   */
+    int64_t *history_sweeps;/* optional caller array [history_cap]: sweeps run by that
+                               entry (inner sweeps summed when refining)             */
+    int32_t history_cap;    /* entries the caller's arrays hold (0: none written)    */
+    int32_t history_len;    /* out: entries written, min(history_total, history_cap) */
+    int32_t history_total;  /* out: entries the solve produced                       */
 } vtm_report;
 
 typedef struct vtm_handle_s *vtm_handle;
@@ -309,7 +321,9 @@ vtm_status vtm_solve(vtm_handle h, const double *b, double *x, int32_t nrhs, dou
  * vtm_solve_adjoint -- solve A^T lambda = g by the same iteration on the torn
  * A^T, reusing the stored sub-circuit inverses read transposed (valid because
  * every cut coupling is symmetric, so the torn A^T is the transposed torn A).
- * Same conventions and errors as vtm_solve.
+ * Handles whose inverses are MFMA tiles (batched) use the same tiles when A is
+ * symmetric and a transposed copy made at setup otherwise (then every sweep of
+ * the adjoint is a full sweep).  Same conventions and errors as vtm_solve.
  */
 vtm_status vtm_solve_adjoint(vtm_handle h, const double *g, double *lambda, int32_t nrhs,
                              double tol, vtm_report *rep);
@@ -339,18 +353,26 @@ vtm_status vtm_solve_noalloc(vtm_handle h, const double *b, double *x, int32_t n
                              vtm_report *rep);
 
 /*
- * vtm_grad -- derivative of a loss L(x) with respect to branch conductances,
- * from A x = b and A^T lambda = dL/dx:
- *     dL_dg[e] = - sum_r (lambda_i - lambda_j)(x_i - x_j),  branch e = (i, j).
+ * vtm_grad -- derivatives of a loss L(x) through A x = b, from x and the
+ * adjoint solution lambda of A^T lambda = dL/dx (vtm_solve_adjoint):
+ *     dL_dg[e] = - sum_r (lambda_i - lambda_j)(x_i - x_j)  for branch e = (i, j)
+ *                (a conductance g stamps +g on A_ii, A_jj and -g on A_ij, A_ji);
+ *     dL_dA[k] = - sum_r lambda_row(k) x_col(k)             for entry k of A,
+ *                e.g. a controlled-source gain, a single entry of A (the
+ *                op-amp example of Section IX, eq. 15).
  * (dL/db = lambda needs no call.)
  *
- *   x, lambda   device FP64 [nrhs][n].
- *   branch_ij   device int32 [m][2] (pairs i, j; original node ids); a pair
- *               naming a node outside [0, n) yields NaN for that branch.
- *   dL_dg       device FP64 [m], overwritten.
+ *   x, lambda      device FP64 [nrhs][n] (the caller's node order).
+ *   branch_ij      device int32 [m][2] (pairs i, j; original node ids); a pair
+ *                  naming a node outside [0, n) yields NaN for that branch.
+ *                  m may be 0 (then branch_ij and dL_dg may be NULL).
+ *   dL_dg          device FP64 [m], overwritten.
+ *   dL_dA_or_null  device FP64 [nnz] or NULL: entry k of the CSR arrays of the A
+ *                  passed to vtm_setup / vtm_setup_vertex (the caller's order,
+ *                  duplicates each get the derivative of their sum), overwritten.
  */
 vtm_status vtm_grad(vtm_handle h, const double *x, const double *lambda, int32_t nrhs,
-                    const int32_t *branch_ij, int64_t m, double *dL_dg);
+                    const int32_t *branch_ij, int64_t m, double *dL_dg, double *dL_dA_or_null);
 
 /*
  * Checkpoint / resume of the iteration state: the incident wave at every port
@@ -383,8 +405,8 @@ const char *vtm_last_error(void);
  * interface node, so the interface block C of either side is diagonal with
  * the twin's 2g, and every rule below gives one W per wire (DIAG = OB there).
  * Tearing at interfacial nodes gives a C with off-diagonal entries (branches
- * between interfacial nodes), hence coupled lines for OB and WOB.  The
- * Schur-complement approximation (rule 5) is not provided. */
+ * between interfacial nodes), hence coupled lines for OB and WOB.  Rule 5,
+ * the Schur-complement approximation, is vtm_vertex_sca (tearing at nodes). */
 typedef enum {
     VTM_W_SCALED_MEAN = 0,  /* W_e = alpha * mean conductance of A's branches      */
     VTM_W_IDENTITY = 1,     /* W = alpha I (rule 1), alpha in siemens               */

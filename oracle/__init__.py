@@ -29,6 +29,7 @@ from .vtm import (  # noqa: F401
     direct_solve,
     direct_adjoint,
     branch_gradient,
+    matrix_gradient,
     jacobi_matrix,
     gauss_seidel_matrix,
 )

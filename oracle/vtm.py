@@ -648,6 +648,20 @@ def branch_gradient(edges, x, lam):
     return -np.sum((lam[:, i] - lam[:, j]) * (x[:, i] - x[:, j]), axis=0)
 
 
+def matrix_gradient(A, x, lam):
+    """dL/dA for every stored entry of A, in A's CSR entry order, from A x = b and
+    A^T lambda = dL/dx: perturbing one entry a_ij moves x by -A^-1 e_i x_j, so
+    dL/da_ij = -lambda_i x_j, summed over right-hand sides ([k, n] arrays).  A
+    controlled source of gain g_m at (k, c) is such an entry (Section IX, eq.
+    15).  Not in the paper (the differentiation the library adds); pinned by
+    central differences of the loss through direct solves."""
+    A = sp.csr_matrix(A)
+    rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    x = np.atleast_2d(x)
+    lam = np.atleast_2d(lam)
+    return -np.sum(lam[:, rows] * x[:, A.indices], axis=0)
+
+
 # --------------------------------------------------------------------------- #
 # Classical stationary methods (only to show where they fail, Section IX)
 # --------------------------------------------------------------------------- #

@@ -11,8 +11,33 @@ from __future__ import annotations
 import numpy as np
 import torch
 
+import scipy.sparse as sp
+
 from .binding import Solver
-from workloads import nodal_matrix
+
+
+def nodal_matrix(n, edges, g, ground, vccs=None):
+    """Nodal-analysis matrix of a current-driven circuit (Section II, eq. 1): a
+    branch of conductance g between i and j stamps +g on A_ii and A_jj and -g on
+    A_ij and A_ji; a conductance to ground stamps the diagonal; a voltage-
+    controlled current source (k, c, gain) stamps the single entry A_kc (the
+    op-amp example, eq. 15).  CSR with sorted columns, duplicates summed."""
+    edges = np.asarray(edges, dtype=np.int64)
+    i, j = edges[:, 0], edges[:, 1]
+    g = np.asarray(g, dtype=np.float64)
+    diag = np.arange(n)
+    rows = [i, j, i, j, diag]
+    cols = [i, j, j, i, diag]
+    vals = [g, g, -g, -g, np.asarray(ground, dtype=np.float64)]
+    if vccs is not None:
+        k, c, gm = vccs
+        rows.append(np.asarray(k))
+        cols.append(np.asarray(c))
+        vals.append(np.asarray(gm, dtype=np.float64))
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n)).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return A
 
 
 class Circuit:

@@ -55,7 +55,9 @@ class Report(C.Structure):
                 ("relres_max", C.c_double), ("solve_ms", C.c_double), ("sweep_kernel_ms", C.c_double),
                 ("sweep_launches", C.c_int64), ("batch_row_tiles", C.c_int32), ("batch_rhs_block", C.c_int32),
                 ("pp_kernel_ms", C.c_double), ("pp_launches", C.c_int64), ("pp_shape", C.c_int32 * 3),
-                ("relres", C.POINTER(C.c_double))]
+                ("relres", C.POINTER(C.c_double)), ("history", C.POINTER(C.c_double)),
+                ("history_sweeps", C.POINTER(C.c_int64)), ("history_cap", C.c_int32),
+                ("history_len", C.c_int32), ("history_total", C.c_int32)]
 
 
 _lib = None
@@ -82,7 +84,7 @@ def lib() -> C.CDLL:
         f = getattr(L, name)
         f.argtypes = [vp, vp, vp, i32, C.c_double, C.POINTER(Report)]
         f.restype = C.c_int
-    L.vtm_grad.argtypes = [vp, vp, vp, i32, vp, i64, vp]
+    L.vtm_grad.argtypes = [vp, vp, vp, i32, vp, i64, vp, vp]
     L.vtm_grad.restype = C.c_int
     L.vtm_get_waves.argtypes = [vp, vp, i32]
     L.vtm_get_waves.restype = C.c_int
@@ -269,6 +271,8 @@ class SolveReport:
     pp_kernel_ms: float = 0.0
     pp_launches: int = 0
     pp_shape: tuple = (0, 0, 0)
+    history: np.ndarray = None          # max relative residual per check (per outer step when refining)
+    history_sweeps: np.ndarray = None   # sweeps run by each entry
 
 
 def _ptr(t) -> int:
@@ -285,6 +289,8 @@ class Solver:
     node); or ``W``, a scipy sparse admittance matrix over the interfacial
     nodes, couples the lines (vtm_setup_vertex_coupled; Z is then ignored).
     """
+
+    HISTORY_CAP = 4096   # residual-history entries kept per solve
 
     def __init__(self, A, part, Z, precision="fp64", nrhs_max=1, check_every=8,
                  max_sweeps=1_000_000, divergence=1e6, inner_drop=0.0, max_outer=30,
@@ -314,6 +320,7 @@ class Solver:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         hc = _HostCsr(A)
         self.n = hc.n
+        self.nnz = int(hc.val.size)   # entries of A as given (the dL/dA of grad)
         part = np.ascontiguousarray(part, dtype=np.int32)
         if part.size != self.n:
             raise ValueError("part must have one label per node")
@@ -362,12 +369,17 @@ class Solver:
         if x is None:
             x = self._torch.empty_like(b)
         rel = np.zeros(nrhs)
-        rep = Report(relres=rel.ctypes.data_as(C.POINTER(C.c_double)))
+        hist = np.zeros(self.HISTORY_CAP)
+        hsw = np.zeros(self.HISTORY_CAP, dtype=np.int64)
+        rep = Report(relres=rel.ctypes.data_as(C.POINTER(C.c_double)),
+                     history=hist.ctypes.data_as(C.POINTER(C.c_double)),
+                     history_sweeps=hsw.ctypes.data_as(C.POINTER(C.c_int64)), history_cap=self.HISTORY_CAP)
         with self._torch.cuda.stream(self.stream):
             st = fn(self._h, C.c_void_p(_ptr(b)), C.c_void_p(_ptr(x)), nrhs, float(tol), C.byref(rep))
+        k = rep.history_len
         r = SolveReport(rep.sweeps, rep.outer, rep.checks, rep.relres_max, rep.solve_ms, rel.copy(),
                         rep.sweep_kernel_ms, rep.sweep_launches, (rep.batch_row_tiles, rep.batch_rhs_block),
-                        rep.pp_kernel_ms, rep.pp_launches, tuple(rep.pp_shape))
+                        rep.pp_kernel_ms, rep.pp_launches, tuple(rep.pp_shape), hist[:k].copy(), hsw[:k].copy())
         _check(st, r)
         return x, r
 
@@ -385,16 +397,24 @@ class Solver:
         """lambda with A^T lambda = g (vtm_solve_adjoint)."""
         return self._run(lib().vtm_solve_adjoint, g, tol, lam)
 
-    def grad(self, x, lam, branch_ij):
-        """dL/dg per branch (vtm_grad); branch_ij int32 [m, 2] on the GPU."""
+    def grad(self, x, lam, branch_ij=None, nnz=None):
+        """dL/dg per branch (vtm_grad); branch_ij int32 [m, 2] on the GPU (or None).
+        With nnz (the entry count of the A given at setup) also dL/dA per entry of
+        that CSR, returned as a second tensor."""
         torch = self._torch
         x = self._vec(x, "x")
         lam = self._vec(lam, "lambda")
-        ij = branch_ij.to(device=x.device, dtype=torch.int32).contiguous()
+        if branch_ij is None:
+            ij = torch.zeros((0, 2), dtype=torch.int32, device=x.device)
+        else:
+            ij = branch_ij.to(device=x.device, dtype=torch.int32).contiguous()
         out = torch.empty(ij.shape[0], dtype=torch.float64, device=x.device)
+        dA = torch.empty(int(nnz), dtype=torch.float64, device=x.device) if nnz is not None else None
         _check(lib().vtm_grad(self._h, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(lam)), x.shape[0],
-                              C.c_void_p(_ptr(ij)), ij.shape[0], C.c_void_p(_ptr(out))))
-        return out
+                              C.c_void_p(_ptr(ij)) if ij.shape[0] else None, ij.shape[0],
+                              C.c_void_p(_ptr(out)) if ij.shape[0] else None,
+                              C.c_void_p(_ptr(dA)) if dA is not None else None))
+        return out if dA is None else (out, dA)
 
     def get_waves(self, nrhs=1):
         w = self._torch.empty((nrhs, 2 * self.n_wires), dtype=self._torch.float64, device="cuda")

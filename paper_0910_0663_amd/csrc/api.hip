@@ -111,6 +111,12 @@ struct vtm_handle_s {
     DevBuf<__bf16> Kbf;
     DevBuf<int64_t> mofs;
     bool tiles = false;
+    // MFMA tiles of the transposed inverses (adjoint of an unsymmetric A)
+    DevBuf<double> K64T;
+    DevBuf<__bf16> KbfT;
+    // the caller's A as passed to setup: row and column of every entry (vtm_grad's dL/dA)
+    DevBuf<int32_t> erow, ecol;
+    int64_t a_nnz = 0;
     // port-to-port operators (opt.local_form = 1): M_s per sub-circuit and h per solve
     bool pp = false;
     DevBuf<int64_t> pofs;
@@ -284,6 +290,20 @@ struct IterOut {
     int64_t pp_launches = 0;
     std::vector<double> rel;
     vtm_status status = VTM_OK;
+    // residual history: max over columns of the relative residual at each check of a
+    // plain solve, or of the FP64 outer residual at each outer step of a refinement,
+    // with the sweeps run by then
+    std::vector<double> hist;
+    std::vector<int64_t> hist_sweeps;
+    void record() {
+        hist.push_back(max_of_rel());
+        hist_sweeps.push_back(sweeps);
+    }
+    double max_of_rel() const {
+        double mx = 0.0;
+        for (double v : rel) mx = std::isnan(v) ? v : std::max(mx, v);
+        return mx;
+    }
 };
 
 // Event around a sweep launch (opt.timing); pairs are reused per check interval.
@@ -324,16 +344,17 @@ vtm_status launch_one(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
                       int rc, bool write_x) {
     const vtm::Plan& P = h->plan;
     if (h->tiles) {
-        if (adjoint) return fail(VTM_E_UNSUPPORTED, "the batched (MFMA tile) layout has no adjoint form");
+        // the adjoint's operator is K^-T: the same tiles when A is symmetric, else the transposed copy
+        const bool kt = adjoint && !P.symmetric;
         if (!low)
             VTM_HIP(vtm::launch_sweep_mfma<double>(int(P.S), P.max_ns, P.max_ports, nrhs, variant, rc, h->lds_limit,
-                                                   h->K64.p, h->mofs.p, h->sub_off.p, h->ports(), h->c64.p,
+                                                   kt ? h->K64T.p : h->K64.p, h->mofs.p, h->sub_off.p, h->ports(), h->c64.p,
                                                    h->beta64.p, h->gamma64.p, static_cast<const double*>(b),
                                                    h->a64[cur].p, h->a64[cur ^ 1].p, static_cast<double*>(x), write_x,
                                                    h->stream));
         else
             VTM_HIP(vtm::launch_sweep_mfma<__bf16>(int(P.S), P.max_ns, P.max_ports, nrhs, variant, rc, h->lds_limit,
-                                                   h->Kbf.p, h->mofs.p, h->sub_off.p, h->ports(), h->c32.p,
+                                                   kt ? h->KbfT.p : h->Kbf.p, h->mofs.p, h->sub_off.p, h->ports(), h->c32.p,
                                                    h->beta32.p, h->gamma32.p, h->b16.p, h->a32[cur].p,
                                                    h->a32[cur ^ 1].p, static_cast<float*>(x), write_x, h->stream));
         return VTM_OK;
@@ -698,6 +719,7 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
     vtm_status st = residual<double>(h, h->bp.p, h->xp.p, nrhs, nullptr, out.rel, adjoint);
     if (st != VTM_OK) return st;
     ++out.checks;
+    out.record();
     auto done = [&](const std::vector<double>& rel) {
         for (double v : rel)
             if (!(v <= tol)) return false;
@@ -717,6 +739,7 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
         if (s2 != VTM_OK) return s2;
         if ((s2 = residual<double>(h, h->bp.p, h->xp.p, nrhs, nullptr, out.rel, adjoint)) != VTM_OK) return s2;
         ++out.checks;
+        out.record();
         return timing_collect(h, out);
     };
     while (true) {
@@ -726,6 +749,7 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
         cur ^= int(chunk & 1);
         out.sweeps += chunk;
         ++out.checks;
+        out.record();
         if ((st = timing_collect(h, out)) != VTM_OK) return st;
         bool bad = false;
         for (double v : out.rel)
@@ -776,6 +800,7 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
         if (st != VTM_OK) return st;
         ++out.checks;
         out.rel = rel;
+        out.record();
         for (double v : rel)
             if (!std::isfinite(v) || v > h->opt.divergence) {
                 out.status = VTM_E_DIVERGED;
@@ -894,6 +919,13 @@ vtm_status solve_common(vtm_handle h, const double* b, double* x, int32_t nrhs, 
         rep->pp_shape[2] = h->ppb ? ((ppv & 2) ? 8 : 4) : 0;
         if (rep->relres)
             for (int r = 0; r < nrhs; ++r) rep->relres[r] = out.rel[r];
+        const int64_t len = std::min<int64_t>(int64_t(out.hist.size()), std::max(rep->history_cap, 0));
+        for (int64_t k = 0; k < len; ++k) {
+            if (rep->history) rep->history[k] = out.hist[k];
+            if (rep->history_sweeps) rep->history_sweeps[k] = out.hist_sweeps[k];
+        }
+        rep->history_len = int32_t(len);
+        rep->history_total = int32_t(out.hist.size());
     }
     if (out.status == VTM_E_DIVERGED) return fail(VTM_E_DIVERGED, "the iteration diverged");
     if (out.status == VTM_E_MAXITER) return fail(VTM_E_MAXITER, "no convergence within the sweep limit");
@@ -1105,6 +1137,19 @@ vtm_status vtm_vertex_admittance(const vtm_csr* A, const int32_t* label, const i
 static vtm_status check_options(const vtm_options& o);
 static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* out);
 
+// Row and column of every entry of the caller's A, in the caller's entry order
+// (vtm_grad's dL/dA); A was validated by the planner.
+static vtm_status keep_pattern(vtm_handle_s* h, const vtm_csr* A) {
+    std::vector<int32_t> row(A->nnz), col(A->col, A->col + A->nnz);
+    for (int64_t i = 0; i < A->n; ++i)
+        for (int64_t q = A->rowptr[i]; q < A->rowptr[i + 1]; ++q) row[q] = int32_t(i);
+    VTM_HIP(h->erow.upload(row, h->stream));
+    VTM_HIP(h->ecol.upload(col, h->stream));
+    VTM_HIP(hipStreamSynchronize(h->stream));
+    h->a_nnz = A->nnz;
+    return VTM_OK;
+}
+
 vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int64_t nZ,
                      const vtm_options* opt, void* stream, vtm_handle* out) {
     if (!out) return fail(VTM_E_ARG, "null output handle");
@@ -1121,6 +1166,7 @@ vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int
     std::string err;
     st = vtm::build_plan(A, part, Z, nZ, h->plan, err);
     if (st != VTM_OK) return fail(st, err);
+    if ((st = keep_pattern(h.get(), A)) != VTM_OK) return st;
     return setup_from_plan(std::move(h), out);
 }
 
@@ -1151,6 +1197,7 @@ static vtm_status setup_vertex_common(const vtm_csr* A, const int32_t* label, co
     std::string err;
     st = vtm::build_plan_vertex(A, label, iface, sides, n_iface, W, nW, h->plan, err, Wc);
     if (st != VTM_OK) return fail(st, err);
+    if ((st = keep_pattern(h.get(), A)) != VTM_OK) return st;
     const vtm::Plan& P = h->plan;
     hipStream_t s = h->stream;
     VTM_HIP(hipGetDevice(&h->device));
@@ -1285,9 +1332,10 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
         VTM_HIP(vtm::launch_fill<double>(P.nports * nr, 0.0, h->a64[0].p, s));
         if (h->tiles) {
             VTM_HIP(h->K64.alloc(nm));
+            if (!P.symmetric) VTM_HIP(h->K64T.alloc(nm));
             VTM_HIP(vtm::launch_setup_tiles<double>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->mofs.p,
                                                     h->rowptr.p, h->col.p, h->val.p, h->dmod.p, h->K64.p, inv64.p,
-                                                    panel.p, ipiv.p, h->flag.p, s));
+                                                    panel.p, ipiv.p, h->flag.p, s, h->K64T.p));
         } else {
             VTM_HIP(h->K64.alloc(nk));
             VTM_HIP(vtm::launch_setup<double>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
@@ -1309,9 +1357,10 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
         VTM_HIP(h->d32.alloc(P.n * nr));
         if (h->tiles) {
             VTM_HIP(h->Kbf.alloc(nm));
+            if (!P.symmetric) VTM_HIP(h->KbfT.alloc(nm));
             VTM_HIP(vtm::launch_setup_tiles<__bf16>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->mofs.p,
                                                     h->rowptr.p, h->col.p, h->val.p, h->dmod.p, h->Kbf.p, inv64.p,
-                                                    panel.p, ipiv.p, h->flag.p, s));
+                                                    panel.p, ipiv.p, h->flag.p, s, h->KbfT.p));
         } else {
             VTM_HIP(h->K32.alloc(nk));
             VTM_HIP(vtm::launch_setup<float>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
@@ -1469,13 +1518,16 @@ vtm_status vtm_solve_noalloc(vtm_handle h, const double* b, double* x, int32_t n
 }
 
 vtm_status vtm_grad(vtm_handle h, const double* x, const double* lambda, int32_t nrhs, const int32_t* branch_ij,
-                    int64_t m, double* dL_dg) {
+                    int64_t m, double* dL_dg, double* dL_dA_or_null) {
     if (!h) return fail(VTM_E_ARG, "null handle");
-    if (m < 0 || nrhs < 1 || (m > 0 && (!x || !lambda || !branch_ij || !dL_dg)))
+    if (m < 0 || nrhs < 1 || ((m > 0 || dL_dA_or_null) && (!x || !lambda)) || (m > 0 && (!branch_ij || !dL_dg)))
         return fail(VTM_E_ARG, "bad gradient arguments");
     VTM_HIP(hipSetDevice(h->device));
     const int64_t nn = h->plan.vertex ? h->plan.n_orig : h->plan.n;  // the caller's nodes
-    VTM_HIP(vtm::launch_grad(m, int(nn), nrhs, x, lambda, branch_ij, dL_dg, h->stream));
+    if (m > 0) VTM_HIP(vtm::launch_grad(m, int(nn), nrhs, x, lambda, branch_ij, dL_dg, h->stream));
+    if (dL_dA_or_null)
+        VTM_HIP(vtm::launch_grad_entries(h->a_nnz, int(nn), nrhs, x, lambda, h->erow.p, h->ecol.p, dL_dA_or_null,
+                                         h->stream));
     VTM_HIP(hipStreamSynchronize(h->stream));
     return VTM_OK;
 }

@@ -49,12 +49,13 @@ hipError_t launch_setup(int S, int max_ns, const int32_t* sub_off, const int64_t
 
 // Same matrices, written as zero-padded MFMA operand tiles (tiles.hpp) of T
 // (BF16 or FP64) at out + mofs[s]; every sub-circuit passes through FP64
-// column-major scratch64 (kofs offsets, required).
+// column-major scratch64 (kofs offsets, required).  out_t (nullable) receives
+// the transposed inverses K_s^-T in the same layout (the adjoint's operator).
 template <typename T>
 hipError_t launch_setup_tiles(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs,
                               const int64_t* mofs, const int32_t* rowptr, const int32_t* col,
                               const double* val, const double* dmod, T* out, double* scratch64, double* panel,
-                              int32_t* ipiv, int* flag, hipStream_t st);
+                              int32_t* ipiv, int* flag, hipStream_t st, T* out_t = nullptr);
 
 // ---- sweep ----------------------------------------------------------------
 // One VTM sweep for every sub-circuit (one workgroup each, per block of up to 8
@@ -74,7 +75,7 @@ hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t*
 // gives it 5; rc_req: right-hand sides per workgroup (multiple of 16; 0 =
 // widest that fits lds_limit).  write_x = false stores x on port rows only (enough
 // for the waves; pass true on the last sweep before a residual check).  The
-// BF16 form reads b in BF16.  No adjoint form.
+// BF16 form reads b in BF16.  The adjoint passes the tiles of K^-T as K.
 template <typename T>
 hipError_t launch_sweep_mfma(int S, int max_ns, int max_ports, int nrhs, int variant, int rc_req,
                              size_t lds_limit, const T* K, const int64_t* mofs, const int32_t* sub_off,
@@ -216,6 +217,9 @@ hipError_t launch_add(int64_t count, const TD* d, double* x, hipStream_t st);
 template <typename TV>
 hipError_t launch_waves_io(int64_t np, int nrhs, const int32_t* abi2port, TV* a, double* abi,
                            bool to_abi, hipStream_t st);
+// dL_dA[k] = -sum_r lam[r][row[k]] x[r][col[k]] (x, lam: [nrhs][n]; row, col: [nnz], in range)
+hipError_t launch_grad_entries(int64_t nnz, int n, int nrhs, const double* x, const double* lam, const int32_t* row,
+                               const int32_t* col, double* dL_dA, hipStream_t st);
 // dL_dg[e] = -sum_r (lam_i - lam_j)(x_i - x_j)
 hipError_t launch_grad(int64_t m, int n, int nrhs, const double* x, const double* lam,
                        const int32_t* ij, double* dL_dg, hipStream_t st);

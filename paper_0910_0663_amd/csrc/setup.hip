@@ -413,7 +413,8 @@ __global__ void __launch_bounds__(kBlock)
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_to_tiles(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs,
-               const int64_t* __restrict__ mofs, const double* __restrict__ src, T* __restrict__ dst) {
+               const int64_t* __restrict__ mofs, const double* __restrict__ src, T* __restrict__ dst,
+               int transpose) {
     const int s = blockIdx.x;
     const int n = sub_off[s + 1] - sub_off[s];
     const int np = tile_pad(n);
@@ -423,7 +424,9 @@ __global__ void __launch_bounds__(kBlock)
     for (int64_t d = int64_t(blockIdx.y) * blockDim.x + threadIdx.x; d < cnt; d += int64_t(blockDim.x) * gridDim.y) {
         int r, c;
         tile_rc<T>(np, d, r, c);
-        o[d] = (r < n && c < n) ? static_cast<T>(M[int64_t(c) * n + r]) : static_cast<T>(0.0);
+        // element (r, c) of K^-1 (column-major), or of K^-T: element (c, r)
+        const int64_t at = transpose ? int64_t(r) * n + c : int64_t(c) * n + r;
+        o[d] = (r < n && c < n) ? static_cast<T>(M[at]) : static_cast<T>(0.0);
     }
 }
 
@@ -484,7 +487,8 @@ hipError_t invert_large(int S, int max_ns, const int32_t* sub_off, const int64_t
 template <typename T>
 hipError_t launch_setup_tiles(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, const int64_t* mofs,
                               const int32_t* rowptr, const int32_t* col, const double* val, const double* dmod,
-                              T* out, double* scratch64, double* panel, int32_t* ipiv, int* flag, hipStream_t st) {
+                              T* out, double* scratch64, double* panel, int32_t* ipiv, int* flag, hipStream_t st,
+                              T* out_t) {
     if (!scratch64) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_setup_lds<double, true>), dim3(S), dim3(kBlock), 0, st, sub_off, kofs, rowptr, col, val,
                        dmod, scratch64, flag);
@@ -494,8 +498,11 @@ hipError_t launch_setup_tiles(int S, int max_ns, const int32_t* sub_off, const i
         e = invert_large(S, max_ns, sub_off, kofs, rowptr, col, val, dmod, scratch64, panel, ipiv, flag, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_to_tiles<T>, dim3(S, copy_parts(S, tile_pad(max_ns))), dim3(kBlock), 0, st, sub_off, kofs,
-                       mofs, scratch64, out);
+    const dim3 grid(unsigned(S), unsigned(copy_parts(S, tile_pad(max_ns))));
+    hipLaunchKernelGGL(k_to_tiles<T>, grid, dim3(kBlock), 0, st, sub_off, kofs, mofs, scratch64, out, 0);
+    e = hipGetLastError();
+    if (e != hipSuccess || !out_t) return e;
+    hipLaunchKernelGGL(k_to_tiles<T>, grid, dim3(kBlock), 0, st, sub_off, kofs, mofs, scratch64, out_t, 1);
     return hipGetLastError();
 }
 
@@ -522,9 +529,9 @@ template hipError_t launch_setup<float>(int, int, const int32_t*, const int64_t*
                                         hipStream_t);
 template hipError_t launch_setup_tiles<__bf16>(int, int, const int32_t*, const int64_t*, const int64_t*,
                                               const int32_t*, const int32_t*, const double*, const double*, __bf16*,
-                                              double*, double*, int32_t*, int*, hipStream_t);
+                                              double*, double*, int32_t*, int*, hipStream_t, __bf16*);
 template hipError_t launch_setup_tiles<double>(int, int, const int32_t*, const int64_t*, const int64_t*,
                                               const int32_t*, const int32_t*, const double*, const double*, double*,
-                                              double*, double*, int32_t*, int*, hipStream_t);
+                                              double*, double*, int32_t*, int*, hipStream_t, double*);
 
 }  // namespace vtm

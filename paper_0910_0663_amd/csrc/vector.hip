@@ -163,9 +163,32 @@ __global__ void k_grad(int64_t m, int n, int nrhs, const double* __restrict__ x,
     out[e] = -acc;
 }
 
+// dL/dA over the entries of a sparse pattern: out[k] = -sum_r lam[r][row[k]] x[r][col[k]]
+__global__ void k_grad_entries(int64_t nnz, int n, int nrhs, const double* __restrict__ x,
+                               const double* __restrict__ lam, const int32_t* __restrict__ row,
+                               const int32_t* __restrict__ col, double* __restrict__ out) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= nnz) return;
+    const int i = row[k], j = col[k];
+    double acc = 0.0;
+    for (int r = 0; r < nrhs; ++r) {
+        const int64_t o = int64_t(r) * n;
+        acc += lam[o + i] * x[o + j];
+    }
+    out[k] = -acc;
+}
+
 inline unsigned blocks_for(int64_t count, int bs = kBlock) { return unsigned((count + bs - 1) / bs); }
 
 }  // namespace
+
+hipError_t launch_grad_entries(int64_t nnz, int n, int nrhs, const double* x, const double* lam, const int32_t* row,
+                               const int32_t* col, double* dL_dA, hipStream_t st) {
+    if (nnz == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grad_entries, dim3(blocks_for(nnz)), dim3(kBlock), 0, st, nnz, n, nrhs, x, lam, row, col,
+                       dL_dA);
+    return hipGetLastError();
+}
 
 hipError_t launch_expand(int rows, int nrhs, int n_in, const int32_t* src, const double* w, const double* in,
                          bool in_rhs_major, double* out, hipStream_t st) {

@@ -545,15 +545,6 @@ def test_batched_bf16_refinement_reaches_fp64_tolerance(torch):
     assert np.abs(xh - xs).max() <= 2e-6 * np.abs(xs).max()
 
 
-def test_batched_layout_has_no_adjoint(torch):
-    V = vtm()
-    w = workloads.make(4, dims=(64, 64), nrhs=16)
-    s = V.Solver(w.A, w.part, w.Z, nrhs_max=16)
-    with pytest.raises(V.VTMError) as ei:
-        s.solve_adjoint(to_dev(torch, w.b), 1e-8)
-    assert ei.value.name == "VTM_E_UNSUPPORTED"
-
-
 # ----------------------------------------------------------------------------- hipGraph replay
 @pytest.mark.parametrize("cfg,kw,prec,nr", [
     (1, dict(), "fp64", 1),

@@ -370,6 +370,42 @@ def test_branch_gradient_matches_finite_differences():
     assert np.abs(fd - grad[pick]).max() <= 1e-5 * np.abs(grad).max()
 
 
+def test_matrix_gradient_matches_finite_differences():
+    """dL/dA per stored entry (-lambda_i x_j, summed over columns) for
+    L = sum over probes of x_p^2 on the unsymmetric 3-D workload, against
+    central differences of L from direct solves: every controlled-source gain
+    (a single one-sided entry, Section IX eq. 15) and some diagonal and branch
+    entries, with two right-hand sides."""
+    w = workloads.make(3, dims=(8, 8, 16), nrhs=2)
+    A = sp.csr_matrix(w.A)
+    probes = np.random.default_rng(3).choice(w.n, 64, replace=False)
+    x = oracle.direct_solve(A, w.b)
+    dLdx = np.zeros_like(x)
+    dLdx[:, probes] = 2 * x[:, probes]
+    grad = oracle.matrix_gradient(A, x, oracle.direct_adjoint(A, dLdx))
+    assert grad.shape == (A.nnz,)
+    rows = np.repeat(np.arange(w.n), np.diff(A.indptr))
+    k_node, c_node, _ = w.vccs
+    vccs_entries = [int(np.nonzero((rows == k) & (A.indices == c))[0][0]) for k, c in zip(k_node, c_node)]
+    rng = np.random.default_rng(5)
+    pick = sorted(set(vccs_entries) | set(rng.choice(A.nnz, 24, replace=False).tolist()))
+
+    def loss(Ak):
+        xx = spla.splu(sp.csc_matrix(Ak)).solve(w.b.T)
+        return np.sum(xx[probes] ** 2)
+
+    fd = []
+    for k in pick:
+        h = 1e-5 * abs(A.data[k])
+        Ap, Am = A.copy(), A.copy()
+        Ap.data[k] += h
+        Am.data[k] -= h
+        fd.append((loss(Ap) - loss(Am)) / (2 * h))
+    fd = np.array(fd)
+    assert len(vccs_entries) >= 20
+    assert np.abs(fd - grad[pick]).max() <= 1e-6 * np.abs(grad[pick]).max()
+
+
 # ----------------------------------------------------------------------------- failure paths
 def test_untearable_cross_coupling_is_rejected():
     """A controlled source between two sub-circuits is not a two-terminal

@@ -375,6 +375,32 @@ vtm_status vtm_grad(vtm_handle h, const double *x, const double *lambda, int32_t
                     const int32_t *branch_ij, int64_t m, double *dL_dg, double *dL_dA_or_null);
 
 /*
+ * vtm_refresh -- new values of A (and optionally new line impedances) on the
+ * pattern and partition a vtm_setup handle was built with: the setup of
+ * Section VI (the sub-circuit matrices with their port conductances, eq. 11,
+ * their inverses and the port-to-port operators) is redone on the device
+ * without planning the tear again.  For loops that re-solve after changing
+ * conductances (power-grid sizing).  The handle then behaves exactly as one
+ * freshly set up with the new values: the same kernels on the same layout,
+ * bitwise the same results.
+ *
+ *   val   host FP64 [nnz]: new values for the CSR arrays given to vtm_setup
+ *         (same rowptr and col, same entry order).
+ *   Z     host, nullable: nZ == 1 or the number of cut wires as for vtm_setup;
+ *         NULL (or nZ == 0) keeps the current line impedances.
+ *
+ * The off-diagonal entries that are zero must stay the same (a different
+ * sparsity pattern is VTM_E_ARG), as must the symmetry of A
+ * (VTM_E_UNSUPPORTED), and every cut coupling must remain A_ij == A_ji < 0
+ * (VTM_E_UNTEARABLE); the handle is unchanged after these errors.  Handles of
+ * vtm_setup_vertex[_coupled] give VTM_E_UNSUPPORTED.  A sub-circuit that becomes
+ * singular gives VTM_E_SINGULAR, after which the handle must be refreshed
+ * again or destroyed.  Stored waves (vtm_set_waves) are discarded.  Returns
+ * after the device work finishes.
+ */
+vtm_status vtm_refresh(vtm_handle h, const double *val, const double *Z, int64_t nZ);
+
+/*
  * Checkpoint / resume of the iteration state: the incident wave at every port
  * (two ports per cut wire: port 2e on the lower node of wire e, 2e+1 on the
  * upper), device FP64 [nrhs][2 * n_wires].  vtm_set_waves makes the next

@@ -61,13 +61,17 @@ class Circuit:
         self.last_adjoint = None
 
     def solver(self, g: torch.Tensor) -> Solver:
+        """The handle for conductances g: set up once, then refreshed in place
+        (vtm_refresh: same pattern and partition, no new tearing plan) whenever g
+        changes."""
         gh = g.detach().to("cpu", torch.float64).numpy()
         key = gh.tobytes()
         if key != self._key:
-            if self._solver is not None:
-                self._solver.close()
             A = nodal_matrix(self.n, self.edges, gh, self.ground, self.vccs)
-            self._solver = Solver(A, self.part, self.Z, precision=self.precision, **self.solver_kw)
+            if self._solver is None:
+                self._solver = Solver(A, self.part, self.Z, precision=self.precision, **self.solver_kw)
+            else:
+                self._solver.refresh(A)
             self._key = key
         return self._solver
 

@@ -26,7 +26,7 @@ EXPORTS = ["vtm_default_options", "vtm_setup", "vtm_solve", "vtm_solve_adjoint",
            "vtm_get_waves", "vtm_set_waves", "vtm_info", "vtm_destroy", "vtm_status_str",
            "vtm_last_error", "vtm_plan", "vtm_line_admittance", "vtm_setup_vertex",
            "vtm_split_vertex", "vtm_setup_vertex_coupled", "vtm_vertex_admittance", "vtm_vertex_sca",
-           "vtm_solve_noalloc"]
+           "vtm_solve_noalloc", "vtm_refresh"]
 
 
 class VTMError(RuntimeError):
@@ -86,6 +86,8 @@ def lib() -> C.CDLL:
         f.restype = C.c_int
     L.vtm_grad.argtypes = [vp, vp, vp, i32, vp, i64, vp, vp]
     L.vtm_grad.restype = C.c_int
+    L.vtm_refresh.argtypes = [vp, dp, dp, i64]
+    L.vtm_refresh.restype = C.c_int
     L.vtm_get_waves.argtypes = [vp, vp, i32]
     L.vtm_get_waves.restype = C.c_int
     L.vtm_set_waves.argtypes = [vp, vp, i32]
@@ -415,6 +417,21 @@ class Solver:
                               C.c_void_p(_ptr(out)) if ij.shape[0] else None,
                               C.c_void_p(_ptr(dA)) if dA is not None else None))
         return out if dA is None else (out, dA)
+
+    def refresh(self, A, Z=None):
+        """New values of A on the pattern given at setup (vtm_refresh): A is a
+        scipy CSR with the same rowptr and column arrays, or the new values
+        array itself; Z (optional) new line impedances, scalar or per cut wire."""
+        import scipy.sparse as sp
+        vals = sp.csr_matrix(A).data if sp.issparse(A) else np.asarray(A)
+        vals = np.ascontiguousarray(vals, dtype=np.float64)
+        if vals.size != self.nnz:
+            raise ValueError("A must have the entries of the matrix given at setup")
+        if Z is None:
+            zp, nz = None, 0
+        else:
+            z, zp, nz = _z_array(Z)
+        _check(lib().vtm_refresh(self._h, vals.ctypes.data_as(C.POINTER(C.c_double)), zp, nz))
 
     def get_waves(self, nrhs=1):
         w = self._torch.empty((nrhs, 2 * self.n_wires), dtype=self._torch.float64, device="cuda")

@@ -42,9 +42,18 @@ struct DevBuf {
     ~DevBuf() {
         if (p) (void)hipFree(p);
     }
+    // a buffer of n elements; one of that size already held is kept (refresh
+    // re-runs setup's uploads on buffers of unchanged sizes)
     hipError_t alloc(size_t n) {
+        if (p && n == count) return hipSuccess;
+        reset();
         count = n;
         return hipMalloc(reinterpret_cast<void**>(&p), (n ? n : 1) * sizeof(T));
+    }
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        count = 0;
     }
     hipError_t upload(const std::vector<T>& v, hipStream_t st) {
         hipError_t e = alloc(v.size());
@@ -1245,15 +1254,16 @@ static vtm_status check_options(const vtm_options& o) {
     return VTM_OK;
 }
 
-static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* out) {
+// Everything of a handle that depends on the values of A and on the line
+// admittances: the uploaded values and port coefficients, the inverses and the
+// port-to-port operators.  Setup runs it once; vtm_refresh runs it again on the
+// same pattern and partition, so every buffer keeps its size and the same
+// kernels run on the same layout.
+static vtm_status build_values(vtm_handle_s* h) {
     const vtm_options& o = h->opt;
-    vtm_status st = VTM_OK;
-    VTM_HIP(hipGetDevice(&h->device));
     const vtm::Plan& P = h->plan;
     hipStream_t s = h->stream;
-
-    VTM_HIP(h->rowptr.upload(P.rowptr, s));
-    VTM_HIP(h->col.upload(P.col, s));
+    const int64_t nk = P.kofs[P.S], nm = P.mofs[P.S];
     VTM_HIP(h->val.upload(P.val, s));
     if (!P.symmetric) {
         std::vector<int32_t> rT, cT;
@@ -1264,20 +1274,166 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
         VTM_HIP(h->valT.upload(vT, s));
         VTM_HIP(hipStreamSynchronize(s));
     }
+    VTM_HIP(h->dmod.upload(P.dmod, s));
+    VTM_HIP(vtm::launch_fill<int>(1, 0, h->flag.p, s));
+    DevBuf<double> inv64, panel;  // FP64 inverses, and the elimination's panels
+    DevBuf<int32_t> ipiv;
+    if (h->tiles || P.max_ns > vtm::kLdsSetupMax) VTM_HIP(inv64.alloc(nk));
+    if (P.max_ns > vtm::kLdsSetupMax) {
+        VTM_HIP(panel.alloc(P.n * (2 * 16 + 1)));
+        VTM_HIP(ipiv.alloc(P.n));
+    }
+    VTM_HIP(h->c64.upload(P.pc, s));
+    VTM_HIP(h->beta64.upload(P.pbeta, s));
+    VTM_HIP(h->gamma64.upload(P.pgamma, s));
+    if (P.coupled) {
+        VTM_HIP(h->bval64.upload(P.bval, s));
+        if (o.precision != VTM_FP64) VTM_HIP(h->bval32.upload(to_float(P.bval), s));
+    }
+    if (o.precision == VTM_FP64) {
+        if (h->tiles) {
+            VTM_HIP(h->K64.alloc(nm));
+            if (!P.symmetric) VTM_HIP(h->K64T.alloc(nm));
+            VTM_HIP(vtm::launch_setup_tiles<double>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->mofs.p,
+                                                    h->rowptr.p, h->col.p, h->val.p, h->dmod.p, h->K64.p, inv64.p,
+                                                    panel.p, ipiv.p, h->flag.p, s, h->K64T.p));
+        } else {
+            VTM_HIP(h->K64.alloc(nk));
+            VTM_HIP(vtm::launch_setup<double>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
+                                              h->val.p, h->dmod.p, h->K64.p, inv64.p, panel.p, ipiv.p, h->flag.p,
+                                              s));
+        }
+    } else {
+        VTM_HIP(h->c32.upload(to_float(P.pc), s));
+        VTM_HIP(h->beta32.upload(to_float(P.pbeta), s));
+        VTM_HIP(h->gamma32.upload(to_float(P.pgamma), s));
+        if (h->tiles) {
+            VTM_HIP(h->Kbf.alloc(nm));
+            if (!P.symmetric) VTM_HIP(h->KbfT.alloc(nm));
+            VTM_HIP(vtm::launch_setup_tiles<__bf16>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->mofs.p,
+                                                    h->rowptr.p, h->col.p, h->val.p, h->dmod.p, h->Kbf.p, inv64.p,
+                                                    panel.p, ipiv.p, h->flag.p, s, h->KbfT.p));
+        } else {
+            VTM_HIP(h->K32.alloc(nk));
+            VTM_HIP(vtm::launch_setup<float>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
+                                             h->val.p, h->dmod.p, h->K32.p, inv64.p, panel.p, ipiv.p, h->flag.p,
+                                             s));
+        }
+    }
+    VTM_HIP(hipStreamSynchronize(s));
+    int flag = 0;
+    VTM_HIP(hipMemcpyAsync(&flag, h->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    VTM_HIP(hipStreamSynchronize(s));
+    if (flag & 1) return fail(VTM_E_SINGULAR, "a sub-circuit matrix is singular");
+    // port-to-port operators from the inverses
+    if (h->ppb) {  // batched form: in tile order, from the FP64 inverses in inv64
+        const int64_t nq = P.qmofs[P.S];
+        if (o.precision == VTM_FP64) {
+            VTM_HIP(h->M64t.alloc(nq));
+            VTM_HIP(vtm::launch_port_matrix_tiles<double>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p,
+                                                          h->port_node.p, h->c64.p, h->beta64.p, h->gamma64.p,
+                                                          inv64.p, h->qmofs.p, h->M64t.p, s, h->coupling<double>()));
+        } else {
+            VTM_HIP(h->Mbt.alloc(nq));
+            VTM_HIP(vtm::launch_port_matrix_tiles<__bf16>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p,
+                                                          h->port_node.p, h->c64.p, h->beta64.p, h->gamma64.p,
+                                                          inv64.p, h->qmofs.p, h->Mbt.p, s, h->coupling<double>()));
+        }
+        VTM_HIP(hipStreamSynchronize(s));
+    }
+    if (h->pp || h->ppb) {
+        VTM_HIP(h->pg64.upload(P.pg, s));
+        VTM_HIP(h->pgd64.upload(P.pgd, s));
+    }
+    if (h->ppn) {
+        const int64_t nn = P.nofs[P.S];
+        if (o.precision == VTM_FP64) {
+            VTM_HIP(h->N64.alloc(nn));
+            VTM_HIP(vtm::launch_port_node_dense<double>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p, h->pn_node.p,
+                                                        h->K64.p, h->nofs.p, h->N64.p, false, s));
+            if (!P.symmetric) {
+                VTM_HIP(h->N64T.alloc(nn));
+                VTM_HIP(vtm::launch_port_node_dense<double>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p,
+                                                            h->pn_node.p, h->K64.p, h->nofs.p, h->N64T.p, true, s));
+            }
+        } else {
+            VTM_HIP(h->N32.alloc(nn));
+            VTM_HIP(vtm::launch_port_node_dense<float>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p, h->pn_node.p,
+                                                       h->K32.p, h->nofs.p, h->N32.p, false, s));
+            if (!P.symmetric) {
+                VTM_HIP(h->N32T.alloc(nn));
+                VTM_HIP(vtm::launch_port_node_dense<float>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p,
+                                                           h->pn_node.p, h->K32.p, h->nofs.p, h->N32T.p, true, s));
+            }
+        }
+        VTM_HIP(hipStreamSynchronize(s));
+    } else if (h->pps) {
+        std::vector<double> Wp;
+        if (!P.uniform_W) {  // line admittance per port (both ports of a wire share it)
+            Wp.resize(P.nports);
+            for (int64_t q = 0; q < P.nports; ++q) Wp[P.abi2port[q]] = P.wW[q / 2];
+        }
+        const int64_t nsp = P.sofs[P.S];
+        if (o.precision == VTM_FP64) {
+            VTM_HIP(h->S64.alloc(nsp));
+            if (!P.uniform_W)
+                VTM_HIP(h->W64p.upload(Wp, s));
+            else
+                h->W64p.reset();  // one W for every port: the kernel takes it as a scalar
+            VTM_HIP(vtm::launch_fill<double>(nsp, double(0), h->S64.p, s));  // pads stay zero
+            VTM_HIP(vtm::launch_port_node_matrix<double>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p,
+                                                         h->pn_node.p, h->K64.p, h->sofs.p, h->S64.p, s));
+        } else {
+            VTM_HIP(h->S32.alloc(nsp));
+            if (!P.uniform_W)
+                VTM_HIP(h->W32p.upload(to_float(Wp), s));
+            else
+                h->W32p.reset();
+            VTM_HIP(vtm::launch_fill<float>(nsp, float(0), h->S32.p, s));  // pads stay zero
+            VTM_HIP(vtm::launch_port_node_matrix<float>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p,
+                                                        h->pn_node.p, h->K32.p, h->sofs.p, h->S32.p, s));
+        }
+        VTM_HIP(hipStreamSynchronize(s));
+    } else if (h->pp) {
+        const int64_t npm = P.pofs[P.S];
+        if (o.precision == VTM_FP64) {
+            VTM_HIP(h->M64.alloc(npm));
+            VTM_HIP(vtm::launch_port_matrix<double>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p, h->port_node.p,
+                                                    h->c64.p, h->beta64.p, h->gamma64.p, h->K64.p, h->pofs.p,
+                                                    h->M64.p, s, h->coupling<double>()));
+        } else {
+            VTM_HIP(h->M32.alloc(npm));
+            VTM_HIP(vtm::launch_port_matrix<float>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p, h->port_node.p,
+                                                   h->c64.p, h->beta64.p, h->gamma64.p, h->K32.p, h->pofs.p,
+                                                   h->M32.p, s, h->coupling<double>()));
+        }
+        VTM_HIP(hipStreamSynchronize(s));
+    }
+    return VTM_OK;
+}
+
+// The handle's structure (index arrays, work buffers, which local forms run),
+// then its values (build_values), then the batched kernels' launch shapes.
+static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* out) {
+    const vtm_options& o = h->opt;
+    vtm_status st = VTM_OK;
+    VTM_HIP(hipGetDevice(&h->device));
+    const vtm::Plan& P = h->plan;
+    hipStream_t s = h->stream;
+
+    VTM_HIP(h->rowptr.upload(P.rowptr, s));
+    VTM_HIP(h->col.upload(P.col, s));
     VTM_HIP(h->perm.upload(P.perm, s));
     VTM_HIP(h->iperm.upload(P.iperm, s));
     VTM_HIP(h->sub_off.upload(P.sub_off, s));
     VTM_HIP(h->kofs.upload(P.kofs, s));
-    VTM_HIP(h->dmod.upload(P.dmod, s));
     VTM_HIP(h->port_off.upload(P.port_off, s));
     VTM_HIP(h->port_node.upload(P.port_node, s));
     VTM_HIP(h->port_slot.upload(P.port_slot, s));
     VTM_HIP(h->port_twin.upload(P.port_twin, s));
     VTM_HIP(h->abi2port.upload(P.abi2port, s));
     VTM_HIP(h->flag.alloc(1));
-    VTM_HIP(hipMemsetAsync(h->flag.p, 0, sizeof(int), s));
 
-    const int64_t nk = P.kofs[P.S];
     const int nr = h->nrhs_max;
     VTM_HIP(h->bp.alloc(P.n * nr));
     VTM_HIP(h->xp.alloc(P.n * nr));
@@ -1308,44 +1464,16 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
         if (nr > 64 && o.precision == VTM_BF16_REFINE) return fail(VTM_E_UNSUPPORTED, "BF16 path takes at most 64 RHS");
         VTM_HIP(h->mofs.upload(P.mofs, s));
     }
-    const int64_t nm = P.mofs[P.S];
-    DevBuf<double> inv64, panel;  // setup only: FP64 inverses, and the elimination's panels
-    DevBuf<int32_t> ipiv;
-    if (h->tiles || P.max_ns > vtm::kLdsSetupMax) VTM_HIP(inv64.alloc(nk));
-    if (P.max_ns > vtm::kLdsSetupMax) {
-        VTM_HIP(panel.alloc(P.n * (2 * 16 + 1)));
-        VTM_HIP(ipiv.alloc(P.n));
-    }
-    VTM_HIP(h->c64.upload(P.pc, s));
-    VTM_HIP(h->beta64.upload(P.pbeta, s));
-    VTM_HIP(h->gamma64.upload(P.pgamma, s));
     if (P.coupled) {
         VTM_HIP(h->brow.upload(P.brow, s));
         VTM_HIP(h->bcol.upload(P.bcol, s));
         VTM_HIP(h->port_row.upload(P.port_row, s));
-        VTM_HIP(h->bval64.upload(P.bval, s));
-        if (o.precision != VTM_FP64) VTM_HIP(h->bval32.upload(to_float(P.bval), s));
     }
     if (o.precision == VTM_FP64) {
         VTM_HIP(h->a64[0].alloc(P.nports * nr));
         VTM_HIP(h->a64[1].alloc(P.nports * nr));
         VTM_HIP(vtm::launch_fill<double>(P.nports * nr, 0.0, h->a64[0].p, s));
-        if (h->tiles) {
-            VTM_HIP(h->K64.alloc(nm));
-            if (!P.symmetric) VTM_HIP(h->K64T.alloc(nm));
-            VTM_HIP(vtm::launch_setup_tiles<double>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->mofs.p,
-                                                    h->rowptr.p, h->col.p, h->val.p, h->dmod.p, h->K64.p, inv64.p,
-                                                    panel.p, ipiv.p, h->flag.p, s, h->K64T.p));
-        } else {
-            VTM_HIP(h->K64.alloc(nk));
-            VTM_HIP(vtm::launch_setup<double>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
-                                              h->val.p, h->dmod.p, h->K64.p, inv64.p, panel.p, ipiv.p, h->flag.p,
-                                              s));
-        }
     } else {
-        VTM_HIP(h->c32.upload(to_float(P.pc), s));
-        VTM_HIP(h->beta32.upload(to_float(P.pbeta), s));
-        VTM_HIP(h->gamma32.upload(to_float(P.pgamma), s));
         VTM_HIP(h->a32[0].alloc(P.nports * nr));
         VTM_HIP(h->a32[1].alloc(P.nports * nr));
         VTM_HIP(vtm::launch_fill<float>(P.nports * nr, 0.0f, h->a32[0].p, s));
@@ -1355,130 +1483,34 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
         else
             VTM_HIP(h->b32.alloc(P.n * nr));
         VTM_HIP(h->d32.alloc(P.n * nr));
-        if (h->tiles) {
-            VTM_HIP(h->Kbf.alloc(nm));
-            if (!P.symmetric) VTM_HIP(h->KbfT.alloc(nm));
-            VTM_HIP(vtm::launch_setup_tiles<__bf16>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->mofs.p,
-                                                    h->rowptr.p, h->col.p, h->val.p, h->dmod.p, h->Kbf.p, inv64.p,
-                                                    panel.p, ipiv.p, h->flag.p, s, h->KbfT.p));
-        } else {
-            VTM_HIP(h->K32.alloc(nk));
-            VTM_HIP(vtm::launch_setup<float>(int(P.S), P.max_ns, h->sub_off.p, h->kofs.p, h->rowptr.p, h->col.p,
-                                             h->val.p, h->dmod.p, h->K32.p, inv64.p, panel.p, ipiv.p, h->flag.p,
-                                             s));
-        }
     }
-    VTM_HIP(hipStreamSynchronize(s));
-    int flag = 0;
-    VTM_HIP(hipMemcpyAsync(&flag, h->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    VTM_HIP(hipStreamSynchronize(s));
-    if (flag & 1) return fail(VTM_E_SINGULAR, "a sub-circuit matrix is singular");
-    // port-to-port operators from the stored inverses
+    // which port-to-port operators the handle keeps (they depend on the pattern only)
     h->pp = o.local_form >= 1 && !h->tiles && P.nports > 0;
     // the port-node forms assume diagonal lines (beta and gamma per port)
     h->pps = h->pp && !P.coupled && o.local_form == 1 && P.symmetric && P.max_npn <= 64 && P.max_ports <= 64;
     const size_t ppn_lds = 2 * size_t(P.max_npn) * (o.precision == VTM_FP64 ? 8 : 4) + size_t(P.max_ports) * 4;
     h->ppn = h->pp && !h->pps && !P.coupled && o.local_form == 1 && P.sqn_entries < P.sq_entries &&
              ppn_lds <= 65536;
-    // batched form: port-to-port operators in tile order, built from the FP64 inverses in inv64
     const int qpad = vtm::tile_pad(P.max_ports);
     h->ppb = o.local_form >= 1 && h->tiles && P.nports > 0 &&
              (o.precision == VTM_FP64 ? vtm::pp_lds_bytes<double>(qpad, 16, false)
                                       : vtm::pp_lds_bytes<__bf16>(qpad, 16, false)) <= h->lds_limit;
+    const bool fp64 = o.precision == VTM_FP64;
     if (h->ppb) {
         VTM_HIP(h->qmofs.upload(P.qmofs, s));
-        const int64_t nq = P.qmofs[P.S];
-        if (o.precision == VTM_FP64) {
-            VTM_HIP(h->M64t.alloc(nq));
-            VTM_HIP(h->h64.alloc(P.nports * nr));
-            VTM_HIP(vtm::launch_port_matrix_tiles<double>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p,
-                                                          h->port_node.p, h->c64.p, h->beta64.p, h->gamma64.p,
-                                                          inv64.p, h->qmofs.p, h->M64t.p, s, h->coupling<double>()));
-        } else {
-            VTM_HIP(h->Mbt.alloc(nq));
-            VTM_HIP(h->h32.alloc(P.nports * nr));
-            VTM_HIP(vtm::launch_port_matrix_tiles<__bf16>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p,
-                                                          h->port_node.p, h->c64.p, h->beta64.p, h->gamma64.p,
-                                                          inv64.p, h->qmofs.p, h->Mbt.p, s, h->coupling<double>()));
-        }
-        VTM_HIP(hipStreamSynchronize(s));
+        VTM_HIP(fp64 ? h->h64.alloc(P.nports * nr) : h->h32.alloc(P.nports * nr));
     }
-    if (h->pp || h->ppb) {
-        VTM_HIP(h->pn_pfirst.upload(P.pn_pfirst, s));
-        VTM_HIP(h->pg64.upload(P.pg, s));
-        VTM_HIP(h->pgd64.upload(P.pgd, s));
-    }
-    if (h->ppn) {
+    if (h->pp || h->ppb) VTM_HIP(h->pn_pfirst.upload(P.pn_pfirst, s));
+    if (h->ppn || h->pps) {
         VTM_HIP(h->pn_off.upload(P.pn_off, s));
         VTM_HIP(h->pn_node.upload(P.pn_node, s));
-        VTM_HIP(h->nofs.upload(P.nofs, s));
-        const int64_t nn = P.nofs[P.S];
-        if (o.precision == VTM_FP64) {
-            VTM_HIP(h->N64.alloc(nn));
-            VTM_HIP(h->h64.alloc(P.nports));
-            VTM_HIP(vtm::launch_port_node_dense<double>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p, h->pn_node.p,
-                                                        h->K64.p, h->nofs.p, h->N64.p, false, s));
-            if (!P.symmetric) {
-                VTM_HIP(h->N64T.alloc(nn));
-                VTM_HIP(vtm::launch_port_node_dense<double>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p,
-                                                            h->pn_node.p, h->K64.p, h->nofs.p, h->N64T.p, true, s));
-            }
-        } else {
-            VTM_HIP(h->N32.alloc(nn));
-            VTM_HIP(h->h32.alloc(P.nports));
-            VTM_HIP(vtm::launch_port_node_dense<float>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p, h->pn_node.p,
-                                                       h->K32.p, h->nofs.p, h->N32.p, false, s));
-            if (!P.symmetric) {
-                VTM_HIP(h->N32T.alloc(nn));
-                VTM_HIP(vtm::launch_port_node_dense<float>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p,
-                                                           h->pn_node.p, h->K32.p, h->nofs.p, h->N32T.p, true, s));
-            }
-        }
-        VTM_HIP(hipStreamSynchronize(s));
-    } else if (h->pps) {
-        VTM_HIP(h->pn_off.upload(P.pn_off, s));
-        VTM_HIP(h->pn_node.upload(P.pn_node, s));
-        VTM_HIP(h->sofs.upload(P.sofs, s));
-        std::vector<double> Wp;
-        if (!P.uniform_W) {  // line admittance per port (both ports of a wire share it)
-            Wp.resize(P.nports);
-            for (int64_t q = 0; q < P.nports; ++q) Wp[P.abi2port[q]] = P.wW[q / 2];
-        }
-        const int64_t nsp = P.sofs[P.S];
-        if (o.precision == VTM_FP64) {
-            VTM_HIP(h->S64.alloc(nsp));
-            VTM_HIP(h->h64.alloc(P.nports));
-            if (!P.uniform_W) VTM_HIP(h->W64p.upload(Wp, s));
-            VTM_HIP(vtm::launch_fill<double>(nsp, double(0), h->S64.p, s));  // pads stay zero
-            VTM_HIP(vtm::launch_port_node_matrix<double>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p,
-                                                         h->pn_node.p, h->K64.p, h->sofs.p, h->S64.p, s));
-        } else {
-            VTM_HIP(h->S32.alloc(nsp));
-            VTM_HIP(h->h32.alloc(P.nports));
-            if (!P.uniform_W) VTM_HIP(h->W32p.upload(to_float(Wp), s));
-            VTM_HIP(vtm::launch_fill<float>(nsp, float(0), h->S32.p, s));  // pads stay zero
-            VTM_HIP(vtm::launch_port_node_matrix<float>(int(P.S), h->sub_off.p, h->kofs.p, h->pn_off.p,
-                                                        h->pn_node.p, h->K32.p, h->sofs.p, h->S32.p, s));
-        }
-        VTM_HIP(hipStreamSynchronize(s));
+        VTM_HIP(h->ppn ? h->nofs.upload(P.nofs, s) : h->sofs.upload(P.sofs, s));
     } else if (h->pp) {
         VTM_HIP(h->pofs.upload(P.pofs, s));
-        const int64_t npm = P.pofs[P.S];
-        if (o.precision == VTM_FP64) {
-            VTM_HIP(h->M64.alloc(npm));
-            VTM_HIP(h->h64.alloc(P.nports));
-            VTM_HIP(vtm::launch_port_matrix<double>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p, h->port_node.p,
-                                                    h->c64.p, h->beta64.p, h->gamma64.p, h->K64.p, h->pofs.p,
-                                                    h->M64.p, s, h->coupling<double>()));
-        } else {
-            VTM_HIP(h->M32.alloc(npm));
-            VTM_HIP(h->h32.alloc(P.nports));
-            VTM_HIP(vtm::launch_port_matrix<float>(int(P.S), h->sub_off.p, h->kofs.p, h->port_off.p, h->port_node.p,
-                                                   h->c64.p, h->beta64.p, h->gamma64.p, h->K32.p, h->pofs.p,
-                                                   h->M32.p, s, h->coupling<double>()));
-        }
-        VTM_HIP(hipStreamSynchronize(s));
     }
+    if (h->pp) VTM_HIP(fp64 ? h->h64.alloc(P.nports) : h->h32.alloc(P.nports));
+
+    if ((st = build_values(h.get())) != VTM_OK) return st;
     if (h->tiles) {
         st = autotune(h.get());
         if (st != VTM_OK) return st;
@@ -1530,6 +1562,21 @@ vtm_status vtm_grad(vtm_handle h, const double* x, const double* lambda, int32_t
                                          h->stream));
     VTM_HIP(hipStreamSynchronize(h->stream));
     return VTM_OK;
+}
+
+vtm_status vtm_refresh(vtm_handle h, const double* val, const double* Z, int64_t nZ) {
+    if (!h) return fail(VTM_E_ARG, "null handle");
+    VTM_HIP(hipSetDevice(h->device));
+    VTM_HIP(hipStreamSynchronize(h->stream));
+    std::string err;
+    vtm_status st = vtm::refresh_plan(h->plan, val, h->a_nnz, Z, Z ? nZ : 0, err);
+    if (st != VTM_OK) return fail(st, err);
+    // captured check intervals hold kernel arguments, some of which (the per-port W of
+    // the packed form) may now live elsewhere: capture them again when next needed
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+    h->waves_set = false;
+    return build_values(h);
 }
 
 vtm_status vtm_get_waves(vtm_handle h, double* waves, int32_t nrhs) {

@@ -31,6 +31,13 @@ struct Entry {
     double v;
 };
 
+// an entry of the caller's CSR while its row is merged: column, value, index
+struct SrcEntry {
+    int32_t c;
+    double v;
+    int32_t k;
+};
+
 }  // namespace
 
 vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, int64_t nZ,
@@ -115,28 +122,54 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
     }
 
     // ---- rows with merged duplicates and sorted columns (old numbering) -------
+    // The order in which the caller's entries are summed is recorded (src_*) so
+    // that vtm_refresh can merge new values the same way without sorting again.
     std::vector<int64_t> mrow(n + 1, 0);
     std::vector<Entry> ment;
     ment.reserve(nnz);
+    const bool record = !explicit_lines;
+    std::vector<int32_t> src_merged;  // per summed position: merged entry (before renumbering), -1 if dropped
+    if (record) {
+        P.src_ent.resize(nnz);
+        P.src_flag.resize(nnz);
+        src_merged.resize(nnz);
+    }
     {
-        std::vector<Entry> row;
+        std::vector<SrcEntry> row;
+        std::vector<int32_t> run_of;  // per merged entry of the row (before dropping zeros): kept index or -1
+        int64_t pos = 0;
         for (int64_t i = 0; i < n; ++i) {
             row.clear();
-            for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) row.push_back({A->col[k], A->val[k]});
-            std::sort(row.begin(), row.end(), [](const Entry& a, const Entry& b) { return a.c < b.c; });
+            for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k)
+                row.push_back({A->col[k], A->val[k], int32_t(k)});
+            std::sort(row.begin(), row.end(), [](const SrcEntry& a, const SrcEntry& b) { return a.c < b.c; });
             size_t start = ment.size();
-            for (const Entry& e : row) {
-                if (ment.size() > start && ment.back().c == e.c)
+            const int64_t pos0 = pos;
+            for (const SrcEntry& e : row) {
+                const bool first = !(ment.size() > start && ment.back().c == e.c);
+                if (!first)
                     ment.back().v += e.v;
                 else
-                    ment.push_back(e);
+                    ment.push_back({e.c, e.v});
+                if (record) {
+                    P.src_ent[pos] = e.k;
+                    P.src_flag[pos] = uint8_t((first ? 1 : 0) | (e.c == i ? 2 : 0));
+                    src_merged[pos] = int32_t(ment.size() - 1 - start);  // run index inside the row for now
+                }
+                ++pos;
             }
             // explicit zeros off the diagonal couple nothing
             size_t w = start;
+            run_of.assign(ment.size() - start, -1);
             for (size_t k = start; k < ment.size(); ++k)
-                if (ment[k].v != 0.0 || ment[k].c == i) ment[w++] = ment[k];
+                if (ment[k].v != 0.0 || ment[k].c == i) {
+                    run_of[k - start] = int32_t(w);
+                    ment[w++] = ment[k];
+                }
             ment.resize(w);
             mrow[i + 1] = int64_t(ment.size());
+            if (record)
+                for (int64_t q = pos0; q < pos; ++q) src_merged[q] = run_of[src_merged[q]];
         }
     }
 
@@ -321,22 +354,148 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
     P.rowptr.assign(n + 1, 0);
     P.col.resize(ment.size());
     P.val.resize(ment.size());
+    std::vector<int32_t> m2r(record ? ment.size() : 0);  // merged entry -> renumbered entry
     {
-        std::vector<Entry> row;
+        std::vector<SrcEntry> row;  // k: the merged entry
         int64_t w = 0;
         for (int64_t r = 0; r < n; ++r) {
             const int32_t i = P.perm[r];
             row.clear();
-            for (int64_t k = mrow[i]; k < mrow[i + 1]; ++k) row.push_back({P.iperm[ment[k].c], ment[k].v});
-            std::sort(row.begin(), row.end(), [](const Entry& a, const Entry& b) { return a.c < b.c; });
-            for (const Entry& e : row) {
+            for (int64_t k = mrow[i]; k < mrow[i + 1]; ++k)
+                row.push_back({P.iperm[ment[k].c], ment[k].v, int32_t(k)});
+            std::sort(row.begin(), row.end(), [](const SrcEntry& a, const SrcEntry& b) { return a.c < b.c; });
+            for (const SrcEntry& e : row) {
                 P.col[w] = e.c;
                 P.val[w] = e.v;
+                if (record) m2r[e.k] = int32_t(w);
                 ++w;
             }
             P.rowptr[r + 1] = int32_t(w);
         }
     }
+    if (record) {
+        P.src_dst.resize(nnz);
+        for (int64_t q = 0; q < nnz; ++q) P.src_dst[q] = src_merged[q] < 0 ? -1 : m2r[src_merged[q]];
+    }
+    return VTM_OK;
+}
+
+// New values of the caller's A on the pattern the plan was built from, merged
+// in the recorded order (so bitwise as build_plan merges them), then the cut
+// wires' conductances, the port coefficients and the diagonal changes as
+// build_plan forms them.  The plan is changed only when every check passes.
+vtm_status refresh_plan(Plan& P, const double* val, int64_t nnz, const double* Z, int64_t nZ, std::string& err) {
+    if (P.vertex || int64_t(P.src_ent.size()) != nnz) {
+        err = P.vertex ? "refresh applies to handles torn along a node partition (vtm_setup)"
+                       : "nnz differs from the A the handle was set up with";
+        return P.vertex ? VTM_E_UNSUPPORTED : VTM_E_ARG;
+    }
+    if (nnz > 0 && !val) {
+        err = "null values";
+        return VTM_E_ARG;
+    }
+    std::vector<double> nv(P.val.size());
+    double cur = 0.0;
+    int32_t dst = -1;
+    bool diag = false;
+    auto close = [&]() -> bool {  // false: the merged entry changes the pattern
+        if (dst >= 0) {
+            if (cur == 0.0 && !diag) return false;
+            nv[dst] = cur;
+        } else if (cur != 0.0) {
+            return false;
+        }
+        return true;
+    };
+    for (int64_t q = 0; q < nnz; ++q) {
+        const double v = val[P.src_ent[q]];
+        if (!std::isfinite(v)) {
+            err = "non-finite matrix entry";
+            return VTM_E_ARG;
+        }
+        if (P.src_flag[q] & 1) {
+            if (q > 0 && !close()) {
+                err = "the new values change which off-diagonal entries are zero (the sparsity pattern)";
+                return VTM_E_ARG;
+            }
+            cur = v;
+            dst = P.src_dst[q];
+            diag = (P.src_flag[q] & 2) != 0;
+        } else {
+            cur += v;
+        }
+    }
+    if (nnz > 0 && !close()) {
+        err = "the new values change which off-diagonal entries are zero (the sparsity pattern)";
+        return VTM_E_ARG;
+    }
+    // value at renumbered (r, c), which the pattern holds
+    auto at = [&](int32_t r, int32_t c) -> int64_t {
+        auto lo = P.col.begin() + P.rowptr[r], hi = P.col.begin() + P.rowptr[r + 1];
+        auto it = std::lower_bound(lo, hi, c);
+        return (it == hi || *it != c) ? -1 : int64_t(it - P.col.begin());
+    };
+    bool sym = true;
+    for (int64_t r = 0; r < P.n && sym; ++r)
+        for (int32_t k = P.rowptr[r]; k < P.rowptr[r + 1]; ++k) {
+            const int64_t t = at(P.col[k], int32_t(r));
+            if (t < 0 || nv[t] != nv[k]) {
+                sym = false;
+                break;
+            }
+        }
+    if (sym != P.symmetric) {
+        err = "the new values change whether A is symmetric (the handle's local forms depend on it)";
+        return VTM_E_UNSUPPORTED;
+    }
+    const int64_t nw = P.nwires;
+    std::vector<double> wg(nw), wW = P.wW;
+    for (int64_t e = 0; e < nw; ++e) {
+        const int32_t r = P.iperm[P.wi[e]], c = P.iperm[P.wj[e]];
+        const double v = nv[at(r, c)], vt = nv[at(c, r)];
+        if (v != vt || !(v < 0.0)) {
+            err = "coupling between nodes " + std::to_string(P.wi[e]) + " and " + std::to_string(P.wj[e]) +
+                  " in different sub-circuits is not a symmetric positive conductance";
+            return VTM_E_UNTEARABLE;
+        }
+        wg[e] = -v;
+    }
+    if (Z && nZ > 0) {
+        if (nZ != 1 && nZ != nw) {
+            err = "nZ must be 0, 1 or the number of cut wires (" + std::to_string(nw) + ")";
+            return VTM_E_ARG;
+        }
+        for (int64_t e = 0; e < nw; ++e) {
+            const double z = Z[nZ == 1 ? 0 : e];
+            if (!(z > 0.0) || !std::isfinite(z)) {
+                err = "line impedance must be positive and finite";
+                return VTM_E_ARG;
+            }
+            wW[e] = 1.0 / z;
+        }
+    }
+    // commit, then the port quantities in the order build_plan forms them
+    P.val.swap(nv);
+    P.wg.swap(wg);
+    P.wW.swap(wW);
+    const int64_t np = P.nports;
+    std::vector<int32_t> port2abi(np);
+    for (int64_t q = 0; q < np; ++q) port2abi[P.abi2port[q]] = int32_t(q);
+    P.dmod.assign(P.n, 0.0);
+    for (int64_t p = 0; p < np; ++p) {
+        const int64_t q = port2abi[p], e = q / 2;
+        const PortCoef k = port_coef(P.wg[e], P.wW[e]);
+        P.pc[p] = k.c;
+        P.pbeta[p] = k.beta;
+        P.pgamma[p] = k.gamma;
+        P.pg[p] = P.wg[e];
+        P.pgd[p] = k.G - P.wg[e];
+        const int32_t node = (q & 1) ? P.wj[e] : P.wi[e];
+        P.dmod[P.iperm[node]] += k.G - P.wg[e];
+    }
+    P.uniform_W = true;
+    for (int64_t e = 1; e < nw; ++e)
+        if (P.wW[e] != P.wW[0]) P.uniform_W = false;
     return VTM_OK;
 }
 

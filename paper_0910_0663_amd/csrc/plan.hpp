@@ -62,6 +62,12 @@ struct Plan {
     // The untorn A renumbered (rows and columns), duplicates merged, columns sorted.
     std::vector<int32_t> rowptr, col;
     std::vector<double> val;
+    // How the caller's entries became it (not for tearing at nodes): the caller's
+    // entry indices in the order they are summed, per position a flag (bit 0: first
+    // entry of a merged entry, bit 1: a diagonal one) and the renumbered entry the
+    // sum goes to (-1: an explicit zero off the diagonal, dropped).
+    std::vector<int32_t> src_ent, src_dst;
+    std::vector<uint8_t> src_flag;
 
     // Tearing at interfacial nodes (build_plan_vertex): the plan above describes the
     // expanded system (every interfacial node replaced by two twins); these map it
@@ -139,6 +145,15 @@ vtm_status partial_schur_vertex(const VertexSplit& X, const int32_t* iface, cons
 vtm_status build_plan_vertex(const vtm_csr* A, const int32_t* label, const int32_t* iface,
                              const int32_t* sides, int64_t n_iface, const double* W, int64_t nW,
                              Plan& plan, std::string& err, const vtm_csr* Wc = nullptr);
+
+// New values for the caller's A on the same pattern (val: nnz values in the
+// caller's entry order) and optionally new line impedances (nZ 0: keep; 1 or
+// n_wires as for build_plan): updates the renumbered values, the cut wires'
+// conductances, the port coefficients and the diagonal changes exactly as
+// build_plan would form them.  Errors: a pattern change (an off-diagonal entry
+// becoming or ceasing to be zero), a change of symmetry, an untearable cut, a
+// plan built for tearing at nodes; the plan is unchanged then.
+vtm_status refresh_plan(Plan& plan, const double* val, int64_t nnz, const double* Z, int64_t nZ, std::string& err);
 
 // Renumbered A^T in compressed rows (columns sorted).
 void transpose_csr(const Plan& plan, std::vector<int32_t>& rowptr, std::vector<int32_t>& col,

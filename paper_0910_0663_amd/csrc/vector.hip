@@ -281,6 +281,7 @@ hipError_t launch_grad(int64_t m, int n, int nrhs, const double* x, const double
 
 template hipError_t launch_fill<double>(int64_t, double, double*, hipStream_t);
 template hipError_t launch_fill<float>(int64_t, float, float*, hipStream_t);
+template hipError_t launch_fill<int>(int64_t, int, int*, hipStream_t);
 template hipError_t launch_convert<double, float>(int64_t, const double*, float*, hipStream_t);
 template hipError_t launch_convert<float, double>(int64_t, const float*, double*, hipStream_t);
 template hipError_t launch_convert<double, __bf16>(int64_t, const double*, __bf16*, hipStream_t);

@@ -70,28 +70,156 @@ def measured_traffic(launches_bytes):
     return c.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(seconds):
+def machine():
+    """The host the CPU baseline ran on: usable cores and CPU model."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"nproc": cores, "cpu_model": model}
+
+
+def cpu_baseline(seconds, full_sweeps):
     """The oracle as it stands, on a 512 x 512 grid of the same kind (4,096 of the
     65,536 sub-circuits): sweeps timed after the (untimed) tear and factorisation,
-    the rate scaled by 4,096 / 65,536 to the full workload."""
-    import numpy as np
+    the rate scaled by 4,096 / 65,536 to the full workload.  Run twice: BLAS
+    threads limited to one, then to every usable core (the oracle's sweep is a
+    SuperLU triangular solve of the block-diagonal local systems and sparse
+    products, which run on one core either way).  Time to tolerance is
+    extrapolated: per-sweep time at full size times the full workload's sweep
+    count.  Context: a sparse LU of the untorn sample (the direct work VTM
+    avoids), with its solve."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    from threadpoolctl import threadpool_limits
     import oracle
     import workloads
     w = workloads.make(2, dims=(512, 512))
     torn = oracle.tear_wires(w.A, w.part, w.Z)
     sw = oracle.Sweeper(torn)
-    t = time.perf_counter()
-    oracle.vtm_solve(torn, w.A, w.b, 0.0, max_sweeps=2, sweeper=sw)
-    per = (time.perf_counter() - t) / 2
-    k = max(3, int(seconds / max(per, 1e-6)))
-    t = time.perf_counter()
-    r = oracle.vtm_solve(torn, w.A, w.b, 0.0, max_sweeps=k, sweeper=sw)
-    dt = time.perf_counter() - t
+    m = machine()
+    runs = {}
+    for label, threads in (("1_thread", 1), ("all_cores", m["nproc"])):
+        with threadpool_limits(limits=threads):
+            t = time.perf_counter()
+            oracle.vtm_solve(torn, w.A, w.b, 0.0, max_sweeps=2, sweeper=sw)
+            per = (time.perf_counter() - t) / 2
+            k = max(3, int(0.5 * seconds / max(per, 1e-6)))
+            t = time.perf_counter()
+            r = oracle.vtm_solve(torn, w.A, w.b, 0.0, max_sweeps=k, sweeper=sw)
+            dt = time.perf_counter() - t
+        runs[label] = (r.sweeps, dt, threads)
     scale = w.n_sub / 65536
-    return {"value": round(r.sweeps / dt * scale, 4), "unit": "sweeps/s", "cores": 1, "kind": "oracle",
-            "sample": f"512x512 grid of the same kind ({w.n_sub} sub-circuits of 8x8), {r.sweeps} sweeps "
-                      f"in {dt:.1f} s after tearing, rate scaled by {w.n_sub}/65536; "
-                      f"single-threaded SuperLU and scipy.sparse"}
+    sweeps1, dt1, _ = runs["1_thread"]
+    sweepsN, dtN, nth = runs["all_cores"]
+    rate1, rateN = sweeps1 / dt1 * scale, sweepsN / dtN * scale
+    t = time.perf_counter()
+    lu = spla.splu(sp.csc_matrix(w.A), permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0,
+                   options=dict(SymmetricMode=True))
+    lu.solve(w.b.ravel())
+    splu_s = time.perf_counter() - t
+    best = max(rate1, rateN)
+    return {"value": round(best, 4), "unit": "sweeps/s", "cores": nth if rateN >= rate1 else 1, "kind": "oracle",
+            "sample": f"512x512 grid of the same kind ({w.n_sub} sub-circuits of 8x8): {sweeps1} sweeps in "
+                      f"{dt1:.1f} s with 1 BLAS thread, {sweepsN} in {dtN:.1f} s with {nth}; rates scaled by "
+                      f"{w.n_sub}/65536 to the full workload",
+            "machine": m,
+            "sweeps_per_s_1_thread": round(rate1, 4), "sweeps_per_s_all_cores": round(rateN, 4),
+            "time_to_tol_s_extrapolated": round(full_sweeps / best, 1),
+            "time_to_tol_note": f"extrapolated: {full_sweeps} sweeps (the full workload's count) at the "
+                                f"full-size per-sweep time",
+            "splu_sample_s": round(splu_s, 2),
+            "splu_note": "sparse LU and solve of the untorn 512x512 sample (SuperLU, minimum-degree ordering "
+                         "of A + A^T), the direct work VTM avoids; context only"}
+
+
+def direct_reference(A, b, cols=None):
+    """x* = A^-1 b for the accuracy figures, by a sparse LU of the untorn A
+    (scipy's SuperLU; symmetric minimum-degree ordering when A is symmetric),
+    for all right-hand sides or the given columns."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    A = sp.csc_matrix(A)
+    sym = abs(A - A.T).max() == 0
+    lu = (spla.splu(A, permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0, options=dict(SymmetricMode=True))
+          if sym else spla.splu(A))
+    bb = np.atleast_2d(b) if cols is None else np.atleast_2d(b)[cols]
+    return lu.solve(np.ascontiguousarray(bb.T)).T
+
+
+def rel_error(x, xs):
+    """max over columns of ||x - x*||_2 / ||x*||_2"""
+    x, xs = np.atleast_2d(x), np.atleast_2d(xs)
+    return float((np.linalg.norm(x - xs, axis=1) / np.linalg.norm(xs, axis=1)).max())
+
+
+def hbm_resident_roofline(vtm, torch, workloads, sweeps=256):
+    """The packed port-to-port sweep on a 4096 x 4096 grid of the bench kind
+    (262,144 sub-circuits of 8 x 8): about 1.2 GB per sweep, 4.4 times the
+    256 MiB Infinity Cache, so the fraction is an HBM one.  A fixed run of
+    sweeps (every sweep after the first port-to-port; no check before the
+    last), timed by HIP events around each run of port-to-port sweeps."""
+    t = time.perf_counter()
+    w = workloads.make(2, dims=(4096, 4096))
+    gen_s = time.perf_counter() - t
+    s = vtm.Solver(w.A, w.part, w.Z, check_every=sweeps, max_sweeps=sweeps, adaptive_checks=False, timing=2)
+    b = torch.as_tensor(w.b, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(b)
+    rep = None
+    for _ in range(2):  # the first run warms up
+        try:
+            s.solve(b, 1e-300, x)
+        except vtm.VTMError as e:
+            rep = e.report
+    nbytes = s.port_sweep_bytes
+    us = rep.pp_kernel_ms / rep.pp_launches * 1e3
+    gbs = nbytes / (us * 1e-6) / 1e9
+    out = {"workload": f"4096x4096 grid, {s.n_sub} sub-circuits of 8x8, log-uniform g, FP64, {sweeps} sweeps",
+           "bound": "hbm", "kernel": "k_sweep_pps<double,double>", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": nbytes,
+           "avg_launch_us": round(us, 2), "launches_timed": int(rep.pp_launches),
+           "working_set_vs_infinity_cache": round(nbytes / float(256 << 20), 2)}
+    s.close()
+    log(f"4096^2 packed sweep: {us:.1f} us per sweep, {gbs:.0f} GB/s, frac {gbs / HBM_PEAK_GBS:.3f} "
+        f"(workload {gen_s:.0f} s to generate)")
+    return out
+
+
+def refresh_timing(vtm, torch, w, s, b, x, reps=3):
+    """vtm_refresh on the bench workload: every branch conductance scaled by
+    U[0.8, 1.25] (the same pattern), timed from the host call to its return
+    (host merge of the values, port coefficients, uploads, inverses, operators),
+    then a solve; beside a fresh vtm_setup of the same values."""
+    g = w.g * np.random.default_rng(1).uniform(0.8, 1.25, w.g.size)
+    A2 = workloads_nodal(w, g)
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s.refresh(A2)
+        times.append(time.perf_counter() - t)
+    _, rep = s.solve(b, w.tol, x)
+    host_rel = float(host_relres(A2, w.b, x.cpu().numpy()).max())
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    fresh = vtm.Solver(A2, w.part, w.Z, check_every=8)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+    fresh.close()
+    s.refresh(w.A)  # back to the bench values
+    return {"refresh_s": round(min(times), 4), "setup_s_same_values": round(setup_s, 3),
+            "solve_after_refresh_sweeps": rep.sweeps, "solve_after_refresh_relres": host_rel}
+
+
+def workloads_nodal(w, g):
+    import workloads
+    return workloads.nodal_matrix(w.n, w.edges, g, w.ground, w.vccs)
 
 
 def measured_read_peak(torch, gib=4, reps=5):
@@ -172,11 +300,17 @@ def mixed_and_batched(vtm, torch, workloads):
     rel64 = float(host_relres(w.A, w.b, x64.cpu().numpy()).max())
     assert rel16 <= w.tol and rel64 <= w.tol, (rel16, rel64)
     diff = float(((x16 - x64).norm(dim=1) / x64.norm(dim=1)).max())
+    cols = list(range(0, 64, 8))   # 8 of the 64 columns: a direct solve of all 64 takes ~40 s on the host
+    xs = direct_reference(w.A, w.b, cols)
+    err16 = rel_error(x16.cpu().numpy()[cols], xs)
+    err64 = rel_error(x64.cpu().numpy()[cols], xs)
     res["batched_bf16_vs_fp64"] = {
         "workload": f"1024x1024 grid, {w.n_sub} uneven sub-circuits (8..24 nodes a side), 64 RHS N(0,1), tol 1e-8",
         "bf16_refine_ms": round(t16, 2), "fp64_batched_ms": round(t64, 2), "speedup": round(t64 / t16, 3),
         "bf16_sweeps": r16.sweeps, "bf16_outer": r16.outer, "fp64_sweeps": r64.sweeps,
         "bf16_relres": rel16, "fp64_relres": rel64, "bf16_vs_fp64_rel_error": diff,
+        "bf16_error_vs_direct": err16, "fp64_error_vs_direct": err64,
+        "error_note": "max over columns 0, 8, ..., 56 of ||x - x*|| / ||x*||, x* by sparse LU of A (SuperLU)",
         "batch_shape_bf16": list(r16.batch_shape), "batch_shape_fp64": list(r64.batch_shape)}
     # the same 64 right-hand sides as 64 single-column FP64 solves (port-to-port form)
     s1 = vtm.Solver(w.A, w.part, w.Z, precision="fp64", nrhs_max=1)
@@ -207,13 +341,22 @@ def mixed_and_batched(vtm, torch, workloads):
     rel32 = float(host_relres(w.A, w.b, x32.cpu().numpy()).max())
     rel64 = float(host_relres(w.A, w.b, x64.cpu().numpy()).max())
     assert rel32 <= w.tol and rel64 <= w.tol, (rel32, rel64)
+    sref = vtm.Solver(w.A, w.part, w.Z)
+    xref, _ = sref.solve(torch.as_tensor(w.b, dtype=torch.float64, device="cuda"), 1e-12)
+    sref.close()
+    xr = xref.cpu().numpy()
+    err32_3d = rel_error(x32.cpu().numpy(), xr)
+    err64_3d = rel_error(x64.cpu().numpy(), xr)
     res["fp32_vs_fp64_3d"] = {
         "workload": f"128^3 7-point grid with {w.vccs[0].size} controlled sources (unsymmetric), "
                     f"{w.n_sub} sub-circuits of 8^3, 1 RHS, tol 1e-8; port-node operators K^-1[N,N] "
                     f"(296 port nodes carry 384 ports)",
         "fp32_refine_ms": round(t32, 2), "fp64_ms": round(t64, 2), "speedup": round(t64 / t32, 3),
         "fp32_sweeps": r32.sweeps, "fp32_outer": r32.outer, "fp64_sweeps": r64.sweeps,
-        "fp32_relres": rel32, "fp64_relres": rel64}
+        "fp32_relres": rel32, "fp64_relres": rel64,
+        "fp32_error_vs_fp64_1e-12": err32_3d, "fp64_error_vs_fp64_1e-12": err64_3d,
+        "error_note": "||x - x_ref|| / ||x_ref|| with x_ref the plain FP64 VTM solve to relative residual "
+                      "1e-12 on the GPU (a sparse LU of this 3-D grid does not fit the host's time budget)"}
     log(f"cfg3: fp32 refine {t32:.1f} ms vs fp64 {t64:.1f} ms: x{t64 / t32:.2f}")
     del x32, x64
     w = workloads.make(5)
@@ -222,11 +365,15 @@ def mixed_and_batched(vtm, torch, workloads):
     rel32 = float(host_relres(w.A, w.b, x32.cpu().numpy()).max())
     rel64 = float(host_relres(w.A, w.b, x64.cpu().numpy()).max())
     assert rel32 <= w.tol and rel64 <= w.tol, (rel32, rel64)
+    xs5 = direct_reference(w.A, w.b)
     res["fp32_vs_fp64"] = {
         "workload": "512x512 grid, 1,024 sub-circuits of 16x16, 1 RHS, tol 1e-8",
         "fp32_refine_ms": round(t32, 3), "fp64_ms": round(t64, 3), "speedup": round(t64 / t32, 3),
         "fp32_sweeps": r32.sweeps, "fp32_outer": r32.outer, "fp64_sweeps": r64.sweeps,
-        "fp32_relres": rel32, "fp64_relres": rel64}
+        "fp32_relres": rel32, "fp64_relres": rel64,
+        "fp32_error_vs_direct": rel_error(x32.cpu().numpy(), xs5),
+        "fp64_error_vs_direct": rel_error(x64.cpu().numpy(), xs5),
+        "error_note": "||x - x*|| / ||x*||, x* by sparse LU of A (SuperLU)"}
     log(f"cfg5: fp32 refine {t32:.2f} ms vs fp64 {t64:.2f} ms: x{t64 / t32:.2f}")
     res["gradient"] = gradient_path(vtm, torch, workloads)
     res["line_admittance_rules_2048sq"] = preconditioners(vtm, torch, workloads)
@@ -363,6 +510,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision / batched comparison")
+    ap.add_argument("--no-hbm", action="store_true", help="skip the 4096x4096 HBM-resident sweep roofline")
+    ap.add_argument("--hbm-only", action="store_true",
+                    help="for profiling: only the 4096x4096 packed sweep run; prints its JSON")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="with --mfma-counters or --hbm-only: end with a 1 GiB device copy (known bytes) to "
+                         "calibrate FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--mfma-counters", action="store_true",
                     help="for MFMA counters: one BF16 and one FP64 batched solve of the 64-RHS workload")
     ap.add_argument("--vertex-only", action="store_true",
@@ -383,6 +536,14 @@ def main():
     import paper_0910_0663_amd as vtm
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+
+    def calibration_copy():
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read, 1 GiB written")
+
     if args.mfma_counters:
         # the 64-RHS workload once in BF16 refinement and once in FP64 batched form (MFMA tiles)
         w4 = workloads.make(4)
@@ -396,6 +557,8 @@ def main():
                          "batch_shape": list(rep4.batch_shape), "port_operator_bytes": s4.port_operator_bytes,
                          "relres": float(host_relres(w4.A, w4.b, x4.cpu().numpy()).max())}
             s4.close()
+        if args.calibrate:
+            calibration_copy()
         print(json.dumps(out), flush=True)
         return
     if args.vertex_only:
@@ -403,6 +566,12 @@ def main():
         return
     if args.batched_only:
         print(json.dumps(mixed_and_batched(vtm, torch, workloads)), flush=True)
+        return
+    if args.hbm_only:
+        r = hbm_resident_roofline(vtm, torch, workloads)
+        if args.calibrate:
+            calibration_copy()
+        print(json.dumps(r), flush=True)
         return
     t = time.perf_counter()
     w = workloads.make(2)
@@ -423,11 +592,7 @@ def main():
             c.solve(b, w.tol, x)
         except vtm.VTMError as e:
             log(f"counter run: {e.name} after {e.report.sweeps} sweeps")
-        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("calibration copy: 1 GiB read, 1 GiB written")
+        calibration_copy()
         return
     for k in range(args.warmup):
         _, rep = s.solve(b, w.tol, x)
@@ -511,12 +676,18 @@ def main():
         },
         "roofline_full_sweep": roof_full,
     }
+    log("refresh of the conductances ...")
+    out["refresh"] = refresh_timing(vtm, torch, w, s, b, x)
+    s.close()
+    if not args.no_hbm:
+        log("HBM-resident packed sweep (4096x4096) ...")
+        out["roofline_hbm_resident"] = hbm_resident_roofline(vtm, torch, workloads)
     if not args.no_mixed:
         log("mixed-precision and batched forms vs plain FP64 ...")
         out["mixed_batched"] = mixed_and_batched(vtm, torch, workloads)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, reps[-1].sweeps)
     print(json.dumps(out), flush=True)
 
 

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libvtm.so")
 
-SOURCES = ["plan.cpp", "setup.hip", "sweep.hip", "ports.hip", "mfma.hip", "residual.hip", "vector.hip", "api.hip"]
+SOURCES = ["plan.cpp", "host_api.cpp", "setup.hip", "sweep.hip", "ports.hip", "mfma.hip", "residual.hip", "vector.hip", "api.hip"]
 
 # -packed-fp32-ops: keep the device compiler from emitting packed FP32 ALU ops.
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

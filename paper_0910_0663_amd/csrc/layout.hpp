@@ -50,11 +50,7 @@ __host__ __device__ inline void inv_rc(int n, int64_t d, int& r, int& c) {
 // b of a grid of n runs on XCD b % 8.  xcd_block renumbers them so that each XCD
 // takes one contiguous range of logical blocks, and sub-circuits that exchange
 // waves (neighbours in the block order) share an L2.  A bijection on [0, n).
-#ifndef VTM_XCD
-#define VTM_XCD 1
-#endif
 __device__ inline int xcd_block(int b, int n) {
-    if (!VTM_XCD) return b;
     const int x = b & 7, q = n >> 3, r = n & 7;
     return x * q + (x < r ? x : r) + (b >> 3);
 }
@@ -62,7 +58,6 @@ __device__ inline int xcd_block(int b, int n) {
 // The same ranges, each walked backwards: every XCD keeps its logical blocks
 // (and what its L2 holds of them), in the opposite order.
 __device__ inline int xcd_block_reversed(int b, int n) {
-    if (!VTM_XCD) return n - 1 - b;
     const int x = b & 7, q = n >> 3, r = n & 7;
     const int count = q + (x < r ? 1 : 0);  // blocks of XCD x
     return x * q + (x < r ? x : r) + (count - 1 - (b >> 3));

@@ -18,42 +18,16 @@
 #include "layout.hpp"
 #include "tiles.hpp"
 
-// walk the sub-circuits in reverse order on every other port-to-port sweep
-#ifndef VTM_MFMA_ALTERNATE
-#define VTM_MFMA_ALTERNATE 1
-#endif
-// batched port-to-port sweep: h loaded into registers before the product (FP64)
-#ifndef VTM_MFMA_PP_PREFETCH_H
-#define VTM_MFMA_PP_PREFETCH_H 1
-#endif
-// batched sweeps: k tiles of A in flight per wavefront (FP64, BF16)
-#ifndef VTM_MFMA_PD64
-#define VTM_MFMA_PD64 2
-#endif
-#ifndef VTM_MFMA_PD16
-#define VTM_MFMA_PD16 2
-#endif
-// full batched sweep: FP64 k tiles of A in flight per wavefront
-#ifndef VTM_MFMA_FULL_PD64
-#define VTM_MFMA_FULL_PD64 6
-#endif
-// full batched sweep: staging loads issued in rounds (aligned right-hand sides)
-#ifndef VTM_MFMA_FULL_ROUNDS
-#define VTM_MFMA_FULL_ROUNDS 1
-#endif
-#ifndef VTM_MFMA_FULL_SU
-#define VTM_MFMA_FULL_SU 2
-#endif
-// batched sweeps: XCD-contiguous ranges of (sub-circuit, column block)
-#ifndef VTM_MFMA_XCD
-#define VTM_MFMA_XCD 1
-#endif
-// batched port-to-port sweep: 16-byte loads of the incident waves when aligned
-#ifndef VTM_MFMA_PP_VEC
-#define VTM_MFMA_PP_VEC 1
-#endif
-
 namespace vtm {
+
+// batched sweeps: k tiles of A in flight per wavefront (port-to-port FP64, BF16)
+constexpr int kMfmaPD64 = 2;
+constexpr int kMfmaPD16 = 2;
+// full batched sweep: FP64 k tiles of A in flight per wavefront (its inverses are
+// up to 72 k tiles long, the port-to-port operators at most 12)
+constexpr int kMfmaFullPD64 = 6;
+// full batched sweep: right-hand-side items per thread in each round of staging loads
+constexpr int kMfmaFullSU = 2;
 
 namespace {
 
@@ -122,7 +96,7 @@ struct Mma<double> {
 // k tile it loads the NT B fragments once from LDS and its row tiles' A tiles
 // from HBM (the next k tile's A tiles are already in flight), then issues the
 // MFMAs.  epi(row, n, value) receives every element of D (rows < np, n < 16 NT).
-template <typename T, int NT, int RT, int WAVES, int PD64 = VTM_MFMA_PD64, typename Epi>
+template <typename T, int NT, int RT, int WAVES, int PD64 = kMfmaPD64, typename Epi>
 __device__ inline void tile_gemm(const T* Ablk, int np, const T* sb, int bsel, int w, Epi epi) {
     using M = Mma<T>;
     using TV = typename M::TV;
@@ -146,7 +120,7 @@ __device__ inline void tile_gemm(const T* Ablk, int np, const T* sb, int bsel, i
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[j][nt][v] = 0;
         // ring of PD k tiles: tile k sits in abuf[k % PD]; the loads run PD - 1 tiles ahead
-        constexpr int PD = sizeof(T) == 8 ? PD64 : VTM_MFMA_PD16;
+        constexpr int PD = sizeof(T) == 8 ? PD64 : kMfmaPD16;
         typename M::AFrag abuf[PD][RT];
 #pragma unroll
         for (int d = 0; d < PD - 1; ++d)
@@ -208,7 +182,7 @@ __global__ void __launch_bounds__(kBlock)
     // each XCD takes a contiguous range of (sub-circuit, column block): the column
     // blocks of one sub-circuit read its inverse through one L2
     const int nb = int(gridDim.x * gridDim.y), bl = int(blockIdx.x + gridDim.x * blockIdx.y);
-    const int u = VTM_MFMA_XCD ? xcd_block(bl, nb) : bl;
+    const int u = xcd_block(bl, nb);
     const int s = u / int(gridDim.x);
     const int r0 = (u - s * int(gridDim.x)) * rc;
     const int w = min(rc, nrhs - r0);
@@ -240,11 +214,11 @@ __global__ void __launch_bounds__(kBlock)
     __syncthreads();
     const bool vec = (nrhs % V) == 0;
     const int rv = rc / V;
-    if (VTM_MFMA_FULL_ROUNDS && vec) {
+    if (vec) {
         // SU items per thread per round; each item's b load is waited on only after
         // its ports' loads are issued (b is added last), so a round costs about one
         // HBM round trip
-        constexpr int SU = VTM_MFMA_FULL_SU;
+        constexpr int SU = kMfmaFullSU;
         const int tot = np * rv;
         for (int t0 = tid; t0 < tot; t0 += SU * kBlock) {
             TB bv[SU][V];
@@ -322,7 +296,7 @@ __global__ void __launch_bounds__(kBlock)
 
     // 2. X = Kinv B, x stored on the rows the wave update reads (all rows with write_x)
     // (the full inverses are long in k: FP64 keeps more of its tiles in flight)
-    tile_gemm<T, NT, RT, kWaves, VTM_MFMA_FULL_PD64>(K + mofs[s], np, sb, sizeof(T) == 2 ? np : rc, w,
+    tile_gemm<T, NT, RT, kWaves, kMfmaFullPD64>(K + mofs[s], np, sb, sizeof(T) == 2 ? np : rc, w,
                                                      [&](int row, int n, TV v, int) {
         if (row < ns && n < w && (write_x || pcount[row])) x[int64_t(off + row) * nrhs + r0 + n] = v;
     });
@@ -330,7 +304,7 @@ __global__ void __launch_bounds__(kBlock)
 
     // 3. outgoing waves, read back x of the port nodes (written by this workgroup), 4 columns at a time
     const int w4 = (w + 3) / 4;
-    if (VTM_MFMA_FULL_ROUNDS && nrhs % 4 == 0) {
+    if (nrhs % 4 == 0) {
         // whole 4-column chunks (w is a multiple of 4), two per thread per round, all
         // loads of a round issued before its stores
         struct alignas(16) C4 {
@@ -404,9 +378,8 @@ __global__ void __launch_bounds__(WAVES * 64)
     // neighbouring sub-circuits share an L2; every other sweep walks each range
     // backwards (what the previous sweep read last is still in the memory-side cache)
     const int nb = int(gridDim.x * gridDim.y), b = int(blockIdx.x + gridDim.x * blockIdx.y);
-    const bool back = VTM_MFMA_ALTERNATE && reverse;
-    const int u = VTM_MFMA_XCD ? (back ? xcd_block_reversed(b, nb) : xcd_block(b, nb))
-                                  : (back ? nb - 1 - b : b);
+    const bool back = reverse;
+    const int u = back ? xcd_block_reversed(b, nb) : xcd_block(b, nb);
     const int s = u / int(gridDim.x);
     const int r0 = (u - s * int(gridDim.x)) * rc;
     const int w = min(rc, nrhs - r0);
@@ -417,7 +390,7 @@ __global__ void __launch_bounds__(WAVES * 64)
     // product so that the epilogue does not wait on it (when one pass of row tiles
     // covers the operator); BF16 stages h in LDS instead (registers cost occupancy)
     const int lane = tid & 63, wave = tid >> 6;
-    constexpr bool kPre = VTM_MFMA_PP_PREFETCH_H && sizeof(T) == 8;
+    constexpr bool kPre = sizeof(T) == 8;
     const bool one = qp / 16 <= WAVES * RT;   // one pass of row tiles covers the operator
     const bool pre = kPre && one;
     TV hreg[kPre ? RT * NT * 4 : 1];
@@ -442,7 +415,7 @@ __global__ void __launch_bounds__(WAVES * 64)
         }
     // BF16 (HL): h of this block staged in LDS beside the waves (its loads overlap
     // theirs); the launch drops HL when there is no room for it (very large operators)
-    constexpr bool hl = HL && VTM_MFMA_PP_H_LDS && sizeof(T) == 2;
+    constexpr bool hl = HL && sizeof(T) == 2;
     const int hst = rc + 16;
     TV* hs = reinterpret_cast<TV*>(smem + tile_lds_bytes<T>(qp, rc));
     const int sst = pp_stage_stride<T>(qp, rc);
@@ -452,7 +425,7 @@ __global__ void __launch_bounds__(WAVES * 64)
     struct alignas(16) Vec {
         TV e[VW];
     };
-    if (VTM_MFMA_PP_VEC && nrhs % VW == 0) {
+    if (nrhs % VW == 0) {
         // SU vectors per thread per round: all loads of a round are issued before its
         // LDS stores, so a round costs one HBM round trip
         constexpr int SU = 4;

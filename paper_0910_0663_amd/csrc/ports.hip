@@ -372,33 +372,17 @@ template hipError_t launch_sweep_pp<float, float>(int, int, const float*, const 
 // entries of every pair with one coalesced 16-byte (FP64) load and receives
 // S(r - d, r) from lane r - d.
 // ---------------------------------------------------------------------------
-// diagonals each lane holds in flight in the packed sweep (two sub-circuits
-// per wavefront / one); even: whole pairs
-#ifndef VTM_PPS_CH_HALF
-#define VTM_PPS_CH_HALF 8
-#endif
-#ifndef VTM_PPS_CH
-#define VTM_PPS_CH 8
-#endif
-// chunks issued before the first barrier (the rest stream that far ahead)
-#ifndef VTM_PPS_PRE_HALF
-#define VTM_PPS_PRE_HALF 2
-#endif
-#ifndef VTM_PPS_PRE
-#define VTM_PPS_PRE 1
-#endif
-// wavefronts per sub-circuit in the one-sub-circuit form (1: one wavefront, which
-// also streams its chunks; more: k_sweep_pps_split)
-#ifndef VTM_PPS_SPLIT
-#define VTM_PPS_SPLIT 8
-#endif
-// walk the units in reverse order on every other sweep
-#ifndef VTM_PPS_ALTERNATE
-#define VTM_PPS_ALTERNATE 1
-#endif
-
 namespace vtm {
 namespace {
+
+// diagonals per chunk of the packed sweep, each lane's loads of one chunk in
+// flight together (even: whole pairs)
+constexpr int kPpsChunk = 8;
+// chunks issued before the first barrier when two sub-circuits share a wavefront
+// (the rest stream that far ahead)
+constexpr int kPpsPre = 2;
+// wavefronts per sub-circuit when a sub-circuit has 33..64 port nodes (k_sweep_pps_split)
+constexpr int kPpsSplit = 8;
 
 // pair m of diagonals (2m, 2m + 1), rows r = 0 .. k - 2m - 1 each holding both entries
 __host__ __device__ inline int pair_start(int k, int m) { return 2 * m * (k - m + 1); }
@@ -439,9 +423,9 @@ __device__ inline void pps_unit(int unit, int S, const TO* __restrict__ Sp, cons
                                 const TV* __restrict__ h, const TV* __restrict__ a_cur, TV* __restrict__ a_next,
                                 TV* ca, TV* tv, TV* zv, int32_t* pnode) {
     constexpr int L = HALF ? 32 : 64;
-    constexpr int CH = HALF ? VTM_PPS_CH_HALF : VTM_PPS_CH;
+    constexpr int CH = kPpsChunk;
     constexpr int NCH = L / CH;
-    constexpr int PRE = HALF ? VTM_PPS_PRE_HALF : VTM_PPS_PRE;
+    constexpr int PRE = HALF ? kPpsPre : 1;
     static_assert(L % CH == 0 && PRE >= 1 && PRE <= NCH, "diagonal chunks must tile the lanes");
     const int tid = threadIdx.x, r = tid % L, hb = tid - r, half = tid / L;
     const int tb = half * 64;  // this sub-circuit's t region
@@ -539,8 +523,7 @@ __global__ void __launch_bounds__(64)
     // every other sweep walks each XCD's units backwards, so that the operators it
     // reads first are the ones the previous sweep read last (still in the
     // memory-side cache), while each XCD keeps the same units (and its L2)
-    const int unit = VTM_PPS_ALTERNATE && reverse ? xcd_block_reversed(blockIdx.x, gridDim.x)
-                                                  : xcd_block(blockIdx.x, gridDim.x);
+    const int unit = reverse ? xcd_block_reversed(blockIdx.x, gridDim.x) : xcd_block(blockIdx.x, gridDim.x);
     pps_unit<TO, TV, HALF>(unit, S, Sp, sofs, pn_off, pn_pfirst, port_off, port_twin, pc, pW, W, h, a_cur, a_next,
                            ca, tv, zv, pnode);
 }
@@ -558,12 +541,11 @@ __global__ void __launch_bounds__(64 * WV)
                       const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_twin,
                       const TV* __restrict__ pc, const TV* __restrict__ pW, TV W, const TV* __restrict__ h,
                       const TV* __restrict__ a_cur, TV* __restrict__ a_next, int reverse) {
-    constexpr int CH = VTM_PPS_CH, NCH = 64 / CH, LCH = NCH / WV;
+    constexpr int CH = kPpsChunk, NCH = 64 / CH, LCH = NCH / WV;
     static_assert(WV >= 2 && NCH % WV == 0 && CH % 2 == 0, "chunks must split evenly over the wavefronts");
     __shared__ TV ca[64], tv[128], zp[WV][64];
     __shared__ int32_t pnode[64];
-    const int s = VTM_PPS_ALTERNATE && reverse ? xcd_block_reversed(blockIdx.x, gridDim.x)
-                                               : xcd_block(blockIdx.x, gridDim.x);
+    const int s = reverse ? xcd_block_reversed(blockIdx.x, gridDim.x) : xcd_block(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x, r = tid & 63, wv = tid >> 6;
     const int n0 = pn_off[s], k = pn_off[s + 1] - n0;
     const int p0 = port_off[s], q = port_off[s + 1] - p0;
@@ -674,14 +656,9 @@ hipError_t launch_sweep_pps(int S, int max_npn, int max_ports, const TO* Sp, con
     if (max_npn <= 32 && max_ports <= 32)
         return launch_pps<TO, TV, true>(S, Sp, sofs, pn_off, pn_pfirst, port_off, port_twin, pc, pW, W, h, a_cur,
                                         a_next, reverse, st);
-    if (VTM_PPS_SPLIT > 1) {
-        hipLaunchKernelGGL((k_sweep_pps_split<TO, TV, (VTM_PPS_SPLIT > 1 ? VTM_PPS_SPLIT : 2)>), dim3(S),
-                           dim3(64 * VTM_PPS_SPLIT), 0, st, Sp, sofs, pn_off, pn_pfirst, port_off, port_twin, pc, pW,
-                           W, h, a_cur, a_next, reverse);
-        return hipGetLastError();
-    }
-    return launch_pps<TO, TV, false>(S, Sp, sofs, pn_off, pn_pfirst, port_off, port_twin, pc, pW, W, h, a_cur,
-                                     a_next, reverse, st);
+    hipLaunchKernelGGL((k_sweep_pps_split<TO, TV, kPpsSplit>), dim3(S), dim3(64 * kPpsSplit), 0, st, Sp, sofs, pn_off,
+                       pn_pfirst, port_off, port_twin, pc, pW, W, h, a_cur, a_next, reverse);
+    return hipGetLastError();
 }
 
 template hipError_t launch_port_node_matrix<double>(int, const int32_t*, const int64_t*, const int32_t*,

@@ -3,11 +3,6 @@
 // formed in a fixed order, so results are bitwise reproducible.
 #include "kernels.hpp"
 
-// residuals of whole-wavefront right-hand-side blocks with wave-uniform rows
-#ifndef VTM_RESID_UNIFORM
-#define VTM_RESID_UNIFORM 1
-#endif
-
 namespace vtm {
 
 namespace {
@@ -133,7 +128,7 @@ hipError_t launch_port_residual(int64_t n_port_nodes, int nrhs, const int32_t* p
                                 hipStream_t st) {
     if (nrhs < 1 || nrhs > kBlock) return hipErrorInvalidValue;
     const int blocks = resid_blocks(n_port_nodes, nrhs);
-    if (VTM_RESID_UNIFORM && nrhs % 64 == 0)
+    if (nrhs % 64 == 0)
         hipLaunchKernelGGL((k_port_resid<TV, true>), dim3(blocks), dim3(kBlock), 0, st, n_port_nodes, nrhs, pn_pfirst,
                            twin, a_cur, a_next, c, beta, gamma, gd, g, partial);
     else
@@ -158,7 +153,7 @@ hipError_t launch_residual(int n, int nrhs, const int32_t* rowptr, const int32_t
                            double* norms, hipStream_t st) {
     if (nrhs < 1 || nrhs > kBlock) return hipErrorInvalidValue;
     const int blocks = resid_blocks(n, nrhs);
-    if (VTM_RESID_UNIFORM && nrhs % 64 == 0)
+    if (nrhs % 64 == 0)
         hipLaunchKernelGGL((k_resid<TX, true>), dim3(blocks), dim3(kBlock), 0, st, n, nrhs, rowptr, col, val, b, x,
                            r_out, r32, r16, partial);
     else

@@ -17,10 +17,7 @@ namespace {
 constexpr int kBlock = 256;
 
 // column groups per prefetched chunk of the single right-hand-side kernel
-#ifndef VTM_SWEEP_CHUNK
-#define VTM_SWEEP_CHUNK 8
-#endif
-constexpr int kSweepChunk = VTM_SWEEP_CHUNK;
+constexpr int kSweepChunk = 8;
 
 template <typename T>
 __device__ inline void load16(const T* p, T (&v)[Group<T>::G]) {

@@ -46,15 +46,8 @@ __host__ __device__ inline size_t tile_lds_bytes(int np, int rc) {
 }
 
 // Batched port-to-port sweep: the BF16 path also stages h (FP32, row stride rc + 16,
-// so that the epilogue's four 16-lane row groups fall in disjoint LDS banks)
-#ifndef VTM_MFMA_PP_H_LDS
-#define VTM_MFMA_PP_H_LDS 1
-#endif
-// ... and the FP64 path pads the staged rows by this many doubles (bank spread of
-// the B-fragment reads, whose four 16-lane groups read four consecutive rows)
-#ifndef VTM_MFMA_PP_F64_PAD
-#define VTM_MFMA_PP_F64_PAD 0
-#endif
+// so that the epilogue's four 16-lane row groups fall in disjoint LDS banks) when
+// the operator leaves room for it; the FP64 path stages the waves unpadded.
 
 // row stride of the staged incident waves of the batched port-to-port sweep
 template <typename T>
@@ -62,7 +55,7 @@ __host__ __device__ inline int pp_stage_stride(int qp, int rc) {
     if constexpr (sizeof(T) == 2)
         return qp + 8;                         // [n][k]
     else
-        return rc + VTM_MFMA_PP_F64_PAD;       // [k][n]
+        return rc;                             // [k][n]
 }
 
 // LDS bytes of the batched port-to-port sweep: staged waves, then (BF16, when
@@ -71,9 +64,9 @@ template <typename T>
 __host__ __device__ inline size_t pp_lds_bytes(int qp, int rc, bool with_h = true) {
     if constexpr (sizeof(T) == 2)
         return size_t(rc) * (qp + 8) * sizeof(T) +
-               (VTM_MFMA_PP_H_LDS && with_h ? size_t(qp) * (rc + 16) * sizeof(float) : 0);
+               (with_h ? size_t(qp) * (rc + 16) * sizeof(float) : 0);
     else
-        return size_t(qp) * (rc + VTM_MFMA_PP_F64_PAD) * sizeof(T);
+        return size_t(qp) * rc * sizeof(T);
 }
 
 // (r, c) of the d-th stored element of a padded block

@@ -214,13 +214,11 @@ template hipError_t launch_restrict<float>(int, int, const int32_t*, const int32
                                            hipStream_t);
 
 // right-hand sides from which the renumberings go through LDS tiles
-#ifndef VTM_TILED_RHS
-#define VTM_TILED_RHS 16
-#endif
+constexpr int kTiledRhs = 16;
 
 hipError_t launch_gather(int n, int nrhs, const int32_t* perm, const double* src, double* dst,
                          hipStream_t st) {
-    if (nrhs >= VTM_TILED_RHS && n > 0) {
+    if (nrhs >= kTiledRhs && n > 0) {
         hipLaunchKernelGGL(k_gather_tiled, dim3(unsigned((n + kTile - 1) / kTile), unsigned((nrhs + kTile - 1) / kTile)),
                            dim3(kBlock), 0, st, n, nrhs, perm, src, dst);
         return hipGetLastError();
@@ -232,7 +230,7 @@ hipError_t launch_gather(int n, int nrhs, const int32_t* perm, const double* src
 
 hipError_t launch_scatter(int n, int nrhs, const int32_t* iperm, const double* src, double* dst,
                           hipStream_t st) {
-    if (nrhs >= VTM_TILED_RHS && n > 0) {
+    if (nrhs >= kTiledRhs && n > 0) {
         hipLaunchKernelGGL(k_scatter_tiled, dim3(unsigned((n + kTile - 1) / kTile), unsigned((nrhs + kTile - 1) / kTile)),
                            dim3(kBlock), 0, st, n, nrhs, iperm, src, dst);
         return hipGetLastError();

@@ -1,0 +1,270 @@
+// Host-only parts of the library under AddressSanitizer / UndefinedBehaviorSanitizer
+// (built with g++ by tests/test_host_sanitizers.py): the tearing planner and its
+// refresh, and the host-only C ABI calls (vtm_plan, vtm_split_vertex,
+// vtm_line_admittance, vtm_vertex_admittance, vtm_vertex_sca, status strings,
+// options) on valid circuits and on malformed input.  Exit status 0 when every
+// check holds; a sanitizer report aborts the run.
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+#include "vtm.h"
+
+namespace {
+
+int g_failures = 0;
+
+void check(bool ok, const std::string& what) {
+    if (!ok) {
+        std::fprintf(stderr, "FAILED: %s (last error: %s)\n", what.c_str(), vtm_last_error());
+        ++g_failures;
+    }
+}
+
+// A resistor grid (ny x nx, 5-point) with random branch conductances and 0.01 S
+// to ground, assembled as COO rows, optionally with a duplicated diagonal half
+// and rows in reverse column order.
+struct Csr {
+    int64_t n = 0;
+    std::vector<int64_t> rowptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    vtm_csr view() const { return vtm_csr{n, int64_t(col.size()), rowptr.data(), col.data(), val.data()}; }
+};
+
+Csr grid(int ny, int nx, unsigned seed, bool duplicates, double vccs_gain = 0.0) {
+    std::mt19937_64 rng(seed);
+    std::uniform_real_distribution<double> g(0.5, 2.0);
+    const int n = ny * nx;
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(n);
+    std::vector<double> diag(n, 0.01);
+    auto branch = [&](int i, int j) {
+        const double v = g(rng);
+        rows[i].push_back({j, -v});
+        rows[j].push_back({i, -v});
+        diag[i] += v;
+        diag[j] += v;
+    };
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            if (x + 1 < nx) branch(y * nx + x, y * nx + x + 1);
+            if (y + 1 < ny) branch(y * nx + x, (y + 1) * nx + x);
+        }
+    if (vccs_gain != 0.0) rows[1].push_back({int32_t(nx + 1), vccs_gain});  // one-sided entry (inside a block)
+    Csr A;
+    A.n = n;
+    A.rowptr.push_back(0);
+    for (int i = 0; i < n; ++i) {
+        if (duplicates) {
+            rows[i].push_back({i, 0.5 * diag[i]});
+            rows[i].push_back({i, 0.5 * diag[i]});
+        } else {
+            rows[i].push_back({i, diag[i]});
+        }
+        for (auto it = rows[i].rbegin(); it != rows[i].rend(); ++it) {
+            A.col.push_back(it->first);
+            A.val.push_back(it->second);
+        }
+        A.rowptr.push_back(int64_t(A.col.size()));
+    }
+    return A;
+}
+
+std::vector<int32_t> blocks(int ny, int nx, int by, int bx) {
+    std::vector<int32_t> part(ny * nx);
+    const int nbx = (nx + bx - 1) / bx;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) part[y * nx + x] = (y / by) * nbx + x / bx;
+    return part;
+}
+
+void plan_checks() {
+    const Csr A = grid(24, 20, 1, true);
+    const vtm_csr a = A.view();
+    const auto part = blocks(24, 20, 8, 5);
+    const double Z = 0.8;
+    int64_t S = 0, nw = 0;
+    check(vtm_plan(&a, part.data(), &Z, 1, &S, &nw, nullptr, nullptr) == VTM_OK, "plan counts");
+    check(S == 12, "sub-circuit count");
+    check(nw == 3 * 24 + 2 * 20, "cut wire count");  // 3 block-column boundaries of 24 rows, 2 block-row boundaries of 20 columns
+    std::vector<int32_t> wires(2 * nw);
+    std::vector<double> coef(4 * nw);
+    check(vtm_plan(&a, part.data(), &Z, 1, nullptr, nullptr, wires.data(), coef.data()) == VTM_OK, "plan fill");
+    for (int64_t e = 0; e < nw; ++e) {
+        check(wires[2 * e] < wires[2 * e + 1], "canonical wire");
+        const double G = coef[4 * e], c = coef[4 * e + 1], beta = coef[4 * e + 2], gamma = coef[4 * e + 3];
+        check(std::fabs(beta - 2.0 * c / Z) <= 1e-14 * beta && std::fabs(gamma - (1.0 - 2.0 * c)) <= 1e-14,
+              "beta = 2 W c, gamma = 1 - 2 c");
+        check(G > 0.0 && c > 0.0 && c < 1.0, "port coefficients in range");
+    }
+    // per-wire impedances, and every malformed input the planner rejects
+    std::vector<double> Zw(nw, 0.5);
+    check(vtm_plan(&a, part.data(), Zw.data(), nw, nullptr, nullptr, nullptr, nullptr) == VTM_OK, "per-wire Z");
+    check(vtm_plan(&a, part.data(), Zw.data(), nw - 1, nullptr, nullptr, nullptr, nullptr) == VTM_E_ARG, "nZ");
+    const double bad_z = -1.0;
+    check(vtm_plan(&a, part.data(), &bad_z, 1, nullptr, nullptr, nullptr, nullptr) == VTM_E_ARG, "Z <= 0");
+    check(vtm_plan(nullptr, part.data(), &Z, 1, nullptr, nullptr, nullptr, nullptr) == VTM_E_ARG, "null A");
+    Csr B = A;
+    B.col[3] = int32_t(B.n);
+    vtm_csr b = B.view();
+    check(vtm_plan(&b, part.data(), &Z, 1, nullptr, nullptr, nullptr, nullptr) == VTM_E_ARG, "column range");
+    B = A;
+    B.val[5] = NAN;
+    b = B.view();
+    check(vtm_plan(&b, part.data(), &Z, 1, nullptr, nullptr, nullptr, nullptr) == VTM_E_ARG, "non-finite");
+    B = A;
+    B.rowptr[7] = B.rowptr[8] + 1;
+    b = B.view();
+    check(vtm_plan(&b, part.data(), &Z, 1, nullptr, nullptr, nullptr, nullptr) == VTM_E_ARG, "rowptr order");
+    auto p2 = part;
+    for (auto& v : p2)
+        if (v == 11) v = 12;  // label 11 unused
+    check(vtm_plan(&a, p2.data(), &Z, 1, nullptr, nullptr, nullptr, nullptr) == VTM_E_ARG, "unused label");
+    // a one-sided coupling across the cut: untearable
+    const Csr C = grid(24, 20, 2, false);
+    Csr D = C;
+    for (int64_t q = D.rowptr[4]; q < D.rowptr[5]; ++q)
+        if (D.col[q] == 5) D.val[q] *= 1.5;  // nodes 4 and 5 lie in different blocks (bx = 5)
+    vtm_csr d = D.view();
+    check(vtm_plan(&d, part.data(), &Z, 1, nullptr, nullptr, nullptr, nullptr) == VTM_E_UNTEARABLE, "untearable");
+    // line admittance rules
+    std::vector<double> W(nw);
+    for (int kind = VTM_W_SCALED_MEAN; kind <= VTM_W_DIAG; ++kind)
+        check(vtm_line_admittance(&a, part.data(), kind, 0.5, W.data(), nw) == VTM_OK, "line admittance rule");
+    check(vtm_line_admittance(&a, part.data(), 7, 0.5, W.data(), nw) == VTM_E_ARG, "bad rule");
+    check(vtm_line_admittance(&a, part.data(), VTM_W_OB, 1.0, W.data(), nw + 1) == VTM_E_ARG, "wire count");
+}
+
+void refresh_checks() {
+    // refresh of a plan against a fresh plan of the new values, bit for bit
+    const auto part = blocks(24, 20, 8, 5);
+    for (double gain : {0.0, 0.3}) {
+        const Csr A = grid(24, 20, 3, true, gain), A2 = grid(24, 20, 4, true, gain);
+        const vtm_csr a = A.view(), a2 = A2.view();
+        const double Z = 0.8, Z2 = 1.3;
+        vtm::Plan P, Q;
+        std::string err;
+        check(vtm::build_plan(&a, part.data(), &Z, 1, P, err) == VTM_OK, "build plan");
+        check(vtm::build_plan(&a2, part.data(), &Z2, 1, Q, err) == VTM_OK, "build plan of the new values");
+        check(vtm::refresh_plan(P, A2.val.data(), int64_t(A2.val.size()), &Z2, 1, err) == VTM_OK, "refresh");
+        check(P.val == Q.val && P.dmod == Q.dmod && P.pc == Q.pc && P.pbeta == Q.pbeta && P.pgamma == Q.pgamma &&
+                  P.pg == Q.pg && P.pgd == Q.pgd && P.wg == Q.wg && P.wW == Q.wW,
+              "refreshed plan equals a fresh plan");
+        // refused changes leave the plan as it was
+        const std::vector<double> before = P.val;
+        std::vector<double> v = A2.val;
+        int64_t off = -1;  // an off-diagonal entry inside a block
+        for (int64_t q = A2.rowptr[0]; q < A2.rowptr[1]; ++q)
+            if (A2.col[q] == 1) off = q;
+        v[off] = 0.0;
+        check(vtm::refresh_plan(P, v.data(), int64_t(v.size()), nullptr, 0, err) == VTM_E_ARG, "pattern change");
+        v = A2.val;
+        v[off] *= 1.25;
+        check(vtm::refresh_plan(P, v.data(), int64_t(v.size()), nullptr, 0, err) ==
+                  (gain == 0.0 ? VTM_E_UNSUPPORTED : VTM_OK),
+              "symmetry change (the circuit with a controlled source stays unsymmetric)");
+        if (gain == 0.0) check(P.val == before, "plan unchanged after a refused refresh");
+        check(vtm::refresh_plan(P, v.data(), int64_t(v.size()) - 1, nullptr, 0, err) == VTM_E_ARG, "entry count");
+    }
+}
+
+void vertex_checks() {
+    // a 12 x 13 grid torn at its middle column into two strips
+    const int ny = 12, nx = 13;
+    const Csr A = grid(ny, nx, 5, false);
+    const vtm_csr a = A.view();
+    std::vector<int32_t> label(ny * nx), iface, sides;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) label[y * nx + x] = x < 6 ? 0 : 1;
+    for (int y = 0; y < ny; ++y) {
+        iface.push_back(y * nx + 6);
+        sides.push_back(0);
+        sides.push_back(1);
+    }
+    const int64_t L = int64_t(iface.size());
+    int64_t nt = 0, nnz = 0;
+    check(vtm_split_vertex(&a, label.data(), iface.data(), sides.data(), L, &nt, &nnz, nullptr, nullptr, nullptr,
+                           nullptr) == VTM_OK,
+          "split sizes");
+    check(nt == A.n + L, "torn node count");
+    std::vector<int64_t> rp(nt + 1);
+    std::vector<int32_t> col(nnz), part(nt);
+    std::vector<double> val(nnz);
+    check(vtm_split_vertex(&a, label.data(), iface.data(), sides.data(), L, nullptr, nullptr, rp.data(), col.data(),
+                           val.data(), part.data()) == VTM_OK,
+          "split fill");
+    double sum_torn = 0.0, sum_orig = 0.0;  // the split conserves the sum of all entries
+    for (double v : val) sum_torn += v;
+    for (double v : A.val) sum_orig += v;
+    check(std::fabs(sum_torn - sum_orig) <= 1e-12 * std::fabs(sum_orig), "split conserves entries");
+    for (int kind = VTM_W_SCALED_MEAN; kind <= VTM_W_DIAG; ++kind)
+        for (int side = 0; side < 2; ++side) {
+            int64_t wn = 0;
+            check(vtm_vertex_admittance(&a, label.data(), iface.data(), sides.data(), L, kind, 0.3, side, &wn,
+                                        nullptr, nullptr, nullptr) == VTM_OK,
+                  "vertex admittance size");
+            std::vector<int64_t> wr(L + 1);
+            std::vector<int32_t> wc(wn);
+            std::vector<double> wv(wn);
+            check(vtm_vertex_admittance(&a, label.data(), iface.data(), sides.data(), L, kind, 0.3, side, nullptr,
+                                        wr.data(), wc.data(), wv.data()) == VTM_OK,
+                  "vertex admittance fill");
+            check(wr[L] == wn, "vertex admittance row pointer");
+        }
+    for (int depth : {0, 1, 3, -1})
+        for (double drop : {0.0, 0.05}) {
+            int64_t wn = 0;
+            check(vtm_vertex_sca(&a, label.data(), iface.data(), sides.data(), L, 0, depth, drop, &wn, nullptr,
+                                 nullptr, nullptr) == VTM_OK,
+                  "SCA size");
+            std::vector<int64_t> wr(L + 1);
+            std::vector<int32_t> wc(wn);
+            std::vector<double> wv(wn);
+            check(vtm_vertex_sca(&a, label.data(), iface.data(), sides.data(), L, 0, depth, drop, nullptr, wr.data(),
+                                 wc.data(), wv.data()) == VTM_OK,
+                  "SCA fill");
+            for (int64_t l = 0; l < L; ++l)
+                for (int64_t q = wr[l]; q < wr[l + 1]; ++q)
+                    if (wc[q] == l) check(wv[q] > 0.0, "SCA diagonal positive");
+        }
+    check(vtm_vertex_sca(&a, label.data(), iface.data(), sides.data(), L, 2, 1, 0.0, nullptr, nullptr, nullptr,
+                         nullptr) == VTM_E_ARG,
+          "SCA side");
+    auto bad_sides = sides;
+    bad_sides[1] = 0;  // both twins in one sub-circuit
+    check(vtm_split_vertex(&a, label.data(), iface.data(), bad_sides.data(), L, &nt, &nnz, nullptr, nullptr, nullptr,
+                           nullptr) == VTM_E_ARG,
+          "sides must differ");
+    auto dup = iface;
+    dup[1] = dup[0];
+    check(vtm_split_vertex(&a, label.data(), dup.data(), sides.data(), L, &nt, &nnz, nullptr, nullptr, nullptr,
+                           nullptr) == VTM_E_ARG,
+          "distinct interfacial nodes");
+}
+
+void misc_checks() {
+    vtm_options o;
+    vtm_default_options(&o);
+    check(o.precision == VTM_FP64 && o.check_every == 8 && o.local_form == 1, "default options");
+    vtm_default_options(nullptr);
+    for (int s = 0; s <= 9; ++s) check(vtm_status_str(vtm_status(s)) != nullptr, "status string");
+}
+
+}  // namespace
+
+int main() {
+    plan_checks();
+    refresh_checks();
+    vertex_checks();
+    misc_checks();
+    if (g_failures) {
+        std::fprintf(stderr, "%d checks failed\n", g_failures);
+        return 1;
+    }
+    std::printf("host ABI checks passed\n");
+    return 0;
+}

@@ -96,7 +96,10 @@ typedef struct {
                                at most 64 of them); 0: check every check_every      */
     int32_t batch_row_tiles;/* batched (MFMA) sweep: 16-row tiles each wavefront holds
                                per pass, 3 or 5; 0 = chosen by the autotuner at setup
-                               (which also tries 1: fewer registers, more wavefronts) */
+                               (which also tries 1: fewer registers, more wavefronts;
+                               its choice is kept for the process and reused by later
+                               setups on the same device with the same precision,
+                               right-hand sides, shape options and plan sizes)   */
     int32_t batch_rhs_block;/* batched sweep: right-hand sides per workgroup, 16, 32,
                                48 or 64; 0 = chosen by the autotuner at setup        */
     int32_t local_form;     /* 0: every sweep applies the full local inverse.

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -64,12 +65,12 @@ std::vector<float> to_float(const std::vector<double>& v) { return std::vector<f
 
 // Workspace of vtm_solve_noalloc, one copy per device, held until the process
 // ends: the residual reductions' per-workgroup partial sums (kResidBlocks
-// workgroups x kNoallocRhs columns x 2 sums) followed by the per-column sums
-// (2 x kNoallocRhs).  Every check writes all of what it then reads, so nothing
-// needs clearing between calls.  Host code never passes this name to a kernel:
+// workgroups x kNoallocRhs columns x 2 sums; the per-column sums go to the
+// handle's pinned host buffer as in vtm_solve).  Every check writes all of what
+// it then reads, so nothing needs clearing between calls.  Host code never passes this name to a kernel:
 // it is a host-side stand-in; scratch_address() gives the device address.
 constexpr int kNoallocRhs = 64;
-constexpr size_t kNoallocDoubles = size_t(vtm::kResidBlocks) * kNoallocRhs * 2 + 2 * kNoallocRhs;
+constexpr size_t kNoallocDoubles = size_t(vtm::kResidBlocks) * kNoallocRhs * 2;
 static __device__ __align__(256) double scratch[kNoallocDoubles];
 
 namespace {
@@ -91,6 +92,26 @@ vtm_status scratch_address(int dev, double** out) {
     *out = it->second;
     return VTM_OK;
 }
+
+}  // namespace
+
+namespace {
+
+// Launch shapes the autotuner chose, per process, keyed by the device and what
+// the timing depends on: precision, right-hand sides, forced shape options and
+// the plan's sizes.  A setup with the same key takes the cached shapes.
+struct TuneKey {
+    int device, precision, nrhs, rows, rc;
+    int64_t S, n, nports, entries, port_entries;
+    int max_ns, max_ports;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(device, precision, nrhs, rows, rc, S, n, nports, entries, port_entries, max_ns, max_ports) <
+               std::tie(o.device, o.precision, o.nrhs, o.rows, o.rc, o.S, o.n, o.nports, o.entries, o.port_entries,
+                        o.max_ns, o.max_ports);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::array<int, 4>> g_tune;  // mfma variant, mfma rc, pp variant, pp rc
 
 }  // namespace
 
@@ -164,14 +185,15 @@ struct vtm_handle_s {
     DevBuf<double> a64[2];                // FP64 waves
     DevBuf<float> b32, d32, a32[2];       // low-precision inner solve
     DevBuf<__bf16> b16;                   // its right-hand side in BF16 (batched BF16 form)
-    DevBuf<double> partial, norms;
+    DevBuf<double> partial;
     // where the residual reductions put their per-workgroup partial sums and
     // per-column sums: the handle's partial / norms, or the static workspace of
     // vtm_solve_noalloc for the duration of such a call
     double* red_partial = nullptr;
-    double* red_norms = nullptr;
+    double* red_norms = nullptr;          // device view of h_norms: the sums land in host memory
     DevBuf<int> flag;
-    double* h_norms = nullptr;            // pinned
+    double* h_norms = nullptr;            // pinned, device-mapped and coherent: the residual kernels
+                                          // write the per-column sums here directly (no copy)
     bool waves_set = false;               // next solve resumes from the stored waves
     // per-launch timing of the sweep kernel (opt.timing)
     std::vector<hipEvent_t> ev;
@@ -236,16 +258,12 @@ vtm_status residual_launch(vtm_handle h, const double* b, const TX* x, int nrhs,
         const int64_t nv = P.n * nrhs;  // the low-precision copies from the expanded residual
         if (r_out && r32) VTM_HIP((vtm::launch_convert<double, float>(nv, r_out, r32, h->stream)));
         if (r_out && r16) VTM_HIP((vtm::launch_convert<double, __bf16>(nv, r_out, r16, h->stream)));
-        VTM_HIP(hipMemcpyAsync(h->h_norms, h->red_norms, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost,
-                               h->stream));
         return VTM_OK;
     }
     const bool useT = transpose && !P.symmetric;
     VTM_HIP(vtm::launch_residual<TX>(int(P.n), nrhs, useT ? h->rowptrT.p : h->rowptr.p,
                                      useT ? h->colT.p : h->col.p, useT ? h->valT.p : h->val.p, b, x, r_out, r32,
                                      r16, h->red_partial, h->red_norms, h->stream));
-    VTM_HIP(hipMemcpyAsync(h->h_norms, h->red_norms, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost,
-                           h->stream));
     return VTM_OK;
 }
 
@@ -281,7 +299,6 @@ vtm_status port_residual_launch(vtm_handle h, bool low, int cur, int nrhs) {
         VTM_HIP(vtm::launch_port_residual<float>(nn, nrhs, h->pn_pfirst.p, h->port_twin.p, h->a32[cur].p,
                                                  h->a32[cur ^ 1].p, h->c64.p, h->beta64.p, h->gamma64.p,
                                                  h->pgd64.p, h->pg64.p, h->red_partial, h->red_norms, h->stream));
-    VTM_HIP(hipMemcpyAsync(h->h_norms, h->red_norms, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, h->stream));
     return VTM_OK;
 }
 
@@ -1236,10 +1253,12 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
     VTM_HIP(h->bp.alloc(P.n * nr));
     VTM_HIP(h->xp.alloc(P.n * nr));
     VTM_HIP(h->partial.alloc(size_t(vtm::kResidBlocks) * nr * 2));
-    VTM_HIP(h->norms.alloc(size_t(2) * nr));
+    // the per-column sums of every check go straight to pinned host memory that the
+    // device writes over the fabric (a 1 KiB copy through a blit kernel cost ~20 us a check)
+    VTM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->h_norms), sizeof(double) * 2 * nr,
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    VTM_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&h->red_norms), h->h_norms, 0));
     h->red_partial = h->partial.p;
-    h->red_norms = h->norms.p;
-    VTM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->h_norms), sizeof(double) * 2 * nr));
     int lds = 0;
     VTM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
     h->lds_limit = size_t(lds > 0 ? lds : 65536);
@@ -1310,9 +1329,30 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
 
     if ((st = build_values(h.get())) != VTM_OK) return st;
     if (h->tiles) {
-        st = autotune(h.get());
-        if (st != VTM_OK) return st;
-        VTM_HIP(hipStreamSynchronize(s));
+        const TuneKey key{h->device, o.precision, nr, o.batch_row_tiles, o.batch_rhs_block, P.S, P.n, P.nports,
+                          P.mofs[P.S], P.qmofs[P.S], P.max_ns, P.max_ports};
+        std::array<int, 4> shape{};
+        bool cached = false;
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            auto it = g_tune.find(key);
+            if (it != g_tune.end()) {
+                shape = it->second;
+                cached = true;
+            }
+        }
+        if (cached) {
+            h->mfma_variant = shape[0];
+            h->mfma_rc = shape[1];
+            h->pp_variant = shape[2];
+            h->pp_rc = shape[3];
+        } else {
+            st = autotune(h.get());
+            if (st != VTM_OK) return st;
+            VTM_HIP(hipStreamSynchronize(s));
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            g_tune[key] = {h->mfma_variant, h->mfma_rc, h->pp_variant, h->pp_rc};
+        }
     }
     *out = h.release();
     return VTM_OK;
@@ -1340,10 +1380,8 @@ vtm_status vtm_solve_noalloc(vtm_handle h, const double* b, double* x, int32_t n
     vtm_status st = scratch_address(h->device, &ws);
     if (st != VTM_OK) return st;
     h->red_partial = ws;
-    h->red_norms = ws + size_t(vtm::kResidBlocks) * kNoallocRhs * 2;
     st = solve_common(h, b, x, nrhs, tol, rep, false);
     h->red_partial = h->partial.p;
-    h->red_norms = h->norms.p;
     return st;
 }
 

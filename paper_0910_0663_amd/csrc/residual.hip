@@ -9,6 +9,29 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// One row of b - A x with every load of the row issued before the first use:
+// the NZ column indices and values (scalar loads when the row is wave-uniform),
+// then the NZ gathers of x, then the subtractions in the row's order (the same
+// arithmetic as a loop over the row, which would wait on each gather in turn).
+template <int NZ, typename TX>
+__device__ inline double row_residual(double bv, int k0, const int32_t* __restrict__ col,
+                                      const double* __restrict__ val, const TX* __restrict__ x, int nrhs, int rhs) {
+    int c[NZ];
+    double v[NZ];
+    TX xv[NZ];
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+        c[j] = col[k0 + j];
+        v[j] = val[k0 + j];
+    }
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) xv[j] = x[int64_t(c[j]) * nrhs + rhs];
+    double acc = bv;
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) acc -= v[j] * double(xv[j]);
+    return acc;
+}
+
 // thread (row slot, rhs): the block's threads cover per = 256 / nrhs rows at a time.
 // UNI (nrhs a multiple of 64): each wavefront holds whole rows of one row slot, so
 // the row index is wave-uniform and the row's index and value loads are scalar
@@ -30,8 +53,23 @@ __global__ void __launch_bounds__(kBlock)
         if (UNI) i0 = __builtin_amdgcn_readfirstlane(i0);
         for (int64_t i = i0; i < n; i += int64_t(gridDim.x) * per) {
             const double bv = b[i * nrhs + rhs];
-            double acc = bv;
-            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc -= val[k] * double(x[int64_t(col[k]) * nrhs + rhs]);
+            const int k0 = rowptr[i], nz = rowptr[i + 1] - k0;
+            double acc;
+            // UNI: nz is wave-uniform, so this branch is a scalar one
+            if (UNI && nz == 5)
+                acc = row_residual<5>(bv, k0, col, val, x, nrhs, rhs);
+            else if (UNI && nz == 7)
+                acc = row_residual<7>(bv, k0, col, val, x, nrhs, rhs);
+            else if (UNI && nz == 4)
+                acc = row_residual<4>(bv, k0, col, val, x, nrhs, rhs);
+            else if (UNI && nz == 3)
+                acc = row_residual<3>(bv, k0, col, val, x, nrhs, rhs);
+            else if (UNI && nz == 6)
+                acc = row_residual<6>(bv, k0, col, val, x, nrhs, rhs);
+            else {
+                acc = bv;
+                for (int k = k0; k < k0 + nz; ++k) acc -= val[k] * double(x[int64_t(col[k]) * nrhs + rhs]);
+            }
             if (r_out) r_out[i * nrhs + rhs] = acc;
             // the low-precision copies round as a separate cast pass would: via FP32
             if (r32) r32[i * nrhs + rhs] = static_cast<float>(acc);

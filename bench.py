@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "VTM time-to-1e-8 residual and sweeps/s; mixed/batched vs plain FP64 speedup"
-COUNTERS = os.path.join(ROOT, "profiles", "sweep_cfg2_counters.json")
+COUNTERS = os.path.join(ROOT, "profiles", "sweep_pps_fp64_2048sq_8x8_counters.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_0910_0663_amd", "csrc", "ports.hip")
 
 

@@ -353,28 +353,53 @@ __global__ void __launch_bounds__(kBlock)
     for (int kk = 0; kk < kb; ++kk) R[int64_t(kk) * n + c] = M[int64_t(k0 + kk) * n + c];
 }
 
+// The rank-kb update of every column outside the panel, one column per thread and
+// kUpdateRows rows per workgroup: the workgroup first stages its rows of
+// E_J - I_J in LDS (zero beyond kb, so no term needs a branch), then each thread
+// takes its column's pivot rows (P R)_J into registers and walks its rows eight at
+// a time with their loads issued together.  Each entry accumulates its kb
+// products in panel order.
 template <int NB>
 __global__ void __launch_bounds__(kBlock)
     k_gj_update(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
                 int k0, const double* __restrict__ panel) {
+    __shared__ double e_s[kUpdateRows][NB];
     const int s = blockIdx.x;
     const int off = sub_off[s], n = sub_off[s + 1] - off;
-    if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;
+    if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;  // uniform over the workgroup
     const int kb = min(NB, n - k0);
-    const int c = blockIdx.y * blockDim.x + threadIdx.x;
     const int i0 = blockIdx.z * kUpdateRows, i1 = min(n, i0 + kUpdateRows);
-    if (c >= n || (c >= k0 && c < k0 + kb) || i0 >= n) return;
-    double* M = base + kofs[s];
+    if (i0 >= n) return;                                         // uniform over the workgroup
     const double* Pn = panel + int64_t(off) * (2 * NB + 1);
     const double* R = Pn + int64_t(n) * NB;
+    for (int t = threadIdx.x; t < kUpdateRows * NB; t += blockDim.x) {
+        const int ii = t / NB, kk = t - ii * NB, i = i0 + ii;
+        e_s[ii][kk] = (i < i1 && kk < kb) ? Pn[int64_t(i) * NB + kk] - (i == k0 + kk ? 1.0 : 0.0) : 0.0;
+    }
+    __syncthreads();
+    const int c = blockIdx.y * blockDim.x + threadIdx.x;
+    if (c >= n || (c >= k0 && c < k0 + kb)) return;  // no barrier follows
+    double* M = base + kofs[s];
     double rj[NB];
 #pragma unroll
     for (int kk = 0; kk < NB; ++kk) rj[kk] = kk < kb ? R[int64_t(kk) * n + c] : 0.0;
-    for (int i = i0; i < i1; ++i) {
+    constexpr int U = 8;
+    int i = i0;
+    for (; i + U <= i1; i += U) {
+        double m[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) m[u] = M[int64_t(i + u) * n + c];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int kk = 0; kk < NB; ++kk) m[u] += e_s[i - i0 + u][kk] * rj[kk];
+#pragma unroll
+        for (int u = 0; u < U; ++u) M[int64_t(i + u) * n + c] = m[u];
+    }
+    for (; i < i1; ++i) {
         double acc = M[int64_t(i) * n + c];
 #pragma unroll
-        for (int kk = 0; kk < NB; ++kk)
-            if (kk < kb) acc += (Pn[i * NB + kk] - (i == k0 + kk ? 1.0 : 0.0)) * rj[kk];
+        for (int kk = 0; kk < NB; ++kk) acc += e_s[i - i0][kk] * rj[kk];
         M[int64_t(i) * n + c] = acc;
     }
 }

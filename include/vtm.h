@@ -44,7 +44,7 @@ typedef enum {
     VTM_E_DIVERGED = 4,     /* residual non-finite or above opt.divergence           */
     VTM_E_MAXITER = 5,      /* opt.max_sweeps reached without convergence            */
     VTM_E_HIP = 6,          /* HIP runtime error                                     */
-    VTM_E_OOM = 7,          /* device or pinned-host allocation failed               */
+    VTM_E_OOM = 7,          /* device, pinned-host or host memory allocation failed  */
     VTM_E_UNSUPPORTED = 8   /* valid input outside the library's limits             */
 } vtm_status;
 

@@ -976,22 +976,24 @@ static vtm_status keep_pattern(vtm_handle_s* h, const vtm_csr* A) {
 
 vtm_status vtm_setup(const vtm_csr* A, const int32_t* part, const double* Z, int64_t nZ,
                      const vtm_options* opt, void* stream, vtm_handle* out) {
-    if (!out) return fail(VTM_E_ARG, "null output handle");
-    *out = nullptr;
-    vtm_options o;
-    vtm_default_options(&o);
-    if (opt) o = *opt;
-    vtm_status st = check_options(o);
-    if (st != VTM_OK) return st;
-    auto h = std::make_unique<vtm_handle_s>();
-    h->opt = o;
-    h->nrhs_max = o.nrhs_max;
-    h->stream = static_cast<hipStream_t>(stream);
-    std::string err;
-    st = vtm::build_plan(A, part, Z, nZ, h->plan, err);
-    if (st != VTM_OK) return fail(st, err);
-    if ((st = keep_pattern(h.get(), A)) != VTM_OK) return st;
-    return setup_from_plan(std::move(h), out);
+    return vtm::guarded([&]() -> vtm_status {
+        if (!out) return fail(VTM_E_ARG, "null output handle");
+        *out = nullptr;
+        vtm_options o;
+        vtm_default_options(&o);
+        if (opt) o = *opt;
+        vtm_status st = check_options(o);
+        if (st != VTM_OK) return st;
+        auto h = std::make_unique<vtm_handle_s>();
+        h->opt = o;
+        h->nrhs_max = o.nrhs_max;
+        h->stream = static_cast<hipStream_t>(stream);
+        std::string err;
+        st = vtm::build_plan(A, part, Z, nZ, h->plan, err);
+        if (st != VTM_OK) return fail(st, err);
+        if ((st = keep_pattern(h.get(), A)) != VTM_OK) return st;
+        return setup_from_plan(std::move(h), out);
+    });
 }
 
 static vtm_status setup_vertex_common(const vtm_csr* A, const int32_t* label, const int32_t* iface, const int32_t* sides,
@@ -1001,7 +1003,9 @@ static vtm_status setup_vertex_common(const vtm_csr* A, const int32_t* label, co
 vtm_status vtm_setup_vertex(const vtm_csr* A, const int32_t* label, const int32_t* iface, const int32_t* sides,
                             int64_t n_iface, const double* W, int64_t nW, const vtm_options* opt, void* stream,
                             vtm_handle* out) {
-    return setup_vertex_common(A, label, iface, sides, n_iface, W, nW, nullptr, opt, stream, out);
+    return vtm::guarded([&]() -> vtm_status {
+        return setup_vertex_common(A, label, iface, sides, n_iface, W, nW, nullptr, opt, stream, out);
+    });
 }
 
 static vtm_status setup_vertex_common(const vtm_csr* A, const int32_t* label, const int32_t* iface, const int32_t* sides,
@@ -1051,8 +1055,10 @@ static vtm_status setup_vertex_common(const vtm_csr* A, const int32_t* label, co
 vtm_status vtm_setup_vertex_coupled(const vtm_csr* A, const int32_t* label, const int32_t* iface,
                                     const int32_t* sides, int64_t n_iface, const vtm_csr* W, const vtm_options* opt,
                                     void* stream, vtm_handle* out) {
-    if (!W) return fail(VTM_E_ARG, "null W");
-    return setup_vertex_common(A, label, iface, sides, n_iface, nullptr, 0, W, opt, stream, out);
+    return vtm::guarded([&]() -> vtm_status {
+        if (!W) return fail(VTM_E_ARG, "null W");
+        return setup_vertex_common(A, label, iface, sides, n_iface, nullptr, 0, W, opt, stream, out);
+    });
 }
 
 static vtm_status check_options(const vtm_options& o) {
@@ -1095,7 +1101,7 @@ static vtm_status build_values(vtm_handle_s* h) {
     DevBuf<int32_t> ipiv;
     if (h->tiles || P.max_ns > vtm::kLdsSetupMax) VTM_HIP(inv64.alloc(nk));
     if (P.max_ns > vtm::kLdsSetupMax) {
-        VTM_HIP(panel.alloc(P.n * (2 * 16 + 1)));
+        VTM_HIP(panel.alloc(vtm::setup_panel_doubles(P.n, P.max_ns)));
         VTM_HIP(ipiv.alloc(P.n));
     }
     VTM_HIP(h->c64.upload(P.pc, s));
@@ -1359,120 +1365,136 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
 }
 
 vtm_status vtm_solve(vtm_handle h, const double* b, double* x, int32_t nrhs, double tol, vtm_report* rep) {
-    return solve_common(h, b, x, nrhs, tol, rep, false);
+    return vtm::guarded([&]() -> vtm_status {
+        return solve_common(h, b, x, nrhs, tol, rep, false);
+    });
 }
 
 vtm_status vtm_solve_adjoint(vtm_handle h, const double* g, double* lambda, int32_t nrhs, double tol,
                              vtm_report* rep) {
-    return solve_common(h, g, lambda, nrhs, tol, rep, true);
+    return vtm::guarded([&]() -> vtm_status {
+        return solve_common(h, g, lambda, nrhs, tol, rep, true);
+    });
 }
 
 vtm_status vtm_solve_noalloc(vtm_handle h, const double* b, double* x, int32_t nrhs, double tol, vtm_report* rep) {
-    if (!h) return fail(VTM_E_ARG, "null handle");
-    if (nrhs > kNoallocRhs)
-        return fail(VTM_E_UNSUPPORTED, "vtm_solve_noalloc takes at most 64 right-hand sides (its static workspace "
-                                       "holds the residual sums of 64 columns)");
-    if (h->opt.use_graph || h->opt.timing)
-        return fail(VTM_E_UNSUPPORTED, "vtm_solve_noalloc needs use_graph = 0 and timing = 0 (graphs and timing "
-                                       "events are runtime objects created on first use)");
-    VTM_HIP(hipSetDevice(h->device));
-    double* ws = nullptr;
-    vtm_status st = scratch_address(h->device, &ws);
-    if (st != VTM_OK) return st;
-    h->red_partial = ws;
-    st = solve_common(h, b, x, nrhs, tol, rep, false);
-    h->red_partial = h->partial.p;
-    return st;
+    return vtm::guarded([&]() -> vtm_status {
+        if (!h) return fail(VTM_E_ARG, "null handle");
+        if (nrhs > kNoallocRhs)
+            return fail(VTM_E_UNSUPPORTED, "vtm_solve_noalloc takes at most 64 right-hand sides (its static workspace "
+                                           "holds the residual sums of 64 columns)");
+        if (h->opt.use_graph || h->opt.timing)
+            return fail(VTM_E_UNSUPPORTED, "vtm_solve_noalloc needs use_graph = 0 and timing = 0 (graphs and timing "
+                                           "events are runtime objects created on first use)");
+        VTM_HIP(hipSetDevice(h->device));
+        double* ws = nullptr;
+        vtm_status st = scratch_address(h->device, &ws);
+        if (st != VTM_OK) return st;
+        h->red_partial = ws;
+        st = solve_common(h, b, x, nrhs, tol, rep, false);
+        h->red_partial = h->partial.p;
+        return st;
+    });
 }
 
 vtm_status vtm_grad(vtm_handle h, const double* x, const double* lambda, int32_t nrhs, const int32_t* branch_ij,
                     int64_t m, double* dL_dg, double* dL_dA_or_null) {
-    if (!h) return fail(VTM_E_ARG, "null handle");
-    if (m < 0 || nrhs < 1 || ((m > 0 || dL_dA_or_null) && (!x || !lambda)) || (m > 0 && (!branch_ij || !dL_dg)))
-        return fail(VTM_E_ARG, "bad gradient arguments");
-    VTM_HIP(hipSetDevice(h->device));
-    const int64_t nn = h->plan.vertex ? h->plan.n_orig : h->plan.n;  // the caller's nodes
-    if (m > 0) VTM_HIP(vtm::launch_grad(m, int(nn), nrhs, x, lambda, branch_ij, dL_dg, h->stream));
-    if (dL_dA_or_null)
-        VTM_HIP(vtm::launch_grad_entries(h->a_nnz, int(nn), nrhs, x, lambda, h->erow.p, h->ecol.p, dL_dA_or_null,
-                                         h->stream));
-    VTM_HIP(hipStreamSynchronize(h->stream));
-    return VTM_OK;
+    return vtm::guarded([&]() -> vtm_status {
+        if (!h) return fail(VTM_E_ARG, "null handle");
+        if (m < 0 || nrhs < 1 || ((m > 0 || dL_dA_or_null) && (!x || !lambda)) || (m > 0 && (!branch_ij || !dL_dg)))
+            return fail(VTM_E_ARG, "bad gradient arguments");
+        VTM_HIP(hipSetDevice(h->device));
+        const int64_t nn = h->plan.vertex ? h->plan.n_orig : h->plan.n;  // the caller's nodes
+        if (m > 0) VTM_HIP(vtm::launch_grad(m, int(nn), nrhs, x, lambda, branch_ij, dL_dg, h->stream));
+        if (dL_dA_or_null)
+            VTM_HIP(vtm::launch_grad_entries(h->a_nnz, int(nn), nrhs, x, lambda, h->erow.p, h->ecol.p, dL_dA_or_null,
+                                             h->stream));
+        VTM_HIP(hipStreamSynchronize(h->stream));
+        return VTM_OK;
+    });
 }
 
 vtm_status vtm_refresh(vtm_handle h, const double* val, const double* Z, int64_t nZ) {
-    if (!h) return fail(VTM_E_ARG, "null handle");
-    VTM_HIP(hipSetDevice(h->device));
-    VTM_HIP(hipStreamSynchronize(h->stream));
-    std::string err;
-    vtm_status st = vtm::refresh_plan(h->plan, val, h->a_nnz, Z, Z ? nZ : 0, err);
-    if (st != VTM_OK) return fail(st, err);
-    // captured check intervals hold kernel arguments, some of which (the per-port W of
-    // the packed form) may now live elsewhere: capture them again when next needed
-    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
-    h->graphs.clear();
-    h->waves_set = false;
-    return build_values(h);
+    return vtm::guarded([&]() -> vtm_status {
+        if (!h) return fail(VTM_E_ARG, "null handle");
+        VTM_HIP(hipSetDevice(h->device));
+        VTM_HIP(hipStreamSynchronize(h->stream));
+        std::string err;
+        vtm_status st = vtm::refresh_plan(h->plan, val, h->a_nnz, Z, Z ? nZ : 0, err);
+        if (st != VTM_OK) return fail(st, err);
+        // captured check intervals hold kernel arguments, some of which (the per-port W of
+        // the packed form) may now live elsewhere: capture them again when next needed
+        for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+        h->graphs.clear();
+        h->waves_set = false;
+        return build_values(h);
+    });
 }
 
 vtm_status vtm_get_waves(vtm_handle h, double* waves, int32_t nrhs) {
-    if (!h || !waves || nrhs < 1 || nrhs > h->nrhs_max) return fail(VTM_E_ARG, "bad wave arguments");
-    VTM_HIP(hipSetDevice(h->device));
-    if (h->opt.precision == VTM_FP64)
-        VTM_HIP(vtm::launch_waves_io<double>(h->plan.nports, nrhs, h->abi2port.p, h->a64[0].p, waves, true,
-                                             h->stream));
-    else
-        VTM_HIP(vtm::launch_waves_io<float>(h->plan.nports, nrhs, h->abi2port.p, h->a32[0].p, waves, true,
-                                            h->stream));
-    VTM_HIP(hipStreamSynchronize(h->stream));
-    return VTM_OK;
+    return vtm::guarded([&]() -> vtm_status {
+        if (!h || !waves || nrhs < 1 || nrhs > h->nrhs_max) return fail(VTM_E_ARG, "bad wave arguments");
+        VTM_HIP(hipSetDevice(h->device));
+        if (h->opt.precision == VTM_FP64)
+            VTM_HIP(vtm::launch_waves_io<double>(h->plan.nports, nrhs, h->abi2port.p, h->a64[0].p, waves, true,
+                                                 h->stream));
+        else
+            VTM_HIP(vtm::launch_waves_io<float>(h->plan.nports, nrhs, h->abi2port.p, h->a32[0].p, waves, true,
+                                                h->stream));
+        VTM_HIP(hipStreamSynchronize(h->stream));
+        return VTM_OK;
+    });
 }
 
 vtm_status vtm_set_waves(vtm_handle h, const double* waves, int32_t nrhs) {
-    if (!h || !waves || nrhs < 1 || nrhs > h->nrhs_max) return fail(VTM_E_ARG, "bad wave arguments");
-    if (h->opt.precision != VTM_FP64) return fail(VTM_E_UNSUPPORTED, "resume needs the FP64 precision");
-    VTM_HIP(hipSetDevice(h->device));
-    VTM_HIP(vtm::launch_waves_io<double>(h->plan.nports, nrhs, h->abi2port.p, h->a64[0].p,
-                                         const_cast<double*>(waves), false, h->stream));
-    VTM_HIP(hipStreamSynchronize(h->stream));
-    h->waves_set = true;
-    return VTM_OK;
+    return vtm::guarded([&]() -> vtm_status {
+        if (!h || !waves || nrhs < 1 || nrhs > h->nrhs_max) return fail(VTM_E_ARG, "bad wave arguments");
+        if (h->opt.precision != VTM_FP64) return fail(VTM_E_UNSUPPORTED, "resume needs the FP64 precision");
+        VTM_HIP(hipSetDevice(h->device));
+        VTM_HIP(vtm::launch_waves_io<double>(h->plan.nports, nrhs, h->abi2port.p, h->a64[0].p,
+                                             const_cast<double*>(waves), false, h->stream));
+        VTM_HIP(hipStreamSynchronize(h->stream));
+        h->waves_set = true;
+        return VTM_OK;
+    });
 }
 
 vtm_status vtm_info(vtm_handle h, int64_t* n, int64_t* n_sub, int64_t* n_wires, int64_t* inverse_bytes,
                     int64_t* port_operator_bytes, int64_t* port_sweep_bytes) {
-    if (!h) return fail(VTM_E_ARG, "null handle");
-    const vtm::Plan& P = h->plan;
-    const int64_t esize = h->opt.precision == VTM_FP64 ? 8 : (h->opt.precision == VTM_FP32_REFINE ? 4 : 2);
-    if (n) *n = P.n;
-    if (n_sub) *n_sub = P.S;
-    if (n_wires) *n_wires = P.nwires;
-    if (inverse_bytes) *inverse_bytes = (h->tiles ? P.mofs[P.S] : P.kofs[P.S]) * esize;
-    const int64_t op = h->ppb   ? P.qmofs[P.S] * esize
-                       : h->ppn ? P.nofs[P.S] * esize
-                       : h->pps ? P.sofs[P.S] * esize
-                       : h->pp  ? P.pofs[P.S] * esize
-                                : 0;
-    if (port_operator_bytes) *port_operator_bytes = op;
-    if (port_sweep_bytes) {
-        // operator entries once (without layout padding); per port the wave in, h in, wave
-        // out (and c for the packed form) plus the twin index; per port node its first port;
-        // per sub-circuit its offsets
-        const int64_t tv = h->opt.precision == VTM_FP64 ? 8 : 4;  // waves (FP32 for the BF16 form)
-        if (h->ppb)
-            *port_sweep_bytes = P.sq_entries * esize + P.nports * (4 + int64_t(h->nrhs_max) * 3 * tv) + P.S * 16;
-        else if (h->ppn)
-            *port_sweep_bytes = P.sqn_entries * esize + P.nports * (6 * esize + 4) +
-                                int64_t(P.pn_node.size()) * 4 + P.S * 16;
-        else if (h->pps)
-            *port_sweep_bytes = P.tri_entries * esize + P.nports * (4 * esize + 4 + (P.uniform_W ? 0 : esize)) +
-                                int64_t(P.pn_node.size()) * 4 + P.S * 16;
-        else if (h->pp)
-            *port_sweep_bytes = P.sq_entries * esize + P.nports * (3 * esize + 4) + P.S * 12;
-        else
-            *port_sweep_bytes = 0;
-    }
-    return VTM_OK;
+    return vtm::guarded([&]() -> vtm_status {
+        if (!h) return fail(VTM_E_ARG, "null handle");
+        const vtm::Plan& P = h->plan;
+        const int64_t esize = h->opt.precision == VTM_FP64 ? 8 : (h->opt.precision == VTM_FP32_REFINE ? 4 : 2);
+        if (n) *n = P.n;
+        if (n_sub) *n_sub = P.S;
+        if (n_wires) *n_wires = P.nwires;
+        if (inverse_bytes) *inverse_bytes = (h->tiles ? P.mofs[P.S] : P.kofs[P.S]) * esize;
+        const int64_t op = h->ppb   ? P.qmofs[P.S] * esize
+                           : h->ppn ? P.nofs[P.S] * esize
+                           : h->pps ? P.sofs[P.S] * esize
+                           : h->pp  ? P.pofs[P.S] * esize
+                                    : 0;
+        if (port_operator_bytes) *port_operator_bytes = op;
+        if (port_sweep_bytes) {
+            // operator entries once (without layout padding); per port the wave in, h in, wave
+            // out (and c for the packed form) plus the twin index; per port node its first port;
+            // per sub-circuit its offsets
+            const int64_t tv = h->opt.precision == VTM_FP64 ? 8 : 4;  // waves (FP32 for the BF16 form)
+            if (h->ppb)
+                *port_sweep_bytes = P.sq_entries * esize + P.nports * (4 + int64_t(h->nrhs_max) * 3 * tv) + P.S * 16;
+            else if (h->ppn)
+                *port_sweep_bytes = P.sqn_entries * esize + P.nports * (6 * esize + 4) +
+                                    int64_t(P.pn_node.size()) * 4 + P.S * 16;
+            else if (h->pps)
+                *port_sweep_bytes = P.tri_entries * esize + P.nports * (4 * esize + 4 + (P.uniform_W ? 0 : esize)) +
+                                    int64_t(P.pn_node.size()) * 4 + P.S * 16;
+            else if (h->pp)
+                *port_sweep_bytes = P.sq_entries * esize + P.nports * (3 * esize + 4) + P.S * 12;
+            else
+                *port_sweep_bytes = 0;
+        }
+        return VTM_OK;
+    });
 }
 
 void vtm_destroy(vtm_handle h) {

@@ -39,8 +39,10 @@ struct PortArrays {
 // ns <= kLdsSetupMax are inverted in LDS; larger ones are assembled into
 // scratch64 (FP64, same offsets, must be non-null then) and inverted there by a
 // blocked Gauss-Jordan elimination with partial pivoting, whose panels use
-// panel (n x 33 doubles) and ipiv (n ints), both non-null then.  flag bit 0 =
-// singular.
+// panel (setup_panel_doubles(n, max_ns) doubles) and ipiv (n ints), both
+// non-null then.  flag bit 0 = singular.
+int64_t setup_panel_doubles(int64_t n, int max_ns);
+
 template <typename TO>
 hipError_t launch_setup(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs,
                         const int32_t* rowptr, const int32_t* col, const double* val,

@@ -12,10 +12,13 @@
 #include "plan.hpp"
 
 #include <algorithm>
-#include <map>
+#include <atomic>
 #include <cmath>
+#include <exception>
 #include <limits>
+#include <map>
 #include <numeric>
+#include <thread>
 
 namespace vtm {
 
@@ -37,6 +40,41 @@ struct SrcEntry {
     double v;
     int32_t k;
 };
+
+// Host threads for a pass over `work` items: up to 16, none below 64k items each.
+int plan_threads(int64_t work) {
+    const int64_t hw = std::max(1u, std::thread::hardware_concurrency());
+    return int(std::max<int64_t>(1, std::min<int64_t>({hw, 16, work / 65536})));
+}
+
+// f(t, lo, hi) over the T contiguous chunks [n t / T, n (t + 1) / T) of [0, n),
+// chunk 0 on the calling thread; a chunk whose thread cannot start runs here.
+// The first exception of a chunk (in chunk order) is rethrown after all joined.
+// The same (n, T) always gives the same chunks.
+template <typename F>
+void for_chunks(int64_t n, int T, F&& f) {
+    std::vector<std::exception_ptr> errs(T);
+    auto run = [&](int t) {
+        try {
+            f(t, n * t / T, n * (t + 1) / T);
+        } catch (...) {
+            errs[t] = std::current_exception();
+        }
+    };
+    std::vector<std::thread> th;
+    th.reserve(T);
+    for (int t = 1; t < T; ++t) {
+        try {
+            th.emplace_back(run, t);
+        } catch (...) {
+            run(t);
+        }
+    }
+    run(0);
+    for (auto& x : th) x.join();
+    for (auto& e : errs)
+        if (e) std::rethrow_exception(e);
+}
 
 }  // namespace
 
@@ -126,7 +164,6 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
     // that vtm_refresh can merge new values the same way without sorting again.
     std::vector<int64_t> mrow(n + 1, 0);
     std::vector<Entry> ment;
-    ment.reserve(nnz);
     const bool record = !explicit_lines;
     std::vector<int32_t> src_merged;  // per summed position: merged entry (before renumbering), -1 if dropped
     if (record) {
@@ -134,43 +171,65 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
         P.src_flag.resize(nnz);
         src_merged.resize(nnz);
     }
+    // rows are merged in chunks on host threads; a chunk's merged entries are
+    // numbered inside the chunk, then shifted when the chunks are joined in row order
+    const int TR = plan_threads(nnz);
     {
-        std::vector<SrcEntry> row;
-        std::vector<int32_t> run_of;  // per merged entry of the row (before dropping zeros): kept index or -1
-        int64_t pos = 0;
-        for (int64_t i = 0; i < n; ++i) {
-            row.clear();
-            for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k)
-                row.push_back({A->col[k], A->val[k], int32_t(k)});
-            std::sort(row.begin(), row.end(), [](const SrcEntry& a, const SrcEntry& b) { return a.c < b.c; });
-            size_t start = ment.size();
-            const int64_t pos0 = pos;
-            for (const SrcEntry& e : row) {
-                const bool first = !(ment.size() > start && ment.back().c == e.c);
-                if (!first)
-                    ment.back().v += e.v;
-                else
-                    ment.push_back({e.c, e.v});
-                if (record) {
-                    P.src_ent[pos] = e.k;
-                    P.src_flag[pos] = uint8_t((first ? 1 : 0) | (e.c == i ? 2 : 0));
-                    src_merged[pos] = int32_t(ment.size() - 1 - start);  // run index inside the row for now
+        std::vector<std::vector<Entry>> part_ent(TR);
+        for_chunks(n, TR, [&](int t, int64_t i0, int64_t i1) {
+            std::vector<Entry>& me = part_ent[t];
+            me.reserve(size_t(A->rowptr[i1] - A->rowptr[i0]));
+            std::vector<SrcEntry> row;
+            std::vector<int32_t> run_of;  // per merged entry of the row (before dropping zeros): kept index or -1
+            for (int64_t i = i0; i < i1; ++i) {
+                row.clear();
+                bool sorted = true;
+                for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) {
+                    if (!row.empty() && A->col[k] <= row.back().c) sorted = false;
+                    row.push_back({A->col[k], A->val[k], int32_t(k)});
                 }
-                ++pos;
+                if (!sorted)
+                    std::sort(row.begin(), row.end(), [](const SrcEntry& a, const SrcEntry& b) { return a.c < b.c; });
+                const size_t start = me.size();
+                int64_t pos = A->rowptr[i];
+                for (const SrcEntry& e : row) {
+                    const bool first = !(me.size() > start && me.back().c == e.c);
+                    if (!first)
+                        me.back().v += e.v;
+                    else
+                        me.push_back({e.c, e.v});
+                    if (record) {
+                        P.src_ent[pos] = e.k;
+                        P.src_flag[pos] = uint8_t((first ? 1 : 0) | (e.c == i ? 2 : 0));
+                        src_merged[pos] = int32_t(me.size() - 1 - start);  // run index inside the row for now
+                    }
+                    ++pos;
+                }
+                // explicit zeros off the diagonal couple nothing
+                size_t w = start;
+                run_of.assign(me.size() - start, -1);
+                for (size_t k = start; k < me.size(); ++k)
+                    if (me[k].v != 0.0 || me[k].c == i) {
+                        run_of[k - start] = int32_t(w);
+                        me[w++] = me[k];
+                    }
+                me.resize(w);
+                mrow[i + 1] = int64_t(w - start);
+                if (record)
+                    for (int64_t q = A->rowptr[i]; q < pos; ++q) src_merged[q] = run_of[src_merged[q]];
             }
-            // explicit zeros off the diagonal couple nothing
-            size_t w = start;
-            run_of.assign(ment.size() - start, -1);
-            for (size_t k = start; k < ment.size(); ++k)
-                if (ment[k].v != 0.0 || ment[k].c == i) {
-                    run_of[k - start] = int32_t(w);
-                    ment[w++] = ment[k];
-                }
-            ment.resize(w);
-            mrow[i + 1] = int64_t(ment.size());
+        });
+        std::vector<int64_t> base(TR + 1, 0);
+        for (int t = 0; t < TR; ++t) base[t + 1] = base[t] + int64_t(part_ent[t].size());
+        ment.resize(size_t(base[TR]));
+        for_chunks(n, TR, [&](int t, int64_t i0, int64_t i1) {
+            std::copy(part_ent[t].begin(), part_ent[t].end(), ment.begin() + base[t]);
+            std::vector<Entry>().swap(part_ent[t]);
             if (record)
-                for (int64_t q = pos0; q < pos; ++q) src_merged[q] = run_of[src_merged[q]];
-        }
+                for (int64_t q = A->rowptr[i0]; q < A->rowptr[i1]; ++q)
+                    if (src_merged[q] >= 0) src_merged[q] += int32_t(base[t]);
+        });
+        for (int64_t i = 0; i < n; ++i) mrow[i + 1] += mrow[i];
     }
 
     // ---- exact symmetry (lets the adjoint share the forward path) -------------
@@ -181,46 +240,74 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
         v = it->v;
         return true;
     };
-    P.symmetric = true;
-    for (int64_t i = 0; i < n && P.symmetric; ++i)
-        for (int64_t k = mrow[i]; k < mrow[i + 1]; ++k) {
-            double v;
-            if (!find(ment[k].c, int32_t(i), v) || v != ment[k].v) {
-                P.symmetric = false;
-                break;
-            }
-        }
+    {
+        std::atomic<bool> sym{true};
+        for_chunks(n, TR, [&](int, int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1 && sym.load(std::memory_order_relaxed); ++i)
+                for (int64_t k = mrow[i]; k < mrow[i + 1]; ++k) {
+                    double v;
+                    if (!find(ment[k].c, int32_t(i), v) || v != ment[k].v) {
+                        sym.store(false, std::memory_order_relaxed);
+                        break;
+                    }
+                }
+        });
+        P.symmetric = sym.load();
+    }
 
     // ---- cut wires (canonical order falls out of the row scan) ----------------
     P.wi.clear();
     P.wj.clear();
     P.wg.clear();
-    for (int64_t i = 0; i < n; ++i)
-        for (int64_t k = mrow[i]; k < mrow[i + 1]; ++k) {
-            const int32_t j = ment[k].c;
-            if (part[i] == part[j]) continue;
-            if (explicit_lines) {
-                err = "nodes " + std::to_string(i) + " and " + std::to_string(j) +
-                      " in different sub-circuits are coupled directly, not through an interfacial node";
-                return VTM_E_UNTEARABLE;
+    {
+        // per chunk of rows: its wires in row order, or its first error
+        struct Cut {
+            std::vector<int32_t> wi, wj;
+            std::vector<double> wg;
+            vtm_status st = VTM_OK;
+            std::string err;
+        };
+        std::vector<Cut> cuts(TR);
+        for_chunks(n, TR, [&](int t, int64_t i0, int64_t i1) {
+            Cut& C = cuts[t];
+            for (int64_t i = i0; i < i1 && C.st == VTM_OK; ++i)
+                for (int64_t k = mrow[i]; k < mrow[i + 1]; ++k) {
+                    const int32_t j = ment[k].c;
+                    if (part[i] == part[j]) continue;
+                    auto pair = [&] { return "nodes " + std::to_string(i) + " and " + std::to_string(j); };
+                    if (explicit_lines) {
+                        C.err = pair() + " in different sub-circuits are coupled directly, not through an interfacial node";
+                        C.st = VTM_E_UNTEARABLE;
+                        break;
+                    }
+                    double vt;
+                    if (!find(j, int32_t(i), vt) || vt != ment[k].v) {
+                        C.err = "coupling between " + pair() + " in different sub-circuits is not symmetric";
+                        C.st = VTM_E_UNTEARABLE;
+                        break;
+                    }
+                    if (!(ment[k].v < 0.0)) {
+                        C.err = "coupling between " + pair() + " in different sub-circuits is not a positive conductance";
+                        C.st = VTM_E_UNTEARABLE;
+                        break;
+                    }
+                    if (j > i) {
+                        C.wi.push_back(int32_t(i));
+                        C.wj.push_back(j);
+                        C.wg.push_back(-ment[k].v);
+                    }
+                }
+        });
+        for (Cut& C : cuts) {
+            if (C.st != VTM_OK) {
+                err = C.err;
+                return C.st;
             }
-            double vt;
-            if (!find(j, int32_t(i), vt) || vt != ment[k].v) {
-                err = "coupling between nodes " + std::to_string(i) + " and " + std::to_string(j) +
-                      " in different sub-circuits is not symmetric";
-                return VTM_E_UNTEARABLE;
-            }
-            if (!(ment[k].v < 0.0)) {
-                err = "coupling between nodes " + std::to_string(i) + " and " + std::to_string(j) +
-                      " in different sub-circuits is not a positive conductance";
-                return VTM_E_UNTEARABLE;
-            }
-            if (j > i) {
-                P.wi.push_back(int32_t(i));
-                P.wj.push_back(j);
-                P.wg.push_back(-ment[k].v);
-            }
+            P.wi.insert(P.wi.end(), C.wi.begin(), C.wi.end());
+            P.wj.insert(P.wj.end(), C.wj.begin(), C.wj.end());
+            P.wg.insert(P.wg.end(), C.wg.begin(), C.wg.end());
         }
+    }
     if (explicit_lines) {
         if (!line_b || n_lines < 0) {
             err = "bad line list";
@@ -267,13 +354,22 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
             q_loc[q] = P.iperm[node] - P.sub_off[part[node]];
         }
     }
+    // ports in (sub-circuit, local node, ABI port) order: a counting sort by
+    // sub-circuit (ABI order inside each), then each sub-circuit's run sorted by
+    // local node, stably
     std::vector<int64_t> order(np);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-        if (q_sub[a] != q_sub[b]) return q_sub[a] < q_sub[b];
-        if (q_loc[a] != q_loc[b]) return q_loc[a] < q_loc[b];
-        return a < b;
-    });
+    {
+        std::vector<int64_t> beg(S + 1, 0);
+        for (int64_t q = 0; q < np; ++q) beg[q_sub[q] + 1]++;
+        for (int64_t s = 0; s < S; ++s) beg[s + 1] += beg[s];
+        std::vector<int64_t> fill(beg.begin(), beg.end() - 1);
+        for (int64_t q = 0; q < np; ++q) order[fill[q_sub[q]]++] = q;
+        for_chunks(S, plan_threads(np), [&](int, int64_t s0, int64_t s1) {
+            for (int64_t s = s0; s < s1; ++s)
+                std::stable_sort(order.begin() + beg[s], order.begin() + beg[s + 1],
+                                 [&](int64_t a, int64_t b) { return q_loc[a] < q_loc[b]; });
+        });
+    }
     P.port_off.assign(S + 1, 0);
     P.port_node.resize(np);
     P.port_slot.resize(np);
@@ -286,28 +382,34 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
     P.pgd.resize(np);
     P.dmod.assign(n, 0.0);
     P.max_slot = 0;
+    for_chunks(np, plan_threads(np), [&](int, int64_t p0, int64_t p1) {
+        for (int64_t p = p0; p < p1; ++p) {
+            const int64_t q = order[p];
+            P.abi2port[q] = int32_t(p);
+            P.port_node[p] = q_loc[q];
+            const int64_t e = q / 2;
+            // a line between twins has no branch: its port adds W to the twin's row, the
+            // wave enters whole (c = 1) and leaves as 2 W u - a (beta = 2 W, gamma = -1),
+            // the limit of a cut branch whose g grows without bound
+            const PortCoef k = P.vertex ? PortCoef{P.coupled ? 0.0 : P.wW[e], 1.0, 2.0 * P.wW[e], -1.0}
+                                        : port_coef(P.wg[e], P.wW[e]);
+            P.pc[p] = k.c;
+            P.pbeta[p] = k.beta;
+            P.pgamma[p] = k.gamma;
+            P.pg[p] = P.wg[e];
+            P.pgd[p] = k.G - P.wg[e];
+        }
+    });
+    // in port order: the slots, and the diagonal changes summed as ports come
     for (int64_t p = 0; p < np; ++p) {
         const int64_t q = order[p];
-        P.abi2port[q] = int32_t(p);
         P.port_off[q_sub[q] + 1]++;
-        P.port_node[p] = q_loc[q];
         P.port_slot[p] = (p > 0 && q_sub[order[p - 1]] == q_sub[q] && q_loc[order[p - 1]] == q_loc[q])
                              ? P.port_slot[p - 1] + 1
                              : 0;
         P.max_slot = std::max(P.max_slot, P.port_slot[p]);
-        const int64_t e = q / 2;
-        // a line between twins has no branch: its port adds W to the twin's row, the
-        // wave enters whole (c = 1) and leaves as 2 W u - a (beta = 2 W, gamma = -1),
-        // the limit of a cut branch whose g grows without bound
-        const PortCoef k = P.vertex ? PortCoef{P.coupled ? 0.0 : P.wW[e], 1.0, 2.0 * P.wW[e], -1.0}
-                                    : port_coef(P.wg[e], P.wW[e]);
-        P.pc[p] = k.c;
-        P.pbeta[p] = k.beta;
-        P.pgamma[p] = k.gamma;
-        P.pg[p] = P.wg[e];
-        P.pgd[p] = k.G - P.wg[e];
-        const int32_t node = (q & 1) ? P.wj[e] : P.wi[e];
-        P.dmod[P.iperm[node]] += k.G - P.wg[e];
+        const int32_t node = (q & 1) ? P.wj[q / 2] : P.wi[q / 2];
+        P.dmod[P.iperm[node]] += P.pgd[p];
     }
     P.pofs.assign(S + 1, 0);
     P.qmofs.assign(S + 1, 0);
@@ -355,27 +457,32 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
     P.col.resize(ment.size());
     P.val.resize(ment.size());
     std::vector<int32_t> m2r(record ? ment.size() : 0);  // merged entry -> renumbered entry
-    {
+    for (int64_t r = 0; r < n; ++r) {
+        const int32_t i = P.perm[r];
+        P.rowptr[r + 1] = P.rowptr[r] + int32_t(mrow[i + 1] - mrow[i]);
+    }
+    for_chunks(n, TR, [&](int, int64_t r0, int64_t r1) {
         std::vector<SrcEntry> row;  // k: the merged entry
-        int64_t w = 0;
-        for (int64_t r = 0; r < n; ++r) {
+        for (int64_t r = r0; r < r1; ++r) {
             const int32_t i = P.perm[r];
             row.clear();
             for (int64_t k = mrow[i]; k < mrow[i + 1]; ++k)
                 row.push_back({P.iperm[ment[k].c], ment[k].v, int32_t(k)});
             std::sort(row.begin(), row.end(), [](const SrcEntry& a, const SrcEntry& b) { return a.c < b.c; });
+            int64_t w = P.rowptr[r];
             for (const SrcEntry& e : row) {
                 P.col[w] = e.c;
                 P.val[w] = e.v;
                 if (record) m2r[e.k] = int32_t(w);
                 ++w;
             }
-            P.rowptr[r + 1] = int32_t(w);
         }
-    }
+    });
     if (record) {
         P.src_dst.resize(nnz);
-        for (int64_t q = 0; q < nnz; ++q) P.src_dst[q] = src_merged[q] < 0 ? -1 : m2r[src_merged[q]];
+        for_chunks(nnz, TR, [&](int, int64_t q0, int64_t q1) {
+            for (int64_t q = q0; q < q1; ++q) P.src_dst[q] = src_merged[q] < 0 ? -1 : m2r[src_merged[q]];
+        });
     }
     return VTM_OK;
 }

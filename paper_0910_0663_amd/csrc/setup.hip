@@ -172,24 +172,33 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ... and invert it in place, NB columns at a time (blocked Gauss-Jordan with
-// partial pivoting; NB = 16).  Each panel step is a few
-// launches, so that a few large sub-circuits still spread over the whole chip.
-// k_gj_panel (one workgroup per sub-circuit) eliminates the panel's columns
-// (pivot search over all rows below the diagonal; the panel E_J in global
-// memory, [n][NB] at panel + (2 NB + 1) sub_off[s]); k_gj_swap applies the
-// panel's row swaps P to every other column and keeps their pivot rows
-// (P R)_J ([NB][n] right after E_J; then n doubles of scratch for the pivot
+// partial pivoting).  Each panel step is a few launches, so that a few large
+// sub-circuits still spread over the whole chip.  k_gj_panel (one workgroup per
+// sub-circuit) eliminates the panel's columns (pivot search over all rows below
+// the diagonal; the panel E_J in global memory, column-major [NB][n] at the
+// sub-circuit's panel slot, so that a column is contiguous); k_gj_swap applies
+// the panel's row swaps P to every other column and keeps their pivot rows
+// (P R)_J ([NB][n] right after E_J, then n doubles of scratch for the pivot
 // column), one column per thread.  k_gj_update then applies the elimination to
-// every other column as one rank-kb update, R <- P R + (E_J - I_J) (P R)_J, over
-// a grid of column blocks x row blocks.  k_gj_unscramble undoes the pivoting's
-// column order at the end.
-constexpr int kNB = 16;
-constexpr int kWideNB = 16;       // panel width of the very large sub-circuits (32 measured no faster:
-                                  // the update is bound by its arithmetic, not by passes over K)
+// every other column as one rank-kb update, R <- P R + (E_J - I_J) (P R)_J, on
+// the FP64 matrix cores.  k_gj_unscramble undoes the pivoting's column order at
+// the end.  Each pass over K moves 16 n^2 bytes for 4 n^2 NB flops, so the panel
+// is as wide as the update's MFMA throughput allows: K is read and written
+// n / NB times.
+constexpr int kNB = 32;           // panel width up to kWide64 nodes
+constexpr int kWideNB = 64;       // panel width from kWide64 nodes
+constexpr int kWide64 = 8192;
+constexpr int kOneGroupMax = 2048;  // up to here one workgroup eliminates a sub-circuit's panel
 constexpr int kMaxLarge = 16384;  // largest sub-circuit (the planner's limit)
 constexpr int kPanelBlock = 1024;
-constexpr int kUpdateRows = 128;  // rows per thread of the update
+constexpr int kUpdWaves = 4;      // wavefronts per workgroup of the update
+constexpr int kUpdRows = 512;     // rows per workgroup of the update (eight 16-row tiles per wavefront)
 
+// doubles per node of the panel buffer for NB-column panels: E_J, (P R)_J, the
+// pivot column, and one of padding that keeps every row of E_J 16-byte aligned
+__host__ __device__ constexpr int panel_stride(int NB) { return 2 * NB + 2; }
+
+template <int NB>
 __global__ void __launch_bounds__(kPanelBlock)
     k_gj_panel(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
                int k0, double* __restrict__ panel, int32_t* __restrict__ ipiv, int* flag) {
@@ -198,21 +207,21 @@ __global__ void __launch_bounds__(kPanelBlock)
     const int s = blockIdx.x;
     const int off = sub_off[s], n = sub_off[s + 1] - off;
     if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;
-    const int kb = min(kNB, n - k0);
+    const int kb = min(NB, n - k0);
     double* M = base + kofs[s];
-    double* Pn = panel + int64_t(off) * (2 * kNB + 1);
-    double* R = Pn + int64_t(n) * kNB;
-    double* fcol = R + int64_t(n) * kNB;
+    double* E = panel + int64_t(off) * panel_stride(NB);  // E_J column-major: entry (i, jj) at jj n + i
+    double* R = E + int64_t(n) * NB;
+    double* fcol = R + int64_t(n) * NB;
     const int tid = threadIdx.x, bs = blockDim.x;
     bool bad = false;
     for (int t = tid; t < n * kb; t += bs) {
         const int i = t / kb, jj = t - i * kb;
-        Pn[i * kNB + jj] = M[int64_t(i) * n + k0 + jj];
+        E[jj * n + i] = M[int64_t(i) * n + k0 + jj];
     }
     __syncthreads();
     for (int kk = 0; kk < kb; ++kk) {
         const int k = k0 + kk;
-        int p = block_argmax(Pn + kk, kNB, k, n, red_v, red_i);
+        int p = block_argmax(E + kk * n, 1, k, n, red_v, red_i);
         if (p == INT_MAX) {
             bad = true;
             p = k;
@@ -220,40 +229,60 @@ __global__ void __launch_bounds__(kPanelBlock)
         if (tid == 0) ipiv[off + k] = p;
         if (p != k)
             for (int jj = tid; jj < kb; jj += bs) {
-                const double t = Pn[k * kNB + jj];
-                Pn[k * kNB + jj] = Pn[p * kNB + jj];
-                Pn[p * kNB + jj] = t;
+                const double t = E[jj * n + k];
+                E[jj * n + k] = E[jj * n + p];
+                E[jj * n + p] = t;
             }
         __syncthreads();
-        double pv = Pn[k * kNB + kk];
+        double pv = E[kk * n + k];
         if (pv == 0.0 || !isfinite(pv)) {
             bad = true;
             pv = 1.0;
         }
-        for (int i = tid; i < n; i += bs) fcol[i] = Pn[i * kNB + kk];
+        for (int i = tid; i < n; i += bs) fcol[i] = E[kk * n + i];
         __syncthreads();
-        for (int jj = tid; jj < kb; jj += bs) Pn[k * kNB + jj] = (jj == kk ? 1.0 : Pn[k * kNB + jj]) / pv;
+        for (int jj = tid; jj < kb; jj += bs) E[jj * n + k] = (jj == kk ? 1.0 : E[jj * n + k]) / pv;
         __syncthreads();
         for (int t = tid; t < n * kb; t += bs) {
-            const int i = t / kb, jj = t - i * kb;
-            if (i != k) Pn[i * kNB + jj] = (jj == kk ? 0.0 : Pn[i * kNB + jj]) - fcol[i] * Pn[k * kNB + jj];
+            const int jj = t / n, i = t - jj * n;
+            if (i != k) E[jj * n + i] = (jj == kk ? 0.0 : E[jj * n + i]) - fcol[i] * E[jj * n + k];
         }
         __syncthreads();
     }
     // the panel's columns are final for this step
     for (int t = tid; t < n * kb; t += bs) {
         const int i = t / kb, jj = t - i * kb;
-        M[int64_t(i) * n + k0 + jj] = Pn[i * kNB + jj];
+        M[int64_t(i) * n + k0 + jj] = E[jj * n + i];
     }
     if (bad && tid == 0) atomicOr(flag, 1);
 }
 
+typedef double dx4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+// Raw buffer access with the hardware's range check: a load at or past the
+// resource's byte count returns zero and such a store is dropped, so a lane is
+// masked by giving it kOffOut (at least the byte count of any buffer here: an
+// inverse of kMaxLarge nodes is exactly 2^31 bytes) instead of a branch.
+constexpr int kBufWord3 = 0x00020000;  // gfx9 descriptor word 3: 32-bit data format
+constexpr unsigned kOffOut = 0x80000000u;
+__device__ inline __amdgpu_buffer_rsrc_t buf(const double* p, int64_t doubles) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), 0, int(unsigned(doubles * 8)), kBufWord3);
+}
+__device__ inline double buf_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(off), 0, 0));
+}
+__device__ inline void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, int(off), 0, 0);
+}
+
 // The same panel elimination for a few very large sub-circuits, where one
-// workgroup's chain of 16 pivot steps over n rows is the setup's bottleneck:
-// each step is two launches, the pivot (search, row swap, scaling of the pivot
-// row; one workgroup per sub-circuit) and the elimination of every other row of
-// the panel (one row per thread over a grid of row blocks).  k_gjw_load and
-// k_gjw_store move the panel between K and the panel buffer.
+// workgroup's chain of pivot steps over n rows is the setup's bottleneck: each
+// step is two launches, the pivot (search, row swap, scaling of the pivot row;
+// one workgroup per sub-circuit) and the elimination of every other row of the
+// panel (one row per thread over a grid of row blocks, column by column, so the
+// loads of a wavefront are contiguous).  k_gjw_load moves the panel between K
+// and the panel buffer (store = 1: back into K).
 template <int NB>
 __global__ void __launch_bounds__(kBlock)
     k_gjw_load(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs,
@@ -265,12 +294,12 @@ __global__ void __launch_bounds__(kBlock)
     if (i >= n) return;
     const int kb = min(NB, n - k0);
     double* M = const_cast<double*>(base) + kofs[s] + int64_t(i) * n + k0;
-    double* Pn = panel + int64_t(off) * (2 * NB + 1) + int64_t(i) * NB;
+    double* E = panel + int64_t(off) * panel_stride(NB) + i;
     for (int jj = 0; jj < kb; ++jj) {
         if (store)
-            M[jj] = Pn[jj];
+            M[jj] = E[int64_t(jj) * n];
         else
-            Pn[jj] = M[jj];
+            E[int64_t(jj) * n] = M[jj];
     }
 }
 
@@ -286,9 +315,9 @@ __global__ void __launch_bounds__(kPanelBlock)
     const int kb = min(NB, n - k0);
     if (k0 >= n || kk >= kb) return;
     const int k = k0 + kk;
-    double* Pn = panel + int64_t(off) * (2 * NB + 1);
+    double* E = panel + int64_t(off) * panel_stride(NB);
     const int tid = threadIdx.x, bs = blockDim.x;
-    int p = block_argmax(Pn + kk, NB, k, n, red_v, red_i);
+    int p = block_argmax(E + int64_t(kk) * n, 1, k, n, red_v, red_i);
     bool bad = false;
     if (p == INT_MAX) {
         bad = true;
@@ -297,21 +326,26 @@ __global__ void __launch_bounds__(kPanelBlock)
     if (tid == 0) ipiv[off + k] = p;
     if (p != k)
         for (int jj = tid; jj < kb; jj += bs) {
-            const double t = Pn[k * NB + jj];
-            Pn[k * NB + jj] = Pn[p * NB + jj];
-            Pn[p * NB + jj] = t;
+            const double t = E[int64_t(jj) * n + k];
+            E[int64_t(jj) * n + k] = E[int64_t(jj) * n + p];
+            E[int64_t(jj) * n + p] = t;
         }
     __syncthreads();
-    double pv = Pn[k * NB + kk];
+    double pv = E[int64_t(kk) * n + k];
     if (pv == 0.0 || !isfinite(pv)) {
         bad = true;
         pv = 1.0;
     }
     __syncthreads();  // every thread has read the pivot before row k is scaled
-    for (int jj = tid; jj < kb; jj += bs) Pn[k * NB + jj] = (jj == kk ? 1.0 : Pn[k * NB + jj]) / pv;
+    for (int jj = tid; jj < kb; jj += bs) E[int64_t(jj) * n + k] = (jj == kk ? 1.0 : E[int64_t(jj) * n + k]) / pv;
     if (bad && tid == 0) atomicOr(flag, 1);
 }
 
+// Row i of the panel (every row but the pivot row k): its kb entries and the
+// pivot row's are all loaded before the first store (the panel is read and
+// written through one pointer, so loads and stores interleaved in a loop would
+// wait on each other), then E[i][jj] <- E[i][jj] - E[i][kk] E[k][jj] with the
+// pivot column itself replaced by -E[i][kk] E[k][kk].
 template <int NB>
 __global__ void __launch_bounds__(kBlock)
     k_gjw_elim(const int32_t* __restrict__ sub_off, int k0, int kk, double* __restrict__ panel) {
@@ -323,10 +357,18 @@ __global__ void __launch_bounds__(kBlock)
     const int k = k0 + kk;
     const int i = blockIdx.y * blockDim.x + threadIdx.x;
     if (i >= n || i == k) return;
-    double* Pn = panel + int64_t(off) * (2 * NB + 1);
-    const double f = Pn[i * NB + kk];
-    for (int jj = 0; jj < kb; ++jj)
-        Pn[i * NB + jj] = (jj == kk ? 0.0 : Pn[i * NB + jj]) - f * Pn[k * NB + jj];
+    double* E = panel + int64_t(off) * panel_stride(NB);
+    const auto rE = buf(E, int64_t(NB) * n);
+    double row[NB], piv[NB];
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj) {
+        row[jj] = buf_load(rE, jj < kb ? unsigned(jj * n + i) * 8u : kOffOut);
+        piv[jj] = buf_load(rE, jj < kb ? unsigned(jj * n + k) * 8u : kOffOut);
+    }
+    const double f = buf_load(rE, unsigned(kk * n + i) * 8u);
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj)
+        buf_store(rE, jj < kb ? unsigned(jj * n + i) * 8u : kOffOut, (jj == kk ? 0.0 : row[jj]) - f * piv[jj]);
 }
 
 // every other column: the panel's row swaps, and its pivot rows kept for the update
@@ -341,7 +383,7 @@ __global__ void __launch_bounds__(kBlock)
     const int c = blockIdx.y * blockDim.x + threadIdx.x;
     if (c >= n || (c >= k0 && c < k0 + kb)) return;
     double* M = base + kofs[s];
-    double* R = panel + int64_t(off) * (2 * NB + 1) + int64_t(n) * NB;
+    double* R = panel + int64_t(off) * panel_stride(NB) + int64_t(n) * NB;
     for (int kk = 0; kk < kb; ++kk) {
         const int k = k0 + kk, p = ipiv[off + k];
         if (p != k) {
@@ -353,54 +395,100 @@ __global__ void __launch_bounds__(kBlock)
     for (int kk = 0; kk < kb; ++kk) R[int64_t(kk) * n + c] = M[int64_t(k0 + kk) * n + c];
 }
 
-// The rank-kb update of every column outside the panel, one column per thread and
-// kUpdateRows rows per workgroup: the workgroup first stages its rows of
-// E_J - I_J in LDS (zero beyond kb, so no term needs a branch), then each thread
-// takes its column's pivot rows (P R)_J into registers and walks its rows eight at
-// a time with their loads issued together.  Each entry accumulates its kb
-// products in panel order.
-template <int NB>
-__global__ void __launch_bounds__(kBlock)
+// The rank-kb update of every column outside the panel on v_mfma_f64_16x16x4f64:
+// a workgroup takes kUpdRows rows x 16 CT columns, its wavefronts every fourth
+// 16-row tile.  The NB panel columns are spread over the MFMA's four k slots: in
+// step q (of NB / 4), slot g = lane / 16 carries panel column g NB / 4 + q.  A
+// lane holds the A operand E_J[row][g NB / 4 + q] - I_J (row lane % 16 of the
+// tile; the column-major panel makes each step's load four 128-byte segments),
+// the B operand (P R)_J[g NB / 4 + q][column] for its CT column tiles (loaded
+// once), and the accumulators, which are the entries of R themselves (row 4 v + g
+// of the tile, column lane % 16), loaded and stored as four 128-byte row
+// segments per instruction.  Masked lanes use out-of-range buffer offsets, so no
+// load or store sits behind a branch and the next tile's loads, issued before
+// this tile's MFMAs, stay in flight while they run.  Columns of the panel are
+// left as k_gj_panel wrote them.
+template <int NB, int CT>
+__global__ void __launch_bounds__(kUpdWaves * 64)
     k_gj_update(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
                 int k0, const double* __restrict__ panel) {
-    __shared__ double e_s[kUpdateRows][NB];
+    constexpr int Q = NB / 4;  // MFMA steps
     const int s = blockIdx.x;
     const int off = sub_off[s], n = sub_off[s + 1] - off;
-    if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;  // uniform over the workgroup
+    if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;
     const int kb = min(NB, n - k0);
-    const int i0 = blockIdx.z * kUpdateRows, i1 = min(n, i0 + kUpdateRows);
-    if (i0 >= n) return;                                         // uniform over the workgroup
-    const double* Pn = panel + int64_t(off) * (2 * NB + 1);
-    const double* R = Pn + int64_t(n) * NB;
-    for (int t = threadIdx.x; t < kUpdateRows * NB; t += blockDim.x) {
-        const int ii = t / NB, kk = t - ii * NB, i = i0 + ii;
-        e_s[ii][kk] = (i < i1 && kk < kb) ? Pn[int64_t(i) * NB + kk] - (i == k0 + kk ? 1.0 : 0.0) : 0.0;
+    const int c0 = blockIdx.y * (16 * CT), r0 = blockIdx.z * kUpdRows;
+    if (c0 >= n || r0 >= n) return;
+    const int r1 = min(n, r0 + kUpdRows);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, l16 = lane & 15;
+    const double* E = panel + int64_t(off) * panel_stride(NB);
+    const auto rE = buf(E, int64_t(NB) * n), rR = buf(E + int64_t(n) * NB, int64_t(NB) * n);
+    const auto rM = buf(base + kofs[s], int64_t(n) * n);
+    double b[CT][Q];
+    unsigned mcol[CT], scol[CT];  // byte offset of the lane's column in row 0: loads, stores
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+        const int c = c0 + 16 * t + l16;
+        mcol[t] = c < n ? unsigned(c) * 8u : kOffOut;
+        scol[t] = (c < n && (c < k0 || c >= k0 + kb)) ? mcol[t] : kOffOut;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int kk = g * Q + q;
+            b[t][q] = buf_load(rR, (kk < kb && c < n) ? unsigned(kk * n + c) * 8u : kOffOut);
+        }
     }
-    __syncthreads();
-    const int c = blockIdx.y * blockDim.x + threadIdx.x;
-    if (c >= n || (c >= k0 && c < k0 + kb)) return;  // no barrier follows
-    double* M = base + kofs[s];
-    double rj[NB];
+    const unsigned rowb = unsigned(n) * 8u;  // bytes per row of R
+    // byte offset of row i (or kOffOut past r1), to be added to a column offset
+    // that is itself kOffOut when masked (any sum with kOffOut stays out of range)
+    auto row_off = [&](int i) { return i < r1 ? unsigned(i) * rowb : kOffOut; };
+    auto load = [&](int i0, double (&a)[Q], dx4 (&acc)[CT]) {
+        const int ia = i0 + l16;
 #pragma unroll
-    for (int kk = 0; kk < NB; ++kk) rj[kk] = kk < kb ? R[int64_t(kk) * n + c] : 0.0;
-    constexpr int U = 8;
-    int i = i0;
-    for (; i + U <= i1; i += U) {
-        double m[U];
+        for (int q = 0; q < Q; ++q) {
+            const int kk = g * Q + q;
+            const bool ok = ia < r1 && kk < kb;
+            const double e = buf_load(rE, ok ? unsigned(kk * n + ia) * 8u : kOffOut);
+            a[q] = ok && ia == k0 + kk ? e - 1.0 : e;
+        }
 #pragma unroll
-        for (int u = 0; u < U; ++u) m[u] = M[int64_t(i + u) * n + c];
+        for (int t = 0; t < CT; ++t)
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+            for (int v = 0; v < 4; ++v) {
+                const unsigned ro = row_off(i0 + g + 4 * v);
+                acc[t][v] = buf_load(rM, (ro | mcol[t]) >= kOffOut ? kOffOut : ro + mcol[t]);
+            }
+    };
+    auto update = [&](int i0, const double (&a)[Q], dx4 (&acc)[CT]) {
 #pragma unroll
-            for (int kk = 0; kk < NB; ++kk) m[u] += e_s[i - i0 + u][kk] * rj[kk];
+        for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int u = 0; u < U; ++u) M[int64_t(i + u) * n + c] = m[u];
-    }
-    for (; i < i1; ++i) {
-        double acc = M[int64_t(i) * n + c];
+            for (int t = 0; t < CT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[t][q], acc[t], 0, 0, 0);
 #pragma unroll
-        for (int kk = 0; kk < NB; ++kk) acc += e_s[i - i0][kk] * rj[kk];
-        M[int64_t(i) * n + c] = acc;
+        for (int t = 0; t < CT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const unsigned ro = row_off(i0 + g + 4 * v);
+                buf_store(rM, (ro | scol[t]) >= kOffOut ? kOffOut : ro + scol[t], acc[t][v]);
+            }
+    };
+    // two register sets, alternating: tile j + 1 is loading while tile j computes
+    constexpr int step = 16 * kUpdWaves;
+    double a0[Q], a1[Q];
+    dx4 m0[CT], m1[CT];
+    int i0 = r0 + 16 * wave;
+    if (i0 >= r1) return;
+    load(i0, a0, m0);
+    for (;;) {
+        const int i1 = i0 + step;
+        load(i1, a1, m1);  // every lane out of range past r1
+        update(i0, a0, m0);
+        if (i1 >= r1) break;
+        const int i2 = i1 + step;
+        load(i2, a0, m0);
+        update(i1, a1, m1);
+        if (i2 >= r1) break;
+        i0 = i2;
     }
 }
 
@@ -462,6 +550,59 @@ int copy_parts(int S, int n) {
     return int(std::max<int64_t>(1, std::min<int64_t>(per, want)));
 }
 
+template <int NB>
+hipError_t launch_update(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, double* scratch64, int k0,
+                         const double* panel, hipStream_t st) {
+    constexpr int CT = NB <= 32 ? 4 : 2;   // column tiles per wavefront (the B operand stays in registers)
+    const dim3 grid(unsigned(S), unsigned((max_ns + 16 * CT - 1) / (16 * CT)),
+                    unsigned((max_ns + kUpdRows - 1) / kUpdRows));
+    hipLaunchKernelGGL((k_gj_update<NB, CT>), grid, dim3(kUpdWaves * 64), 0, st, sub_off, kofs, scratch64, k0,
+                       panel);
+    return hipGetLastError();
+}
+
+// panels eliminated by one workgroup per sub-circuit
+template <int NB>
+hipError_t invert_panels(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, double* scratch64,
+                         double* panel, int32_t* ipiv, int* flag, hipStream_t st) {
+    const dim3 cols(unsigned(S), unsigned((max_ns + kBlock - 1) / kBlock));
+    hipError_t e;
+    for (int k0 = 0; k0 < max_ns; k0 += NB) {
+        hipLaunchKernelGGL(k_gj_panel<NB>, dim3(S), dim3(kPanelBlock), 0, st, sub_off, kofs, scratch64, k0, panel,
+                           ipiv, flag);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gj_swap<NB>, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, ipiv);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = launch_update<NB>(S, max_ns, sub_off, kofs, scratch64, k0, panel, st)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// panels whose pivot steps are launches of their own, spread over the chip
+template <int NB>
+hipError_t invert_wide(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, double* scratch64,
+                       double* panel, int32_t* ipiv, int* flag, hipStream_t st) {
+    const dim3 cols(unsigned(S), unsigned((max_ns + kBlock - 1) / kBlock));
+    hipError_t e;
+    for (int k0 = 0; k0 < max_ns; k0 += NB) {
+        hipLaunchKernelGGL(k_gjw_load<NB>, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, 0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (int kk = 0; kk < NB; ++kk) {
+            hipLaunchKernelGGL(k_gjw_pivot<NB>, dim3(S), dim3(kPanelBlock), 0, st, sub_off, k0, kk, panel, ipiv,
+                               flag);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_gjw_elim<NB>, cols, dim3(kBlock), 0, st, sub_off, k0, kk, panel);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_gjw_load<NB>, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, 1);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gj_swap<NB>, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, ipiv);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = launch_update<NB>(S, max_ns, sub_off, kofs, scratch64, k0, panel, st)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // the large sub-circuits: assemble and invert in FP64 scratch (column-major)
 hipError_t invert_large(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, const int32_t* rowptr,
                         const int32_t* col, const double* val, const double* dmod, double* scratch64, double* panel,
@@ -471,43 +612,24 @@ hipError_t invert_large(int S, int max_ns, const int32_t* sub_off, const int64_t
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 cols(unsigned(S), unsigned((max_ns + kBlock - 1) / kBlock));
-    const dim3 tiles(unsigned(S), cols.y, unsigned((max_ns + kUpdateRows - 1) / kUpdateRows));
-    // above 2,048 nodes the panel's pivot steps are spread over the chip (two launches each)
-    if (max_ns > 2048) {
-        constexpr int NB = kWideNB;
-        for (int k0 = 0; k0 < max_ns; k0 += NB) {
-            hipLaunchKernelGGL(k_gjw_load<NB>, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, 0);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            for (int kk = 0; kk < NB; ++kk) {
-                hipLaunchKernelGGL(k_gjw_pivot<NB>, dim3(S), dim3(kPanelBlock), 0, st, sub_off, k0, kk, panel, ipiv,
-                                   flag);
-                if ((e = hipGetLastError()) != hipSuccess) return e;
-                hipLaunchKernelGGL(k_gjw_elim<NB>, cols, dim3(kBlock), 0, st, sub_off, k0, kk, panel);
-                if ((e = hipGetLastError()) != hipSuccess) return e;
-            }
-            hipLaunchKernelGGL(k_gjw_load<NB>, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, 1);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            hipLaunchKernelGGL(k_gj_swap<NB>, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, ipiv);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            hipLaunchKernelGGL(k_gj_update<NB>, tiles, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-    } else {
-        for (int k0 = 0; k0 < max_ns; k0 += kNB) {
-            hipLaunchKernelGGL(k_gj_panel, dim3(S), dim3(kPanelBlock), 0, st, sub_off, kofs, scratch64, k0, panel,
-                               ipiv, flag);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            hipLaunchKernelGGL(k_gj_swap<kNB>, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, ipiv);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            hipLaunchKernelGGL(k_gj_update<kNB>, tiles, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-    }
+    // larger sub-circuits spread each pivot step over the chip (two launches per column)
+    if (max_ns <= kOneGroupMax)
+        e = invert_panels<kNB>(S, max_ns, sub_off, kofs, scratch64, panel, ipiv, flag, st);
+    else if (max_ns < kWide64)
+        e = invert_wide<kNB>(S, max_ns, sub_off, kofs, scratch64, panel, ipiv, flag, st);
+    else
+        e = invert_wide<kWideNB>(S, max_ns, sub_off, kofs, scratch64, panel, ipiv, flag, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gj_unscramble, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, ipiv);
     return hipGetLastError();
 }
 
 }  // namespace
+
+int64_t setup_panel_doubles(int64_t n, int max_ns) {
+    if (max_ns <= kLdsSetupMax) return 0;
+    return n * panel_stride(max_ns < kWide64 ? kNB : kWideNB);
+}
 
 template <typename T>
 hipError_t launch_setup_tiles(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, const int64_t* mofs,

@@ -1,12 +1,14 @@
 // Host-only parts of the library under AddressSanitizer / UndefinedBehaviorSanitizer
-// (built with g++ by tests/test_host_sanitizers.py): the tearing planner and its
-// refresh, and the host-only C ABI calls (vtm_plan, vtm_split_vertex,
+// and ThreadSanitizer (built with g++ by tests/test_host_sanitizers.py): the
+// tearing planner (with a circuit large enough for its passes to run on several
+// host threads) and its refresh, and the host-only C ABI calls (vtm_plan, vtm_split_vertex,
 // vtm_line_admittance, vtm_vertex_admittance, vtm_vertex_sca, status strings,
 // options) on valid circuits and on malformed input.  Exit status 0 when every
 // check holds; a sanitizer report aborts the run.
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <random>
 #include <string>
 #include <vector>
@@ -254,10 +256,62 @@ void misc_checks() {
     for (int s = 0; s <= 9; ++s) check(vtm_status_str(vtm_status(s)) != nullptr, "status string");
 }
 
+// A grid large enough that the planner splits its passes over several host
+// threads (1.1 M entries): the renumbered matrix must be the caller's merged and
+// permuted, the recorded merge order must rebuild its values bitwise, and the
+// port tables must be consistent.
+void threaded_plan_checks() {
+    const int ny = 300, nx = 420;
+    const Csr A = grid(ny, nx, 9, true);
+    const vtm_csr a = A.view();
+    const auto part = blocks(ny, nx, 12, 12);
+    const double Z = 1.0;
+    vtm::Plan P;
+    std::string err;
+    check(vtm::build_plan(&a, part.data(), &Z, 1, P, err) == VTM_OK, "threaded plan: " + err);
+    check(P.nwires == int64_t(34 * ny + 24 * nx), "threaded plan: cut wire count");
+    check(P.symmetric, "threaded plan: symmetric");
+    bool ok = true;
+    for (int64_t r = 0; r < P.n && ok; ++r) {
+        const int32_t i = P.perm[r];
+        ok = P.iperm[i] == r;
+        std::map<int32_t, double> want;  // the caller's row i merged (duplicate halves sum exactly)
+        for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) want[P.iperm[A.col[k]]] += A.val[k];
+        ok = ok && int64_t(want.size()) == P.rowptr[r + 1] - P.rowptr[r];
+        auto it = want.begin();
+        for (int32_t k = P.rowptr[r]; ok && k < P.rowptr[r + 1]; ++k, ++it)
+            ok = it->first == P.col[k] && it->second == P.val[k];
+    }
+    check(ok, "threaded plan: renumbered matrix");
+    std::vector<double> rebuilt(P.val.size(), 0.0);
+    for (size_t q = 0; q < P.src_ent.size(); ++q) {
+        const int32_t d = P.src_dst[q];
+        if (d < 0) continue;
+        const double v = A.val[P.src_ent[q]];
+        rebuilt[d] = (P.src_flag[q] & 1) ? v : rebuilt[d] + v;
+    }
+    check(rebuilt == P.val, "threaded plan: recorded merge order");
+    ok = true;
+    for (int64_t q = 0; q < P.nports && ok; ++q) {
+        const int32_t p = P.abi2port[q];
+        ok = P.port_twin[p] == P.abi2port[q ^ 1] && P.port_twin[P.port_twin[p]] == p;
+    }
+    for (int64_t s = 0; s < P.S && ok; ++s)
+        for (int32_t p = P.port_off[s] + 1; p < P.port_off[s + 1] && ok; ++p)
+            ok = P.port_node[p - 1] < P.port_node[p] ||
+                 (P.port_node[p - 1] == P.port_node[p] && P.port_slot[p] == P.port_slot[p - 1] + 1);
+    check(ok, "threaded plan: port tables");
+    vtm::Plan R = P;
+    check(vtm::refresh_plan(R, A.val.data(), int64_t(A.val.size()), &Z, 1, err) == VTM_OK &&
+              R.val == P.val && R.dmod == P.dmod && R.pbeta == P.pbeta,
+          "threaded plan: refresh with the same values");
+}
+
 }  // namespace
 
 int main() {
     plan_checks();
+    threaded_plan_checks();
     refresh_checks();
     vertex_checks();
     misc_checks();

@@ -198,10 +198,15 @@ constexpr int kUpdRows = 512;     // rows per workgroup of the update (eight 16-
 // pivot column, and one of padding that keeps every row of E_J 16-byte aligned
 __host__ __device__ constexpr int panel_stride(int NB) { return 2 * NB + 2; }
 
-template <int NB>
+// One workgroup per sub-circuit eliminates the panel's kb columns one after the
+// other.  IN_LDS: the panel and the pivot column live in LDS (dynamic, NB + 1
+// doubles per node) and go to the panel slot at the end (k_gj_update reads them
+// there); else they are worked on in the panel slot itself.
+template <int NB, bool IN_LDS>
 __global__ void __launch_bounds__(kPanelBlock)
     k_gj_panel(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
                int k0, double* __restrict__ panel, int32_t* __restrict__ ipiv, int* flag) {
+    extern __shared__ double lds_panel[];
     __shared__ double red_v[kPanelBlock / 64];
     __shared__ int red_i[kPanelBlock / 64];
     const int s = blockIdx.x;
@@ -209,9 +214,9 @@ __global__ void __launch_bounds__(kPanelBlock)
     if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;
     const int kb = min(NB, n - k0);
     double* M = base + kofs[s];
-    double* E = panel + int64_t(off) * panel_stride(NB);  // E_J column-major: entry (i, jj) at jj n + i
-    double* R = E + int64_t(n) * NB;
-    double* fcol = R + int64_t(n) * NB;
+    double* slot = panel + int64_t(off) * panel_stride(NB);  // E_J column-major: entry (i, jj) at jj n + i
+    double* E = IN_LDS ? lds_panel : slot;
+    double* fcol = IN_LDS ? lds_panel + NB * n : slot + int64_t(2) * n * NB;
     const int tid = threadIdx.x, bs = blockDim.x;
     bool bad = false;
     for (int t = tid; t < n * kb; t += bs) {
@@ -254,6 +259,8 @@ __global__ void __launch_bounds__(kPanelBlock)
         const int i = t / kb, jj = t - i * kb;
         M[int64_t(i) * n + k0 + jj] = E[jj * n + i];
     }
+    if (IN_LDS)
+        for (int t = tid; t < n * kb; t += bs) slot[t] = E[t];
     if (bad && tid == 0) atomicOr(flag, 1);
 }
 
@@ -561,15 +568,30 @@ hipError_t launch_update(int S, int max_ns, const int32_t* sub_off, const int64_
     return hipGetLastError();
 }
 
-// panels eliminated by one workgroup per sub-circuit
+// panels eliminated by one workgroup per sub-circuit, in LDS when it holds them
 template <int NB>
 hipError_t invert_panels(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, double* scratch64,
                          double* panel, int32_t* ipiv, int* flag, hipStream_t st) {
     const dim3 cols(unsigned(S), unsigned((max_ns + kBlock - 1) / kBlock));
     hipError_t e;
+    int dev = 0, lds_max = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
+    const size_t lds = size_t(NB + 1) * max_ns * sizeof(double);
+    const size_t lds_static = kPanelBlock / 64 * (sizeof(double) + sizeof(int));
+    const bool in_lds = lds + lds_static <= size_t(lds_max);
+    if (in_lds && lds > 65536) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_gj_panel<NB, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
     for (int k0 = 0; k0 < max_ns; k0 += NB) {
-        hipLaunchKernelGGL(k_gj_panel<NB>, dim3(S), dim3(kPanelBlock), 0, st, sub_off, kofs, scratch64, k0, panel,
-                           ipiv, flag);
+        if (in_lds)
+            hipLaunchKernelGGL((k_gj_panel<NB, true>), dim3(S), dim3(kPanelBlock), lds, st, sub_off, kofs, scratch64,
+                               k0, panel, ipiv, flag);
+        else
+            hipLaunchKernelGGL((k_gj_panel<NB, false>), dim3(S), dim3(kPanelBlock), 0, st, sub_off, kofs, scratch64,
+                               k0, panel, ipiv, flag);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(k_gj_swap<NB>, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, ipiv);
         if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -914,45 +914,68 @@ vtm_status build_plan_vertex(const vtm_csr* A, const int32_t* label, const int32
             err = "W must be an n_iface x n_iface CSR";
             return VTM_E_ARG;
         }
-        std::map<std::pair<int32_t, int32_t>, double> ent;
-        for (int64_t l = 0; l < L; ++l) {
-            if (Wc->rowptr[l + 1] < Wc->rowptr[l]) {
-                err = "W: rowptr must be non-decreasing";
-                return VTM_E_ARG;
-            }
-            for (int64_t q = Wc->rowptr[l]; q < Wc->rowptr[l + 1]; ++q) {
-                const int32_t m = Wc->col[q];
-                if (m < 0 || m >= L || !std::isfinite(Wc->val[q])) {
-                    err = "W: column out of range or non-finite entry";
-                    return VTM_E_ARG;
-                }
-                if (sides[2 * l] != sides[2 * m] || sides[2 * l + 1] != sides[2 * m + 1]) {
-                    err = "W couples interfacial nodes " + std::to_string(iface[l]) + " and " +
-                          std::to_string(iface[m]) + ", which do not border the same two sub-circuits in the same order";
-                    return VTM_E_ARG;
-                }
-                ent[{int32_t(l), m}] += Wc->val[q];
-            }
-        }
+        // rows of W with duplicates summed in the caller's order and columns sorted
         wr.assign(L + 1, 0);
-        for (const auto& e : ent) {
-            auto it = ent.find({e.first.second, e.first.first});
-            if (it == ent.end() || it->second != e.second) {
-                err = "W must be symmetric";
-                return VTM_E_ARG;
+        {
+            std::vector<std::pair<int32_t, double>> row;
+            for (int64_t l = 0; l < L; ++l) {
+                if (Wc->rowptr[l + 1] < Wc->rowptr[l]) {
+                    err = "W: rowptr must be non-decreasing";
+                    return VTM_E_ARG;
+                }
+                row.clear();
+                for (int64_t q = Wc->rowptr[l]; q < Wc->rowptr[l + 1]; ++q) {
+                    const int32_t m = Wc->col[q];
+                    if (m < 0 || m >= L || !std::isfinite(Wc->val[q])) {
+                        err = "W: column out of range or non-finite entry";
+                        return VTM_E_ARG;
+                    }
+                    if (sides[2 * l] != sides[2 * m] || sides[2 * l + 1] != sides[2 * m + 1]) {
+                        err = "W couples interfacial nodes " + std::to_string(iface[l]) + " and " +
+                              std::to_string(iface[m]) +
+                              ", which do not border the same two sub-circuits in the same order";
+                        return VTM_E_ARG;
+                    }
+                    row.push_back({m, Wc->val[q]});
+                }
+                std::stable_sort(row.begin(), row.end(),
+                                 [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
+                                     return x.first < y.first;
+                                 });
+                const size_t start = wc.size();
+                for (const auto& e : row) {
+                    if (wc.size() > start && wc.back() == e.first)
+                        wv.back() += e.second;
+                    else {
+                        wc.push_back(e.first);
+                        wv.push_back(e.second);
+                    }
+                }
+                wr[l + 1] = int32_t(wc.size());
             }
-            wc.push_back(e.first.second);
-            wv.push_back(e.second);
-            wr[e.first.first + 1]++;
         }
-        for (int64_t l = 0; l < L; ++l) wr[l + 1] += wr[l];
+        auto wfind = [&](int32_t r, int32_t c, double& v) -> bool {
+            auto lo = wc.begin() + wr[r], hi = wc.begin() + wr[r + 1];
+            auto it = std::lower_bound(lo, hi, c);
+            if (it == hi || *it != c) return false;
+            v = wv[size_t(it - wc.begin())];
+            return true;
+        };
+        for (int64_t l = 0; l < L; ++l)
+            for (int32_t q = wr[l]; q < wr[l + 1]; ++q) {
+                double v;
+                if (!wfind(wc[q], int32_t(l), v) || v != wv[q]) {
+                    err = "W must be symmetric";
+                    return VTM_E_ARG;
+                }
+            }
         for (int64_t l = 0; l < L; ++l) {
-            auto it = ent.find({int32_t(l), int32_t(l)});
-            if (it == ent.end() || !(it->second > 0.0)) {
+            double v;
+            if (!wfind(int32_t(l), int32_t(l), v) || !(v > 0.0)) {
                 err = "W needs a positive diagonal";
                 return VTM_E_ARG;
             }
-            Z[l] = 1.0 / it->second;
+            Z[l] = 1.0 / v;
         }
         // W between the twins on each side: rows of the torn matrix
         std::vector<std::vector<std::pair<int32_t, double>>> rows(N);

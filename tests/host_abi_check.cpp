@@ -246,6 +246,44 @@ void vertex_checks() {
     check(vtm_split_vertex(&a, label.data(), dup.data(), sides.data(), L, &nt, &nnz, nullptr, nullptr, nullptr,
                            nullptr) == VTM_E_ARG,
           "distinct interfacial nodes");
+
+    // coupled lines: a dense symmetric W over the column's lines, given with its
+    // rows in reverse order and every entry split in two (duplicates summed)
+    std::vector<int64_t> wr(L + 1, 0);
+    std::vector<int32_t> wcol;
+    std::vector<double> wval;
+    auto w_of = [](int64_t l, int64_t m) { return l == m ? 4.0 : 1.0 / double(1 + (l > m ? l - m : m - l)); };
+    for (int64_t l = 0; l < L; ++l) {
+        for (int64_t m = L - 1; m >= 0; --m)
+            for (int half = 0; half < 2; ++half) {
+                wcol.push_back(int32_t(m));
+                wval.push_back(0.5 * w_of(l, m));
+            }
+        wr[l + 1] = int64_t(wcol.size());
+    }
+    auto plan_coupled = [&](const std::vector<double>& v, vtm::Plan& P) {
+        const vtm_csr Wc{L, int64_t(wcol.size()), wr.data(), wcol.data(), v.data()};
+        std::string err;
+        return vtm::build_plan_vertex(&a, label.data(), iface.data(), sides.data(), L, nullptr, 0, P, err, &Wc);
+    };
+    vtm::Plan P;
+    check(plan_coupled(wval, P) == VTM_OK && P.coupled, "coupled plan");
+    bool ok = int64_t(P.brow.size()) == P.nports + 1;
+    for (int64_t p = 0; ok && p < P.nports; ++p) {  // B = 2 W: a full row of L entries per port
+        ok = P.brow[p + 1] - P.brow[p] == L;
+        for (int32_t k = P.brow[p]; ok && k < P.brow[p + 1]; ++k) ok = P.bval[k] > 0.0;
+    }
+    check(ok, "coupled plan: B = 2 W over the ports");
+    auto asym = wval;
+    asym[2] *= 1.5;  // row 0, one half of an off-diagonal entry
+    check(plan_coupled(asym, P) == VTM_E_ARG, "coupled W must be symmetric");
+    auto nodiag = wval;
+    for (int64_t q = wr[3]; q < wr[4]; ++q)
+        if (wcol[q] == 3) nodiag[q] = -2.0;
+    check(plan_coupled(nodiag, P) == VTM_E_ARG, "coupled W needs a positive diagonal");
+    auto nan = wval;
+    nan[5] = NAN;
+    check(plan_coupled(nan, P) == VTM_E_ARG, "coupled W entries finite");
 }
 
 void misc_checks() {

@@ -798,95 +798,118 @@ vtm_status partial_schur_vertex(const VertexSplit& X, const int32_t* iface, cons
             adj[r].push_back(c);
             adj[c].push_back(int32_t(r));
         }
-    std::map<std::pair<int32_t, int32_t>, std::vector<int32_t>> groups;
-    for (int64_t l = 0; l < L; ++l) groups[{sides[2 * l], sides[2 * l + 1]}].push_back(int32_t(l));
+    // groups of lines with the same two sub-circuits, in (first, second) order
+    std::map<std::pair<int32_t, int32_t>, std::vector<int32_t>> by_pair;
+    for (int64_t l = 0; l < L; ++l) by_pair[{sides[2 * l], sides[2 * l + 1]}].push_back(int32_t(l));
+    const std::vector<std::pair<std::pair<int32_t, int32_t>, std::vector<int32_t>>> groups(by_pair.begin(),
+                                                                                         by_pair.end());
+    const int64_t G = int64_t(groups.size());
     W.assign(L, {});
-    std::vector<int32_t> loc(N, -1);  // index among the group's twins (< k) or chosen inner nodes (>= k)
-    for (const auto& grp : groups) {
-        const std::vector<int32_t>& lines = grp.second;
-        const int32_t blk = side ? grp.first.second : grp.first.first;
-        const int k = int(lines.size());
-        std::vector<int32_t> nodes(k);
-        for (int a = 0; a < k; ++a) {
-            nodes[a] = side ? int32_t(n + lines[a]) : iface[lines[a]];
-            loc[nodes[a]] = a;
-        }
-        // inner nodes of the sub-circuit within depth hops of the twins, breadth first
-        std::vector<int32_t> frontier(nodes), next;
-        for (int hop = 0; !frontier.empty() && (depth < 0 || hop < depth); ++hop) {
-            next.clear();
-            for (int32_t u : frontier)
-                for (int32_t v : adj[u])
-                    if (!is_twin[v] && X.part[v] == blk && loc[v] < 0) {
-                        loc[v] = int32_t(nodes.size());
-                        nodes.push_back(v);
-                        next.push_back(v);
+    // the groups are independent (each writes the rows of its own lines): they run
+    // on host threads, each thread with its own node-index scratch
+    std::vector<char> singular(G, 0);
+    const int64_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const int T = int(std::max<int64_t>(1, std::min<int64_t>({hw, 16, G})));
+    for_chunks(G, T, [&](int, int64_t g0, int64_t g1) {
+        std::vector<int32_t> loc(N, -1);  // index among the group's twins (< k) or chosen inner nodes (>= k)
+        for (int64_t g = g0; g < g1; ++g) {
+            auto one_group = [&]() {
+                const std::vector<int32_t>& lines = groups[g].second;
+                const int32_t blk = side ? groups[g].first.second : groups[g].first.first;
+                const int k = int(lines.size());
+                std::vector<int32_t> nodes(k);
+                for (int a = 0; a < k; ++a) {
+                    nodes[a] = side ? int32_t(n + lines[a]) : iface[lines[a]];
+                    loc[nodes[a]] = a;
+                }
+                // inner nodes of the sub-circuit within depth hops of the twins, breadth first
+                std::vector<int32_t> frontier(nodes), next;
+                for (int hop = 0; !frontier.empty() && (depth < 0 || hop < depth); ++hop) {
+                    next.clear();
+                    for (int32_t u : frontier)
+                        for (int32_t v : adj[u])
+                            if (!is_twin[v] && X.part[v] == blk && loc[v] < 0) {
+                                loc[v] = int32_t(nodes.size());
+                                nodes.push_back(v);
+                                next.push_back(v);
+                            }
+                    frontier.swap(next);
+                }
+                const int m = int(nodes.size()) - k;
+                // dense blocks: C (k x k), E (k x m), F (m x k), D (m x m), from the torn rows
+                std::vector<double> C(size_t(k) * k, 0.0), E(size_t(k) * m, 0.0), F(size_t(m) * k, 0.0),
+                    D(size_t(m) * m, 0.0);
+                for (int a = 0; a < int(nodes.size()); ++a) {
+                    const int32_t r = nodes[a];
+                    for (int64_t q = X.rowptr[r]; q < X.rowptr[r + 1]; ++q) {
+                        const int b = loc[X.col[q]];
+                        if (b < 0) continue;
+                        const double v = X.val[q];
+                        if (a < k && b < k) C[size_t(a) * k + b] += v;
+                        else if (a < k) E[size_t(a) * m + (b - k)] += v;
+                        else if (b < k) F[size_t(a - k) * k + b] += v;
+                        else D[size_t(a - k) * m + (b - k)] += v;
                     }
-            frontier.swap(next);
-        }
-        const int m = int(nodes.size()) - k;
-        // dense blocks: C (k x k), E (k x m), F (m x k), D (m x m), from the torn rows
-        std::vector<double> C(size_t(k) * k, 0.0), E(size_t(k) * m, 0.0), F(size_t(m) * k, 0.0),
-            D(size_t(m) * m, 0.0);
-        for (int a = 0; a < int(nodes.size()); ++a) {
-            const int32_t r = nodes[a];
-            for (int64_t q = X.rowptr[r]; q < X.rowptr[r + 1]; ++q) {
-                const int b = loc[X.col[q]];
-                if (b < 0) continue;
-                const double v = X.val[q];
-                if (a < k && b < k) C[size_t(a) * k + b] += v;
-                else if (a < k) E[size_t(a) * m + (b - k)] += v;
-                else if (b < k) F[size_t(a - k) * k + b] += v;
-                else D[size_t(a - k) * m + (b - k)] += v;
-            }
-        }
-        // F <- D^-1 F by Gaussian elimination with partial pivoting
-        for (int c = 0; c < m; ++c) {
-            int p = c;
-            for (int r = c + 1; r < m; ++r)
-                if (std::fabs(D[size_t(r) * m + c]) > std::fabs(D[size_t(p) * m + c])) p = r;
-            const double piv = D[size_t(p) * m + c];
-            if (piv == 0.0 || !std::isfinite(piv)) {
-                err = "the inner block of the Schur complement approximation is singular";
+                }
+                // F <- D^-1 F by Gaussian elimination with partial pivoting
+                for (int c = 0; c < m; ++c) {
+                    int p = c;
+                    for (int r = c + 1; r < m; ++r)
+                        if (std::fabs(D[size_t(r) * m + c]) > std::fabs(D[size_t(p) * m + c])) p = r;
+                    const double piv = D[size_t(p) * m + c];
+                    if (piv == 0.0 || !std::isfinite(piv)) {
+                        singular[g] = 1;
+                        for (int32_t v : nodes) loc[v] = -1;
+                        return;
+                    }
+                    if (p != c) {
+                        for (int j = 0; j < m; ++j) std::swap(D[size_t(p) * m + j], D[size_t(c) * m + j]);
+                        for (int j = 0; j < k; ++j) std::swap(F[size_t(p) * k + j], F[size_t(c) * k + j]);
+                    }
+                    for (int r = c + 1; r < m; ++r) {
+                        const double f = D[size_t(r) * m + c] / piv;
+                        if (f == 0.0) continue;
+                        for (int j = c; j < m; ++j) D[size_t(r) * m + j] -= f * D[size_t(c) * m + j];
+                        for (int j = 0; j < k; ++j) F[size_t(r) * k + j] -= f * F[size_t(c) * k + j];
+                    }
+                }
+                // back substitution as row operations: each entry of row c takes the
+                // products of rows t = c + 1, ... in that order, then the division
+                for (int c = m - 1; c >= 0; --c) {
+                    const double piv = D[size_t(c) * m + c];
+                    double* Fc = &F[size_t(c) * k];
+                    for (int t = c + 1; t < m; ++t) {
+                        const double d = D[size_t(c) * m + t];
+                        const double* Ft = &F[size_t(t) * k];
+                        for (int j = 0; j < k; ++j) Fc[j] -= d * Ft[j];
+                    }
+                    for (int j = 0; j < k; ++j) Fc[j] /= piv;
+                }
+                // S = C - E (D^-1 F), symmetrized, small entries dropped
+                for (int a = 0; a < k; ++a)
+                    for (int t = 0; t < m; ++t) {
+                        const double e = E[size_t(a) * m + t];
+                        if (e == 0.0) continue;
+                        for (int j = 0; j < k; ++j) C[size_t(a) * k + j] -= e * F[size_t(t) * k + j];
+                    }
+                for (int a = 0; a < k; ++a)
+                    for (int j = 0; j < k; ++j) {
+                        const double v = 0.5 * (C[size_t(a) * k + j] + C[size_t(j) * k + a]);
+                        if (a != j && (v == 0.0 || std::fabs(v) < drop * std::sqrt(std::fabs(C[size_t(a) * k + a] *
+                                                                                              C[size_t(j) * k + j]))))
+                            continue;
+                        W[lines[a]].push_back({lines[j], v});
+                    }
                 for (int32_t v : nodes) loc[v] = -1;
-                return VTM_E_SINGULAR;
-            }
-            if (p != c) {
-                for (int j = 0; j < m; ++j) std::swap(D[size_t(p) * m + j], D[size_t(c) * m + j]);
-                for (int j = 0; j < k; ++j) std::swap(F[size_t(p) * k + j], F[size_t(c) * k + j]);
-            }
-            for (int r = c + 1; r < m; ++r) {
-                const double f = D[size_t(r) * m + c] / piv;
-                if (f == 0.0) continue;
-                for (int j = c; j < m; ++j) D[size_t(r) * m + j] -= f * D[size_t(c) * m + j];
-                for (int j = 0; j < k; ++j) F[size_t(r) * k + j] -= f * F[size_t(c) * k + j];
-            }
+            };
+            one_group();
         }
-        for (int c = m - 1; c >= 0; --c) {
-            const double piv = D[size_t(c) * m + c];
-            for (int j = 0; j < k; ++j) {
-                double v = F[size_t(c) * k + j];
-                for (int t = c + 1; t < m; ++t) v -= D[size_t(c) * m + t] * F[size_t(t) * k + j];
-                F[size_t(c) * k + j] = v / piv;
-            }
+    });
+    for (int64_t g = 0; g < G; ++g)
+        if (singular[g]) {
+            err = "the inner block of the Schur complement approximation is singular";
+            return VTM_E_SINGULAR;
         }
-        // S = C - E (D^-1 F), symmetrized, small entries dropped
-        for (int a = 0; a < k; ++a)
-            for (int t = 0; t < m; ++t) {
-                const double e = E[size_t(a) * m + t];
-                if (e == 0.0) continue;
-                for (int j = 0; j < k; ++j) C[size_t(a) * k + j] -= e * F[size_t(t) * k + j];
-            }
-        for (int a = 0; a < k; ++a)
-            for (int j = 0; j < k; ++j) {
-                const double v = 0.5 * (C[size_t(a) * k + j] + C[size_t(j) * k + a]);
-                if (a != j && (v == 0.0 || std::fabs(v) < drop * std::sqrt(std::fabs(C[size_t(a) * k + a] *
-                                                                                      C[size_t(j) * k + j]))))
-                    continue;
-                W[lines[a]].push_back({lines[j], v});
-            }
-        for (int32_t v : nodes) loc[v] = -1;
-    }
     return VTM_OK;
 }
 

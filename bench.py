@@ -453,6 +453,39 @@ def preconditioners(vtm, torch, workloads):
     return out
 
 
+def setup_times(vtm, torch, workloads, which="all"):
+    """Setup (plan, uploads, blocked Gauss-Jordan inverses on the GPU, port operators)
+    of the two workloads with the largest sub-circuits, each set up twice: "128",
+    the 128^3 grid with controlled sources (4,096 inverses of 512 nodes); "30", the
+    30^3 unit grid torn at one separator plane (two inverses of 14,400 nodes)."""
+    cases = {}
+    if which in ("all", "128"):
+        w = workloads.make(3)
+        cases["128^3, 4096 sub-circuits of 512 nodes, FP64"] = lambda: vtm.Solver(w.A, w.part, w.Z)
+    if which in ("all", "30"):
+        dims = (30, 30, 30)
+        e = workloads.grid3d_edges(*dims)
+        n = int(np.prod(dims))
+        A = workloads.nodal_matrix(n, e, np.ones(e.shape[0]), np.full(n, workloads.GROUND_S))
+        label, iface, sides = workloads.separator_strips(dims, 14)
+        W = vtm.vertex_admittance(A, label, iface, sides, "diag", 1.0)
+        cases["30^3 torn at one separator plane, 2 sub-circuits of 14,400 nodes, FP64"] = \
+            lambda: vtm.Solver(A, label, None, iface=iface, sides=sides, W=W)
+    out = {}
+    for name, make in cases.items():
+        ms = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            s = make()
+            torch.cuda.synchronize()
+            ms.append(round((time.perf_counter() - t) * 1e3, 1))
+            s.close()
+        out[name] = {"setup_ms": ms}
+        log(f"setup {name}: {ms} ms")
+    return out
+
+
 def vertex_tearing(vtm, torch, workloads):
     """Tearing at interfacial nodes (Section V) with the admittance rules of
     Section VIII as coupled lines, on unit resistor grids like Table I's Grid2d
@@ -518,6 +551,10 @@ def main():
                          "calibrate FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--mfma-counters", action="store_true",
                     help="for MFMA counters: one BF16 and one FP64 batched solve of the 64-RHS workload")
+    ap.add_argument("--setup-only", nargs="?", const="all", choices=["all", "128", "30"],
+                    help="for profiling: only the setups of large sub-circuits (128: the 128^3 grid's 4,096 "
+                         "inverses of 512 nodes; 30: the 30^3 grid torn at one separator plane, two inverses "
+                         "of 14,400 nodes; all: both); prints their JSON")
     ap.add_argument("--vertex-only", action="store_true",
                     help="for profiling: only the tearing at interfacial nodes; prints its JSON")
     ap.add_argument("--batched-only", action="store_true",
@@ -557,6 +594,12 @@ def main():
                          "batch_shape": list(rep4.batch_shape), "port_operator_bytes": s4.port_operator_bytes,
                          "relres": float(host_relres(w4.A, w4.b, x4.cpu().numpy()).max())}
             s4.close()
+        if args.calibrate:
+            calibration_copy()
+        print(json.dumps(out), flush=True)
+        return
+    if args.setup_only:
+        out = setup_times(vtm, torch, workloads, args.setup_only)
         if args.calibrate:
             calibration_copy()
         print(json.dumps(out), flush=True)

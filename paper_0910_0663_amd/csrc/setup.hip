@@ -188,7 +188,8 @@ __global__ void __launch_bounds__(kBlock)
 constexpr int kNB = 32;           // panel width up to kWide64 nodes
 constexpr int kWideNB = 64;       // panel width from kWide64 nodes
 constexpr int kWide64 = 8192;
-constexpr int kOneGroupMax = 2048;  // up to here one workgroup eliminates a sub-circuit's panel
+constexpr int kOneGroupMax = 2048;     // up to here one workgroup eliminates a sub-circuit's panel,
+constexpr int kOneGroupMinSubs = 256;  // when there are enough sub-circuits to fill the chip
 constexpr int kMaxLarge = 16384;  // largest sub-circuit (the planner's limit)
 constexpr int kPanelBlock = 1024;
 constexpr int kUpdWaves = 4;      // wavefronts per workgroup of the update
@@ -634,8 +635,8 @@ hipError_t invert_large(int S, int max_ns, const int32_t* sub_off, const int64_t
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 cols(unsigned(S), unsigned((max_ns + kBlock - 1) / kBlock));
-    // larger sub-circuits spread each pivot step over the chip (two launches per column)
-    if (max_ns <= kOneGroupMax)
+    // larger sub-circuits, or a few, spread each pivot step over the chip (two launches per column)
+    if (max_ns <= kOneGroupMax && S >= kOneGroupMinSubs)
         e = invert_panels<kNB>(S, max_ns, sub_off, kofs, scratch64, panel, ipiv, flag, st);
     else if (max_ns < kWide64)
         e = invert_wide<kNB>(S, max_ns, sub_off, kofs, scratch64, panel, ipiv, flag, st);

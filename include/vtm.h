@@ -406,8 +406,12 @@ vtm_status vtm_refresh(vtm_handle h, const double *val, const double *Z, int64_t
 /*
  * Checkpoint / resume of the iteration state: the incident wave at every port
  * (two ports per cut wire: port 2e on the lower node of wire e, 2e+1 on the
- * upper), device FP64 [nrhs][2 * n_wires].  vtm_set_waves makes the next
- * vtm_solve start from these waves instead of zero.
+ * upper), device FP64 [nrhs][2 * n_wires].  vtm_get_waves gives the waves of
+ * the last sweep; vtm_set_waves makes the next vtm_solve start from these
+ * waves instead of zero.  FP64 handles only: a refining handle's iteration
+ * state is its FP64 solution together with the waves of an inner solve of a
+ * correction equation, which no wave vector alone resumes, so both calls give
+ * VTM_E_UNSUPPORTED there.
  */
 vtm_status vtm_get_waves(vtm_handle h, double *waves, int32_t nrhs);
 vtm_status vtm_set_waves(vtm_handle h, const double *waves, int32_t nrhs);

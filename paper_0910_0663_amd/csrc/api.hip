@@ -693,6 +693,8 @@ vtm_status run_chunk(vtm_handle h, bool low, int nrhs, bool adjoint, int64_t chu
 struct Cadence {
     int64_t m = 1;
     bool adaptive = false;
+    double reach = 0.5;     // fraction of the predicted sweeps to the target before the next check
+    int64_t cap = 64;       // at most this many m between checks
     int64_t s_prev = -1, s_last = -1;
     double r_prev = 0.0, r_last = 0.0;
     void record(int64_t s, double r) {
@@ -707,8 +709,8 @@ struct Cadence {
             return m;
         const double rate = std::log(r_last / r_prev) / double(s_last - s_prev);  // < 0
         const double left = std::log(target / r_last) / rate;                       // > 0
-        const int64_t k = int64_t(0.5 * left / double(m)) * m;
-        return std::min<int64_t>(std::max<int64_t>(k, m), 64 * m);
+        const int64_t k = int64_t(reach * left / double(m)) * m;
+        return std::min<int64_t>(std::max<int64_t>(k, m), cap * m);
     }
 };
 
@@ -801,6 +803,48 @@ vtm_status run_fp64(vtm_handle h, int nrhs, double tol, bool adjoint, bool resum
 }
 
 // Mixed precision: FP64 outer refinement around an FP32 inner VTM.
+// Algorithmic bytes of one port-to-port sweep of nrhs right-hand sides: operator
+// entries once (without layout padding); per port the wave in, h in, wave out
+// (and c for the packed form) plus the twin index; per port node its first port;
+// per sub-circuit its offsets.  0 without a port-to-port form.
+int64_t pp_sweep_bytes(const vtm_handle_s* h, int64_t nrhs) {
+    const vtm::Plan& P = h->plan;
+    const int64_t esize = h->opt.precision == VTM_FP64 ? 8 : (h->opt.precision == VTM_FP32_REFINE ? 4 : 2);
+    const int64_t tv = h->opt.precision == VTM_FP64 ? 8 : 4;  // waves (FP32 for the BF16 form)
+    if (h->ppb) return P.sq_entries * esize + P.nports * (4 + nrhs * 3 * tv) + P.S * 16;
+    if (h->ppn)
+        return P.sqn_entries * esize + P.nports * (6 * esize + 4) + int64_t(P.pn_node.size()) * 4 + P.S * 16;
+    if (h->pps)
+        return P.tri_entries * esize + P.nports * (4 * esize + 4 + (P.uniform_W ? 0 : esize)) +
+               int64_t(P.pn_node.size()) * 4 + P.S * 16;
+    if (h->pp) return P.sq_entries * esize + P.nports * (3 * esize + 4) + P.S * 12;
+    return 0;
+}
+
+// How far towards the predicted target an inner solve's next check goes: the
+// next check comes after this fraction of the predicted sweeps.  Far (0.9) when a
+// check costs more than a sweep, so that few checks are spent; halfway (0.5)
+// when sweeps cost more, so that little is overshot.  Costs from the bytes each
+// moves: a sweep streams its operator and vectors (plus ~4 us of launch, 20 MB at
+// 5 TB/s); a check reads per port its waves and its twin's with six
+// coefficients (port form) or A, b and x (CSR form), at about half a sweep's
+// rate (gathers), and waits for the host (~25 us, 125 MB).
+double inner_reach(const vtm_handle_s* h, int nrhs, bool pp) {
+    const vtm::Plan& P = h->plan;
+    const int64_t tv = h->opt.precision == VTM_FP64 ? 8 : 4;
+    const int64_t esize = h->opt.precision == VTM_FP64 ? 8 : (h->opt.precision == VTM_FP32_REFINE ? 4 : 2);
+    double sweep, check;
+    if (pp) {
+        sweep = double(pp_sweep_bytes(h, nrhs));
+        check = double(P.nports) * (3.0 * nrhs * tv + 44.0) + double(P.pn_node.size()) * (nrhs * tv + 8.0);
+    } else {
+        sweep = double(h->tiles ? P.mofs[P.S] : P.kofs[P.S]) * esize + double(P.n) * nrhs * 2.0 * tv;
+        check = double(P.col.size()) * 12.0 + double(P.n) * nrhs * (16.0 + tv);
+    }
+    const double c = (2.0 * check + 125e6) / (sweep + 20e6);
+    return c > 1.0 ? 0.9 : 0.5;
+}
+
 vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut& out) {
     const vtm::Plan& P = h->plan;
     const int64_t nv = P.n * nrhs, np = P.nports * nrhs;
@@ -841,6 +885,8 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
         Cadence cad;
         cad.m = h->opt.check_every;
         cad.adaptive = h->opt.adaptive_checks != 0;
+        cad.reach = inner_reach(h, nrhs, pp);
+        cad.cap = 4;
         cad.record(0, 1.0);
         double goal = 1.0;
         for (int r = 0; r < nrhs; ++r) goal = std::min(goal, target[r]);
@@ -850,9 +896,9 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
         int since = 0;
         while (true) {
             // an inner solve may stall above its target (the low-precision inverse
-            // bounds the reachable reduction), so its checks grow to at most 4 m
-            const int64_t chunk = std::min<int64_t>(
-                graph_length(h, std::min<int64_t>(cad.next(goal), 4 * cad.m)), h->opt.max_sweeps - inner);
+            // bounds the reachable reduction), so its checks are at most 4 m apart
+            const int64_t chunk =
+                std::min<int64_t>(graph_length(h, cad.next(goal)), h->opt.max_sweeps - inner);
             // sweeps, then ||r - A d|| / ||r|| in FP64 (from port quantities with pp)
             st = run_chunk(h, true, nrhs, adjoint, chunk, cur, e, pp, inner == 0, pp && !P.vertex, &rr);
             if (st != VTM_OK) return st;
@@ -1434,13 +1480,11 @@ vtm_status vtm_refresh(vtm_handle h, const double* val, const double* Z, int64_t
 vtm_status vtm_get_waves(vtm_handle h, double* waves, int32_t nrhs) {
     return vtm::guarded([&]() -> vtm_status {
         if (!h || !waves || nrhs < 1 || nrhs > h->nrhs_max) return fail(VTM_E_ARG, "bad wave arguments");
+        if (h->opt.precision != VTM_FP64)
+            return fail(VTM_E_UNSUPPORTED, "checkpoint and resume of the waves need the FP64 precision");
         VTM_HIP(hipSetDevice(h->device));
-        if (h->opt.precision == VTM_FP64)
-            VTM_HIP(vtm::launch_waves_io<double>(h->plan.nports, nrhs, h->abi2port.p, h->a64[0].p, waves, true,
-                                                 h->stream));
-        else
-            VTM_HIP(vtm::launch_waves_io<float>(h->plan.nports, nrhs, h->abi2port.p, h->a32[0].p, waves, true,
-                                                h->stream));
+        VTM_HIP(vtm::launch_waves_io<double>(h->plan.nports, nrhs, h->abi2port.p, h->a64[0].p, waves, true,
+                                             h->stream));
         VTM_HIP(hipStreamSynchronize(h->stream));
         return VTM_OK;
     });
@@ -1449,7 +1493,8 @@ vtm_status vtm_get_waves(vtm_handle h, double* waves, int32_t nrhs) {
 vtm_status vtm_set_waves(vtm_handle h, const double* waves, int32_t nrhs) {
     return vtm::guarded([&]() -> vtm_status {
         if (!h || !waves || nrhs < 1 || nrhs > h->nrhs_max) return fail(VTM_E_ARG, "bad wave arguments");
-        if (h->opt.precision != VTM_FP64) return fail(VTM_E_UNSUPPORTED, "resume needs the FP64 precision");
+        if (h->opt.precision != VTM_FP64)
+            return fail(VTM_E_UNSUPPORTED, "checkpoint and resume of the waves need the FP64 precision");
         VTM_HIP(hipSetDevice(h->device));
         VTM_HIP(vtm::launch_waves_io<double>(h->plan.nports, nrhs, h->abi2port.p, h->a64[0].p,
                                              const_cast<double*>(waves), false, h->stream));
@@ -1475,24 +1520,7 @@ vtm_status vtm_info(vtm_handle h, int64_t* n, int64_t* n_sub, int64_t* n_wires, 
                            : h->pp  ? P.pofs[P.S] * esize
                                     : 0;
         if (port_operator_bytes) *port_operator_bytes = op;
-        if (port_sweep_bytes) {
-            // operator entries once (without layout padding); per port the wave in, h in, wave
-            // out (and c for the packed form) plus the twin index; per port node its first port;
-            // per sub-circuit its offsets
-            const int64_t tv = h->opt.precision == VTM_FP64 ? 8 : 4;  // waves (FP32 for the BF16 form)
-            if (h->ppb)
-                *port_sweep_bytes = P.sq_entries * esize + P.nports * (4 + int64_t(h->nrhs_max) * 3 * tv) + P.S * 16;
-            else if (h->ppn)
-                *port_sweep_bytes = P.sqn_entries * esize + P.nports * (6 * esize + 4) +
-                                    int64_t(P.pn_node.size()) * 4 + P.S * 16;
-            else if (h->pps)
-                *port_sweep_bytes = P.tri_entries * esize + P.nports * (4 * esize + 4 + (P.uniform_W ? 0 : esize)) +
-                                    int64_t(P.pn_node.size()) * 4 + P.S * 16;
-            else if (h->pp)
-                *port_sweep_bytes = P.sq_entries * esize + P.nports * (3 * esize + 4) + P.S * 12;
-            else
-                *port_sweep_bytes = 0;
-        }
+        if (port_sweep_bytes) *port_sweep_bytes = pp_sweep_bytes(h, h->nrhs_max);
         return VTM_OK;
     });
 }

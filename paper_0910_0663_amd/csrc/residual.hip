@@ -2,6 +2,7 @@
 // and b^2 (the convergence test ||b - A x||_2 / ||b||_2 <= tol).  Sums are
 // formed in a fixed order, so results are bitwise reproducible.
 #include "kernels.hpp"
+#include "layout.hpp"
 
 namespace vtm {
 
@@ -47,9 +48,13 @@ __global__ void __launch_bounds__(kBlock)
     const int per = blockDim.x / nrhs;
     const int used = per * nrhs;
     double rr = 0.0, bb = 0.0;
+    // each XCD takes one contiguous range of logical blocks, so that rows whose x
+    // rows overlap share an L2; a logical block's rows and partial sums are the
+    // same whichever hardware block runs it
+    const int lb = xcd_block(int(blockIdx.x), int(gridDim.x));
     if (tid < used) {
         const int rhs = tid % nrhs, rl = tid / nrhs;
-        int i0 = blockIdx.x * per + rl;
+        int i0 = lb * per + rl;
         if (UNI) i0 = __builtin_amdgcn_readfirstlane(i0);
         for (int64_t i = i0; i < n; i += int64_t(gridDim.x) * per) {
             const double bv = b[i * nrhs + rhs];
@@ -87,8 +92,8 @@ __global__ void __launch_bounds__(kBlock)
             a += s_rr[q * nrhs + j];
             c += s_bb[q * nrhs + j];
         }
-        partial[(int64_t(blockIdx.x) * nrhs + j) * 2 + 0] = a;
-        partial[(int64_t(blockIdx.x) * nrhs + j) * 2 + 1] = c;
+        partial[(int64_t(lb) * nrhs + j) * 2 + 0] = a;
+        partial[(int64_t(lb) * nrhs + j) * 2 + 1] = c;
     }
 }
 
@@ -127,6 +132,8 @@ __global__ void __launch_bounds__(kBlock)
     const int per = blockDim.x / nrhs;
     const int used = per * nrhs;
     double rr = 0.0;
+    // (blocks in dispatch order: the XCD-contiguous order of k_resid measured
+    // slower here, the twins' gathers then crowd one L2)
     if (tid < used) {
         const int rhs = tid % nrhs, rl = tid / nrhs;
         int n0 = blockIdx.x * per + rl;

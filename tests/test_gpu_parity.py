@@ -326,6 +326,14 @@ def test_resume_from_waves_is_bitwise_continuation(torch):
     x_cont, rep_cont = cont.solve(b, w.tol)
     assert rep_cont.sweeps + 24 == rep_full.sweeps
     assert torch.equal(x_cont, x_full)
+    # a refining handle has no wave checkpoint (its state is x with an inner solve's waves)
+    r = V.Solver(w.A, w.part, w.Z, precision="fp32_refine")
+    r.solve(b, w.tol)
+    for call in (r.get_waves, lambda: r.set_waves(waves)):
+        with pytest.raises(V.VTMError) as ei:
+            call()
+        assert ei.value.name == "VTM_E_UNSUPPORTED"
+    r.close()
 
 
 def test_repeat_runs_are_bitwise_identical(torch):

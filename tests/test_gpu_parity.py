@@ -189,8 +189,8 @@ def test_singular_sub_circuit_is_reported(torch):
 
 @pytest.mark.parametrize("kw", [dict(), dict(nrhs=16)])
 def test_largest_sub_circuits(torch, kw):
-    """Two sub-circuits of 8,192 nodes (the largest a handle takes, inverted in
-    blocked global-memory Gauss-Jordan; the full sweep stages 128 KiB of LDS):
+    """Two sub-circuits of 8,192 nodes (inverted in blocked global-memory
+    Gauss-Jordan with 64-column panels; the full sweep stages 128 KiB of LDS):
     iterates equal the oracle's in the port (128 ports each, dense operator)
     and full forms; with 16 right-hand sides the FP64 handle keeps the
     column-group layout because an 8,192-row block does not fit the batched
@@ -202,6 +202,26 @@ def test_largest_sub_circuits(torch, kw):
     for form in ("port", "full"):
         for k in ks:
             assert_close(gpu_iterate(torch, w, k, check_every=k, local_form=form), ref[k])
+
+
+def test_sub_circuits_at_the_size_limit(torch):
+    """Two sub-circuits of 16,384 nodes, the planner's limit: each FP64 inverse
+    is exactly 2^31 bytes, the largest range the setup's buffer loads and stores
+    address (an offset of 2^31 marks a masked lane), inverted with 64-column
+    panels whose pivot steps are launches of their own.  The solve (port-to-port,
+    128 ports each) reaches the sparse LU's solution; a second right-hand side is
+    refused (a full sweep of this size stages one in LDS)."""
+    w = workloads.make(1, dims=(128, 256), block=(128, 128))
+    assert w.n_sub == 2 and np.bincount(w.part).max() == 16384
+    s = vtm().Solver(w.A, w.part, w.Z)
+    x, rep = s.solve(to_dev(torch, w.b), 1e-10)
+    s.close()
+    xs = spla.spsolve(w.A.tocsc(), w.b[0])
+    assert oracle.relative_residual(w.A, w.b, x.cpu().numpy()).max() <= 1e-10
+    assert np.abs(x.cpu().numpy()[0] - xs).max() <= 1e-6 * np.abs(xs).max()
+    with pytest.raises(vtm().VTMError) as ei:
+        vtm().Solver(w.A, w.part, w.Z, nrhs_max=2)
+    assert ei.value.name == "VTM_E_UNSUPPORTED"
 
 
 @pytest.mark.parametrize("cfg,kw,rule,alpha", [

@@ -419,13 +419,18 @@ __global__ void __launch_bounds__(kBlock)
 template <int NB, int CT>
 __global__ void __launch_bounds__(kUpdWaves * 64)
     k_gj_update(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
-                int k0, const double* __restrict__ panel) {
+                int k0, const double* __restrict__ panel, int S, int ncb) {
     constexpr int Q = NB / 4;  // MFMA steps
-    const int s = blockIdx.x;
+    // one-dimensional grid of (row block, sub-circuit, column block), column block
+    // fastest, each XCD taking a contiguous range: the column blocks that read the
+    // same rows of a sub-circuit's panel run one after another on one L2
+    const int u = xcd_block(int(blockIdx.x), int(gridDim.x));
+    const int cb = u % ncb, t = u / ncb;
+    const int s = t % S, rb = t / S;
     const int off = sub_off[s], n = sub_off[s + 1] - off;
     if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;
     const int kb = min(NB, n - k0);
-    const int c0 = blockIdx.y * (16 * CT), r0 = blockIdx.z * kUpdRows;
+    const int c0 = cb * (16 * CT), r0 = rb * kUpdRows;
     if (c0 >= n || r0 >= n) return;
     const int r1 = min(n, r0 + kUpdRows);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -562,10 +567,11 @@ template <int NB>
 hipError_t launch_update(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, double* scratch64, int k0,
                          const double* panel, hipStream_t st) {
     constexpr int CT = NB <= 32 ? 4 : 2;   // column tiles per wavefront (the B operand stays in registers)
-    const dim3 grid(unsigned(S), unsigned((max_ns + 16 * CT - 1) / (16 * CT)),
-                    unsigned((max_ns + kUpdRows - 1) / kUpdRows));
-    hipLaunchKernelGGL((k_gj_update<NB, CT>), grid, dim3(kUpdWaves * 64), 0, st, sub_off, kofs, scratch64, k0,
-                       panel);
+    const int ncb = (max_ns + 16 * CT - 1) / (16 * CT), nrb = (max_ns + kUpdRows - 1) / kUpdRows;
+    const int64_t blocks = int64_t(S) * ncb * nrb;
+    if (blocks > INT_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_gj_update<NB, CT>), dim3(unsigned(blocks)), dim3(kUpdWaves * 64), 0, st, sub_off, kofs,
+                       scratch64, k0, panel, S, ncb);
     return hipGetLastError();
 }
 

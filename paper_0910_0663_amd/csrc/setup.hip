@@ -173,10 +173,11 @@ __global__ void __launch_bounds__(kBlock)
 
 // ... and invert it in place, NB columns at a time (blocked Gauss-Jordan with
 // partial pivoting).  Each panel step is a few launches, so that a few large
-// sub-circuits still spread over the whole chip.  k_gj_panel (one workgroup per
-// sub-circuit) eliminates the panel's columns (pivot search over all rows below
-// the diagonal; the panel E_J in global memory, column-major [NB][n] at the
-// sub-circuit's panel slot, so that a column is contiguous); k_gj_swap applies
+// sub-circuits still spread over the whole chip.  k_gj_panel_reg (one workgroup
+// per sub-circuit, a row per thread) or k_gjw_pivot / k_gjw_elim (a launch each
+// per column, for large or few sub-circuits) eliminate the panel's columns (pivot
+// search over all rows below the diagonal) and leave E_J in global memory,
+// column-major [NB][n] at the sub-circuit's panel slot; k_gj_swap applies
 // the panel's row swaps P to every other column and keeps their pivot rows
 // (P R)_J ([NB][n] right after E_J, then n doubles of scratch for the pivot
 // column), one column per thread.  k_gj_update then applies the elimination to
@@ -188,8 +189,8 @@ __global__ void __launch_bounds__(kBlock)
 constexpr int kNB = 32;           // panel width up to kWide64 nodes
 constexpr int kWideNB = 64;       // panel width from kWide64 nodes
 constexpr int kWide64 = 8192;
-constexpr int kOneGroupMax = 2048;     // up to here one workgroup eliminates a sub-circuit's panel,
-constexpr int kOneGroupMinSubs = 256;  // when there are enough sub-circuits to fill the chip
+constexpr int kOneGroupMinSubs = 256;  // one workgroup eliminates each sub-circuit's panel (up to
+                                       // kPanelBlock nodes) when there are enough to fill the chip
 constexpr int kMaxLarge = 16384;  // largest sub-circuit (the planner's limit)
 constexpr int kPanelBlock = 1024;
 constexpr int kUpdWaves = 4;      // wavefronts per workgroup of the update
@@ -198,72 +199,6 @@ constexpr int kUpdRows = 512;     // rows per workgroup of the update (eight 16-
 // doubles per node of the panel buffer for NB-column panels: E_J, (P R)_J, the
 // pivot column, and one of padding that keeps every row of E_J 16-byte aligned
 __host__ __device__ constexpr int panel_stride(int NB) { return 2 * NB + 2; }
-
-// One workgroup per sub-circuit eliminates the panel's kb columns one after the
-// other.  IN_LDS: the panel and the pivot column live in LDS (dynamic, NB + 1
-// doubles per node) and go to the panel slot at the end (k_gj_update reads them
-// there); else they are worked on in the panel slot itself.
-template <int NB, bool IN_LDS>
-__global__ void __launch_bounds__(kPanelBlock)
-    k_gj_panel(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
-               int k0, double* __restrict__ panel, int32_t* __restrict__ ipiv, int* flag) {
-    extern __shared__ double lds_panel[];
-    __shared__ double red_v[kPanelBlock / 64];
-    __shared__ int red_i[kPanelBlock / 64];
-    const int s = blockIdx.x;
-    const int off = sub_off[s], n = sub_off[s + 1] - off;
-    if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;
-    const int kb = min(NB, n - k0);
-    double* M = base + kofs[s];
-    double* slot = panel + int64_t(off) * panel_stride(NB);  // E_J column-major: entry (i, jj) at jj n + i
-    double* E = IN_LDS ? lds_panel : slot;
-    double* fcol = IN_LDS ? lds_panel + NB * n : slot + int64_t(2) * n * NB;
-    const int tid = threadIdx.x, bs = blockDim.x;
-    bool bad = false;
-    for (int t = tid; t < n * kb; t += bs) {
-        const int i = t / kb, jj = t - i * kb;
-        E[jj * n + i] = M[int64_t(i) * n + k0 + jj];
-    }
-    __syncthreads();
-    for (int kk = 0; kk < kb; ++kk) {
-        const int k = k0 + kk;
-        int p = block_argmax(E + kk * n, 1, k, n, red_v, red_i);
-        if (p == INT_MAX) {
-            bad = true;
-            p = k;
-        }
-        if (tid == 0) ipiv[off + k] = p;
-        if (p != k)
-            for (int jj = tid; jj < kb; jj += bs) {
-                const double t = E[jj * n + k];
-                E[jj * n + k] = E[jj * n + p];
-                E[jj * n + p] = t;
-            }
-        __syncthreads();
-        double pv = E[kk * n + k];
-        if (pv == 0.0 || !isfinite(pv)) {
-            bad = true;
-            pv = 1.0;
-        }
-        for (int i = tid; i < n; i += bs) fcol[i] = E[kk * n + i];
-        __syncthreads();
-        for (int jj = tid; jj < kb; jj += bs) E[jj * n + k] = (jj == kk ? 1.0 : E[jj * n + k]) / pv;
-        __syncthreads();
-        for (int t = tid; t < n * kb; t += bs) {
-            const int jj = t / n, i = t - jj * n;
-            if (i != k) E[jj * n + i] = (jj == kk ? 0.0 : E[jj * n + i]) - fcol[i] * E[jj * n + k];
-        }
-        __syncthreads();
-    }
-    // the panel's columns are final for this step
-    for (int t = tid; t < n * kb; t += bs) {
-        const int i = t / kb, jj = t - i * kb;
-        M[int64_t(i) * n + k0 + jj] = E[jj * n + i];
-    }
-    if (IN_LDS)
-        for (int t = tid; t < n * kb; t += bs) slot[t] = E[t];
-    if (bad && tid == 0) atomicOr(flag, 1);
-}
 
 typedef double dx4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
@@ -282,6 +217,124 @@ __device__ inline double buf_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
 }
 __device__ inline void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, double v) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, int(off), 0, 0);
+}
+
+// Block-wide argmax of the threads' own candidates (v < 0: none); ties go to the
+// lowest row, and no candidate that is a number gives INT_MAX, as block_argmax.
+__device__ int block_argmax_own(double v, int idx, double* red_v, int* red_i) {
+    double bv = -1.0;
+    int bi = INT_MAX;
+    if (v >= 0.0 || v != v) arg_better(bv, bi, v, idx);  // a NaN candidate never wins, as there
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        arg_better(bv, bi, ov, oi);
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red_v[wave] = bv;
+        red_i[wave] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v0 = red_v[0];
+        int i0 = red_i[0];
+        for (int w = 1; w < int(blockDim.x >> 6); ++w) arg_better(v0, i0, red_v[w], red_i[w]);
+        red_i[0] = i0;
+    }
+    __syncthreads();
+    const int p = red_i[0];
+    __syncthreads();
+    return p;
+}
+
+// The panel elimination for sub-circuits of up to blockDim.x (at most
+// kPanelBlock) nodes, one workgroup per sub-circuit, with row i of the panel in
+// thread i's registers.  Column by column: the pivot search reduces the threads'
+// own entries (ties to the lowest row), rows k and p trade places through LDS,
+// the pivot row is scaled and published in LDS, and every other row updates
+// itself.  No panel in LDS, so several workgroups share a CU.  An entry of column
+// kk is picked from the registers by selects (a register array indexed at run
+// time would go to scratch memory).
+template <int NB>
+__global__ void __launch_bounds__(kPanelBlock)
+    k_gj_panel_reg(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
+                   int k0, double* __restrict__ panel, int32_t* __restrict__ ipiv, int* flag) {
+    __shared__ double red_v[kPanelBlock / 64];
+    __shared__ int red_i[kPanelBlock / 64];
+    __shared__ double prow[NB], xrow[NB], pv_s;
+    const int s = blockIdx.x;
+    const int off = sub_off[s], n = sub_off[s + 1] - off;
+    if (n <= kLdsSetupMax || k0 >= n || n > int(blockDim.x)) return;  // uniform over the workgroup
+    const int kb = min(NB, n - k0);
+    double* M = base + kofs[s];
+    double* slot = panel + int64_t(off) * panel_stride(NB);  // E_J column-major: entry (i, jj) at jj n + i
+    const int i = threadIdx.x;
+    const bool mine = i < n;
+    double row[NB];
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj) row[jj] = (mine && jj < kb) ? M[int64_t(i) * n + k0 + jj] : 0.0;
+    auto pick = [&](int kk) {
+        double v = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj) v = jj == kk ? row[jj] : v;
+        return v;
+    };
+    bool bad = false;
+    for (int kk = 0; kk < kb; ++kk) {
+        const int k = k0 + kk;
+        int p = block_argmax_own(mine && i >= k ? fabs(pick(kk)) : -1.0, i, red_v, red_i);
+        if (p == INT_MAX) {
+            bad = true;
+            p = k;
+        }
+        if (i == 0) ipiv[off + k] = p;
+        if (p != k) {  // uniform: rows k and p trade places through LDS
+            if (i == k)
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) prow[jj] = row[jj];
+            if (i == p)
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) xrow[jj] = row[jj];
+            __syncthreads();
+            if (i == k)
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) row[jj] = xrow[jj];
+            if (i == p)
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) row[jj] = prow[jj];
+            __syncthreads();
+        }
+        if (i == k) pv_s = pick(kk);
+        __syncthreads();
+        double pv = pv_s;
+        if (pv == 0.0 || !isfinite(pv)) {
+            bad = true;
+            pv = 1.0;
+        }
+        if (i == k) {
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) {
+                row[jj] = (jj == kk ? 1.0 : row[jj]) / pv;
+                prow[jj] = row[jj];
+            }
+        }
+        __syncthreads();
+        if (mine && i != k) {
+            const double f = pick(kk);
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) row[jj] = (jj == kk ? 0.0 : row[jj]) - f * prow[jj];
+        }
+    }
+    // the panel's columns are final for this step; k_gj_update reads them from the slot
+    if (mine)
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj)
+            if (jj < kb) {
+                M[int64_t(i) * n + k0 + jj] = row[jj];
+                slot[int64_t(jj) * n + i] = row[jj];
+            }
+    if (bad && i == 0) atomicOr(flag, 1);
 }
 
 // The same panel elimination for a few very large sub-circuits, where one
@@ -415,7 +468,7 @@ __global__ void __launch_bounds__(kBlock)
 // segments per instruction.  Masked lanes use out-of-range buffer offsets, so no
 // load or store sits behind a branch and the next tile's loads, issued before
 // this tile's MFMAs, stay in flight while they run.  Columns of the panel are
-// left as k_gj_panel wrote them.
+// left as the panel elimination wrote them.
 template <int NB, int CT>
 __global__ void __launch_bounds__(kUpdWaves * 64)
     k_gj_update(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
@@ -575,30 +628,19 @@ hipError_t launch_update(int S, int max_ns, const int32_t* sub_off, const int64_
     return hipGetLastError();
 }
 
-// panels eliminated by one workgroup per sub-circuit, in LDS when it holds them
+// panels eliminated by one workgroup per sub-circuit (max_ns <= kPanelBlock), a
+// row per thread in registers, as many threads as the largest sub-circuit has
+// rows (smaller workgroups reduce faster and share a CU)
 template <int NB>
 hipError_t invert_panels(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, double* scratch64,
                          double* panel, int32_t* ipiv, int* flag, hipStream_t st) {
+    if (max_ns > kPanelBlock) return hipErrorInvalidValue;
     const dim3 cols(unsigned(S), unsigned((max_ns + kBlock - 1) / kBlock));
     hipError_t e;
-    int dev = 0, lds_max = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
-    const size_t lds = size_t(NB + 1) * max_ns * sizeof(double);
-    const size_t lds_static = kPanelBlock / 64 * (sizeof(double) + sizeof(int));
-    const bool in_lds = lds + lds_static <= size_t(lds_max);
-    if (in_lds && lds > 65536) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_gj_panel<NB, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-    }
+    const unsigned reg_threads = unsigned((max_ns + 63) / 64 * 64);
     for (int k0 = 0; k0 < max_ns; k0 += NB) {
-        if (in_lds)
-            hipLaunchKernelGGL((k_gj_panel<NB, true>), dim3(S), dim3(kPanelBlock), lds, st, sub_off, kofs, scratch64,
-                               k0, panel, ipiv, flag);
-        else
-            hipLaunchKernelGGL((k_gj_panel<NB, false>), dim3(S), dim3(kPanelBlock), 0, st, sub_off, kofs, scratch64,
-                               k0, panel, ipiv, flag);
+        hipLaunchKernelGGL(k_gj_panel_reg<NB>, dim3(S), dim3(reg_threads), 0, st, sub_off, kofs, scratch64, k0,
+                           panel, ipiv, flag);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(k_gj_swap<NB>, cols, dim3(kBlock), 0, st, sub_off, kofs, scratch64, k0, panel, ipiv);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -642,7 +684,7 @@ hipError_t invert_large(int S, int max_ns, const int32_t* sub_off, const int64_t
     if (e != hipSuccess) return e;
     const dim3 cols(unsigned(S), unsigned((max_ns + kBlock - 1) / kBlock));
     // larger sub-circuits, or a few, spread each pivot step over the chip (two launches per column)
-    if (max_ns <= kOneGroupMax && S >= kOneGroupMinSubs)
+    if (max_ns <= kPanelBlock && S >= kOneGroupMinSubs)
         e = invert_panels<kNB>(S, max_ns, sub_off, kofs, scratch64, panel, ipiv, flag, st);
     else if (max_ns < kWide64)
         e = invert_wide<kNB>(S, max_ns, sub_off, kofs, scratch64, panel, ipiv, flag, st);

@@ -1095,18 +1095,39 @@ vtm_status build_plan_vertex(const vtm_csr* A, const int32_t* label, const int32
 void transpose_csr(const Plan& P, std::vector<int32_t>& rowptr, std::vector<int32_t>& col,
                    std::vector<double>& val) {
     const int64_t n = P.n, nnz = int64_t(P.col.size());
+    // contiguous ranges of rows on host threads; a thread's entries of column c go
+    // after those of the threads before it, so every column of A^T lists its rows
+    // in ascending order (as a single pass over the rows would)
+    const int T = plan_threads(nnz);
+    std::vector<std::vector<int32_t>> cnt(T, std::vector<int32_t>(n, 0));
+    for_chunks(n, T, [&](int t, int64_t r0, int64_t r1) {
+        for (int64_t k = P.rowptr[r0]; k < P.rowptr[r1]; ++k) cnt[t][P.col[k]]++;
+    });
     rowptr.assign(n + 1, 0);
-    for (int64_t k = 0; k < nnz; ++k) rowptr[P.col[k] + 1]++;
+    for_chunks(n, T, [&](int, int64_t c0, int64_t c1) {  // per column: its length, each thread's start in it
+        for (int64_t c = c0; c < c1; ++c) {
+            int32_t run = 0;
+            for (int t = 0; t < T; ++t) {
+                const int32_t k = cnt[t][c];
+                cnt[t][c] = run;
+                run += k;
+            }
+            rowptr[c + 1] = run;
+        }
+    });
     for (int64_t i = 0; i < n; ++i) rowptr[i + 1] += rowptr[i];
     col.resize(nnz);
     val.resize(nnz);
-    std::vector<int32_t> fill(rowptr.begin(), rowptr.end() - 1);
-    for (int64_t r = 0; r < n; ++r)  // rows ascending -> columns of A^T come out sorted
-        for (int32_t k = P.rowptr[r]; k < P.rowptr[r + 1]; ++k) {
-            const int32_t w = fill[P.col[k]]++;
-            col[w] = int32_t(r);
-            val[w] = P.val[k];
-        }
+    for_chunks(n, T, [&](int t, int64_t r0, int64_t r1) {
+        std::vector<int32_t>& fill = cnt[t];
+        for (int64_t r = r0; r < r1; ++r)
+            for (int32_t k = P.rowptr[r]; k < P.rowptr[r + 1]; ++k) {
+                const int32_t c = P.col[k];
+                const int32_t w = rowptr[c] + fill[c]++;
+                col[w] = int32_t(r);
+                val[w] = P.val[k];
+            }
+    });
 }
 
 }  // namespace vtm

@@ -339,6 +339,20 @@ void threaded_plan_checks() {
             ok = P.port_node[p - 1] < P.port_node[p] ||
                  (P.port_node[p - 1] == P.port_node[p] && P.port_slot[p] == P.port_slot[p - 1] + 1);
     check(ok, "threaded plan: port tables");
+    // the transpose (split over threads) against a single pass over the rows
+    std::vector<int32_t> rT, cT, rS(P.n + 1, 0), cS(P.col.size());
+    std::vector<double> vT, vS(P.col.size());
+    vtm::transpose_csr(P, rT, cT, vT);
+    for (int32_t c : P.col) rS[c + 1]++;
+    for (int64_t i = 0; i < P.n; ++i) rS[i + 1] += rS[i];
+    std::vector<int32_t> fill(rS.begin(), rS.end() - 1);
+    for (int64_t r = 0; r < P.n; ++r)
+        for (int32_t k = P.rowptr[r]; k < P.rowptr[r + 1]; ++k) {
+            const int32_t w = fill[P.col[k]]++;
+            cS[w] = int32_t(r);
+            vS[w] = P.val[k];
+        }
+    check(rT == rS && cT == cS && vT == vS, "threaded plan: transpose");
     vtm::Plan R = P;
     check(vtm::refresh_plan(R, A.val.data(), int64_t(A.val.size()), &Z, 1, err) == VTM_OK &&
               R.val == P.val && R.dmod == P.dmod && R.pbeta == P.pbeta,

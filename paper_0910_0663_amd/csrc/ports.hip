@@ -452,9 +452,10 @@ __device__ inline void pps_unit(int unit, int S, const TO* __restrict__ Sp, cons
         ca[hb + r] = c * a;
     }
     int f0 = 0, f1 = 0;
-    if (r < k) {
-        f0 = pn_pfirst[n0 + r] - p0;
-        f1 = pn_pfirst[n0 + r + 1] - p0;
+    if (r < k) f0 = pn_pfirst[n0 + r] - p0;
+    {
+        const int nx = __shfl(f0, tid + 1);  // lane r + 1's first port (the last lane: q)
+        f1 = r + 1 < k ? nx : q;
     }
     TO buf[L];  // diagonal d of this lane's row (compile-time indices only)
     // CH / 2 pairs per chunk, one 16-byte (FP64) load each: S(r, r + 2m), S(r, r + 2m + 1)

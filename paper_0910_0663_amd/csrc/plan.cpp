@@ -17,6 +17,7 @@
 #include <exception>
 #include <limits>
 #include <map>
+#include <memory>
 #include <numeric>
 #include <thread>
 
@@ -501,39 +502,62 @@ vtm_status refresh_plan(Plan& P, const double* val, int64_t nnz, const double* Z
         err = "null values";
         return VTM_E_ARG;
     }
-    std::vector<double> nv(P.val.size());
-    double cur = 0.0;
-    int32_t dst = -1;
-    bool diag = false;
-    auto close = [&]() -> bool {  // false: the merged entry changes the pattern
-        if (dst >= 0) {
-            if (cur == 0.0 && !diag) return false;
-            nv[dst] = cur;
-        } else if (cur != 0.0) {
-            return false;
-        }
-        return true;
-    };
-    for (int64_t q = 0; q < nnz; ++q) {
-        const double v = val[P.src_ent[q]];
-        if (!std::isfinite(v)) {
-            err = "non-finite matrix entry";
-            return VTM_E_ARG;
-        }
-        if (P.src_flag[q] & 1) {
-            if (q > 0 && !close()) {
-                err = "the new values change which off-diagonal entries are zero (the sparsity pattern)";
-                return VTM_E_ARG;
-            }
-            cur = v;
-            dst = P.src_dst[q];
-            diag = (P.src_flag[q] & 2) != 0;
-        } else {
-            cur += v;
-        }
+    // The merge runs on threads, each over whole merged entries: chunk t starts at
+    // the first merged entry that begins at or after nnz t / T.  A chunk stops at
+    // its first failure; the failure a single pass would meet first wins, keyed by
+    // the source position (a non-finite value at q before the pattern check of the
+    // merged entry that ends just before q).  Every entry of nv is written when no
+    // chunk fails; it is left uninitialised so that its pages are first touched by
+    // the threads rather than zeroed on one.
+    const int64_t m = int64_t(P.val.size());
+    std::unique_ptr<double[]> nv(new double[size_t(std::max<int64_t>(m, 1))]);
+    const int T = plan_threads(nnz);
+    std::vector<int64_t> lo(T + 1, nnz), fkey(T, INT64_MAX);
+    lo[0] = 0;
+    for (int t = 1; t < T; ++t) {
+        int64_t q = nnz * t / T;
+        while (q < nnz && !(P.src_flag[q] & 1)) ++q;
+        lo[t] = q;
     }
-    if (nnz > 0 && !close()) {
-        err = "the new values change which off-diagonal entries are zero (the sparsity pattern)";
+    for (int t = T - 1; t >= 1; --t) lo[t] = std::min(lo[t], lo[t + 1]);
+    for_chunks(T, T, [&](int t, int64_t, int64_t) {
+        double cur = 0.0;
+        int32_t dst = -1;
+        bool diag = false;
+        auto close = [&]() -> bool {  // false: the merged entry changes the pattern
+            if (dst >= 0) {
+                if (cur == 0.0 && !diag) return false;
+                nv[dst] = cur;
+            } else if (cur != 0.0) {
+                return false;
+            }
+            return true;
+        };
+        const int64_t q0 = lo[t], q1 = lo[t + 1];
+        for (int64_t q = q0; q < q1; ++q) {
+            const double v = val[P.src_ent[q]];
+            if (!std::isfinite(v)) {
+                fkey[t] = 2 * q;
+                return;
+            }
+            if (P.src_flag[q] & 1) {
+                if (q > q0 && !close()) {
+                    fkey[t] = 2 * q + 1;
+                    return;
+                }
+                cur = v;
+                dst = P.src_dst[q];
+                diag = (P.src_flag[q] & 2) != 0;
+            } else {
+                cur += v;
+            }
+        }
+        if (q1 > q0 && !close()) fkey[t] = 2 * q1 + 1;
+    });
+    const int64_t first = *std::min_element(fkey.begin(), fkey.end());
+    if (first != INT64_MAX) {
+        err = (first & 1) ? "the new values change which off-diagonal entries are zero (the sparsity pattern)"
+                          : "non-finite matrix entry";
         return VTM_E_ARG;
     }
     // value at renumbered (r, c), which the pattern holds
@@ -542,30 +566,41 @@ vtm_status refresh_plan(Plan& P, const double* val, int64_t nnz, const double* Z
         auto it = std::lower_bound(lo, hi, c);
         return (it == hi || *it != c) ? -1 : int64_t(it - P.col.begin());
     };
-    bool sym = true;
-    for (int64_t r = 0; r < P.n && sym; ++r)
-        for (int32_t k = P.rowptr[r]; k < P.rowptr[r + 1]; ++k) {
-            const int64_t t = at(P.col[k], int32_t(r));
-            if (t < 0 || nv[t] != nv[k]) {
-                sym = false;
-                break;
+    std::vector<uint8_t> asym(T, 0);
+    for_chunks(P.n, T, [&](int t, int64_t r0, int64_t r1) {
+        for (int64_t r = r0; r < r1; ++r)
+            for (int32_t k = P.rowptr[r]; k < P.rowptr[r + 1]; ++k) {
+                const int64_t u = at(P.col[k], int32_t(r));
+                if (u < 0 || nv[u] != nv[k]) {
+                    asym[t] = 1;
+                    return;
+                }
             }
-        }
+    });
+    const bool sym = std::find(asym.begin(), asym.end(), 1) == asym.end();
     if (sym != P.symmetric) {
         err = "the new values change whether A is symmetric (the handle's local forms depend on it)";
         return VTM_E_UNSUPPORTED;
     }
     const int64_t nw = P.nwires;
+    const int TW = plan_threads(nw);
     std::vector<double> wg(nw), wW = P.wW;
-    for (int64_t e = 0; e < nw; ++e) {
-        const int32_t r = P.iperm[P.wi[e]], c = P.iperm[P.wj[e]];
-        const double v = nv[at(r, c)], vt = nv[at(c, r)];
-        if (v != vt || !(v < 0.0)) {
-            err = "coupling between nodes " + std::to_string(P.wi[e]) + " and " + std::to_string(P.wj[e]) +
-                  " in different sub-circuits is not a symmetric positive conductance";
-            return VTM_E_UNTEARABLE;
+    std::vector<int64_t> bad(TW, INT64_MAX);  // each chunk's first wire that is no conductance
+    for_chunks(nw, TW, [&](int t, int64_t e0, int64_t e1) {
+        for (int64_t e = e0; e < e1; ++e) {
+            const int32_t r = P.iperm[P.wi[e]], c = P.iperm[P.wj[e]];
+            const double v = nv[at(r, c)], vt = nv[at(c, r)];
+            if (v != vt || !(v < 0.0)) {
+                bad[t] = e;
+                return;
+            }
+            wg[e] = -v;
         }
-        wg[e] = -v;
+    });
+    if (const int64_t e = *std::min_element(bad.begin(), bad.end()); e != INT64_MAX) {
+        err = "coupling between nodes " + std::to_string(P.wi[e]) + " and " + std::to_string(P.wj[e]) +
+              " in different sub-circuits is not a symmetric positive conductance";
+        return VTM_E_UNTEARABLE;
     }
     if (Z && nZ > 0) {
         if (nZ != 1 && nZ != nw) {
@@ -581,25 +616,42 @@ vtm_status refresh_plan(Plan& P, const double* val, int64_t nnz, const double* Z
             wW[e] = 1.0 / z;
         }
     }
-    // commit, then the port quantities in the order build_plan forms them
-    P.val.swap(nv);
+    // commit, then the port quantities as build_plan forms them (the diagonal
+    // changes summed in port order, one pass)
+    for_chunks(m, plan_threads(m), [&](int, int64_t k0, int64_t k1) {
+        std::copy(nv.get() + k0, nv.get() + k1, P.val.begin() + k0);
+    });
     P.wg.swap(wg);
     P.wW.swap(wW);
     const int64_t np = P.nports;
+    const int TP = plan_threads(np);
     std::vector<int32_t> port2abi(np);
-    for (int64_t q = 0; q < np; ++q) port2abi[P.abi2port[q]] = int32_t(q);
-    P.dmod.assign(P.n, 0.0);
-    for (int64_t p = 0; p < np; ++p) {
-        const int64_t q = port2abi[p], e = q / 2;
-        const PortCoef k = port_coef(P.wg[e], P.wW[e]);
-        P.pc[p] = k.c;
-        P.pbeta[p] = k.beta;
-        P.pgamma[p] = k.gamma;
-        P.pg[p] = P.wg[e];
-        P.pgd[p] = k.G - P.wg[e];
-        const int32_t node = (q & 1) ? P.wj[e] : P.wi[e];
-        P.dmod[P.iperm[node]] += k.G - P.wg[e];
-    }
+    for_chunks(np, TP, [&](int, int64_t q0, int64_t q1) {
+        for (int64_t q = q0; q < q1; ++q) port2abi[P.abi2port[q]] = int32_t(q);
+    });
+    for_chunks(np, TP, [&](int, int64_t p0, int64_t p1) {
+        for (int64_t p = p0; p < p1; ++p) {
+            const int64_t e = port2abi[p] / 2;
+            const PortCoef k = port_coef(P.wg[e], P.wW[e]);
+            P.pc[p] = k.c;
+            P.pbeta[p] = k.beta;
+            P.pgamma[p] = k.gamma;
+            P.pg[p] = P.wg[e];
+            P.pgd[p] = k.G - P.wg[e];
+        }
+    });
+    // a node's ports are those of its sub-circuit, consecutive in port order: the
+    // sub-circuits split over threads sum each node's changes in that order
+    for_chunks(P.n, plan_threads(P.n), [&](int, int64_t r0, int64_t r1) {
+        std::fill(P.dmod.begin() + r0, P.dmod.begin() + r1, 0.0);
+    });
+    for_chunks(P.S, TP, [&](int, int64_t s0, int64_t s1) {
+        for (int64_t p = P.port_off[s0]; p < P.port_off[s1]; ++p) {
+            const int64_t q = port2abi[p];
+            const int32_t node = (q & 1) ? P.wj[q / 2] : P.wi[q / 2];
+            P.dmod[P.iperm[node]] += P.pgd[p];
+        }
+    });
     P.uniform_W = true;
     for (int64_t e = 1; e < nw; ++e)
         if (P.wW[e] != P.wW[0]) P.uniform_W = false;

@@ -357,6 +357,43 @@ void threaded_plan_checks() {
     check(vtm::refresh_plan(R, A.val.data(), int64_t(A.val.size()), &Z, 1, err) == VTM_OK &&
               R.val == P.val && R.dmod == P.dmod && R.pbeta == P.pbeta,
           "threaded plan: refresh with the same values");
+    // the refresh (its passes split over threads) against a fresh plan of new values
+    const Csr A2 = grid(ny, nx, 10, true);
+    const vtm_csr a2 = A2.view();
+    const double Z2 = 0.7;
+    vtm::Plan Q;
+    check(vtm::build_plan(&a2, part.data(), &Z2, 1, Q, err) == VTM_OK, "threaded plan of new values");
+    check(vtm::refresh_plan(R, A2.val.data(), int64_t(A2.val.size()), &Z2, 1, err) == VTM_OK, "threaded refresh");
+    check(R.val == Q.val && R.dmod == Q.dmod && R.pc == Q.pc && R.pbeta == Q.pbeta && R.pgamma == Q.pgamma &&
+              R.pg == Q.pg && R.pgd == Q.pgd && R.wg == Q.wg && R.wW == Q.wW,
+          "threaded refresh equals a fresh plan");
+    // with two faults the one a single pass over the recorded order meets first is
+    // reported, wherever the threads' chunks fall: a merged off-diagonal entry made
+    // zero (all its sources) and a non-finite value
+    const int64_t nq = int64_t(P.src_ent.size());
+    auto group_at = [&](int64_t q) {  // first off-diagonal merged entry starting at or after q
+        while (q < nq && !((P.src_flag[q] & 1) && !(P.src_flag[q] & 2) && P.src_dst[q] >= 0)) ++q;
+        int64_t e = q + 1;
+        while (e < nq && !(P.src_flag[e] & 1)) ++e;
+        return std::make_pair(q, e);
+    };
+    auto two_faults = [&](int64_t zero_from, int64_t nan_at) {
+        std::vector<double> v = A2.val;
+        const auto g = group_at(zero_from);
+        for (int64_t q = g.first; q < g.second; ++q) v[P.src_ent[q]] = 0.0;
+        const int64_t qn = nan_at < 0 ? g.second : nan_at;
+        v[P.src_ent[qn]] = NAN;
+        vtm::Plan T = R;
+        const vtm_status st = vtm::refresh_plan(T, v.data(), int64_t(v.size()), nullptr, 0, err);
+        check(T.val == R.val && T.dmod == R.dmod, "threaded refresh: a refused refresh changes nothing");
+        return st == VTM_E_ARG ? err : std::string("status ") + std::to_string(int(st));
+    };
+    const std::string pattern = "the new values change which off-diagonal entries are zero (the sparsity pattern)";
+    check(two_faults(nq / 10, 9 * nq / 10) == pattern, "threaded refresh: an earlier pattern change first");
+    check(two_faults(9 * nq / 10, nq / 10) == "non-finite matrix entry",
+          "threaded refresh: an earlier non-finite value first");
+    check(two_faults(nq / 2, -1) == "non-finite matrix entry",
+          "threaded refresh: a non-finite value where the zeroed entry's successor starts comes first");
 }
 
 }  // namespace

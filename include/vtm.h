@@ -179,9 +179,9 @@ void vtm_default_options(vtm_options *opt);
  * Every pair (i, j) in different sub-circuits with a nonzero entry must have
  * A_ij == A_ji < 0 (a two-terminal conductance g = -A_ij), else
  * VTM_E_UNTEARABLE.  Sub-circuits may not exceed 16384 nodes
- * (VTM_E_UNSUPPORTED); above 10240 nodes (FP64) a handle takes one
- * right-hand side (nrhs_max = 1, else VTM_E_UNSUPPORTED) and has no adjoint
- * (vtm_solve_adjoint gives VTM_E_UNSUPPORTED).  n and nnz must fit int32.  A sub-circuit matrix
+ * (VTM_E_UNSUPPORTED), nor a device's LDS per workgroup in right-hand-side
+ * values (8 bytes each in FP64, 4 otherwise; 160 KiB on gfx950 holds the
+ * largest).  n and nnz must fit int32.  A sub-circuit matrix
  * (with its port conductances) whose elimination meets an exactly zero or
  * non-finite pivot gives VTM_E_SINGULAR.  Returns after the setup kernels
  * finish.

@@ -177,7 +177,6 @@ struct vtm_handle_s {
     DevBuf<double> S64, W64p;
     DevBuf<float> S32, W32p;
     size_t lds_limit = 65536;
-    bool one_rhs_only = false;            // sub-circuits too large for a multi-RHS or adjoint sweep
     int mfma_variant = 0;                 // chosen by the autotuner
     int mfma_rc = 0;
     // work vectors, [rows][nrhs]
@@ -944,8 +943,6 @@ vtm_status solve_common(vtm_handle h, const double* b, double* x, int32_t nrhs, 
     if (!(tol > 0.0)) return fail(VTM_E_ARG, "tol must be positive");
     VTM_HIP(hipSetDevice(h->device));
     const vtm::Plan& P = h->plan;
-    if (adjoint && h->one_rhs_only)
-        return fail(VTM_E_UNSUPPORTED, "the adjoint sweep of sub-circuits this large does not fit LDS");
     if (P.vertex) {
         // interfacial sources split between the twins; b also kept in node order for the residual
         VTM_HIP(vtm::launch_expand(int(P.n), nrhs, int(P.n_orig), h->vx_src.p, h->vx_w.p, b, true, h->bp.p,
@@ -1314,11 +1311,9 @@ static vtm_status setup_from_plan(std::unique_ptr<vtm_handle_s> h, vtm_handle* o
     int lds = 0;
     VTM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
     h->lds_limit = size_t(lds > 0 ? lds : 65536);
-    // the full sweep of several right-hand sides (and the adjoint's) stages rhs and x of a
-    // sub-circuit in LDS; one right-hand side needs only rhs there
-    h->one_rhs_only = size_t(2) * P.max_ns * (o.precision == VTM_FP64 ? 8 : 4) > h->lds_limit;
-    if (h->one_rhs_only && nr > 1)
-        return fail(VTM_E_UNSUPPORTED, "sub-circuits this large take one right-hand side (nrhs_max = 1)");
+    // a full sweep stages a sub-circuit's right-hand side in LDS (and its x where both fit)
+    if (size_t(P.max_ns) * (o.precision == VTM_FP64 ? 8 : 4) > h->lds_limit)
+        return fail(VTM_E_UNSUPPORTED, "a sub-circuit is too large for the sweep's LDS staging of its right-hand side");
     // batched form: MFMA tiles for BF16, and for FP64 handles sized for 16+ right-hand sides
     // when a 16-column block of the largest sub-circuit fits the LDS staging of the batched
     // sweep (else FP64 keeps the column-group layout; BF16 has no other form)

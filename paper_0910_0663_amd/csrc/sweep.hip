@@ -41,11 +41,11 @@ __global__ void __launch_bounds__(kBlock)
             const int32_t* __restrict__ port_slot, const int32_t* __restrict__ port_twin,
             const TV* __restrict__ pc, const TV* __restrict__ pbeta, const TV* __restrict__ pgamma,
             const TV* __restrict__ b, const TV* __restrict__ a_cur, TV* __restrict__ a_next, TV* __restrict__ x,
-            int nrhs, int max_ns, int max_slot, int adjoint) {
+            int nrhs, int max_ns, int max_slot, int adjoint, int xs_lds) {
     constexpr int G = Group<TO>::G;
     extern __shared__ char smem[];
     TV* rhs = reinterpret_cast<TV*>(smem);   // [max_ns][R]
-    TV* xs = rhs + max_ns * R;               // [max_ns][R]
+    TV* xs = rhs + max_ns * R;               // [max_ns][R] when xs_lds (else the waves read x back)
     const int s = blockIdx.x;
     const int r0 = blockIdx.y * R;
     const int w = min(R, nrhs - r0);
@@ -53,6 +53,10 @@ __global__ void __launch_bounds__(kBlock)
     const int ns = sub_off[s + 1] - off;
     const int p0 = port_off[s], p1 = port_off[s + 1];
     const int tid = threadIdx.x, bs = blockDim.x;
+    // rows of this block: [z * bs, z * bs + bs) + k * bs * gridDim.z (gridDim.z > 1 spreads the
+    // rows of a few large sub-circuits over several workgroups)
+    const int row0 = int(blockIdx.z) * bs, rstep = bs * int(gridDim.z);
+    if (row0 >= ns) return;  // uniform over the workgroup
 
     for (int t = tid; t < ns * R; t += bs) {
         const int row = t / R, k = t - row * R;
@@ -74,7 +78,7 @@ __global__ void __launch_bounds__(kBlock)
 
     const TO* Ks = K + kofs[s];
     const int full = (ns / G) * G;
-    for (int row = tid; row < ns; row += bs) {
+    for (int row = row0 + tid; row < ns; row += rstep) {
         TV acc[R][G];
 #pragma unroll
         for (int k = 0; k < R; ++k)
@@ -118,17 +122,19 @@ __global__ void __launch_bounds__(kBlock)
             TV v = acc[k][0];
 #pragma unroll
             for (int j = 1; j < G; ++j) v += acc[k][j];
-            xs[row * R + k] = v;
+            if (xs_lds) xs[row * R + k] = v;
             if (k < w) x[int64_t(off + row) * nrhs + r0 + k] = v;
         }
     }
     __syncthreads();
     for (int p = p0 + tid; p < p1; p += bs) {
         const int node = port_node[p];
+        if ((node / bs) % int(gridDim.z) != int(blockIdx.z)) continue;  // x of this node was formed elsewhere
         const int64_t tw = int64_t(port_twin[p]) * nrhs + r0;
         const int64_t pa = int64_t(p) * nrhs + r0;
+        const int64_t px = int64_t(off + node) * nrhs + r0;
         const TV be = pbeta[p], ga = pgamma[p];
-        for (int k = 0; k < w; ++k) a_next[tw + k] = be * xs[node * R + k] + ga * a_cur[pa + k];
+        for (int k = 0; k < w; ++k) a_next[tw + k] = be * (xs_lds ? xs[node * R + k] : x[px + k]) + ga * a_cur[pa + k];
     }
 }
 
@@ -232,16 +238,18 @@ __global__ void __launch_bounds__(kBlock)
 template <typename TO, typename TV, int R>
 hipError_t launch_r(int S, int max_ns, int nrhs, const TO* K, const int64_t* kofs, const int32_t* sub_off,
                     PortArrays ports, const TV* pc, const TV* pbeta, const TV* pgamma, const TV* b,
-                    const TV* a_cur, TV* a_next, TV* x, bool adjoint, hipStream_t st) {
+                    const TV* a_cur, TV* a_next, TV* x, bool adjoint, bool xs_lds, hipStream_t st) {
     const int bs = max_ns <= 64 ? 64 : kBlock;
-    const size_t lds = size_t(2) * max_ns * R * sizeof(TV);
+    const size_t lds = size_t(xs_lds ? 2 : 1) * max_ns * R * sizeof(TV);
     const unsigned ny = unsigned((nrhs + R - 1) / R);
+    // few workgroups in all: the rows of each sub-circuit over several
+    const unsigned nz = int64_t(S) * ny < 1024 && max_ns > bs ? unsigned((max_ns + bs - 1) / bs) : 1u;
     if (lds > 65536)
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep<TO, TV, R>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    hipLaunchKernelGGL((k_sweep<TO, TV, R>), dim3(S, ny), dim3(bs), lds, st, K, kofs, sub_off, ports.off,
+    hipLaunchKernelGGL((k_sweep<TO, TV, R>), dim3(S, ny, nz), dim3(bs), lds, st, K, kofs, sub_off, ports.off,
                        ports.node, ports.slot, ports.twin, pc, pbeta, pgamma, b, a_cur, a_next, x, nrhs, max_ns,
-                       ports.max_slot, adjoint ? 1 : 0);
+                       ports.max_slot, adjoint ? 1 : 0, xs_lds ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -254,9 +262,9 @@ hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t*
     // right-hand sides per block: rhs and x of the sub-circuit in 64 KiB of LDS; one
     // right-hand side of a larger sub-circuit may use up to lds_limit
     auto fits = [&](int r) { return size_t(2) * max_ns * r * sizeof(TV) <= 65536; };
-    const bool one = fits(1) || size_t(2) * max_ns * sizeof(TV) <= lds_limit;
-    // the single right-hand-side sweep also runs with only rhs in LDS (x read back for the waves)
+    // one right-hand side a block also runs with only rhs in LDS (x read back for the waves)
     const bool xs_lds = size_t(2) * max_ns * sizeof(TV) <= lds_limit;
+    const bool one = xs_lds || size_t(max_ns) * sizeof(TV) <= lds_limit;
     if (kSweepChunk > 0 && nrhs == 1 && !adjoint && size_t(max_ns) * sizeof(TV) <= lds_limit) {
         // few sub-circuits: one-wavefront blocks, each sub-circuit's rows spread over several
         const bool split = S < 1024 && max_ns > 64;
@@ -274,16 +282,16 @@ hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t*
     }
     if (nrhs == 1 || !fits(2))
         return one ? launch_r<TO, TV, 1>(S, max_ns, nrhs, K, kofs, sub_off, ports, pc, pbeta, pgamma, b, a_cur,
-                                             a_next, x, adjoint, st)
+                                             a_next, x, adjoint, xs_lds, st)
                        : hipErrorInvalidValue;
     if (nrhs == 2 || !fits(4))
         return launch_r<TO, TV, 2>(S, max_ns, nrhs, K, kofs, sub_off, ports, pc, pbeta, pgamma, b, a_cur, a_next,
-                                   x, adjoint, st);
+                                   x, adjoint, true, st);
     if (nrhs <= 4 || !fits(8))
         return launch_r<TO, TV, 4>(S, max_ns, nrhs, K, kofs, sub_off, ports, pc, pbeta, pgamma, b, a_cur, a_next,
-                                   x, adjoint, st);
+                                   x, adjoint, true, st);
     return launch_r<TO, TV, 8>(S, max_ns, nrhs, K, kofs, sub_off, ports, pc, pbeta, pgamma, b, a_cur, a_next, x,
-                               adjoint, st);
+                               adjoint, true, st);
 }
 
 template hipError_t launch_sweep<double, double>(int, int, int, const double*, const int64_t*, const int32_t*,

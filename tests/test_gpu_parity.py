@@ -209,19 +209,42 @@ def test_sub_circuits_at_the_size_limit(torch):
     is exactly 2^31 bytes, the largest range the setup's buffer loads and stores
     address (an offset of 2^31 marks a masked lane), inverted with 64-column
     panels whose pivot steps are launches of their own.  The solve (port-to-port,
-    128 ports each) reaches the sparse LU's solution; a second right-hand side is
-    refused (a full sweep of this size stages one in LDS)."""
-    w = workloads.make(1, dims=(128, 256), block=(128, 128))
+    128 ports each) reaches the sparse LU's solution, and so do two right-hand
+    sides at once (full sweeps, one column a workgroup, x read back from HBM for
+    the waves: the right-hand side alone fills 128 KiB of LDS)."""
+    w = workloads.make(1, dims=(128, 256), block=(128, 128), nrhs=2)
     assert w.n_sub == 2 and np.bincount(w.part).max() == 16384
+    xs = oracle.direct_solve(w.A, w.b)
     s = vtm().Solver(w.A, w.part, w.Z)
+    x, rep = s.solve(to_dev(torch, w.b[:1]), 1e-10)
+    s.close()
+    assert oracle.relative_residual(w.A, w.b[:1], x.cpu().numpy()).max() <= 1e-10
+    assert np.abs(x.cpu().numpy()[0] - xs[0]).max() <= 1e-6 * np.abs(xs[0]).max()
+    s = vtm().Solver(w.A, w.part, w.Z, nrhs_max=2)
     x, rep = s.solve(to_dev(torch, w.b), 1e-10)
     s.close()
-    xs = spla.spsolve(w.A.tocsc(), w.b[0])
     assert oracle.relative_residual(w.A, w.b, x.cpu().numpy()).max() <= 1e-10
-    assert np.abs(x.cpu().numpy()[0] - xs).max() <= 1e-6 * np.abs(xs).max()
-    with pytest.raises(vtm().VTMError) as ei:
-        vtm().Solver(w.A, w.part, w.Z, nrhs_max=2)
-    assert ei.value.name == "VTM_E_UNSUPPORTED"
+    assert np.abs(x.cpu().numpy() - xs).max() <= 1e-6 * np.abs(xs).max()
+
+
+def test_large_unsymmetric_sub_circuits_several_rhs_and_adjoint(torch):
+    """An unsymmetric circuit (controlled sources) in two 13,824-node blocks,
+    above the 10,240 nodes whose x fits LDS beside the right-hand side: two
+    right-hand sides and the adjoint (the stored inverses read transposed) reach
+    the sparse LU's solutions of A x = b and A^T lambda = g."""
+    w = workloads.make(3, dims=(24, 24, 48), block=(24, 24, 24), nrhs=2)
+    assert w.n_sub == 2 and np.bincount(w.part).min() > 10240
+    s = vtm().Solver(w.A, w.part, w.Z, nrhs_max=2)
+    x, rep = s.solve(to_dev(torch, w.b), 1e-10)
+    xs = oracle.direct_solve(w.A, w.b)
+    assert oracle.relative_residual(w.A, w.b, x.cpu().numpy()).max() <= 1e-10
+    assert np.abs(x.cpu().numpy() - xs).max() <= 1e-6 * np.abs(xs).max()
+    g = np.random.default_rng(11).standard_normal((1, w.n))
+    lam, rep = s.solve_adjoint(to_dev(torch, g), 1e-10)
+    s.close()
+    lam_ref = oracle.direct_adjoint(w.A, g)
+    assert oracle.relative_residual(w.A.T.tocsr(), g, lam.cpu().numpy()).max() <= 1e-10
+    assert np.abs(lam.cpu().numpy() - lam_ref).max() <= 1e-6 * np.abs(lam_ref).max()
 
 
 @pytest.mark.parametrize("cfg,kw,rule,alpha", [

@@ -392,8 +392,9 @@ def test_table2_grid3d_two_sub_circuits_on_the_gpu(torch):
     """Table II's Grid3d setting: a 30^3 unit resistor grid torn in two at one
     30 x 30 separator plane (900 interfacial nodes; 12,600 + 900 and 13,500 +
     900 torn nodes, one right-hand side).  With W = 0.3 C the GPU needs the
-    oracle's sweeps and reaches the direct solution; handles this large take no
-    adjoint."""
+    oracle's sweeps and reaches the direct solution.  Sub-circuits this large
+    (their x does not fit LDS beside the right-hand side) also take the adjoint
+    and two right-hand sides, which reach the direct solutions too."""
     dims = (30, 30, 30)
     e = workloads.grid3d_edges(*dims)
     n = int(np.prod(dims))
@@ -408,13 +409,15 @@ def test_table2_grid3d_two_sub_circuits_on_the_gpu(torch):
     assert r.status == "ok" and abs(rep.sweeps - r.sweeps) <= 1
     xs = spla.spsolve(A.tocsc(), b[0])
     assert np.abs(x.cpu().numpy()[0] - xs).max() <= 1e-6 * np.abs(xs).max()
-    with pytest.raises(vtm().VTMError) as ei:
-        s.solve_adjoint(to_dev(torch, b), 1e-8)
-    assert ei.value.name == "VTM_E_UNSUPPORTED"
+    lam, _ = s.solve_adjoint(to_dev(torch, b), 1e-8)  # A is symmetric: A^-T b = A^-1 b
+    assert np.abs(lam.cpu().numpy()[0] - xs).max() <= 1e-6 * np.abs(xs).max()
     s.close()
-    with pytest.raises(vtm().VTMError) as ei:
-        solver(A, label, iface, sides, W, nrhs_max=2)
-    assert ei.value.name == "VTM_E_UNSUPPORTED"
+    b2 = np.concatenate([b, np.random.default_rng(1).standard_normal((1, n))])
+    s = solver(A, label, iface, sides, W, nrhs_max=2)
+    x2, _ = s.solve(to_dev(torch, b2), 1e-8)
+    s.close()
+    xs2 = oracle.direct_solve(A, b2)
+    assert np.abs(x2.cpu().numpy() - xs2).max() <= 1e-6 * np.abs(xs2).max()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])

@@ -857,10 +857,13 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
             if (!(v[i] <= t[i])) return false;
         return true;
     };
+    // the inner checks: ||r - A d|| from port quantities (then r itself is not read
+    // again), else on A with the FP64 r kept by the outer residual
+    const bool iface = pp && !P.vertex;
     for (int outer = 0;; ++outer) {
-        // r = b - A x (FP64), kept for the inner solve, and its BF16 or FP32 copy (the
-        // inner right-hand side) written by the same pass
-        vtm_status st = residual<double>(h, h->bp.p, h->xp.p, nrhs, h->rp.p, rel, adjoint,
+        // r = b - A x (FP64) and its BF16 or FP32 copy (the inner right-hand side),
+        // written by the same pass
+        vtm_status st = residual<double>(h, h->bp.p, h->xp.p, nrhs, iface ? nullptr : h->rp.p, rel, adjoint,
                                          h->tiles ? nullptr : h->b32.p, h->tiles ? h->b16.p : nullptr);
         if (st != VTM_OK) return st;
         ++out.checks;
@@ -899,7 +902,7 @@ vtm_status run_refine(vtm_handle h, int nrhs, double tol, bool adjoint, IterOut&
             const int64_t chunk =
                 std::min<int64_t>(graph_length(h, cad.next(goal)), h->opt.max_sweeps - inner);
             // sweeps, then ||r - A d|| / ||r|| in FP64 (from port quantities with pp)
-            st = run_chunk(h, true, nrhs, adjoint, chunk, cur, e, pp, inner == 0, pp && !P.vertex, &rr);
+            st = run_chunk(h, true, nrhs, adjoint, chunk, cur, e, pp, inner == 0, iface, &rr);
             if (st != VTM_OK) return st;
             cur ^= int(chunk & 1);
             inner += chunk;

@@ -33,36 +33,6 @@ __device__ inline double row_residual(double bv, int k0, const int32_t* __restri
     return acc;
 }
 
-// Two rows of NZ entries each (rows i and j of one wavefront), every load of both
-// issued before the first use, so that their chains of dependent loads overlap.
-template <int NZ, typename TX>
-__device__ inline void row_residual2(double b0, double b1, int k0, int k1, const int32_t* __restrict__ col,
-                                     const double* __restrict__ val, const TX* __restrict__ x, int nrhs, int rhs,
-                                     double& r0, double& r1) {
-    int c0[NZ], c1[NZ];
-    double v0[NZ], v1[NZ];
-    TX x0[NZ], x1[NZ];
-#pragma unroll
-    for (int j = 0; j < NZ; ++j) {
-        c0[j] = col[k0 + j];
-        v0[j] = val[k0 + j];
-        c1[j] = col[k1 + j];
-        v1[j] = val[k1 + j];
-    }
-#pragma unroll
-    for (int j = 0; j < NZ; ++j) {
-        x0[j] = x[int64_t(c0[j]) * nrhs + rhs];
-        x1[j] = x[int64_t(c1[j]) * nrhs + rhs];
-    }
-    r0 = b0;
-    r1 = b1;
-#pragma unroll
-    for (int j = 0; j < NZ; ++j) {
-        r0 -= v0[j] * double(x0[j]);
-        r1 -= v1[j] * double(x1[j]);
-    }
-}
-
 // thread (row slot, rhs): the block's threads cover per = 256 / nrhs rows at a time.
 // UNI (nrhs a multiple of 64): each wavefront holds whole rows of one row slot, so
 // the row index is wave-uniform and the row's index and value loads are scalar
@@ -86,56 +56,31 @@ __global__ void __launch_bounds__(kBlock)
         const int rhs = tid % nrhs, rl = tid / nrhs;
         int i0 = lb * per + rl;
         if (UNI) i0 = __builtin_amdgcn_readfirstlane(i0);
-        const int64_t stride = int64_t(gridDim.x) * per;
-        auto row = [&](int64_t i, double bv, int k0, int nz) -> double {
+        for (int64_t i = i0; i < n; i += int64_t(gridDim.x) * per) {
+            const double bv = b[i * nrhs + rhs];
+            const int k0 = rowptr[i], nz = rowptr[i + 1] - k0;
+            double acc;
             // UNI: nz is wave-uniform, so this branch is a scalar one
-            if (UNI && nz == 5) return row_residual<5>(bv, k0, col, val, x, nrhs, rhs);
-            if (UNI && nz == 7) return row_residual<7>(bv, k0, col, val, x, nrhs, rhs);
-            if (UNI && nz == 4) return row_residual<4>(bv, k0, col, val, x, nrhs, rhs);
-            if (UNI && nz == 3) return row_residual<3>(bv, k0, col, val, x, nrhs, rhs);
-            if (UNI && nz == 6) return row_residual<6>(bv, k0, col, val, x, nrhs, rhs);
-            double acc = bv;
-            for (int k = k0; k < k0 + nz; ++k) acc -= val[k] * double(x[int64_t(col[k]) * nrhs + rhs]);
-            return acc;
-        };
-        auto emit = [&](int64_t i, double bv, double acc) {
+            if (UNI && nz == 5)
+                acc = row_residual<5>(bv, k0, col, val, x, nrhs, rhs);
+            else if (UNI && nz == 7)
+                acc = row_residual<7>(bv, k0, col, val, x, nrhs, rhs);
+            else if (UNI && nz == 4)
+                acc = row_residual<4>(bv, k0, col, val, x, nrhs, rhs);
+            else if (UNI && nz == 3)
+                acc = row_residual<3>(bv, k0, col, val, x, nrhs, rhs);
+            else if (UNI && nz == 6)
+                acc = row_residual<6>(bv, k0, col, val, x, nrhs, rhs);
+            else {
+                acc = bv;
+                for (int k = k0; k < k0 + nz; ++k) acc -= val[k] * double(x[int64_t(col[k]) * nrhs + rhs]);
+            }
             if (r_out) r_out[i * nrhs + rhs] = acc;
             // the low-precision copies round as a separate cast pass would: via FP32
             if (r32) r32[i * nrhs + rhs] = static_cast<float>(acc);
             if (r16) r16[i * nrhs + rhs] = static_cast<__bf16>(static_cast<float>(acc));
             rr += acc * acc;
             bb += bv * bv;
-        };
-        if (UNI) {
-            // rows i and i + stride together (the same rows, in the same order, as one at
-            // a time): both rows' loads in flight at once when their lengths agree
-            for (int64_t i = i0; i < n; i += 2 * stride) {
-                const int64_t j = i + stride;
-                const bool two = j < n;  // wave-uniform
-                const double b0 = b[i * nrhs + rhs];
-                const double b1 = two ? b[j * nrhs + rhs] : 0.0;
-                const int k0 = rowptr[i], nz0 = rowptr[i + 1] - k0;
-                const int k1 = two ? rowptr[j] : 0, nz1 = two ? rowptr[j + 1] - k1 : -1;
-                double a0, a1;
-                if (nz0 == nz1 && nz0 == 5) {
-                    row_residual2<5>(b0, b1, k0, k1, col, val, x, nrhs, rhs, a0, a1);
-                } else if (nz0 == nz1 && nz0 == 7) {
-                    row_residual2<7>(b0, b1, k0, k1, col, val, x, nrhs, rhs, a0, a1);
-                } else if (nz0 == nz1 && nz0 == 4) {
-                    row_residual2<4>(b0, b1, k0, k1, col, val, x, nrhs, rhs, a0, a1);
-                } else {
-                    a0 = row(i, b0, k0, nz0);
-                    a1 = two ? row(j, b1, k1, nz1) : 0.0;
-                }
-                emit(i, b0, a0);
-                if (two) emit(j, b1, a1);
-            }
-        } else {
-            for (int64_t i = i0; i < n; i += stride) {
-                const double bv = b[i * nrhs + rhs];
-                const int k0 = rowptr[i], nz = rowptr[i + 1] - k0;
-                emit(i, bv, row(i, bv, k0, nz));
-            }
         }
     }
     s_rr[tid] = rr;
@@ -193,8 +138,8 @@ __global__ void __launch_bounds__(kBlock)
         const int rhs = tid % nrhs, rl = tid / nrhs;
         int n0 = blockIdx.x * per + rl;
         if (UNI) n0 = __builtin_amdgcn_readfirstlane(n0);  // as in k_resid
-        const int64_t stride = int64_t(gridDim.x) * per;
-        auto node = [&](int p0, int p1) -> double {
+        for (int64_t n = n0; n < nn; n += int64_t(gridDim.x) * per) {
+            const int p0 = pn_pfirst[n], p1 = pn_pfirst[n + 1];
             const double xn =
                 (double(a_next[int64_t(twin[p0]) * nrhs + rhs]) - gamma[p0] * double(a_cur[int64_t(p0) * nrhs + rhs])) /
                 beta[p0];
@@ -206,43 +151,7 @@ __global__ void __launch_bounds__(kBlock)
                     beta[q];
                 r += gd[p] * xn + g[p] * xj - c[p] * double(a_cur[int64_t(p) * nrhs + rhs]);
             }
-            return r;
-        };
-        // a port node with one port: the same arithmetic with no loop, so that two such
-        // nodes' loads (each a chain: the port, its twin, the waves) are in flight together
-        auto node1 = [&](int p0) -> double {
-            const int q = twin[p0];
-            const double an = double(a_next[int64_t(q) * nrhs + rhs]), ac = double(a_cur[int64_t(p0) * nrhs + rhs]);
-            const double anp = double(a_next[int64_t(p0) * nrhs + rhs]), acq = double(a_cur[int64_t(q) * nrhs + rhs]);
-            const double xn = (an - gamma[p0] * ac) / beta[p0];
-            const double xj = (anp - gamma[q] * acq) / beta[q];
-            double r = 0.0;
-            r += gd[p0] * xn + g[p0] * xj - c[p0] * ac;
-            return r;
-        };
-        if (UNI) {
-            // nodes n and n + stride together (the same nodes, in the same order)
-            for (int64_t n = n0; n < nn; n += 2 * stride) {
-                const int64_t m = n + stride;
-                const bool two = m < nn;  // wave-uniform
-                const int a0 = pn_pfirst[n], a1 = pn_pfirst[n + 1];
-                const int b0 = two ? pn_pfirst[m] : 0, b1 = two ? pn_pfirst[m + 1] : 0;
-                double ra, rb = 0.0;
-                if (two && a1 - a0 == 1 && b1 - b0 == 1) {
-                    ra = node1(a0);
-                    rb = node1(b0);
-                } else {
-                    ra = node(a0, a1);
-                    if (two) rb = node(b0, b1);
-                }
-                rr += ra * ra;
-                if (two) rr += rb * rb;
-            }
-        } else {
-            for (int64_t n = n0; n < nn; n += stride) {
-                const double r = node(pn_pfirst[n], pn_pfirst[n + 1]);
-                rr += r * r;
-            }
+            rr += r * r;
         }
     }
     s_rr[tid] = rr;

@@ -188,6 +188,33 @@ def test_partial_schur_reduces_to_its_special_cases():
     assert r.status == "ok" and r.sweeps <= 3
 
 
+@pytest.mark.parametrize("side", [0, 1])
+def test_partial_schur_at_depth_d_is_a_block_continued_fraction(side):
+    """Rule 5 at the depths between none and all, by an independent route: on a
+    unit grid torn at one column of nodes, the inner nodes within d hops of one
+    side's twins are the d columns beside the separator, so C - E D~^-1 F is a
+    block continued fraction over those columns, eliminated from the farthest
+    inwards: Z = B_far, Z <- B - Z^-1 column by column (unit couplings between
+    neighbouring columns and to the twins), and S~ = C - Z^-1.  Each B is the
+    column's tridiagonal block of the untorn A."""
+    ny, nx, s = 9, 17, 8
+    A = unit_grid((ny, nx))
+    label, iface, sides = workloads.separator_strips((ny, nx), s)
+    assert np.array_equal(iface, np.arange(ny) * nx + s)
+    torn = oracle.tear_at_vertices(A, label, iface, sides, 1.0)
+    P = torn.pa if side == 0 else torn.pb
+    C = torn.T.tocsr()[P][:, P].toarray()
+    Ad = A.toarray()
+    step = -1 if side == 0 else 1
+    for d in (1, 2, 3, 5):
+        cols = [np.arange(ny) * nx + s + step * h for h in range(1, d + 1)]
+        Z = Ad[np.ix_(cols[-1], cols[-1])]
+        for c in reversed(cols[:-1]):
+            Z = Ad[np.ix_(c, c)] - np.linalg.inv(Z)
+        S = C - np.linalg.inv(Z)
+        assert np.allclose(oracle.partial_schur(torn, side, d), 0.5 * (S + S.T), rtol=1e-12, atol=1e-14), d
+
+
 def test_partial_schur_drops_small_entries():
     dims = (10, 21)
     A = unit_grid(dims)

@@ -603,8 +603,9 @@ def vtm_refine(torn: Torn, A, b, tol, inner_drop, max_outer=60, max_inner=100000
     max(inner_drop, tol ||b|| / (2 ||r||)) or when two checks in a row bring no
     column 20% below its best; then x += d; until ||b - A x|| / ||b|| <= tol.
     The oracle runs the inner solves in FP64 (the schedule, not the precision,
-    is what it reproduces).  Parity unpinned beyond the final residual and the
-    direct solution it must agree with."""
+    is what it reproduces).  Pinned by rebuilding its steps from plain VTM on
+    each residual (the same stopping sweeps and iterates), and by the final
+    residual and the direct solution it must agree with."""
     b = np.atleast_2d(np.asarray(b, dtype=np.float64))
     sw = sweeper or Sweeper(torn)
     x = np.zeros_like(b)

@@ -437,6 +437,29 @@ def test_refinement_reaches_tolerance():
     assert np.abs(rr.x - xs).max() <= 1e-6 * np.abs(xs).max()
 
 
+def test_refinement_steps_are_plain_vtm_on_the_residual():
+    """Each outer step of the refinement schedule is plain VTM (Section VI) on the
+    current residual r = b - A x from zero waves: it stops at the first check
+    (every 8 sweeps) where plain VTM on r meets the step's target, max(drop,
+    tol / (2 ||r|| / ||b||)), and adds that VTM iterate to x.  Two steps are
+    rebuilt here from vtm_solve alone (its own pins hold it to the paper)."""
+    w = workloads.make(5, dims=(64, 64))
+    torn = oracle.tear_wires(w.A, w.part, w.Z)
+    tol, drop = 1e-8, 1e-5
+    x = np.zeros_like(w.b)
+    for step in (1, 2):
+        rel = oracle.relative_residual(w.A, w.b, x).max()
+        target = max(drop, 0.5 * tol / rel)
+        r = w.b - (w.A @ x.T).T
+        plain = oracle.vtm_solve(torn, w.A, r, target)
+        assert plain.status == "ok"
+        stop = 8 * -(-plain.sweeps // 8)
+        x = x + oracle.vtm_solve(torn, w.A, r, 0.0, max_sweeps=stop).x
+        rr = oracle.vtm_refine(torn, w.A, w.b, tol, inner_drop=drop, max_outer=step)
+        assert rr.inner_sweeps[step - 1] == stop
+        assert np.allclose(rr.x, x, rtol=0, atol=1e-13 * np.abs(x).max())
+
+
 @pytest.mark.parametrize("cfg,kw", [(1, dict()), (3, dict(dims=(16, 16, 16))), (4, dict(dims=(48, 48)))])
 def test_interface_residual_equals_untorn_residual(cfg, kw):
     """The residual of a VTM iterate lives on the port nodes: computed from the

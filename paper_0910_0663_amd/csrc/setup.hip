@@ -474,12 +474,14 @@ __global__ void __launch_bounds__(kUpdWaves * 64)
     k_gj_update(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
                 int k0, const double* __restrict__ panel, int S, int ncb) {
     constexpr int Q = NB / 4;  // MFMA steps
-    // one-dimensional grid of (row block, sub-circuit, column block), column block
-    // fastest, each XCD taking a contiguous range: the column blocks that read the
-    // same rows of a sub-circuit's panel run one after another on one L2
-    const int u = xcd_block(int(blockIdx.x), int(gridDim.x));
-    const int cb = u % ncb, t = u / ncb;
-    const int s = t % S, rb = t / S;
+    // one-dimensional grid over (row block, sub-circuit) pairs t and column blocks cb:
+    // the column blocks of one pair, which read the same rows of its panel, run one
+    // after another on one XCD (so those rows come from its L2), and consecutive pairs
+    // go to different XCDs, so that a run of large sub-circuits spreads over the chip.
+    // Blocks are dealt round-robin to the 8 XCDs: XCD b % 8 takes pairs t = 8 i + b % 8.
+    const int x = int(blockIdx.x) & 7, j = int(blockIdx.x) >> 3;
+    const int cb = j % ncb, t = (j / ncb) * 8 + x;
+    const int s = t % S, rb = t / S;  // rb past the last row block: r0 >= n below
     const int off = sub_off[s], n = sub_off[s + 1] - off;
     if (n <= kLdsSetupMax || k0 >= n || n > kMaxLarge) return;
     const int kb = min(NB, n - k0);
@@ -621,7 +623,7 @@ hipError_t launch_update(int S, int max_ns, const int32_t* sub_off, const int64_
                          const double* panel, hipStream_t st) {
     constexpr int CT = NB <= 32 ? 4 : 2;   // column tiles per wavefront (the B operand stays in registers)
     const int ncb = (max_ns + 16 * CT - 1) / (16 * CT), nrb = (max_ns + kUpdRows - 1) / kUpdRows;
-    const int64_t blocks = int64_t(S) * ncb * nrb;
+    const int64_t blocks = 8 * int64_t(ncb) * ((int64_t(S) * nrb + 7) / 8);
     if (blocks > INT_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_gj_update<NB, CT>), dim3(unsigned(blocks)), dim3(kUpdWaves * 64), 0, st, sub_off, kofs,
                        scratch64, k0, panel, S, ncb);

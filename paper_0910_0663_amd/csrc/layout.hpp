@@ -63,6 +63,20 @@ __device__ inline int xcd_block_reversed(int b, int n) {
     return x * q + (x < r ? x : r) + (count - 1 - (b >> 3));
 }
 
+// Items of m consecutive logical blocks each (a sub-circuit's column blocks),
+// dealt to the XCDs in turn: item i runs on XCD i % 8, its m blocks one after
+// another there, so that items of uneven cost spread over the chip while an
+// item's blocks share an L2.  The grid holds 8 m ceil(n_items / 8) blocks; a
+// block past the last item of its XCD gets -1.  reversed walks each XCD's items
+// backwards.
+__device__ inline int xcd_item_block(int b, int n_items, int m, bool reversed) {
+    const int x = b & 7, j = b >> 3;
+    const int k = j / m, r = j - k * m;      // block r of the k-th item of XCD x
+    const int count = (n_items - x + 7) >> 3;  // items x, x + 8, ... below n_items
+    if (k >= count) return -1;
+    return ((reversed ? count - 1 - k : k) * 8 + x) * m + r;
+}
+
 // elements reserved for an n x n block (rounded up to a multiple of 4)
 __host__ __device__ inline int64_t inv_block_elems(int n) { return (int64_t(n) * n + 3) & ~int64_t(3); }
 

@@ -174,15 +174,15 @@ __global__ void __launch_bounds__(kBlock)
                  const typename Mma<T>::TV* __restrict__ pbeta, const typename Mma<T>::TV* __restrict__ pgamma,
                  const TB* __restrict__ b, const typename Mma<T>::TV* __restrict__ a_cur,
                  typename Mma<T>::TV* __restrict__ a_next, typename Mma<T>::TV* __restrict__ x, int nrhs, int rc,
-                 int write_x) {
+                 int write_x, int S) {
     using M = Mma<T>;
     using TV = typename M::TV;
     extern __shared__ char smem[];
     T* sb = reinterpret_cast<T*>(smem);
-    // each XCD takes a contiguous range of (sub-circuit, column block): the column
-    // blocks of one sub-circuit read its inverse through one L2
-    const int nb = int(gridDim.x * gridDim.y), bl = int(blockIdx.x + gridDim.x * blockIdx.y);
-    const int u = xcd_block(bl, nb);
+    // sub-circuits dealt to the XCDs in turn, the column blocks of one sub-circuit
+    // (which read its inverse) consecutive on one XCD's L2
+    const int u = xcd_item_block(int(blockIdx.x + gridDim.x * blockIdx.y), S, int(gridDim.x), false);
+    if (u < 0) return;  // uniform over the workgroup
     const int s = u / int(gridDim.x);
     const int r0 = (u - s * int(gridDim.x)) * rc;
     const int w = min(rc, nrhs - r0);
@@ -368,18 +368,26 @@ __global__ void __launch_bounds__(WAVES * 64)
     k_sweep_mfma_pp(const T* __restrict__ Mop, const int64_t* __restrict__ qmofs,
                     const int32_t* __restrict__ port_off, const int32_t* __restrict__ port_twin,
                     const typename Mma<T>::TV* __restrict__ h, const typename Mma<T>::TV* __restrict__ a_cur,
-                    typename Mma<T>::TV* __restrict__ a_next, int nrhs, int rc, int reverse) {
+                    typename Mma<T>::TV* __restrict__ a_next, int nrhs, int rc, int reverse, int S) {
     using M = Mma<T>;
     using TV = typename M::TV;
     extern __shared__ char smem[];
     T* sb = reinterpret_cast<T*>(smem);
-    // logical block u = (sub-circuit, column block): each XCD takes a contiguous range,
-    // so the column blocks of one sub-circuit (which read the same operator) and
-    // neighbouring sub-circuits share an L2; every other sweep walks each range
-    // backwards (what the previous sweep read last is still in the memory-side cache)
-    const int nb = int(gridDim.x * gridDim.y), b = int(blockIdx.x + gridDim.x * blockIdx.y);
-    const bool back = reverse;
-    const int u = back ? xcd_block_reversed(b, nb) : xcd_block(b, nb);
+    // logical block u = (sub-circuit, column block), the column blocks of one
+    // sub-circuit (which read the same operator) consecutive on one XCD's L2; every
+    // other sweep walks each XCD's sub-circuits backwards (what the previous sweep read
+    // last is still in the memory-side cache).  FP64: sub-circuits dealt to the XCDs in
+    // turn, so that their uneven costs spread over the chip (grid S rounded up to a
+    // multiple of 8); BF16: each XCD a contiguous range (grid S), measured faster there.
+    const int b = int(blockIdx.x + gridDim.x * blockIdx.y);
+    int u;
+    if constexpr (sizeof(T) == 2) {
+        const int nb = int(gridDim.x * gridDim.y);
+        u = reverse ? xcd_block_reversed(b, nb) : xcd_block(b, nb);
+    } else {
+        u = xcd_item_block(b, S, int(gridDim.x), reverse != 0);
+        if (u < 0) return;  // uniform over the workgroup
+    }
     const int s = u / int(gridDim.x);
     const int r0 = (u - s * int(gridDim.x)) * rc;
     const int w = min(rc, nrhs - r0);
@@ -535,8 +543,10 @@ hipError_t launch_pp_k(int S, int nrhs, int rc, size_t lds, const T* Mop, const 
         lds_set = lds;
     }
     const unsigned ny = unsigned((nrhs + rc - 1) / rc);
-    hipLaunchKernelGGL(kern, dim3(ny, S), dim3(WAVES * 64), lds, st, Mop, qmofs, port_off, port_twin, h, a_cur,
-                       a_next, nrhs, rc, reverse);
+    // FP64: S rounded up to a multiple of 8, every XCD taking whole sub-circuits in turn
+    const unsigned gy = sizeof(T) == 2 ? unsigned(S) : unsigned((S + 7) / 8 * 8);
+    hipLaunchKernelGGL(kern, dim3(ny, gy), dim3(WAVES * 64), lds, st, Mop, qmofs, port_off, port_twin, h, a_cur,
+                       a_next, nrhs, rc, reverse, S);
     return hipGetLastError();
 }
 
@@ -572,8 +582,8 @@ hipError_t launch_t(int S, int nrhs, int rc, size_t lds, const T* K, const int64
         lds_set = lds;
     }
     const unsigned ny = unsigned((nrhs + rc - 1) / rc);
-    hipLaunchKernelGGL(kern, dim3(ny, S), dim3(kBlock), lds, st, K, mofs, sub_off, ports.off, ports.node,
-                       ports.twin, pc, pbeta, pgamma, b, a_cur, a_next, x, nrhs, rc, write_x ? 1 : 0);
+    hipLaunchKernelGGL(kern, dim3(ny, unsigned((S + 7) / 8 * 8)), dim3(kBlock), lds, st, K, mofs, sub_off, ports.off,
+                       ports.node, ports.twin, pc, pbeta, pgamma, b, a_cur, a_next, x, nrhs, rc, write_x ? 1 : 0, S);
     return hipGetLastError();
 }
 

@@ -362,7 +362,7 @@ vtm_status timing_collect(vtm_handle h, IterOut& out) {
 }
 
 vtm_status launch_one(vtm_handle h, bool low, int nrhs, const void* b, void* x, int cur, bool adjoint, int variant,
-                      int rc, bool write_x) {
+                      int rc, bool write_x, bool port_rows = false) {
     const vtm::Plan& P = h->plan;
     if (h->tiles) {
         // the adjoint's operator is K^-T: the same tiles when A is symmetric, else the transposed copy
@@ -372,12 +372,13 @@ vtm_status launch_one(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
                                                    kt ? h->K64T.p : h->K64.p, h->mofs.p, h->sub_off.p, h->ports(), h->c64.p,
                                                    h->beta64.p, h->gamma64.p, static_cast<const double*>(b),
                                                    h->a64[cur].p, h->a64[cur ^ 1].p, static_cast<double*>(x), write_x,
-                                                   h->stream));
+                                                   h->stream, port_rows));
         else
             VTM_HIP(vtm::launch_sweep_mfma<__bf16>(int(P.S), P.max_ns, P.max_ports, nrhs, variant, rc, h->lds_limit,
                                                    kt ? h->KbfT.p : h->Kbf.p, h->mofs.p, h->sub_off.p, h->ports(), h->c32.p,
                                                    h->beta32.p, h->gamma32.p, h->b16.p, h->a32[cur].p,
-                                                   h->a32[cur ^ 1].p, static_cast<float*>(x), write_x, h->stream));
+                                                   h->a32[cur ^ 1].p, static_cast<float*>(x), write_x, h->stream,
+                                                   port_rows));
         return VTM_OK;
     }
     if (!low) {
@@ -385,12 +386,13 @@ vtm_status launch_one(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
                                                    h->ports(), h->c64.p, h->beta64.p, h->gamma64.p,
                                                    static_cast<const double*>(b), h->a64[cur].p,
                                                    h->a64[cur ^ 1].p, static_cast<double*>(x), adjoint,
-                                                   h->lds_limit, h->stream)));
+                                                   h->lds_limit, h->stream, port_rows)));
     } else {
         VTM_HIP((vtm::launch_sweep<float, float>(int(P.S), P.max_ns, nrhs, h->K32.p, h->kofs.p, h->sub_off.p,
                                                  h->ports(), h->c32.p, h->beta32.p, h->gamma32.p,
                                                  static_cast<const float*>(b), h->a32[cur].p, h->a32[cur ^ 1].p,
-                                                 static_cast<float*>(x), adjoint, h->lds_limit, h->stream)));
+                                                 static_cast<float*>(x), adjoint, h->lds_limit, h->stream,
+                                                 port_rows)));
     }
     return VTM_OK;
 }
@@ -398,8 +400,11 @@ vtm_status launch_one(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
 // One sweep on the FP64 or FP32/BF16 buffers; cur selects the wave buffer read.
 // write_x: the sweep's x must be complete (the last sweep before a check).
 // pp: a port-to-port sweep (waves only; needs h of this right-hand side).
+// port_rows: a full sweep whose x is read on the port nodes only (the first sweep
+// of a port-to-port run, whose x feeds h and is rebuilt later); kernels that can
+// form those rows alone do so.
 vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, int cur, bool adjoint,
-                      bool write_x, bool pp = false) {
+                      bool write_x, bool pp = false, bool port_rows = false) {
     hipEvent_t e0, e1;
     vtm_status st;
     // timing 1: events around every launch; 2: only full sweeps here (runs of
@@ -456,7 +461,8 @@ vtm_status sweep_once(vtm_handle h, bool low, int nrhs, const void* b, void* x, 
                                                         h->port_twin.p, h->h32.p, h->a32[cur].p, h->a32[cur ^ 1].p,
                                                         h->stream)));
     } else {
-        if ((st = launch_one(h, low, nrhs, b, x, cur, adjoint, h->mfma_variant, h->mfma_rc, write_x)) != VTM_OK)
+        if ((st = launch_one(h, low, nrhs, b, x, cur, adjoint, h->mfma_variant, h->mfma_rc, write_x, port_rows)) !=
+            VTM_OK)
             return st;
         const vtm::Plan& P = h->plan;
         if (P.coupled) {  // the waves of coupled lines need W over the port rows of x
@@ -616,7 +622,10 @@ vtm_status run_chunk(vtm_handle h, bool low, int nrhs, bool adjoint, int64_t chu
                 r0_slot = h->ev_used;
                 if ((st = timing_event(h, &r0, 1)) != VTM_OK) return st;
             }
-            st = sweep_once(h, low, nrhs, b, x, (cur + int(k)) & 1, adjoint, k + 1 == chunk, !full);
+            // the first sweep of a port-to-port run needs x on the port nodes only (for h),
+            // unless it also ends a chunk whose check reads x on A
+            const bool port_rows = full && pp && first && k == 0 && (iface || k + 1 < chunk);
+            st = sweep_once(h, low, nrhs, b, x, (cur + int(k)) & 1, adjoint, k + 1 == chunk, !full, port_rows);
             if (st != VTM_OK) return st;
             if (!full) ++run;
             if (pp && first && k == 0 && (st = port_h(h, low, nrhs)) != VTM_OK) return st;

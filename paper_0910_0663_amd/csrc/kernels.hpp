@@ -64,20 +64,24 @@ hipError_t launch_setup_tiles(int S, int max_ns, const int32_t* sub_off, const i
 // right-hand sides): right-hand side b + c * a at the port nodes,
 // x = K^-1 rhs (K^-T when adjoint), then the outgoing wave beta * x + gamma * a
 // sent to the twin port in a_next.  Vectors are [rows][nrhs] (right-hand side
-// fastest).
+// fastest).  port_rows: x may be formed on the port nodes only (numbered first
+// in each sub-circuit), all the waves need; the single right-hand-side forward
+// sweep does so, the others form every row.
 template <typename TO, typename TV>
 hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t* kofs,
                         const int32_t* sub_off, PortArrays ports, const TV* pc, const TV* pbeta,
                         const TV* pgamma, const TV* b, const TV* a_cur, TV* a_next, TV* x,
-                        bool adjoint, size_t lds_limit, hipStream_t st);
+                        bool adjoint, size_t lds_limit, hipStream_t st, bool port_rows = false);
 
 // Batched sweep on MFMA (mfma.hip) with the inverses in tile layout: per
 // sub-circuit X = Kinv [b + c a] for blocks of up to 64 right-hand sides, then
 // the outgoing waves.  variant: 0 gives each wavefront 3 row tiles per pass, 1
 // gives it 5; rc_req: right-hand sides per workgroup (multiple of 16; 0 =
 // widest that fits lds_limit).  write_x = false stores x on port rows only (enough
-// for the waves; pass true on the last sweep before a residual check).  The
-// BF16 form reads b in BF16.  The adjoint passes the tiles of K^-T as K.
+// for the waves; pass true on the last sweep before a residual check); port_rows
+// forms x only in the row tiles that hold port nodes (numbered first in each
+// sub-circuit).  The BF16 form reads b in BF16.  The adjoint passes the tiles of
+// K^-T as K.
 template <typename T>
 hipError_t launch_sweep_mfma(int S, int max_ns, int max_ports, int nrhs, int variant, int rc_req,
                              size_t lds_limit, const T* K, const int64_t* mofs, const int32_t* sub_off,
@@ -85,7 +89,7 @@ hipError_t launch_sweep_mfma(int S, int max_ns, int max_ports, int nrhs, int var
                              const typename MfmaTypes<T>::TV* pbeta, const typename MfmaTypes<T>::TV* pgamma,
                              const typename MfmaTypes<T>::TB* b, const typename MfmaTypes<T>::TV* a_cur,
                              typename MfmaTypes<T>::TV* a_next, typename MfmaTypes<T>::TV* x, bool write_x,
-                             hipStream_t st);
+                             hipStream_t st, bool port_rows = false);
 // Batched port-to-port sweep: a_next[twin(p)][r] = h[p][r] + (M_s a_cur)_p[r] per
 // sub-circuit, M_s (q x q) in A-tile order at Mop + qmofs[s] (padded to
 // roundup(q, 32)); variant bit 0 as above (5 row tiles per pass, else 3), bit 1

@@ -95,13 +95,14 @@ struct Mma<double> {
 // takes up to RT row tiles (mt = wave, wave + W, ...) per pass and walks k: per
 // k tile it loads the NT B fragments once from LDS and its row tiles' A tiles
 // from HBM (the next k tile's A tiles are already in flight), then issues the
-// MFMAs.  epi(row, n, value) receives every element of D (rows < np, n < 16 NT).
+// MFMAs.  epi(row, n, value) receives every element of D (rows < np, n < 16 NT);
+// mt_lim >= 0 forms only the first mt_lim row tiles.
 template <typename T, int NT, int RT, int WAVES, int PD64 = kMfmaPD64, typename Epi>
-__device__ inline void tile_gemm(const T* Ablk, int np, const T* sb, int bsel, int w, Epi epi) {
+__device__ inline void tile_gemm(const T* Ablk, int np, const T* sb, int bsel, int w, Epi epi, int mt_lim = -1) {
     using M = Mma<T>;
     using TV = typename M::TV;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int MT = np / 16, KT = np / M::KT;
+    const int MT = mt_lim >= 0 ? min(np / 16, mt_lim) : np / 16, KT = np / M::KT;
     const typename M::AFrag* A0 = reinterpret_cast<const typename M::AFrag*>(Ablk) + lane;
     for (int g0 = 0; g0 < MT; g0 += WAVES * RT) {
         int mts[RT];
@@ -174,7 +175,7 @@ __global__ void __launch_bounds__(kBlock)
                  const typename Mma<T>::TV* __restrict__ pbeta, const typename Mma<T>::TV* __restrict__ pgamma,
                  const TB* __restrict__ b, const typename Mma<T>::TV* __restrict__ a_cur,
                  typename Mma<T>::TV* __restrict__ a_next, typename Mma<T>::TV* __restrict__ x, int nrhs, int rc,
-                 int write_x, int S) {
+                 int write_x, int S, int port_rows) {
     using M = Mma<T>;
     using TV = typename M::TV;
     extern __shared__ char smem[];
@@ -295,11 +296,14 @@ __global__ void __launch_bounds__(kBlock)
     __syncthreads();
 
     // 2. X = Kinv B, x stored on the rows the wave update reads (all rows with write_x)
-    // (the full inverses are long in k: FP64 keeps more of its tiles in flight)
+    // (the full inverses are long in k: FP64 keeps more of its tiles in flight);
+    // port_rows: only the row tiles of the port nodes, numbered first (the last
+    // port's node is the last of them)
+    const int mt_lim = port_rows ? (nps > 0 ? pnode[nps - 1] + 16 : 0) / 16 : -1;
     tile_gemm<T, NT, RT, kWaves, kMfmaFullPD64>(K + mofs[s], np, sb, sizeof(T) == 2 ? np : rc, w,
                                                      [&](int row, int n, TV v, int) {
         if (row < ns && n < w && (write_x || pcount[row])) x[int64_t(off + row) * nrhs + r0 + n] = v;
-    });
+    }, mt_lim);
     __syncthreads();
 
     // 3. outgoing waves, read back x of the port nodes (written by this workgroup), 4 columns at a time
@@ -570,7 +574,7 @@ hipError_t launch_t(int S, int nrhs, int rc, size_t lds, const T* K, const int64
                     PortArrays ports, const typename Mma<T>::TV* pc, const typename Mma<T>::TV* pbeta,
                     const typename Mma<T>::TV* pgamma, const typename MfmaTypes<T>::TB* b,
                     const typename Mma<T>::TV* a_cur, typename Mma<T>::TV* a_next, typename Mma<T>::TV* x,
-                    bool write_x, hipStream_t st) {
+                    bool write_x, hipStream_t st, bool port_rows) {
     auto kern = k_sweep_mfma<T, typename MfmaTypes<T>::TB, NT, RT>;
     // raise the dynamic LDS limit once per instantiation (the first launch comes from
     // the setup's autotuner, never from inside a graph capture)
@@ -583,7 +587,8 @@ hipError_t launch_t(int S, int nrhs, int rc, size_t lds, const T* K, const int64
     }
     const unsigned ny = unsigned((nrhs + rc - 1) / rc);
     hipLaunchKernelGGL(kern, dim3(ny, unsigned((S + 7) / 8 * 8)), dim3(kBlock), lds, st, K, mofs, sub_off, ports.off,
-                       ports.node, ports.twin, pc, pbeta, pgamma, b, a_cur, a_next, x, nrhs, rc, write_x ? 1 : 0, S);
+                       ports.node, ports.twin, pc, pbeta, pgamma, b, a_cur, a_next, x, nrhs, rc, write_x ? 1 : 0, S,
+                       port_rows ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -596,7 +601,7 @@ hipError_t launch_sweep_mfma(int S, int max_ns, int max_ports, int nrhs, int var
                              const typename MfmaTypes<T>::TV* pc, const typename MfmaTypes<T>::TV* pbeta,
                              const typename MfmaTypes<T>::TV* pgamma, const typename MfmaTypes<T>::TB* b,
                              const typename MfmaTypes<T>::TV* a_cur, typename MfmaTypes<T>::TV* a_next,
-                             typename MfmaTypes<T>::TV* x, bool write_x, hipStream_t st) {
+                             typename MfmaTypes<T>::TV* x, bool write_x, hipStream_t st, bool port_rows) {
     const int np = tile_pad(max_ns);
     // widest right-hand-side block (a multiple of 16, at most 64) whose staging fits the LDS limit
     int rc = rc_req > 0 ? ((rc_req + 15) / 16) * 16 : 64;
@@ -613,11 +618,11 @@ hipError_t launch_sweep_mfma(int S, int max_ns, int max_ports, int nrhs, int var
     if (nt == NTV) {                                                                                            \
         if (variant == 2)                                                                                       \
             return launch_t<T, NTV, 1>(S, nrhs, rc, lds, K, mofs, sub_off, ports, pc, pbeta, pgamma, b, a_cur,  \
-                                       a_next, x, write_x, st);                                                 \
+                                       a_next, x, write_x, st, port_rows);                                      \
         return variant == 1 ? launch_t<T, NTV, 5>(S, nrhs, rc, lds, K, mofs, sub_off, ports, pc, pbeta, pgamma, \
-                                                  b, a_cur, a_next, x, write_x, st)                             \
+                                                  b, a_cur, a_next, x, write_x, st, port_rows)                  \
                             : launch_t<T, NTV, 3>(S, nrhs, rc, lds, K, mofs, sub_off, ports, pc, pbeta, pgamma, \
-                                                  b, a_cur, a_next, x, write_x, st);                            \
+                                                  b, a_cur, a_next, x, write_x, st, port_rows);                 \
     }
     VTM_MFMA_CASE(1)
     VTM_MFMA_CASE(2)
@@ -697,10 +702,11 @@ template hipError_t launch_port_matrix_tiles<double>(int, const int32_t*, const 
                                                     Coupling<double>);
 template hipError_t launch_sweep_mfma<__bf16>(int, int, int, int, int, int, size_t, const __bf16*, const int64_t*,
                                              const int32_t*, PortArrays, const float*, const float*, const float*,
-                                             const __bf16*, const float*, float*, float*, bool, hipStream_t);
+                                             const __bf16*, const float*, float*, float*, bool, hipStream_t,
+                                             bool);
 template hipError_t launch_sweep_mfma<double>(int, int, int, int, int, int, size_t, const double*, const int64_t*,
                                              const int32_t*, PortArrays, const double*, const double*,
                                              const double*, const double*, const double*, double*, double*, bool,
-                                             hipStream_t);
+                                             hipStream_t, bool);
 
 }  // namespace vtm

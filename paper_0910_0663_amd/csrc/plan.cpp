@@ -140,16 +140,6 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
         err = "a sub-circuit has more than " + std::to_string(kMaxSubCircuit) + " nodes";
         return VTM_E_UNSUPPORTED;
     }
-    P.perm.resize(n);
-    P.iperm.resize(n);
-    {
-        std::vector<int32_t> fill(P.sub_off.begin(), P.sub_off.end() - 1);
-        for (int64_t i = 0; i < n; ++i) {
-            const int32_t r = fill[part[i]]++;
-            P.perm[r] = int32_t(i);
-            P.iperm[i] = r;
-        }
-    }
     // inverse blocks start 16-byte aligned (multiples of 4 elements), as the sweep's loads need
     P.kofs.assign(S + 1, 0);
     for (int64_t s = 0; s < S; ++s) P.kofs[s + 1] = P.kofs[s] + ((int64_t(count[s]) * count[s] + 3) & ~int64_t(3));
@@ -341,6 +331,25 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
             return VTM_E_ARG;
         }
         P.wW[e] = 1.0 / z;
+    }
+
+    // ---- renumbering: sub-circuit by sub-circuit, each one's port nodes (the ends of
+    // its lines) first, then its other nodes, ascending node id in each group; the
+    // rows a sweep needs for the waves alone are then a sub-circuit's first rows
+    P.perm.resize(n);
+    P.iperm.resize(n);
+    {
+        std::vector<uint8_t> is_port(n, 0);
+        for (int64_t e = 0; e < nw; ++e) is_port[P.wi[e]] = is_port[P.wj[e]] = 1;
+        std::vector<int32_t> fill_p(P.sub_off.begin(), P.sub_off.end() - 1), fill_o(S);
+        for (int64_t i = 0; i < n; ++i)
+            if (is_port[i]) fill_o[part[i]]++;
+        for (int64_t s = 0; s < S; ++s) fill_o[s] += P.sub_off[s];
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t r = is_port[i] ? fill_p[part[i]]++ : fill_o[part[i]]++;
+            P.perm[r] = int32_t(i);
+            P.iperm[i] = r;
+        }
     }
 
     // ---- ports -----------------------------------------------------------------

@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kBlock)
              const int32_t* __restrict__ port_slot, const int32_t* __restrict__ port_twin,
              const TV* __restrict__ pc, const TV* __restrict__ pbeta, const TV* __restrict__ pgamma,
              const TV* __restrict__ b, const TV* __restrict__ a_cur, TV* __restrict__ a_next, TV* __restrict__ x,
-             int max_ns, int max_slot, int xs_lds) {
+             int max_ns, int max_slot, int xs_lds, int port_rows) {
     constexpr int G = Group<TO>::G;
     extern __shared__ char smem[];
     TV* rhs = reinterpret_cast<TV*>(smem);   // [max_ns]
@@ -159,6 +159,9 @@ __global__ void __launch_bounds__(kBlock)
     const int ns = sub_off[s + 1] - off;
     const int p0 = port_off[s], p1 = port_off[s + 1];
     const int tid = threadIdx.x, bs = blockDim.x;
+    // port_rows: only the rows the waves need, the port nodes, which are numbered
+    // first in each sub-circuit (its last port's node is the last of them)
+    const int nrow = port_rows ? (p1 > p0 ? port_node[p1 - 1] + 1 : 0) : ns;
     const TO* Ks = K + kofs[s];
     const int full = (ns / G) * G;
     const int ngroups = full / G;
@@ -166,7 +169,7 @@ __global__ void __launch_bounds__(kBlock)
     // rows of this block: [y * bs, y * bs + bs) + k * bs * gridDim.y (gridDim.y > 1 spreads the
     // rows of a few large sub-circuits over several workgroups)
     const int row0 = int(blockIdx.y) * bs, rstep = bs * int(gridDim.y);
-    if (row0 >= ns) return;  // uniform over the workgroup
+    if (row0 >= nrow) return;  // uniform over the workgroup (its rows, and so its port nodes, are none)
 
     TO buf0[CH][G], buf1[CH][G];
     auto load_chunk = [&](TO (&buf)[CH][G], int ch, int row) {
@@ -181,7 +184,7 @@ __global__ void __launch_bounds__(kBlock)
             }
         }
     };
-    if (row0 + tid < ns) load_chunk(buf0, 0, row0 + tid);
+    if (row0 + tid < nrow) load_chunk(buf0, 0, row0 + tid);
 
     for (int t = tid; t < ns; t += bs) rhs[t] = b[off + t];
     __syncthreads();
@@ -198,7 +201,7 @@ __global__ void __launch_bounds__(kBlock)
         }
     }
 
-    for (int row = row0 + tid; row < ns; row += rstep) {
+    for (int row = row0 + tid; row < nrow; row += rstep) {
         if (row != row0 + tid) load_chunk(buf0, 0, row);
         TV acc[G];
 #pragma unroll
@@ -258,7 +261,8 @@ hipError_t launch_r(int S, int max_ns, int nrhs, const TO* K, const int64_t* kof
 template <typename TO, typename TV>
 hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t* kofs, const int32_t* sub_off,
                         PortArrays ports, const TV* pc, const TV* pbeta, const TV* pgamma, const TV* b,
-                        const TV* a_cur, TV* a_next, TV* x, bool adjoint, size_t lds_limit, hipStream_t st) {
+                        const TV* a_cur, TV* a_next, TV* x, bool adjoint, size_t lds_limit, hipStream_t st,
+                        bool port_rows) {
     // right-hand sides per block: rhs and x of the sub-circuit in 64 KiB of LDS; one
     // right-hand side of a larger sub-circuit may use up to lds_limit
     auto fits = [&](int r) { return size_t(2) * max_ns * r * sizeof(TV) <= 65536; };
@@ -277,7 +281,7 @@ hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t*
                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         hipLaunchKernelGGL((k_sweep1<TO, TV, CH>), dim3(S, ry), dim3(bs), lds, st, K, kofs, sub_off, ports.off,
                            ports.node, ports.slot, ports.twin, pc, pbeta, pgamma, b, a_cur, a_next, x, max_ns,
-                           ports.max_slot, xs_lds ? 1 : 0);
+                           ports.max_slot, xs_lds ? 1 : 0, port_rows ? 1 : 0);
         return hipGetLastError();
     }
     if (nrhs == 1 || !fits(2))
@@ -297,10 +301,10 @@ hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t*
 template hipError_t launch_sweep<double, double>(int, int, int, const double*, const int64_t*, const int32_t*,
                                                  PortArrays, const double*, const double*, const double*,
                                                  const double*, const double*, double*, double*, bool, size_t,
-                                                 hipStream_t);
+                                                 hipStream_t, bool);
 template hipError_t launch_sweep<float, float>(int, int, int, const float*, const int64_t*, const int32_t*,
                                                PortArrays, const float*, const float*, const float*,
                                                const float*, const float*, float*, float*, bool, size_t,
-                                               hipStream_t);
+                                               hipStream_t, bool);
 
 }  // namespace vtm

@@ -141,6 +141,26 @@ void plan_checks() {
     check(vtm_line_admittance(&a, part.data(), VTM_W_OB, 1.0, W.data(), nw + 1) == VTM_E_ARG, "wire count");
 }
 
+// The numbering the sweeps' port-row forms rely on: in every sub-circuit the
+// port nodes are its first local nodes (0 .. k-1, every one carrying a port),
+// and the renumbering is a permutation that keeps each node in its sub-circuit.
+bool port_nodes_first(const vtm::Plan& P, const int32_t* part) {
+    for (int64_t r = 0; r < P.n; ++r)
+        if (P.iperm[P.perm[r]] != r) return false;
+    for (int64_t s = 0; s < P.S; ++s) {
+        for (int32_t r = P.sub_off[s]; r < P.sub_off[s + 1]; ++r)
+            if (part && part[P.perm[r]] != s) return false;
+        const int32_t p0 = P.port_off[s], p1 = P.port_off[s + 1];
+        int32_t k = 0;  // distinct port nodes, in order
+        for (int32_t p = p0; p < p1; ++p) {
+            if (p > p0 && P.port_node[p] == P.port_node[p - 1]) continue;
+            if (P.port_node[p] != k) return false;
+            ++k;
+        }
+    }
+    return true;
+}
+
 void refresh_checks() {
     // refresh of a plan against a fresh plan of the new values, bit for bit
     const auto part = blocks(24, 20, 8, 5);
@@ -268,6 +288,7 @@ void vertex_checks() {
     };
     vtm::Plan P;
     check(plan_coupled(wval, P) == VTM_OK && P.coupled, "coupled plan");
+    check(port_nodes_first(P, nullptr), "coupled plan: port nodes (twins) numbered first in each sub-circuit");
     bool ok = int64_t(P.brow.size()) == P.nports + 1;
     for (int64_t p = 0; ok && p < P.nports; ++p) {  // B = 2 W: a full row of L entries per port
         ok = P.brow[p + 1] - P.brow[p] == L;
@@ -308,6 +329,7 @@ void threaded_plan_checks() {
     std::string err;
     check(vtm::build_plan(&a, part.data(), &Z, 1, P, err) == VTM_OK, "threaded plan: " + err);
     check(P.nwires == int64_t(34 * ny + 24 * nx), "threaded plan: cut wire count");
+    check(port_nodes_first(P, part.data()), "threaded plan: port nodes numbered first in each sub-circuit");
     check(P.symmetric, "threaded plan: symmetric");
     bool ok = true;
     for (int64_t r = 0; r < P.n && ok; ++r) {

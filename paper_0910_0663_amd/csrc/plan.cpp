@@ -20,6 +20,7 @@
 #include <memory>
 #include <numeric>
 #include <thread>
+#include <utility>
 
 namespace vtm {
 
@@ -41,6 +42,29 @@ struct SrcEntry {
     double v;
     int32_t k;
 };
+
+// An allocator whose value-initialization is default-initialization, so that
+// resize() leaves trivial elements unwritten: for large buffers that host threads
+// then fill whole (their pages are first touched by those threads instead of
+// being zeroed on one).
+template <typename T>
+struct NoInit : std::allocator<T> {
+    using std::allocator<T>::allocator;
+    template <typename U>
+    struct rebind {
+        using other = NoInit<U>;
+    };
+    template <typename U>
+    void construct(U* p) noexcept {
+        ::new (static_cast<void*>(p)) U;
+    }
+    template <typename U, typename... Args>
+    void construct(U* p, Args&&... args) {
+        ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
+    }
+};
+template <typename T>
+using scratch_vec = std::vector<T, NoInit<T>>;
 
 // Host threads for a pass over `work` items: up to 16, none below 64k items each.
 int plan_threads(int64_t work) {
@@ -153,10 +177,11 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
     // ---- rows with merged duplicates and sorted columns (old numbering) -------
     // The order in which the caller's entries are summed is recorded (src_*) so
     // that vtm_refresh can merge new values the same way without sorting again.
-    std::vector<int64_t> mrow(n + 1, 0);
-    std::vector<Entry> ment;
+    scratch_vec<int64_t> mrow(n + 1);  // every entry written below
+    mrow[0] = 0;
+    scratch_vec<Entry> ment;
     const bool record = !explicit_lines;
-    std::vector<int32_t> src_merged;  // per summed position: merged entry (before renumbering), -1 if dropped
+    scratch_vec<int32_t> src_merged;  // per summed position: merged entry (before renumbering), -1 if dropped
     if (record) {
         P.src_ent.resize(nnz);
         P.src_flag.resize(nnz);
@@ -466,7 +491,7 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
     P.rowptr.assign(n + 1, 0);
     P.col.resize(ment.size());
     P.val.resize(ment.size());
-    std::vector<int32_t> m2r(record ? ment.size() : 0);  // merged entry -> renumbered entry
+    scratch_vec<int32_t> m2r(record ? ment.size() : 0);  // merged entry -> renumbered entry (each written once)
     for (int64_t r = 0; r < n; ++r) {
         const int32_t i = P.perm[r];
         P.rowptr[r + 1] = P.rowptr[r] + int32_t(mrow[i + 1] - mrow[i]);

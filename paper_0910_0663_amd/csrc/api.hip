@@ -52,7 +52,8 @@ struct DevBuf {
         p = nullptr;
         count = 0;
     }
-    hipError_t upload(const std::vector<T>& v, hipStream_t st) {
+    template <typename Alloc>
+    hipError_t upload(const std::vector<T, Alloc>& v, hipStream_t st) {
         hipError_t e = alloc(v.size());
         if (e != hipSuccess || v.empty()) return e;
         return hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);

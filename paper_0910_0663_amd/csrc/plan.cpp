@@ -43,29 +43,6 @@ struct SrcEntry {
     int32_t k;
 };
 
-// An allocator whose value-initialization is default-initialization, so that
-// resize() leaves trivial elements unwritten: for large buffers that host threads
-// then fill whole (their pages are first touched by those threads instead of
-// being zeroed on one).
-template <typename T>
-struct NoInit : std::allocator<T> {
-    using std::allocator<T>::allocator;
-    template <typename U>
-    struct rebind {
-        using other = NoInit<U>;
-    };
-    template <typename U>
-    void construct(U* p) noexcept {
-        ::new (static_cast<void*>(p)) U;
-    }
-    template <typename U, typename... Args>
-    void construct(U* p, Args&&... args) {
-        ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
-    }
-};
-template <typename T>
-using scratch_vec = std::vector<T, NoInit<T>>;
-
 // Host threads for a pass over `work` items: up to 16, none below 64k items each.
 int plan_threads(int64_t work) {
     const int64_t hw = std::max(1u, std::thread::hardware_concurrency());
@@ -187,65 +164,84 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
         P.src_flag.resize(nnz);
         src_merged.resize(nnz);
     }
-    // rows are merged in chunks on host threads; a chunk's merged entries are
-    // numbered inside the chunk, then shifted when the chunks are joined in row order
+    // rows are merged on host threads in two passes: the merged length of every row,
+    // then, with the row offsets known, the merged entries written in place
     const int TR = plan_threads(nnz);
     {
-        std::vector<std::vector<Entry>> part_ent(TR);
-        for_chunks(n, TR, [&](int t, int64_t i0, int64_t i1) {
-            std::vector<Entry>& me = part_ent[t];
-            me.reserve(size_t(A->rowptr[i1] - A->rowptr[i0]));
+        // row i merged into tmp (columns sorted, duplicates summed, zeros off the
+        // diagonal dropped); with record, the summation order goes to src_ent and
+        // src_flag and each position's entry index within tmp (-1: dropped) to pos_of
+        auto merge_row = [&](int64_t i, std::vector<SrcEntry>& row, std::vector<Entry>& tmp,
+                             std::vector<int32_t>& run_of, int32_t* pos_of) {
+            row.clear();
+            bool sorted = true;
+            for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) {
+                if (!row.empty() && A->col[k] <= row.back().c) sorted = false;
+                row.push_back({A->col[k], A->val[k], int32_t(k)});
+            }
+            if (!sorted)
+                std::sort(row.begin(), row.end(), [](const SrcEntry& a, const SrcEntry& b) { return a.c < b.c; });
+            tmp.clear();
+            int64_t pos = A->rowptr[i];
+            for (const SrcEntry& e : row) {
+                const bool first = !(!tmp.empty() && tmp.back().c == e.c);
+                if (!first)
+                    tmp.back().v += e.v;
+                else
+                    tmp.push_back({e.c, e.v});
+                if (pos_of) {
+                    P.src_ent[pos] = e.k;
+                    P.src_flag[pos] = uint8_t((first ? 1 : 0) | (e.c == i ? 2 : 0));
+                    pos_of[pos - A->rowptr[i]] = int32_t(tmp.size() - 1);  // run index for now
+                }
+                ++pos;
+            }
+            // explicit zeros off the diagonal couple nothing
+            size_t w = 0;
+            run_of.assign(tmp.size(), -1);
+            for (size_t k = 0; k < tmp.size(); ++k)
+                if (tmp[k].v != 0.0 || tmp[k].c == i) {
+                    run_of[k] = int32_t(w);
+                    tmp[w++] = tmp[k];
+                }
+            tmp.resize(w);
+            if (pos_of)
+                for (int64_t q = 0; q < pos - A->rowptr[i]; ++q) pos_of[q] = run_of[pos_of[q]];
+        };
+        for_chunks(n, TR, [&](int, int64_t i0, int64_t i1) {
             std::vector<SrcEntry> row;
-            std::vector<int32_t> run_of;  // per merged entry of the row (before dropping zeros): kept index or -1
+            std::vector<Entry> tmp;
+            std::vector<int32_t> run_of;
             for (int64_t i = i0; i < i1; ++i) {
-                row.clear();
-                bool sorted = true;
+                // a row with strictly increasing columns has no duplicates to sum
+                bool inc = true;
+                int64_t cnt = 0;
                 for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) {
-                    if (!row.empty() && A->col[k] <= row.back().c) sorted = false;
-                    row.push_back({A->col[k], A->val[k], int32_t(k)});
+                    if (k > A->rowptr[i] && A->col[k] <= A->col[k - 1]) inc = false;
+                    if (A->val[k] != 0.0 || A->col[k] == i) ++cnt;
                 }
-                if (!sorted)
-                    std::sort(row.begin(), row.end(), [](const SrcEntry& a, const SrcEntry& b) { return a.c < b.c; });
-                const size_t start = me.size();
-                int64_t pos = A->rowptr[i];
-                for (const SrcEntry& e : row) {
-                    const bool first = !(me.size() > start && me.back().c == e.c);
-                    if (!first)
-                        me.back().v += e.v;
-                    else
-                        me.push_back({e.c, e.v});
-                    if (record) {
-                        P.src_ent[pos] = e.k;
-                        P.src_flag[pos] = uint8_t((first ? 1 : 0) | (e.c == i ? 2 : 0));
-                        src_merged[pos] = int32_t(me.size() - 1 - start);  // run index inside the row for now
-                    }
-                    ++pos;
+                if (!inc) {
+                    merge_row(i, row, tmp, run_of, nullptr);
+                    cnt = int64_t(tmp.size());
                 }
-                // explicit zeros off the diagonal couple nothing
-                size_t w = start;
-                run_of.assign(me.size() - start, -1);
-                for (size_t k = start; k < me.size(); ++k)
-                    if (me[k].v != 0.0 || me[k].c == i) {
-                        run_of[k - start] = int32_t(w);
-                        me[w++] = me[k];
-                    }
-                me.resize(w);
-                mrow[i + 1] = int64_t(w - start);
-                if (record)
-                    for (int64_t q = A->rowptr[i]; q < pos; ++q) src_merged[q] = run_of[src_merged[q]];
+                mrow[i + 1] = cnt;
             }
         });
-        std::vector<int64_t> base(TR + 1, 0);
-        for (int t = 0; t < TR; ++t) base[t + 1] = base[t] + int64_t(part_ent[t].size());
-        ment.resize(size_t(base[TR]));
-        for_chunks(n, TR, [&](int t, int64_t i0, int64_t i1) {
-            std::copy(part_ent[t].begin(), part_ent[t].end(), ment.begin() + base[t]);
-            std::vector<Entry>().swap(part_ent[t]);
-            if (record)
-                for (int64_t q = A->rowptr[i0]; q < A->rowptr[i1]; ++q)
-                    if (src_merged[q] >= 0) src_merged[q] += int32_t(base[t]);
-        });
         for (int64_t i = 0; i < n; ++i) mrow[i + 1] += mrow[i];
+        ment.resize(size_t(mrow[n]));
+        for_chunks(n, TR, [&](int, int64_t i0, int64_t i1) {
+            std::vector<SrcEntry> row;
+            std::vector<Entry> tmp;
+            std::vector<int32_t> run_of;
+            for (int64_t i = i0; i < i1; ++i) {
+                int32_t* pos_of = record ? src_merged.data() + A->rowptr[i] : nullptr;
+                merge_row(i, row, tmp, run_of, pos_of);
+                std::copy(tmp.begin(), tmp.end(), ment.begin() + mrow[i]);
+                if (record)
+                    for (int64_t q = 0; q < A->rowptr[i + 1] - A->rowptr[i]; ++q)
+                        if (pos_of[q] >= 0) pos_of[q] += int32_t(mrow[i]);
+            }
+        });
     }
 
     // ---- exact symmetry (lets the adjoint share the forward path) -------------

@@ -4,12 +4,37 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "vtm.h"
 
 namespace vtm {
+
+// An allocator whose value-initialization is default-initialization, so that
+// resize() leaves trivial elements unwritten: for large buffers that host threads
+// then fill whole (their pages are first touched by those threads instead of
+// being zeroed on one).
+template <typename T>
+struct NoInit : std::allocator<T> {
+    using std::allocator<T>::allocator;
+    template <typename U>
+    struct rebind {
+        using other = NoInit<U>;
+    };
+    template <typename U>
+    void construct(U* p) noexcept {
+        ::new (static_cast<void*>(p)) U;
+    }
+    template <typename U, typename... Args>
+    void construct(U* p, Args&&... args) {
+        ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
+    }
+};
+template <typename T>
+using scratch_vec = std::vector<T, NoInit<T>>;
 
 struct Plan {
     int64_t n = 0;        // nodes
@@ -20,7 +45,8 @@ struct Plan {
     int32_t max_slot = 0; // most ports on one node, minus one
     bool symmetric = false;
 
-    // Sub-circuit-major renumbering: new id = position after a stable sort by label.
+    // Sub-circuit-major renumbering: inside each sub-circuit its port nodes (the
+    // ends of its lines) first, then its other nodes, ascending old id in each group.
     std::vector<int32_t> perm;     // new -> old
     std::vector<int32_t> iperm;    // old -> new
     std::vector<int32_t> sub_off;  // [S + 1] first new id of each sub-circuit
@@ -60,14 +86,15 @@ struct Plan {
     std::vector<double> dmod;      // per new node: sum over its ports of (G - g)
 
     // The untorn A renumbered (rows and columns), duplicates merged, columns sorted.
-    std::vector<int32_t> rowptr, col;
-    std::vector<double> val;
+    std::vector<int32_t> rowptr;
+    scratch_vec<int32_t> col;
+    scratch_vec<double> val;
     // How the caller's entries became it (not for tearing at nodes): the caller's
     // entry indices in the order they are summed, per position a flag (bit 0: first
     // entry of a merged entry, bit 1: a diagonal one) and the renumbered entry the
     // sum goes to (-1: an explicit zero off the diagonal, dropped).
-    std::vector<int32_t> src_ent, src_dst;
-    std::vector<uint8_t> src_flag;
+    scratch_vec<int32_t> src_ent, src_dst;
+    scratch_vec<uint8_t> src_flag;
 
     // Tearing at interfacial nodes (build_plan_vertex): the plan above describes the
     // expanded system (every interfacial node replaced by two twins); these map it

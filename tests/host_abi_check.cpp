@@ -5,6 +5,7 @@
 // vtm_line_admittance, vtm_vertex_admittance, vtm_vertex_sca, status strings,
 // options) on valid circuits and on malformed input.  Exit status 0 when every
 // check holds; a sanitizer report aborts the run.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -177,7 +178,7 @@ void refresh_checks() {
                   P.pg == Q.pg && P.pgd == Q.pgd && P.wg == Q.wg && P.wW == Q.wW,
               "refreshed plan equals a fresh plan");
         // refused changes leave the plan as it was
-        const std::vector<double> before = P.val;
+        const auto before = P.val;
         std::vector<double> v = A2.val;
         int64_t off = -1;  // an off-diagonal entry inside a block
         for (int64_t q = A2.rowptr[0]; q < A2.rowptr[1]; ++q)
@@ -350,7 +351,7 @@ void threaded_plan_checks() {
         const double v = A.val[P.src_ent[q]];
         rebuilt[d] = (P.src_flag[q] & 1) ? v : rebuilt[d] + v;
     }
-    check(rebuilt == P.val, "threaded plan: recorded merge order");
+    check(std::equal(rebuilt.begin(), rebuilt.end(), P.val.begin(), P.val.end()), "threaded plan: recorded merge order");
     ok = true;
     for (int64_t q = 0; q < P.nports && ok; ++q) {
         const int32_t p = P.abi2port[q];

@@ -17,6 +17,7 @@ namespace vtm {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kRegSetupMax = 64;  // sub-circuits up to this size: one wavefront each, rows in registers
 
 __device__ inline void arg_better(double& bv, int& bi, double v, int i) {
     if (v > bv || (v == bv && i < bi)) {
@@ -85,7 +86,7 @@ __global__ void __launch_bounds__(kBlock)
     const int s = blockIdx.x;
     const int off = sub_off[s];
     const int n = sub_off[s + 1] - off;
-    if (n > kLdsSetupMax) return;
+    if (n > kLdsSetupMax || n <= kRegSetupMax) return;  // k_setup_reg takes n <= kRegSetupMax
     const int tid = threadIdx.x, bs = blockDim.x;
 
     for (int t = tid; t < n * n; t += bs) M[t] = 0.0;
@@ -145,6 +146,142 @@ __global__ void __launch_bounds__(kBlock)
         store_layout<TO>(M, n, out + kofs[s]);
     }
     if (bad && tid == 0) atomicOr(flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Register path: one wavefront per sub-circuit with n <= kRegSetupMax, lane j
+// holding row j of K.  The same Gauss-Jordan steps as k_setup_lds, which works
+// on M = K^T: its pivot search over M's column k is a search along K's row k,
+// its swap of M's rows k and p swaps K's columns k and p in every lane's row, and
+// each of its row operations on M is a column operation on K that every lane
+// applies to its own row, in the same order and arithmetic.  The result (M^-1,
+// row-major) is K^-1 with row r in lane r; the final column unscrambling of M is
+// a permutation of those rows, applied where they are stored.  Row k of K is
+// passed to the wavefront through LDS; an entry at a run-time index of a lane's
+// row is read and written through selects (a register array indexed at run time
+// would go to scratch memory).  No workgroup-wide barrier is needed beyond the
+// wavefront's own.
+// ---------------------------------------------------------------------------
+template <typename TO, bool COLMAJOR>
+__global__ void __launch_bounds__(64)
+    k_setup_reg(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs,
+                const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                const double* __restrict__ val, const double* __restrict__ dmod, TO* __restrict__ out,
+                int* flag) {
+    __shared__ double prow[kRegSetupMax];
+    __shared__ int ipiv[kRegSetupMax];
+    const int s = blockIdx.x;
+    const int off = sub_off[s];
+    const int n = sub_off[s + 1] - off;
+    if (n > kRegSetupMax) return;  // uniform over the workgroup
+    const int j = threadIdx.x;
+    const bool mine = j < n;
+    double row[kRegSetupMax];
+#pragma unroll
+    for (int c = 0; c < kRegSetupMax; ++c) row[c] = 0.0;
+    // K's row j, summed as k_setup_lds sums M's column j: the row's entries, then dmod
+    if (mine) {
+        // the row's entries 8 at a time (its columns are distinct), each added to the
+        // entry of its column
+        for (int k0 = rowptr[off + j], k1 = rowptr[off + j + 1]; k0 < k1; k0 += 8) {
+            int ce[8];
+            double ve[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int c = k0 + e < k1 ? col[k0 + e] - off : -1;
+                ce[e] = c >= 0 && c < n ? c : -1;  // entries outside the sub-circuit: none
+                ve[e] = k0 + e < k1 ? val[k0 + e] : 0.0;
+            }
+#pragma unroll
+            for (int cc = 0; cc < kRegSetupMax; ++cc) {
+                double v = row[cc];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v = ce[e] == cc ? v + ve[e] : v;
+                row[cc] = v;
+            }
+        }
+        const double d = dmod[off + j];
+#pragma unroll
+        for (int cc = 0; cc < kRegSetupMax; ++cc) row[cc] = cc == j ? row[cc] + d : row[cc];
+    }
+    bool bad = false;
+    // Each lane keeps its row rotated: at column step k, register slot i holds
+    // column (i + k) mod 64, so the step's column is always slot 0 and every register
+    // index below is fixed at compile time; the row turns by one slot per step.
+    for (int k = 0; k < n; ++k) {
+        // pivot: the largest |K(k, i)|, i >= k, ties to the lowest i (none: INT_MAX)
+        if (j == k)
+#pragma unroll
+            for (int i = 0; i < kRegSetupMax; ++i) prow[(i + k) & (kRegSetupMax - 1)] = row[i];
+        __syncthreads();
+        double bv = -1.0;
+        int p = INT_MAX;
+        if (j >= k && j < n) arg_better(bv, p, fabs(prow[j]), j);
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o, 64);
+            const int oi = __shfl_xor(p, o, 64);
+            arg_better(bv, p, ov, oi);
+        }
+        if (p == INT_MAX) {
+            bad = true;
+            p = k;
+        }
+        if (j == 0) ipiv[k] = p;
+        if (p != k) {  // uniform: columns k (slot 0) and p (slot p - k) of every row trade places
+            const int sp = p - k;
+            const double a = row[0];
+            double b = 0.0;
+#pragma unroll
+            for (int i = 1; i < kRegSetupMax; ++i) b = i == sp ? row[i] : b;
+#pragma unroll
+            for (int i = 1; i < kRegSetupMax; ++i) row[i] = i == sp ? a : row[i];
+            row[0] = b;
+        }
+        __syncthreads();
+        // row k of K after the swap: the pivot and the multipliers (M's column k)
+        if (j == k)
+#pragma unroll
+            for (int i = 0; i < kRegSetupMax; ++i) prow[(i + k) & (kRegSetupMax - 1)] = row[i];
+        __syncthreads();
+        double pv = prow[k];
+        if (pv == 0.0 || !isfinite(pv)) {
+            bad = true;
+            pv = 1.0;
+        }
+        const double rk = (j == k ? 1.0 : row[0]) / pv;  // M(k, j) scaled
+        // the update, each slot written back one slot lower (the turn for the next step)
+        const double r0 = rk;
+#pragma unroll
+        for (int i = 1; i < kRegSetupMax; ++i)
+            row[i - 1] = (j == k ? 0.0 : row[i]) - prow[(i + k) & (kRegSetupMax - 1)] * rk;
+        row[kRegSetupMax - 1] = r0;
+        __syncthreads();
+    }
+    // after n steps slot i holds column (i + n) mod 64
+    // M's columns k and ipiv[k] swapped for k = n-1 .. 0: K^-1's rows, so lane j's
+    // row goes to the position those swaps carry it to
+    int pos = j;
+    for (int k = n - 1; k >= 0; --k) {
+        const int p = ipiv[k];
+        if (pos == k)
+            pos = p;
+        else if (pos == p)
+            pos = k;
+    }
+    if (mine) {
+        TO* dst = out + kofs[s];
+#pragma unroll
+        for (int i = 0; i < kRegSetupMax; ++i) {
+            const int c = (i + n) & (kRegSetupMax - 1);
+            if (c < n) {
+                if constexpr (COLMAJOR)
+                    dst[int64_t(c) * n + pos] = TO(row[i]);
+                else
+                    dst[inv_offset<TO>(n, pos, c)] = TO(row[i]);
+            }
+        }
+    }
+    if (bad && j == 0) atomicOr(flag, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -710,10 +847,15 @@ hipError_t launch_setup_tiles(int S, int max_ns, const int32_t* sub_off, const i
                               T* out, double* scratch64, double* panel, int32_t* ipiv, int* flag, hipStream_t st,
                               T* out_t) {
     if (!scratch64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_setup_lds<double, true>), dim3(S), dim3(kBlock), 0, st, sub_off, kofs, rowptr, col, val,
-                       dmod, scratch64, flag);
+    hipLaunchKernelGGL((k_setup_reg<double, true>), dim3(S), dim3(64), 0, st, sub_off, kofs, rowptr, col, val, dmod,
+                       scratch64, flag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (max_ns > kRegSetupMax) {
+        hipLaunchKernelGGL((k_setup_lds<double, true>), dim3(S), dim3(kBlock), 0, st, sub_off, kofs, rowptr, col, val,
+                           dmod, scratch64, flag);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if (max_ns > kLdsSetupMax) {
         e = invert_large(S, max_ns, sub_off, kofs, rowptr, col, val, dmod, scratch64, panel, ipiv, flag, st);
         if (e != hipSuccess) return e;
@@ -730,9 +872,13 @@ template <typename TO>
 hipError_t launch_setup(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, const int32_t* rowptr,
                         const int32_t* col, const double* val, const double* dmod, TO* out, double* scratch64,
                         double* panel, int32_t* ipiv, int* flag, hipStream_t st) {
+    hipLaunchKernelGGL((k_setup_reg<TO, false>), dim3(S), dim3(64), 0, st, sub_off, kofs, rowptr, col, val, dmod, out,
+                       flag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || max_ns <= kRegSetupMax) return e;
     hipLaunchKernelGGL((k_setup_lds<TO, false>), dim3(S), dim3(kBlock), 0, st, sub_off, kofs, rowptr, col, val,
                        dmod, out, flag);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess || max_ns <= kLdsSetupMax) return e;
     e = invert_large(S, max_ns, sub_off, kofs, rowptr, col, val, dmod, scratch64, panel, ipiv, flag, st);
     if (e != hipSuccess) return e;

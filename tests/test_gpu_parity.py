@@ -172,6 +172,42 @@ def test_sub_circuit_without_ports_in_every_form(torch, nrhs):
     s.close()
 
 
+def _strong_one_sided_couplings(w, scale, seed):
+    """w with one-sided entries larger than the diagonal added inside its
+    sub-circuits (controlled sources of large gain), so that the elimination of
+    every local matrix has to pivot."""
+    rng = np.random.default_rng(seed)
+    A = w.A.tolil()
+    d = w.A.diagonal()
+    for s_ in range(w.n_sub):
+        nodes = np.nonzero(w.part == s_)[0]
+        for i in rng.choice(nodes, size=len(nodes) // 2, replace=False):
+            j = rng.choice(nodes[nodes != i])
+            A[i, j] = A[i, j] + scale * d[i] * rng.choice([-1.0, 1.0])
+    w.A = A.tocsr()
+    return w
+
+
+@pytest.mark.parametrize("kind", ["pivoting 64-node", "ragged 63-node"])
+def test_register_setup_iterates_match_oracle(torch, kind):
+    """Sub-circuits of up to 64 nodes are inverted by one wavefront each: with
+    one-sided entries larger than the diagonal (every elimination pivots) on
+    4x4x4 blocks, and on 7x9 blocks (63 nodes, a ragged register row), the first
+    iterates in the full and port-to-port forms equal the oracle's (exact local
+    solves by sparse LU)."""
+    if kind.startswith("pivoting"):
+        w = _strong_one_sided_couplings(workloads.make(3, dims=(8, 8, 8), block=(4, 4, 4)), 3.0, 4)
+        assert np.bincount(w.part).max() == 64
+    else:
+        w = workloads.make(1, dims=(63, 63), block=(7, 9))
+        assert np.bincount(w.part).max() == 63
+    ks = [1, 3]
+    ref = oracle_iterates(w, ks)
+    for k in ks:
+        assert_close(gpu_iterate(torch, w, k, local_form="full"), ref[k])
+        assert_close(gpu_iterate(torch, w, k, check_every=k), ref[k])
+
+
 def test_singular_sub_circuit_is_reported(torch):
     """A node with no branch and no ground, alone in its sub-circuit, makes that
     sub-circuit's matrix singular: setup fails with VTM_E_SINGULAR, for FP64 and

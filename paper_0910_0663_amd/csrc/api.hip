@@ -60,7 +60,10 @@ struct DevBuf {
     }
 };
 
-std::vector<float> to_float(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
+template <typename Alloc>
+std::vector<float> to_float(const std::vector<double, Alloc>& v) {
+    return std::vector<float>(v.begin(), v.end());
+}
 
 }  // namespace
 

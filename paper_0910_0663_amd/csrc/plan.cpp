@@ -105,13 +105,20 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
             err = "rowptr must be non-decreasing";
             return VTM_E_ARG;
         }
-    for (int64_t k = 0; k < nnz; ++k) {
-        if (A->col[k] < 0 || A->col[k] >= n) {
-            err = "column index out of range";
-            return VTM_E_ARG;
-        }
-        if (!std::isfinite(A->val[k])) {
-            err = "non-finite matrix entry";
+    {
+        // entries checked on threads; the first bad entry in order decides the message
+        const int TV = plan_threads(nnz);
+        std::vector<int64_t> first_bad(TV, INT64_MAX);
+        for_chunks(nnz, TV, [&](int t, int64_t k0, int64_t k1) {
+            for (int64_t k = k0; k < k1; ++k)
+                if (A->col[k] < 0 || A->col[k] >= n || !std::isfinite(A->val[k])) {
+                    first_bad[t] = k;
+                    return;
+                }
+        });
+        const int64_t k = *std::min_element(first_bad.begin(), first_bad.end());
+        if (k != INT64_MAX) {
+            err = (A->col[k] < 0 || A->col[k] >= n) ? "column index out of range" : "non-finite matrix entry";
             return VTM_E_ARG;
         }
     }
@@ -376,32 +383,34 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
     // ---- ports -----------------------------------------------------------------
     // key per ABI port q (2e lower node, 2e+1 upper): (sub, local node, wire)
     const int64_t np = P.nports;
+    const int TP = plan_threads(np);
     std::vector<int32_t> q_sub(np), q_loc(np);
-    for (int64_t e = 0; e < nw; ++e) {
-        for (int side = 0; side < 2; ++side) {
-            const int32_t node = side ? P.wj[e] : P.wi[e];
-            const int64_t q = 2 * e + side;
-            q_sub[q] = part[node];
-            q_loc[q] = P.iperm[node] - P.sub_off[part[node]];
-        }
-    }
+    for_chunks(nw, TP, [&](int, int64_t e0, int64_t e1) {
+        for (int64_t e = e0; e < e1; ++e)
+            for (int side = 0; side < 2; ++side) {
+                const int32_t node = side ? P.wj[e] : P.wi[e];
+                const int64_t q = 2 * e + side;
+                q_sub[q] = part[node];
+                q_loc[q] = P.iperm[node] - P.sub_off[part[node]];
+            }
+    });
     // ports in (sub-circuit, local node, ABI port) order: a counting sort by
     // sub-circuit (ABI order inside each), then each sub-circuit's run sorted by
-    // local node, stably
-    std::vector<int64_t> order(np);
+    // local node, stably; beg[s] is the first port of sub-circuit s
+    std::vector<int64_t> order(np), beg(S + 1, 0);
     {
-        std::vector<int64_t> beg(S + 1, 0);
         for (int64_t q = 0; q < np; ++q) beg[q_sub[q] + 1]++;
         for (int64_t s = 0; s < S; ++s) beg[s + 1] += beg[s];
         std::vector<int64_t> fill(beg.begin(), beg.end() - 1);
         for (int64_t q = 0; q < np; ++q) order[fill[q_sub[q]]++] = q;
-        for_chunks(S, plan_threads(np), [&](int, int64_t s0, int64_t s1) {
+        for_chunks(S, TP, [&](int, int64_t s0, int64_t s1) {
             for (int64_t s = s0; s < s1; ++s)
                 std::stable_sort(order.begin() + beg[s], order.begin() + beg[s + 1],
                                  [&](int64_t a, int64_t b) { return q_loc[a] < q_loc[b]; });
         });
     }
     P.port_off.assign(S + 1, 0);
+    for (int64_t s = 0; s < S; ++s) P.port_off[s + 1] = int32_t(beg[s + 1] - beg[s]);  // counts for now
     P.port_node.resize(np);
     P.port_slot.resize(np);
     P.port_twin.resize(np);
@@ -413,7 +422,7 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
     P.pgd.resize(np);
     P.dmod.assign(n, 0.0);
     P.max_slot = 0;
-    for_chunks(np, plan_threads(np), [&](int, int64_t p0, int64_t p1) {
+    for_chunks(np, TP, [&](int, int64_t p0, int64_t p1) {
         for (int64_t p = p0; p < p1; ++p) {
             const int64_t q = order[p];
             P.abi2port[q] = int32_t(p);
@@ -431,17 +440,24 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
             P.pgd[p] = k.G - P.wg[e];
         }
     });
-    // in port order: the slots, and the diagonal changes summed as ports come
-    for (int64_t p = 0; p < np; ++p) {
-        const int64_t q = order[p];
-        P.port_off[q_sub[q] + 1]++;
-        P.port_slot[p] = (p > 0 && q_sub[order[p - 1]] == q_sub[q] && q_loc[order[p - 1]] == q_loc[q])
-                             ? P.port_slot[p - 1] + 1
-                             : 0;
-        P.max_slot = std::max(P.max_slot, P.port_slot[p]);
-        const int32_t node = (q & 1) ? P.wj[q / 2] : P.wi[q / 2];
-        P.dmod[P.iperm[node]] += P.pgd[p];
-    }
+    // in port order: the slots, and the diagonal changes summed as ports come; a
+    // node's ports are its sub-circuit's, so sub-circuits split over threads keep
+    // every node's order
+    std::vector<int32_t> tmax(TP, 0);
+    for_chunks(S, TP, [&](int t, int64_t s0, int64_t s1) {
+        int32_t mx = 0;
+        for (int64_t p = beg[s0]; p < beg[s1]; ++p) {
+            const int64_t q = order[p];
+            P.port_slot[p] = (p > beg[s0] && q_sub[order[p - 1]] == q_sub[q] && q_loc[order[p - 1]] == q_loc[q])
+                                 ? P.port_slot[p - 1] + 1
+                                 : 0;
+            mx = std::max(mx, P.port_slot[p]);
+            const int32_t node = (q & 1) ? P.wj[q / 2] : P.wi[q / 2];
+            P.dmod[P.iperm[node]] += P.pgd[p];
+        }
+        tmax[t] = mx;
+    });
+    for (int32_t v : tmax) P.max_slot = std::max(P.max_slot, v);
     P.pofs.assign(S + 1, 0);
     P.qmofs.assign(S + 1, 0);
     for (int64_t s = 0; s < S; ++s) {
@@ -453,7 +469,9 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
         P.qmofs[s + 1] = P.qmofs[s] + qp * qp;
         P.port_off[s + 1] += P.port_off[s];
     }
-    for (int64_t q = 0; q < np; ++q) P.port_twin[P.abi2port[q]] = P.abi2port[q ^ 1];
+    for_chunks(np, TP, [&](int, int64_t q0, int64_t q1) {
+        for (int64_t q = q0; q < q1; ++q) P.port_twin[P.abi2port[q]] = P.abi2port[q ^ 1];
+    });
     for (int64_t e = 1; e < nw; ++e)
         if (P.wW[e] != P.wW[0]) P.uniform_W = false;
 

@@ -76,12 +76,12 @@ struct Plan {
 
     // Ports: two per wire, grouped by sub-circuit, inside one by (local node, wire).
     std::vector<int32_t> port_off;   // [S + 1]
-    std::vector<int32_t> port_node;  // local node index inside its sub-circuit
-    std::vector<int32_t> port_slot;  // rank among the ports of the same node
-    std::vector<int32_t> port_twin;  // the other port of the same wire
-    std::vector<int32_t> abi2port;   // [2 * nwires]: ABI port (2e lower, 2e+1 upper) -> port
-    std::vector<double> pc, pbeta, pgamma;  // per port: c, beta, gamma
-    std::vector<double> pg, pgd;            // per port: wire conductance g and G - g
+    scratch_vec<int32_t> port_node;  // local node index inside its sub-circuit
+    scratch_vec<int32_t> port_slot;  // rank among the ports of the same node
+    scratch_vec<int32_t> port_twin;  // the other port of the same wire
+    scratch_vec<int32_t> abi2port;   // [2 * nwires]: ABI port (2e lower, 2e+1 upper) -> port
+    scratch_vec<double> pc, pbeta, pgamma;  // per port: c, beta, gamma
+    scratch_vec<double> pg, pgd;            // per port: wire conductance g and G - g
 
     std::vector<double> dmod;      // per new node: sum over its ports of (G - g)
 

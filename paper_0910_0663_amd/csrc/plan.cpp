@@ -532,6 +532,25 @@ vtm_status build_plan(const vtm_csr* A, const int32_t* part, const double* Z, in
         for_chunks(nnz, TR, [&](int, int64_t q0, int64_t q1) {
             for (int64_t q = q0; q < q1; ++q) P.src_dst[q] = src_merged[q] < 0 ? -1 : m2r[src_merged[q]];
         });
+        // transpose and wire positions, so that a refresh compares values without searching
+        auto at = [&](int32_t r, int32_t c) -> int32_t {
+            auto lo = P.col.begin() + P.rowptr[r], hi = P.col.begin() + P.rowptr[r + 1];
+            auto it = std::lower_bound(lo, hi, c);
+            return (it == hi || *it != c) ? -1 : int32_t(it - P.col.begin());
+        };
+        P.tpos.resize(P.col.size());
+        for_chunks(n, TR, [&](int, int64_t r0, int64_t r1) {
+            for (int64_t r = r0; r < r1; ++r)
+                for (int32_t k = P.rowptr[r]; k < P.rowptr[r + 1]; ++k) P.tpos[k] = at(P.col[k], int32_t(r));
+        });
+        P.wpos.resize(2 * nw);
+        for_chunks(nw, TP, [&](int, int64_t e0, int64_t e1) {
+            for (int64_t e = e0; e < e1; ++e) {
+                const int32_t r = P.iperm[P.wi[e]], c = P.iperm[P.wj[e]];
+                P.wpos[2 * e] = at(r, c);
+                P.wpos[2 * e + 1] = at(c, r);
+            }
+        });
     }
     return VTM_OK;
 }
@@ -608,22 +627,16 @@ vtm_status refresh_plan(Plan& P, const double* val, int64_t nnz, const double* Z
                           : "non-finite matrix entry";
         return VTM_E_ARG;
     }
-    // value at renumbered (r, c), which the pattern holds
-    auto at = [&](int32_t r, int32_t c) -> int64_t {
-        auto lo = P.col.begin() + P.rowptr[r], hi = P.col.begin() + P.rowptr[r + 1];
-        auto it = std::lower_bound(lo, hi, c);
-        return (it == hi || *it != c) ? -1 : int64_t(it - P.col.begin());
-    };
+    // symmetric: every entry has its transpose in the pattern, of equal value
     std::vector<uint8_t> asym(T, 0);
-    for_chunks(P.n, T, [&](int t, int64_t r0, int64_t r1) {
-        for (int64_t r = r0; r < r1; ++r)
-            for (int32_t k = P.rowptr[r]; k < P.rowptr[r + 1]; ++k) {
-                const int64_t u = at(P.col[k], int32_t(r));
-                if (u < 0 || nv[u] != nv[k]) {
-                    asym[t] = 1;
-                    return;
-                }
+    for_chunks(m, T, [&](int t, int64_t k0, int64_t k1) {
+        for (int64_t k = k0; k < k1; ++k) {
+            const int32_t u = P.tpos[k];
+            if (u < 0 || nv[u] != nv[k]) {
+                asym[t] = 1;
+                return;
             }
+        }
     });
     const bool sym = std::find(asym.begin(), asym.end(), 1) == asym.end();
     if (sym != P.symmetric) {
@@ -636,8 +649,7 @@ vtm_status refresh_plan(Plan& P, const double* val, int64_t nnz, const double* Z
     std::vector<int64_t> bad(TW, INT64_MAX);  // each chunk's first wire that is no conductance
     for_chunks(nw, TW, [&](int t, int64_t e0, int64_t e1) {
         for (int64_t e = e0; e < e1; ++e) {
-            const int32_t r = P.iperm[P.wi[e]], c = P.iperm[P.wj[e]];
-            const double v = nv[at(r, c)], vt = nv[at(c, r)];
+            const double v = nv[P.wpos[2 * e]], vt = nv[P.wpos[2 * e + 1]];
             if (v != vt || !(v < 0.0)) {
                 bad[t] = e;
                 return;

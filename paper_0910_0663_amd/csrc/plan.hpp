@@ -95,6 +95,10 @@ struct Plan {
     // sum goes to (-1: an explicit zero off the diagonal, dropped).
     scratch_vec<int32_t> src_ent, src_dst;
     scratch_vec<uint8_t> src_flag;
+    // For the refresh's checks (same plans): per renumbered entry (r, c) the position
+    // of (c, r), -1 if the pattern lacks it; per cut wire e the positions of its two
+    // entries (r, c) and (c, r), at 2 e and 2 e + 1.
+    scratch_vec<int32_t> tpos, wpos;
 
     // Tearing at interfacial nodes (build_plan_vertex): the plan above describes the
     // expanded system (every interfacial node replaced by two twins); these map it

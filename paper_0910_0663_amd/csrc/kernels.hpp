@@ -6,10 +6,32 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "tiles.hpp"
 
 namespace vtm {
+
+// Raises kern's dynamic LDS limit on the current device to at least lds bytes
+// (launches above 64 KiB need it).  A (kernel, device) pair is raised only when a
+// larger size comes, under a lock, so handles on different host threads may
+// launch the same kernel together.
+inline hipError_t raise_lds_limit(const void* kern, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, size_t> raised;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t& cur = raised[{kern, dev}];
+    if (lds <= cur) return hipSuccess;
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e == hipSuccess) cur = lds;
+    return e;
+}
 
 // Largest sub-circuit whose local matrix is factored entirely in LDS.
 constexpr int kLdsSetupMax = 80;

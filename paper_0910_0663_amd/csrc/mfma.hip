@@ -539,13 +539,7 @@ hipError_t launch_pp_k(int S, int nrhs, int rc, size_t lds, const T* Mop, const 
                        const int32_t* port_off, const int32_t* port_twin, const typename Mma<T>::TV* h,
                        const typename Mma<T>::TV* a_cur, typename Mma<T>::TV* a_next, int reverse, hipStream_t st) {
     auto kern = k_sweep_mfma_pp<T, NT, RT, WAVES, HL>;
-    static size_t lds_set = 65536;
-    if (lds > lds_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-        lds_set = lds;
-    }
+    if (hipError_t e = raise_lds_limit(reinterpret_cast<const void*>(kern), lds); e != hipSuccess) return e;
     const unsigned ny = unsigned((nrhs + rc - 1) / rc);
     // FP64: S rounded up to a multiple of 8, every XCD taking whole sub-circuits in turn
     const unsigned gy = sizeof(T) == 2 ? unsigned(S) : unsigned((S + 7) / 8 * 8);
@@ -576,15 +570,7 @@ hipError_t launch_t(int S, int nrhs, int rc, size_t lds, const T* K, const int64
                     const typename Mma<T>::TV* a_cur, typename Mma<T>::TV* a_next, typename Mma<T>::TV* x,
                     bool write_x, hipStream_t st, bool port_rows) {
     auto kern = k_sweep_mfma<T, typename MfmaTypes<T>::TB, NT, RT>;
-    // raise the dynamic LDS limit once per instantiation (the first launch comes from
-    // the setup's autotuner, never from inside a graph capture)
-    static size_t lds_set = 65536;
-    if (lds > lds_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-        lds_set = lds;
-    }
+    if (hipError_t e = raise_lds_limit(reinterpret_cast<const void*>(kern), lds); e != hipSuccess) return e;
     const unsigned ny = unsigned((nrhs + rc - 1) / rc);
     hipLaunchKernelGGL(kern, dim3(ny, unsigned((S + 7) / 8 * 8)), dim3(kBlock), lds, st, K, mofs, sub_off, ports.off,
                        ports.node, ports.twin, pc, pbeta, pgamma, b, a_cur, a_next, x, nrhs, rc, write_x ? 1 : 0, S,

@@ -247,9 +247,8 @@ hipError_t launch_r(int S, int max_ns, int nrhs, const TO* K, const int64_t* kof
     const unsigned ny = unsigned((nrhs + R - 1) / R);
     // few workgroups in all: the rows of each sub-circuit over several
     const unsigned nz = int64_t(S) * ny < 1024 && max_ns > bs ? unsigned((max_ns + bs - 1) / bs) : 1u;
-    if (lds > 65536)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep<TO, TV, R>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (hipError_t e = raise_lds_limit(reinterpret_cast<const void*>(&k_sweep<TO, TV, R>), lds); e != hipSuccess)
+        return e;
     hipLaunchKernelGGL((k_sweep<TO, TV, R>), dim3(S, ny, nz), dim3(bs), lds, st, K, kofs, sub_off, ports.off,
                        ports.node, ports.slot, ports.twin, pc, pbeta, pgamma, b, a_cur, a_next, x, nrhs, max_ns,
                        ports.max_slot, adjoint ? 1 : 0, xs_lds ? 1 : 0);
@@ -276,9 +275,9 @@ hipError_t launch_sweep(int S, int max_ns, int nrhs, const TO* K, const int64_t*
         const int ry = split ? (max_ns + bs - 1) / bs : 1;
         const size_t lds = size_t(xs_lds ? 2 : 1) * max_ns * sizeof(TV);
         constexpr int CH = kSweepChunk > 0 ? kSweepChunk : 1;
-        if (lds > 65536)
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep1<TO, TV, CH>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (hipError_t e = raise_lds_limit(reinterpret_cast<const void*>(&k_sweep1<TO, TV, CH>), lds);
+            e != hipSuccess)
+            return e;
         hipLaunchKernelGGL((k_sweep1<TO, TV, CH>), dim3(S, ry), dim3(bs), lds, st, K, kofs, sub_off, ports.off,
                            ports.node, ports.slot, ports.twin, pc, pbeta, pgamma, b, a_cur, a_next, x, max_ns,
                            ports.max_slot, xs_lds ? 1 : 0, port_rows ? 1 : 0);

@@ -42,13 +42,15 @@ __global__ void __launch_bounds__(kBlock)
     const int i = i0 + lx;
     const int pi = i < n ? perm[i] : 0;
 #pragma unroll
-    for (int rr = ly; rr < kTile; rr += kBlock / 64) {
+    for (int k = 0; k < kTile / (kBlock / 64); ++k) {
+        const int rr = ly + k * (kBlock / 64);
         const int r = r0 + rr;
         tile[rr][lx] = (i < n && r < nrhs) ? src[int64_t(r) * n + pi] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int ii = ly; ii < kTile; ii += kBlock / 64) {
+    for (int k = 0; k < kTile / (kBlock / 64); ++k) {
+        const int ii = ly + k * (kBlock / 64);
         const int i2 = i0 + ii, r = r0 + lx;
         if (i2 < n && r < nrhs) dst[int64_t(i2) * nrhs + r] = tile[lx][ii];
     }
@@ -61,13 +63,15 @@ __global__ void __launch_bounds__(kBlock)
     const int j0 = blockIdx.x * kTile, r0 = blockIdx.y * kTile;
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
 #pragma unroll
-    for (int jj = ly; jj < kTile; jj += kBlock / 64) {
+    for (int k = 0; k < kTile / (kBlock / 64); ++k) {
+        const int jj = ly + k * (kBlock / 64);
         const int j = j0 + jj, r = r0 + lx;
         tile[jj][lx] = (j < n && r < nrhs) ? src[int64_t(iperm[j]) * nrhs + r] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int rr = ly; rr < kTile; rr += kBlock / 64) {
+    for (int k = 0; k < kTile / (kBlock / 64); ++k) {
+        const int rr = ly + k * (kBlock / 64);
         const int r = r0 + rr, j = j0 + lx;
         if (j < n && r < nrhs) dst[int64_t(r) * n + j] = tile[lx][rr];
     }

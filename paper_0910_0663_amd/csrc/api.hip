@@ -1163,13 +1163,6 @@ static vtm_status build_values(vtm_handle_s* h) {
         VTM_HIP(panel.alloc(vtm::setup_panel_doubles(P.n, P.max_ns)));
         VTM_HIP(ipiv.alloc(P.n));
     }
-    VTM_HIP(h->c64.upload(P.pc, s));
-    VTM_HIP(h->beta64.upload(P.pbeta, s));
-    VTM_HIP(h->gamma64.upload(P.pgamma, s));
-    if (P.coupled) {
-        VTM_HIP(h->bval64.upload(P.bval, s));
-        if (o.precision != VTM_FP64) VTM_HIP(h->bval32.upload(to_float(P.bval), s));
-    }
     if (o.precision == VTM_FP64) {
         if (h->tiles) {
             VTM_HIP(h->K64.alloc(nm));
@@ -1184,9 +1177,6 @@ static vtm_status build_values(vtm_handle_s* h) {
                                               s));
         }
     } else {
-        VTM_HIP(h->c32.upload(to_float(P.pc), s));
-        VTM_HIP(h->beta32.upload(to_float(P.pbeta), s));
-        VTM_HIP(h->gamma32.upload(to_float(P.pgamma), s));
         if (h->tiles) {
             VTM_HIP(h->Kbf.alloc(nm));
             if (!P.symmetric) VTM_HIP(h->KbfT.alloc(nm));
@@ -1199,6 +1189,40 @@ static vtm_status build_values(vtm_handle_s* h) {
                                              h->val.p, h->dmod.p, h->K32.p, inv64.p, panel.p, ipiv.p, h->flag.p,
                                              s));
         }
+    }
+    // The inversion reads none of the port coefficients: their uploads (staged
+    // through host memory by this thread) go on a second stream while its kernels
+    // run, and the handle's stream waits for them before anything reads them.
+    {
+        struct Side {
+            hipStream_t st = nullptr;
+            hipEvent_t ev = nullptr;
+            ~Side() {
+                if (ev) (void)hipEventDestroy(ev);
+                if (st) (void)hipStreamDestroy(st);
+            }
+        } side;
+        VTM_HIP(hipStreamCreateWithFlags(&side.st, hipStreamNonBlocking));
+        VTM_HIP(hipEventCreateWithFlags(&side.ev, hipEventDisableTiming));
+        hipStream_t s2 = side.st;
+        VTM_HIP(h->c64.upload(P.pc, s2));
+        VTM_HIP(h->beta64.upload(P.pbeta, s2));
+        VTM_HIP(h->gamma64.upload(P.pgamma, s2));
+        if (P.coupled) {
+            VTM_HIP(h->bval64.upload(P.bval, s2));
+            if (o.precision != VTM_FP64) VTM_HIP(h->bval32.upload(to_float(P.bval), s2));
+        }
+        if (o.precision != VTM_FP64) {
+            VTM_HIP(h->c32.upload(to_float(P.pc), s2));
+            VTM_HIP(h->beta32.upload(to_float(P.pbeta), s2));
+            VTM_HIP(h->gamma32.upload(to_float(P.pgamma), s2));
+        }
+        if (h->pp || h->ppb) {
+            VTM_HIP(h->pg64.upload(P.pg, s2));
+            VTM_HIP(h->pgd64.upload(P.pgd, s2));
+        }
+        VTM_HIP(hipEventRecord(side.ev, s2));
+        VTM_HIP(hipStreamWaitEvent(s, side.ev, 0));
     }
     VTM_HIP(hipStreamSynchronize(s));
     int flag = 0;
@@ -1220,10 +1244,6 @@ static vtm_status build_values(vtm_handle_s* h) {
                                                           inv64.p, h->qmofs.p, h->Mbt.p, s, h->coupling<double>()));
         }
         VTM_HIP(hipStreamSynchronize(s));
-    }
-    if (h->pp || h->ppb) {
-        VTM_HIP(h->pg64.upload(P.pg, s));
-        VTM_HIP(h->pgd64.upload(P.pgd, s));
     }
     if (h->ppn) {
         const int64_t nn = P.nofs[P.S];

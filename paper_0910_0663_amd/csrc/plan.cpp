@@ -17,7 +17,6 @@
 #include <exception>
 #include <limits>
 #include <map>
-#include <memory>
 #include <numeric>
 #include <thread>
 #include <utility>
@@ -574,10 +573,12 @@ vtm_status refresh_plan(Plan& P, const double* val, int64_t nnz, const double* Z
     // its first failure; the failure a single pass would meet first wins, keyed by
     // the source position (a non-finite value at q before the pattern check of the
     // merged entry that ends just before q).  Every entry of nv is written when no
-    // chunk fails; it is left uninitialised so that its pages are first touched by
-    // the threads rather than zeroed on one.
+    // chunk fails.  It is the plan's spare value buffer, left uninitialised the
+    // first time so that its pages are first touched by the threads rather than
+    // zeroed on one, and swapped with the values once every check has passed.
     const int64_t m = int64_t(P.val.size());
-    std::unique_ptr<double[]> nv(new double[size_t(std::max<int64_t>(m, 1))]);
+    if (int64_t(P.val_spare.size()) != m) P.val_spare.resize(size_t(m));
+    double* const nv = P.val_spare.data();
     const int T = plan_threads(nnz);
     std::vector<int64_t> lo(T + 1, nnz), fkey(T, INT64_MAX);
     lo[0] = 0;
@@ -678,9 +679,7 @@ vtm_status refresh_plan(Plan& P, const double* val, int64_t nnz, const double* Z
     }
     // commit, then the port quantities as build_plan forms them (the diagonal
     // changes summed in port order, one pass)
-    for_chunks(m, plan_threads(m), [&](int, int64_t k0, int64_t k1) {
-        std::copy(nv.get() + k0, nv.get() + k1, P.val.begin() + k0);
-    });
+    P.val.swap(P.val_spare);
     P.wg.swap(wg);
     P.wW.swap(wW);
     const int64_t np = P.nports;

@@ -89,6 +89,9 @@ struct Plan {
     std::vector<int32_t> rowptr;
     scratch_vec<int32_t> col;
     scratch_vec<double> val;
+    // a refresh merges new values here and swaps it with val once they pass every
+    // check (kept between refreshes, so its pages are not faulted in again)
+    scratch_vec<double> val_spare;
     // How the caller's entries became it (not for tearing at nodes): the caller's
     // entry indices in the order they are summed, per position a flag (bit 0: first
     // entry of a merged entry, bit 1: a diagonal one) and the renumbered entry the

@@ -208,19 +208,28 @@ __global__ void __launch_bounds__(64)
     // Each lane keeps its row rotated: at column step k, register slot i holds
     // column (i + k) mod 64, so the step's column is always slot 0 and every register
     // index below is fixed at compile time; the row turns by one slot per step.
+    // Row k of K goes through LDS in the same slot order (prow[i]: column (i + k) mod
+    // 64), so every lane reads its slot i at prow[i].
     for (int k = 0; k < n; ++k) {
         // pivot: the largest |K(k, i)|, i >= k, ties to the lowest i (none: INT_MAX)
         if (j == k)
 #pragma unroll
-            for (int i = 0; i < kRegSetupMax; ++i) prow[(i + k) & (kRegSetupMax - 1)] = row[i];
+            for (int i = 0; i < kRegSetupMax; ++i) prow[i] = row[i];
         __syncthreads();
-        double bv = -1.0;
-        int p = INT_MAX;
-        if (j >= k && j < n) arg_better(bv, p, fabs(prow[j]), j);
-        for (int o = 32; o > 0; o >>= 1) {
-            const double ov = __shfl_xor(bv, o, 64);
-            const int oi = __shfl_xor(p, o, 64);
-            arg_better(bv, p, ov, oi);
+        // the diagonal is the pivot when it is a number and no entry to its right is
+        // larger in magnitude (ties go to the lowest column, k): one ballot; otherwise
+        // the full search across the lanes
+        const double dk = fabs(prow[0]);
+        int p = k;
+        if (!(dk >= 0.0) || __ballot(j > k && j < n && fabs(prow[j - k]) > dk) != 0) {
+            double bv = -1.0;
+            p = INT_MAX;
+            if (j >= k && j < n) arg_better(bv, p, fabs(prow[j - k]), j);
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(bv, o, 64);
+                const int oi = __shfl_xor(p, o, 64);
+                arg_better(bv, p, ov, oi);
+            }
         }
         if (p == INT_MAX) {
             bad = true;
@@ -236,14 +245,15 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
             for (int i = 1; i < kRegSetupMax; ++i) row[i] = i == sp ? a : row[i];
             row[0] = b;
+            __syncthreads();  // the search has read prow
+            // row k of K after the swap
+            if (j == k)
+#pragma unroll
+                for (int i = 0; i < kRegSetupMax; ++i) prow[i] = row[i];
         }
         __syncthreads();
-        // row k of K after the swap: the pivot and the multipliers (M's column k)
-        if (j == k)
-#pragma unroll
-            for (int i = 0; i < kRegSetupMax; ++i) prow[(i + k) & (kRegSetupMax - 1)] = row[i];
-        __syncthreads();
-        double pv = prow[k];
+        // the pivot and the multipliers (M's column k)
+        double pv = prow[0];
         if (pv == 0.0 || !isfinite(pv)) {
             bad = true;
             pv = 1.0;
@@ -253,7 +263,7 @@ __global__ void __launch_bounds__(64)
         const double r0 = rk;
 #pragma unroll
         for (int i = 1; i < kRegSetupMax; ++i)
-            row[i - 1] = (j == k ? 0.0 : row[i]) - prow[(i + k) & (kRegSetupMax - 1)] * rk;
+            row[i - 1] = (j == k ? 0.0 : row[i]) - prow[i] * rk;
         row[kRegSetupMax - 1] = r0;
         __syncthreads();
     }

@@ -1163,6 +1163,25 @@ static vtm_status build_values(vtm_handle_s* h) {
         VTM_HIP(panel.alloc(vtm::setup_panel_doubles(P.n, P.max_ns)));
         VTM_HIP(ipiv.alloc(P.n));
     }
+    // The inversion reads none of the port coefficients: their uploads (staged
+    // through host memory by this thread) go on a second stream while its kernels
+    // run.  That stream first waits for the work the handle's stream holds before
+    // the inversion (nothing still reads the old coefficients then), and the
+    // handle's stream waits for the uploads before anything reads them.
+    struct Side {
+        hipStream_t st = nullptr;
+        hipEvent_t before = nullptr, done = nullptr;
+        ~Side() {
+            if (before) (void)hipEventDestroy(before);
+            if (done) (void)hipEventDestroy(done);
+            if (st) (void)hipStreamDestroy(st);
+        }
+    } side;
+    VTM_HIP(hipStreamCreateWithFlags(&side.st, hipStreamNonBlocking));
+    VTM_HIP(hipEventCreateWithFlags(&side.before, hipEventDisableTiming));
+    VTM_HIP(hipEventCreateWithFlags(&side.done, hipEventDisableTiming));
+    VTM_HIP(hipEventRecord(side.before, s));
+    VTM_HIP(hipStreamWaitEvent(side.st, side.before, 0));
     if (o.precision == VTM_FP64) {
         if (h->tiles) {
             VTM_HIP(h->K64.alloc(nm));
@@ -1190,20 +1209,7 @@ static vtm_status build_values(vtm_handle_s* h) {
                                              s));
         }
     }
-    // The inversion reads none of the port coefficients: their uploads (staged
-    // through host memory by this thread) go on a second stream while its kernels
-    // run, and the handle's stream waits for them before anything reads them.
     {
-        struct Side {
-            hipStream_t st = nullptr;
-            hipEvent_t ev = nullptr;
-            ~Side() {
-                if (ev) (void)hipEventDestroy(ev);
-                if (st) (void)hipStreamDestroy(st);
-            }
-        } side;
-        VTM_HIP(hipStreamCreateWithFlags(&side.st, hipStreamNonBlocking));
-        VTM_HIP(hipEventCreateWithFlags(&side.ev, hipEventDisableTiming));
         hipStream_t s2 = side.st;
         VTM_HIP(h->c64.upload(P.pc, s2));
         VTM_HIP(h->beta64.upload(P.pbeta, s2));
@@ -1221,8 +1227,8 @@ static vtm_status build_values(vtm_handle_s* h) {
             VTM_HIP(h->pg64.upload(P.pg, s2));
             VTM_HIP(h->pgd64.upload(P.pgd, s2));
         }
-        VTM_HIP(hipEventRecord(side.ev, s2));
-        VTM_HIP(hipStreamWaitEvent(s, side.ev, 0));
+        VTM_HIP(hipEventRecord(side.done, s2));
+        VTM_HIP(hipStreamWaitEvent(s, side.done, 0));
     }
     VTM_HIP(hipStreamSynchronize(s));
     int flag = 0;

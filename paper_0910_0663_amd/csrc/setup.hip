@@ -397,18 +397,24 @@ __device__ int block_argmax_own(double v, int idx, double* red_v, int* red_i) {
 
 // The panel elimination for sub-circuits of up to blockDim.x (at most
 // kPanelBlock) nodes, one workgroup per sub-circuit, with row i of the panel in
-// thread i's registers.  Column by column: the pivot search reduces the threads'
-// own entries (ties to the lowest row), rows k and p trade places through LDS,
-// the pivot row is scaled and published in LDS, and every other row updates
-// itself.  No panel in LDS, so several workgroups share a CU.  An entry of column
-// kk is picked from the registers by selects (a register array indexed at run
-// time would go to scratch memory).
+// thread i's registers.  Column by column: the pivot search (ties to the lowest
+// row), rows k and p trade places through LDS, the pivot row is scaled and
+// published in LDS, and every other row updates itself.  No panel in LDS, so
+// several workgroups share a CU.  Each thread keeps its row rotated: at step kk
+// register slot t holds panel column (t + kk) mod NB, so the step's column is
+// always slot 0, every register index is fixed at compile time, and the row
+// turns by one slot per step (the pivot row is published in the same slot
+// order).  The pivot search is first one ballot per wavefront: the diagonal is
+// the pivot when it is a number and no row below holds a larger entry, which is
+// what the full search (run otherwise) would find.
 template <int NB>
 __global__ void __launch_bounds__(kPanelBlock)
     k_gj_panel_reg(const int32_t* __restrict__ sub_off, const int64_t* __restrict__ kofs, double* __restrict__ base,
                    int k0, double* __restrict__ panel, int32_t* __restrict__ ipiv, int* flag) {
+    static_assert((NB & (NB - 1)) == 0, "the rotation wraps by masking");
     __shared__ double red_v[kPanelBlock / 64];
     __shared__ int red_i[kPanelBlock / 64];
+    __shared__ int any_w[kPanelBlock / 64];
     __shared__ double prow[NB], xrow[NB], pv_s;
     const int s = blockIdx.x;
     const int off = sub_off[s], n = sub_off[s + 1] - off;
@@ -418,22 +424,29 @@ __global__ void __launch_bounds__(kPanelBlock)
     double* slot = panel + int64_t(off) * panel_stride(NB);  // E_J column-major: entry (i, jj) at jj n + i
     const int i = threadIdx.x;
     const bool mine = i < n;
+    const int nw = int(blockDim.x) >> 6;
     double row[NB];
 #pragma unroll
     for (int jj = 0; jj < NB; ++jj) row[jj] = (mine && jj < kb) ? M[int64_t(i) * n + k0 + jj] : 0.0;
-    auto pick = [&](int kk) {
-        double v = 0.0;
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj) v = jj == kk ? row[jj] : v;
-        return v;
-    };
     bool bad = false;
     for (int kk = 0; kk < kb; ++kk) {
         const int k = k0 + kk;
-        int p = block_argmax_own(mine && i >= k ? fabs(pick(kk)) : -1.0, i, red_v, red_i);
-        if (p == INT_MAX) {
-            bad = true;
-            p = k;
+        // the diagonal, then one ballot per wavefront for a larger entry below it
+        if (i == k) pv_s = row[0];
+        __syncthreads();
+        const double d = fabs(pv_s);
+        const unsigned long long big = __ballot(mine && i > k && fabs(row[0]) > d);
+        if ((i & 63) == 0) any_w[i >> 6] = big != 0ull;
+        __syncthreads();
+        bool search = !(d >= 0.0);  // a diagonal that is not a number never wins
+        for (int w = 0; w < nw; ++w) search = search || any_w[w] != 0;
+        int p = k;
+        if (search) {  // uniform
+            p = block_argmax_own(mine && i >= k ? fabs(row[0]) : -1.0, i, red_v, red_i);
+            if (p == INT_MAX) {
+                bad = true;
+                p = k;
+            }
         }
         if (i == 0) ipiv[off + k] = p;
         if (p != k) {  // uniform: rows k and p trade places through LDS
@@ -451,36 +464,44 @@ __global__ void __launch_bounds__(kPanelBlock)
 #pragma unroll
                 for (int jj = 0; jj < NB; ++jj) row[jj] = prow[jj];
             __syncthreads();
+            if (i == k) pv_s = row[0];
+            __syncthreads();
         }
-        if (i == k) pv_s = pick(kk);
-        __syncthreads();
         double pv = pv_s;
         if (pv == 0.0 || !isfinite(pv)) {
             bad = true;
             pv = 1.0;
         }
+        // the pivot row scaled (its own column becomes 1 / pv), each slot written
+        // back one slot lower (the turn for the next step)
         if (i == k) {
+            prow[0] = 1.0 / pv;
 #pragma unroll
-            for (int jj = 0; jj < NB; ++jj) {
-                row[jj] = (jj == kk ? 1.0 : row[jj]) / pv;
-                prow[jj] = row[jj];
+            for (int t = 1; t < NB; ++t) {
+                prow[t] = row[t] / pv;
+                row[t - 1] = prow[t];
             }
+            row[NB - 1] = prow[0];
         }
         __syncthreads();
         if (mine && i != k) {
-            const double f = pick(kk);
+            const double f = row[0];
 #pragma unroll
-            for (int jj = 0; jj < NB; ++jj) row[jj] = (jj == kk ? 0.0 : row[jj]) - f * prow[jj];
+            for (int t = 1; t < NB; ++t) row[t - 1] = row[t] - f * prow[t];
+            row[NB - 1] = 0.0 - f * prow[0];
         }
     }
-    // the panel's columns are final for this step; k_gj_update reads them from the slot
+    // the panel's columns are final for this step; k_gj_update reads them from the slot.
+    // After kb steps slot t holds column (t + kb) mod NB.
     if (mine)
 #pragma unroll
-        for (int jj = 0; jj < NB; ++jj)
+        for (int t = 0; t < NB; ++t) {
+            const int jj = (t + kb) & (NB - 1);
             if (jj < kb) {
-                M[int64_t(i) * n + k0 + jj] = row[jj];
-                slot[int64_t(jj) * n + i] = row[jj];
+                M[int64_t(i) * n + k0 + jj] = row[t];
+                slot[int64_t(jj) * n + i] = row[t];
             }
+        }
     if (bad && i == 0) atomicOr(flag, 1);
 }
 

@@ -409,7 +409,13 @@ void threaded_plan_checks() {
         vtm::Plan T = R;
         const vtm_status st = vtm::refresh_plan(T, v.data(), int64_t(v.size()), nullptr, 0, err);
         check(T.val == R.val && T.dmod == R.dmod, "threaded refresh: a refused refresh changes nothing");
-        return st == VTM_E_ARG ? err : std::string("status ") + std::to_string(int(st));
+        const std::string msg = st == VTM_E_ARG ? err : std::string("status ") + std::to_string(int(st));
+        // the refused refresh left partial values in the plan's spare buffer: the next
+        // refresh still forms every value
+        check(vtm::refresh_plan(T, A.val.data(), int64_t(A.val.size()), &Z, 1, err) == VTM_OK && T.val == P.val &&
+                  T.dmod == P.dmod && T.pc == P.pc,
+              "threaded refresh after a refused one equals a fresh plan");
+        return msg;
     };
     const std::string pattern = "the new values change which off-diagonal entries are zero (the sparsity pattern)";
     check(two_faults(nq / 10, 9 * nq / 10) == pattern, "threaded refresh: an earlier pattern change first");

@@ -188,16 +188,21 @@ def _strong_one_sided_couplings(w, scale, seed):
     return w
 
 
-@pytest.mark.parametrize("kind", ["pivoting 64-node", "ragged 63-node"])
+@pytest.mark.parametrize("kind", ["pivoting 64-node", "ragged 63-node", "pivoting 125-node panels"])
 def test_register_setup_iterates_match_oracle(torch, kind):
     """Sub-circuits of up to 64 nodes are inverted by one wavefront each: with
     one-sided entries larger than the diagonal (every elimination pivots) on
     4x4x4 blocks, and on 7x9 blocks (63 nodes, a ragged register row), the first
     iterates in the full and port-to-port forms equal the oracle's (exact local
-    solves by sparse LU)."""
-    if kind.startswith("pivoting"):
+    solves by sparse LU).  The same pivoting on 256 blocks of 5x5x5 exercises the
+    panel elimination with a row per thread (panels of 32 columns, the last one
+    29 wide)."""
+    if kind == "pivoting 64-node":
         w = _strong_one_sided_couplings(workloads.make(3, dims=(8, 8, 8), block=(4, 4, 4)), 3.0, 4)
         assert np.bincount(w.part).max() == 64
+    elif kind.startswith("pivoting 125"):
+        w = _strong_one_sided_couplings(workloads.make(3, dims=(40, 40, 20), block=(5, 5, 5)), 3.0, 5)
+        assert w.n_sub == 256 and np.bincount(w.part).min() == 125
     else:
         w = workloads.make(1, dims=(63, 63), block=(7, 9))
         assert np.bincount(w.part).max() == 63

@@ -789,7 +789,7 @@ int copy_parts(int S, int n) {
 template <int NB>
 hipError_t launch_update(int S, int max_ns, const int32_t* sub_off, const int64_t* kofs, double* scratch64, int k0,
                          const double* panel, hipStream_t st) {
-    constexpr int CT = NB <= 32 ? 4 : 2;   // column tiles per wavefront (the B operand stays in registers)
+    constexpr int CT = 4;  // column tiles per wavefront (the B operand stays in registers)
     const int ncb = (max_ns + 16 * CT - 1) / (16 * CT), nrb = (max_ns + kUpdRows - 1) / kUpdRows;
     const int64_t blocks = 8 * int64_t(ncb) * ((int64_t(S) * nrb + 7) / 8);
     if (blocks > INT_MAX) return hipErrorInvalidValue;
